@@ -1,0 +1,195 @@
+"""CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+A plain, single-threaded C implementation of what the k-mer rank +
+regular-sampling decomposition computes (``kd_oracle.c``), and this ctypes
+wrapper.  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+CPU-baseline leg may import it; the GPU library never does, and the two share
+no code.  Citations point at the paper's sections / equations; each C function
+names the passage it follows.
+
+Parity status: every function here is pinned by ``tests/test_oracle_pins.py``
+(worked examples, closed forms, brute force over the dense count vectors,
+invariants).  The paper's Table 1 statistics cannot be reproduced (its data
+set and Delta are not given), so they pin nothing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+EPS = 46656
+K_LEN = 6
+
+ERRORS = {0: "ok", -1: "invalid argument", -2: "bad residue", -3: "sequence shorter than k",
+          -4: "sequence has more than 65535 k-mers", -5: "out of memory"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, seq=None, pos=None):
+        super().__init__(f"oracle error {code} ({ERRORS.get(code, '?')}) seq={seq} pos={pos}")
+        self.code, self.seq, self.pos = code, seq, pos
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, single-threaded)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.orc_code.argtypes = [C.c_uint8]
+        L.orc_code.restype = C.c_int
+        L.orc_kmer_words.argtypes = [P, C.c_uint64, P, P]
+        L.orc_kmer_words.restype = C.c_int64
+        L.orc_count_dense.argtypes = [P, C.c_uint64, P]
+        L.orc_count_dense.restype = C.c_int64
+        L.orc_count_set.argtypes = [P, P, C.c_uint32, P, P, P, P, P, P]
+        L.orc_count_set.restype = C.c_int
+        L.orc_shared.argtypes = [P, P, C.c_uint64, P, P, C.c_uint64]
+        L.orc_shared.restype = C.c_uint32
+        L.orc_shared_dense.argtypes = [P, P]
+        L.orc_shared_dense.restype = C.c_uint32
+        L.orc_fraction.argtypes = [C.c_uint32, C.c_uint32]
+        L.orc_fraction.restype = C.c_double
+        L.orc_distance.argtypes = [C.c_double, C.c_double]
+        L.orc_distance.restype = C.c_double
+        L.orc_similarity_block.argtypes = [P, P, P, P, C.c_uint32, C.c_uint32, C.c_uint32,
+                                           C.c_uint32, P, P]
+        L.orc_similarity_block.restype = None
+        L.orc_rank_rows.argtypes = [P, P, P, P, C.c_uint32, P, C.c_uint32, C.c_double, P]
+        L.orc_rank_rows.restype = None
+        L.orc_partition.argtypes = [P, C.c_uint32, C.c_uint32, P, P, P, P, P]
+        L.orc_partition.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Lists:
+    """Count vectors of a set as sorted nonzero entries (CSR)."""
+
+    def __init__(self, ids, cnt, off, K):
+        self.ids, self.cnt, self.off, self.K = ids, cnt, off, K
+
+    @property
+    def n(self):
+        return int(self.K.shape[0])
+
+    def entries(self, i):
+        a, b = int(self.off[i]), int(self.off[i + 1])
+        return self.ids[a:b], self.cnt[a:b]
+
+
+def code(ch: int) -> int:
+    return lib().orc_code(ch)
+
+
+def kmer_words(seq: bytes) -> np.ndarray:
+    s = np.frombuffer(seq, dtype=np.uint8).copy()
+    out = np.zeros(max(len(seq), 1), dtype=np.uint32)
+    bad = np.zeros(1, dtype=np.uint64)
+    r = lib().orc_kmer_words(_p(s), len(seq), _p(out), _p(bad))
+    if r < 0:
+        raise OracleError(int(r), 0, int(bad[0]))
+    return out[:r]
+
+
+def count_dense(seq: bytes) -> np.ndarray:
+    s = np.frombuffer(seq, dtype=np.uint8).copy()
+    out = np.zeros(EPS, dtype=np.uint32)
+    r = lib().orc_count_dense(_p(s), len(seq), _p(out))
+    if r < 0:
+        raise OracleError(int(r))
+    return out
+
+
+def count(ss) -> Lists:
+    """Count vectors for a synth.SeqSet (or anything with residues/offsets)."""
+    res = np.ascontiguousarray(ss.residues, dtype=np.uint8)
+    off_in = np.ascontiguousarray(ss.offsets, dtype=np.uint64)
+    N = off_in.shape[0] - 1
+    cap = max(int(np.maximum(np.diff(off_in.astype(np.int64)) - (K_LEN - 1), 0).sum()), 1)
+    ids = np.zeros(cap, dtype=np.uint16)
+    cnt = np.zeros(cap, dtype=np.uint16)
+    off = np.zeros(N + 1, dtype=np.uint64)
+    K = np.zeros(max(N, 1), dtype=np.uint32)
+    es = np.zeros(1, dtype=np.uint64)
+    ep = np.zeros(1, dtype=np.uint64)
+    r = lib().orc_count_set(_p(res), _p(off_in), N, _p(ids), _p(cnt), _p(off), _p(K), _p(es), _p(ep))
+    if r != 0:
+        raise OracleError(r, int(es[0]), int(ep[0]))
+    tot = int(off[N])
+    return Lists(ids[:tot].copy(), cnt[:tot].copy(), off, K[:N].copy())
+
+
+def shared(L: Lists, i: int, j: int) -> int:
+    ia, ca = L.entries(i)
+    ib, cb = L.entries(j)
+    ia, ca, ib, cb = (np.ascontiguousarray(x) for x in (ia, ca, ib, cb))
+    return int(lib().orc_shared(_p(ia), _p(ca), len(ia), _p(ib), _p(cb), len(ib)))
+
+
+def shared_dense(cx: np.ndarray, cy: np.ndarray) -> int:
+    cx = np.ascontiguousarray(cx, dtype=np.uint32)
+    cy = np.ascontiguousarray(cy, dtype=np.uint32)
+    return int(lib().orc_shared_dense(_p(cx), _p(cy)))
+
+
+def fraction(s: int, d: int) -> float:
+    return float(lib().orc_fraction(s, d))
+
+
+def distance(F: float, delta: float) -> float:
+    return float(lib().orc_distance(F, delta))
+
+
+def similarity(L: Lists, r0: int, nr: int, c0: int, nc: int):
+    S = np.zeros((nr, nc), dtype=np.uint16)
+    D = np.zeros((nr, nc), dtype=np.uint16)
+    lib().orc_similarity_block(_p(L.ids), _p(L.cnt), _p(L.off), _p(L.K), r0, nr, c0, nc, _p(S), _p(D))
+    return S, D
+
+
+def rank(L: Lists, delta: float, rows=None) -> np.ndarray:
+    N = L.n
+    rows = np.arange(N, dtype=np.uint32) if rows is None else np.ascontiguousarray(rows, dtype=np.uint32)
+    out = np.zeros(max(len(rows), 1), dtype=np.float64)
+    lib().orc_rank_rows(_p(L.ids), _p(L.cnt), _p(L.off), _p(L.K), N, _p(rows), len(rows), delta, _p(out))
+    return out[:len(rows)]
+
+
+def partition(R: np.ndarray, B: int):
+    """Returns dict(bucket, order, offsets, pivot_rank, pivot_idx)."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    N = R.shape[0]
+    bucket = np.zeros(max(N, 1), dtype=np.uint32)
+    order = np.zeros(max(N, 1), dtype=np.uint32)
+    offsets = np.zeros(B + 1 if B > 0 else 1, dtype=np.uint32)
+    pr = np.zeros(max(B - 1, 1), dtype=np.float64)
+    pi = np.zeros(max(B - 1, 1), dtype=np.uint32)
+    r = lib().orc_partition(_p(R), N, B, _p(bucket), _p(order), _p(offsets), _p(pr), _p(pi))
+    if r != 0:
+        raise OracleError(r)
+    return dict(bucket=bucket[:N], order=order[:N], offsets=offsets[:B + 1],
+                pivot_rank=pr[:max(B - 1, 0)], pivot_idx=pi[:max(B - 1, 0)])

@@ -1,0 +1,296 @@
+"""Pins for the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-type the oracle's code: the k-mer words are checked against
+hand-worked values and Python's own base-6 parsing, shared counts against a
+dense brute force built through that independent route, ranks against closed
+forms and an exactly-rounded sum, and the decomposition against hand-worked
+cases and the regular-sampling balance bound of Section 3.2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import golden_lines
+
+AA = "ACDEFGHIKLMNPQRSTVWY"
+
+
+def _dayhoff():
+    return {l.split()[0]: int(l.split()[1]) for l in golden_lines("dayhoff6.txt")}
+
+
+def _words_indep(seq: str):
+    """k-mer words via str.translate + int(text, 6): positional base-6 notation
+    is big-endian by definition, independent of the oracle's loop."""
+    tab = str.maketrans({k: str(v) for k, v in _dayhoff().items()})
+    digits = seq.translate(tab)
+    return [int(digits[t:t + 6], 6) for t in range(len(seq) - 5)]
+
+
+def _dense_indep(seq: str):
+    return np.bincount(np.array(_words_indep(seq), dtype=np.int64), minlength=46656)
+
+
+# ---------------------------------------------------------------- encoding --
+
+def test_dayhoff_groups(oracle_mod):
+    g = _dayhoff()
+    assert sorted(g) == sorted(AA)
+    for ch, v in g.items():
+        assert oracle_mod.code(ord(ch)) == v, ch
+    for ch in b"BJOUXZacdefg*- \n0":
+        assert oracle_mod.code(ch) == -1, chr(ch)
+
+
+def test_kmer_words_golden(oracle_mod):
+    for line in golden_lines("kmer_words.txt"):
+        seq, *w = line.split()
+        assert list(oracle_mod.kmer_words(seq.encode())) == [int(x) for x in w], seq
+        assert _words_indep(seq) == [int(x) for x in w], seq
+
+
+def test_kmer_words_vs_base6(oracle_mod):
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        s = "".join(rng.choice(list(AA), size=int(rng.integers(6, 80))))
+        assert list(oracle_mod.kmer_words(s.encode())) == _words_indep(s)
+
+
+def test_count_errors(oracle_mod):
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.count(synth.from_strings(["ACDEFGH", "ACDXFGH"]))
+    assert e.value.code == -2 and e.value.seq == 1 and e.value.pos == 3
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.count(synth.from_strings(["ACDEFGH", "ACDEF"]))
+    assert e.value.code == -3 and e.value.seq == 1
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.count(synth.from_strings(["A" * (65535 + 5 + 1)]))
+    assert e.value.code == -4
+    # the longest allowed sequence: 65535 words
+    L = oracle_mod.count(synth.from_strings(["A" * (65535 + 5)]))
+    assert L.K[0] == 65535 and list(L.cnt) == [65535]
+
+
+def test_count_lists_vs_dense(oracle_mod):
+    rng = np.random.default_rng(12)
+    ss = synth.random_tiny(rng, 24, 6, 120)
+    L = oracle_mod.count(ss)
+    for i in range(ss.n):
+        s = ss.seq(i).decode()
+        dense = _dense_indep(s)
+        nz = np.flatnonzero(dense)
+        ids, cnt = L.entries(i)
+        assert np.array_equal(ids, nz)
+        assert np.array_equal(cnt, dense[nz])
+        assert int(cnt.sum()) == len(s) - 5 == int(L.K[i])
+        assert np.all(np.diff(ids.astype(np.int64)) > 0)
+
+
+# ------------------------------------------------------------ shared count --
+
+@pytest.mark.parametrize("alphabet,seed", [(AA, 1), ("AC", 2), ("ACD", 3), ("AGPSTC", 4)])
+def test_shared_vs_dense_bruteforce(oracle_mod, alphabet, seed):
+    """Section 3: shared = sum over all epsilon words of min(cX, cY).  Small
+    alphabets force repeated words (counts >= 2) so the min matters."""
+    rng = np.random.default_rng(seed)
+    ss = synth.random_tiny(rng, 20, 6, 90, alphabet.encode())
+    L = oracle_mod.count(ss)
+    dense = [_dense_indep(ss.seq(i).decode()) for i in range(ss.n)]
+    S, D = oracle_mod.similarity(L, 0, ss.n, 0, ss.n)
+    for i in range(ss.n):
+        for j in range(ss.n):
+            assert S[i, j] == int(np.minimum(dense[i], dense[j]).sum())
+            assert D[i, j] == min(len(ss.seq(i)), len(ss.seq(j))) - 5
+    # the oracle's literal dense routine agrees too
+    cx = oracle_mod.count_dense(ss.seq(0))
+    cy = oracle_mod.count_dense(ss.seq(1))
+    assert oracle_mod.shared_dense(cx, cy) == S[0, 1]
+
+
+def test_shared_invariants(oracle_mod):
+    rng = np.random.default_rng(5)
+    ss = synth.random_tiny(rng, 16, 6, 200, b"ACDEFGHIK")
+    L = oracle_mod.count(ss)
+    S, D = oracle_mod.similarity(L, 0, ss.n, 0, ss.n)
+    assert np.array_equal(S, S.T)
+    assert np.array_equal(np.diag(S), L.K)
+    assert np.all(S <= D)
+
+
+def test_shared_dayhoff_relabel_metamorphic(oracle_mod):
+    """Swapping residues within a Dayhoff group, or renaming the groups
+    consistently, leaves every shared count unchanged."""
+    rng = np.random.default_rng(6)
+    groups = ["AGPST", "C", "DENQ", "FWY", "HKR", "ILMV"]
+    ss = synth.random_tiny(rng, 12, 6, 150)
+    within = {c: g[int(rng.integers(len(g)))] for g in groups for c in g}
+    perm = rng.permutation(6)
+    across = {c: groups[perm[k]][0] for k, g in enumerate(groups) for c in g}
+    base = oracle_mod.similarity(oracle_mod.count(ss), 0, ss.n, 0, ss.n)[0]
+    for m in (within, across):
+        t = synth.from_strings(["".join(m[c] for c in ss.seq(i).decode()) for i in range(ss.n)])
+        assert np.array_equal(oracle_mod.similarity(oracle_mod.count(t), 0, t.n, 0, t.n)[0], base)
+
+
+# ------------------------------------------------ fraction, distance, rank --
+
+def test_fraction_distance_closed_forms(oracle_mod):
+    for d in (1, 7, 344, 65535):
+        assert oracle_mod.fraction(d, d) == 1.0
+        assert oracle_mod.fraction(0, d) == 0.0
+    for delta in (0.1, 1e-3, 0.5):
+        # Delta + 1 is rounded once in double before the log: a relative
+        # change of at most 2^-53 in the argument, so at most 2^-53 (1.1e-16)
+        # absolute in d; allow that plus one ulp of the log itself.
+        assert oracle_mod.distance(1.0, delta) == pytest.approx(-math.log1p(delta), rel=2.3e-16, abs=1.2e-16)
+        assert oracle_mod.distance(0.0, delta) == pytest.approx(-math.log(delta), rel=2.3e-16, abs=0)
+    # F = 1 - Delta gives distance exactly 0
+    assert oracle_mod.distance(0.75, 0.25) == 0.0
+
+
+def test_rank_worked_example(oracle_mod):
+    kv = {}
+    for line in golden_lines("worked_rank.txt"):
+        k, *v = line.split()
+        kv[(k, v[0]) if k == "seq" else k] = v
+    delta = float(kv["delta"][0])
+    seqs = [kv[("seq", n)][1] for n in "XYZ"]
+    L = oracle_mod.count(synth.from_strings(seqs))
+    S, D = oracle_mod.similarity(L, 0, 3, 0, 3)
+    assert S[0, 1] == int(kv["shared_XY"][0]) and D[0, 1] == int(kv["denom_XY"][0])
+    assert S[0, 2] == int(kv["shared_XZ"][0]) and S[1, 2] == int(kv["shared_YZ"][0])
+    R = oracle_mod.rank(L, delta)
+    # closed forms from Equations 1-3
+    rx = (2 * -math.log1p(delta) - math.log(delta)) / 3
+    rz = (2 * -math.log(delta) - math.log1p(delta)) / 3
+    assert R[0] == R[1]                       # exact tie
+    assert R[0] == pytest.approx(rx, rel=1e-15, abs=0)
+    assert R[2] == pytest.approx(rz, rel=1e-15, abs=0)
+    assert R[0] == pytest.approx(float(kv["rank_X"][0]), rel=1e-15, abs=0)
+    assert R[2] == pytest.approx(float(kv["rank_Z"][0]), rel=1e-15, abs=0)
+
+
+def test_rank_identical_sequences(oracle_mod):
+    for delta in (0.1, 0.01):
+        L = oracle_mod.count(synth.from_strings(["MKVLAAGIVGLLLAQ"] * 37))
+        R = oracle_mod.rank(L, delta)
+        np.testing.assert_allclose(R, -math.log1p(delta), rtol=1e-15, atol=0)
+
+
+def test_rank_disjoint_sequences(oracle_mod):
+    """No shared word between any two sequences: R = ((N-1)(-ln D) - ln(1+D))/N."""
+    seqs = ["AAAAAAAA", "CCCCCC", "DDDDDDDDDDD", "FFFFFFF", "HHHHHH", "IIIIIIIIIIIIIII",
+            "ACACACACAC", "DFDFDFDFDF"]
+    L = oracle_mod.count(synth.from_strings(seqs))
+    S, _ = oracle_mod.similarity(L, 0, len(seqs), 0, len(seqs))
+    assert np.count_nonzero(S - np.diag(np.diag(S))) == 0
+    N, delta = len(seqs), 0.1
+    expect = ((N - 1) * -math.log(delta) - math.log1p(delta)) / N
+    np.testing.assert_allclose(oracle_mod.rank(L, delta), expect, rtol=1e-15, atol=0)
+
+
+def test_rank_vs_exact_sum_bruteforce(oracle_mod):
+    """Equation 3 including the j = i term, summed exactly with math.fsum over
+    distances built from the dense brute-force shared counts."""
+    rng = np.random.default_rng(7)
+    ss = synth.random_tiny(rng, 30, 6, 100, b"ACDEFGHIKLM")
+    dense = [_dense_indep(ss.seq(i).decode()) for i in range(ss.n)]
+    n = ss.lengths()
+    delta = 0.1
+    L = oracle_mod.count(ss)
+    R = oracle_mod.rank(L, delta)
+    for i in range(ss.n):
+        ds = [-math.log(delta + int(np.minimum(dense[i], dense[j]).sum()) / (min(n[i], n[j]) - 5))
+              for j in range(ss.n)]
+        ref = math.fsum(ds) / ss.n
+        assert R[i] == pytest.approx(ref, rel=4e-16, abs=1e-300)
+
+
+def test_rank_bounds_and_permutation(oracle_mod):
+    s = synth.small()
+    sub = synth.from_strings([s.seq(i) for i in range(64)])
+    L = oracle_mod.count(sub)
+    delta = 0.1
+    R = oracle_mod.rank(L, delta)
+    assert np.all(R >= -math.log1p(delta) - 1e-15) and np.all(R <= -math.log(delta) + 1e-15)
+    perm = np.random.default_rng(8).permutation(64)
+    P = oracle_mod.rank(oracle_mod.count(synth.from_strings([sub.seq(int(i)) for i in perm])), delta)
+    np.testing.assert_allclose(P, R[perm], rtol=1e-15, atol=0)
+
+
+# ---------------------------------------------------------- decomposition --
+
+def _cases():
+    cur = None
+    for line in golden_lines("partition_cases.txt"):
+        k, *v = line.split()
+        if k == "case":
+            cur = {"name": v[0]}
+        elif k == "end":
+            yield cur
+        else:
+            cur[k] = v
+
+
+@pytest.mark.parametrize("case", list(_cases()), ids=lambda c: c["name"])
+def test_partition_golden(oracle_mod, case):
+    R = np.array([float(x) for x in case["ranks"]])
+    B = int(case["B"][0])
+    p = oracle_mod.partition(R, B)
+    assert list(p["bucket"]) == [int(x) for x in case["bucket"]]
+    assert list(p["offsets"]) == [int(x) for x in case["offsets"]]
+    assert list(p["order"]) == [int(x) for x in case["order"]]
+    assert list(p["pivot_idx"]) == [int(x) for x in case["pivot_idx"]]
+    assert np.array_equal(p["pivot_rank"], R[p["pivot_idx"]])
+
+
+def _check_partition_invariants(R, B, p):
+    N = len(R)
+    bucket, order, off = p["bucket"], p["order"], p["offsets"]
+    assert sorted(order.tolist()) == list(range(N))
+    assert off[0] == 0 and off[-1] == N and np.all(np.diff(off.astype(np.int64)) >= 0)
+    assert np.array_equal(np.bincount(bucket, minlength=B), np.diff(off.astype(np.int64)))
+    keys = sorted(range(N), key=lambda i: (R[i], i))
+    assert list(order) == keys                       # grouped order == key order
+    for b in range(B):
+        assert np.all(bucket[order[off[b]:off[b + 1]]] == b)
+    if N >= B * B:                                   # Section 3.2 bound
+        assert np.diff(off.astype(np.int64)).max() <= 2 * math.ceil(N / B)
+    assert len(p["pivot_idx"]) == B - 1
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_partition_invariants_random(oracle_mod, seed):
+    rng = np.random.default_rng(100 + seed)
+    B = int(rng.integers(1, 13))
+    N = int(rng.integers(B, 8 * B * B + 2))
+    kind = seed % 4
+    if kind == 0:
+        R = rng.random(N)
+    elif kind == 1:
+        R = np.sort(rng.random(N))
+    elif kind == 2:
+        R = np.sort(rng.random(N))[::-1].copy()
+    else:
+        R = rng.integers(0, 3, size=N).astype(np.float64)   # heavy ties
+    p = oracle_mod.partition(R, B)
+    _check_partition_invariants(R, B, p)
+    if B == 1:
+        assert np.all(p["bucket"] == 0)
+
+
+def test_partition_errors(oracle_mod):
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.partition(np.zeros(3), 0)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.partition(np.zeros(3), 4)
+
+
+def test_partition_small_workload(oracle_mod):
+    s = synth.small()
+    L = oracle_mod.count(s)
+    R = oracle_mod.rank(L, 0.1)
+    p = oracle_mod.partition(R, s.B)
+    _check_partition_invariants(R, s.B, p)
