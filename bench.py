@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark: one step = k-mer counting -> all-pairs similarity + k-mer rank
+-> regular-sampling split, on the paper-scale synthetic workload (N = 20,000
+protein sequences in 200 families, Dayhoff-6 k = 6, B = 16 buckets,
+delta = 0.1), inputs resident in HBM before timing starts.
+
+Prints one JSON line with the whole-job throughput in k-mer pair
+similarities per second, the roofline position of the dominant kernel (the
+all-pairs rank kernel, timed live with HIP events on its stream), and the
+single-threaded CPU oracle timed on a bounded sample of the same job.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "k-mer pair-similarities/sec (GPU vs oracle); p50/p99 request latency"
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 VALU lane-instructions/s; a
+# probe (one 16-bit min + add of the shared-count sum) is counted at one
+# lane-instruction, i.e. the packed-int16 rate of 78.6e12 ops/s / 2.
+PEAK_TPROBE = 256 * 64 * 2.4e9 / 1e12
+
+WORKLOADS = {
+    "paper20k": ("paper-scale: N=20000 sequences, 200 families, lognormal length mean 350, "
+                 "divergence 5-30%, Dayhoff-6 k=6, B=16, delta=0.1, seed 2"),
+    "small": "small: N=512, 8 families, length U[200,400], divergence 10%, B=4, delta=0.1, seed 1",
+    "large100k": ("large: N=100000, 1000 families, lognormal mean 300, divergence 5-40%, "
+                  "B=64, delta=0.1, seed 3"),
+}
+
+
+def probe_count(D):
+    """sum over unordered pairs of min(D_i, D_j) (work of walking the shorter list)."""
+    import numpy as np
+    d = np.sort(np.asarray(D, dtype=np.int64))
+    n = d.shape[0]
+    return int((d * (n - 1 - np.arange(n))).sum())
+
+
+def cpu_baseline(ss, delta, budget_s):
+    """Time the CPU oracle (single thread) on the first M rows of the rank
+    (each row is N pair similarities) and extrapolate the whole job."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    L = oracle.count(ss)
+    t_count = time.perf_counter() - t0
+    N = ss.n
+    rows = np.arange(min(8, N), dtype=np.uint32)
+    t0 = time.perf_counter()
+    oracle.rank(L, delta, rows=rows)
+    per_row = (time.perf_counter() - t0) / len(rows)
+    M = int(min(N, max(len(rows), budget_s / max(per_row, 1e-9))))
+    rows = np.arange(M, dtype=np.uint32)
+    t0 = time.perf_counter()
+    oracle.rank(L, delta, rows=rows)
+    t_rows = time.perf_counter() - t0
+    job_s = t_count + t_rows * N / M
+    pairs = N * (N - 1) / 2
+    return {
+        "value": pairs / job_s,
+        "unit": "pair-similarities/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle k-mer counting of all {N} sequences ({t_count:.2f} s) + rank rows "
+                   f"0..{M - 1} each against all {N} sequences ({t_rows:.2f} s, {M * N} pair "
+                   f"similarities), single thread; job time extrapolated to all {N} rows = "
+                   f"{job_s:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS))
+    ap.add_argument("--delta", type=float, default=0.1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0905_1744_amd as kd
+    import synth
+
+    gen = {"paper20k": synth.paper20k, "small": synth.small, "large100k": synth.large100k}
+    ss = gen[args.workload]()
+    N, B, delta = ss.n, ss.B, args.delta
+    print(f"[bench] workload {args.workload} N={N} B={B}", file=sys.stderr, flush=True)
+    dev = torch.device("cuda", 0)
+    res = torch.from_numpy(ss.residues).to(dev)
+    off = torch.from_numpy(ss.offsets.view(np.int64)).to(dev)
+    ctx = kd.Context(0)
+    R = torch.empty(N, dtype=torch.float64, device=dev)
+
+    def step():
+        kset = ctx.kmer_count(res, off)
+        ctx.kmer_rank(kset, delta, out=R)
+        part = ctx.sample_partition(R, B)
+        return kset, part
+
+    for _ in range(args.warmup):
+        kset, _ = step()
+        kset.destroy()
+    torch.cuda.synchronize()
+    ctx.enable_timing(True)
+    ctx.reset_timing()
+    kset = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        if kset is not None:
+            kset.destroy()
+        kset, part = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = ctx.stage_times()
+    ctx.enable_timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    pairs = N * (N - 1) / 2
+    value = pairs / (ms_per_step / 1e3)
+
+    _, _, loff = kset.export_lists()
+    D = np.diff(loff.cpu().numpy())
+    probes = probe_count(D)
+    pair_ms, pair_n = stages["pairs"]
+    t_pair = pair_ms / max(pair_n, 1) / 1e3
+    achieved = probes / t_pair / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
+                "frac": achieved / PEAK_TPROBE, "traffic": None,
+                "kernel": "rank_pairs_kernel", "kernel_ms": t_pair * 1e3,
+                "work_per_launch": {"probes": probes, "pairs": pairs}}
+    line = {
+        "metric": METRIC, "value": value, "unit": "pair-similarities/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16/f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "N": N, "B": B, "delta": delta,
+                   "step": "kmer_count + kmer_rank + sample_partition"},
+        "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(ss, delta, args.cpu_seconds)
+    kset.destroy()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

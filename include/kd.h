@@ -1,0 +1,179 @@
+/*
+ * kd.h - C ABI of libkmerdecomp, the MI355X (gfx950) implementation of the
+ * data-parallel front end of Sample-Align-D (Saeed & Khokhar, "A Domain
+ * Decomposition Strategy for Alignment of Multiple Biological Sequences on
+ * Multiprocessor Platforms"): per-sequence k-mer counting, all-pairs k-mer
+ * similarity, the k-mer rank of every sequence, and the rank-ordered
+ * regular-sampling split of the set into B buckets.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every array argument is a DEVICE pointer (HBM of the context's GPU),
+ *    caller-owned unless stated otherwise.  Work is enqueued on the context's
+ *    stream and reads/writes happen in that stream's order; a call returns
+ *    after enqueueing unless its description says it synchronizes.
+ *  - Status codes are negative on error.  No C++ exception crosses this ABI.
+ *    On error nothing is returned through `out` parameters; output arrays
+ *    are left unspecified only where the description says so.
+ *  - One context per host thread.  Contexts are not internally synchronized
+ *    (the server object below is).
+ *  - Alphabet and word length: k = 6 over the Dayhoff-6 grouping of the 20
+ *    standard amino acids {AGPST}{C}{DENQ}{FWY}{HKR}{ILMV}; word w of a
+ *    sequence is the base-6 number of the group codes of residues w..w+5,
+ *    first residue most significant (0 <= w < 46656).  Upper-case ASCII
+ *    only; any other byte is rejected.
+ */
+#ifndef KD_H
+#define KD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kd_status;
+
+#define KD_OK 0
+#define KD_EINVAL (-1)        /* bad argument: NULL, B == 0, B > n, bad offsets, delta <= 0 ... */
+#define KD_EBADRESIDUE (-2)   /* a byte outside the 20 standard amino acids */
+#define KD_ESHORTSEQ (-3)     /* a sequence with fewer than k = 6 residues */
+#define KD_ETOOLONG (-4)      /* a sequence with more than 65535 k-mers */
+#define KD_ENOMEM (-5)        /* device allocation failed */
+#define KD_EBUSY (-6)         /* server: job does not fit the HBM budget right now */
+#define KD_EDEVICE (-7)       /* a HIP runtime error */
+#define KD_ECANCELLED (-8)    /* server: job was cancelled */
+
+#define KD_K 6
+#define KD_WORDS 46656        /* 6^6 distinct words */
+#define KD_MAX_KMERS 65535    /* per sequence: n - k + 1 must not exceed this */
+
+typedef struct kd_ctx kd_ctx;
+typedef struct kd_set kd_set;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a
+ * hipStream_t; NULL is the device's null stream, the one PyTorch uses by
+ * default).  The stream stays caller-owned.  The context owns a device
+ * memory pool that is released by kd_ctx_destroy. */
+kd_status kd_ctx_create(int device, void *hip_stream, kd_ctx **out);
+void kd_ctx_destroy(kd_ctx *ctx);
+const char *kd_strerror(kd_status status);
+/* Sequence index and residue position of the last KD_EBADRESIDUE /
+ * KD_ESHORTSEQ / KD_ETOOLONG reported on this context. */
+kd_status kd_last_error_info(const kd_ctx *ctx, uint64_t *seq, uint64_t *pos);
+/* Block until all work enqueued on the context's stream has finished. */
+kd_status kd_ctx_synchronize(kd_ctx *ctx);
+/* The hipStream_t the context enqueues on. */
+void *kd_ctx_stream(kd_ctx *ctx);
+
+/* Stage timing.  While enabled, the context records a pair of HIP events on
+ * its stream around every stage it enqueues; kd_ctx_stage_time synchronizes
+ * the stream and returns the summed elapsed milliseconds and the number of
+ * timed launches of one stage since the last reset. */
+#define KD_STAGE_COUNT 0      /* kmer_count: counting kernels */
+#define KD_STAGE_LAYOUT 1     /* kmer_count: sort by distinct words, layout */
+#define KD_STAGE_PAIRS 2      /* kmer_rank: the all-pairs kernel */
+#define KD_STAGE_FINALIZE 3   /* kmer_rank: accumulator clear + finalize */
+#define KD_STAGE_PARTITION 4  /* sample_partition */
+#define KD_STAGE_SIMILARITY 5 /* kmer_similarity */
+#define KD_NSTAGES 6
+kd_status kd_ctx_enable_timing(kd_ctx *ctx, int enable);
+kd_status kd_ctx_stage_time(kd_ctx *ctx, int stage, double *ms, uint64_t *launches);
+kd_status kd_ctx_reset_timing(kd_ctx *ctx);
+
+/* ------------------------------------------------------------- kmer_count */
+
+/* Count vectors c^X of every sequence of the set (paper, Section 3, "k-mer
+ * Rank": the vector of occurrence counts of each of the epsilon = c^k words).
+ *
+ *   residues    device u8[n_residues]: the sequences back to back (ASCII)
+ *   offsets     device u64[n_seqs+1]: sequence i is residues[offsets[i] ..
+ *               offsets[i+1]); offsets[0] = 0, offsets[n_seqs] = n_residues
+ *   n_seqs      number of sequences N (0 gives an empty set)
+ *   out         receives a library-owned, device-resident kd_set holding the
+ *               count vectors in the layout the similarity and rank calls
+ *               consume; free it with kd_set_destroy before the context.
+ *
+ * Synchronizes the stream once (to report input errors and size the set).
+ * Errors: KD_EBADRESIDUE / KD_ESHORTSEQ / KD_ETOOLONG for the lowest-indexed
+ * offending sequence (kd_last_error_info gives it and the residue position),
+ * KD_EINVAL for inconsistent offsets.  Inputs are only read; they may be
+ * reused as soon as the call returns. */
+kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                     uint32_t n_seqs, uint64_t n_residues, kd_set **out);
+
+uint32_t kd_set_size(const kd_set *set);          /* N */
+uint64_t kd_set_entries(const kd_set *set);       /* sum over sequences of distinct words */
+/* Export the count vectors as sorted nonzero entries: sequence i owns
+ * ids/counts[off[i] .. off[i+1]) in increasing word order.  ids and counts
+ * are device u16[kd_set_entries], off is device u64[N+1]. */
+kd_status kd_set_export_lists(kd_ctx *ctx, const kd_set *set, uint16_t *ids, uint16_t *counts,
+                              uint64_t *off);
+/* Export dense count vectors of sequences first..first+count-1 as a device
+ * u16[count x 46656] row-major array. */
+kd_status kd_set_export_dense(kd_ctx *ctx, const kd_set *set, uint32_t first, uint32_t count,
+                              uint16_t *out);
+void kd_set_destroy(kd_set *set);
+
+/* -------------------------------------------------------- kmer_similarity */
+
+/* Common k-mer counts of a block of pairs (Section 3: C_i = min(c^X_i, c^Y_i)
+ * summed over all words, the numerator of Equation 1) and, optionally, the
+ * Equation 1 denominators min(n, m) - k + 1.
+ *
+ *   rows r0 .. r0+nr-1 and columns c0 .. c0+nc-1 (sequence indices of `set`)
+ *   shared  device u16[nr x nc], row-major: shared[r*nc + c] for the pair
+ *           (r0 + r, c0 + c)
+ *   denom   device u16[nr x nc] or NULL
+ * Errors: KD_EINVAL when the block leaves [0, N). */
+kd_status kmer_similarity(kd_ctx *ctx, const kd_set *set, uint32_t r0, uint32_t nr, uint32_t c0,
+                          uint32_t nc, uint16_t *shared, uint16_t *denom);
+
+/* -------------------------------------------------------------- kmer_rank */
+
+/* k-mer rank of every sequence (Equation 3): R_i = (1/N) sum_{j=1..N} d(i,j),
+ * the sum running over all N sequences including i itself, with
+ * d = -ln(delta + F) (Equation 2, natural logarithm) and F the fraction of
+ * Equation 1.
+ *
+ *   delta  the paper's small positive constant (finite, > 0)
+ *   ranks  device f64[N], indexed like the input sequences
+ * The pairwise sum is accumulated exactly (fixed point), so the result does
+ * not depend on scheduling, tiling or what else runs on the device.
+ * Errors: KD_EINVAL for delta <= 0 or not finite. */
+kd_status kmer_rank(kd_ctx *ctx, const kd_set *set, double delta, double *ranks);
+
+/* -------------------------------------------------------- sample_partition */
+
+/* Regular-sampling split of n ranked sequences into B buckets (Section
+ * 3.1.2; Algorithm 2 steps 3 and 8-11), with B playing the paper's p:
+ *   1. virtual processor b holds input indices [floor(bn/B), floor((b+1)n/B))
+ *      and orders them by key (rank, index);
+ *   2. it contributes the keys at 0-based positions floor(t w_b / B),
+ *      t = 1..B-1, of its ordered block (w_b keys) as regular samples;
+ *   3. the B(B-1) samples are ordered and the ones at 0-based positions
+ *      (i-1)B + floor(B/2) - 1, i = 1..B-1, become the B-1 pivots;
+ *   4. a key goes to the bucket numbered by how many pivots lie strictly
+ *      below it, i.e. bucket b holds keys in (pivot_{b-1}, pivot_b].
+ * Keys compare by rank, then by index, so all keys are distinct.  With
+ * n >= B*B no bucket exceeds 2*ceil(n/B) sequences (Section 3.2).
+ *
+ *   ranks       device f64[n] (not NaN)
+ *   bucket      device u32[n]: bucket of sequence i
+ *   order       device u32[n]: sequence indices bucket by bucket, each
+ *               bucket in key order (equivalently: all keys in order)
+ *   offsets     device u32[B+1]: bucket b is order[offsets[b] .. offsets[b+1])
+ *   pivot_rank  device f64[B-1] or NULL; pivot_idx device u32[B-1] or NULL
+ * Errors: KD_EINVAL for n == 0, B == 0 or B > n. */
+kd_status sample_partition(kd_ctx *ctx, const double *ranks, uint32_t n, uint32_t B,
+                           uint32_t *bucket, uint32_t *order, uint32_t *offsets,
+                           double *pivot_rank, uint32_t *pivot_idx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KD_H */

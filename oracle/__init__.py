@@ -74,7 +74,7 @@ def lib():
         L.orc_similarity_block.argtypes = [P, P, P, P, C.c_uint32, C.c_uint32, C.c_uint32,
                                            C.c_uint32, P, P]
         L.orc_similarity_block.restype = None
-        L.orc_rank_rows.argtypes = [P, P, P, P, C.c_uint32, P, C.c_uint32, C.c_double, P]
+        L.orc_rank_rows.argtypes = [P, P, P, P, C.c_uint32, P, C.c_uint32, C.c_double, P, P]
         L.orc_rank_rows.restype = None
         L.orc_partition.argtypes = [P, C.c_uint32, C.c_uint32, P, P, P, P, P]
         L.orc_partition.restype = C.c_int
@@ -171,11 +171,17 @@ def similarity(L: Lists, r0: int, nr: int, c0: int, nc: int):
     return S, D
 
 
-def rank(L: Lists, delta: float, rows=None) -> np.ndarray:
+def rank(L: Lists, delta: float, rows=None, with_scale: bool = False):
+    """Equation 3 for the given rows (all rows by default).  With
+    ``with_scale`` also returns (1/N) sum_j |d(i,j)| per row."""
     N = L.n
     rows = np.arange(N, dtype=np.uint32) if rows is None else np.ascontiguousarray(rows, dtype=np.uint32)
     out = np.zeros(max(len(rows), 1), dtype=np.float64)
-    lib().orc_rank_rows(_p(L.ids), _p(L.cnt), _p(L.off), _p(L.K), N, _p(rows), len(rows), delta, _p(out))
+    sc = np.zeros(max(len(rows), 1), dtype=np.float64)
+    lib().orc_rank_rows(_p(L.ids), _p(L.cnt), _p(L.off), _p(L.K), N, _p(rows), len(rows), delta,
+                        _p(out), _p(sc))
+    if with_scale:
+        return out[:len(rows)], sc[:len(rows)]
     return out[:len(rows)]
 
 

@@ -191,11 +191,11 @@ void orc_similarity_block(const uint16_t *ids, const uint16_t *cnt, const uint64
  * below the comparison tolerance. */
 void orc_rank_rows(const uint16_t *ids, const uint16_t *cnt, const uint64_t *off,
                    const uint32_t *K, uint32_t N, const uint32_t *rows, uint32_t nrows,
-                   double delta, double *out)
+                   double delta, double *out, double *scale)
 {
     for (uint32_t q = 0; q < nrows; q++) {
         uint32_t i = rows[q];
-        double sum = 0.0, comp = 0.0;
+        double sum = 0.0, comp = 0.0, mag = 0.0;
         for (uint32_t j = 0; j < N; j++) {
             uint32_t s = orc_shared(ids + off[i], cnt + off[i], off[i + 1] - off[i],
                                     ids + off[j], cnt + off[j], off[j + 1] - off[j]);
@@ -205,8 +205,11 @@ void orc_rank_rows(const uint16_t *ids, const uint16_t *cnt, const uint64_t *off
             if (fabs(sum) >= fabs(d)) comp += (sum - t) + d;
             else comp += (d - t) + sum;
             sum = t;
+            mag += fabs(d);
         }
         out[q] = (sum + comp) / (double)N;
+        /* (1/N) sum_j |d(i,j)|: the magnitude a comparison tolerance scales with */
+        if (scale) scale[q] = mag / (double)N;
     }
 }
 

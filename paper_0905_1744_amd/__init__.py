@@ -1,0 +1,264 @@
+"""MI355X (gfx950) k-mer rank + regular-sampling decomposition.
+
+Thin ctypes binding over ``libkmerdecomp.so`` (declared in ``include/kd.h``).
+Every step runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch provides device memory and the stream: tensors passed in
+must live on the context's GPU, and results come back as CUDA tensors.
+
+    import paper_0905_1744_amd as kd
+    ctx = kd.Context()                       # on torch's current stream
+    kset = ctx.kmer_count(residues, offsets) # uint8 / int64 CUDA tensors
+    ranks = ctx.kmer_rank(kset, delta=0.1)   # float64 [N]
+    part = ctx.sample_partition(ranks, B=16) # bucket / order / offsets ...
+
+There is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # must load before the library so both share one HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkmerdecomp.so")
+_lib = None
+
+KD_OK = 0
+STATUS = {0: "KD_OK", -1: "KD_EINVAL", -2: "KD_EBADRESIDUE", -3: "KD_ESHORTSEQ",
+          -4: "KD_ETOOLONG", -5: "KD_ENOMEM", -6: "KD_EBUSY", -7: "KD_EDEVICE",
+          -8: "KD_ECANCELLED"}
+WORDS = 46656
+
+
+class KdError(RuntimeError):
+    def __init__(self, status: int, what: str, seq=None, pos=None):
+        msg = f"{what}: {STATUS.get(status, status)} ({lib().kd_strerror(status).decode()})"
+        if seq is not None:
+            msg += f" at sequence {seq}, position {pos}"
+        super().__init__(msg)
+        self.status, self.seq, self.pos = status, seq, pos
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_0905_1744_amd.build` (no CPU fallback exists)")
+    L = C.CDLL(LIB_PATH)
+    P, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32
+    PP = C.POINTER(C.c_void_p)
+    sig = {
+        "kd_ctx_create": (i32, [C.c_int, P, PP]),
+        "kd_ctx_destroy": (None, [P]),
+        "kd_strerror": (C.c_char_p, [i32]),
+        "kd_last_error_info": (i32, [P, C.POINTER(u64), C.POINTER(u64)]),
+        "kd_ctx_synchronize": (i32, [P]),
+        "kd_ctx_stream": (P, [P]),
+        "kd_ctx_enable_timing": (i32, [P, C.c_int]),
+        "kd_ctx_stage_time": (i32, [P, C.c_int, C.POINTER(C.c_double), C.POINTER(u64)]),
+        "kd_ctx_reset_timing": (i32, [P]),
+        "kmer_count": (i32, [P, P, P, u32, u64, PP]),
+        "kd_set_size": (u32, [P]),
+        "kd_set_entries": (u64, [P]),
+        "kd_set_export_lists": (i32, [P, P, P, P, P]),
+        "kd_set_export_dense": (i32, [P, P, u32, u32, P]),
+        "kd_set_destroy": (None, [P]),
+        "kmer_similarity": (i32, [P, P, u32, u32, u32, u32, P, P]),
+        "kmer_rank": (i32, [P, P, C.c_double, P]),
+        "sample_partition": (i32, [P, P, u32, u32, P, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype, f.argtypes = res, args
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev_tensor(x, dtype, device):
+    """numpy array or tensor -> contiguous CUDA tensor of the given dtype."""
+    if isinstance(x, torch.Tensor):
+        t = x
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(x))
+    if t.dtype != dtype:
+        t = t.view(dtype) if t.element_size() == torch.empty((), dtype=dtype).element_size() else t.to(dtype)
+    return t.to(device, non_blocking=False).contiguous()
+
+
+class KmerSet:
+    """Device-resident counted set (owned by the library)."""
+
+    def __init__(self, ctx: "Context", handle: C.c_void_p):
+        self.ctx, self.handle = ctx, handle
+
+    @property
+    def n(self) -> int:
+        return int(lib().kd_set_size(self.handle))
+
+    @property
+    def entries(self) -> int:
+        return int(lib().kd_set_entries(self.handle))
+
+    def export_lists(self):
+        """(ids u16, counts u16, off u64) as CUDA tensors (int16/int16/int64 storage)."""
+        dev = self.ctx.device
+        ids = torch.empty(max(self.entries, 1), dtype=torch.int16, device=dev)
+        cnt = torch.empty(max(self.entries, 1), dtype=torch.int16, device=dev)
+        off = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
+        self.ctx._check(lib().kd_set_export_lists(self.ctx.handle, self.handle, _ptr(ids), _ptr(cnt),
+                                                  _ptr(off)), "kd_set_export_lists")
+        return ids[:self.entries], cnt[:self.entries], off
+
+    def export_dense(self, first: int, count: int):
+        out = torch.empty((count, WORDS), dtype=torch.int16, device=self.ctx.device)
+        self.ctx._check(lib().kd_set_export_dense(self.ctx.handle, self.handle, first, count, _ptr(out)),
+                        "kd_set_export_dense")
+        return out
+
+    def destroy(self):
+        if self.handle:
+            lib().kd_set_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle and self.ctx.handle:
+                self.destroy()
+        except Exception:
+            pass
+
+
+class Context:
+    """A library context bound to one GPU and one HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = lib()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        out = C.c_void_p()
+        st = L.kd_ctx_create(device, C.c_void_p(h), C.byref(out))
+        if st != KD_OK:
+            raise KdError(st, "kd_ctx_create")
+        self.handle = out
+
+    def _check(self, st, what):
+        if st != KD_OK:
+            seq = pos = None
+            if st in (-2, -3, -4):
+                s, p = C.c_uint64(), C.c_uint64()
+                lib().kd_last_error_info(self.handle, C.byref(s), C.byref(p))
+                seq, pos = int(s.value), int(p.value)
+            raise KdError(st, what, seq, pos)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().kd_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    STAGES = ("count", "layout", "pairs", "finalize", "partition", "similarity")
+
+    def enable_timing(self, on: bool = True):
+        self._check(lib().kd_ctx_enable_timing(self.handle, 1 if on else 0), "kd_ctx_enable_timing")
+
+    def reset_timing(self):
+        self._check(lib().kd_ctx_reset_timing(self.handle), "kd_ctx_reset_timing")
+
+    def stage_times(self):
+        """{stage: (total_ms, launches)} since the last reset (synchronizes)."""
+        out = {}
+        for i, name in enumerate(self.STAGES):
+            ms, n = C.c_double(), C.c_uint64()
+            self._check(lib().kd_ctx_stage_time(self.handle, i, C.byref(ms), C.byref(n)), "kd_ctx_stage_time")
+            out[name] = (ms.value, int(n.value))
+        return out
+
+    def synchronize(self):
+        self._check(lib().kd_ctx_synchronize(self.handle), "kd_ctx_synchronize")
+
+    # -------------------------------------------------------------- calls
+    def kmer_count(self, residues, offsets) -> KmerSet:
+        res = _dev_tensor(residues, torch.uint8, self.device)
+        off = _dev_tensor(offsets, torch.int64, self.device)
+        n = off.numel() - 1
+        out = C.c_void_p()
+        self._check(lib().kmer_count(self.handle, _ptr(res), _ptr(off), n, res.numel(), C.byref(out)),
+                    "kmer_count")
+        return KmerSet(self, out)
+
+    def kmer_similarity(self, kset: KmerSet, r0: int, nr: int, c0: int, nc: int, denom: bool = False):
+        S = torch.empty((nr, nc), dtype=torch.int16, device=self.device)
+        Dn = torch.empty((nr, nc), dtype=torch.int16, device=self.device) if denom else None
+        self._check(lib().kmer_similarity(self.handle, kset.handle, r0, nr, c0, nc, _ptr(S), _ptr(Dn)),
+                    "kmer_similarity")
+        return (S, Dn) if denom else S
+
+    def kmer_rank(self, kset: KmerSet, delta: float = 0.1, out=None):
+        R = out if out is not None else torch.empty(kset.n, dtype=torch.float64, device=self.device)
+        self._check(lib().kmer_rank(self.handle, kset.handle, float(delta), _ptr(R)), "kmer_rank")
+        return R
+
+    def sample_partition(self, ranks, B: int):
+        R = _dev_tensor(ranks, torch.float64, self.device)
+        n = R.numel()
+        bucket = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        order = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        offsets = torch.empty(B + 1 if B > 0 else 1, dtype=torch.int32, device=self.device)
+        pr = torch.empty(max(B - 1, 1), dtype=torch.float64, device=self.device)
+        pi = torch.empty(max(B - 1, 1), dtype=torch.int32, device=self.device)
+        self._check(lib().sample_partition(self.handle, _ptr(R), n, B, _ptr(bucket), _ptr(order),
+                                           _ptr(offsets), _ptr(pr), _ptr(pi)), "sample_partition")
+        return dict(bucket=bucket[:n], order=order[:n], offsets=offsets, pivot_rank=pr[:max(B - 1, 0)],
+                    pivot_idx=pi[:max(B - 1, 0)])
+
+
+_default = None
+
+
+def default_context() -> Context:
+    global _default
+    if _default is None:
+        _default = Context()
+    return _default
+
+
+def kmer_count(residues, offsets) -> KmerSet:
+    return default_context().kmer_count(residues, offsets)
+
+
+def kmer_similarity(kset, r0, nr, c0, nc, denom=False):
+    return default_context().kmer_similarity(kset, r0, nr, c0, nc, denom)
+
+
+def kmer_rank(kset, delta=0.1, out=None):
+    return default_context().kmer_rank(kset, delta, out)
+
+
+def sample_partition(ranks, B):
+    return default_context().sample_partition(ranks, B)
+
+
+def u16(t) -> np.ndarray:
+    """CUDA int16-stored u16 tensor -> numpy uint16."""
+    return t.cpu().numpy().view(np.uint16)
+
+
+def u32(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)

@@ -1,0 +1,215 @@
+// k-mer counting (paper Section 3, "k-mer Rank": the count vector c^X of a
+// sequence over the epsilon = 6^6 words).
+//
+// Output per input sequence i, at capacity offset offsets[i] - 5i (the sum
+// of K = n - 5 over the sequences before it, so no scan is needed): its
+// distinct words in increasing order with their counts, plus D (distinct
+// words), K and the number of words seen at least twice.
+//
+// Sequences of up to 4096 words: one 64-lane workgroup each; the residues
+// are mapped through an LDS Dayhoff-6 table, the words are formed in LDS,
+// bitonic-sorted in LDS and run-length encoded with ballots.  Longer
+// sequences (rare) are queued and handled by a persistent kernel that
+// histograms into a dense 46656-bin LDS table (two 16-bit bins per word;
+// a sequence has at most 65535 words, so a bin never carries).
+#include "radix.h"
+
+namespace kd {
+
+__device__ inline unsigned long long pack_err(uint32_t seq, uint32_t code, uint64_t pos) {
+  uint64_t p = pos < (1ull << 28) ? pos : (1ull << 28) - 1;
+  return ((unsigned long long)seq << 32) | ((unsigned long long)code << 28) | p;
+}
+
+// Validate the offsets of sequence i; returns an error code or kErrNone.
+__device__ inline uint32_t check_offsets(const uint64_t *off, uint32_t i, uint32_t N, uint64_t nres,
+                                         uint64_t &o0, uint64_t &o1) {
+  o0 = off[i];
+  o1 = off[i + 1];
+  if (o1 < o0 || o1 > nres || (i + 1 == N && o1 != nres) || (i == 0 && o0 != 0)) return kErrInval;
+  if (o1 - o0 < (uint64_t)kK) return kErrShort;
+  if (o1 - o0 - (kK - 1) > 65535ull) return kErrLong;
+  return kErrNone;
+}
+
+__global__ __launch_bounds__(64) void count_short_kernel(
+    const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint32_t N, uint64_t nres,
+    uint64_t cap, uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt,
+    uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout, uint32_t *__restrict__ nhiout,
+    uint32_t *__restrict__ long_list, uint32_t *__restrict__ nlong, unsigned long long *err) {
+  __shared__ uint8_t lut[256];
+  __shared__ uint8_t codes[kShortMax + 8];
+  __shared__ uint16_t w[kShortMax];
+  __shared__ uint16_t hp[kShortMax + 1];
+  const uint32_t i = blockIdx.x;
+  const uint32_t lane = threadIdx.x;
+  for (uint32_t c = lane; c < 256; c += 64) lut[c] = dayhoff6(c);
+  uint64_t o0, o1;
+  const uint32_t code = check_offsets(off, i, N, nres, o0, o1);
+  if (code != kErrNone) {
+    if (lane == 0) atomicMin(err, pack_err(i, code, 0));
+    return;
+  }
+  const uint32_t n = (uint32_t)(o1 - o0);
+  const uint32_t K = n - (kK - 1);
+  if (K > (uint32_t)kShortMax) {
+    if (lane == 0) long_list[atomicAdd(nlong, 1u)] = i;
+    return;
+  }
+  __syncthreads();
+  uint32_t bad = 0xFFFFFFFFu;
+  for (uint32_t t = lane; t < n; t += 64) {
+    uint8_t c = lut[res[o0 + t]];
+    codes[t] = c;
+    if (c == 255 && t < bad) bad = t;
+  }
+#pragma unroll
+  for (int o = 32; o; o >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, o, 64));
+  if (bad != 0xFFFFFFFFu) {
+    if (lane == 0) atomicMin(err, pack_err(i, kErrBadResidue, bad));
+    return;
+  }
+  __syncthreads();
+  uint32_t P = 64;
+  while (P < K) P <<= 1;
+  for (uint32_t t = lane; t < P; t += 64) {
+    uint32_t v = 0xFFFFu;
+    if (t < K)
+      v = codes[t] * 7776u + codes[t + 1] * 1296u + codes[t + 2] * 216u + codes[t + 3] * 36u +
+          codes[t + 4] * 6u + codes[t + 5];
+    w[t] = (uint16_t)v;
+  }
+  __syncthreads();
+  // bitonic sort of w[0, P) (padding 0xFFFF sorts last)
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t x = lane; x < (P >> 1); x += 64) {
+        const uint32_t a = ((x & ~(j - 1)) << 1) | (x & (j - 1));
+        const uint32_t b = a | j;
+        const uint16_t va = w[a], vb = w[b];
+        const bool up = (a & k) == 0;
+        if ((va > vb) == up) {
+          w[a] = vb;
+          w[b] = va;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // run-length encode: run starts ("heads") in order
+  uint32_t D = 0;
+  for (uint32_t base = 0; base < K; base += 64) {
+    const uint32_t p = base + lane;
+    const bool valid = p < K;
+    const uint16_t v = valid ? w[p] : 0;
+    const bool head = valid && (p == 0 || w[p - 1] != v);
+    const unsigned long long m = __ballot(head);
+    if (head) hp[D + (uint32_t)__popcll(m & lanemask_lt())] = (uint16_t)p;
+    D += (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  const uint64_t co = o0 - 5ull * i;
+  const bool ok = (o0 >= 5ull * i) && (co + K <= cap);
+  uint32_t nh = 0;
+  for (uint32_t r = lane; r < D; r += 64) {
+    const uint32_t h0 = hp[r];
+    const uint32_t h1 = (r + 1 < D) ? hp[r + 1] : K;
+    const uint32_t c = h1 - h0;
+    if (ok) {
+      cap_ids[co + r] = w[h0];
+      cap_cnt[co + r] = (uint16_t)c;
+    }
+    nh += (c >= 2);
+  }
+#pragma unroll
+  for (int o = 32; o; o >>= 1) nh += (uint32_t)__shfl_xor((int)nh, o, 64);
+  if (lane == 0) {
+    Dout[i] = D;
+    Kout[i] = K;
+    nhiout[i] = nh;
+  }
+}
+
+__global__ __launch_bounds__(1024) void count_long_kernel(
+    const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint32_t N, uint64_t nres,
+    uint64_t cap, uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt,
+    uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout, uint32_t *__restrict__ nhiout,
+    const uint32_t *__restrict__ long_list, const uint32_t *__restrict__ nlong,
+    unsigned long long *err) {
+  __shared__ uint32_t hist[kWords / 2];
+  __shared__ uint8_t lut[256];
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t s_bad;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t c = tid; c < 256; c += 1024) lut[c] = dayhoff6(c);
+  const uint32_t nl = *nlong;
+  for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
+    const uint32_t i = long_list[q];
+    const uint64_t o0 = off[i], o1 = off[i + 1];
+    const uint32_t n = (uint32_t)(o1 - o0);
+    const uint32_t K = n - (kK - 1);
+    for (uint32_t x = tid; x < kWords / 2; x += 1024) hist[x] = 0;
+    if (tid == 0) s_bad = 0xFFFFFFFFu;
+    __syncthreads();
+    for (uint32_t t = tid; t < n; t += 1024)
+      if (lut[res[o0 + t]] == 255) atomicMin(&s_bad, t);
+    __syncthreads();
+    if (s_bad != 0xFFFFFFFFu) {
+      if (tid == 0) atomicMin(err, pack_err(i, kErrBadResidue, s_bad));
+      __syncthreads();
+      continue;
+    }
+    for (uint32_t t = tid; t < K; t += 1024) {
+      const uint8_t *p = res + o0 + t;
+      uint32_t v = lut[p[0]] * 7776u + lut[p[1]] * 1296u + lut[p[2]] * 216u + lut[p[3]] * 36u +
+                   lut[p[4]] * 6u + lut[p[5]];
+      atomicAdd(&hist[v >> 1], 1u << ((v & 1u) << 4));
+    }
+    __syncthreads();
+    // thread tid owns bins [46 tid, 46 tid + 46)
+    const uint32_t b0 = tid * 46u, b1 = min(b0 + 46u, (uint32_t)kWords);
+    uint32_t cnt = 0, nh = 0;
+    for (uint32_t b = b0; b < b1; b++) {
+      const uint32_t c = (hist[b >> 1] >> ((b & 1u) << 4)) & 0xFFFFu;
+      cnt += (c != 0);
+      nh += (c >= 2);
+    }
+    uint32_t D, NH;
+    uint32_t pos = block_exclusive_scan<1024>(cnt, wsum, D);
+    block_exclusive_scan<1024>(nh, wsum, NH);
+    const uint64_t co = o0 - 5ull * i;
+    const bool ok = (o0 >= 5ull * i) && (co + K <= cap);
+    for (uint32_t b = b0; b < b1; b++) {
+      const uint32_t c = (hist[b >> 1] >> ((b & 1u) << 4)) & 0xFFFFu;
+      if (c) {
+        if (ok) {
+          cap_ids[co + pos] = (uint16_t)b;
+          cap_cnt[co + pos] = (uint16_t)c;
+        }
+        pos++;
+      }
+    }
+    if (tid == 0) {
+      Dout[i] = D;
+      Kout[i] = K;
+      nhiout[i] = NH;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off, uint32_t N,
+                        uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
+                        uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig, uint32_t *long_list,
+                        uint32_t *nlong, unsigned long long *err, int cus) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(count_short_kernel, dim3(N), dim3(64), 0, st, res, off, N, nres, cap, cap_ids,
+                     cap_cnt, Dorig, Korig, nhi_orig, long_list, nlong, err);
+  KD_HIP(hipGetLastError());
+  const uint32_t grid = (uint32_t)(cus > 0 ? cus : 256);
+  hipLaunchKernelGGL(count_long_kernel, dim3(grid), dim3(1024), 0, st, res, off, N, nres, cap,
+                     cap_ids, cap_cnt, Dorig, Korig, nhi_orig, long_list, nlong, err);
+  return hipGetLastError();
+}
+
+}  // namespace kd

@@ -1,0 +1,547 @@
+// C ABI entry points (include/kd.h): argument checks, device memory, and the
+// order in which the kernels of each call are enqueued.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "kd_internal.h"
+
+using namespace kd;
+
+// ------------------------------------------------------------------ pool
+
+namespace kd {
+
+static size_t size_class(size_t b) {
+  if (b < 256) b = 256;
+  if (b <= (1u << 20)) {
+    size_t c = 256;
+    while (c < b) c <<= 1;
+    return c;
+  }
+  const size_t m = 2u << 20;
+  return (b + m - 1) / m * m;
+}
+
+void *Pool::alloc(size_t bytes) {
+  const size_t c = size_class(bytes);
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = free_.find(c);
+    if (it != free_.end() && !it->second.empty()) {
+      void *p = it->second.back();
+      it->second.pop_back();
+      live_ += c;
+      return p;
+    }
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, c) != hipSuccess) {
+    (void)hipGetLastError();
+    // release cached blocks and retry once
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto &kv : free_)
+      for (void *q : kv.second) {
+        (void)hipFree(q);
+        size_.erase(q);
+      }
+    free_.clear();
+    if (hipMalloc(&p, c) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  std::lock_guard<std::mutex> g(mu_);
+  size_[p] = c;
+  live_ += c;
+  return p;
+}
+
+void Pool::free(void *p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = size_.find(p);
+  if (it == size_.end()) return;
+  free_[it->second].push_back(p);
+  live_ -= it->second;
+}
+
+Pool::~Pool() {
+  for (auto &kv : size_) (void)hipFree(kv.first);
+}
+
+}  // namespace kd
+
+// --------------------------------------------------------------- helpers
+
+namespace {
+
+struct Scope {  // pool blocks released at scope exit (stream order makes reuse safe)
+  kd_ctx *ctx;
+  std::vector<void *> blocks;
+  explicit Scope(kd_ctx *c) : ctx(c) {}
+  template <typename T>
+  T *get(size_t count) {
+    void *p = ctx->pool->alloc(sizeof(T) * (count ? count : 1));
+    if (p) blocks.push_back(p);
+    return static_cast<T *>(p);
+  }
+  ~Scope() {
+    for (void *p : blocks) ctx->pool->free(p);
+  }
+};
+
+kd_status from_hip(hipError_t e) { return e == hipSuccess ? KD_OK : KD_EDEVICE; }
+
+#define KD_TRY(x)                             \
+  do {                                        \
+    hipError_t e_ = (x);                      \
+    if (e_ != hipSuccess) return KD_EDEVICE;  \
+  } while (0)
+
+template <typename T>
+T *set_alloc(kd_set *s, size_t count) {
+  void *p = s->ctx->pool->alloc(sizeof(T) * (count ? count : 1));
+  if (p) s->blocks.push_back(p);
+  return static_cast<T *>(p);
+}
+
+void set_free(kd_set *s) {
+  if (!s) return;
+  for (void *p : s->blocks) s->ctx->pool->free(p);
+  delete s;
+}
+
+kd_status map_err(uint32_t code) {
+  switch (code) {
+    case kErrBadResidue: return KD_EBADRESIDUE;
+    case kErrShort: return KD_ESHORTSEQ;
+    case kErrLong: return KD_ETOOLONG;
+    default: return KD_EINVAL;
+  }
+}
+
+// Records the start/end events of one stage when timing is enabled.
+struct StageTimer {
+  kd_ctx *ctx;
+  int stage;
+  hipEvent_t a = nullptr, b = nullptr;
+  static hipEvent_t take(kd_ctx *c) {
+    if (!c->ev_free.empty()) {
+      hipEvent_t e = c->ev_free.back();
+      c->ev_free.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+  StageTimer(kd_ctx *c, int s) : ctx(c), stage(s) {
+    if (!ctx->timing) return;
+    a = take(ctx);
+    b = take(ctx);
+    if (!a || !b || hipEventRecord(a, ctx->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      if (a) ctx->ev_free.push_back(a);
+      if (b) ctx->ev_free.push_back(b);
+      a = b = nullptr;
+    }
+  }
+  void done() {
+    if (!a) return;
+    if (hipEventRecord(b, ctx->stream) == hipSuccess) {
+      ctx->pending.push_back({stage, a, b});
+    } else {
+      (void)hipGetLastError();
+      ctx->ev_free.push_back(a);
+      ctx->ev_free.push_back(b);
+    }
+    a = b = nullptr;
+  }
+  ~StageTimer() {
+    if (a) ctx->ev_free.push_back(a);
+    if (b) ctx->ev_free.push_back(b);
+  }
+};
+
+void drain_timing(kd_ctx *ctx) {
+  for (auto &p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->stage_ms[p.stage] += ms;
+      ctx->stage_n[p.stage] += 1;
+    }
+    ctx->ev_free.push_back(p.a);
+    ctx->ev_free.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- context
+
+extern "C" kd_status kd_ctx_enable_timing(kd_ctx *ctx, int enable) {
+  if (!ctx) return KD_EINVAL;
+  ctx->timing = enable != 0;
+  return KD_OK;
+}
+
+extern "C" kd_status kd_ctx_stage_time(kd_ctx *ctx, int stage, double *ms, uint64_t *launches) {
+  if (!ctx || stage < 0 || stage >= KD_NSTAGES) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  drain_timing(ctx);
+  if (ms) *ms = ctx->stage_ms[stage];
+  if (launches) *launches = ctx->stage_n[stage];
+  return KD_OK;
+}
+
+extern "C" kd_status kd_ctx_reset_timing(kd_ctx *ctx) {
+  if (!ctx) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  drain_timing(ctx);
+  for (int i = 0; i < KD_NSTAGES; i++) {
+    ctx->stage_ms[i] = 0;
+    ctx->stage_n[i] = 0;
+  }
+  return KD_OK;
+}
+
+extern "C" kd_status kd_ctx_create(int device, void *hip_stream, kd_ctx **out) {
+  if (!out) return KD_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return KD_EINVAL;
+  KD_TRY(hipSetDevice(device));
+  kd_ctx *c = new (std::nothrow) kd_ctx;
+  if (!c) return KD_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;  // NULL: the null stream
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    c->cus = cus;
+  c->pool = new kd::Pool();
+  if (hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete c->pool;
+    delete c;
+    return KD_EDEVICE;
+  }
+  *out = c;
+  return KD_OK;
+}
+
+extern "C" void kd_ctx_destroy(kd_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  drain_timing(ctx);
+  for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
+  delete ctx->pool;  // frees task lists and anything still live
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+extern "C" const char *kd_strerror(kd_status s) {
+  switch (s) {
+    case KD_OK: return "ok";
+    case KD_EINVAL: return "invalid argument";
+    case KD_EBADRESIDUE: return "residue outside the 20 standard amino acids";
+    case KD_ESHORTSEQ: return "sequence shorter than k = 6";
+    case KD_ETOOLONG: return "sequence with more than 65535 k-mers";
+    case KD_ENOMEM: return "out of device memory";
+    case KD_EBUSY: return "HBM budget exhausted";
+    case KD_EDEVICE: return "HIP runtime error";
+    case KD_ECANCELLED: return "cancelled";
+    default: return "unknown status";
+  }
+}
+
+extern "C" kd_status kd_last_error_info(const kd_ctx *ctx, uint64_t *seq, uint64_t *pos) {
+  if (!ctx) return KD_EINVAL;
+  if (seq) *seq = ctx->err_seq;
+  if (pos) *pos = ctx->err_pos;
+  return KD_OK;
+}
+
+extern "C" kd_status kd_ctx_synchronize(kd_ctx *ctx) {
+  if (!ctx) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  return from_hip(hipStreamSynchronize(ctx->stream));
+}
+
+extern "C" void *kd_ctx_stream(kd_ctx *ctx) { return ctx ? (void *)ctx->stream : nullptr; }
+
+// ------------------------------------------------------------ kmer_count
+
+extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                                uint32_t n_seqs, uint64_t n_residues, kd_set **out) {
+  if (!ctx || !out) return KD_EINVAL;
+  *out = nullptr;
+  if (n_seqs > 0 && (!offsets || (!residues && n_residues > 0))) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  kd_set *s = new (std::nothrow) kd_set;
+  if (!s) return KD_ENOMEM;
+  s->ctx = ctx;
+  const uint32_t N = n_seqs;
+  s->v.N = N;
+  s->v.G = (N + 63) / 64;
+  s->v.RB = (N + 15) / 16;
+  if (N == 0) {
+    *out = s;
+    return KD_OK;
+  }
+  const hipStream_t st = ctx->stream;
+  const uint64_t cap = n_residues >= 5ull * N ? n_residues - 5ull * N : 0;
+  Scope tmp(ctx);
+  // set-owned arrays
+  uint64_t *in_off = set_alloc<uint64_t>(s, N + 1);
+  uint16_t *cap_ids = set_alloc<uint16_t>(s, cap);
+  uint16_t *cap_cnt = set_alloc<uint16_t>(s, cap);
+  uint32_t *Dorig = set_alloc<uint32_t>(s, N);
+  uint32_t *perm = set_alloc<uint32_t>(s, N);
+  uint32_t *inv = set_alloc<uint32_t>(s, N);
+  uint32_t *K = set_alloc<uint32_t>(s, N);
+  uint32_t *D = set_alloc<uint32_t>(s, N);
+  uint32_t *hi_off = set_alloc<uint32_t>(s, N + 1);
+  uint64_t *grp_off = set_alloc<uint64_t>(s, s->v.G + 1);
+  uint32_t *grp_len = set_alloc<uint32_t>(s, s->v.G);
+  uint32_t *exc_off = set_alloc<uint32_t>(s, s->v.RB + 1);
+  uint32_t *exc_n = set_alloc<uint32_t>(s, s->v.RB);
+  long long *acc = set_alloc<long long>(s, 3ull * N);
+  SetView *d_view = set_alloc<SetView>(s, 1);
+  // temporaries
+  uint32_t *Korig = tmp.get<uint32_t>(N);
+  uint32_t *nhi_orig = tmp.get<uint32_t>(N);
+  uint32_t *long_list = tmp.get<uint32_t>(N);
+  uint32_t *sortk = tmp.get<uint32_t>(2ull * N);
+  uint32_t *sortv = tmp.get<uint32_t>(2ull * N);
+  unsigned long long *small = tmp.get<unsigned long long>(8);  // [0] err, [1] nlong
+  LayoutMeta *meta = tmp.get<LayoutMeta>(1);
+  if (!in_off || !cap_ids || !cap_cnt || !Dorig || !perm || !inv || !K || !D || !hi_off ||
+      !grp_off || !grp_len || !exc_off || !exc_n || !acc || !d_view || !Korig || !nhi_orig ||
+      !long_list || !sortk || !sortv || !small || !meta) {
+    set_free(s);
+    return KD_ENOMEM;
+  }
+  unsigned long long *err = small;
+  uint32_t *nlong = reinterpret_cast<uint32_t *>(small + 1);
+  hipError_t e = launch_fill_u64(st, small, 1, ~0ull);
+  if (e == hipSuccess) e = launch_fill_u64(st, small + 1, 1, 0ull);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(in_off, offsets, sizeof(uint64_t) * (N + 1), hipMemcpyDeviceToDevice, st);
+  StageTimer t_count(ctx, KD_STAGE_COUNT);
+  if (e == hipSuccess)
+    e = launch_count(st, residues, offsets, N, n_residues, cap, cap_ids, cap_cnt, Dorig, Korig,
+                     nhi_orig, long_list, nlong, err, ctx->cus);
+  t_count.done();
+  StageTimer t_layout(ctx, KD_STAGE_LAYOUT);
+  if (e == hipSuccess) e = launch_sort_u32_index(st, Dorig, N, 16, perm, sortk, sortv);
+  if (e == hipSuccess)
+    e = launch_layout_meta(st, N, perm, Dorig, Korig, nhi_orig, inv, K, D, hi_off, grp_off,
+                           grp_len, exc_off, err, meta);
+  t_layout.done();
+  LayoutMeta *hm = static_cast<LayoutMeta *>(ctx->pinned);
+  if (e == hipSuccess) e = hipMemcpyAsync(hm, meta, sizeof(LayoutMeta), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    set_free(s);
+    return KD_EDEVICE;
+  }
+  if (hm->err != ~0ull) {
+    ctx->err_seq = hm->err >> 32;
+    ctx->err_pos = hm->err & ((1ull << 28) - 1);
+    const uint32_t code = (uint32_t)((hm->err >> 28) & 0xF);
+    set_free(s);
+    return map_err(code);
+  }
+  s->entries = hm->entries;
+  s->cap = cap;
+  s->n_hi = hm->n_hi;
+  s->n_gids = hm->n_gids;
+  s->n_exc = hm->n_exc;
+  uint16_t *gids = set_alloc<uint16_t>(s, s->n_gids);
+  uint16_t *hi_ids = set_alloc<uint16_t>(s, s->n_hi);
+  uint16_t *hi_cnt = set_alloc<uint16_t>(s, s->n_hi);
+  uint16_t *exc_ids = set_alloc<uint16_t>(s, s->n_exc);
+  uint16_t *exc_cnt = set_alloc<uint16_t>(s, 16ull * s->n_exc);
+  if (!gids || !hi_ids || !hi_cnt || !exc_ids || !exc_cnt) {
+    set_free(s);
+    return KD_ENOMEM;
+  }
+  SetView &v = s->v;
+  v.perm = perm;
+  v.inv = inv;
+  v.K = K;
+  v.D = D;
+  v.grp_off = grp_off;
+  v.grp_len = grp_len;
+  v.gids = gids;
+  v.hi_off = hi_off;
+  v.hi_ids = hi_ids;
+  v.hi_cnt = hi_cnt;
+  v.exc_off = exc_off;
+  v.exc_n = exc_n;
+  v.exc_ids = exc_ids;
+  v.exc_cnt = exc_cnt;
+  v.acc = acc;
+  s->cap_ids = cap_ids;
+  s->cap_cnt = cap_cnt;
+  s->Dorig = Dorig;
+  s->in_off = in_off;
+  s->d_view = d_view;
+  StageTimer t_fill(ctx, KD_STAGE_LAYOUT);
+  e = launch_layout_fill(st, v, in_off, cap_ids, cap_cnt, gids, hi_ids, hi_cnt);
+  if (e == hipSuccess) e = launch_exc_build(st, v, v.RB, nullptr, exc_off, exc_n, exc_ids, exc_cnt);
+  if (e == hipSuccess) e = launch_store_view(st, v, d_view);
+  t_fill.done();
+  if (e != hipSuccess) {
+    set_free(s);
+    return KD_EDEVICE;
+  }
+  *out = s;
+  return KD_OK;
+}
+
+extern "C" uint32_t kd_set_size(const kd_set *s) { return s ? s->v.N : 0; }
+extern "C" uint64_t kd_set_entries(const kd_set *s) { return s ? s->entries : 0; }
+
+extern "C" void kd_set_destroy(kd_set *s) {
+  if (!s) return;
+  (void)hipSetDevice(s->ctx->device);
+  set_free(s);
+}
+
+extern "C" kd_status kd_set_export_lists(kd_ctx *ctx, const kd_set *s, uint16_t *ids,
+                                         uint16_t *counts, uint64_t *off) {
+  if (!ctx || !s || !off || (s->entries && (!ids || !counts))) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  return from_hip(launch_export_lists(ctx->stream, s, ids, counts, off));
+}
+
+extern "C" kd_status kd_set_export_dense(kd_ctx *ctx, const kd_set *s, uint32_t first,
+                                         uint32_t count, uint16_t *out) {
+  if (!ctx || !s || (uint64_t)first + count > s->v.N || (count && !out)) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  return from_hip(launch_export_dense(ctx->stream, s, first, count, out));
+}
+
+// ------------------------------------------------------- kmer_similarity
+
+extern "C" kd_status kmer_similarity(kd_ctx *ctx, const kd_set *s, uint32_t r0, uint32_t nr,
+                                     uint32_t c0, uint32_t nc, uint16_t *shared, uint16_t *denom) {
+  if (!ctx || !s) return KD_EINVAL;
+  const uint32_t N = s->v.N;
+  if ((uint64_t)r0 + nr > N || (uint64_t)c0 + nc > N) return KD_EINVAL;
+  if (nr == 0 || nc == 0) return KD_OK;
+  if (!shared) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  Scope tmp(ctx);
+  const uint32_t nb = (nr + 15) / 16;
+  uint32_t *rowpos = tmp.get<uint32_t>(16ull * nb);
+  uint32_t *colpos = tmp.get<uint32_t>((nc + 15) / 16 * 16ull);
+  uint32_t *exc_off = tmp.get<uint32_t>(nb + 1);
+  uint32_t *exc_n = tmp.get<uint32_t>(nb);
+  uint16_t *exc_ids = tmp.get<uint16_t>(s->n_hi);
+  uint16_t *exc_cnt = tmp.get<uint16_t>(16ull * s->n_hi);
+  if (!rowpos || !colpos || !exc_off || !exc_n || !exc_ids || !exc_cnt) return KD_ENOMEM;
+  KD_TRY(launch_map_positions(st, s->v.inv, r0, nr, rowpos));
+  KD_TRY(launch_map_positions(st, s->v.inv, c0, nc, colpos));
+  StageTimer t(ctx, KD_STAGE_SIMILARITY);
+  KD_TRY(launch_exc_offsets(st, s->v, rowpos, nr, exc_off));
+  KD_TRY(launch_exc_build(st, s->v, nb, rowpos, exc_off, exc_n, exc_ids, exc_cnt));
+  KD_TRY(launch_similarity(st, s->v, rowpos, nr, colpos, nc, exc_off, exc_n, exc_ids, exc_cnt,
+                           shared, denom));
+  t.done();
+  return KD_OK;
+}
+
+// ------------------------------------------------------------- kmer_rank
+
+namespace {
+
+// Work list of the rank kernel for a set of N sequences: every row block
+// pairs with the column groups holding sorted positions below its last row,
+// cut into chunks of `cg` groups; longest chunks first.
+std::vector<PairTask> make_tasks(uint32_t N, uint32_t cg, uint32_t set_index) {
+  std::vector<PairTask> t;
+  const uint32_t RB = (N + 15) / 16, G = (N + 63) / 64;
+  for (uint32_t rb = 0; rb < RB; rb++) {
+    const uint32_t ng = std::min(G, (16u * rb + 14u) / 64u + 1u);
+    for (uint32_t g0 = 0; g0 < ng; g0 += cg) t.push_back({set_index, rb, g0, std::min(g0 + cg, ng)});
+  }
+  std::stable_sort(t.begin(), t.end(), [](const PairTask &a, const PairTask &b) {
+    const uint32_t la = a.g1 - a.g0, lb = b.g1 - b.g0;
+    if (la != lb) return la > lb;
+    return a.g0 > b.g0;
+  });
+  return t;
+}
+
+kd_status get_tasks(kd_ctx *ctx, uint32_t N, uint32_t cg, PairTask **d, uint32_t *n) {
+  auto key = std::make_pair(N, cg);
+  auto it = ctx->task_cache.find(key);
+  if (it != ctx->task_cache.end()) {
+    *d = it->second.first;
+    *n = it->second.second;
+    return KD_OK;
+  }
+  std::vector<PairTask> t = make_tasks(N, cg, 0);
+  PairTask *p = static_cast<PairTask *>(ctx->pool->alloc(sizeof(PairTask) * (t.size() + 1)));
+  if (!p) return KD_ENOMEM;
+  if (hipMemcpy(p, t.data(), sizeof(PairTask) * t.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    ctx->pool->free(p);
+    return KD_EDEVICE;
+  }
+  ctx->task_cache[key] = std::make_pair(p, (uint32_t)t.size());
+  *d = p;
+  *n = (uint32_t)t.size();
+  return KD_OK;
+}
+
+}  // namespace
+
+extern "C" kd_status kmer_rank(kd_ctx *ctx, const kd_set *s, double delta, double *ranks) {
+  if (!ctx || !s) return KD_EINVAL;
+  if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
+  if (s->v.N == 0) return KD_OK;
+  if (!ranks) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  PairTask *tasks = nullptr;
+  uint32_t ntasks = 0;
+  kd_status rc = get_tasks(ctx, s->v.N, 16, &tasks, &ntasks);
+  if (rc != KD_OK) return rc;
+  const hipStream_t st = ctx->stream;
+  StageTimer t0(ctx, KD_STAGE_FINALIZE);
+  KD_TRY(launch_fill_u64(st, s->v.acc, 3ull * s->v.N, 0));
+  t0.done();
+  StageTimer t1(ctx, KD_STAGE_PAIRS);
+  KD_TRY(launch_rank_pairs(st, s->d_view, tasks, ntasks, delta));
+  t1.done();
+  StageTimer t2(ctx, KD_STAGE_FINALIZE);
+  KD_TRY(launch_rank_finalize(st, s->v, delta, ranks));
+  t2.done();
+  return KD_OK;
+}
+
+// ------------------------------------------------------ sample_partition
+
+extern "C" kd_status sample_partition(kd_ctx *ctx, const double *ranks, uint32_t n, uint32_t B,
+                                      uint32_t *bucket, uint32_t *order, uint32_t *offsets,
+                                      double *pivot_rank, uint32_t *pivot_idx) {
+  if (!ctx || !ranks || !bucket || !order || !offsets) return KD_EINVAL;
+  if (n == 0 || B == 0 || B > n || B > kMaxBuckets) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  Scope tmp(ctx);
+  void *scratch = tmp.get<char>(partition_scratch_bytes(n, B));
+  if (!scratch) return KD_ENOMEM;
+  StageTimer t(ctx, KD_STAGE_PARTITION);
+  KD_TRY(launch_partition(ctx->stream, ranks, n, B, bucket, order, offsets, pivot_rank, pivot_idx,
+                          scratch));
+  t.done();
+  return KD_OK;
+}

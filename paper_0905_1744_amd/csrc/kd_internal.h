@@ -1,0 +1,245 @@
+// Internal declarations of libkmerdecomp: device layout of a counted set,
+// constants of the word space, the device memory pool, kernel launchers and
+// the small device helpers several kernels share.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kd.h"
+
+namespace kd {
+
+// ---------------------------------------------------------------- constants
+
+constexpr int kK = 6;                 // word length
+constexpr int kWords = 46656;         // 6^6
+constexpr uint16_t kSentinel = 46656; // padding word: its table entry stays 0
+constexpr int kTableWords = 23329;    // u32 words holding 46658 u16 table slots
+constexpr int kBitmapWords = 1458;    // 46656 bits
+constexpr int kRowsPerBlock = 16;     // rows sharing one LDS presence table
+constexpr int kGroup = 64;            // columns per interleaved group (one per lane)
+constexpr int kShortMax = 4096;       // words per sequence handled by the one-wave counter
+constexpr int kFixFrac = 72;          // fractional bits of the exact rank accumulator
+constexpr uint32_t kMaxBuckets = 1024; // sample_partition: B(B-1) samples stay small
+
+// error word written by the counting kernels: (seq << 32) | (code << 28) | pos
+enum : uint32_t { kErrNone = 0, kErrInval = 1, kErrBadResidue = 2, kErrShort = 3, kErrLong = 4 };
+
+// ----------------------------------------------------------- device layout
+
+// A counted set in device memory.  Sequences are re-ordered by ascending
+// number of distinct words (ties by input index); "sorted position" s refers
+// to that order, perm[s] is the input index and inv[i] its inverse.
+struct SetView {
+  uint32_t N;
+  uint32_t G;                  // column groups: ceil(N / 64)
+  uint32_t RB;                 // row blocks: ceil(N / 16)
+  uint32_t pad;
+  const uint32_t *perm;        // [N] sorted position -> input index
+  const uint32_t *inv;         // [N] input index -> sorted position
+  const uint32_t *K;           // [N] words per sequence (n - 5), sorted order
+  const uint32_t *D;           // [N] distinct words, sorted order
+  const uint64_t *grp_off;     // [G+1] u16-element offset of each group in gids
+  const uint32_t *grp_len;     // [G] padded list length of the group (multiple of 8)
+  const uint16_t *gids;        // interleaved distinct words: element t of the
+                               // sequence in lane l of group g lives at
+                               // grp_off[g] + ((t/8)*64 + l)*8 + t%8
+  const uint32_t *hi_off;      // [N+1] entries with count >= 2, sorted order
+  const uint16_t *hi_ids;
+  const uint16_t *hi_cnt;
+  const uint32_t *exc_off;     // [RB+1] per row block: merged count>=2 words
+  const uint32_t *exc_n;       // [RB] used entries in the block's range
+  const uint16_t *exc_ids;     // [cap] sorted words
+  const uint16_t *exc_cnt;     // [cap*16] count of the word in each of the 16 rows
+  long long *acc;              // [3*N] exact rank accumulators (40-bit limbs)
+};
+
+struct PairTask {  // one workgroup's work in the rank kernel
+  uint32_t set;    // index into the SetView array
+  uint32_t rb;     // row block
+  uint32_t g0, g1; // column groups [g0, g1)
+};
+
+// ---------------------------------------------------------- host objects
+
+class Pool {  // caching device allocator (one per context)
+ public:
+  Pool() = default;
+  ~Pool();
+  void *alloc(size_t bytes);
+  void free(void *p);
+  size_t live_bytes() const { return live_; }
+
+ private:
+  std::mutex mu_;
+  std::map<size_t, std::vector<void *>> free_;
+  std::map<void *, size_t> size_;
+  size_t live_ = 0;
+};
+
+}  // namespace kd
+
+struct kd_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;  // caller's stream (nullptr: null stream)
+  kd::Pool *pool = nullptr;
+  uint64_t err_seq = 0, err_pos = 0;
+  int cus = 256;
+  // cached rank task lists keyed by (N, groups per task)
+  std::map<std::pair<uint32_t, uint32_t>, std::pair<kd::PairTask *, uint32_t>> task_cache;
+  void *pinned = nullptr;         // small pinned staging area
+  // stage timing (kd_ctx_enable_timing)
+  bool timing = false;
+  struct Pending { int stage; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_free;  // recycled timing events
+  double stage_ms[KD_NSTAGES] = {0};
+  uint64_t stage_n[KD_NSTAGES] = {0};
+};
+
+struct kd_set {
+  kd_ctx *ctx = nullptr;
+  kd::SetView v{};
+  kd::SetView *d_view = nullptr;  // device copy of v
+  uint64_t entries = 0;   // sum of D
+  uint64_t cap = 0;       // sum of K
+  uint64_t n_hi = 0;      // entries with count >= 2
+  uint64_t n_gids = 0;
+  uint64_t n_exc = 0;
+  std::vector<void *> blocks;  // pool blocks owned by the set
+  // per-input-index lists as produced by counting (kept for export):
+  // sequence i at cap_ids/cap_cnt[in_off[i] - 5i ...], Dorig[i] entries
+  uint16_t *cap_ids = nullptr, *cap_cnt = nullptr;
+  uint32_t *Dorig = nullptr;
+  uint64_t *in_off = nullptr;
+};
+
+namespace kd {
+
+// ------------------------------------------------------------ launchers
+
+hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off, uint32_t N,
+                        uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
+                        uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig, uint32_t *long_list,
+                        uint32_t *nlong, unsigned long long *err, int cus);
+
+// stable sort of (key u32 < 2^bits, value = index) for N entries; writes perm
+hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, uint32_t N, int bits,
+                                 uint32_t *perm, uint32_t *scratch_keys, uint32_t *scratch_vals);
+
+struct LayoutMeta {  // totals written by layout_meta, read by the host
+  unsigned long long err;
+  unsigned long long n_hi;
+  unsigned long long n_gids;
+  unsigned long long n_exc;
+  unsigned long long entries;
+};
+
+hipError_t launch_layout_meta(hipStream_t st, uint32_t N, const uint32_t *perm,
+                              const uint32_t *Dorig, const uint32_t *Korig,
+                              const uint32_t *nhi_orig, uint32_t *inv, uint32_t *K, uint32_t *D,
+                              uint32_t *hi_off, uint64_t *grp_off, uint32_t *grp_len,
+                              uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta);
+
+hipError_t launch_layout_fill(hipStream_t st, const SetView &v, const uint64_t *offsets,
+                              const uint16_t *cap_ids, const uint16_t *cap_cnt,
+                              uint16_t *gids, uint16_t *hi_ids, uint16_t *hi_cnt);
+
+// merged count>=2 words of row blocks; rowpos == nullptr means block b holds
+// sorted positions 16b..16b+15
+hipError_t launch_exc_build(hipStream_t st, const SetView &v, uint32_t nblocks,
+                            const uint32_t *rowpos, const uint32_t *exc_off, uint32_t *exc_n,
+                            uint16_t *exc_ids, uint16_t *exc_cnt);
+
+hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairTask *tasks,
+                             uint32_t ntasks, double delta);
+hipError_t launch_rank_finalize(hipStream_t st, const SetView &v, double delta, double *ranks);
+hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);
+
+hipError_t launch_similarity(hipStream_t st, const SetView &v, const uint32_t *rowpos,
+                             uint32_t nr, const uint32_t *colpos, uint32_t nc,
+                             const uint32_t *exc_off, const uint32_t *exc_n,
+                             const uint16_t *exc_ids, const uint16_t *exc_cnt, uint16_t *shared,
+                             uint16_t *denom);
+hipError_t launch_map_positions(hipStream_t st, const uint32_t *inv, uint32_t first, uint32_t n,
+                                uint32_t *pos);
+hipError_t launch_exc_offsets(hipStream_t st, const SetView &v, const uint32_t *rowpos,
+                              uint32_t nrows, uint32_t *exc_off);
+
+hipError_t launch_export_lists(hipStream_t st, const kd_set *s, uint16_t *ids, uint16_t *counts,
+                               uint64_t *off);
+hipError_t launch_store_view(hipStream_t st, const SetView &v, SetView *dst);
+hipError_t launch_export_dense(hipStream_t st, const kd_set *s, uint32_t first, uint32_t count,
+                               uint16_t *out);
+
+// scratch needed by launch_partition for n keys and B buckets (bytes)
+size_t partition_scratch_bytes(uint32_t n, uint32_t B);
+hipError_t launch_partition(hipStream_t st, const double *ranks, uint32_t n, uint32_t B,
+                            uint32_t *bucket, uint32_t *order, uint32_t *offsets,
+                            double *pivot_rank, uint32_t *pivot_idx, void *scratch);
+
+// ------------------------------------------------------- device helpers
+
+#ifdef __HIPCC__
+
+__host__ __device__ inline uint8_t dayhoff6(uint32_t ch) {
+  switch (ch) {
+    case 'A': case 'G': case 'P': case 'S': case 'T': return 0;
+    case 'C': return 1;
+    case 'D': case 'E': case 'N': case 'Q': return 2;
+    case 'F': case 'W': case 'Y': return 3;
+    case 'H': case 'K': case 'R': return 4;
+    case 'I': case 'L': case 'M': case 'V': return 5;
+    default: return 255;
+  }
+}
+
+// Split trunc(v * 2^72) (two's complement, |v| < 2^47) into 40-bit limbs
+// l0, l1 >= 0 and signed l2 with value = l0 + l1*2^40 + l2*2^80.  Sums of
+// limbs are exact integer sums, so accumulating them is order independent.
+__device__ inline void fix_limbs(double v, long long &l0, long long &l1, long long &l2) {
+  unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  unsigned e = (unsigned)((bits >> 52) & 0x7ff);
+  if (e == 0) { l0 = l1 = l2 = 0; return; }
+  unsigned long long m = (bits & ((1ull << 52) - 1)) | (1ull << 52);
+  int sh = (int)e - 1075 + kFixFrac;
+  unsigned __int128 T;
+  if (sh >= 0) T = (unsigned __int128)m << sh;
+  else if (sh > -64) T = (unsigned __int128)(m >> (-sh));
+  else T = 0;
+  __int128 S = (bits >> 63) ? -(__int128)T : (__int128)T;
+  l0 = (long long)(S & (__int128)0xFFFFFFFFFFll);
+  l1 = (long long)((S >> 40) & (__int128)0xFFFFFFFFFFll);
+  l2 = (long long)(S >> 80);
+}
+
+__device__ inline double fix_to_double(long long s0, long long s1, long long s2) {
+  __int128 T = ((__int128)s2 << 80) + ((__int128)s1 << 40) + (__int128)s0;
+  bool neg = T < 0;
+  unsigned __int128 M = neg ? (unsigned __int128)(-T) : (unsigned __int128)T;
+  double hi = (double)(unsigned long long)(M >> 64);
+  double lo = (double)(unsigned long long)M;
+  double r = hi * 0x1p64 + lo;
+  r *= 0x1p-72;
+  return neg ? -r : r;
+}
+
+__device__ inline unsigned long long lanemask_lt() {
+  return (1ull << __lane_id()) - 1ull;
+}
+
+#endif  // __HIPCC__
+
+}  // namespace kd
+
+#define KD_HIP(x)                                  \
+  do {                                             \
+    hipError_t e_ = (x);                           \
+    if (e_ != hipSuccess) return e_;               \
+  } while (0)

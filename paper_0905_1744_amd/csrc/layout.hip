@@ -1,0 +1,396 @@
+// Device layout of a counted set.
+//
+// Sequences are re-ordered by ascending number of distinct words D (ties by
+// input index).  In that order:
+//  * column groups of 64 consecutive sequences store their distinct words
+//    interleaved (lane l = sequence 64g + l; 8 words per lane per 16-byte
+//    chunk; chunks of the 64 lanes adjacent), each list padded with a
+//    sentinel word up to the group's longest list rounded to 16, so one
+//    wave reads 64 lists with fully coalesced 16-byte loads;
+//  * entries with count >= 2 are kept in a separate short CSR list;
+//  * every row block of 16 sequences gets the merged, sorted set of words
+//    that some row of the block holds at least twice, with the 16 counts.
+#include "radix.h"
+
+namespace kd {
+
+__global__ __launch_bounds__(1024) void sort_u32_index_kernel(const uint32_t *__restrict__ keys,
+                                                              uint32_t N, int bits,
+                                                              uint32_t *__restrict__ perm,
+                                                              uint32_t *k0, uint32_t *v0,
+                                                              uint32_t *k1, uint32_t *v1) {
+  __shared__ RadixShared<1024> sh;
+  for (uint32_t i = threadIdx.x; i < N; i += 1024) {
+    k0[i] = keys[i];
+    v0[i] = i;
+  }
+  __syncthreads();
+  const int where = block_radix_sort<1024, uint32_t>(k0, v0, k1, v1, N, 0, bits, sh);
+  const uint32_t *src = where ? v1 : v0;
+  for (uint32_t i = threadIdx.x; i < N; i += 1024) perm[i] = src[i];
+}
+
+hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, uint32_t N, int bits,
+                                 uint32_t *perm, uint32_t *scratch_keys, uint32_t *scratch_vals) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(sort_u32_index_kernel, dim3(1), dim3(1024), 0, st, keys, N, bits, perm,
+                     scratch_keys, scratch_vals, scratch_keys + N, scratch_vals + N);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(1024) void layout_meta_kernel(
+    uint32_t N, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ Dorig,
+    const uint32_t *__restrict__ Korig, const uint32_t *__restrict__ nhi_orig,
+    uint32_t *__restrict__ inv, uint32_t *__restrict__ K, uint32_t *__restrict__ D,
+    uint32_t *__restrict__ hi_off, uint64_t *__restrict__ grp_off, uint32_t *__restrict__ grp_len,
+    uint32_t *__restrict__ exc_off, const unsigned long long *err, LayoutMeta *meta) {
+  __shared__ uint32_t wsum[16];
+  __shared__ unsigned long long wsum64[16];
+  const uint32_t tid = threadIdx.x;
+  if (*err != ~0ull) {  // counting failed: report only the error
+    if (tid == 0) {
+      meta->err = *err;
+      meta->n_hi = meta->n_gids = meta->n_exc = meta->entries = 0;
+    }
+    return;
+  }
+  unsigned long long entries = 0;
+  // per sorted position: K, D, inverse permutation, count>=2 prefix
+  uint32_t carry = 0;
+  for (uint32_t b = 0; b < N; b += 1024) {
+    const uint32_t s = b + tid;
+    uint32_t h = 0;
+    if (s < N) {
+      const uint32_t i = perm[s];
+      inv[i] = s;
+      K[s] = Korig[i];
+      D[s] = Dorig[i];
+      entries += Dorig[i];
+      h = nhi_orig[i];
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<1024>(h, wsum, tot);
+    if (s < N) hi_off[s] = carry + ex;
+    carry += tot;
+  }
+  if (tid == 0) hi_off[N] = carry;
+  __syncthreads();
+  // column groups
+  const uint32_t G = (N + 63) / 64;
+  unsigned long long gcarry = 0;
+  for (uint32_t b = 0; b < G; b += 1024) {
+    const uint32_t g = b + tid;
+    unsigned long long sz = 0;
+    if (g < G) {
+      const uint32_t last = min(64u * g + 63u, N - 1);
+      const uint32_t L = (D[last] + 15u) & ~15u;
+      grp_len[g] = L;
+      sz = 64ull * L;
+    }
+    unsigned long long tot;
+    const unsigned long long ex = block_exclusive_scan64<1024>(sz, wsum64, tot);
+    if (g < G) grp_off[g] = gcarry + ex;
+    gcarry += tot;
+  }
+  if (tid == 0) grp_off[G] = gcarry;
+  __syncthreads();
+  // row blocks: capacity for merged count>=2 words = sum over the 16 rows
+  const uint32_t RB = (N + 15) / 16;
+  uint32_t ecarry = 0;
+  for (uint32_t b = 0; b < RB; b += 1024) {
+    const uint32_t rb = b + tid;
+    uint32_t c = 0;
+    if (rb < RB) {
+      const uint32_t s0 = 16u * rb, s1 = min(s0 + 16u, N);
+      c = hi_off[s1] - hi_off[s0];
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<1024>(c, wsum, tot);
+    if (rb < RB) exc_off[rb] = ecarry + ex;
+    ecarry += tot;
+  }
+  if (tid == 0) exc_off[RB] = ecarry;
+  // total entries
+  unsigned long long et;
+  block_exclusive_scan64<1024>(entries, wsum64, et);
+  if (tid == 0) {
+    meta->err = ~0ull;
+    meta->n_hi = carry;
+    meta->n_gids = gcarry;
+    meta->n_exc = ecarry;
+    meta->entries = et;
+  }
+}
+
+hipError_t launch_layout_meta(hipStream_t st, uint32_t N, const uint32_t *perm,
+                              const uint32_t *Dorig, const uint32_t *Korig,
+                              const uint32_t *nhi_orig, uint32_t *inv, uint32_t *K, uint32_t *D,
+                              uint32_t *hi_off, uint64_t *grp_off, uint32_t *grp_len,
+                              uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta) {
+  hipLaunchKernelGGL(layout_meta_kernel, dim3(1), dim3(1024), 0, st, N, perm, Dorig, Korig,
+                     nhi_orig, inv, K, D, hi_off, grp_off, grp_len, exc_off, err, meta);
+  return hipGetLastError();
+}
+
+// One 64-lane workgroup per column group: lane l copies the distinct words of
+// sorted position 64g + l into the interleaved layout (16-byte stores, the
+// 64 lanes' chunks adjacent).
+__global__ __launch_bounds__(64) void layout_groups_kernel(SetView v,
+                                                           const uint64_t *__restrict__ offsets,
+                                                           const uint16_t *__restrict__ cap_ids,
+                                                           uint16_t *__restrict__ gids) {
+  const uint32_t g = blockIdx.x, lane = threadIdx.x;
+  const uint32_t s = 64u * g + lane;
+  const uint32_t L = v.grp_len[g];
+  uint32_t Dl = 0;
+  const uint16_t *src = nullptr;
+  if (s < v.N) {
+    const uint32_t i = v.perm[s];
+    src = cap_ids + (offsets[i] - 5ull * i);
+    Dl = v.D[s];
+  }
+  uint4 *dst = reinterpret_cast<uint4 *>(gids + v.grp_off[g]) + lane;
+  for (uint32_t t8 = 0; t8 < L / 8; t8++) {
+    uint32_t e[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const uint32_t t = t8 * 8 + u;
+      e[u] = t < Dl ? src[t] : kSentinel;
+    }
+    uint4 q;
+    q.x = e[0] | (e[1] << 16);
+    q.y = e[2] | (e[3] << 16);
+    q.z = e[4] | (e[5] << 16);
+    q.w = e[6] | (e[7] << 16);
+    dst[(size_t)t8 * 64] = q;
+  }
+}
+
+// One wave per sorted position: entries with count >= 2, compacted in order.
+__global__ __launch_bounds__(256) void layout_hi_kernel(SetView v,
+                                                        const uint64_t *__restrict__ offsets,
+                                                        const uint16_t *__restrict__ cap_ids,
+                                                        const uint16_t *__restrict__ cap_cnt,
+                                                        uint16_t *__restrict__ hi_ids,
+                                                        uint16_t *__restrict__ hi_cnt) {
+  const uint32_t s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (s >= v.N) return;
+  const uint32_t i = v.perm[s];
+  const uint64_t co = offsets[i] - 5ull * i;
+  const uint32_t Dl = v.D[s];
+  uint32_t o = v.hi_off[s];
+  for (uint32_t b = 0; b < Dl; b += 64) {
+    const uint32_t t = b + lane;
+    uint16_t id = 0, c = 0;
+    if (t < Dl) {
+      id = cap_ids[co + t];
+      c = cap_cnt[co + t];
+    }
+    const bool f = t < Dl && c >= 2;
+    const unsigned long long m = __ballot(f);
+    if (f) {
+      const uint32_t p = o + (uint32_t)__popcll(m & lanemask_lt());
+      hi_ids[p] = id;
+      hi_cnt[p] = c;
+    }
+    o += (uint32_t)__popcll(m);
+  }
+}
+
+hipError_t launch_layout_fill(hipStream_t st, const SetView &v, const uint64_t *offsets,
+                              const uint16_t *cap_ids, const uint16_t *cap_cnt, uint16_t *gids,
+                              uint16_t *hi_ids, uint16_t *hi_cnt) {
+  if (v.N == 0) return hipSuccess;
+  hipLaunchKernelGGL(layout_groups_kernel, dim3(v.G), dim3(64), 0, st, v, offsets, cap_ids, gids);
+  KD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(layout_hi_kernel, dim3((v.N + 3) / 4), dim3(256), 0, st, v, offsets, cap_ids,
+                     cap_cnt, hi_ids, hi_cnt);
+  return hipGetLastError();
+}
+
+// Merged count>=2 words of row blocks.  A quarter-wave (16 lanes, one per
+// row) merges one block: each lane walks its row's sorted list, the quarter
+// agrees on the smallest pending word, and every lane writes its row's
+// count for it (0 when the row lacks it).
+__global__ __launch_bounds__(256) void exc_build_kernel(SetView v, uint32_t nblocks,
+                                                        const uint32_t *__restrict__ rowpos,
+                                                        const uint32_t *__restrict__ exc_off,
+                                                        uint32_t *__restrict__ exc_n,
+                                                        uint16_t *__restrict__ exc_ids,
+                                                        uint16_t *__restrict__ exc_cnt) {
+  const uint32_t gq = blockIdx.x * 16 + (threadIdx.x >> 4);  // block handled by this quarter
+  const uint32_t r = threadIdx.x & 15;
+  const bool active = gq < nblocks;
+  uint32_t s = 0xFFFFFFFFu;
+  if (active) {
+    if (rowpos) s = rowpos[16u * gq + r];
+    else if (16u * gq + r < v.N) s = 16u * gq + r;
+  }
+  uint32_t p = 0, pe = 0;
+  if (s != 0xFFFFFFFFu) {
+    p = v.hi_off[s];
+    pe = v.hi_off[s + 1];
+  }
+  const uint32_t base = active ? exc_off[gq] : 0;
+  uint32_t e = 0;
+  while (true) {
+    uint32_t cur = p < pe ? v.hi_ids[p] : 0xFFFFFFFFu;
+    uint32_t mn = cur;
+#pragma unroll
+    for (int o = 8; o; o >>= 1) mn = min(mn, (uint32_t)__shfl_xor((int)mn, o, 16));
+    if (mn == 0xFFFFFFFFu) break;  // uniform within the quarter
+    const bool take = cur == mn;
+    exc_cnt[(size_t)(base + e) * 16 + r] = take ? v.hi_cnt[p] : (uint16_t)0;
+    if (r == 0) exc_ids[base + e] = (uint16_t)mn;
+    if (take) p++;
+    e++;
+  }
+  if (active && r == 0) exc_n[gq] = e;
+}
+
+hipError_t launch_exc_build(hipStream_t st, const SetView &v, uint32_t nblocks,
+                            const uint32_t *rowpos, const uint32_t *exc_off, uint32_t *exc_n,
+                            uint16_t *exc_ids, uint16_t *exc_cnt) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(exc_build_kernel, dim3((nblocks + 15) / 16), dim3(256), 0, st, v, nblocks,
+                     rowpos, exc_off, exc_n, exc_ids, exc_cnt);
+  return hipGetLastError();
+}
+
+// exc_off for arbitrary row lists (blocks of 16 entries of rowpos).
+__global__ __launch_bounds__(1024) void exc_offsets_kernel(SetView v,
+                                                           const uint32_t *__restrict__ rowpos,
+                                                           uint32_t nrows,
+                                                           uint32_t *__restrict__ exc_off) {
+  __shared__ uint32_t wsum[16];
+  const uint32_t nb = (nrows + 15) / 16;
+  uint32_t carry = 0;
+  for (uint32_t b = 0; b < nb; b += 1024) {
+    const uint32_t blk = b + threadIdx.x;
+    uint32_t c = 0;
+    if (blk < nb) {
+      for (int r = 0; r < 16; r++) {
+        const uint32_t s = rowpos[16u * blk + r];
+        if (s != 0xFFFFFFFFu) c += v.hi_off[s + 1] - v.hi_off[s];
+      }
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<1024>(c, wsum, tot);
+    if (blk < nb) exc_off[blk] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) exc_off[nb] = carry;
+}
+
+hipError_t launch_exc_offsets(hipStream_t st, const SetView &v, const uint32_t *rowpos,
+                              uint32_t nrows, uint32_t *exc_off) {
+  hipLaunchKernelGGL(exc_offsets_kernel, dim3(1), dim3(1024), 0, st, v, rowpos, nrows, exc_off);
+  return hipGetLastError();
+}
+
+// pos[16 * ceil(n/16)]: sorted positions of input indices first..first+n-1,
+// padded with 0xFFFFFFFF.
+__global__ void map_positions_kernel(const uint32_t *__restrict__ inv, uint32_t first, uint32_t n,
+                                     uint32_t *__restrict__ pos) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t tot = (n + 15) / 16 * 16;
+  if (t < tot) pos[t] = t < n ? inv[first + t] : 0xFFFFFFFFu;
+}
+
+hipError_t launch_map_positions(hipStream_t st, const uint32_t *inv, uint32_t first, uint32_t n,
+                                uint32_t *pos) {
+  const uint32_t tot = (n + 15) / 16 * 16;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(map_positions_kernel, dim3((tot + 255) / 256), dim3(256), 0, st, inv, first,
+                     n, pos);
+  return hipGetLastError();
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, uint64_t n, unsigned long long value) {
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (uint64_t)gridDim.x * blockDim.x)
+    p[t] = value;
+}
+
+hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value) {
+  if (n_words == 0) return hipSuccess;
+  uint64_t blocks = (n_words + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((uint32_t)blocks), dim3(256), 0, st,
+                     (unsigned long long *)p, n_words, (unsigned long long)value);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- export
+
+__global__ void export_offsets_kernel(const uint32_t *__restrict__ Dorig, uint32_t N,
+                                      uint64_t *__restrict__ off) {
+  __shared__ unsigned long long wsum[16];
+  unsigned long long carry = 0;
+  for (uint32_t b = 0; b < N; b += 1024) {
+    const uint32_t i = b + threadIdx.x;
+    unsigned long long d = i < N ? Dorig[i] : 0;
+    unsigned long long tot;
+    const unsigned long long ex = block_exclusive_scan64<1024>(d, wsum, tot);
+    if (i < N) off[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) off[N] = carry;
+}
+
+__global__ void export_copy_kernel(const uint64_t *__restrict__ in_off,
+                                   const uint16_t *__restrict__ cap_ids,
+                                   const uint16_t *__restrict__ cap_cnt,
+                                   const uint32_t *__restrict__ Dorig, uint32_t N,
+                                   const uint64_t *__restrict__ off, uint16_t *__restrict__ ids,
+                                   uint16_t *__restrict__ counts) {
+  const uint32_t i = blockIdx.x;
+  if (i >= N) return;
+  const uint64_t co = in_off[i] - 5ull * i;
+  const uint64_t o = off[i];
+  for (uint32_t t = threadIdx.x; t < Dorig[i]; t += blockDim.x) {
+    ids[o + t] = cap_ids[co + t];
+    counts[o + t] = cap_cnt[co + t];
+  }
+}
+
+__global__ void export_dense_kernel(const uint64_t *__restrict__ in_off,
+                                    const uint16_t *__restrict__ cap_ids,
+                                    const uint16_t *__restrict__ cap_cnt,
+                                    const uint32_t *__restrict__ Dorig, uint32_t first,
+                                    uint16_t *__restrict__ out) {
+  const uint32_t q = blockIdx.x, i = first + q;
+  uint16_t *row = out + (size_t)q * kWords;
+  for (uint32_t x = threadIdx.x; x < (uint32_t)kWords; x += blockDim.x) row[x] = 0;
+  __syncthreads();
+  const uint64_t co = in_off[i] - 5ull * i;
+  for (uint32_t t = threadIdx.x; t < Dorig[i]; t += blockDim.x) row[cap_ids[co + t]] = cap_cnt[co + t];
+}
+
+hipError_t launch_export_lists(hipStream_t st, const kd_set *s, uint16_t *ids, uint16_t *counts,
+                               uint64_t *off) {
+  const uint32_t N = s->v.N;
+  hipLaunchKernelGGL(export_offsets_kernel, dim3(1), dim3(1024), 0, st, s->Dorig, N, off);
+  KD_HIP(hipGetLastError());
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(export_copy_kernel, dim3(N), dim3(64), 0, st, s->in_off, s->cap_ids,
+                     s->cap_cnt, s->Dorig, N, off, ids, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_dense(hipStream_t st, const kd_set *s, uint32_t first, uint32_t count,
+                               uint16_t *out) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(export_dense_kernel, dim3(count), dim3(256), 0, st, s->in_off, s->cap_ids,
+                     s->cap_cnt, s->Dorig, first, out);
+  return hipGetLastError();
+}
+
+__global__ void store_view_kernel(SetView v, SetView *dst) { *dst = v; }
+
+hipError_t launch_store_view(hipStream_t st, const SetView &v, SetView *dst) {
+  hipLaunchKernelGGL(store_view_kernel, dim3(1), dim3(1), 0, st, v, dst);
+  return hipGetLastError();
+}
+
+}  // namespace kd

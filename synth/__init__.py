@@ -222,3 +222,21 @@ CONFIGS = {
     "paper20k": paper20k,
     "large100k": large100k,
 }
+
+
+def rank_like(N: int, seed: int, spread: float = 0.06, center: float = 2.0,
+              tie_frac: float = 0.05) -> np.ndarray:
+    """Synthetic k-mer-rank-shaped values for exercising the decomposition at
+    full size without computing ranks: a few tight clusters (one per family
+    group) around ``center``, with ``tie_frac`` of the entries made exact
+    duplicates of other entries so that index tie-breaking matters."""
+    rng = np.random.default_rng(seed)
+    nclus = max(1, N // 100)
+    mu = center + spread * rng.standard_normal(nclus)
+    R = mu[rng.integers(0, nclus, size=N)] + 0.2 * spread * rng.standard_normal(N)
+    k = int(tie_frac * N)
+    if k and N > 1:
+        dst = rng.integers(0, N, size=k)
+        src = rng.integers(0, N, size=k)
+        R[dst] = R[src]
+    return R.astype(np.float64)
