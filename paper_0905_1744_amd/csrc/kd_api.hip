@@ -306,6 +306,7 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   uint32_t *inv = set_alloc<uint32_t>(s, N);
   uint32_t *K = set_alloc<uint32_t>(s, N);
   uint32_t *D = set_alloc<uint32_t>(s, N);
+  double *invK = set_alloc<double>(s, N);
   uint32_t *hi_off = set_alloc<uint32_t>(s, N + 1);
   uint64_t *grp_off = set_alloc<uint64_t>(s, s->v.G + 1);
   uint32_t *grp_len = set_alloc<uint32_t>(s, s->v.G);
@@ -321,7 +322,7 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   uint32_t *sortv = tmp.get<uint32_t>(2ull * N);
   unsigned long long *small = tmp.get<unsigned long long>(8);  // [0] err, [1] nlong
   LayoutMeta *meta = tmp.get<LayoutMeta>(1);
-  if (!in_off || !cap_ids || !cap_cnt || !Dorig || !perm || !inv || !K || !D || !hi_off ||
+  if (!in_off || !cap_ids || !cap_cnt || !Dorig || !perm || !inv || !K || !D || !invK || !hi_off ||
       !grp_off || !grp_len || !exc_off || !exc_n || !acc || !d_view || !Korig || !nhi_orig ||
       !long_list || !sortk || !sortv || !small || !meta) {
     set_free(s);
@@ -341,7 +342,7 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   StageTimer t_layout(ctx, KD_STAGE_LAYOUT);
   if (e == hipSuccess) e = launch_sort_u32_index(st, Dorig, N, 16, perm, sortk, sortv);
   if (e == hipSuccess)
-    e = launch_layout_meta(st, N, perm, Dorig, Korig, nhi_orig, inv, K, D, hi_off, grp_off,
+    e = launch_layout_meta(st, N, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hi_off, grp_off,
                            grp_len, exc_off, err, meta);
   t_layout.done();
   LayoutMeta *hm = static_cast<LayoutMeta *>(ctx->pinned);
@@ -363,7 +364,7 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   s->n_hi = hm->n_hi;
   s->n_gids = hm->n_gids;
   s->n_exc = hm->n_exc;
-  uint16_t *gids = set_alloc<uint16_t>(s, s->n_gids);
+  uint16_t *gids = set_alloc<uint16_t>(s, s->n_gids + kGidsSlack);
   uint16_t *hi_ids = set_alloc<uint16_t>(s, s->n_hi);
   uint16_t *hi_cnt = set_alloc<uint16_t>(s, s->n_hi);
   uint16_t *exc_ids = set_alloc<uint16_t>(s, s->n_exc);
@@ -377,6 +378,7 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   v.inv = inv;
   v.K = K;
   v.D = D;
+  v.invK = invK;
   v.grp_off = grp_off;
   v.grp_len = grp_len;
   v.gids = gids;
@@ -394,7 +396,9 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   s->in_off = in_off;
   s->d_view = d_view;
   StageTimer t_fill(ctx, KD_STAGE_LAYOUT);
-  e = launch_layout_fill(st, v, in_off, cap_ids, cap_cnt, gids, hi_ids, hi_cnt);
+  // sentinel slack after the last group: the pair kernel reads ahead into it
+  e = launch_fill_u64(st, gids + s->n_gids, kGidsSlack / 4, 0xB640B640B640B640ull);
+  if (e == hipSuccess) e = launch_layout_fill(st, v, in_off, cap_ids, cap_cnt, gids, hi_ids, hi_cnt);
   if (e == hipSuccess) e = launch_exc_build(st, v, v.RB, nullptr, exc_off, exc_n, exc_ids, exc_cnt);
   if (e == hipSuccess) e = launch_store_view(st, v, d_view);
   t_fill.done();
@@ -464,20 +468,20 @@ extern "C" kd_status kmer_similarity(kd_ctx *ctx, const kd_set *s, uint32_t r0, 
 
 namespace {
 
-// Work list of the rank kernel for a set of N sequences: every row block
-// pairs with the column groups holding sorted positions below its last row,
-// cut into chunks of `cg` groups; longest chunks first.
-std::vector<PairTask> make_tasks(uint32_t N, uint32_t cg, uint32_t set_index) {
+// Work list of the rank kernel for a set of N sequences: strips of 16
+// column groups (a workgroup's 16 waves) against runs of row blocks; a
+// row block rb only meets column groups g <= rb/4 (pairs below the
+// diagonal of the sorted order).  Strips with the longest lists first.
+std::vector<PairTask> make_tasks(uint32_t N, uint32_t set_index) {
   std::vector<PairTask> t;
   const uint32_t RB = (N + 15) / 16, G = (N + 63) / 64;
-  for (uint32_t rb = 0; rb < RB; rb++) {
-    const uint32_t ng = std::min(G, (16u * rb + 14u) / 64u + 1u);
-    for (uint32_t g0 = 0; g0 < ng; g0 += cg) t.push_back({set_index, rb, g0, std::min(g0 + cg, ng)});
+  for (uint32_t g0 = 0; g0 < G; g0 += kGroupsPerTask) {
+    for (uint32_t rb0 = 4u * g0; rb0 < RB; rb0 += kRowBlocksPerTask)
+      t.push_back({set_index, rb0, std::min(rb0 + kRowBlocksPerTask, RB), g0});
   }
   std::stable_sort(t.begin(), t.end(), [](const PairTask &a, const PairTask &b) {
-    const uint32_t la = a.g1 - a.g0, lb = b.g1 - b.g0;
-    if (la != lb) return la > lb;
-    return a.g0 > b.g0;
+    if (a.g0 != b.g0) return a.g0 > b.g0;
+    return a.rb1 - a.rb0 > b.rb1 - b.rb0;
   });
   return t;
 }
@@ -490,7 +494,7 @@ kd_status get_tasks(kd_ctx *ctx, uint32_t N, uint32_t cg, PairTask **d, uint32_t
     *n = it->second.second;
     return KD_OK;
   }
-  std::vector<PairTask> t = make_tasks(N, cg, 0);
+  std::vector<PairTask> t = make_tasks(N, 0);
   PairTask *p = static_cast<PairTask *>(ctx->pool->alloc(sizeof(PairTask) * (t.size() + 1)));
   if (!p) return KD_ENOMEM;
   if (hipMemcpy(p, t.data(), sizeof(PairTask) * t.size(), hipMemcpyHostToDevice) != hipSuccess) {
@@ -513,7 +517,7 @@ extern "C" kd_status kmer_rank(kd_ctx *ctx, const kd_set *s, double delta, doubl
   KD_TRY(hipSetDevice(ctx->device));
   PairTask *tasks = nullptr;
   uint32_t ntasks = 0;
-  kd_status rc = get_tasks(ctx, s->v.N, 16, &tasks, &ntasks);
+  kd_status rc = get_tasks(ctx, s->v.N, kRowBlocksPerTask, &tasks, &ntasks);
   if (rc != KD_OK) return rc;
   const hipStream_t st = ctx->stream;
   StageTimer t0(ctx, KD_STAGE_FINALIZE);

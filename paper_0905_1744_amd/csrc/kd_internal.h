@@ -45,6 +45,7 @@ struct SetView {
   const uint32_t *inv;         // [N] input index -> sorted position
   const uint32_t *K;           // [N] words per sequence (n - 5), sorted order
   const uint32_t *D;           // [N] distinct words, sorted order
+  const double *invK;          // [N] 1 / K, sorted order
   const uint64_t *grp_off;     // [G+1] u16-element offset of each group in gids
   const uint32_t *grp_len;     // [G] padded list length of the group (multiple of 8)
   const uint16_t *gids;        // interleaved distinct words: element t of the
@@ -60,11 +61,14 @@ struct SetView {
   long long *acc;              // [3*N] exact rank accumulators (40-bit limbs)
 };
 
-struct PairTask {  // one workgroup's work in the rank kernel
-  uint32_t set;    // index into the SetView array
-  uint32_t rb;     // row block
-  uint32_t g0, g1; // column groups [g0, g1)
+struct PairTask {     // one workgroup's work in the rank kernel
+  uint32_t set;       // index into the SetView array
+  uint32_t rb0, rb1;  // row blocks [rb0, rb1), processed one after another
+  uint32_t g0;        // column groups g0 .. g0+15, one per wave
 };
+constexpr uint32_t kGroupsPerTask = 16;
+constexpr uint32_t kRowBlocksPerTask = 4;
+constexpr size_t kGidsSlack = 16384;  // sentinel words after the last group (read-ahead)
 
 // ---------------------------------------------------------- host objects
 
@@ -144,6 +148,7 @@ struct LayoutMeta {  // totals written by layout_meta, read by the host
 hipError_t launch_layout_meta(hipStream_t st, uint32_t N, const uint32_t *perm,
                               const uint32_t *Dorig, const uint32_t *Korig,
                               const uint32_t *nhi_orig, uint32_t *inv, uint32_t *K, uint32_t *D,
+                              double *invK,
                               uint32_t *hi_off, uint64_t *grp_off, uint32_t *grp_len,
                               uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta);
 

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(1024) void layout_meta_kernel(
     uint32_t N, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ Dorig,
     const uint32_t *__restrict__ Korig, const uint32_t *__restrict__ nhi_orig,
     uint32_t *__restrict__ inv, uint32_t *__restrict__ K, uint32_t *__restrict__ D,
-    uint32_t *__restrict__ hi_off, uint64_t *__restrict__ grp_off, uint32_t *__restrict__ grp_len,
+    double *__restrict__ invK, uint32_t *__restrict__ hi_off, uint64_t *__restrict__ grp_off, uint32_t *__restrict__ grp_len,
     uint32_t *__restrict__ exc_off, const unsigned long long *err, LayoutMeta *meta) {
   __shared__ uint32_t wsum[16];
   __shared__ unsigned long long wsum64[16];
@@ -64,6 +64,7 @@ __global__ __launch_bounds__(1024) void layout_meta_kernel(
       const uint32_t i = perm[s];
       inv[i] = s;
       K[s] = Korig[i];
+      invK[s] = 1.0 / (double)Korig[i];
       D[s] = Dorig[i];
       entries += Dorig[i];
       h = nhi_orig[i];
@@ -125,10 +126,10 @@ __global__ __launch_bounds__(1024) void layout_meta_kernel(
 hipError_t launch_layout_meta(hipStream_t st, uint32_t N, const uint32_t *perm,
                               const uint32_t *Dorig, const uint32_t *Korig,
                               const uint32_t *nhi_orig, uint32_t *inv, uint32_t *K, uint32_t *D,
-                              uint32_t *hi_off, uint64_t *grp_off, uint32_t *grp_len,
+                              double *invK, uint32_t *hi_off, uint64_t *grp_off, uint32_t *grp_len,
                               uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta) {
   hipLaunchKernelGGL(layout_meta_kernel, dim3(1), dim3(1024), 0, st, N, perm, Dorig, Korig,
-                     nhi_orig, inv, K, D, hi_off, grp_off, grp_len, exc_off, err, meta);
+                     nhi_orig, inv, K, D, invK, hi_off, grp_off, grp_len, exc_off, err, meta);
   return hipGetLastError();
 }
 

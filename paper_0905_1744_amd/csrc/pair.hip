@@ -30,113 +30,119 @@
 // co-running work.  Each unordered pair is computed once (column position
 // below row position in the sorted order), and the j = i term is added by
 // the finalize kernel.
+#include "bitcount.h"
 #include "kd_internal.h"
+#include "klog.h"
 
 namespace kd {
 
-// carry-save add: (hi, lo) <- majority / parity of (lo, a, b)
-__device__ __forceinline__ void csa(uint32_t &hi, uint32_t &lo, uint32_t a, uint32_t b) {
-  const uint32_t u = lo ^ a;
-  hi = (u & b) | (~u & lo);
-  lo = u ^ b;
-}
-
-// Adds 8 words (16 looked-up masks) into the bit planes P (P[k] has weight
-// 2^k).  Planes 0-2 are the carry-save state; the weight-8 output ripples
-// into planes 3..kmax-1.
-__device__ __forceinline__ void add8(uint32_t (&P)[16], const uint32_t (&w)[8], uint32_t kmax) {
-  uint32_t twosA, twosB, foursA, foursB, eights;
-  csa(twosA, P[0], w[0], w[1]);
-  csa(twosB, P[0], w[2], w[3]);
-  csa(foursA, P[1], twosA, twosB);
-  csa(twosA, P[0], w[4], w[5]);
-  csa(twosB, P[0], w[6], w[7]);
-  csa(foursB, P[1], twosA, twosB);
-  csa(eights, P[2], foursA, foursB);
-  uint32_t c = eights;
-#pragma unroll
-  for (int k = 3; k < 16; k++) {
-    if ((uint32_t)k < kmax) {
-      const uint32_t t = P[k] & c;
-      P[k] ^= c;
-      c = t;
-    }
-  }
-}
-
-__device__ __forceinline__ void swap_bits(uint32_t &x, uint32_t &y, int j, uint32_t m) {
-  const uint32_t t = ((x >> j) ^ y) & m;
-  y ^= t;
-  x ^= t << j;
-}
-
-// Transposes two 16x16 bit matrices held in the low and high halves of
-// A[0..15]: on entry bit (16h + r) of A[k] is bit k of counter (h, r); on
-// exit bit (16h + k) of A[r] is that same bit.
-__device__ __forceinline__ void transpose16(uint32_t (&A)[16]) {
-#pragma unroll
-  for (int k = 0; k < 8; k++) swap_bits(A[k], A[k + 8], 8, 0x00FF00FFu);
-#pragma unroll
-  for (int k = 0; k < 16; k++)
-    if (!(k & 4)) swap_bits(A[k], A[k + 4], 4, 0x0F0F0F0Fu);
-#pragma unroll
-  for (int k = 0; k < 16; k++)
-    if (!(k & 2)) swap_bits(A[k], A[k + 2], 2, 0x33333333u);
-#pragma unroll
-  for (int k = 0; k < 16; k += 2) swap_bits(A[k], A[k + 1], 1, 0x55555555u);
-}
-
-__device__ __forceinline__ uint32_t plane_count(uint32_t L) {
-  // one-bit counters see at most L/2 words; planes needed = bit length
-  const uint32_t h = L >> 1;
-  const uint32_t b = 32u - (uint32_t)__clz((int)h);
-  return b < 3u ? 3u : (b > 16u ? 16u : b);
-}
-
+// one 32-word step: 16 masks per uint4 pair... (see bitcount.h)
+// masks of the two words packed in x, as one 32-bit word (low half: x's
+// low word); built as a two-element vector so the halves merge with v_perm
 __device__ __forceinline__ uint32_t look2(const uint16_t *T16, uint32_t x) {
-  return (uint32_t)T16[x & 0xFFFFu] | ((uint32_t)T16[x >> 16] << 16);
+  typedef __attribute__((ext_vector_type(2))) unsigned short us2;
+  us2 v;
+  v.x = T16[x & 0xFFFFu];
+  v.y = T16[x >> 16];
+  return __builtin_bit_cast(uint32_t, v);
 }
 
-// Level-1 counts of one column (this lane) against the 16 rows of the LDS
-// table.  Chunk it (16 words) of the column is at p[2*it*64] and
-// p[(2*it+1)*64]; iterations at or beyond niter_lane read sentinel words.
-template <bool kUniform>
-__device__ __forceinline__ void column_counts(const uint16_t *T16, const uint4 *__restrict__ p,
-                                              uint32_t niter_lane, uint32_t niter_wave,
-                                              uint32_t kmax, uint32_t (&cnt)[16]) {
-  uint32_t P[16];
-#pragma unroll
-  for (int k = 0; k < 16; k++) P[k] = 0;
-  const uint4 sent = make_uint4(0xB640B640u, 0xB640B640u, 0xB640B640u, 0xB640B640u);
-  uint4 a = sent, b = sent;
-  if (kUniform || niter_lane > 0) {
-    a = p[0];
-    b = p[64];
-  }
-  for (uint32_t it = 0; it < niter_wave; it++) {
-    uint4 na = sent, nb = sent;
-    if (kUniform ? (it + 1 < niter_wave) : (it + 1 < niter_lane)) {
-      na = p[(size_t)(2 * it + 2) * 64];
-      nb = p[(size_t)(2 * it + 3) * 64];
-    }
-    uint32_t w[8];
-    w[0] = look2(T16, a.x);
-    w[1] = look2(T16, a.y);
-    w[2] = look2(T16, a.z);
-    w[3] = look2(T16, a.w);
-    w[4] = look2(T16, b.x);
-    w[5] = look2(T16, b.y);
-    w[6] = look2(T16, b.z);
-    w[7] = look2(T16, b.w);
-    add8(P, w, kmax);
-    a = na;
-    b = nb;
-  }
+template <int NP>
+__device__ __forceinline__ void step32(const uint16_t *T16, uint32_t (&P)[16], const uint4 &a0,
+                                       const uint4 &a1, const uint4 &a2, const uint4 &a3) {
+  uint32_t w[16];
+  w[0] = look2(T16, a0.x);  w[1] = look2(T16, a0.y);  w[2] = look2(T16, a0.z);  w[3] = look2(T16, a0.w);
+  w[4] = look2(T16, a1.x);  w[5] = look2(T16, a1.y);  w[6] = look2(T16, a1.z);  w[7] = look2(T16, a1.w);
+  w[8] = look2(T16, a2.x);  w[9] = look2(T16, a2.y);  w[10] = look2(T16, a2.z); w[11] = look2(T16, a2.w);
+  w[12] = look2(T16, a3.x); w[13] = look2(T16, a3.y); w[14] = look2(T16, a3.z); w[15] = look2(T16, a3.w);
+  add16<NP>(P, w);
+}
+
+template <int NP>
+__device__ __forceinline__ void step16(const uint16_t *T16, uint32_t (&P)[16], const uint4 &a0,
+                                       const uint4 &a1) {
+  uint32_t w[8];
+  w[0] = look2(T16, a0.x); w[1] = look2(T16, a0.y); w[2] = look2(T16, a0.z); w[3] = look2(T16, a0.w);
+  w[4] = look2(T16, a1.x); w[5] = look2(T16, a1.y); w[6] = look2(T16, a1.z); w[7] = look2(T16, a1.w);
+  add8<NP>(P, w);
+}
+
+__device__ __forceinline__ void planes_to_counts(uint32_t (&P)[16], uint32_t (&cnt)[16]) {
   transpose16(P);
   typedef __attribute__((ext_vector_type(2))) unsigned short us2;
   const us2 ones = __builtin_bit_cast(us2, 0x00010001u);
 #pragma unroll
-  for (int r = 0; r < 16; r++) cnt[r] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, P[r]), ones, 0u, false);
+  for (int r = 0; r < 16; r++)
+    cnt[r] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, P[r]), ones, 0u, false);
+}
+
+// Level-1 counts of this lane's column (list length L, a multiple of 16,
+// the same for the whole wave) against the 16 rows of the LDS table.
+// Chunk k of the column (8 words) is p[64 k].  Loads run up to two 32-word
+// steps ahead; the word buffer carries enough sentinel slack after the last
+// group for that.
+template <int NP>
+__device__ __forceinline__ void column_counts_uniform(const uint16_t *T16, const uint4 *__restrict__ p,
+                                                      uint32_t L, uint32_t (&cnt)[16]) {
+  uint32_t P[16];
+#pragma unroll
+  for (int k = 0; k < 16; k++) P[k] = 0;
+  const uint32_t n32 = L >> 5;
+  uint4 a0 = p[0], a1 = p[64], a2 = p[128], a3 = p[192];
+  uint32_t it = 0;
+  for (; it + 2 <= n32; it += 2) {
+    const uint4 *q = p + (size_t)(it + 1) * 256;
+    const uint4 b0 = q[0], b1 = q[64], b2 = q[128], b3 = q[192];
+    step32<NP>(T16, P, a0, a1, a2, a3);
+    q += 256;
+    a0 = q[0];
+    a1 = q[64];
+    a2 = q[128];
+    a3 = q[192];
+    step32<NP>(T16, P, b0, b1, b2, b3);
+  }
+  if (it < n32) {
+    const uint4 *q = p + (size_t)(it + 1) * 256;
+    const uint4 b0 = q[0], b1 = q[64];
+    step32<NP>(T16, P, a0, a1, a2, a3);
+    a0 = b0;
+    a1 = b1;
+  }
+  if (L & 16u) step16<NP>(T16, P, a0, a1);
+  planes_to_counts(P, cnt);
+}
+
+// Same for lanes whose columns have different list lengths (L_lane, the
+// wave's longest being L_wave); chunks past L_lane read as sentinels.
+template <int NP>
+__device__ __forceinline__ void column_counts_ragged(const uint16_t *T16, const uint4 *__restrict__ p,
+                                                     uint32_t L_lane, uint32_t L_wave,
+                                                     uint32_t (&cnt)[16]) {
+  uint32_t P[16];
+#pragma unroll
+  for (int k = 0; k < 16; k++) P[k] = 0;
+  const uint4 sent = make_uint4(0xB640B640u, 0xB640B640u, 0xB640B640u, 0xB640B640u);
+  const uint32_t nchunk = L_lane >> 3;
+  uint32_t k = 0;
+  for (; k + 4 <= (L_wave >> 3); k += 4) {
+    const uint4 a0 = k < nchunk ? p[(size_t)k * 64] : sent;
+    const uint4 a1 = k + 1 < nchunk ? p[(size_t)(k + 1) * 64] : sent;
+    const uint4 a2 = k + 2 < nchunk ? p[(size_t)(k + 2) * 64] : sent;
+    const uint4 a3 = k + 3 < nchunk ? p[(size_t)(k + 3) * 64] : sent;
+    step32<NP>(T16, P, a0, a1, a2, a3);
+  }
+  if (k < (L_wave >> 3)) {
+    const uint4 a0 = k < nchunk ? p[(size_t)k * 64] : sent;
+    const uint4 a1 = k + 1 < nchunk ? p[(size_t)(k + 1) * 64] : sent;
+    step16<NP>(T16, P, a0, a1);
+  }
+  planes_to_counts(P, cnt);
+}
+
+// plane-count bucket of a list length L (counters see at most L/2 words)
+__device__ __forceinline__ int np_bucket(uint32_t L) {
+  const int need = planes_for(L >> 1);
+  return need <= 8 ? 8 : need <= 10 ? 10 : need <= 12 ? 12 : need <= 14 ? 14 : 16;
 }
 
 // Levels >= 2 for one column: the column's count>=2 words against the row
@@ -166,17 +172,12 @@ __device__ __forceinline__ void column_excess(const SetView &v, uint32_t sc, con
   }
 }
 
-// Reduces 16 values per lane over the 64 lanes with a fixed halving
-// butterfly; lanes 4r..4r+3 return the total of value r.
-__device__ __forceinline__ double halving_reduce16(const double (&v)[16], uint32_t lane) {
-  double u8[8], u4[4], u2[2];
-  const bool b5 = lane & 32u, b4 = lane & 16u, b3 = lane & 8u, b2 = lane & 4u;
-#pragma unroll
-  for (int i = 0; i < 8; i++) {
-    const double send = b5 ? v[i] : v[i + 8];
-    const double keep = b5 ? v[i + 8] : v[i];
-    u8[i] = keep + __shfl_xor(send, 32, 64);
-  }
+// Finishes a fixed halving butterfly over the 64 lanes.  On entry lane l
+// holds u8[i] = the pair sum (lanes l, l^32) of value i + 8 (l >> 5); on
+// exit lanes 4r..4r+3 return the total of value r over all 64 lanes.
+__device__ __forceinline__ double halving_reduce8(const double (&u8)[8], uint32_t lane) {
+  double u4[4], u2[2];
+  const bool b4 = lane & 16u, b3 = lane & 8u, b2 = lane & 4u;
 #pragma unroll
   for (int i = 0; i < 4; i++) {
     const double send = b4 ? u8[i] : u8[i + 4];
@@ -197,49 +198,48 @@ __device__ __forceinline__ double halving_reduce16(const double (&v)[16], uint32
   return u1;
 }
 
-__device__ __forceinline__ void acc_add(long long *acc, uint32_t s, double x) {
-  long long l0, l1, l2;
-  fix_limbs(x, l0, l1, l2);
-  unsigned long long *a = reinterpret_cast<unsigned long long *>(acc) + 3ull * s;
-  atomicAdd(a, (unsigned long long)l0);
-  atomicAdd(a + 1, (unsigned long long)l1);
-  atomicAdd(a + 2, (unsigned long long)l2);
-}
-
-// LDS state of one row block: presence table, count>=2 bitmap, row K.
+// LDS state of one row block: presence table, count>=2 bitmap, row data.
 struct RowShared {
   uint32_t T32[kTableWords];
   uint32_t BM[kBitmapWords];
   uint32_t rowK[16];
+  double rowInv[16];
 };
 
-// Builds the table for rows rowpos(r) (sorted positions; 0xFFFFFFFF = none).
-// Requires 1024 threads: wave r inserts row r.
-template <class RowPos>
-__device__ __forceinline__ void build_rows(const SetView &v, RowPos rowpos,
+// Inserts (set = true) or removes the rows rowpos(r) (sorted positions,
+// 0xFFFFFFFF = none) and their count>=2 words.  Needs 1024 threads: wave r
+// walks row r.  Removal zeroes whole entries, which is exact because the
+// table holds only the rows being removed.
+template <bool kSet, class RowPos>
+__device__ __forceinline__ void touch_rows(const SetView &v, RowPos rowpos,
                                            const uint16_t *__restrict__ exc_ids, uint32_t e0,
                                            uint32_t en, RowShared &sh) {
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-  for (uint32_t x = tid; x < (uint32_t)kTableWords; x += 1024) sh.T32[x] = 0;
-  for (uint32_t x = tid; x < (uint32_t)kBitmapWords; x += 1024) sh.BM[x] = 0;
-  __syncthreads();
   const uint32_t r = wave, sr = rowpos(r);
+  uint16_t *T16 = reinterpret_cast<uint16_t *>(sh.T32);
   if (sr != 0xFFFFFFFFu) {
     const uint32_t g = sr >> 6, ln = sr & 63u, Dr = v.D[sr];
     const uint16_t *base = v.gids + v.grp_off[g];
     for (uint32_t t = lane; t < Dr; t += 64) {
       const uint32_t id = base[((size_t)(t >> 3) * 64 + ln) * 8 + (t & 7u)];
-      atomicOr(&sh.T32[id >> 1], (1u << r) << ((id & 1u) << 4));
+      if (kSet) atomicOr(&sh.T32[id >> 1], (1u << r) << ((id & 1u) << 4));
+      else T16[id] = 0;
     }
-    if (lane == 0) sh.rowK[r] = v.K[sr];
-  } else if (lane == 0) {
-    sh.rowK[r] = 0;
+  }
+  if (kSet && lane == 0) {
+    sh.rowK[r] = sr != 0xFFFFFFFFu ? v.K[sr] : 0u;
+    sh.rowInv[r] = sr != 0xFFFFFFFFu ? v.invK[sr] : 0.0;
   }
   for (uint32_t e = tid; e < en; e += 1024) {
     const uint32_t id = exc_ids[e0 + e];
-    atomicOr(&sh.BM[id >> 5], 1u << (id & 31u));
+    if (kSet) atomicOr(&sh.BM[id >> 5], 1u << (id & 31u));
+    else sh.BM[id >> 5] = 0;
   }
-  __syncthreads();
+}
+
+__device__ __forceinline__ void clear_rows(RowShared &sh) {
+  for (uint32_t x = threadIdx.x; x < (uint32_t)kTableWords; x += blockDim.x) sh.T32[x] = 0;
+  for (uint32_t x = threadIdx.x; x < (uint32_t)kBitmapWords; x += blockDim.x) sh.BM[x] = 0;
 }
 
 struct ConsecutiveRows {
@@ -252,44 +252,127 @@ struct ListedRows {
   __device__ uint32_t operator()(uint32_t r) const { return pos[r]; }
 };
 
+struct RankShared {
+  RowShared row;
+  LogEntry logt[kLogEntries];
+  double ln2;
+  unsigned long long racc[48];  // 16 rows x 3 limbs of the current row block
+};
+
+// Level-1 counts for this lane's column, dispatching on the plane bucket.
+__device__ __forceinline__ void column_counts(const uint16_t *T16, const uint4 *p, uint32_t L,
+                                              uint32_t (&cnt)[16]) {
+  switch (np_bucket(L)) {
+    case 8: column_counts_uniform<8>(T16, p, L, cnt); break;
+    case 10: column_counts_uniform<10>(T16, p, L, cnt); break;
+    case 12: column_counts_uniform<12>(T16, p, L, cnt); break;
+    case 14: column_counts_uniform<14>(T16, p, L, cnt); break;
+    default: column_counts_uniform<16>(T16, p, L, cnt); break;
+  }
+}
+
+// One workgroup = 16 waves = 16 consecutive column groups g0..g0+15 (wave w
+// takes group g0 + w) against row blocks rb0..rb1-1, one row block at a
+// time.  Row partials of a row block meet in LDS (exact integer adds) and
+// go to HBM once; a column's partials stay in registers across the row
+// blocks and go to HBM once at the end.
 __global__ __launch_bounds__(1024) void rank_pairs_kernel(const SetView *__restrict__ views,
                                                           const PairTask *__restrict__ tasks,
                                                           double delta) {
-  __shared__ RowShared sh;
+  __shared__ RankShared sh;
   const PairTask tk = tasks[blockIdx.x];
   const SetView v = views[tk.set];
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const uint32_t e0 = v.exc_off[tk.rb], en = v.exc_n[tk.rb];
-  build_rows(v, ConsecutiveRows{16u * tk.rb, v.N}, v.exc_ids, e0, en, sh);
-  const uint16_t *T16 = reinterpret_cast<const uint16_t *>(sh.T32);
-  for (uint32_t g = tk.g0 + wave; g < tk.g1; g += 16) {
-    const uint32_t sc = 64u * g + lane;
-    const bool vc = sc < v.N;
-    const uint32_t L = v.grp_len[g];
-    const uint4 *p = reinterpret_cast<const uint4 *>(v.gids + v.grp_off[g]) + lane;
-    uint32_t cnt[16];
-    column_counts<true>(T16, p, L >> 4, L >> 4, plane_count(L), cnt);
-    if (vc) column_excess(v, sc, sh.BM, v.exc_ids, v.exc_cnt, e0, en, cnt);
-    const uint32_t Kc = vc ? v.K[sc] : 1u;
-    double rv[16];
-    double colsum = 0.0;
-#pragma unroll
-    for (int r = 0; r < 16; r++) {
-      const uint32_t sr = 16u * tk.rb + r;
-      double d = 0.0;
-      if (vc && sc < sr && sr < v.N) {
-        const uint32_t den = min(sh.rowK[r], Kc);
-        d = -log(delta + (double)cnt[r] / (double)den);
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  for (uint32_t q = tid; q < (uint32_t)kLogEntries; q += 1024) log_table_entry((int)q, sh.logt[q]);
+  if (tid == 0) sh.ln2 = log(2.0);
+  if (tid < 48) sh.racc[tid] = 0;
+  clear_rows(sh.row);
+
+  const uint32_t g = tk.g0 + wave;
+  const bool gvalid = g < v.G;
+  const uint32_t sc = 64u * g + lane;
+  const bool vc = gvalid && sc < v.N;
+  const uint32_t Kc = vc ? v.K[sc] : 1u;
+  const double invKc = vc ? v.invK[sc] : 0.0;
+  const uint32_t L = gvalid ? v.grp_len[g] : 0u;
+  const uint4 *p = gvalid ? reinterpret_cast<const uint4 *>(v.gids + v.grp_off[g]) + lane : nullptr;
+  const uint16_t *T16 = reinterpret_cast<const uint16_t *>(sh.row.T32);
+  long long c0 = 0, c1 = 0, c2 = 0;
+  bool any = false;
+
+  for (uint32_t rb = tk.rb0; rb < tk.rb1; rb++) {
+    if (rb > tk.rb0) {
+      // previous row block: flush its row sums, then remove it from the table
+      const uint32_t pr = rb - 1;
+      if (tid < 48) {
+        const uint32_t s = 16u * pr + tid / 3u;
+        if (s < v.N)
+          atomicAdd(reinterpret_cast<unsigned long long *>(v.acc) + 3ull * s + tid % 3u, sh.racc[tid]);
+        sh.racc[tid] = 0;
       }
-      rv[r] = d;
-      colsum += d;
+      touch_rows<false>(v, ConsecutiveRows{16u * pr, v.N}, v.exc_ids, v.exc_off[pr], v.exc_n[pr], sh.row);
     }
-    const double rowtot = halving_reduce16(rv, lane);
-    if ((lane & 3u) == 0) {
-      const uint32_t sr = 16u * tk.rb + (lane >> 2);
-      if (sr < v.N) acc_add(v.acc, sr, rowtot);
+    __syncthreads();
+    const uint32_t e0 = v.exc_off[rb], en = v.exc_n[rb];
+    touch_rows<true>(v, ConsecutiveRows{16u * rb, v.N}, v.exc_ids, e0, en, sh.row);
+    __syncthreads();
+    // the tile has pairs below the diagonal only when rb >= 4 g
+    if (gvalid && rb >= 4u * g) {
+      uint32_t cnt[16];
+      column_counts(T16, p, L, cnt);
+      if (vc) column_excess(v, sc, sh.row.BM, v.exc_ids, v.exc_cnt, e0, en, cnt);
+      // F = shared / min(K_r, K_c) (Equation 1), d = -ln(delta + F) (Equation 2);
+      // rows r and r + 8 are formed together and immediately folded across
+      // lanes l and l ^ 32 (first step of the halving butterfly)
+      double u8[8];
+      double colsum = 0.0;
+      const bool b5 = lane & 32u;
+#pragma unroll
+      for (int r = 0; r < 8; r++) {
+        double d[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const uint32_t rr = r + 8 * h, sr = 16u * rb + rr;
+          d[h] = 0.0;
+          if (vc && sc < sr && sr < v.N) {
+            const double inv = sh.row.rowK[rr] < Kc ? sh.row.rowInv[rr] : invKc;
+            d[h] = -log_tab(fma((double)cnt[rr], inv, delta), sh.logt, sh.ln2);
+          }
+        }
+        colsum += d[0];
+        colsum += d[1];
+        const double send = b5 ? d[0] : d[1];
+        const double keep = b5 ? d[1] : d[0];
+        u8[r] = keep + __shfl_xor(send, 32, 64);
+      }
+      const double rowtot = halving_reduce8(u8, lane);
+      if ((lane & 3u) == 0) {
+        long long l0, l1, l2;
+        fix_limbs(rowtot, l0, l1, l2);
+        unsigned long long *ra = sh.racc + 3u * (lane >> 2);
+        atomicAdd(ra, (unsigned long long)l0);
+        atomicAdd(ra + 1, (unsigned long long)l1);
+        atomicAdd(ra + 2, (unsigned long long)l2);
+      }
+      long long l0, l1, l2;
+      fix_limbs(colsum, l0, l1, l2);
+      c0 += l0;
+      c1 += l1;
+      c2 += l2;
+      any = true;
     }
-    if (vc) acc_add(v.acc, sc, colsum);
+    __syncthreads();
+  }
+  if (tid < 48) {
+    const uint32_t s = 16u * (tk.rb1 - 1) + tid / 3u;
+    if (s < v.N)
+      atomicAdd(reinterpret_cast<unsigned long long *>(v.acc) + 3ull * s + tid % 3u, sh.racc[tid]);
+  }
+  if (vc && any) {
+    unsigned long long *a = reinterpret_cast<unsigned long long *>(v.acc) + 3ull * sc;
+    atomicAdd(a, (unsigned long long)c0);
+    atomicAdd(a + 1, (unsigned long long)c1);
+    atomicAdd(a + 2, (unsigned long long)c2);
   }
 }
 
@@ -329,7 +412,10 @@ __global__ __launch_bounds__(1024) void similarity_kernel(
   const uint32_t bx = blockIdx.x;
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t e0 = exc_off[bx], en = exc_n[bx];
-  build_rows(v, ListedRows{rowpos + 16u * bx}, exc_ids, e0, en, sh);
+  clear_rows(sh);
+  __syncthreads();
+  touch_rows<true>(v, ListedRows{rowpos + 16u * bx}, exc_ids, e0, en, sh);
+  __syncthreads();
   const uint16_t *T16 = reinterpret_cast<const uint16_t *>(sh.T32);
   const uint32_t c = blockIdx.y * 1024u + wave * 64u + lane;
   const bool vc = c < nc;
@@ -342,7 +428,13 @@ __global__ __launch_bounds__(1024) void similarity_kernel(
   if (Lw == 0) return;
   const uint4 *p = reinterpret_cast<const uint4 *>(v.gids + v.grp_off[g]) + ln;
   uint32_t cnt[16];
-  column_counts<false>(T16, p, L >> 4, Lw >> 4, plane_count(Lw), cnt);
+  switch (np_bucket(Lw)) {
+    case 8: column_counts_ragged<8>(T16, p, L, Lw, cnt); break;
+    case 10: column_counts_ragged<10>(T16, p, L, Lw, cnt); break;
+    case 12: column_counts_ragged<12>(T16, p, L, Lw, cnt); break;
+    case 14: column_counts_ragged<14>(T16, p, L, Lw, cnt); break;
+    default: column_counts_ragged<16>(T16, p, L, Lw, cnt); break;
+  }
   if (!vc) return;
   column_excess(v, sc, sh.BM, exc_ids, exc_cnt, e0, en, cnt);
   const uint32_t Kc = v.K[sc];

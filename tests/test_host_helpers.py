@@ -1,0 +1,25 @@
+"""CPU checks of the device helpers that are plain arithmetic (compiled with
+hipcc as host code, no GPU needed): the table-driven log used for the
+Equation 2 distance against the C library log, and the bit-sliced
+carry-save counting + plane transpose against direct counting."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_helpers_on_host(tmp_path):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "helpers_check")
+    subprocess.run([hipcc, "-x", "hip", "--cuda-host-only", "-O2", "-std=c++17",
+                    "-I", os.path.join(ROOT, "paper_0905_1744_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "helpers_check.cpp"), "-o", exe],
+                   check=True, capture_output=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "OK" in r.stdout
