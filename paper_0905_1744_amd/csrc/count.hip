@@ -32,34 +32,21 @@ __device__ inline uint32_t check_offsets(const uint64_t *off, uint32_t i, uint32
   return kErrNone;
 }
 
-__global__ __launch_bounds__(64) void count_short_kernel(
-    const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint32_t N, uint64_t nres,
-    uint64_t cap, uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt,
-    uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout, uint32_t *__restrict__ nhiout,
-    uint32_t *__restrict__ long_list, uint32_t *__restrict__ nlong, unsigned long long *err) {
-  __shared__ uint8_t lut[256];
-  __shared__ uint8_t codes[kShortMax + 8];
-  __shared__ uint16_t w[kShortMax];
-  __shared__ uint16_t hp[kShortMax + 1];
-  const uint32_t i = blockIdx.x;
+// Counts one sequence of K <= CAP words with one 64-lane workgroup.
+// Returns false (without touching outputs) when the sequence is longer.
+template <int CAP>
+__device__ __forceinline__ void count_one(const uint8_t *__restrict__ res, uint32_t i, uint64_t o0,
+                                          uint32_t n, uint64_t cap, const uint8_t *lut,
+                                          uint8_t *codes, uint16_t *w, uint16_t *hp,
+                                          uint16_t *__restrict__ cap_ids,
+                                          uint16_t *__restrict__ cap_cnt, uint32_t *__restrict__ Dout,
+                                          uint32_t *__restrict__ Kout,
+                                          uint32_t *__restrict__ nhiout, unsigned long long *err) {
   const uint32_t lane = threadIdx.x;
-  for (uint32_t c = lane; c < 256; c += 64) lut[c] = dayhoff6(c);
-  uint64_t o0, o1;
-  const uint32_t code = check_offsets(off, i, N, nres, o0, o1);
-  if (code != kErrNone) {
-    if (lane == 0) atomicMin(err, pack_err(i, code, 0));
-    return;
-  }
-  const uint32_t n = (uint32_t)(o1 - o0);
   const uint32_t K = n - (kK - 1);
-  if (K > (uint32_t)kShortMax) {
-    if (lane == 0) long_list[atomicAdd(nlong, 1u)] = i;
-    return;
-  }
-  __syncthreads();
   uint32_t bad = 0xFFFFFFFFu;
   for (uint32_t t = lane; t < n; t += 64) {
-    uint8_t c = lut[res[o0 + t]];
+    const uint8_t c = lut[res[o0 + t]];
     codes[t] = c;
     if (c == 255 && t < bad) bad = t;
   }
@@ -127,6 +114,67 @@ __global__ __launch_bounds__(64) void count_short_kernel(
     Dout[i] = D;
     Kout[i] = K;
     nhiout[i] = nh;
+  }
+}
+
+// First pass, one workgroup per sequence: validates every sequence, counts
+// those of at most 1024 words (LDS sized for them, so ~29 fit per CU), and
+// queues longer ones for the 4096-word kernel or the dense-histogram one.
+__global__ __launch_bounds__(64) void count_short_kernel(
+    const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint32_t N, uint64_t nres,
+    uint64_t cap, uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt,
+    uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout, uint32_t *__restrict__ nhiout,
+    uint32_t *__restrict__ mid_list, uint32_t *__restrict__ nmid, uint32_t *__restrict__ long_list,
+    uint32_t *__restrict__ nlong, unsigned long long *err) {
+  constexpr int CAP = 1024;
+  __shared__ uint8_t lut[256];
+  __shared__ uint8_t codes[CAP + 8];
+  __shared__ uint16_t w[CAP];
+  __shared__ uint16_t hp[CAP + 1];
+  const uint32_t i = blockIdx.x;
+  const uint32_t lane = threadIdx.x;
+  for (uint32_t c = lane; c < 256; c += 64) lut[c] = dayhoff6(c);
+  uint64_t o0, o1;
+  const uint32_t code = check_offsets(off, i, N, nres, o0, o1);
+  if (code != kErrNone) {
+    if (lane == 0) atomicMin(err, pack_err(i, code, 0));
+    return;
+  }
+  const uint32_t n = (uint32_t)(o1 - o0);
+  const uint32_t K = n - (kK - 1);
+  if (K > (uint32_t)CAP) {
+    if (lane == 0) {
+      if (K <= (uint32_t)kShortMax) mid_list[atomicAdd(nmid, 1u)] = i;
+      else long_list[atomicAdd(nlong, 1u)] = i;
+    }
+    return;
+  }
+  __syncthreads();
+  count_one<CAP>(res, i, o0, n, cap, lut, codes, w, hp, cap_ids, cap_cnt, Dout, Kout, nhiout, err);
+}
+
+// Sequences of 1025..4096 words, queued by the first pass.
+__global__ __launch_bounds__(64) void count_mid_kernel(
+    const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint64_t cap,
+    uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt, uint32_t *__restrict__ Dout,
+    uint32_t *__restrict__ Kout, uint32_t *__restrict__ nhiout,
+    const uint32_t *__restrict__ mid_list, const uint32_t *__restrict__ nmid,
+    unsigned long long *err) {
+  constexpr int CAP = kShortMax;
+  __shared__ uint8_t lut[256];
+  __shared__ uint8_t codes[CAP + 8];
+  __shared__ uint16_t w[CAP];
+  __shared__ uint16_t hp[CAP + 1];
+  const uint32_t lane = threadIdx.x;
+  for (uint32_t c = lane; c < 256; c += 64) lut[c] = dayhoff6(c);
+  __syncthreads();
+  const uint32_t nm = *nmid;
+  for (uint32_t q = blockIdx.x; q < nm; q += gridDim.x) {
+    const uint32_t i = mid_list[q];
+    const uint64_t o0 = off[i], o1 = off[i + 1];
+    count_one<CAP>(res, i, o0, (uint32_t)(o1 - o0), cap, lut, codes, w, hp, cap_ids, cap_cnt, Dout,
+                   Kout, nhiout, err);
+    __syncthreads();
   }
 }
 
@@ -200,13 +248,17 @@ __global__ __launch_bounds__(1024) void count_long_kernel(
 
 hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off, uint32_t N,
                         uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
-                        uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig, uint32_t *long_list,
-                        uint32_t *nlong, unsigned long long *err, int cus) {
+                        uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig, uint32_t *mid_list,
+                        uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
+                        unsigned long long *err, int cus) {
   if (N == 0) return hipSuccess;
   hipLaunchKernelGGL(count_short_kernel, dim3(N), dim3(64), 0, st, res, off, N, nres, cap, cap_ids,
-                     cap_cnt, Dorig, Korig, nhi_orig, long_list, nlong, err);
+                     cap_cnt, Dorig, Korig, nhi_orig, mid_list, nmid, long_list, nlong, err);
   KD_HIP(hipGetLastError());
   const uint32_t grid = (uint32_t)(cus > 0 ? cus : 256);
+  hipLaunchKernelGGL(count_mid_kernel, dim3(4 * grid), dim3(64), 0, st, res, off, cap, cap_ids,
+                     cap_cnt, Dorig, Korig, nhi_orig, mid_list, nmid, err);
+  KD_HIP(hipGetLastError());
   hipLaunchKernelGGL(count_long_kernel, dim3(grid), dim3(1024), 0, st, res, off, N, nres, cap,
                      cap_ids, cap_cnt, Dorig, Korig, nhi_orig, long_list, nlong, err);
   return hipGetLastError();

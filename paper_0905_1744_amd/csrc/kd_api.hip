@@ -310,26 +310,31 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   uint32_t *hi_off = set_alloc<uint32_t>(s, N + 1);
   uint64_t *grp_off = set_alloc<uint64_t>(s, s->v.G + 1);
   uint32_t *grp_len = set_alloc<uint32_t>(s, s->v.G);
+  uint64_t *ghi_off = set_alloc<uint64_t>(s, s->v.G + 1);
+  uint32_t *ghi_len = set_alloc<uint32_t>(s, s->v.G);
   uint32_t *exc_off = set_alloc<uint32_t>(s, s->v.RB + 1);
   uint32_t *exc_n = set_alloc<uint32_t>(s, s->v.RB);
   long long *acc = set_alloc<long long>(s, 3ull * N);
   SetView *d_view = set_alloc<SetView>(s, 1);
   // temporaries
   uint32_t *Korig = tmp.get<uint32_t>(N);
+  uint32_t *hcount = tmp.get<uint32_t>(N);
   uint32_t *nhi_orig = tmp.get<uint32_t>(N);
   uint32_t *long_list = tmp.get<uint32_t>(N);
+  uint32_t *mid_list = tmp.get<uint32_t>(N);
   uint32_t *sortk = tmp.get<uint32_t>(2ull * N);
   uint32_t *sortv = tmp.get<uint32_t>(2ull * N);
   unsigned long long *small = tmp.get<unsigned long long>(8);  // [0] err, [1] nlong
   LayoutMeta *meta = tmp.get<LayoutMeta>(1);
-  if (!in_off || !cap_ids || !cap_cnt || !Dorig || !perm || !inv || !K || !D || !invK || !hi_off ||
-      !grp_off || !grp_len || !exc_off || !exc_n || !acc || !d_view || !Korig || !nhi_orig ||
-      !long_list || !sortk || !sortv || !small || !meta) {
+  if (!in_off || !cap_ids || !cap_cnt || !Dorig || !perm || !inv || !K || !D || !invK || !hi_off || !hcount ||
+      !grp_off || !grp_len || !ghi_off || !ghi_len || !exc_off || !exc_n || !acc || !d_view || !Korig || !nhi_orig ||
+      !long_list || !mid_list || !sortk || !sortv || !small || !meta) {
     set_free(s);
     return KD_ENOMEM;
   }
   unsigned long long *err = small;
-  uint32_t *nlong = reinterpret_cast<uint32_t *>(small + 1);
+  uint32_t *nlong = reinterpret_cast<uint32_t *>(small + 1);  // [0] long, [1] mid
+  uint32_t *nmid = nlong + 1;
   hipError_t e = launch_fill_u64(st, small, 1, ~0ull);
   if (e == hipSuccess) e = launch_fill_u64(st, small + 1, 1, 0ull);
   if (e == hipSuccess)
@@ -337,13 +342,13 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   StageTimer t_count(ctx, KD_STAGE_COUNT);
   if (e == hipSuccess)
     e = launch_count(st, residues, offsets, N, n_residues, cap, cap_ids, cap_cnt, Dorig, Korig,
-                     nhi_orig, long_list, nlong, err, ctx->cus);
+                     nhi_orig, mid_list, nmid, long_list, nlong, err, ctx->cus);
   t_count.done();
   StageTimer t_layout(ctx, KD_STAGE_LAYOUT);
   if (e == hipSuccess) e = launch_sort_u32_index(st, Dorig, N, 16, perm, sortk, sortv);
   if (e == hipSuccess)
-    e = launch_layout_meta(st, N, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hi_off, grp_off,
-                           grp_len, exc_off, err, meta);
+    e = launch_layout_meta(st, N, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hcount, hi_off,
+                           grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta);
   t_layout.done();
   LayoutMeta *hm = static_cast<LayoutMeta *>(ctx->pinned);
   if (e == hipSuccess) e = hipMemcpyAsync(hm, meta, sizeof(LayoutMeta), hipMemcpyDeviceToHost, st);
@@ -369,7 +374,8 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   uint16_t *hi_cnt = set_alloc<uint16_t>(s, s->n_hi);
   uint16_t *exc_ids = set_alloc<uint16_t>(s, s->n_exc);
   uint16_t *exc_cnt = set_alloc<uint16_t>(s, 16ull * s->n_exc);
-  if (!gids || !hi_ids || !hi_cnt || !exc_ids || !exc_cnt) {
+  uint32_t *ghi = set_alloc<uint32_t>(s, hm->n_ghi + 2);
+  if (!gids || !hi_ids || !hi_cnt || !exc_ids || !exc_cnt || !ghi) {
     set_free(s);
     return KD_ENOMEM;
   }
@@ -385,6 +391,9 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   v.hi_off = hi_off;
   v.hi_ids = hi_ids;
   v.hi_cnt = hi_cnt;
+  v.ghi = ghi;
+  v.ghi_off = ghi_off;
+  v.ghi_len = ghi_len;
   v.exc_off = exc_off;
   v.exc_n = exc_n;
   v.exc_ids = exc_ids;
@@ -398,7 +407,10 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   StageTimer t_fill(ctx, KD_STAGE_LAYOUT);
   // sentinel slack after the last group: the pair kernel reads ahead into it
   e = launch_fill_u64(st, gids + s->n_gids, kGidsSlack / 4, 0xB640B640B640B640ull);
-  if (e == hipSuccess) e = launch_layout_fill(st, v, in_off, cap_ids, cap_cnt, gids, hi_ids, hi_cnt);
+  if (e == hipSuccess) e = launch_fill_u64(st, ghi, (hm->n_ghi + 1) / 2, 0ull);
+  if (e == hipSuccess)
+    e = launch_layout_fill(st, v, in_off, cap_ids, cap_cnt, gids, hi_ids, hi_cnt, ghi,
+                           (uint32_t)hm->max_len);
   if (e == hipSuccess) e = launch_exc_build(st, v, v.RB, nullptr, exc_off, exc_n, exc_ids, exc_cnt);
   if (e == hipSuccess) e = launch_store_view(st, v, d_view);
   t_fill.done();
@@ -468,8 +480,8 @@ extern "C" kd_status kmer_similarity(kd_ctx *ctx, const kd_set *s, uint32_t r0, 
 
 namespace {
 
-// Work list of the rank kernel for a set of N sequences: strips of 16
-// column groups (a workgroup's 16 waves) against runs of row blocks; a
+// Work list of the rank kernel for a set of N sequences: strips of 32
+// column groups (two per wave of a workgroup) against runs of row blocks; a
 // row block rb only meets column groups g <= rb/4 (pairs below the
 // diagonal of the sorted order).  Strips with the longest lists first.
 std::vector<PairTask> make_tasks(uint32_t N, uint32_t set_index) {

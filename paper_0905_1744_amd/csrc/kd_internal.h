@@ -54,6 +54,11 @@ struct SetView {
   const uint32_t *hi_off;      // [N+1] entries with count >= 2, sorted order
   const uint16_t *hi_ids;
   const uint16_t *hi_cnt;
+  const uint32_t *ghi;         // count>=2 entries per column group, interleaved like
+                               // gids (entry t of lane l at ghi_off[g] + 64 t + l),
+                               // packed word | count << 16, zero padded
+  const uint64_t *ghi_off;     // [G+1]
+  const uint32_t *ghi_len;     // [G] entries per lane, multiple of 4
   const uint32_t *exc_off;     // [RB+1] per row block: merged count>=2 words
   const uint32_t *exc_n;       // [RB] used entries in the block's range
   const uint16_t *exc_ids;     // [cap] sorted words
@@ -66,7 +71,7 @@ struct PairTask {     // one workgroup's work in the rank kernel
   uint32_t rb0, rb1;  // row blocks [rb0, rb1), processed one after another
   uint32_t g0;        // column groups g0 .. g0+15, one per wave
 };
-constexpr uint32_t kGroupsPerTask = 16;
+constexpr uint32_t kGroupsPerTask = 32;  // two column groups per wave
 constexpr uint32_t kRowBlocksPerTask = 4;
 constexpr size_t kGidsSlack = 16384;  // sentinel words after the last group (read-ahead)
 
@@ -130,8 +135,9 @@ namespace kd {
 
 hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off, uint32_t N,
                         uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
-                        uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig, uint32_t *long_list,
-                        uint32_t *nlong, unsigned long long *err, int cus);
+                        uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig, uint32_t *mid_list,
+                        uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
+                        unsigned long long *err, int cus);
 
 // stable sort of (key u32 < 2^bits, value = index) for N entries; writes perm
 hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, uint32_t N, int bits,
@@ -143,18 +149,22 @@ struct LayoutMeta {  // totals written by layout_meta, read by the host
   unsigned long long n_gids;
   unsigned long long n_exc;
   unsigned long long entries;
+  unsigned long long max_len;  // longest padded group list
+  unsigned long long n_ghi;    // grouped count>=2 entries incl. padding
 };
 
 hipError_t launch_layout_meta(hipStream_t st, uint32_t N, const uint32_t *perm,
                               const uint32_t *Dorig, const uint32_t *Korig,
                               const uint32_t *nhi_orig, uint32_t *inv, uint32_t *K, uint32_t *D,
-                              double *invK,
+                              double *invK, uint32_t *hcount,
                               uint32_t *hi_off, uint64_t *grp_off, uint32_t *grp_len,
+                              uint64_t *ghi_off, uint32_t *ghi_len,
                               uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta);
 
 hipError_t launch_layout_fill(hipStream_t st, const SetView &v, const uint64_t *offsets,
                               const uint16_t *cap_ids, const uint16_t *cap_cnt,
-                              uint16_t *gids, uint16_t *hi_ids, uint16_t *hi_cnt);
+                              uint16_t *gids, uint16_t *hi_ids, uint16_t *hi_cnt, uint32_t *ghi,
+                              uint32_t max_len);
 
 // merged count>=2 words of row blocks; rowpos == nullptr means block b holds
 // sorted positions 16b..16b+15

@@ -38,111 +38,151 @@ hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, uint32_t 
   return hipGetLastError();
 }
 
+// Per sorted position: inverse permutation, K, 1/K, D and the count of
+// entries seen at least twice (into hcount).
+__global__ void layout_gather_kernel(uint32_t N, const uint32_t *__restrict__ perm,
+                                     const uint32_t *__restrict__ Dorig,
+                                     const uint32_t *__restrict__ Korig,
+                                     const uint32_t *__restrict__ nhi_orig,
+                                     uint32_t *__restrict__ inv, uint32_t *__restrict__ K,
+                                     uint32_t *__restrict__ D, double *__restrict__ invK,
+                                     uint32_t *__restrict__ hcount, const unsigned long long *err) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N || *err != ~0ull) return;
+  const uint32_t i = perm[s];
+  inv[i] = s;
+  K[s] = Korig[i];
+  invK[s] = 1.0 / (double)Korig[i];
+  D[s] = Dorig[i];
+  hcount[s] = nhi_orig[i];
+}
+
+// Exclusive scan of n values with one 1024-thread workgroup, each thread
+// summing a contiguous chunk; out[n] gets the total, which is returned.
+template <typename In, typename Out>
+__device__ Out chunked_scan(const In &in, uint32_t n, Out *out, Out *wsum) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (n + 1023) / 1024;
+  const uint32_t lo = min(tid * per, n), hi = min(lo + per, n);
+  Out local = 0;
+  for (uint32_t x = lo; x < hi; x++) local += in(x);
+  const int lane = tid & 63, wave = tid >> 6;
+  Out incl = local;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const Out y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  Out before = 0, all = 0;
+  for (int w = 0; w < 16; w++) {
+    before += (w < wave) ? wsum[w] : 0;
+    all += wsum[w];
+  }
+  __syncthreads();
+  Out run = before + incl - local;
+  for (uint32_t x = lo; x < hi; x++) {
+    out[x] = run;
+    run += in(x);
+  }
+  if (tid == 0) out[n] = all;
+  return all;
+}
+
+struct HcountIn {
+  const uint32_t *h;
+  __device__ uint32_t operator()(uint32_t s) const { return h[s]; }
+};
+struct GroupIn {
+  const uint32_t *len;
+  __device__ unsigned long long operator()(uint32_t g) const { return 64ull * len[g]; }
+};
+struct BlockHiIn {
+  const uint32_t *hi_off;
+  uint32_t N;
+  __device__ uint32_t operator()(uint32_t rb) const {
+    return hi_off[min(16u * rb + 16u, N)] - hi_off[16u * rb];
+  }
+};
+
 __global__ __launch_bounds__(1024) void layout_meta_kernel(
-    uint32_t N, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ Dorig,
-    const uint32_t *__restrict__ Korig, const uint32_t *__restrict__ nhi_orig,
-    uint32_t *__restrict__ inv, uint32_t *__restrict__ K, uint32_t *__restrict__ D,
-    double *__restrict__ invK, uint32_t *__restrict__ hi_off, uint64_t *__restrict__ grp_off, uint32_t *__restrict__ grp_len,
+    uint32_t N, const uint32_t *__restrict__ D, const uint32_t *__restrict__ hcount,
+    uint32_t *__restrict__ hi_off, uint64_t *__restrict__ grp_off, uint32_t *__restrict__ grp_len,
+    uint64_t *__restrict__ ghi_off, uint32_t *__restrict__ ghi_len,
     uint32_t *__restrict__ exc_off, const unsigned long long *err, LayoutMeta *meta) {
   __shared__ uint32_t wsum[16];
   __shared__ unsigned long long wsum64[16];
+  __shared__ unsigned long long s_ent[16];
   const uint32_t tid = threadIdx.x;
   if (*err != ~0ull) {  // counting failed: report only the error
     if (tid == 0) {
       meta->err = *err;
-      meta->n_hi = meta->n_gids = meta->n_exc = meta->entries = 0;
+      meta->n_hi = meta->n_gids = meta->n_exc = meta->entries = meta->max_len = meta->n_ghi = 0;
     }
     return;
   }
-  unsigned long long entries = 0;
-  // per sorted position: K, D, inverse permutation, count>=2 prefix
-  uint32_t carry = 0;
-  for (uint32_t b = 0; b < N; b += 1024) {
-    const uint32_t s = b + tid;
-    uint32_t h = 0;
-    if (s < N) {
-      const uint32_t i = perm[s];
-      inv[i] = s;
-      K[s] = Korig[i];
-      invK[s] = 1.0 / (double)Korig[i];
-      D[s] = Dorig[i];
-      entries += Dorig[i];
-      h = nhi_orig[i];
-    }
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<1024>(h, wsum, tot);
-    if (s < N) hi_off[s] = carry + ex;
-    carry += tot;
-  }
-  if (tid == 0) hi_off[N] = carry;
-  __syncthreads();
-  // column groups
+  const uint32_t n_hi = chunked_scan(HcountIn{hcount}, N, hi_off, wsum);
+  // column groups: padded length = longest list (the last, D ascending) rounded to 16
   const uint32_t G = (N + 63) / 64;
-  unsigned long long gcarry = 0;
-  for (uint32_t b = 0; b < G; b += 1024) {
-    const uint32_t g = b + tid;
-    unsigned long long sz = 0;
-    if (g < G) {
-      const uint32_t last = min(64u * g + 63u, N - 1);
-      const uint32_t L = (D[last] + 15u) & ~15u;
-      grp_len[g] = L;
-      sz = 64ull * L;
-    }
-    unsigned long long tot;
-    const unsigned long long ex = block_exclusive_scan64<1024>(sz, wsum64, tot);
-    if (g < G) grp_off[g] = gcarry + ex;
-    gcarry += tot;
-  }
-  if (tid == 0) grp_off[G] = gcarry;
+  for (uint32_t g = tid; g < G; g += 1024) grp_len[g] = (D[min(64u * g + 63u, N - 1)] + 15u) & ~15u;
   __syncthreads();
-  // row blocks: capacity for merged count>=2 words = sum over the 16 rows
-  const uint32_t RB = (N + 15) / 16;
-  uint32_t ecarry = 0;
-  for (uint32_t b = 0; b < RB; b += 1024) {
-    const uint32_t rb = b + tid;
-    uint32_t c = 0;
-    if (rb < RB) {
-      const uint32_t s0 = 16u * rb, s1 = min(s0 + 16u, N);
-      c = hi_off[s1] - hi_off[s0];
-    }
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<1024>(c, wsum, tot);
-    if (rb < RB) exc_off[rb] = ecarry + ex;
-    ecarry += tot;
+  const unsigned long long n_gids = chunked_scan(GroupIn{grp_len}, G, (unsigned long long *)grp_off, wsum64);
+  // count>=2 entries per group: longest lane, rounded up to 4
+  for (uint32_t g = tid; g < G; g += 1024) {
+    uint32_t m = 0;
+    for (uint32_t s = 64u * g; s < min(64u * g + 64u, N); s++) m = max(m, hcount[s]);
+    ghi_len[g] = (m + 3u) & ~3u;
   }
-  if (tid == 0) exc_off[RB] = ecarry;
-  // total entries
-  unsigned long long et;
-  block_exclusive_scan64<1024>(entries, wsum64, et);
+  __syncthreads();
+  const unsigned long long n_ghi = chunked_scan(GroupIn{ghi_len}, G, (unsigned long long *)ghi_off, wsum64);
+  const uint32_t RB = (N + 15) / 16;
+  const uint32_t n_exc = chunked_scan(BlockHiIn{hi_off, N}, RB, exc_off, wsum);
+  unsigned long long ent = 0;
+  for (uint32_t s = tid; s < N; s += 1024) ent += D[s];
+#pragma unroll
+  for (int o = 32; o; o >>= 1) ent += __shfl_xor(ent, o, 64);
+  if ((tid & 63) == 0) s_ent[tid >> 6] = ent;
+  __syncthreads();
   if (tid == 0) {
+    unsigned long long e = 0;
+    for (int w = 0; w < 16; w++) e += s_ent[w];
     meta->err = ~0ull;
-    meta->n_hi = carry;
-    meta->n_gids = gcarry;
-    meta->n_exc = ecarry;
-    meta->entries = et;
+    meta->n_hi = n_hi;
+    meta->n_gids = n_gids;
+    meta->n_exc = n_exc;
+    meta->entries = e;
+    meta->max_len = grp_len[G - 1];
+    meta->n_ghi = n_ghi;
   }
 }
 
 hipError_t launch_layout_meta(hipStream_t st, uint32_t N, const uint32_t *perm,
                               const uint32_t *Dorig, const uint32_t *Korig,
                               const uint32_t *nhi_orig, uint32_t *inv, uint32_t *K, uint32_t *D,
-                              double *invK, uint32_t *hi_off, uint64_t *grp_off, uint32_t *grp_len,
+                              double *invK, uint32_t *hcount, uint32_t *hi_off, uint64_t *grp_off,
+                              uint32_t *grp_len, uint64_t *ghi_off, uint32_t *ghi_len,
                               uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta) {
-  hipLaunchKernelGGL(layout_meta_kernel, dim3(1), dim3(1024), 0, st, N, perm, Dorig, Korig,
-                     nhi_orig, inv, K, D, invK, hi_off, grp_off, grp_len, exc_off, err, meta);
+  hipLaunchKernelGGL(layout_gather_kernel, dim3((N + 255) / 256), dim3(256), 0, st, N, perm, Dorig,
+                     Korig, nhi_orig, inv, K, D, invK, hcount, err);
+  KD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(layout_meta_kernel, dim3(1), dim3(1024), 0, st, N, D, hcount, hi_off, grp_off,
+                     grp_len, ghi_off, ghi_len, exc_off, err, meta);
   return hipGetLastError();
 }
 
-// One 64-lane workgroup per column group: lane l copies the distinct words of
-// sorted position 64g + l into the interleaved layout (16-byte stores, the
-// 64 lanes' chunks adjacent).
-__global__ __launch_bounds__(64) void layout_groups_kernel(SetView v,
-                                                           const uint64_t *__restrict__ offsets,
-                                                           const uint16_t *__restrict__ cap_ids,
-                                                           uint16_t *__restrict__ gids) {
-  const uint32_t g = blockIdx.x, lane = threadIdx.x;
-  const uint32_t s = 64u * g + lane;
+// Grid (column group, slice of 16 chunks), 256 threads: lane l = tid % 64
+// writes chunks 16 y + tid / 64 + 4 k (k = 0..3) of sequence 64 g + l into
+// the interleaved layout (the 64 lanes' 16-byte chunks adjacent).
+__global__ __launch_bounds__(256) void layout_groups_kernel(SetView v,
+                                                            const uint64_t *__restrict__ offsets,
+                                                            const uint16_t *__restrict__ cap_ids,
+                                                            uint16_t *__restrict__ gids) {
+  const uint32_t g = blockIdx.x, lane = threadIdx.x & 63u, sub = threadIdx.x >> 6;
   const uint32_t L = v.grp_len[g];
+  const uint32_t t8_0 = blockIdx.y * 16u;
+  if (t8_0 * 8u >= L) return;
+  const uint32_t s = 64u * g + lane;
   uint32_t Dl = 0;
   const uint16_t *src = nullptr;
   if (s < v.N) {
@@ -151,7 +191,10 @@ __global__ __launch_bounds__(64) void layout_groups_kernel(SetView v,
     Dl = v.D[s];
   }
   uint4 *dst = reinterpret_cast<uint4 *>(gids + v.grp_off[g]) + lane;
-  for (uint32_t t8 = 0; t8 < L / 8; t8++) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const uint32_t t8 = t8_0 + sub + 4u * k;
+    if (t8 * 8u >= L) break;
     uint32_t e[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) {
@@ -173,7 +216,8 @@ __global__ __launch_bounds__(256) void layout_hi_kernel(SetView v,
                                                         const uint16_t *__restrict__ cap_ids,
                                                         const uint16_t *__restrict__ cap_cnt,
                                                         uint16_t *__restrict__ hi_ids,
-                                                        uint16_t *__restrict__ hi_cnt) {
+                                                        uint16_t *__restrict__ hi_cnt,
+                                                        uint32_t *__restrict__ ghi) {
   const uint32_t s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (s >= v.N) return;
   const uint32_t i = v.perm[s];
@@ -193,6 +237,8 @@ __global__ __launch_bounds__(256) void layout_hi_kernel(SetView v,
       const uint32_t p = o + (uint32_t)__popcll(m & lanemask_lt());
       hi_ids[p] = id;
       hi_cnt[p] = c;
+      const uint32_t t = p - v.hi_off[s];
+      ghi[v.ghi_off[s >> 6] + 64ull * t + (s & 63u)] = (uint32_t)id | ((uint32_t)c << 16);
     }
     o += (uint32_t)__popcll(m);
   }
@@ -200,12 +246,15 @@ __global__ __launch_bounds__(256) void layout_hi_kernel(SetView v,
 
 hipError_t launch_layout_fill(hipStream_t st, const SetView &v, const uint64_t *offsets,
                               const uint16_t *cap_ids, const uint16_t *cap_cnt, uint16_t *gids,
-                              uint16_t *hi_ids, uint16_t *hi_cnt) {
+                              uint16_t *hi_ids, uint16_t *hi_cnt, uint32_t *ghi,
+                              uint32_t max_len) {
   if (v.N == 0) return hipSuccess;
-  hipLaunchKernelGGL(layout_groups_kernel, dim3(v.G), dim3(64), 0, st, v, offsets, cap_ids, gids);
+  const uint32_t slices = (max_len / 8 + 15) / 16;
+  hipLaunchKernelGGL(layout_groups_kernel, dim3(v.G, slices > 0 ? slices : 1), dim3(256), 0, st, v,
+                     offsets, cap_ids, gids);
   KD_HIP(hipGetLastError());
   hipLaunchKernelGGL(layout_hi_kernel, dim3((v.N + 3) / 4), dim3(256), 0, st, v, offsets, cap_ids,
-                     cap_cnt, hi_ids, hi_cnt);
+                     cap_cnt, hi_ids, hi_cnt, ghi);
   return hipGetLastError();
 }
 
@@ -213,13 +262,13 @@ hipError_t launch_layout_fill(hipStream_t st, const SetView &v, const uint64_t *
 // row) merges one block: each lane walks its row's sorted list, the quarter
 // agrees on the smallest pending word, and every lane writes its row's
 // count for it (0 when the row lacks it).
-__global__ __launch_bounds__(256) void exc_build_kernel(SetView v, uint32_t nblocks,
+__global__ __launch_bounds__(64) void exc_build_kernel(SetView v, uint32_t nblocks,
                                                         const uint32_t *__restrict__ rowpos,
                                                         const uint32_t *__restrict__ exc_off,
                                                         uint32_t *__restrict__ exc_n,
                                                         uint16_t *__restrict__ exc_ids,
                                                         uint16_t *__restrict__ exc_cnt) {
-  const uint32_t gq = blockIdx.x * 16 + (threadIdx.x >> 4);  // block handled by this quarter
+  const uint32_t gq = blockIdx.x * 4 + (threadIdx.x >> 4);  // block handled by this quarter
   const uint32_t r = threadIdx.x & 15;
   const bool active = gq < nblocks;
   uint32_t s = 0xFFFFFFFFu;
@@ -253,7 +302,7 @@ hipError_t launch_exc_build(hipStream_t st, const SetView &v, uint32_t nblocks,
                             const uint32_t *rowpos, const uint32_t *exc_off, uint32_t *exc_n,
                             uint16_t *exc_ids, uint16_t *exc_cnt) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(exc_build_kernel, dim3((nblocks + 15) / 16), dim3(256), 0, st, v, nblocks,
+  hipLaunchKernelGGL(exc_build_kernel, dim3((nblocks + 3) / 4), dim3(64), 0, st, v, nblocks,
                      rowpos, exc_off, exc_n, exc_ids, exc_cnt);
   return hipGetLastError();
 }

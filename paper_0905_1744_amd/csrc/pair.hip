@@ -172,6 +172,39 @@ __device__ __forceinline__ void column_excess(const SetView &v, uint32_t sc, con
   }
 }
 
+// Levels >= 2 for one column of the rank kernel: the column's count>=2
+// entries come from the group-interleaved list (q0..q3 are its first four,
+// loaded before the level-1 loop); hits in the row block's bitmap are
+// looked up in the block's merged list (eid/ecnt: LDS copy or HBM).
+__device__ __forceinline__ void column_excess_grouped(const uint32_t *__restrict__ hp, uint32_t hl,
+                                                      const uint32_t (&q0)[4], const uint32_t *BM,
+                                                      const uint16_t *eid, const uint16_t *ecnt,
+                                                      uint32_t en, uint32_t (&cnt)[16]) {
+  for (uint32_t t = 0; t < hl; t += 4) {
+    uint32_t q[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) q[k] = t == 0 ? q0[k] : hp[(size_t)(t + k) * 64];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint32_t id = q[k] & 0xFFFFu, cj = q[k] >> 16;
+      if (cj < 2u || !((BM[id >> 5] >> (id & 31u)) & 1u)) continue;
+      uint32_t lo = 0, hi = en;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (eid[mid] < id) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo >= en || eid[lo] != id) continue;
+      const uint16_t *c = ecnt + (size_t)lo * 16;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const uint32_t cr = c[r];
+        cnt[r] += cr >= 2u ? min(cr, cj) - 1u : 0u;
+      }
+    }
+  }
+}
+
 // Finishes a fixed halving butterfly over the 64 lanes.  On entry lane l
 // holds u8[i] = the pair sum (lanes l, l^32) of value i + 8 (l >> 5); on
 // exit lanes 4r..4r+3 return the total of value r over all 64 lanes.
@@ -252,11 +285,16 @@ struct ListedRows {
   __device__ uint32_t operator()(uint32_t r) const { return pos[r]; }
 };
 
+constexpr uint32_t kExcLds = 256;  // merged count>=2 words of a row block kept in LDS
+
 struct RankShared {
   RowShared row;
   LogEntry logt[kLogEntries];
   double ln2;
   unsigned long long racc[48];  // 16 rows x 3 limbs of the current row block
+  uint16_t exc_id[kExcLds];
+  uint16_t exc_c[kExcLds * 16];
+  long long colacc[16][2][3][64];  // [wave][group of the wave][limb][lane]
 };
 
 // Level-1 counts for this lane's column, dispatching on the plane bucket.
@@ -271,34 +309,90 @@ __device__ __forceinline__ void column_counts(const uint16_t *T16, const uint4 *
   }
 }
 
-// One workgroup = 16 waves = 16 consecutive column groups g0..g0+15 (wave w
-// takes group g0 + w) against row blocks rb0..rb1-1, one row block at a
-// time.  Row partials of a row block meet in LDS (exact integer adds) and
-// go to HBM once; a column's partials stay in registers across the row
-// blocks and go to HBM once at the end.
+// One 16 x 64 tile: row block rb (in LDS) against column group g (this
+// wave).  Adds the tile's row sums into sh.racc (LDS, exact) and its column
+// sums into the lane's limbs.
+__device__ __forceinline__ void rank_tile(const SetView &v, RankShared &sh, uint32_t rb, uint32_t g,
+                                          double delta, const uint16_t *eid, const uint16_t *ecnt,
+                                          uint32_t en, long long (&col)[3][64]) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t L = __builtin_amdgcn_readfirstlane(v.grp_len[g]);
+  const uint32_t hl = __builtin_amdgcn_readfirstlane(v.ghi_len[g]);
+  const uint32_t sc = 64u * g + lane;
+  const bool vc = sc < v.N;
+  const uint4 *p = reinterpret_cast<const uint4 *>(v.gids + v.grp_off[g]) + lane;
+  const uint32_t *hp = v.ghi + v.ghi_off[g] + lane;
+  uint32_t q0[4] = {0u, 0u, 0u, 0u};
+  if (hl > 0) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) q0[k] = hp[(size_t)k * 64];
+  }
+  const uint32_t Kc = vc ? v.K[sc] : 1u;
+  const double invKc = vc ? v.invK[sc] : 0.0;
+  uint32_t cnt[16];
+  column_counts(reinterpret_cast<const uint16_t *>(sh.row.T32), p, L, cnt);
+  column_excess_grouped(hp, hl, q0, sh.row.BM, eid, ecnt, en, cnt);
+  // F = shared / min(K_r, K_c) (Equation 1), d = -ln(delta + F) (Equation 2);
+  // rows r and r + 8 are formed together and immediately folded across
+  // lanes l and l ^ 32 (first step of the halving butterfly)
+  double u8[8];
+  double colsum = 0.0;
+  const bool b5 = lane & 32u;
+#pragma unroll
+  for (int r = 0; r < 8; r++) {
+    double d[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      const uint32_t rr = r + 8 * h, sr = 16u * rb + rr;
+      d[h] = 0.0;
+      if (vc && sc < sr && sr < v.N) {
+        const double inv = sh.row.rowK[rr] < Kc ? sh.row.rowInv[rr] : invKc;
+        d[h] = -log_tab(fma((double)cnt[rr], inv, delta), sh.logt, sh.ln2);
+      }
+    }
+    colsum += d[0];
+    colsum += d[1];
+    const double send = b5 ? d[0] : d[1];
+    const double keep = b5 ? d[1] : d[0];
+    u8[r] = keep + __shfl_xor(send, 32, 64);
+  }
+  const double rowtot = halving_reduce8(u8, lane);
+  if ((lane & 3u) == 0) {
+    long long l0, l1, l2;
+    fix_limbs(rowtot, l0, l1, l2);
+    unsigned long long *ra = sh.racc + 3u * (lane >> 2);
+    atomicAdd(ra, (unsigned long long)l0);
+    atomicAdd(ra + 1, (unsigned long long)l1);
+    atomicAdd(ra + 2, (unsigned long long)l2);
+  }
+  long long l0, l1, l2;
+  fix_limbs(colsum, l0, l1, l2);
+  col[0][lane] += l0;
+  col[1][lane] += l1;
+  col[2][lane] += l2;
+}
+
+// One workgroup = 16 waves x 2 = 32 consecutive column groups g0..g0+31
+// (wave w takes g0 + w and g0 + 16 + w) against row blocks rb0..rb1-1, one
+// row block at a time.  Row partials of a row block meet in LDS (exact
+// integer adds) and go to HBM once; column partials stay in registers
+// across the row blocks and go to HBM once at the end.
 __global__ __launch_bounds__(1024) void rank_pairs_kernel(const SetView *__restrict__ views,
                                                           const PairTask *__restrict__ tasks,
                                                           double delta) {
   __shared__ RankShared sh;
   const PairTask tk = tasks[blockIdx.x];
   const SetView v = views[tk.set];
-  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (uint32_t q = tid; q < (uint32_t)kLogEntries; q += 1024) log_table_entry((int)q, sh.logt[q]);
   if (tid == 0) sh.ln2 = log(2.0);
   if (tid < 48) sh.racc[tid] = 0;
   clear_rows(sh.row);
 
-  const uint32_t g = tk.g0 + wave;
-  const bool gvalid = g < v.G;
-  const uint32_t sc = 64u * g + lane;
-  const bool vc = gvalid && sc < v.N;
-  const uint32_t Kc = vc ? v.K[sc] : 1u;
-  const double invKc = vc ? v.invK[sc] : 0.0;
-  const uint32_t L = gvalid ? v.grp_len[g] : 0u;
-  const uint4 *p = gvalid ? reinterpret_cast<const uint4 *>(v.gids + v.grp_off[g]) + lane : nullptr;
-  const uint16_t *T16 = reinterpret_cast<const uint16_t *>(sh.row.T32);
-  long long c0 = 0, c1 = 0, c2 = 0;
-  bool any = false;
+  const uint32_t ga = tk.g0 + wave, gb = tk.g0 + 16u + wave;
+#pragma unroll
+  for (int k = 0; k < 6; k++) (&sh.colacc[wave][0][0][0])[k * 64 + lane] = 0;
 
   for (uint32_t rb = tk.rb0; rb < tk.rb1; rb++) {
     if (rb > tk.rb0) {
@@ -315,52 +409,17 @@ __global__ __launch_bounds__(1024) void rank_pairs_kernel(const SetView *__restr
     __syncthreads();
     const uint32_t e0 = v.exc_off[rb], en = v.exc_n[rb];
     touch_rows<true>(v, ConsecutiveRows{16u * rb, v.N}, v.exc_ids, e0, en, sh.row);
-    __syncthreads();
-    // the tile has pairs below the diagonal only when rb >= 4 g
-    if (gvalid && rb >= 4u * g) {
-      uint32_t cnt[16];
-      column_counts(T16, p, L, cnt);
-      if (vc) column_excess(v, sc, sh.row.BM, v.exc_ids, v.exc_cnt, e0, en, cnt);
-      // F = shared / min(K_r, K_c) (Equation 1), d = -ln(delta + F) (Equation 2);
-      // rows r and r + 8 are formed together and immediately folded across
-      // lanes l and l ^ 32 (first step of the halving butterfly)
-      double u8[8];
-      double colsum = 0.0;
-      const bool b5 = lane & 32u;
-#pragma unroll
-      for (int r = 0; r < 8; r++) {
-        double d[2];
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-          const uint32_t rr = r + 8 * h, sr = 16u * rb + rr;
-          d[h] = 0.0;
-          if (vc && sc < sr && sr < v.N) {
-            const double inv = sh.row.rowK[rr] < Kc ? sh.row.rowInv[rr] : invKc;
-            d[h] = -log_tab(fma((double)cnt[rr], inv, delta), sh.logt, sh.ln2);
-          }
-        }
-        colsum += d[0];
-        colsum += d[1];
-        const double send = b5 ? d[0] : d[1];
-        const double keep = b5 ? d[1] : d[0];
-        u8[r] = keep + __shfl_xor(send, 32, 64);
-      }
-      const double rowtot = halving_reduce8(u8, lane);
-      if ((lane & 3u) == 0) {
-        long long l0, l1, l2;
-        fix_limbs(rowtot, l0, l1, l2);
-        unsigned long long *ra = sh.racc + 3u * (lane >> 2);
-        atomicAdd(ra, (unsigned long long)l0);
-        atomicAdd(ra + 1, (unsigned long long)l1);
-        atomicAdd(ra + 2, (unsigned long long)l2);
-      }
-      long long l0, l1, l2;
-      fix_limbs(colsum, l0, l1, l2);
-      c0 += l0;
-      c1 += l1;
-      c2 += l2;
-      any = true;
+    const bool lds_exc = en <= kExcLds;
+    if (lds_exc) {
+      for (uint32_t e = tid; e < en; e += 1024) sh.exc_id[e] = v.exc_ids[e0 + e];
+      for (uint32_t e = tid; e < 16u * en; e += 1024) sh.exc_c[e] = v.exc_cnt[16ull * e0 + e];
     }
+    __syncthreads();
+    const uint16_t *eid = lds_exc ? sh.exc_id : v.exc_ids + e0;
+    const uint16_t *ecnt = lds_exc ? sh.exc_c : v.exc_cnt + 16ull * e0;
+    // a tile has pairs below the diagonal only when rb >= 4 g
+    if (ga < v.G && rb >= 4u * ga) rank_tile(v, sh, rb, ga, delta, eid, ecnt, en, sh.colacc[wave][0]);
+    if (gb < v.G && rb >= 4u * gb) rank_tile(v, sh, rb, gb, delta, eid, ecnt, en, sh.colacc[wave][1]);
     __syncthreads();
   }
   if (tid < 48) {
@@ -368,11 +427,15 @@ __global__ __launch_bounds__(1024) void rank_pairs_kernel(const SetView *__restr
     if (s < v.N)
       atomicAdd(reinterpret_cast<unsigned long long *>(v.acc) + 3ull * s + tid % 3u, sh.racc[tid]);
   }
-  if (vc && any) {
-    unsigned long long *a = reinterpret_cast<unsigned long long *>(v.acc) + 3ull * sc;
-    atomicAdd(a, (unsigned long long)c0);
-    atomicAdd(a + 1, (unsigned long long)c1);
-    atomicAdd(a + 2, (unsigned long long)c2);
+  unsigned long long *acc = reinterpret_cast<unsigned long long *>(v.acc);
+#pragma unroll
+  for (uint32_t gi = 0; gi < 2; gi++) {
+    const uint32_t g = gi ? gb : ga, sc = 64u * g + lane;
+    if (g < v.G && sc < v.N && tk.rb1 > 4u * g) {
+#pragma unroll
+      for (int k = 0; k < 3; k++)
+        atomicAdd(acc + 3ull * sc + k, (unsigned long long)sh.colacc[wave][gi][k][lane]);
+    }
   }
 }
 

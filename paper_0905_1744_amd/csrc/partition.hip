@@ -58,7 +58,8 @@ size_t partition_scratch_bytes(uint32_t n, uint32_t B) {
 __device__ void partition_one(const double *__restrict__ R, uint32_t n, uint32_t B,
                               uint32_t *__restrict__ bucket, uint32_t *__restrict__ order,
                               uint32_t *__restrict__ offsets, double *__restrict__ piv_r,
-                              uint32_t *__restrict__ piv_i, PartScratch s, RadixShared<1024> &sh) {
+                              uint32_t *__restrict__ piv_i, PartScratch s, RadixShared<1024> &sh,
+                              uint32_t *s_prho) {
   const uint32_t tid = threadIdx.x;
   for (uint32_t i = tid; i < n; i += 1024) {
     s.k0[i] = rank_key(R[i]);
@@ -97,7 +98,7 @@ __device__ void partition_one(const double *__restrict__ R, uint32_t n, uint32_t
   const uint32_t *sv = w3 ? s.sv1 : s.sv0;
   for (uint32_t i = tid; i + 1 < B; i += 1024) {
     const uint32_t pos = i * B + B / 2 - 1;
-    s.prho[i] = ss[pos];
+    s_prho[i] = ss[pos];
     if (piv_i) piv_i[i] = sv[pos];
     if (piv_r) piv_r[i] = R[sv[pos]];
     offsets[i + 1] = ss[pos] + 1;
@@ -113,7 +114,7 @@ __device__ void partition_one(const double *__restrict__ R, uint32_t n, uint32_t
     uint32_t lo = 0, hi = B - 1;  // count pivots with prho < r
     while (lo < hi) {
       const uint32_t mid = (lo + hi) >> 1;
-      if (s.prho[mid] < r) lo = mid + 1;
+      if (s_prho[mid] < r) lo = mid + 1;
       else hi = mid;
     }
     bucket[i] = lo;
@@ -125,7 +126,8 @@ __global__ __launch_bounds__(1024) void partition_kernel(const double *R, uint32
                                                          uint32_t *offsets, double *piv_r,
                                                          uint32_t *piv_i, void *scratch) {
   __shared__ RadixShared<1024> sh;
-  partition_one(R, n, B, bucket, order, offsets, piv_r, piv_i, carve(scratch, n, B), sh);
+  __shared__ uint32_t prho[kMaxBuckets];
+  partition_one(R, n, B, bucket, order, offsets, piv_r, piv_i, carve(scratch, n, B), sh, prho);
 }
 
 hipError_t launch_partition(hipStream_t st, const double *ranks, uint32_t n, uint32_t B,

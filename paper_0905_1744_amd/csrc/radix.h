@@ -2,10 +2,11 @@
 //
 // One workgroup sorts one segment, so a batch of independent segments is
 // sorted by a grid with one workgroup per segment.  Keys and values live in
-// global memory and ping-pong between two buffers; each pass moves the
-// elements in tiles of NT with a wave-level multi-split (ballots on the
-// digit bits) so equal digits keep their input order.  A pass whose digit is
-// the same for every key is skipped.
+// global memory and ping-pong between two buffers.  The digit histograms of
+// all passes are taken in one read (they do not depend on the order); each
+// pass then moves the elements in tiles of 4 x NT with a wave-level
+// multi-split (ballots on the digit bits) so equal digits keep their input
+// order.  A pass whose digit is the same for every key is skipped.
 #pragma once
 
 #include "kd_internal.h"
@@ -15,9 +16,11 @@ namespace kd {
 template <int NT>
 struct RadixShared {
   static constexpr int NW = NT / 64;
+  static constexpr int SUB = 4;   // elements per thread per tile
+  uint32_t hist[8][256];          // digit histograms of every pass
   uint32_t base[256];
   uint32_t tot[256];
-  uint32_t wcnt[NW][256];
+  uint16_t wcnt[SUB][NW][256];    // per (sub-tile, wave, digit) counts, then prefixes
   uint32_t flag;
   uint32_t wsum[NW];
 };
@@ -74,83 +77,110 @@ __device__ inline unsigned long long block_exclusive_scan64(unsigned long long x
   return before + incl - x;
 }
 
-// Sorts (k0, v0)[0, n) stably by key bits [bit_lo, bit_hi).  Returns 0 when
-// the result ends in (k0, v0) and 1 when it ends in (k1, v1).
+// Sorts (k0, v0)[0, n) stably by key bits [bit_lo, bit_hi) (at most 64
+// bits, 8 per pass).  Returns 0 when the result ends in (k0, v0) and 1
+// when it ends in (k1, v1).  A tile is SUB x NT elements: element
+// t0 + s NT + tid; its position among equal digits of the tile is found
+// from ballots (wave), then per-(sub-tile, wave) prefix counts (LDS).
 template <int NT, typename KeyT>
 __device__ int block_radix_sort(KeyT *k0, uint32_t *v0, KeyT *k1, uint32_t *v1, uint32_t n,
                                 int bit_lo, int bit_hi, RadixShared<NT> &sh) {
-  constexpr int NW = NT / 64;
+  constexpr int NW = NT / 64, SUB = RadixShared<NT>::SUB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int npass = (bit_hi - bit_lo + 7) / 8;
+  for (int x = tid; x < npass * 256; x += NT) (&sh.hist[0][0])[x] = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += NT) {
+    const KeyT key = k0[i];
+    for (int q = 0; q < npass; q++) {
+      const int sh_q = bit_lo + 8 * q, nb_q = (bit_hi - sh_q) < 8 ? (bit_hi - sh_q) : 8;
+      atomicAdd(&sh.hist[q][(uint32_t)(key >> sh_q) & ((1u << nb_q) - 1u)], 1u);
+    }
+  }
+  __syncthreads();
   int cur = 0;
-  for (int shift = bit_lo; shift < bit_hi; shift += 8) {
+  for (int q = 0; q < npass; q++) {
+    const int shift = bit_lo + 8 * q;
+    const int nb = (bit_hi - shift) < 8 ? (bit_hi - shift) : 8;
+    const uint32_t dmask = (1u << nb) - 1u;
     KeyT *kin = cur ? k1 : k0;
     uint32_t *vin = cur ? v1 : v0;
     KeyT *kout = cur ? k0 : k1;
     uint32_t *vout = cur ? v0 : v1;
-    const int nb = (bit_hi - shift) < 8 ? (bit_hi - shift) : 8;
-    const uint32_t dmask = (1u << nb) - 1u;
-    for (int d = tid; d < 256; d += NT) sh.tot[d] = 0;
     if (tid == 0) sh.flag = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < n; i += NT) atomicAdd(&sh.tot[(uint32_t)(kin[i] >> shift) & dmask], 1u);
-    __syncthreads();
     for (int d = tid; d < 256; d += NT)
-      if (sh.tot[d] == n) sh.flag = 1;
+      if (sh.hist[q][d] == n) sh.flag = 1;
     __syncthreads();
     if (sh.flag) continue;  // identical digit everywhere: the pass is the identity
     if (wave == 0) {
-      uint32_t a0 = sh.tot[lane * 4], a1 = sh.tot[lane * 4 + 1];
-      uint32_t a2 = sh.tot[lane * 4 + 2], a3 = sh.tot[lane * 4 + 3];
-      uint32_t s = a0 + a1 + a2 + a3, incl = s;
+      const uint32_t a0 = sh.hist[q][lane * 4], a1 = sh.hist[q][lane * 4 + 1];
+      const uint32_t a2 = sh.hist[q][lane * 4 + 2], a3 = sh.hist[q][lane * 4 + 3];
+      const uint32_t sum = a0 + a1 + a2 + a3;
+      uint32_t incl = sum;
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(incl, o, 64);
+        const uint32_t y = __shfl_up(incl, o, 64);
         if (lane >= o) incl += y;
       }
-      uint32_t ex = incl - s;
+      const uint32_t ex = incl - sum;
       sh.base[lane * 4] = ex;
       sh.base[lane * 4 + 1] = ex + a0;
       sh.base[lane * 4 + 2] = ex + a0 + a1;
       sh.base[lane * 4 + 3] = ex + a0 + a1 + a2;
     }
-    for (int x = tid; x < NW * 256; x += NT) (&sh.wcnt[0][0])[x] = 0;
+    for (int x = tid; x < SUB * NW * 256; x += NT) (&sh.wcnt[0][0][0])[x] = 0;
     __syncthreads();
-    for (uint32_t t0 = 0; t0 < n; t0 += NT) {
-      const uint32_t i = t0 + tid;
-      const bool valid = i < n;
-      KeyT key = valid ? kin[i] : (KeyT)0;
-      uint32_t val = valid ? vin[i] : 0u;
-      uint32_t d = valid ? ((uint32_t)(key >> shift) & dmask) : 0u;
-      unsigned long long m = __ballot(valid);
-      for (int b = 0; b < nb; b++) {
-        unsigned long long bb = __ballot((d >> b) & 1u);
-        m &= ((d >> b) & 1u) ? bb : ~bb;
+    for (uint32_t t0 = 0; t0 < n; t0 += SUB * NT) {
+      KeyT key[SUB];
+      uint32_t val[SUB], dig[SUB], rank[SUB];
+      bool valid[SUB];
+#pragma unroll
+      for (int s = 0; s < SUB; s++) {  // issue every load of the tile first
+        const uint32_t i = t0 + s * NT + tid;
+        valid[s] = i < n;
+        key[s] = valid[s] ? kin[i] : (KeyT)0;
+        val[s] = valid[s] ? vin[i] : 0u;
       }
-      const unsigned long long lt = m & lanemask_lt();
-      const uint32_t rank = (uint32_t)__popcll(lt);
-      if (valid && lt == 0) sh.wcnt[wave][d] = (uint32_t)__popcll(m);
+#pragma unroll
+      for (int s = 0; s < SUB; s++) {
+        dig[s] = (uint32_t)(key[s] >> shift) & dmask;
+        unsigned long long m = __ballot(valid[s]);
+        for (int b = 0; b < nb; b++) {
+          const unsigned long long bb = __ballot((dig[s] >> b) & 1u);
+          m &= ((dig[s] >> b) & 1u) ? bb : ~bb;
+        }
+        const unsigned long long lt = m & lanemask_lt();
+        rank[s] = (uint32_t)__popcll(lt);
+        if (valid[s] && lt == 0) sh.wcnt[s][wave][dig[s]] = (uint16_t)__popcll(m);
+      }
       __syncthreads();
       for (int d2 = tid; d2 < 256; d2 += NT) {
         uint32_t run = 0;
+        for (int s = 0; s < SUB; s++)
 #pragma unroll
-        for (int w = 0; w < NW; w++) {
-          uint32_t c = sh.wcnt[w][d2];
-          sh.wcnt[w][d2] = run;
-          run += c;
-        }
+          for (int w = 0; w < NW; w++) {
+            const uint32_t c = sh.wcnt[s][w][d2];
+            sh.wcnt[s][w][d2] = (uint16_t)run;
+            run += c;
+          }
         sh.tot[d2] = run;
       }
       __syncthreads();
-      if (valid) {
-        uint32_t pos = sh.base[d] + sh.wcnt[wave][d] + rank;
-        kout[pos] = key;
-        vout[pos] = val;
+#pragma unroll
+      for (int s = 0; s < SUB; s++) {
+        if (valid[s]) {
+          const uint32_t pos = sh.base[dig[s]] + sh.wcnt[s][wave][dig[s]] + rank[s];
+          kout[pos] = key[s];
+          vout[pos] = val[s];
+        }
       }
       __syncthreads();
       for (int d2 = tid; d2 < 256; d2 += NT) {
         sh.base[d2] += sh.tot[d2];
+        for (int s = 0; s < SUB; s++)
 #pragma unroll
-        for (int w = 0; w < NW; w++) sh.wcnt[w][d2] = 0;
+          for (int w = 0; w < NW; w++) sh.wcnt[s][w][d2] = 0;
       }
       __syncthreads();
     }
