@@ -7,8 +7,8 @@
 // words), K and the number of words seen at least twice.
 //
 // Sequences of up to 4096 words: one 64-lane workgroup each; the residues
-// are mapped through an LDS Dayhoff-6 table, the words are formed in LDS,
-// bitonic-sorted in LDS and run-length encoded with ballots.  Longer
+// are mapped through an LDS Dayhoff-6 table and the words collected in an
+// LDS presence bitmap (see count_one).  Longer
 // sequences (rare) are queued and handled by a persistent kernel that
 // histograms into a dense 46656-bin LDS table (two 16-bit bins per word;
 // a sequence has at most 65535 words, so a bin never carries).
@@ -33,21 +33,38 @@ __device__ inline uint32_t check_offsets(const uint64_t *off, uint32_t i, uint32
 }
 
 // Counts one sequence of K <= CAP words with one 64-lane workgroup.
-// Returns false (without touching outputs) when the sequence is longer.
+//
+// Every word sets its bit in a 46656-bit LDS bitmap; a word whose bit was
+// already set is appended to a list of repeats.  Lane l then owns bitmap
+// words [23 l, 23 l + 23): a wave prefix sum of their popcounts gives each
+// lane the rank of its first set bit, so walking the bits in order emits the
+// distinct words already sorted.  A repeat's rank is the prefix of its
+// bitmap chunk plus the popcounts before it; its count slot is incremented.
+template <int CAP>
+struct CountShared {
+  uint32_t bm[kBitmapWords];
+  uint32_t cnt[CAP / 2];   // two 16-bit counts per word (a count never exceeds K <= 65535)
+  uint16_t rep[CAP];       // repeated occurrences
+  uint32_t cpre[64];       // rank of the first set bit of each lane's chunk
+  uint32_t nrep;
+  uint8_t codes[CAP + 8];
+  uint8_t lut[256];
+};
+
 template <int CAP>
 __device__ __forceinline__ void count_one(const uint8_t *__restrict__ res, uint32_t i, uint64_t o0,
-                                          uint32_t n, uint64_t cap, const uint8_t *lut,
-                                          uint8_t *codes, uint16_t *w, uint16_t *hp,
+                                          uint32_t n, uint64_t cap, CountShared<CAP> &sh,
                                           uint16_t *__restrict__ cap_ids,
                                           uint16_t *__restrict__ cap_cnt, uint32_t *__restrict__ Dout,
                                           uint32_t *__restrict__ Kout,
                                           uint32_t *__restrict__ nhiout, unsigned long long *err) {
+  constexpr uint32_t kChunk = (kBitmapWords + 63) / 64;  // 23 bitmap words per lane
   const uint32_t lane = threadIdx.x;
   const uint32_t K = n - (kK - 1);
   uint32_t bad = 0xFFFFFFFFu;
   for (uint32_t t = lane; t < n; t += 64) {
-    const uint8_t c = lut[res[o0 + t]];
-    codes[t] = c;
+    const uint8_t c = sh.lut[res[o0 + t]];
+    sh.codes[t] = c;
     if (c == 255 && t < bad) bad = t;
   }
 #pragma unroll
@@ -56,56 +73,54 @@ __device__ __forceinline__ void count_one(const uint8_t *__restrict__ res, uint3
     if (lane == 0) atomicMin(err, pack_err(i, kErrBadResidue, bad));
     return;
   }
+  for (uint32_t x = lane; x < (uint32_t)kBitmapWords; x += 64) sh.bm[x] = 0;
+  for (uint32_t x = lane; x < (K + 1) / 2; x += 64) sh.cnt[x] = 0;
+  if (lane == 0) sh.nrep = 0;
   __syncthreads();
-  uint32_t P = 64;
-  while (P < K) P <<= 1;
-  for (uint32_t t = lane; t < P; t += 64) {
-    uint32_t v = 0xFFFFu;
-    if (t < K)
-      v = codes[t] * 7776u + codes[t + 1] * 1296u + codes[t + 2] * 216u + codes[t + 3] * 36u +
-          codes[t + 4] * 6u + codes[t + 5];
-    w[t] = (uint16_t)v;
+  for (uint32_t t = lane; t < K; t += 64) {
+    const uint8_t *c = sh.codes + t;
+    const uint32_t w = c[0] * 7776u + c[1] * 1296u + c[2] * 216u + c[3] * 36u + c[4] * 6u + c[5];
+    const uint32_t bit = 1u << (w & 31u);
+    if (atomicOr(&sh.bm[w >> 5], bit) & bit) sh.rep[atomicAdd(&sh.nrep, 1u)] = (uint16_t)w;
   }
   __syncthreads();
-  // bitonic sort of w[0, P) (padding 0xFFFF sorts last)
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t x = lane; x < (P >> 1); x += 64) {
-        const uint32_t a = ((x & ~(j - 1)) << 1) | (x & (j - 1));
-        const uint32_t b = a | j;
-        const uint16_t va = w[a], vb = w[b];
-        const bool up = (a & k) == 0;
-        if ((va > vb) == up) {
-          w[a] = vb;
-          w[b] = va;
-        }
-      }
-      __syncthreads();
-    }
+  const uint32_t x0 = lane * kChunk, x1 = min(x0 + kChunk, (uint32_t)kBitmapWords);
+  uint32_t local = 0;
+  for (uint32_t x = x0; x < x1; x++) local += __popc(sh.bm[x]);
+  uint32_t incl = local;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= (uint32_t)o) incl += y;
   }
-  // run-length encode: run starts ("heads") in order
-  uint32_t D = 0;
-  for (uint32_t base = 0; base < K; base += 64) {
-    const uint32_t p = base + lane;
-    const bool valid = p < K;
-    const uint16_t v = valid ? w[p] : 0;
-    const bool head = valid && (p == 0 || w[p - 1] != v);
-    const unsigned long long m = __ballot(head);
-    if (head) hp[D + (uint32_t)__popcll(m & lanemask_lt())] = (uint16_t)p;
-    D += (uint32_t)__popcll(m);
-  }
-  __syncthreads();
+  const uint32_t D = __shfl(incl, 63, 64);
+  uint32_t rank = incl - local;
+  sh.cpre[lane] = rank;
   const uint64_t co = o0 - 5ull * i;
   const bool ok = (o0 >= 5ull * i) && (co + K <= cap);
+  for (uint32_t x = x0; x < x1; x++) {
+    uint32_t m = sh.bm[x];
+    while (m) {
+      const uint32_t b = __ffs(m) - 1u;
+      m &= m - 1u;
+      if (ok) cap_ids[co + rank] = (uint16_t)(32u * x + b);
+      rank++;
+    }
+  }
+  __syncthreads();
+  const uint32_t nrep = sh.nrep;
+  for (uint32_t q = lane; q < nrep; q += 64) {
+    const uint32_t w = sh.rep[q], x = w >> 5, c = x / kChunk;
+    uint32_t r = sh.cpre[c];
+    for (uint32_t y = c * kChunk; y < x; y++) r += __popc(sh.bm[y]);
+    r += __popc(sh.bm[x] & ((1u << (w & 31u)) - 1u));
+    atomicAdd(&sh.cnt[r >> 1], 1u << ((r & 1u) << 4));
+  }
+  __syncthreads();
   uint32_t nh = 0;
   for (uint32_t r = lane; r < D; r += 64) {
-    const uint32_t h0 = hp[r];
-    const uint32_t h1 = (r + 1 < D) ? hp[r + 1] : K;
-    const uint32_t c = h1 - h0;
-    if (ok) {
-      cap_ids[co + r] = w[h0];
-      cap_cnt[co + r] = (uint16_t)c;
-    }
+    const uint32_t c = 1u + ((sh.cnt[r >> 1] >> ((r & 1u) << 4)) & 0xFFFFu);
+    if (ok) cap_cnt[co + r] = (uint16_t)c;
     nh += (c >= 2);
   }
 #pragma unroll
@@ -118,8 +133,8 @@ __device__ __forceinline__ void count_one(const uint8_t *__restrict__ res, uint3
 }
 
 // First pass, one workgroup per sequence: validates every sequence, counts
-// those of at most 1024 words (LDS sized for them, so ~29 fit per CU), and
-// queues longer ones for the 4096-word kernel or the dense-histogram one.
+// those of at most 1024 words (LDS sized for them), and queues longer ones
+// for the 4096-word kernel or the dense-histogram one.
 __global__ __launch_bounds__(64) void count_short_kernel(
     const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint32_t N, uint64_t nres,
     uint64_t cap, uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt,
@@ -127,13 +142,10 @@ __global__ __launch_bounds__(64) void count_short_kernel(
     uint32_t *__restrict__ mid_list, uint32_t *__restrict__ nmid, uint32_t *__restrict__ long_list,
     uint32_t *__restrict__ nlong, unsigned long long *err) {
   constexpr int CAP = 1024;
-  __shared__ uint8_t lut[256];
-  __shared__ uint8_t codes[CAP + 8];
-  __shared__ uint16_t w[CAP];
-  __shared__ uint16_t hp[CAP + 1];
+  __shared__ CountShared<CAP> sh;
   const uint32_t i = blockIdx.x;
   const uint32_t lane = threadIdx.x;
-  for (uint32_t c = lane; c < 256; c += 64) lut[c] = dayhoff6(c);
+  for (uint32_t c = lane; c < 256; c += 64) sh.lut[c] = dayhoff6(c);
   uint64_t o0, o1;
   const uint32_t code = check_offsets(off, i, N, nres, o0, o1);
   if (code != kErrNone) {
@@ -150,7 +162,7 @@ __global__ __launch_bounds__(64) void count_short_kernel(
     return;
   }
   __syncthreads();
-  count_one<CAP>(res, i, o0, n, cap, lut, codes, w, hp, cap_ids, cap_cnt, Dout, Kout, nhiout, err);
+  count_one<CAP>(res, i, o0, n, cap, sh, cap_ids, cap_cnt, Dout, Kout, nhiout, err);
 }
 
 // Sequences of 1025..4096 words, queued by the first pass.
@@ -161,19 +173,16 @@ __global__ __launch_bounds__(64) void count_mid_kernel(
     const uint32_t *__restrict__ mid_list, const uint32_t *__restrict__ nmid,
     unsigned long long *err) {
   constexpr int CAP = kShortMax;
-  __shared__ uint8_t lut[256];
-  __shared__ uint8_t codes[CAP + 8];
-  __shared__ uint16_t w[CAP];
-  __shared__ uint16_t hp[CAP + 1];
+  __shared__ CountShared<CAP> sh;
   const uint32_t lane = threadIdx.x;
-  for (uint32_t c = lane; c < 256; c += 64) lut[c] = dayhoff6(c);
+  for (uint32_t c = lane; c < 256; c += 64) sh.lut[c] = dayhoff6(c);
   __syncthreads();
   const uint32_t nm = *nmid;
   for (uint32_t q = blockIdx.x; q < nm; q += gridDim.x) {
     const uint32_t i = mid_list[q];
     const uint64_t o0 = off[i], o1 = off[i + 1];
-    count_one<CAP>(res, i, o0, (uint32_t)(o1 - o0), cap, lut, codes, w, hp, cap_ids, cap_cnt, Dout,
-                   Kout, nhiout, err);
+    count_one<CAP>(res, i, o0, (uint32_t)(o1 - o0), cap, sh, cap_ids, cap_cnt, Dout, Kout, nhiout,
+                   err);
     __syncthreads();
   }
 }

@@ -15,9 +15,19 @@
 //     positions (i-1)B + floor(B/2) - 1, i = 1..B-1, become the pivots;
 //  5. bucket = number of pivots with smaller rho; bucket b starts at
 //     rho(pivot_{b-1}) + 1 in the key order.
+//
+// Sets of at most kCountRankMax keys take a fully parallel route instead:
+// rho_i = #{j : (R_j, j) < (R_i, i)} is counted directly by a 2-D grid over
+// all (i, j) tiles (n^2 comparisons spread over the whole GPU), the local
+// rank of i inside its virtual block is the number of block members with
+// smaller rho, and samples / pivots / buckets follow from rho exactly as
+// above.
 #include "radix.h"
 
 namespace kd {
+
+constexpr uint32_t kCountRankMax = 32768;
+constexpr uint32_t kRhoChunk = 2048;  // j values per workgroup of the counting grid
 
 __device__ __forceinline__ unsigned long long rank_key(double r) {
   if (r == 0.0) r = 0.0;  // -0 and +0 are the same rank
@@ -130,11 +140,151 @@ __global__ __launch_bounds__(1024) void partition_kernel(const double *R, uint32
   partition_one(R, n, B, bucket, order, offsets, piv_r, piv_i, carve(scratch, n, B), sh, prho);
 }
 
+// rho[i] += #{j in this workgroup's chunk : key_j < key_i, or key_j == key_i
+// and j < i}.  A wave whose 64 indices lie wholly above (below) the chunk
+// counts key_j <= key_i (key_j < key_i) with one compare per j.
+__global__ __launch_bounds__(256) void rho_count_kernel(const double *__restrict__ R, uint32_t n,
+                                                        uint32_t *__restrict__ rho) {
+  __shared__ unsigned long long sk[kRhoChunk];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t j0 = blockIdx.y * kRhoChunk, j1 = min(j0 + kRhoChunk, n);
+  for (uint32_t j = j0 + tid; j < j1; j += 256) sk[j - j0] = rank_key(R[j]);
+  __syncthreads();
+  const uint32_t i = blockIdx.x * 256u + tid;
+  const uint32_t iw0 = __builtin_amdgcn_readfirstlane(blockIdx.x * 256u + (tid & ~63u));
+  const unsigned long long ki = i < n ? rank_key(R[i]) : ~0ull;
+  const uint32_t m = j1 - j0;
+  uint32_t c = 0;
+  if (j1 <= iw0) {  // every j below every i of the wave
+    for (uint32_t q = 0; q < m; q++) c += sk[q] <= ki;
+  } else if (j0 >= iw0 + 64u) {  // every j above
+    for (uint32_t q = 0; q < m; q++) c += sk[q] < ki;
+  } else {
+    for (uint32_t q = 0; q < m; q++) {
+      const unsigned long long kj = sk[q];
+      c += (kj < ki) | ((kj == ki) & (j0 + q < i));
+    }
+  }
+  if (i < n && c) atomicAdd(&rho[i], c);
+}
+
+// order[rho_i] = i; local rank of i in its virtual block = number of block
+// members with smaller rho; loc[lo_b + local rank] = i (the block in key
+// order, i.e. the paper's locally sorted processor list).
+__global__ __launch_bounds__(256) void local_rank_kernel(uint32_t n, uint32_t B,
+                                                         const uint32_t *__restrict__ rho,
+                                                         uint32_t *__restrict__ order,
+                                                         uint32_t *__restrict__ loc) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t r = rho[i];
+  order[r] = i;
+  if (B == 1) return;
+  const uint32_t b = (uint32_t)(((unsigned long long)(i + 1) * B - 1) / n);
+  const uint32_t lo = (uint32_t)((unsigned long long)b * n / B);
+  const uint32_t hi = (uint32_t)((unsigned long long)(b + 1) * n / B);
+  uint32_t lr = 0;
+  for (uint32_t j = lo; j < hi; j++) lr += rho[j] < r;
+  loc[lo + lr] = i;
+}
+
+// Samples, their order, and the pivots / offsets (one workgroup).  The
+// B(B-1) sample positions are sorted by rho with a bitonic network in LDS.
+constexpr uint32_t kBitonicSamples = 8192;
+
+__global__ __launch_bounds__(1024) void pivots_kernel(const double *__restrict__ R, uint32_t n,
+                                                      uint32_t B, const uint32_t *__restrict__ rho,
+                                                      const uint32_t *__restrict__ order,
+                                                      const uint32_t *__restrict__ loc,
+                                                      uint32_t *__restrict__ prho_out,
+                                                      uint32_t *__restrict__ offsets,
+                                                      double *__restrict__ piv_r,
+                                                      uint32_t *__restrict__ piv_i) {
+  __shared__ uint32_t smp[kBitonicSamples];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t S = B * (B - 1);
+  uint32_t P = 1;
+  while (P < S) P <<= 1;
+  for (uint32_t q = tid; q < P; q += 1024) {
+    uint32_t v = 0xFFFFFFFFu;
+    if (q < S) {
+      const uint32_t b = q / (B - 1), t = q % (B - 1) + 1;
+      const uint32_t lo = (uint32_t)((unsigned long long)b * n / B);
+      const uint32_t w = (uint32_t)((unsigned long long)(b + 1) * n / B) - lo;
+      v = rho[loc[lo + (uint32_t)((unsigned long long)t * w / B)]];
+    }
+    smp[q] = v;
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t x = tid; x < (P >> 1); x += 1024) {
+        const uint32_t a = ((x & ~(j - 1)) << 1) | (x & (j - 1));
+        const uint32_t b = a | j;
+        const uint32_t va = smp[a], vb = smp[b];
+        if ((va > vb) == ((a & k) == 0)) {
+          smp[a] = vb;
+          smp[b] = va;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = tid; i + 1 < B; i += 1024) {
+    const uint32_t r = smp[i * B + B / 2 - 1];
+    prho_out[i] = r;
+    offsets[i + 1] = r + 1;
+    const uint32_t idx = order[r];
+    if (piv_i) piv_i[i] = idx;
+    if (piv_r) piv_r[i] = R[idx];
+  }
+  if (tid == 0) {
+    offsets[0] = 0;
+    offsets[B] = n;
+  }
+}
+
+__global__ __launch_bounds__(256) void bucket_kernel(uint32_t n, uint32_t B,
+                                                     const uint32_t *__restrict__ rho,
+                                                     const uint32_t *__restrict__ prho,
+                                                     uint32_t *__restrict__ bucket) {
+  __shared__ uint32_t sp[kMaxBuckets];
+  for (uint32_t q = threadIdx.x; q + 1 < B; q += 256) sp[q] = prho[q];
+  __syncthreads();
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t r = rho[i];
+  uint32_t lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (sp[mid] < r) lo = mid + 1;
+    else hi = mid;
+  }
+  bucket[i] = lo;
+}
+
 hipError_t launch_partition(hipStream_t st, const double *ranks, uint32_t n, uint32_t B,
                             uint32_t *bucket, uint32_t *order, uint32_t *offsets,
                             double *pivot_rank, uint32_t *pivot_idx, void *scratch) {
-  hipLaunchKernelGGL(partition_kernel, dim3(1), dim3(1024), 0, st, ranks, n, B, bucket, order,
-                     offsets, pivot_rank, pivot_idx, scratch);
+  const uint64_t S = (uint64_t)B * (B - 1);
+  if (n > kCountRankMax || S > kBitonicSamples) {
+    hipLaunchKernelGGL(partition_kernel, dim3(1), dim3(1024), 0, st, ranks, n, B, bucket, order,
+                       offsets, pivot_rank, pivot_idx, scratch);
+    return hipGetLastError();
+  }
+  uint32_t *rho = reinterpret_cast<uint32_t *>(scratch);
+  uint32_t *loc = rho + align256(4ull * n) / 4;
+  uint32_t *prho = loc + align256(4ull * n) / 4;
+  KD_HIP(launch_fill_u64(st, rho, (n + 1) / 2, 0));
+  const uint32_t gi = (n + 255) / 256, gj = (n + kRhoChunk - 1) / kRhoChunk;
+  hipLaunchKernelGGL(rho_count_kernel, dim3(gi, gj), dim3(256), 0, st, ranks, n, rho);
+  KD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(local_rank_kernel, dim3(gi), dim3(256), 0, st, n, B, rho, order, loc);
+  KD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(pivots_kernel, dim3(1), dim3(1024), 0, st, ranks, n, B, rho, order, loc, prho,
+                     offsets, pivot_rank, pivot_idx);
+  KD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(bucket_kernel, dim3(gi), dim3(256), 0, st, n, B, rho, prho, bucket);
   return hipGetLastError();
 }
 
