@@ -74,12 +74,95 @@ def cpu_baseline(ss, delta, budget_s):
     }
 
 
+def bench_batched(args):
+    """Many independent sets in one call (kd_batch_run) against the plain
+    per-set loop (kmer_count -> kmer_rank -> sample_partition, synchronizing
+    after every set) on the same device, with identical outputs required."""
+    import numpy as np
+    import synth
+    t0 = time.perf_counter()
+    sets = synth.batched(4, args.sets, workers=min(16, os.cpu_count() or 1))
+    res_h, off_h, first, Bs = synth.concat(sets)
+    print(f"[bench] batched workload: {len(sets)} sets, {int(first[-1])} sequences, "
+          f"generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    import torch
+    import paper_0905_1744_amd as kd
+    dev = torch.device("cuda", 0)
+    res = torch.from_numpy(res_h).to(dev)
+    off = torch.from_numpy(off_h.view(np.int64)).to(dev)
+    ctx = kd.Context(0)
+    Ntot = int(first[-1])
+    nb = int(Bs.astype(np.int64).sum()) + len(sets)
+    out = dict(ranks=torch.empty(Ntot, dtype=torch.float64, device=dev),
+               bucket=torch.empty(Ntot, dtype=torch.int32, device=dev),
+               order=torch.empty(Ntot, dtype=torch.int32, device=dev),
+               offsets=torch.empty(nb, dtype=torch.int32, device=dev))
+    ns = np.diff(first.astype(np.int64))
+    pairs = float((ns * (ns - 1) // 2).sum())
+    for _ in range(args.warmup):
+        ctx.batch_run(res, off, first, Bs, args.delta, out=out)
+    torch.cuda.synchronize()
+    ctx.enable_timing(True)
+    ctx.reset_timing()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.batch_run(res, off, first, Bs, args.delta, out=out)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    stages = ctx.stage_times()
+    ctx.enable_timing(False)
+    print(f"[bench] batched: {t_batch * 1e3:.2f} ms per batch", file=sys.stderr, flush=True)
+    # per-set inputs prepared before timing (residue views, rebased offsets)
+    per = []
+    for q in range(len(sets)):
+        a, b = int(first[q]), int(first[q + 1])
+        o0, o1 = int(off_h[a]), int(off_h[b])
+        per.append((res[o0:o1], (off[a:b + 1] - o0).contiguous(), b - a, int(Bs[q])))
+    R1 = torch.empty(Ntot, dtype=torch.float64, device=dev)
+    loop_out = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, (r, o, n, B) in enumerate(per):
+        ks = ctx.kmer_count(r, o)
+        Rq = ctx.kmer_rank(ks, args.delta, out=R1[int(first[q]):int(first[q]) + n])
+        loop_out.append(ctx.sample_partition(Rq, B))
+        ks.destroy()
+        torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    print(f"[bench] per-set loop: {t_loop * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    same = bool(torch.equal(R1, out["ranks"]))
+    ob = np.concatenate([[0], np.cumsum(Bs.astype(np.int64) + 1)])
+    bb, oo, ff = out["bucket"].cpu(), out["order"].cpu(), out["offsets"].cpu()
+    for q, p in enumerate(loop_out):
+        a, b = int(first[q]), int(first[q + 1])
+        same = same and torch.equal(p["bucket"].cpu(), bb[a:b]) and torch.equal(p["order"].cpu(), oo[a:b]) \
+            and torch.equal(p["offsets"].cpu(), ff[int(ob[q]):int(ob[q + 1])])
+    line = {
+        "metric": "batched k-mer rank + split: pair-similarities/s and sets/s", "value": pairs / t_batch,
+        "unit": "pair-similarities/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u16/f64", "data": "synthetic",
+        "config": {"workload": (f"batched: {len(sets)} sets, N log-uniform [32, 2048], 4-32 families, "
+                                "lognormal length mean 300, divergence 5-30%, B = min(8, N/32), seed 4"),
+                   "sets": len(sets), "sequences": Ntot, "pairs": pairs, "delta": args.delta,
+                   "step": "kd_batch_run (count + rank + split of every set)"},
+        "sets_per_s": len(sets) / t_batch,
+        "per_set_loop": {"ms": t_loop * 1e3, "sets_per_s": len(sets) / t_loop, "pairs_per_s": pairs / t_loop},
+        "speedup_vs_per_set_loop": t_loop / t_batch,
+        "identical_outputs": same,
+        "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS) + ["batched"])
+    ap.add_argument("--sets", type=int, default=4096, help="batched workload: number of sets")
     ap.add_argument("--delta", type=float, default=0.1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -101,6 +184,10 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched":
+        bench_batched(args)
+        return
 
     import numpy as np
     import torch

@@ -167,10 +167,52 @@ kd_status kmer_rank(kd_ctx *ctx, const kd_set *set, double delta, double *ranks)
  *               bucket in key order (equivalently: all keys in order)
  *   offsets     device u32[B+1]: bucket b is order[offsets[b] .. offsets[b+1])
  *   pivot_rank  device f64[B-1] or NULL; pivot_idx device u32[B-1] or NULL
- * Errors: KD_EINVAL for n == 0, B == 0 or B > n. */
+ * Errors: KD_EINVAL for n == 0, B == 0, B > n or B > 1024. */
 kd_status sample_partition(kd_ctx *ctx, const double *ranks, uint32_t n, uint32_t B,
                            uint32_t *bucket, uint32_t *order, uint32_t *offsets,
                            double *pivot_rank, uint32_t *pivot_idx);
+
+/* ---------------------------------------------------------------- batches */
+
+/* Many independent sequence sets handled together: every kernel of the
+ * count, rank and split runs once over all of them, and each set's result
+ * is bit-for-bit what the single-set calls above give for that set alone
+ * (the rank accumulation is exact and every set keeps its own tiling).
+ *
+ * Set s is the sequences set_first[s] .. set_first[s+1]-1 of one input
+ * (residues / offsets laid out as for kmer_count, over all sets).
+ * set_first is HOST u32[nsets+1] with set_first[0] = 0 and non-decreasing
+ * entries; set_B is HOST u32[nsets] (each 1 <= B <= set size, <= 1024). */
+
+/* Count every set; the returned kd_set holds all of them.  kmer_rank on it
+ * writes each set's ranks (normalized by that set's size) at the sequences'
+ * batch-wide indices; kd_set_export_* cover all sequences; kmer_similarity
+ * rejects a set holding more than one set (KD_EINVAL).  Errors as
+ * kmer_count, plus KD_EINVAL for a malformed set_first. */
+kd_status kmer_count_batch(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                           uint64_t n_residues, uint32_t nsets, const uint32_t *set_first,
+                           kd_set **out);
+uint32_t kd_set_count(const kd_set *set); /* number of sets it holds */
+
+/* sample_partition of every set, one workgroup per set.
+ *   ranks, bucket, order  device f64/u32/u32[set_first[nsets]]; set s uses
+ *                         entries set_first[s] .. and its bucket / order
+ *                         values are local to the set (0 .. n_s - 1)
+ *   offsets               device u32[sum_s (B_s + 1)], set after set
+ *   pivot_rank/pivot_idx  device [sum_s (B_s - 1)] or NULL, set after set
+ * Errors: KD_EINVAL for a malformed set_first or an invalid B_s. */
+kd_status sample_partition_batch(kd_ctx *ctx, const double *ranks, uint32_t nsets,
+                                 const uint32_t *set_first, const uint32_t *set_B,
+                                 uint32_t *bucket, uint32_t *order, uint32_t *offsets,
+                                 double *pivot_rank, uint32_t *pivot_idx);
+
+/* kmer_count_batch + kmer_rank + sample_partition_batch in one call (the
+ * counted layout is released on return, in stream order).  Outputs as
+ * described for sample_partition_batch; ranks is device f64[set_first[nsets]]. */
+kd_status kd_batch_run(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                       uint64_t n_residues, uint32_t nsets, const uint32_t *set_first,
+                       const uint32_t *set_B, double delta, double *ranks, uint32_t *bucket,
+                       uint32_t *order, uint32_t *offsets_out);
 
 #ifdef __cplusplus
 }

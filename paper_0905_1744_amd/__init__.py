@@ -71,6 +71,10 @@ def lib():
         "kmer_similarity": (i32, [P, P, u32, u32, u32, u32, P, P]),
         "kmer_rank": (i32, [P, P, C.c_double, P]),
         "sample_partition": (i32, [P, P, u32, u32, P, P, P, P, P]),
+        "kmer_count_batch": (i32, [P, P, P, u64, u32, P, PP]),
+        "kd_set_count": (u32, [P]),
+        "sample_partition_batch": (i32, [P, P, u32, P, P, P, P, P, P, P]),
+        "kd_batch_run": (i32, [P, P, P, u64, u32, P, P, C.c_double, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -103,6 +107,10 @@ class KmerSet:
     @property
     def n(self) -> int:
         return int(lib().kd_set_size(self.handle))
+
+    @property
+    def nsets(self) -> int:
+        return int(lib().kd_set_count(self.handle))
 
     @property
     def entries(self) -> int:
@@ -227,6 +235,78 @@ class Context:
                                            _ptr(offsets), _ptr(pr), _ptr(pi)), "sample_partition")
         return dict(bucket=bucket[:n], order=order[:n], offsets=offsets, pivot_rank=pr[:max(B - 1, 0)],
                     pivot_idx=pi[:max(B - 1, 0)])
+
+    # ------------------------------------------------------------ batches
+    @staticmethod
+    def _set_first(set_first, off):
+        # the library cannot see device array sizes: the bounds must match here
+        sf = np.ascontiguousarray(np.asarray(set_first, dtype=np.uint32))
+        if sf.ndim != 1 or sf.size < 2 or int(sf[-1]) != off.numel() - 1:
+            raise ValueError("set_first must have nsets+1 entries ending at the number of sequences")
+        return sf
+
+    @staticmethod
+    def _host_u32(x, n, what):
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.uint32))
+        if a.ndim != 1 or a.size != n:
+            raise ValueError(f"{what}: expected {n} entries, got {a.size}")
+        return a
+
+    def kmer_count_batch(self, residues, offsets, set_first) -> KmerSet:
+        """Count many sets at once; set s = sequences set_first[s] .. set_first[s+1]-1."""
+        res = _dev_tensor(residues, torch.uint8, self.device)
+        off = _dev_tensor(offsets, torch.int64, self.device)
+        sf = self._set_first(set_first, off)
+        out = C.c_void_p()
+        self._check(lib().kmer_count_batch(self.handle, _ptr(res), _ptr(off), res.numel(), sf.size - 1,
+                                           sf.ctypes.data_as(C.c_void_p), C.byref(out)),
+                    "kmer_count_batch")
+        return KmerSet(self, out)
+
+    def sample_partition_batch(self, ranks, set_first, set_B, pivots: bool = True):
+        R = _dev_tensor(ranks, torch.float64, self.device)
+        sf = np.ascontiguousarray(np.asarray(set_first, dtype=np.uint32))
+        if sf.ndim != 1 or sf.size < 2 or int(sf[-1]) != R.numel():
+            raise ValueError("set_first must have nsets+1 entries ending at the number of ranks")
+        nsets = sf.size - 1
+        Bs = self._host_u32(set_B, nsets, "set_B")
+        n = R.numel()
+        nb, npv = int(Bs.astype(np.int64).sum()) + nsets, int(Bs.astype(np.int64).sum()) - nsets
+        bucket = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        order = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        offsets = torch.empty(max(nb, 1), dtype=torch.int32, device=self.device)
+        pr = torch.empty(max(npv, 1), dtype=torch.float64, device=self.device) if pivots else None
+        pi = torch.empty(max(npv, 1), dtype=torch.int32, device=self.device) if pivots else None
+        self._check(lib().sample_partition_batch(self.handle, _ptr(R), nsets, sf.ctypes.data_as(C.c_void_p),
+                                                 Bs.ctypes.data_as(C.c_void_p), _ptr(bucket), _ptr(order),
+                                                 _ptr(offsets), _ptr(pr), _ptr(pi)), "sample_partition_batch")
+        out = dict(bucket=bucket[:n], order=order[:n], offsets=offsets[:nb])
+        if pivots:
+            out.update(pivot_rank=pr[:npv], pivot_idx=pi[:npv])
+        return out
+
+    def batch_run(self, residues, offsets, set_first, set_B, delta: float = 0.1, out=None):
+        """Count, rank and split every set of a batch in one call.
+
+        Returns dict(ranks f64[N], bucket, order (set-local), offsets
+        (B_s + 1 per set, set after set)); `out` may supply those tensors."""
+        res = _dev_tensor(residues, torch.uint8, self.device)
+        off = _dev_tensor(offsets, torch.int64, self.device)
+        sf = self._set_first(set_first, off)
+        nsets = sf.size - 1
+        Bs = self._host_u32(set_B, nsets, "set_B")
+        n = off.numel() - 1
+        nb = int(Bs.astype(np.int64).sum()) + nsets
+        if out is None:
+            out = dict(ranks=torch.empty(max(n, 1), dtype=torch.float64, device=self.device),
+                       bucket=torch.empty(max(n, 1), dtype=torch.int32, device=self.device),
+                       order=torch.empty(max(n, 1), dtype=torch.int32, device=self.device),
+                       offsets=torch.empty(max(nb, 1), dtype=torch.int32, device=self.device))
+        self._check(lib().kd_batch_run(self.handle, _ptr(res), _ptr(off), res.numel(), nsets,
+                                       sf.ctypes.data_as(C.c_void_p), Bs.ctypes.data_as(C.c_void_p),
+                                       float(delta), _ptr(out["ranks"]), _ptr(out["bucket"]),
+                                       _ptr(out["order"]), _ptr(out["offsets"])), "kd_batch_run")
+        return out
 
 
 _default = None

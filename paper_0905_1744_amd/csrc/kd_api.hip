@@ -168,6 +168,39 @@ struct StageTimer {
   }
 };
 
+// Copies host data to device memory on the context's stream through a
+// pinned staging buffer, so the caller's host memory may change as soon as
+// this returns.
+hipError_t upload(kd_ctx *ctx, void *dst, const void *src, size_t bytes) {
+  if (bytes == 0) return hipSuccess;
+  kd_ctx::Staged *slot = nullptr;
+  for (auto &b : ctx->staging) {
+    if (b.cap < bytes) continue;
+    if (b.used) {
+      const hipError_t q = hipEventQuery(b.ev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return q;
+    }
+    slot = &b;
+    break;
+  }
+  if (!slot) {
+    kd_ctx::Staged b{nullptr, std::max<size_t>(bytes, 64u << 10), nullptr, false};
+    KD_HIP(hipHostMalloc(&b.p, b.cap, hipHostMallocDefault));
+    if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipHostFree(b.p);
+      return hipErrorOutOfMemory;
+    }
+    ctx->staging.push_back(b);
+    slot = &ctx->staging.back();
+  }
+  std::memcpy(slot->p, src, bytes);
+  KD_HIP(hipMemcpyAsync(dst, slot->p, bytes, hipMemcpyHostToDevice, ctx->stream));
+  KD_HIP(hipEventRecord(slot->ev, ctx->stream));
+  slot->used = true;
+  return hipSuccess;
+}
+
 void drain_timing(kd_ctx *ctx) {
   for (auto &p : ctx->pending) {
     float ms = 0.f;
@@ -240,6 +273,10 @@ extern "C" void kd_ctx_destroy(kd_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   drain_timing(ctx);
   for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
+  for (auto &b : ctx->staging) {
+    (void)hipEventDestroy(b.ev);
+    (void)hipHostFree(b.p);
+  }
   delete ctx->pool;  // frees task lists and anything still live
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
@@ -277,24 +314,75 @@ extern "C" void *kd_ctx_stream(kd_ctx *ctx) { return ctx ? (void *)ctx->stream :
 
 // ------------------------------------------------------------ kmer_count
 
-extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
-                                uint32_t n_seqs, uint64_t n_residues, kd_set **out) {
-  if (!ctx || !out) return KD_EINVAL;
+namespace {
+
+// Work list of the rank kernel for one set of N sequences: strips of 32
+// column groups (two per wave of a workgroup) against runs of row blocks; a
+// row block rb only meets column groups g <= rb/4 (pairs below the
+// diagonal of the sorted order).  Strips with the longest lists first.
+void make_tasks(uint32_t N, uint32_t set_index, std::vector<PairTask> &out) {
+  std::vector<PairTask> t;
+  const uint32_t RB = (N + 15) / 16, G = (N + 63) / 64;
+  for (uint32_t g0 = 0; g0 < G; g0 += kGroupsPerTask) {
+    for (uint32_t rb0 = 4u * g0; rb0 < RB; rb0 += kRowBlocksPerTask)
+      t.push_back({set_index, rb0, std::min(rb0 + kRowBlocksPerTask, RB), g0});
+  }
+  std::stable_sort(t.begin(), t.end(), [](const PairTask &a, const PairTask &b) {
+    if (a.g0 != b.g0) return a.g0 > b.g0;
+    return a.rb1 - a.rb0 > b.rb1 - b.rb0;
+  });
+  out.insert(out.end(), t.begin(), t.end());
+}
+
+// number of 16 x 64 tiles of a task (its share of the triangle)
+uint64_t task_tiles(const PairTask &t, uint32_t G) {
+  uint64_t n = 0;
+  const uint32_t g1 = std::min(t.g0 + kGroupsPerTask, G);
+  for (uint32_t rb = t.rb0; rb < t.rb1; rb++) {
+    const uint32_t gmax = rb / 4;  // groups g <= rb/4 are active
+    if (gmax >= t.g0) n += std::min(gmax + 1, g1) - t.g0;
+  }
+  return n;
+}
+
+// Counts every set of a batch (set s = sequences first[s] .. first[s+1]-1
+// of the input) and lays all of them out in one pass of each kernel.
+kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                     uint32_t nsets, const uint32_t *first, uint64_t n_residues, kd_set **out) {
   *out = nullptr;
-  if (n_seqs > 0 && (!offsets || (!residues && n_residues > 0))) return KD_EINVAL;
+  const uint32_t N = first[nsets];
+  if (N > 0 && (!offsets || (!residues && n_residues > 0))) return KD_EINVAL;
   KD_TRY(hipSetDevice(ctx->device));
   kd_set *s = new (std::nothrow) kd_set;
   if (!s) return KD_ENOMEM;
   s->ctx = ctx;
-  const uint32_t N = n_seqs;
+  s->nsets = nsets;
+  s->seq_first.assign(first, first + nsets + 1);
+  s->grp_first.assign(nsets + 1, 0);
+  s->rb_first.assign(nsets + 1, 0);
+  for (uint32_t q = 0; q < nsets; q++) {
+    const uint32_t n = first[q + 1] - first[q];
+    s->grp_first[q + 1] = s->grp_first[q] + (n + 63) / 64;
+    s->rb_first[q + 1] = s->rb_first[q] + (n + 15) / 16;
+  }
   s->v.N = N;
-  s->v.G = (N + 63) / 64;
-  s->v.RB = (N + 15) / 16;
+  s->v.G = s->grp_first[nsets];
+  s->v.RB = s->rb_first[nsets];
+  s->v.base = 0;
+  s->views.assign(nsets, SetView{});
+  for (uint32_t q = 0; q < nsets; q++) {
+    const uint32_t n = first[q + 1] - first[q];
+    s->views[q].N = n;
+    s->views[q].G = (n + 63) / 64;
+    s->views[q].RB = (n + 15) / 16;
+    s->views[q].base = first[q];
+  }
   if (N == 0) {
     *out = s;
     return KD_OK;
   }
   const hipStream_t st = ctx->stream;
+  const uint32_t G = s->v.G, RB = s->v.RB;
   const uint64_t cap = n_residues >= 5ull * N ? n_residues - 5ull * N : 0;
   Scope tmp(ctx);
   // set-owned arrays
@@ -308,14 +396,15 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   uint32_t *D = set_alloc<uint32_t>(s, N);
   double *invK = set_alloc<double>(s, N);
   uint32_t *hi_off = set_alloc<uint32_t>(s, N + 1);
-  uint64_t *grp_off = set_alloc<uint64_t>(s, s->v.G + 1);
-  uint32_t *grp_len = set_alloc<uint32_t>(s, s->v.G);
-  uint64_t *ghi_off = set_alloc<uint64_t>(s, s->v.G + 1);
-  uint32_t *ghi_len = set_alloc<uint32_t>(s, s->v.G);
-  uint32_t *exc_off = set_alloc<uint32_t>(s, s->v.RB + 1);
-  uint32_t *exc_n = set_alloc<uint32_t>(s, s->v.RB);
+  uint64_t *grp_off = set_alloc<uint64_t>(s, G + 1);
+  uint32_t *grp_len = set_alloc<uint32_t>(s, G);
+  uint64_t *ghi_off = set_alloc<uint64_t>(s, G + 1);
+  uint32_t *ghi_len = set_alloc<uint32_t>(s, G);
+  uint32_t *exc_off = set_alloc<uint32_t>(s, RB + 1);
+  uint32_t *exc_n = set_alloc<uint32_t>(s, RB);
   long long *acc = set_alloc<long long>(s, 3ull * N);
-  SetView *d_view = set_alloc<SetView>(s, 1);
+  uint32_t *segb = set_alloc<uint32_t>(s, 3ull * (nsets + 1));
+  SetView *d_view = set_alloc<SetView>(s, nsets);
   // temporaries
   uint32_t *Korig = tmp.get<uint32_t>(N);
   uint32_t *hcount = tmp.get<uint32_t>(N);
@@ -327,15 +416,26 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   unsigned long long *small = tmp.get<unsigned long long>(8);  // [0] err, [1] nlong
   LayoutMeta *meta = tmp.get<LayoutMeta>(1);
   if (!in_off || !cap_ids || !cap_cnt || !Dorig || !perm || !inv || !K || !D || !invK || !hi_off || !hcount ||
-      !grp_off || !grp_len || !ghi_off || !ghi_len || !exc_off || !exc_n || !acc || !d_view || !Korig || !nhi_orig ||
-      !long_list || !mid_list || !sortk || !sortv || !small || !meta) {
+      !grp_off || !grp_len || !ghi_off || !ghi_len || !exc_off || !exc_n || !acc || !segb || !d_view ||
+      !Korig || !nhi_orig || !long_list || !mid_list || !sortk || !sortv || !small || !meta) {
     set_free(s);
     return KD_ENOMEM;
   }
+  std::vector<uint32_t> hb;
+  hb.insert(hb.end(), s->seq_first.begin(), s->seq_first.end());
+  hb.insert(hb.end(), s->grp_first.begin(), s->grp_first.end());
+  hb.insert(hb.end(), s->rb_first.begin(), s->rb_first.end());
+  Segs &sg = s->segs;
+  sg.nsets = nsets;
+  sg.seq = segb;
+  sg.grp = segb + (nsets + 1);
+  sg.rb = segb + 2 * (nsets + 1);
+  sg.views = d_view;
   unsigned long long *err = small;
   uint32_t *nlong = reinterpret_cast<uint32_t *>(small + 1);  // [0] long, [1] mid
   uint32_t *nmid = nlong + 1;
-  hipError_t e = launch_fill_u64(st, small, 1, ~0ull);
+  hipError_t e = upload(ctx, segb, hb.data(), sizeof(uint32_t) * hb.size());
+  if (e == hipSuccess) e = launch_fill_u64(st, small, 1, ~0ull);
   if (e == hipSuccess) e = launch_fill_u64(st, small + 1, 1, 0ull);
   if (e == hipSuccess)
     e = hipMemcpyAsync(in_off, offsets, sizeof(uint64_t) * (N + 1), hipMemcpyDeviceToDevice, st);
@@ -345,15 +445,16 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
                      nhi_orig, mid_list, nmid, long_list, nlong, err, ctx->cus);
   t_count.done();
   StageTimer t_layout(ctx, KD_STAGE_LAYOUT);
-  if (e == hipSuccess) e = launch_sort_u32_index(st, Dorig, N, 16, perm, sortk, sortv);
+  if (e == hipSuccess) e = launch_sort_u32_index(st, Dorig, sg, N, 16, perm, sortk, sortv);
   if (e == hipSuccess)
-    e = launch_layout_meta(st, N, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hcount, hi_off,
-                           grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta);
+    e = launch_layout_meta(st, sg, N, G, RB, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hcount,
+                           hi_off, grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta);
   t_layout.done();
   LayoutMeta *hm = static_cast<LayoutMeta *>(ctx->pinned);
   if (e == hipSuccess) e = hipMemcpyAsync(hm, meta, sizeof(LayoutMeta), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
     set_free(s);
     return KD_EDEVICE;
   }
@@ -399,20 +500,65 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   v.exc_ids = exc_ids;
   v.exc_cnt = exc_cnt;
   v.acc = acc;
+  for (uint32_t q = 0; q < nsets; q++) {
+    SetView &w = s->views[q];
+    const uint32_t a = first[q], ga = s->grp_first[q], ra = s->rb_first[q];
+    w.perm = perm + a;
+    w.inv = inv + a;
+    w.K = K + a;
+    w.D = D + a;
+    w.invK = invK + a;
+    w.grp_off = grp_off + ga;
+    w.grp_len = grp_len + ga;
+    w.gids = gids;
+    w.hi_off = hi_off + a;
+    w.hi_ids = hi_ids;
+    w.hi_cnt = hi_cnt;
+    w.ghi = ghi;
+    w.ghi_off = ghi_off + ga;
+    w.ghi_len = ghi_len + ga;
+    w.exc_off = exc_off + ra;
+    w.exc_n = exc_n + ra;
+    w.exc_ids = exc_ids;
+    w.exc_cnt = exc_cnt;
+    w.acc = acc + 3ull * a;
+  }
   s->cap_ids = cap_ids;
   s->cap_cnt = cap_cnt;
   s->Dorig = Dorig;
   s->in_off = in_off;
   s->d_view = d_view;
+  // rank work list of every set; with several sets the largest tasks go
+  // first (the per-set lists keep their own order otherwise)
+  s->h_tasks.clear();
+  for (uint32_t q = 0; q < nsets; q++) make_tasks(s->views[q].N, q, s->h_tasks);
+  if (nsets > 1) {
+    std::vector<std::pair<uint64_t, uint32_t>> key(s->h_tasks.size());
+    for (size_t t = 0; t < key.size(); t++)
+      key[t] = {task_tiles(s->h_tasks[t], s->views[s->h_tasks[t].set].G), (uint32_t)t};
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<uint64_t, uint32_t> &a,
+                        const std::pair<uint64_t, uint32_t> &b) { return a.first > b.first; });
+    std::vector<PairTask> sorted(key.size());
+    for (size_t t = 0; t < key.size(); t++) sorted[t] = s->h_tasks[key[t].second];
+    s->h_tasks.swap(sorted);
+  }
+  s->ntasks = (uint32_t)s->h_tasks.size();
+  s->tasks = set_alloc<PairTask>(s, s->ntasks + 1);
+  if (!s->tasks) {
+    set_free(s);
+    return KD_ENOMEM;
+  }
   StageTimer t_fill(ctx, KD_STAGE_LAYOUT);
+  e = upload(ctx, d_view, s->views.data(), sizeof(SetView) * nsets);
+  if (e == hipSuccess) e = upload(ctx, s->tasks, s->h_tasks.data(), sizeof(PairTask) * s->ntasks);
   // sentinel slack after the last group: the pair kernel reads ahead into it
-  e = launch_fill_u64(st, gids + s->n_gids, kGidsSlack / 4, 0xB640B640B640B640ull);
+  if (e == hipSuccess) e = launch_fill_u64(st, gids + s->n_gids, kGidsSlack / 4, 0xB640B640B640B640ull);
   if (e == hipSuccess) e = launch_fill_u64(st, ghi, (hm->n_ghi + 1) / 2, 0ull);
   if (e == hipSuccess)
-    e = launch_layout_fill(st, v, in_off, cap_ids, cap_cnt, gids, hi_ids, hi_cnt, ghi,
+    e = launch_layout_fill(st, sg, v, in_off, cap_ids, cap_cnt, gids, hi_ids, hi_cnt, ghi,
                            (uint32_t)hm->max_len);
-  if (e == hipSuccess) e = launch_exc_build(st, v, v.RB, nullptr, exc_off, exc_n, exc_ids, exc_cnt);
-  if (e == hipSuccess) e = launch_store_view(st, v, d_view);
+  if (e == hipSuccess) e = launch_exc_build(st, sg, RB, nullptr, exc_off, exc_n, exc_ids, exc_cnt);
   t_fill.done();
   if (e != hipSuccess) {
     set_free(s);
@@ -421,6 +567,29 @@ extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint
   *out = s;
   return KD_OK;
 }
+
+}  // namespace
+
+extern "C" kd_status kmer_count(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                                uint32_t n_seqs, uint64_t n_residues, kd_set **out) {
+  if (!ctx || !out) return KD_EINVAL;
+  *out = nullptr;
+  const uint32_t first[2] = {0u, n_seqs};
+  return build_sets(ctx, residues, offsets, 1, first, n_residues, out);
+}
+
+extern "C" kd_status kmer_count_batch(kd_ctx *ctx, const uint8_t *residues,
+                                      const uint64_t *offsets, uint64_t n_residues,
+                                      uint32_t nsets, const uint32_t *set_first, kd_set **out) {
+  if (!ctx || !out) return KD_EINVAL;
+  *out = nullptr;
+  if (nsets == 0 || !set_first || set_first[0] != 0) return KD_EINVAL;
+  for (uint32_t q = 0; q < nsets; q++)
+    if (set_first[q + 1] < set_first[q]) return KD_EINVAL;
+  return build_sets(ctx, residues, offsets, nsets, set_first, n_residues, out);
+}
+
+extern "C" uint32_t kd_set_count(const kd_set *s) { return s ? s->nsets : 0; }
 
 extern "C" uint32_t kd_set_size(const kd_set *s) { return s ? s->v.N : 0; }
 extern "C" uint64_t kd_set_entries(const kd_set *s) { return s ? s->entries : 0; }
@@ -449,7 +618,7 @@ extern "C" kd_status kd_set_export_dense(kd_ctx *ctx, const kd_set *s, uint32_t 
 
 extern "C" kd_status kmer_similarity(kd_ctx *ctx, const kd_set *s, uint32_t r0, uint32_t nr,
                                      uint32_t c0, uint32_t nc, uint16_t *shared, uint16_t *denom) {
-  if (!ctx || !s) return KD_EINVAL;
+  if (!ctx || !s || s->nsets != 1) return KD_EINVAL;
   const uint32_t N = s->v.N;
   if ((uint64_t)r0 + nr > N || (uint64_t)c0 + nc > N) return KD_EINVAL;
   if (nr == 0 || nc == 0) return KD_OK;
@@ -469,7 +638,7 @@ extern "C" kd_status kmer_similarity(kd_ctx *ctx, const kd_set *s, uint32_t r0, 
   KD_TRY(launch_map_positions(st, s->v.inv, c0, nc, colpos));
   StageTimer t(ctx, KD_STAGE_SIMILARITY);
   KD_TRY(launch_exc_offsets(st, s->v, rowpos, nr, exc_off));
-  KD_TRY(launch_exc_build(st, s->v, nb, rowpos, exc_off, exc_n, exc_ids, exc_cnt));
+  KD_TRY(launch_exc_build(st, s->segs, nb, rowpos, exc_off, exc_n, exc_ids, exc_cnt));
   KD_TRY(launch_similarity(st, s->v, rowpos, nr, colpos, nc, exc_off, exc_n, exc_ids, exc_cnt,
                            shared, denom));
   t.done();
@@ -478,68 +647,21 @@ extern "C" kd_status kmer_similarity(kd_ctx *ctx, const kd_set *s, uint32_t r0, 
 
 // ------------------------------------------------------------- kmer_rank
 
-namespace {
-
-// Work list of the rank kernel for a set of N sequences: strips of 32
-// column groups (two per wave of a workgroup) against runs of row blocks; a
-// row block rb only meets column groups g <= rb/4 (pairs below the
-// diagonal of the sorted order).  Strips with the longest lists first.
-std::vector<PairTask> make_tasks(uint32_t N, uint32_t set_index) {
-  std::vector<PairTask> t;
-  const uint32_t RB = (N + 15) / 16, G = (N + 63) / 64;
-  for (uint32_t g0 = 0; g0 < G; g0 += kGroupsPerTask) {
-    for (uint32_t rb0 = 4u * g0; rb0 < RB; rb0 += kRowBlocksPerTask)
-      t.push_back({set_index, rb0, std::min(rb0 + kRowBlocksPerTask, RB), g0});
-  }
-  std::stable_sort(t.begin(), t.end(), [](const PairTask &a, const PairTask &b) {
-    if (a.g0 != b.g0) return a.g0 > b.g0;
-    return a.rb1 - a.rb0 > b.rb1 - b.rb0;
-  });
-  return t;
-}
-
-kd_status get_tasks(kd_ctx *ctx, uint32_t N, uint32_t cg, PairTask **d, uint32_t *n) {
-  auto key = std::make_pair(N, cg);
-  auto it = ctx->task_cache.find(key);
-  if (it != ctx->task_cache.end()) {
-    *d = it->second.first;
-    *n = it->second.second;
-    return KD_OK;
-  }
-  std::vector<PairTask> t = make_tasks(N, 0);
-  PairTask *p = static_cast<PairTask *>(ctx->pool->alloc(sizeof(PairTask) * (t.size() + 1)));
-  if (!p) return KD_ENOMEM;
-  if (hipMemcpy(p, t.data(), sizeof(PairTask) * t.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    ctx->pool->free(p);
-    return KD_EDEVICE;
-  }
-  ctx->task_cache[key] = std::make_pair(p, (uint32_t)t.size());
-  *d = p;
-  *n = (uint32_t)t.size();
-  return KD_OK;
-}
-
-}  // namespace
-
 extern "C" kd_status kmer_rank(kd_ctx *ctx, const kd_set *s, double delta, double *ranks) {
   if (!ctx || !s) return KD_EINVAL;
   if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
   if (s->v.N == 0) return KD_OK;
   if (!ranks) return KD_EINVAL;
   KD_TRY(hipSetDevice(ctx->device));
-  PairTask *tasks = nullptr;
-  uint32_t ntasks = 0;
-  kd_status rc = get_tasks(ctx, s->v.N, kRowBlocksPerTask, &tasks, &ntasks);
-  if (rc != KD_OK) return rc;
   const hipStream_t st = ctx->stream;
   StageTimer t0(ctx, KD_STAGE_FINALIZE);
   KD_TRY(launch_fill_u64(st, s->v.acc, 3ull * s->v.N, 0));
   t0.done();
   StageTimer t1(ctx, KD_STAGE_PAIRS);
-  KD_TRY(launch_rank_pairs(st, s->d_view, tasks, ntasks, delta));
+  KD_TRY(launch_rank_pairs(st, s->d_view, s->tasks, s->ntasks, delta));
   t1.done();
   StageTimer t2(ctx, KD_STAGE_FINALIZE);
-  KD_TRY(launch_rank_finalize(st, s->v, delta, ranks));
+  KD_TRY(launch_rank_finalize(st, s->segs, s->v.N, delta, ranks));
   t2.done();
   return KD_OK;
 }
@@ -560,4 +682,81 @@ extern "C" kd_status sample_partition(kd_ctx *ctx, const double *ranks, uint32_t
                           scratch));
   t.done();
   return KD_OK;
+}
+
+namespace {
+
+// Per-set split descriptors of a batch: where each set's keys, outputs and
+// scratch start.
+kd_status plan_partition(uint32_t nsets, const uint32_t *first, const uint32_t *Bs,
+                         std::vector<PartDesc> &desc, uint64_t &scratch) {
+  desc.resize(nsets);
+  scratch = 0;
+  uint64_t ob = 0, pb = 0;
+  for (uint32_t q = 0; q < nsets; q++) {
+    const uint32_t n = first[q + 1] - first[q], B = Bs[q];
+    if (n == 0 || B == 0 || B > n || B > kMaxBuckets) return KD_EINVAL;
+    desc[q].scratch_off = scratch;
+    desc[q].first = first[q];
+    desc[q].n = n;
+    desc[q].B = B;
+    desc[q].off_base = (uint32_t)ob;
+    desc[q].piv_base = (uint32_t)pb;
+    scratch += (partition_scratch_bytes(n, B) + 255) & ~(uint64_t)255;
+    ob += B + 1;
+    pb += B - 1;
+  }
+  return KD_OK;
+}
+
+}  // namespace
+
+extern "C" kd_status sample_partition_batch(kd_ctx *ctx, const double *ranks, uint32_t nsets,
+                                            const uint32_t *set_first, const uint32_t *set_B,
+                                            uint32_t *bucket, uint32_t *order, uint32_t *offsets,
+                                            double *pivot_rank, uint32_t *pivot_idx) {
+  if (!ctx || !ranks || !bucket || !order || !offsets || !set_first || !set_B || nsets == 0)
+    return KD_EINVAL;
+  if (set_first[0] != 0) return KD_EINVAL;
+  for (uint32_t q = 0; q < nsets; q++)
+    if (set_first[q + 1] < set_first[q]) return KD_EINVAL;
+  std::vector<PartDesc> desc;
+  uint64_t scratch_bytes = 0;
+  kd_status rc = plan_partition(nsets, set_first, set_B, desc, scratch_bytes);
+  if (rc != KD_OK) return rc;
+  KD_TRY(hipSetDevice(ctx->device));
+  Scope tmp(ctx);
+  void *scratch = tmp.get<char>(scratch_bytes);
+  PartDesc *d_desc = tmp.get<PartDesc>(nsets);
+  if (!scratch || !d_desc) return KD_ENOMEM;
+  KD_TRY(upload(ctx, d_desc, desc.data(), sizeof(PartDesc) * nsets));
+  StageTimer t(ctx, KD_STAGE_PARTITION);
+  KD_TRY(launch_partition_batch(ctx->stream, d_desc, nsets, ranks, bucket, order, offsets,
+                                pivot_rank, pivot_idx, scratch));
+  t.done();
+  return KD_OK;
+}
+
+extern "C" kd_status kd_batch_run(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                                  uint64_t n_residues, uint32_t nsets, const uint32_t *set_first,
+                                  const uint32_t *set_B, double delta, double *ranks,
+                                  uint32_t *bucket, uint32_t *order, uint32_t *bucket_off) {
+  if (!ctx || !set_first || !set_B || nsets == 0 || !ranks || !bucket || !order || !bucket_off)
+    return KD_EINVAL;
+  if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
+  if (set_first[0] != 0) return KD_EINVAL;
+  for (uint32_t q = 0; q < nsets; q++) {
+    const uint32_t n = set_first[q + 1] - set_first[q];
+    if (set_first[q + 1] < set_first[q] || set_B[q] == 0 || set_B[q] > n || set_B[q] > kMaxBuckets)
+      return KD_EINVAL;
+  }
+  kd_set *s = nullptr;
+  kd_status rc = kmer_count_batch(ctx, residues, offsets, n_residues, nsets, set_first, &s);
+  if (rc != KD_OK) return rc;
+  rc = kmer_rank(ctx, s, delta, ranks);
+  if (rc == KD_OK)
+    rc = sample_partition_batch(ctx, ranks, nsets, set_first, set_B, bucket, order, bucket_off,
+                                nullptr, nullptr);
+  kd_set_destroy(s);  // its blocks return to the pool; stream order keeps them valid
+  return rc;
 }

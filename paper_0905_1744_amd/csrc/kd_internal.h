@@ -36,13 +36,19 @@ enum : uint32_t { kErrNone = 0, kErrInval = 1, kErrBadResidue = 2, kErrShort = 3
 // A counted set in device memory.  Sequences are re-ordered by ascending
 // number of distinct words (ties by input index); "sorted position" s refers
 // to that order, perm[s] is the input index and inv[i] its inverse.
+//
+// A counted object can hold several independent sets (a batch).  Set s owns
+// the input sequences base .. base+N-1, the same range of sorted positions,
+// and its own column groups and row blocks; all its arrays are views into
+// batch-wide arrays, and indices stored in them (perm, inv) are local to the
+// set, so every kernel sees one set exactly as if it had been counted alone.
 struct SetView {
   uint32_t N;
   uint32_t G;                  // column groups: ceil(N / 64)
   uint32_t RB;                 // row blocks: ceil(N / 16)
-  uint32_t pad;
-  const uint32_t *perm;        // [N] sorted position -> input index
-  const uint32_t *inv;         // [N] input index -> sorted position
+  uint32_t base;               // input index of the set's first sequence in the batch
+  const uint32_t *perm;        // [N] sorted position -> input index (local)
+  const uint32_t *inv;         // [N] input index -> sorted position (local)
   const uint32_t *K;           // [N] words per sequence (n - 5), sorted order
   const uint32_t *D;           // [N] distinct words, sorted order
   const double *invK;          // [N] 1 / K, sorted order
@@ -64,6 +70,16 @@ struct SetView {
   const uint16_t *exc_ids;     // [cap] sorted words
   const uint16_t *exc_cnt;     // [cap*16] count of the word in each of the 16 rows
   long long *acc;              // [3*N] exact rank accumulators (40-bit limbs)
+};
+
+// Batch-wide numbering: set s holds sequences seq[s] .. seq[s+1]-1, column
+// groups grp[s] .. grp[s+1]-1 and row blocks rb[s] .. rb[s+1]-1.
+struct Segs {
+  uint32_t nsets;
+  const uint32_t *seq;     // device [nsets+1]
+  const uint32_t *grp;     // device [nsets+1]
+  const uint32_t *rb;      // device [nsets+1]
+  const SetView *views;    // device [nsets]
 };
 
 struct PairTask {     // one workgroup's work in the rank kernel
@@ -100,9 +116,11 @@ struct kd_ctx {
   kd::Pool *pool = nullptr;
   uint64_t err_seq = 0, err_pos = 0;
   int cus = 256;
-  // cached rank task lists keyed by (N, groups per task)
-  std::map<std::pair<uint32_t, uint32_t>, std::pair<kd::PairTask *, uint32_t>> task_cache;
-  void *pinned = nullptr;         // small pinned staging area
+  void *pinned = nullptr;         // small pinned readback area
+  // pinned upload buffers: host data is staged here and copied on the
+  // context's stream; a buffer is reused once its copy's event completed
+  struct Staged { void *p; size_t cap; hipEvent_t ev; bool used; };
+  std::vector<Staged> staging;
   // stage timing (kd_ctx_enable_timing)
   bool timing = false;
   struct Pending { int stage; hipEvent_t a, b; };
@@ -114,8 +132,15 @@ struct kd_ctx {
 
 struct kd_set {
   kd_ctx *ctx = nullptr;
-  kd::SetView v{};
-  kd::SetView *d_view = nullptr;  // device copy of v
+  kd::SetView v{};        // batch-wide arrays (N, G, RB are totals); equals views[0] for one set
+  uint32_t nsets = 1;
+  std::vector<kd::SetView> views;                      // per set (host copy)
+  std::vector<uint32_t> seq_first, grp_first, rb_first;  // host copies of the segment bounds
+  kd::Segs segs{};                                     // device copies
+  kd::SetView *d_view = nullptr;  // device copy of views
+  kd::PairTask *tasks = nullptr;  // rank work list of all sets (device)
+  uint32_t ntasks = 0;
+  std::vector<kd::PairTask> h_tasks;
   uint64_t entries = 0;   // sum of D
   uint64_t cap = 0;       // sum of K
   uint64_t n_hi = 0;      // entries with count >= 2
@@ -139,9 +164,11 @@ hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off,
                         uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
                         unsigned long long *err, int cus);
 
-// stable sort of (key u32 < 2^bits, value = index) for N entries; writes perm
-hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, uint32_t N, int bits,
-                                 uint32_t *perm, uint32_t *scratch_keys, uint32_t *scratch_vals);
+// per set s: stable sort of (key u32 < 2^bits, value = local index) over the
+// set's range of keys; writes perm (local indices) over the same range
+hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, const Segs &sg, uint32_t N,
+                                 int bits, uint32_t *perm, uint32_t *scratch_keys,
+                                 uint32_t *scratch_vals);
 
 struct LayoutMeta {  // totals written by layout_meta, read by the host
   unsigned long long err;
@@ -153,7 +180,8 @@ struct LayoutMeta {  // totals written by layout_meta, read by the host
   unsigned long long n_ghi;    // grouped count>=2 entries incl. padding
 };
 
-hipError_t launch_layout_meta(hipStream_t st, uint32_t N, const uint32_t *perm,
+hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32_t G,
+                              uint32_t RB, const uint32_t *perm,
                               const uint32_t *Dorig, const uint32_t *Korig,
                               const uint32_t *nhi_orig, uint32_t *inv, uint32_t *K, uint32_t *D,
                               double *invK, uint32_t *hcount,
@@ -161,20 +189,23 @@ hipError_t launch_layout_meta(hipStream_t st, uint32_t N, const uint32_t *perm,
                               uint64_t *ghi_off, uint32_t *ghi_len,
                               uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta);
 
-hipError_t launch_layout_fill(hipStream_t st, const SetView &v, const uint64_t *offsets,
+hipError_t launch_layout_fill(hipStream_t st, const Segs &sg, const SetView &v,
+                              const uint64_t *offsets,
                               const uint16_t *cap_ids, const uint16_t *cap_cnt,
                               uint16_t *gids, uint16_t *hi_ids, uint16_t *hi_cnt, uint32_t *ghi,
                               uint32_t max_len);
 
-// merged count>=2 words of row blocks; rowpos == nullptr means block b holds
-// sorted positions 16b..16b+15
-hipError_t launch_exc_build(hipStream_t st, const SetView &v, uint32_t nblocks,
+// merged count>=2 words of row blocks.  rowpos == nullptr: every row block
+// of every set (batch-wide numbering); otherwise block b of the first set
+// holds the sorted positions rowpos[16b .. 16b+15]
+hipError_t launch_exc_build(hipStream_t st, const Segs &sg, uint32_t nblocks,
                             const uint32_t *rowpos, const uint32_t *exc_off, uint32_t *exc_n,
                             uint16_t *exc_ids, uint16_t *exc_cnt);
 
 hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairTask *tasks,
                              uint32_t ntasks, double delta);
-hipError_t launch_rank_finalize(hipStream_t st, const SetView &v, double delta, double *ranks);
+hipError_t launch_rank_finalize(hipStream_t st, const Segs &sg, uint32_t N, double delta,
+                                double *ranks);
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);
 
 hipError_t launch_similarity(hipStream_t st, const SetView &v, const uint32_t *rowpos,
@@ -189,9 +220,21 @@ hipError_t launch_exc_offsets(hipStream_t st, const SetView &v, const uint32_t *
 
 hipError_t launch_export_lists(hipStream_t st, const kd_set *s, uint16_t *ids, uint16_t *counts,
                                uint64_t *off);
-hipError_t launch_store_view(hipStream_t st, const SetView &v, SetView *dst);
 hipError_t launch_export_dense(hipStream_t st, const kd_set *s, uint32_t first, uint32_t count,
                                uint16_t *out);
+
+// one regular-sampling split per set of a batch, one workgroup each
+struct PartDesc {
+  uint64_t scratch_off;  // byte offset of the set's scratch
+  uint32_t first;        // first key (ranks, bucket and order are indexed from here)
+  uint32_t n, B;
+  uint32_t off_base;     // first entry of the set's B+1 offsets
+  uint32_t piv_base;     // first entry of the set's B-1 pivots
+};
+hipError_t launch_partition_batch(hipStream_t st, const PartDesc *desc, uint32_t nsets,
+                                  const double *ranks, uint32_t *bucket, uint32_t *order,
+                                  uint32_t *offsets, double *pivot_rank, uint32_t *pivot_idx,
+                                  void *scratch);
 
 // scratch needed by launch_partition for n keys and B buckets (bytes)
 size_t partition_scratch_bytes(uint32_t n, uint32_t B);
@@ -243,6 +286,18 @@ __device__ inline double fix_to_double(long long s0, long long s1, long long s2)
   double r = hi * 0x1p64 + lo;
   r *= 0x1p-72;
   return neg ? -r : r;
+}
+
+// the set holding batch-wide item x: the largest s with first[s] <= x
+// (first[0] = 0; empty sets share their bound with the next set)
+__device__ inline uint32_t seg_of(const uint32_t *first, uint32_t nsets, uint32_t x) {
+  uint32_t lo = 0, hi = nsets - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 __device__ inline unsigned long long lanemask_lt() {

@@ -14,12 +14,23 @@
 
 namespace kd {
 
+// One workgroup per set: stable radix sort of the set's keys with their
+// local indices as values.
 __global__ __launch_bounds__(1024) void sort_u32_index_kernel(const uint32_t *__restrict__ keys,
-                                                              uint32_t N, int bits,
+                                                              const uint32_t *__restrict__ seq,
+                                                              int bits,
                                                               uint32_t *__restrict__ perm,
                                                               uint32_t *k0, uint32_t *v0,
                                                               uint32_t *k1, uint32_t *v1) {
   __shared__ RadixShared<1024> sh;
+  const uint32_t a = seq[blockIdx.x], N = seq[blockIdx.x + 1] - a;
+  if (N == 0) return;
+  keys += a;
+  perm += a;
+  k0 += a;
+  v0 += a;
+  k1 += a;
+  v1 += a;
   for (uint32_t i = threadIdx.x; i < N; i += 1024) {
     k0[i] = keys[i];
     v0[i] = i;
@@ -30,17 +41,19 @@ __global__ __launch_bounds__(1024) void sort_u32_index_kernel(const uint32_t *__
   for (uint32_t i = threadIdx.x; i < N; i += 1024) perm[i] = src[i];
 }
 
-hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, uint32_t N, int bits,
-                                 uint32_t *perm, uint32_t *scratch_keys, uint32_t *scratch_vals) {
+hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, const Segs &sg, uint32_t N,
+                                 int bits, uint32_t *perm, uint32_t *scratch_keys,
+                                 uint32_t *scratch_vals) {
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(sort_u32_index_kernel, dim3(1), dim3(1024), 0, st, keys, N, bits, perm,
-                     scratch_keys, scratch_vals, scratch_keys + N, scratch_vals + N);
+  hipLaunchKernelGGL(sort_u32_index_kernel, dim3(sg.nsets), dim3(1024), 0, st, keys, sg.seq, bits,
+                     perm, scratch_keys, scratch_vals, scratch_keys + N, scratch_vals + N);
   return hipGetLastError();
 }
 
 // Per sorted position: inverse permutation, K, 1/K, D and the count of
-// entries seen at least twice (into hcount).
-__global__ void layout_gather_kernel(uint32_t N, const uint32_t *__restrict__ perm,
+// entries seen at least twice (into hcount).  perm and inv hold indices
+// local to the set.
+__global__ void layout_gather_kernel(Segs sg, uint32_t N, const uint32_t *__restrict__ perm,
                                      const uint32_t *__restrict__ Dorig,
                                      const uint32_t *__restrict__ Korig,
                                      const uint32_t *__restrict__ nhi_orig,
@@ -49,8 +62,9 @@ __global__ void layout_gather_kernel(uint32_t N, const uint32_t *__restrict__ pe
                                      uint32_t *__restrict__ hcount, const unsigned long long *err) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= N || *err != ~0ull) return;
-  const uint32_t i = perm[s];
-  inv[i] = s;
+  const uint32_t a = sg.seq[seg_of(sg.seq, sg.nsets, s)];
+  const uint32_t i = a + perm[s];
+  inv[i] = s - a;
   K[s] = Korig[i];
   invK[s] = 1.0 / (double)Korig[i];
   D[s] = Dorig[i];
@@ -98,22 +112,27 @@ struct GroupIn {
   const uint32_t *len;
   __device__ unsigned long long operator()(uint32_t g) const { return 64ull * len[g]; }
 };
+// count>=2 entries of the 16 rows of batch-wide row block x
 struct BlockHiIn {
+  Segs sg;
   const uint32_t *hi_off;
-  uint32_t N;
-  __device__ uint32_t operator()(uint32_t rb) const {
-    return hi_off[min(16u * rb + 16u, N)] - hi_off[16u * rb];
+  __device__ uint32_t operator()(uint32_t x) const {
+    const uint32_t s = seg_of(sg.rb, sg.nsets, x);
+    const uint32_t a = sg.seq[s], n = sg.seq[s + 1] - a, rb = x - sg.rb[s];
+    return hi_off[a + min(16u * rb + 16u, n)] - hi_off[a + 16u * rb];
   }
 };
 
 __global__ __launch_bounds__(1024) void layout_meta_kernel(
-    uint32_t N, const uint32_t *__restrict__ D, const uint32_t *__restrict__ hcount,
-    uint32_t *__restrict__ hi_off, uint64_t *__restrict__ grp_off, uint32_t *__restrict__ grp_len,
+    Segs sg, uint32_t N, uint32_t G, uint32_t RB, const uint32_t *__restrict__ D,
+    const uint32_t *__restrict__ hcount, uint32_t *__restrict__ hi_off,
+    uint64_t *__restrict__ grp_off, uint32_t *__restrict__ grp_len,
     uint64_t *__restrict__ ghi_off, uint32_t *__restrict__ ghi_len,
     uint32_t *__restrict__ exc_off, const unsigned long long *err, LayoutMeta *meta) {
   __shared__ uint32_t wsum[16];
   __shared__ unsigned long long wsum64[16];
   __shared__ unsigned long long s_ent[16];
+  __shared__ uint32_t s_max[16];
   const uint32_t tid = threadIdx.x;
   if (*err != ~0ull) {  // counting failed: report only the error
     if (tid == 0) {
@@ -123,21 +142,28 @@ __global__ __launch_bounds__(1024) void layout_meta_kernel(
     return;
   }
   const uint32_t n_hi = chunked_scan(HcountIn{hcount}, N, hi_off, wsum);
-  // column groups: padded length = longest list (the last, D ascending) rounded to 16
-  const uint32_t G = (N + 63) / 64;
-  for (uint32_t g = tid; g < G; g += 1024) grp_len[g] = (D[min(64u * g + 63u, N - 1)] + 15u) & ~15u;
+  // column group x of set s holds positions a + 64 g .. (g = x - grp[s]);
+  // padded length = longest list (the last one: D ascending) rounded to 16;
+  // count>=2 entries: longest lane, rounded up to 4
+  uint32_t mx = 0;
+  for (uint32_t x = tid; x < G; x += 1024) {
+    const uint32_t s = seg_of(sg.grp, sg.nsets, x);
+    const uint32_t a = sg.seq[s], n = sg.seq[s + 1] - a, g = x - sg.grp[s];
+    const uint32_t p0 = a + 64u * g, p1 = a + min(64u * g + 64u, n);
+    const uint32_t L = (D[p1 - 1] + 15u) & ~15u;
+    grp_len[x] = L;
+    mx = max(mx, L);
+    uint32_t m = 0;
+    for (uint32_t p = p0; p < p1; p++) m = max(m, hcount[p]);
+    ghi_len[x] = (m + 3u) & ~3u;
+  }
+#pragma unroll
+  for (int o = 32; o; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+  if ((tid & 63) == 0) s_max[tid >> 6] = mx;
   __syncthreads();
   const unsigned long long n_gids = chunked_scan(GroupIn{grp_len}, G, (unsigned long long *)grp_off, wsum64);
-  // count>=2 entries per group: longest lane, rounded up to 4
-  for (uint32_t g = tid; g < G; g += 1024) {
-    uint32_t m = 0;
-    for (uint32_t s = 64u * g; s < min(64u * g + 64u, N); s++) m = max(m, hcount[s]);
-    ghi_len[g] = (m + 3u) & ~3u;
-  }
-  __syncthreads();
   const unsigned long long n_ghi = chunked_scan(GroupIn{ghi_len}, G, (unsigned long long *)ghi_off, wsum64);
-  const uint32_t RB = (N + 15) / 16;
-  const uint32_t n_exc = chunked_scan(BlockHiIn{hi_off, N}, RB, exc_off, wsum);
+  const uint32_t n_exc = chunked_scan(BlockHiIn{sg, hi_off}, RB, exc_off, wsum);
   unsigned long long ent = 0;
   for (uint32_t s = tid; s < N; s += 1024) ent += D[s];
 #pragma unroll
@@ -146,39 +172,48 @@ __global__ __launch_bounds__(1024) void layout_meta_kernel(
   __syncthreads();
   if (tid == 0) {
     unsigned long long e = 0;
-    for (int w = 0; w < 16; w++) e += s_ent[w];
+    uint32_t m = 0;
+    for (int w = 0; w < 16; w++) {
+      e += s_ent[w];
+      m = max(m, s_max[w]);
+    }
     meta->err = ~0ull;
     meta->n_hi = n_hi;
     meta->n_gids = n_gids;
     meta->n_exc = n_exc;
     meta->entries = e;
-    meta->max_len = grp_len[G - 1];
+    meta->max_len = m;
     meta->n_ghi = n_ghi;
   }
 }
 
-hipError_t launch_layout_meta(hipStream_t st, uint32_t N, const uint32_t *perm,
+hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32_t G,
+                              uint32_t RB, const uint32_t *perm,
                               const uint32_t *Dorig, const uint32_t *Korig,
                               const uint32_t *nhi_orig, uint32_t *inv, uint32_t *K, uint32_t *D,
                               double *invK, uint32_t *hcount, uint32_t *hi_off, uint64_t *grp_off,
                               uint32_t *grp_len, uint64_t *ghi_off, uint32_t *ghi_len,
                               uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta) {
-  hipLaunchKernelGGL(layout_gather_kernel, dim3((N + 255) / 256), dim3(256), 0, st, N, perm, Dorig,
-                     Korig, nhi_orig, inv, K, D, invK, hcount, err);
+  hipLaunchKernelGGL(layout_gather_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, perm,
+                     Dorig, Korig, nhi_orig, inv, K, D, invK, hcount, err);
   KD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(layout_meta_kernel, dim3(1), dim3(1024), 0, st, N, D, hcount, hi_off, grp_off,
-                     grp_len, ghi_off, ghi_len, exc_off, err, meta);
+  hipLaunchKernelGGL(layout_meta_kernel, dim3(1), dim3(1024), 0, st, sg, N, G, RB, D, hcount,
+                     hi_off, grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta);
   return hipGetLastError();
 }
 
-// Grid (column group, slice of 16 chunks), 256 threads: lane l = tid % 64
-// writes chunks 16 y + tid / 64 + 4 k (k = 0..3) of sequence 64 g + l into
-// the interleaved layout (the 64 lanes' 16-byte chunks adjacent).
-__global__ __launch_bounds__(256) void layout_groups_kernel(SetView v,
+// Grid (batch-wide column group, slice of 16 chunks), 256 threads: lane
+// l = tid % 64 writes chunks 16 y + tid / 64 + 4 k (k = 0..3) of sequence
+// 64 g + l of the group's set into the interleaved layout (the 64 lanes'
+// 16-byte chunks adjacent).
+__global__ __launch_bounds__(256) void layout_groups_kernel(Segs sg,
                                                             const uint64_t *__restrict__ offsets,
                                                             const uint16_t *__restrict__ cap_ids,
                                                             uint16_t *__restrict__ gids) {
-  const uint32_t g = blockIdx.x, lane = threadIdx.x & 63u, sub = threadIdx.x >> 6;
+  const uint32_t x = blockIdx.x, lane = threadIdx.x & 63u, sub = threadIdx.x >> 6;
+  const uint32_t set = seg_of(sg.grp, sg.nsets, x);
+  const SetView &v = sg.views[set];
+  const uint32_t g = x - sg.grp[set];
   const uint32_t L = v.grp_len[g];
   const uint32_t t8_0 = blockIdx.y * 16u;
   if (t8_0 * 8u >= L) return;
@@ -186,7 +221,7 @@ __global__ __launch_bounds__(256) void layout_groups_kernel(SetView v,
   uint32_t Dl = 0;
   const uint16_t *src = nullptr;
   if (s < v.N) {
-    const uint32_t i = v.perm[s];
+    const uint32_t i = v.base + v.perm[s];
     src = cap_ids + (offsets[i] - 5ull * i);
     Dl = v.D[s];
   }
@@ -210,20 +245,26 @@ __global__ __launch_bounds__(256) void layout_groups_kernel(SetView v,
   }
 }
 
-// One wave per sorted position: entries with count >= 2, compacted in order.
-__global__ __launch_bounds__(256) void layout_hi_kernel(SetView v,
+// One wave per batch-wide sorted position: entries with count >= 2,
+// compacted in order.
+__global__ __launch_bounds__(256) void layout_hi_kernel(Segs sg, uint32_t N,
                                                         const uint64_t *__restrict__ offsets,
                                                         const uint16_t *__restrict__ cap_ids,
                                                         const uint16_t *__restrict__ cap_cnt,
                                                         uint16_t *__restrict__ hi_ids,
                                                         uint16_t *__restrict__ hi_cnt,
                                                         uint32_t *__restrict__ ghi) {
-  const uint32_t s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (s >= v.N) return;
-  const uint32_t i = v.perm[s];
+  const uint32_t p = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (p >= N) return;
+  const uint32_t set = seg_of(sg.seq, sg.nsets, p);
+  const SetView &v = sg.views[set];
+  const uint32_t s = p - v.base;
+  const uint32_t i = v.base + v.perm[s];
   const uint64_t co = offsets[i] - 5ull * i;
   const uint32_t Dl = v.D[s];
-  uint32_t o = v.hi_off[s];
+  const uint32_t h0 = v.hi_off[s];
+  const uint64_t gb = v.ghi_off[s >> 6];
+  uint32_t o = h0;
   for (uint32_t b = 0; b < Dl; b += 64) {
     const uint32_t t = b + lane;
     uint16_t id = 0, c = 0;
@@ -234,27 +275,27 @@ __global__ __launch_bounds__(256) void layout_hi_kernel(SetView v,
     const bool f = t < Dl && c >= 2;
     const unsigned long long m = __ballot(f);
     if (f) {
-      const uint32_t p = o + (uint32_t)__popcll(m & lanemask_lt());
-      hi_ids[p] = id;
-      hi_cnt[p] = c;
-      const uint32_t t = p - v.hi_off[s];
-      ghi[v.ghi_off[s >> 6] + 64ull * t + (s & 63u)] = (uint32_t)id | ((uint32_t)c << 16);
+      const uint32_t q = o + (uint32_t)__popcll(m & lanemask_lt());
+      hi_ids[q] = id;
+      hi_cnt[q] = c;
+      ghi[gb + 64ull * (q - h0) + (s & 63u)] = (uint32_t)id | ((uint32_t)c << 16);
     }
     o += (uint32_t)__popcll(m);
   }
 }
 
-hipError_t launch_layout_fill(hipStream_t st, const SetView &v, const uint64_t *offsets,
+hipError_t launch_layout_fill(hipStream_t st, const Segs &sg, const SetView &v,
+                              const uint64_t *offsets,
                               const uint16_t *cap_ids, const uint16_t *cap_cnt, uint16_t *gids,
                               uint16_t *hi_ids, uint16_t *hi_cnt, uint32_t *ghi,
                               uint32_t max_len) {
   if (v.N == 0) return hipSuccess;
   const uint32_t slices = (max_len / 8 + 15) / 16;
-  hipLaunchKernelGGL(layout_groups_kernel, dim3(v.G, slices > 0 ? slices : 1), dim3(256), 0, st, v,
+  hipLaunchKernelGGL(layout_groups_kernel, dim3(v.G, slices > 0 ? slices : 1), dim3(256), 0, st, sg,
                      offsets, cap_ids, gids);
   KD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(layout_hi_kernel, dim3((v.N + 3) / 4), dim3(256), 0, st, v, offsets, cap_ids,
-                     cap_cnt, hi_ids, hi_cnt, ghi);
+  hipLaunchKernelGGL(layout_hi_kernel, dim3((v.N + 3) / 4), dim3(256), 0, st, sg, v.N, offsets,
+                     cap_ids, cap_cnt, hi_ids, hi_cnt, ghi);
   return hipGetLastError();
 }
 
@@ -262,7 +303,7 @@ hipError_t launch_layout_fill(hipStream_t st, const SetView &v, const uint64_t *
 // row) merges one block: each lane walks its row's sorted list, the quarter
 // agrees on the smallest pending word, and every lane writes its row's
 // count for it (0 when the row lacks it).
-__global__ __launch_bounds__(64) void exc_build_kernel(SetView v, uint32_t nblocks,
+__global__ __launch_bounds__(64) void exc_build_kernel(Segs sg, uint32_t nblocks,
                                                         const uint32_t *__restrict__ rowpos,
                                                         const uint32_t *__restrict__ exc_off,
                                                         uint32_t *__restrict__ exc_n,
@@ -272,10 +313,17 @@ __global__ __launch_bounds__(64) void exc_build_kernel(SetView v, uint32_t nbloc
   const uint32_t r = threadIdx.x & 15;
   const bool active = gq < nblocks;
   uint32_t s = 0xFFFFFFFFu;
+  uint32_t set = 0;
   if (active) {
-    if (rowpos) s = rowpos[16u * gq + r];
-    else if (16u * gq + r < v.N) s = 16u * gq + r;
+    if (rowpos) {
+      s = rowpos[16u * gq + r];
+    } else {
+      set = seg_of(sg.rb, sg.nsets, gq);
+      const uint32_t rb = gq - sg.rb[set];
+      if (16u * rb + r < sg.seq[set + 1] - sg.seq[set]) s = 16u * rb + r;
+    }
   }
+  const SetView &v = sg.views[set];
   uint32_t p = 0, pe = 0;
   if (s != 0xFFFFFFFFu) {
     p = v.hi_off[s];
@@ -298,11 +346,11 @@ __global__ __launch_bounds__(64) void exc_build_kernel(SetView v, uint32_t nbloc
   if (active && r == 0) exc_n[gq] = e;
 }
 
-hipError_t launch_exc_build(hipStream_t st, const SetView &v, uint32_t nblocks,
+hipError_t launch_exc_build(hipStream_t st, const Segs &sg, uint32_t nblocks,
                             const uint32_t *rowpos, const uint32_t *exc_off, uint32_t *exc_n,
                             uint16_t *exc_ids, uint16_t *exc_cnt) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(exc_build_kernel, dim3((nblocks + 3) / 4), dim3(64), 0, st, v, nblocks,
+  hipLaunchKernelGGL(exc_build_kernel, dim3((nblocks + 3) / 4), dim3(64), 0, st, sg, nblocks,
                      rowpos, exc_off, exc_n, exc_ids, exc_cnt);
   return hipGetLastError();
 }
@@ -433,13 +481,6 @@ hipError_t launch_export_dense(hipStream_t st, const kd_set *s, uint32_t first, 
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(export_dense_kernel, dim3(count), dim3(256), 0, st, s->in_off, s->cap_ids,
                      s->cap_cnt, s->Dorig, first, out);
-  return hipGetLastError();
-}
-
-__global__ void store_view_kernel(SetView v, SetView *dst) { *dst = v; }
-
-hipError_t launch_store_view(hipStream_t st, const SetView &v, SetView *dst) {
-  hipLaunchKernelGGL(store_view_kernel, dim3(1), dim3(1), 0, st, v, dst);
   return hipGetLastError();
 }
 

@@ -446,19 +446,25 @@ hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairT
   return hipGetLastError();
 }
 
-__global__ void rank_finalize_kernel(SetView v, double delta, double *__restrict__ ranks) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= v.N) return;
-  const long long *a = v.acc + 3ull * s;
+// R = (sum of the pair terms + the j = i term) / N for every sorted
+// position of every set; written at the sequence's input index.
+__global__ void rank_finalize_kernel(Segs sg, uint32_t N, double delta, double *__restrict__ ranks) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const uint32_t set = seg_of(sg.seq, sg.nsets, p);
+  const uint32_t a = sg.seq[set], n = sg.seq[set + 1] - a;
+  const SetView &v = sg.views[set];
+  const long long *acc = v.acc + 3ull * (p - a);
   long long l0, l1, l2;
   fix_limbs(-log(delta + 1.0), l0, l1, l2);  // the j = i term: F = 1
-  const double sum = fix_to_double(a[0] + l0, a[1] + l1, a[2] + l2);
-  ranks[v.perm[s]] = sum / (double)v.N;
+  const double sum = fix_to_double(acc[0] + l0, acc[1] + l1, acc[2] + l2);
+  ranks[a + v.perm[p - a]] = sum / (double)n;
 }
 
-hipError_t launch_rank_finalize(hipStream_t st, const SetView &v, double delta, double *ranks) {
-  if (v.N == 0) return hipSuccess;
-  hipLaunchKernelGGL(rank_finalize_kernel, dim3((v.N + 255) / 256), dim3(256), 0, st, v, delta,
+hipError_t launch_rank_finalize(hipStream_t st, const Segs &sg, uint32_t N, double delta,
+                                double *ranks) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_finalize_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, delta,
                      ranks);
   return hipGetLastError();
 }

@@ -1,7 +1,7 @@
 // Regular-sampling decomposition (paper Section 3.1.2; Algorithm 2 steps 3
 // and 8-11) with B virtual processors on one GPU.
 //
-// One workgroup handles one set:
+// One workgroup handles one set (a batch of sets runs one workgroup per set):
 //  1. keys (rank, index) are sorted once (stable LSD radix sort of an
 //     order-preserving 64-bit image of the rank over index-ordered input);
 //     the sorted indices are the grouped output order and give every key its
@@ -138,6 +138,29 @@ __global__ __launch_bounds__(1024) void partition_kernel(const double *R, uint32
   __shared__ RadixShared<1024> sh;
   __shared__ uint32_t prho[kMaxBuckets];
   partition_one(R, n, B, bucket, order, offsets, piv_r, piv_i, carve(scratch, n, B), sh, prho);
+}
+
+__global__ __launch_bounds__(1024) void partition_batch_kernel(const PartDesc *__restrict__ desc,
+                                                               const double *R, uint32_t *bucket,
+                                                               uint32_t *order, uint32_t *offsets,
+                                                               double *piv_r, uint32_t *piv_i,
+                                                               char *scratch) {
+  __shared__ RadixShared<1024> sh;
+  __shared__ uint32_t prho[kMaxBuckets];
+  const PartDesc d = desc[blockIdx.x];
+  partition_one(R + d.first, d.n, d.B, bucket + d.first, order + d.first, offsets + d.off_base,
+                piv_r ? piv_r + d.piv_base : nullptr, piv_i ? piv_i + d.piv_base : nullptr,
+                carve(scratch + d.scratch_off, d.n, d.B), sh, prho);
+}
+
+hipError_t launch_partition_batch(hipStream_t st, const PartDesc *desc, uint32_t nsets,
+                                  const double *ranks, uint32_t *bucket, uint32_t *order,
+                                  uint32_t *offsets, double *pivot_rank, uint32_t *pivot_idx,
+                                  void *scratch) {
+  if (nsets == 0) return hipSuccess;
+  hipLaunchKernelGGL(partition_batch_kernel, dim3(nsets), dim3(1024), 0, st, desc, ranks, bucket,
+                     order, offsets, pivot_rank, pivot_idx, (char *)scratch);
+  return hipGetLastError();
 }
 
 // rho[i] += #{j in this workgroup's chunk : key_j < key_i, or key_j == key_i

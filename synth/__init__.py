@@ -186,9 +186,36 @@ def batch_set(seq: np.random.SeedSequence) -> SeqSet:
     return families(rng, N, F, lens, rates, name=f"batch-{N}", B=min(8, N // 32))
 
 
-def batched(seed: int = 4, nsets: int = 4096):
-    """The batched workload: ``nsets`` independent sets (list of SeqSet)."""
-    return [batch_set(s) for s in np.random.SeedSequence(seed).spawn(nsets)]
+def batched(seed: int = 4, nsets: int = 4096, workers: int = 1):
+    """The batched workload: ``nsets`` independent sets (list of SeqSet).
+
+    Set s is drawn from child s of ``SeedSequence(seed)``, so the result does
+    not depend on ``workers`` (processes forked to draw sets in parallel;
+    call this before the process initializes a GPU)."""
+    children = np.random.SeedSequence(seed).spawn(nsets)
+    if workers <= 1 or nsets < 2 * workers:
+        return [batch_set(c) for c in children]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(batch_set, children, chunksize=max(1, nsets // (8 * workers)))
+
+
+def concat(sets):
+    """Lay several SeqSets end to end.
+
+    Returns (residues u8, offsets u64[sum N + 1], set_first u32[len(sets)+1],
+    B u32[len(sets)]): set s is sequences set_first[s] .. set_first[s+1]-1."""
+    ns = np.array([x.offsets.size - 1 for x in sets], dtype=np.int64)
+    first = np.zeros(len(sets) + 1, dtype=np.uint32)
+    np.cumsum(ns, out=first[1:])
+    res = np.concatenate([x.residues for x in sets]) if sets else np.zeros(0, np.uint8)
+    tot = np.cumsum([0] + [int(x.residues.size) for x in sets[:-1]]).astype(np.uint64)
+    off = np.zeros(int(first[-1]) + 1, dtype=np.uint64)
+    for q, x in enumerate(sets):
+        off[int(first[q]):int(first[q + 1])] = x.offsets[:-1] + tot[q]
+    off[-1] = res.size
+    Bs = np.array([x.B for x in sets], dtype=np.uint32)
+    return res, off, first, Bs
 
 
 def served_job(seq: np.random.SeedSequence, nmin: int = 64, nmax: int = 8192) -> SeqSet:
