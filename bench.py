@@ -156,13 +156,92 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_served(args):
+    """Poisson request streams through the server (continuous batching) and
+    through the same server limited to one job at a time (the FIFO loop);
+    latency = completion - scheduled arrival.  Every served result is
+    compared bit for bit with the job run alone through the single-set calls."""
+    import numpy as np
+    import synth
+    rates = [float(x) for x in args.rates.split(",")]
+    t0 = time.perf_counter()
+    jobs = synth.served_jobs(5, args.jobs, workers=min(16, os.cpu_count() or 1))
+    print(f"[bench] served workload: {len(jobs)} jobs, {sum(j.n for j in jobs)} sequences, "
+          f"generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    import paper_0905_1744_amd as kd
+    ctx = kd.Context(0)
+    ref = []
+    for x in jobs:  # each job alone through the single-set calls
+        ks = ctx.kmer_count(x.residues, x.offsets.view(np.int64))
+        R = ctx.kmer_rank(ks, args.delta)
+        p = ctx.sample_partition(R, x.B)
+        ref.append((R.cpu().numpy(), kd.u32(p["bucket"]), kd.u32(p["order"]), kd.u32(p["offsets"])))
+        ks.destroy()
+    pairs = np.array([x.n * (x.n - 1) / 2 for x in jobs])
+    results = {}
+    identical = True
+    for mode in ("batched", "fifo"):
+        for lam in rates:
+            arr = synth.served_arrivals(5, len(jobs), lam)
+            srv = kd.Server(0, hbm_budget=200 << 30, max_batch_jobs=0 if mode == "batched" else 1)
+            for x in jobs[:2]:  # first-call costs out of the way
+                srv.submit(x.residues, x.offsets, x.B, args.delta)
+            got = 0
+            while got < 2:
+                got += len(srv.poll(8, wait_s=0.1))
+            recs, tick = {}, {}
+            i = 0
+            start = time.monotonic_ns()
+            while len(recs) < len(jobs):
+                now = time.monotonic_ns()
+                while i < len(jobs) and start + int(arr[i] * 1e9) <= now:
+                    tick[srv.submit(jobs[i].residues, jobs[i].offsets, jobs[i].B, args.delta)] = i
+                    i += 1
+                wait = (start + int(arr[i] * 1e9) - time.monotonic_ns()) / 1e9 if i < len(jobs) else 0.05
+                for r in srv.poll(256, wait_s=min(max(wait, 0.0), 0.002)):
+                    recs[tick[r["ticket"]]] = r
+            srv.close()
+            lat = np.array([(recs[q]["t_done_ns"] - start) / 1e9 - arr[q] for q in range(len(jobs))])
+            end = max(r["t_done_ns"] for r in recs.values())
+            ok = all(recs[q]["status"] == 0 for q in range(len(jobs)))
+            for q in range(len(jobs)):
+                r = recs[q]
+                ok = ok and np.array_equal(r["ranks"], ref[q][0]) and np.array_equal(r["bucket"], ref[q][1]) \
+                    and np.array_equal(r["order"], ref[q][2]) and np.array_equal(r["offsets"], ref[q][3])
+            identical = identical and ok
+            span = (end - start) / 1e9
+            results.setdefault(mode, {})[str(int(lam) if lam.is_integer() else lam)] = {
+                "jobs_per_s": len(jobs) / span, "pairs_per_s": float(pairs.sum()) / span,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_batch_jobs": float(np.mean([recs[q]["batch_jobs"] for q in range(len(jobs))])),
+                "identical_to_alone": ok}
+            print(f"[bench] served {mode} rate {lam:g}/s: p50 {results[mode][str(int(lam) if lam.is_integer() else lam)]['p50_ms']:.2f} ms "
+                  f"p99 {np.percentile(lat, 99) * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    top = str(int(rates[-1]) if rates[-1].is_integer() else rates[-1])
+    line = {
+        "metric": "served k-mer rank + split: p50/p99 request latency and jobs/s per arrival rate",
+        "value": results["batched"][top]["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1,
+        "steps": len(jobs), "warmup": 2, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u16/f64", "data": "synthetic",
+        "config": {"workload": (f"served: {len(jobs)} jobs per rate, Poisson arrivals at {args.rates}/s, "
+                                "N log-uniform [64, 8192], 4-32 families, lognormal length mean 300, "
+                                "divergence 5-30%, B = max(1, N/256), seed 5, budget 200 GiB"),
+                   "delta": args.delta},
+        "rates": results, "identical_to_alone": identical,
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS) + ["batched"])
+    ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS) + ["batched", "served"])
     ap.add_argument("--sets", type=int, default=4096, help="batched workload: number of sets")
+    ap.add_argument("--jobs", type=int, default=200, help="served workload: jobs per arrival rate")
+    ap.add_argument("--rates", default="10,20,50,100,200,500", help="served workload: arrival rates (jobs/s)")
     ap.add_argument("--delta", type=float, default=0.1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -187,6 +266,9 @@ def main():
 
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "served":
+        bench_served(args)
         return
 
     import numpy as np

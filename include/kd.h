@@ -214,6 +214,71 @@ kd_status kd_batch_run(kd_ctx *ctx, const uint8_t *residues, const uint64_t *off
                        const uint32_t *set_B, double delta, double *ranks, uint32_t *bucket,
                        uint32_t *order, uint32_t *offsets_out);
 
+/* ----------------------------------------------------------------- server */
+
+/* A request server for many independent jobs (each job = one sequence set
+ * to count, rank and split).  A worker thread with its own context and
+ * stream on `device` serves them: a job is admitted once the device memory
+ * it will need fits the budget next to the other admitted jobs, and every
+ * time the device becomes free the worker runs all admitted jobs (of one
+ * delta, within the batch limits) as one batch through kd_batch_run's path.
+ * Each job's results are bit-for-bit those of running it alone.  All calls
+ * are internally synchronized and may come from any thread. */
+typedef struct kd_server kd_server;
+
+typedef struct kd_server_opts {
+  uint64_t hbm_budget;     /* bytes the admitted jobs may reserve; a job is charged
+                              KD_JOB_BYTES(n_residues, n_seqs), an estimate of its
+                              peak device memory inside a batch */
+  uint32_t max_batch_jobs; /* jobs per batch; 0 = no limit, 1 = one job at a time */
+  uint32_t max_batch_seqs; /* sequences per batch; 0 = no limit */
+} kd_server_opts;
+
+#define KD_JOB_BYTES(n_residues, n_seqs) (8ull * (n_residues) + 256ull * (n_seqs) + 65536ull)
+
+typedef struct kd_job {
+  const uint8_t *residues;   /* HOST u8[n_residues]; copied by kd_server_submit */
+  const uint64_t *offsets;   /* HOST u64[n_seqs+1] as for kmer_count; copied */
+  uint32_t n_seqs;
+  uint64_t n_residues;
+  uint32_t B;                /* buckets: 1 <= B <= n_seqs, B <= 1024 */
+  double delta;              /* Equation 2's constant (finite, > 0) */
+  double *ranks;             /* HOST f64[n_seqs] or NULL: written before completion */
+  uint32_t *bucket;          /* HOST u32[n_seqs] or NULL */
+  uint32_t *order;           /* HOST u32[n_seqs] or NULL */
+  uint32_t *bucket_offsets;  /* HOST u32[B+1] or NULL */
+} kd_job;
+
+typedef struct kd_done {
+  uint64_t ticket;
+  kd_status status;          /* KD_OK, the job's input error (KD_EBADRESIDUE ...),
+                                KD_ECANCELLED or KD_EDEVICE */
+  uint32_t batch_jobs;       /* jobs in the batch that served it */
+  uint64_t t_submit_ns;      /* CLOCK_MONOTONIC times: submit, batch start, results written */
+  uint64_t t_start_ns;
+  uint64_t t_done_ns;
+} kd_done;
+
+/* Errors: KD_EINVAL for a bad device or NULL arguments, KD_EDEVICE. */
+kd_status kd_server_create(int device, const kd_server_opts *opts, kd_server **out);
+/* Queue a job; its inputs are copied before this returns, its output
+ * buffers must stay valid until its kd_done has been polled.  Errors:
+ * KD_EINVAL (bad offsets, B or delta; detected here), KD_EBUSY (the job
+ * alone exceeds the budget). */
+kd_status kd_server_submit(kd_server *srv, const kd_job *job, uint64_t *ticket);
+/* Move up to `max` completion records into out[0 .. *n); waits up to
+ * wait_ns nanoseconds (0: do not wait) when none is ready. */
+kd_status kd_server_poll(kd_server *srv, kd_done *out, uint32_t max, uint32_t *n, int64_t wait_ns);
+/* Cancel a job that has not started (its record reports KD_ECANCELLED);
+ * KD_EBUSY if it is running, KD_EINVAL if the ticket is unknown or done. */
+kd_status kd_server_cancel(kd_server *srv, uint64_t ticket);
+/* Jobs queued, admitted-and-waiting, running; completion records not yet
+ * polled; device bytes reserved by admitted jobs. */
+kd_status kd_server_status(kd_server *srv, uint32_t *waiting, uint32_t *admitted,
+                           uint32_t *running, uint32_t *done, uint64_t *reserved);
+/* Finishes the running batch, drops queued jobs, joins the worker. */
+void kd_server_destroy(kd_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

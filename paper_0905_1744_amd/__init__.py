@@ -41,6 +41,27 @@ class KdError(RuntimeError):
         self.status, self.seq, self.pos = status, seq, pos
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_batch_jobs", C.c_uint32), ("max_batch_seqs", C.c_uint32)]
+
+
+class Job(C.Structure):
+    _fields_ = [("residues", C.c_void_p), ("offsets", C.c_void_p), ("n_seqs", C.c_uint32),
+                ("n_residues", C.c_uint64), ("B", C.c_uint32), ("delta", C.c_double),
+                ("ranks", C.c_void_p), ("bucket", C.c_void_p), ("order", C.c_void_p),
+                ("bucket_offsets", C.c_void_p)]
+
+
+class Done(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("batch_jobs", C.c_uint32),
+                ("t_submit_ns", C.c_uint64), ("t_start_ns", C.c_uint64), ("t_done_ns", C.c_uint64)]
+
+
+def job_bytes(n_residues: int, n_seqs: int) -> int:
+    """Device bytes the server charges a job against its budget (KD_JOB_BYTES)."""
+    return 8 * n_residues + 256 * n_seqs + 65536
+
+
 def lib():
     """Load the HIP library (raises if it has not been built)."""
     global _lib
@@ -75,6 +96,13 @@ def lib():
         "kd_set_count": (u32, [P]),
         "sample_partition_batch": (i32, [P, P, u32, P, P, P, P, P, P, P]),
         "kd_batch_run": (i32, [P, P, P, u64, u32, P, P, C.c_double, P, P, P, P]),
+        "kd_server_create": (i32, [C.c_int, C.POINTER(ServerOpts), PP]),
+        "kd_server_submit": (i32, [P, C.POINTER(Job), C.POINTER(u64)]),
+        "kd_server_poll": (i32, [P, C.POINTER(Done), u32, C.POINTER(u32), C.c_int64]),
+        "kd_server_cancel": (i32, [P, u64]),
+        "kd_server_status": (i32, [P, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32), C.POINTER(u32),
+                                   C.POINTER(u64)]),
+        "kd_server_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -307,6 +335,81 @@ class Context:
                                        float(delta), _ptr(out["ranks"]), _ptr(out["bucket"]),
                                        _ptr(out["order"]), _ptr(out["offsets"])), "kd_batch_run")
         return out
+
+
+class Server:
+    """Request server (kd_server_*): jobs are host arrays; results land in
+    numpy arrays owned by this object until the job's record is polled."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 200 << 30, max_batch_jobs: int = 0,
+                 max_batch_seqs: int = 0):
+        L = lib()
+        opts = ServerOpts(hbm_budget, max_batch_jobs, max_batch_seqs)
+        out = C.c_void_p()
+        st = L.kd_server_create(device, C.byref(opts), C.byref(out))
+        if st != KD_OK:
+            raise KdError(st, "kd_server_create")
+        self.handle = out
+        self._live = {}  # ticket -> (inputs kept for the call, outputs)
+
+    def submit(self, residues, offsets, B: int, delta: float = 0.1) -> int:
+        res = np.ascontiguousarray(residues, dtype=np.uint8)
+        off = np.ascontiguousarray(np.asarray(offsets).view(np.uint64) if np.asarray(offsets).dtype == np.int64
+                                   else np.asarray(offsets, dtype=np.uint64))
+        n = off.size - 1
+        out = dict(ranks=np.empty(max(n, 1), np.float64), bucket=np.empty(max(n, 1), np.uint32),
+                   order=np.empty(max(n, 1), np.uint32), offsets=np.empty(B + 1 if B > 0 else 1, np.uint32))
+        job = Job(res.ctypes.data, off.ctypes.data, n, res.size, B, float(delta),
+                  out["ranks"].ctypes.data, out["bucket"].ctypes.data, out["order"].ctypes.data,
+                  out["offsets"].ctypes.data)
+        t = C.c_uint64()
+        st = lib().kd_server_submit(self.handle, C.byref(job), C.byref(t))
+        if st != KD_OK:
+            raise KdError(st, "kd_server_submit")
+        for k in ("ranks", "bucket", "order"):
+            out[k] = out[k][:n]
+        self._live[int(t.value)] = out
+        return int(t.value)
+
+    def poll(self, max_records: int = 256, wait_s: float = 0.0):
+        """List of dicts (ticket, status, batch_jobs, t_submit/start/done ns, and
+        the result arrays when status is KD_OK)."""
+        buf = (Done * max_records)()
+        n = C.c_uint32()
+        st = lib().kd_server_poll(self.handle, buf, max_records, C.byref(n), int(wait_s * 1e9))
+        if st != KD_OK:
+            raise KdError(st, "kd_server_poll")
+        recs = []
+        for d in buf[:n.value]:
+            r = dict(ticket=int(d.ticket), status=int(d.status), batch_jobs=int(d.batch_jobs),
+                     t_submit_ns=int(d.t_submit_ns), t_start_ns=int(d.t_start_ns), t_done_ns=int(d.t_done_ns))
+            out = self._live.pop(r["ticket"], None)
+            if out is not None and r["status"] == KD_OK:
+                r.update(out)
+            recs.append(r)
+        return recs
+
+    def cancel(self, ticket: int) -> int:
+        """KD_OK, or the status code (KD_EBUSY: already running)."""
+        return int(lib().kd_server_cancel(self.handle, ticket))
+
+    def status(self):
+        w, a, r, d = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()
+        res = C.c_uint64()
+        lib().kd_server_status(self.handle, C.byref(w), C.byref(a), C.byref(r), C.byref(d), C.byref(res))
+        return dict(waiting=w.value, admitted=a.value, running=r.value, done=d.value, reserved=res.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().kd_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default = None

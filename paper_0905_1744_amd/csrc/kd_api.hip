@@ -415,9 +415,10 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint32_t *sortv = tmp.get<uint32_t>(2ull * N);
   unsigned long long *small = tmp.get<unsigned long long>(8);  // [0] err, [1] nlong
   LayoutMeta *meta = tmp.get<LayoutMeta>(1);
+  void *meta_tmp = tmp.get<char>(layout_meta_scratch_bytes(N, RB));
   if (!in_off || !cap_ids || !cap_cnt || !Dorig || !perm || !inv || !K || !D || !invK || !hi_off || !hcount ||
       !grp_off || !grp_len || !ghi_off || !ghi_len || !exc_off || !exc_n || !acc || !segb || !d_view ||
-      !Korig || !nhi_orig || !long_list || !mid_list || !sortk || !sortv || !small || !meta) {
+      !Korig || !nhi_orig || !long_list || !mid_list || !sortk || !sortv || !small || !meta || !meta_tmp) {
     set_free(s);
     return KD_ENOMEM;
   }
@@ -445,10 +446,12 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
                      nhi_orig, mid_list, nmid, long_list, nlong, err, ctx->cus);
   t_count.done();
   StageTimer t_layout(ctx, KD_STAGE_LAYOUT);
-  if (e == hipSuccess) e = launch_sort_u32_index(st, Dorig, sg, N, 16, perm, sortk, sortv);
+  uint32_t max_n = 0;
+  for (uint32_t q = 0; q < nsets; q++) max_n = std::max(max_n, first[q + 1] - first[q]);
+  if (e == hipSuccess) e = launch_sort_u32_index(st, Dorig, sg, max_n, 16, perm, sortk, sortv, N);
   if (e == hipSuccess)
     e = launch_layout_meta(st, sg, N, G, RB, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hcount,
-                           hi_off, grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta);
+                           hi_off, grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta, meta_tmp);
   t_layout.done();
   LayoutMeta *hm = static_cast<LayoutMeta *>(ctx->pinned);
   if (e == hipSuccess) e = hipMemcpyAsync(hm, meta, sizeof(LayoutMeta), hipMemcpyDeviceToHost, st);

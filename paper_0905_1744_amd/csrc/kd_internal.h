@@ -164,11 +164,12 @@ hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off,
                         uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
                         unsigned long long *err, int cus);
 
-// per set s: stable sort of (key u32 < 2^bits, value = local index) over the
-// set's range of keys; writes perm (local indices) over the same range
-hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, const Segs &sg, uint32_t N,
-                                 int bits, uint32_t *perm, uint32_t *scratch_keys,
-                                 uint32_t *scratch_vals);
+// per set s: stable sort of (key u32 < 2^bits, bits <= 16, value = local
+// index) over the set's range of keys; writes perm (local indices) over the
+// same range.  max_n = largest set; scratch_* hold 2N entries each.
+hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, const Segs &sg,
+                                 uint32_t max_n, int bits, uint32_t *perm, uint32_t *scratch_keys,
+                                 uint32_t *scratch_vals, uint32_t N);
 
 struct LayoutMeta {  // totals written by layout_meta, read by the host
   unsigned long long err;
@@ -187,7 +188,10 @@ hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32
                               double *invK, uint32_t *hcount,
                               uint32_t *hi_off, uint64_t *grp_off, uint32_t *grp_len,
                               uint64_t *ghi_off, uint32_t *ghi_len,
-                              uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta);
+                              uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta,
+                              void *scratch);
+// scratch bytes launch_layout_meta needs
+size_t layout_meta_scratch_bytes(uint32_t N, uint32_t RB);
 
 hipError_t launch_layout_fill(hipStream_t st, const Segs &sg, const SetView &v,
                               const uint64_t *offsets,

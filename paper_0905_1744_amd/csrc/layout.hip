@@ -14,8 +14,53 @@
 
 namespace kd {
 
-// One workgroup per set: stable radix sort of the set's keys with their
-// local indices as values.
+// Sets of at most kBitonicSortMax sequences: one workgroup per set sorts
+// the unique keys (key << 15) | local index (key < 2^16) with a bitonic
+// network in LDS; ties in key keep index order because the index is part
+// of the sort key.  (Beyond a few thousand keys the network's barrier
+// count makes the radix sort below faster.)
+constexpr uint32_t kBitonicSortMax = 2048;
+
+__host__ __device__ inline uint32_t pow2_at_least(uint32_t n) {
+  uint32_t p = 2;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// In-place ascending bitonic sort of P (a power of two) u32 values in LDS.
+__device__ inline void bitonic_lds(uint32_t *sk, uint32_t P, uint32_t nt) {
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t x = tid; x < (P >> 1); x += nt) {
+        const uint32_t a = ((x & ~(j - 1)) << 1) | (x & (j - 1));
+        const uint32_t b = a | j;
+        const uint32_t va = sk[a], vb = sk[b];
+        if ((va > vb) == ((a & k) == 0)) {
+          sk[a] = vb;
+          sk[b] = va;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void sort_small_kernel(const uint32_t *__restrict__ keys,
+                                                          const uint32_t *__restrict__ seq,
+                                                          uint32_t *__restrict__ perm) {
+  extern __shared__ uint32_t sk[];
+  const uint32_t a = seq[blockIdx.x], n = seq[blockIdx.x + 1] - a;
+  if (n == 0 || n > kBitonicSortMax) return;
+  const uint32_t P = pow2_at_least(n);
+  for (uint32_t t = threadIdx.x; t < P; t += 1024) sk[t] = t < n ? (keys[a + t] << 15) | t : 0xFFFFFFFFu;
+  __syncthreads();
+  bitonic_lds(sk, P, 1024);
+  for (uint32_t t = threadIdx.x; t < n; t += 1024) perm[a + t] = sk[t] & 0x7FFFu;
+}
+
+// Larger sets: one workgroup per set, stable radix sort of the keys with
+// their local indices as values.
 __global__ __launch_bounds__(1024) void sort_u32_index_kernel(const uint32_t *__restrict__ keys,
                                                               const uint32_t *__restrict__ seq,
                                                               int bits,
@@ -24,7 +69,7 @@ __global__ __launch_bounds__(1024) void sort_u32_index_kernel(const uint32_t *__
                                                               uint32_t *k1, uint32_t *v1) {
   __shared__ RadixShared<1024> sh;
   const uint32_t a = seq[blockIdx.x], N = seq[blockIdx.x + 1] - a;
-  if (N == 0) return;
+  if (N <= kBitonicSortMax) return;
   keys += a;
   perm += a;
   k0 += a;
@@ -41,13 +86,21 @@ __global__ __launch_bounds__(1024) void sort_u32_index_kernel(const uint32_t *__
   for (uint32_t i = threadIdx.x; i < N; i += 1024) perm[i] = src[i];
 }
 
-hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, const Segs &sg, uint32_t N,
-                                 int bits, uint32_t *perm, uint32_t *scratch_keys,
-                                 uint32_t *scratch_vals) {
+hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, const Segs &sg,
+                                 uint32_t max_n, int bits, uint32_t *perm, uint32_t *scratch_keys,
+                                 uint32_t *scratch_vals, uint32_t N) {
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(sort_u32_index_kernel, dim3(sg.nsets), dim3(1024), 0, st, keys, sg.seq, bits,
-                     perm, scratch_keys, scratch_vals, scratch_keys + N, scratch_vals + N);
-  return hipGetLastError();
+  if (bits > 16) return hipErrorInvalidValue;  // the bitonic keys hold 16 bits of key
+  const uint32_t small_max = max_n < kBitonicSortMax ? max_n : kBitonicSortMax;
+  hipLaunchKernelGGL(sort_small_kernel, dim3(sg.nsets), dim3(1024),
+                     sizeof(uint32_t) * pow2_at_least(small_max), st, keys, sg.seq, perm);
+  KD_HIP(hipGetLastError());
+  if (max_n > kBitonicSortMax) {
+    hipLaunchKernelGGL(sort_u32_index_kernel, dim3(sg.nsets), dim3(1024), 0, st, keys, sg.seq,
+                       bits, perm, scratch_keys, scratch_vals, scratch_keys + N, scratch_vals + N);
+    KD_HIP(hipGetLastError());
+  }
+  return hipSuccess;
 }
 
 // Per sorted position: inverse permutation, K, 1/K, D and the count of
@@ -71,120 +124,136 @@ __global__ void layout_gather_kernel(Segs sg, uint32_t N, const uint32_t *__rest
   hcount[s] = nhi_orig[i];
 }
 
-// Exclusive scan of n values with one 1024-thread workgroup, each thread
-// summing a contiguous chunk; out[n] gets the total, which is returned.
-template <typename In, typename Out>
-__device__ Out chunked_scan(const In &in, uint32_t n, Out *out, Out *wsum) {
-  const uint32_t tid = threadIdx.x;
-  const uint32_t per = (n + 1023) / 1024;
-  const uint32_t lo = min(tid * per, n), hi = min(lo + per, n);
-  Out local = 0;
-  for (uint32_t x = lo; x < hi; x++) local += in(x);
-  const int lane = tid & 63, wave = tid >> 6;
-  Out incl = local;
+// Per batch-wide column group (one wave each): padded list length (the
+// group's longest list, i.e. its last: D ascending, rounded to 16), longest
+// count>=2 list (rounded to 4), and the count>=2 entries of each of its
+// four row blocks; sums of D and the longest padded list go to the totals.
+__global__ __launch_bounds__(256) void layout_groups_meta_kernel(
+    Segs sg, uint32_t G, const uint32_t *__restrict__ D, const uint32_t *__restrict__ hcount,
+    uint32_t *__restrict__ grp_len, uint32_t *__restrict__ ghi_len, uint32_t *__restrict__ rbcnt,
+    const unsigned long long *err, LayoutMeta *meta) {
+  const uint32_t x = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63u;
+  if (x >= G || *err != ~0ull) return;
+  const uint32_t s = seg_of(sg.grp, sg.nsets, x);
+  const uint32_t a = sg.seq[s], n = sg.seq[s + 1] - a, g = x - sg.grp[s];
+  const bool valid = 64u * g + lane < n;
+  const uint32_t h = valid ? hcount[a + 64u * g + lane] : 0u;
+  const uint32_t d = valid ? D[a + 64u * g + lane] : 0u;
+  uint32_t mh = h, md = d, rs = h;
+  unsigned long long sd = d;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const Out y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
+  for (int o = 32; o; o >>= 1) {
+    mh = max(mh, (uint32_t)__shfl_xor((int)mh, o, 64));
+    md = max(md, (uint32_t)__shfl_xor((int)md, o, 64));
+    sd += __shfl_xor(sd, o, 64);
   }
-  if (lane == 63) wsum[wave] = incl;
-  __syncthreads();
-  Out before = 0, all = 0;
-  for (int w = 0; w < 16; w++) {
-    before += (w < wave) ? wsum[w] : 0;
-    all += wsum[w];
+#pragma unroll
+  for (int o = 8; o; o >>= 1) rs += (uint32_t)__shfl_xor((int)rs, o, 16);
+  const uint32_t L = (md + 15u) & ~15u;
+  if (lane == 0) {
+    grp_len[x] = L;
+    ghi_len[x] = (mh + 3u) & ~3u;
+    atomicAdd(&meta->entries, sd);
+    atomicMax(&meta->max_len, (unsigned long long)L);
   }
-  __syncthreads();
-  Out run = before + incl - local;
-  for (uint32_t x = lo; x < hi; x++) {
-    out[x] = run;
-    run += in(x);
-  }
-  if (tid == 0) out[n] = all;
-  return all;
+  const uint32_t rb = 4u * g + (lane >> 4);
+  if ((lane & 15u) == 0 && 16u * rb < n) rbcnt[sg.rb[s] + rb] = rs;
 }
 
-struct HcountIn {
-  const uint32_t *h;
-  __device__ uint32_t operator()(uint32_t s) const { return h[s]; }
+// Exclusive scans of four arrays at once (y = which): hi_off over the
+// sorted positions, grp_off and ghi_off (64 x length) over the column
+// groups, exc_off over the row blocks.  Three passes: tile sums, a scan of
+// the tile sums (which also writes the totals), the scan of each tile.
+constexpr uint32_t kScanTile = 4096;  // 1024 threads x 4 values
+
+struct ScanJob {
+  const uint32_t *in;
+  uint32_t n;
+  uint32_t mul;
+  uint32_t *out32;  // one of out32 / out64
+  uint64_t *out64;
 };
-struct GroupIn {
-  const uint32_t *len;
-  __device__ unsigned long long operator()(uint32_t g) const { return 64ull * len[g]; }
-};
-// count>=2 entries of the 16 rows of batch-wide row block x
-struct BlockHiIn {
-  Segs sg;
-  const uint32_t *hi_off;
-  __device__ uint32_t operator()(uint32_t x) const {
-    const uint32_t s = seg_of(sg.rb, sg.nsets, x);
-    const uint32_t a = sg.seq[s], n = sg.seq[s + 1] - a, rb = x - sg.rb[s];
-    return hi_off[a + min(16u * rb + 16u, n)] - hi_off[a + 16u * rb];
-  }
+struct ScanJobs {
+  ScanJob j[4];
+  unsigned long long *part;  // [4][nblk] tile sums, then tile offsets
+  uint32_t nblk;
 };
 
-__global__ __launch_bounds__(1024) void layout_meta_kernel(
-    Segs sg, uint32_t N, uint32_t G, uint32_t RB, const uint32_t *__restrict__ D,
-    const uint32_t *__restrict__ hcount, uint32_t *__restrict__ hi_off,
-    uint64_t *__restrict__ grp_off, uint32_t *__restrict__ grp_len,
-    uint64_t *__restrict__ ghi_off, uint32_t *__restrict__ ghi_len,
-    uint32_t *__restrict__ exc_off, const unsigned long long *err, LayoutMeta *meta) {
-  __shared__ uint32_t wsum[16];
-  __shared__ unsigned long long wsum64[16];
-  __shared__ unsigned long long s_ent[16];
-  __shared__ uint32_t s_max[16];
-  const uint32_t tid = threadIdx.x;
-  if (*err != ~0ull) {  // counting failed: report only the error
-    if (tid == 0) {
-      meta->err = *err;
-      meta->n_hi = meta->n_gids = meta->n_exc = meta->entries = meta->max_len = meta->n_ghi = 0;
-    }
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(ScanJobs J, const unsigned long long *err) {
+  __shared__ unsigned long long wsum[16];
+  const ScanJob jb = J.j[blockIdx.y];
+  const uint32_t x0 = blockIdx.x * kScanTile;
+  if (x0 >= jb.n || *err != ~0ull) return;
+  unsigned long long v = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const uint32_t x = x0 + 4u * threadIdx.x + k;
+    if (x < jb.n) v += (unsigned long long)jb.in[x] * jb.mul;
+  }
+  unsigned long long tot;
+  block_exclusive_scan64<1024>(v, wsum, tot);
+  if (threadIdx.x == 0) J.part[blockIdx.y * J.nblk + blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void scan_top_kernel(ScanJobs J, const unsigned long long *err,
+                                                        LayoutMeta *meta) {
+  __shared__ unsigned long long wsum[16];
+  const uint32_t y = blockIdx.x;
+  if (*err != ~0ull) {
+    if (y == 0 && threadIdx.x == 0) meta->err = *err;
     return;
   }
-  const uint32_t n_hi = chunked_scan(HcountIn{hcount}, N, hi_off, wsum);
-  // column group x of set s holds positions a + 64 g .. (g = x - grp[s]);
-  // padded length = longest list (the last one: D ascending) rounded to 16;
-  // count>=2 entries: longest lane, rounded up to 4
-  uint32_t mx = 0;
-  for (uint32_t x = tid; x < G; x += 1024) {
-    const uint32_t s = seg_of(sg.grp, sg.nsets, x);
-    const uint32_t a = sg.seq[s], n = sg.seq[s + 1] - a, g = x - sg.grp[s];
-    const uint32_t p0 = a + 64u * g, p1 = a + min(64u * g + 64u, n);
-    const uint32_t L = (D[p1 - 1] + 15u) & ~15u;
-    grp_len[x] = L;
-    mx = max(mx, L);
-    uint32_t m = 0;
-    for (uint32_t p = p0; p < p1; p++) m = max(m, hcount[p]);
-    ghi_len[x] = (m + 3u) & ~3u;
+  const ScanJob jb = J.j[y];
+  const uint32_t nb = (jb.n + kScanTile - 1) / kScanTile;
+  unsigned long long *part = J.part + y * J.nblk;
+  unsigned long long carry = 0;
+  for (uint32_t b0 = 0; b0 < nb; b0 += 1024) {
+    const uint32_t b = b0 + threadIdx.x;
+    const unsigned long long v = b < nb ? part[b] : 0ull;
+    unsigned long long tot;
+    const unsigned long long ex = block_exclusive_scan64<1024>(v, wsum, tot);
+    if (b < nb) part[b] = carry + ex;
+    carry += tot;
   }
+  if (threadIdx.x == 0) {
+    if (jb.out32) jb.out32[jb.n] = (uint32_t)carry;
+    else jb.out64[jb.n] = carry;
+    if (y == 0) meta->n_hi = carry;
+    if (y == 1) meta->n_gids = carry;
+    if (y == 2) meta->n_ghi = carry;
+    if (y == 3) meta->n_exc = carry;
+    if (y == 0) meta->err = ~0ull;
+  }
+}
+
+__global__ __launch_bounds__(1024) void scan_write_kernel(ScanJobs J, const unsigned long long *err) {
+  __shared__ unsigned long long wsum[16];
+  const ScanJob jb = J.j[blockIdx.y];
+  const uint32_t x0 = blockIdx.x * kScanTile;
+  if (x0 >= jb.n || *err != ~0ull) return;
+  unsigned long long v[4], loc = 0;
 #pragma unroll
-  for (int o = 32; o; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
-  if ((tid & 63) == 0) s_max[tid >> 6] = mx;
-  __syncthreads();
-  const unsigned long long n_gids = chunked_scan(GroupIn{grp_len}, G, (unsigned long long *)grp_off, wsum64);
-  const unsigned long long n_ghi = chunked_scan(GroupIn{ghi_len}, G, (unsigned long long *)ghi_off, wsum64);
-  const uint32_t n_exc = chunked_scan(BlockHiIn{sg, hi_off}, RB, exc_off, wsum);
-  unsigned long long ent = 0;
-  for (uint32_t s = tid; s < N; s += 1024) ent += D[s];
+  for (int k = 0; k < 4; k++) {
+    const uint32_t x = x0 + 4u * threadIdx.x + k;
+    v[k] = x < jb.n ? (unsigned long long)jb.in[x] * jb.mul : 0ull;
+    loc += v[k];
+  }
+  unsigned long long tot;
+  unsigned long long run = J.part[blockIdx.y * J.nblk + blockIdx.x] + block_exclusive_scan64<1024>(loc, wsum, tot);
 #pragma unroll
-  for (int o = 32; o; o >>= 1) ent += __shfl_xor(ent, o, 64);
-  if ((tid & 63) == 0) s_ent[tid >> 6] = ent;
-  __syncthreads();
-  if (tid == 0) {
-    unsigned long long e = 0;
-    uint32_t m = 0;
-    for (int w = 0; w < 16; w++) {
-      e += s_ent[w];
-      m = max(m, s_max[w]);
+  for (int k = 0; k < 4; k++) {
+    const uint32_t x = x0 + 4u * threadIdx.x + k;
+    if (x < jb.n) {
+      if (jb.out32) jb.out32[x] = (uint32_t)run;
+      else jb.out64[x] = run;
     }
-    meta->err = ~0ull;
-    meta->n_hi = n_hi;
-    meta->n_gids = n_gids;
-    meta->n_exc = n_exc;
-    meta->entries = e;
-    meta->max_len = m;
-    meta->n_ghi = n_ghi;
+    run += v[k];
   }
+}
+
+size_t layout_meta_scratch_bytes(uint32_t N, uint32_t RB) {
+  const uint32_t nblk = (N + kScanTile - 1) / kScanTile;
+  return 4ull * RB + 256 + 8ull * 4 * (nblk ? nblk : 1);
 }
 
 hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32_t G,
@@ -193,12 +262,30 @@ hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32
                               const uint32_t *nhi_orig, uint32_t *inv, uint32_t *K, uint32_t *D,
                               double *invK, uint32_t *hcount, uint32_t *hi_off, uint64_t *grp_off,
                               uint32_t *grp_len, uint64_t *ghi_off, uint32_t *ghi_len,
-                              uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta) {
+                              uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta,
+                              void *scratch) {
+  uint32_t *rbcnt = static_cast<uint32_t *>(scratch);
+  const uint32_t nblk = (N + kScanTile - 1) / kScanTile;  // N >= G, RB
+  ScanJobs J;
+  J.part = reinterpret_cast<unsigned long long *>(static_cast<char *>(scratch) +
+                                                  ((4ull * RB + 255) & ~255ull));
+  J.nblk = nblk;
+  J.j[0] = {hcount, N, 1u, hi_off, nullptr};
+  J.j[1] = {grp_len, G, 64u, nullptr, grp_off};
+  J.j[2] = {ghi_len, G, 64u, nullptr, ghi_off};
+  J.j[3] = {rbcnt, RB, 1u, exc_off, nullptr};
+  KD_HIP(launch_fill_u64(st, meta, sizeof(LayoutMeta) / 8, 0ull));
   hipLaunchKernelGGL(layout_gather_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, perm,
                      Dorig, Korig, nhi_orig, inv, K, D, invK, hcount, err);
   KD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(layout_meta_kernel, dim3(1), dim3(1024), 0, st, sg, N, G, RB, D, hcount,
-                     hi_off, grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta);
+  hipLaunchKernelGGL(layout_groups_meta_kernel, dim3((G + 3) / 4), dim3(256), 0, st, sg, G, D,
+                     hcount, grp_len, ghi_len, rbcnt, err, meta);
+  KD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3(nblk, 4), dim3(1024), 0, st, J, err);
+  KD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(scan_top_kernel, dim3(4), dim3(1024), 0, st, J, err, meta);
+  KD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(scan_write_kernel, dim3(nblk, 4), dim3(1024), 0, st, J, err);
   return hipGetLastError();
 }
 
@@ -299,37 +386,19 @@ hipError_t launch_layout_fill(hipStream_t st, const Segs &sg, const SetView &v,
   return hipGetLastError();
 }
 
-// Merged count>=2 words of row blocks.  A quarter-wave (16 lanes, one per
-// row) merges one block: each lane walks its row's sorted list, the quarter
-// agrees on the smallest pending word, and every lane writes its row's
-// count for it (0 when the row lacks it).
-__global__ __launch_bounds__(64) void exc_build_kernel(Segs sg, uint32_t nblocks,
-                                                        const uint32_t *__restrict__ rowpos,
-                                                        const uint32_t *__restrict__ exc_off,
-                                                        uint32_t *__restrict__ exc_n,
-                                                        uint16_t *__restrict__ exc_ids,
-                                                        uint16_t *__restrict__ exc_cnt) {
-  const uint32_t gq = blockIdx.x * 4 + (threadIdx.x >> 4);  // block handled by this quarter
-  const uint32_t r = threadIdx.x & 15;
-  const bool active = gq < nblocks;
-  uint32_t s = 0xFFFFFFFFu;
-  uint32_t set = 0;
-  if (active) {
-    if (rowpos) {
-      s = rowpos[16u * gq + r];
-    } else {
-      set = seg_of(sg.rb, sg.nsets, gq);
-      const uint32_t rb = gq - sg.rb[set];
-      if (16u * rb + r < sg.seq[set + 1] - sg.seq[set]) s = 16u * rb + r;
-    }
-  }
-  const SetView &v = sg.views[set];
+// Merged count>=2 words of a row block by a quarter-wave (16 lanes, one
+// per row): each lane walks its row's sorted list (sorted position s, or
+// 0xFFFFFFFF for none), the quarter agrees on the smallest pending word,
+// and every lane writes its row's count for it (0 when the row lacks it).
+// Returns the number of merged words.
+__device__ inline uint32_t merge_rows(const SetView &v, uint32_t s, uint32_t r, uint32_t base,
+                                      uint16_t *__restrict__ exc_ids,
+                                      uint16_t *__restrict__ exc_cnt) {
   uint32_t p = 0, pe = 0;
   if (s != 0xFFFFFFFFu) {
     p = v.hi_off[s];
     pe = v.hi_off[s + 1];
   }
-  const uint32_t base = active ? exc_off[gq] : 0;
   uint32_t e = 0;
   while (true) {
     uint32_t cur = p < pe ? v.hi_ids[p] : 0xFFFFFFFFu;
@@ -343,15 +412,115 @@ __global__ __launch_bounds__(64) void exc_build_kernel(Segs sg, uint32_t nblocks
     if (take) p++;
     e++;
   }
+  return e;
+}
+
+// Listed rows (block b = sorted positions rowpos[16b .. 16b+15] of the first
+// set): one quarter-wave per block.
+__global__ __launch_bounds__(64) void exc_build_kernel(Segs sg, uint32_t nblocks,
+                                                        const uint32_t *__restrict__ rowpos,
+                                                        const uint32_t *__restrict__ exc_off,
+                                                        uint32_t *__restrict__ exc_n,
+                                                        uint16_t *__restrict__ exc_ids,
+                                                        uint16_t *__restrict__ exc_cnt) {
+  const uint32_t gq = blockIdx.x * 4 + (threadIdx.x >> 4);  // block handled by this quarter
+  const uint32_t r = threadIdx.x & 15;
+  const bool active = gq < nblocks;
+  const uint32_t s = active ? rowpos[16u * gq + r] : 0xFFFFFFFFu;
+  const uint32_t e = merge_rows(sg.views[0], s, r, active ? exc_off[gq] : 0u, exc_ids, exc_cnt);
   if (active && r == 0) exc_n[gq] = e;
+}
+
+// Every row block of every set (batch-wide numbering), one wave each.  The
+// 16 rows are consecutive sorted positions, so their count>=2 entries are
+// one contiguous range; up to kExcStage of them are staged in LDS as keys
+// (word, row, slot), sorted, and each distinct word emits its 16 counts.
+// Larger blocks (rare) fall back to the quarter-wave merge.
+constexpr uint32_t kExcStage = 512;
+
+__global__ __launch_bounds__(64) void exc_build_rows_kernel(Segs sg,
+                                                            const uint32_t *__restrict__ exc_off,
+                                                            uint32_t *__restrict__ exc_n,
+                                                            uint16_t *__restrict__ exc_ids,
+                                                            uint16_t *__restrict__ exc_cnt) {
+  __shared__ uint32_t key[kExcStage];
+  __shared__ uint16_t cv[kExcStage];
+  __shared__ uint16_t ust[kExcStage];
+  __shared__ uint32_t roff[17];
+  const uint32_t gq = blockIdx.x, lane = threadIdx.x;
+  const uint32_t set = seg_of(sg.rb, sg.nsets, gq);
+  const SetView &v = sg.views[set];
+  const uint32_t n = sg.seq[set + 1] - sg.seq[set];
+  const uint32_t s0 = 16u * (gq - sg.rb[set]), s1 = min(s0 + 16u, n);
+  if (lane <= 16u) roff[lane] = v.hi_off[min(s0 + lane, s1)];
+  __syncthreads();
+  const uint32_t e0 = roff[0], T = roff[16] - e0;
+  const uint32_t base = exc_off[gq];
+  if (T > kExcStage) {
+    if (lane < 16u) {
+      const uint32_t e = merge_rows(v, s0 + lane < s1 ? s0 + lane : 0xFFFFFFFFu, lane, base,
+                                    exc_ids, exc_cnt);
+      if (lane == 0) exc_n[gq] = e;
+    }
+    return;
+  }
+  if (T == 0) {
+    if (lane == 0) exc_n[gq] = 0;
+    return;
+  }
+  const uint32_t P = pow2_at_least(T);
+  for (uint32_t t = lane; t < P; t += 64) {
+    uint32_t k = 0xFFFFFFFFu;
+    if (t < T) {
+      const uint32_t x = e0 + t;
+      uint32_t r = 0;
+#pragma unroll
+      for (int q = 1; q < 16; q++) r += roff[q] <= x;
+      k = ((uint32_t)v.hi_ids[x] << 13) | (r << 9) | t;
+      cv[t] = v.hi_cnt[x];
+    }
+    key[t] = k;
+  }
+  __syncthreads();
+  bitonic_lds(key, P, 64);
+  // distinct words: each lane takes a contiguous run of sorted slots
+  const uint32_t per = (T + 63) / 64, t0 = min(lane * per, T), t1 = min(t0 + per, T);
+  uint32_t nf = 0;
+  for (uint32_t t = t0; t < t1; t++) nf += (t == 0 || (key[t] >> 13) != (key[t - 1] >> 13));
+  uint32_t incl = nf;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= (uint32_t)o) incl += y;
+  }
+  const uint32_t nu = __shfl(incl, 63, 64);
+  uint32_t u = incl - nf;
+  for (uint32_t t = t0; t < t1; t++)
+    if (t == 0 || (key[t] >> 13) != (key[t - 1] >> 13)) ust[u++] = (uint16_t)t;
+  __syncthreads();
+  for (uint32_t w = lane; w < nu; w += 64) {
+    uint32_t t = ust[w];
+    const uint32_t id = key[t] >> 13;
+    uint16_t *row = exc_cnt + (size_t)(base + w) * 16;
+    uint4 *row4 = reinterpret_cast<uint4 *>(row);
+    row4[0] = make_uint4(0u, 0u, 0u, 0u);
+    row4[1] = make_uint4(0u, 0u, 0u, 0u);
+    for (; t < T && (key[t] >> 13) == id; t++) row[(key[t] >> 9) & 15u] = cv[key[t] & 511u];
+    exc_ids[base + w] = (uint16_t)id;
+  }
+  if (lane == 0) exc_n[gq] = nu;
 }
 
 hipError_t launch_exc_build(hipStream_t st, const Segs &sg, uint32_t nblocks,
                             const uint32_t *rowpos, const uint32_t *exc_off, uint32_t *exc_n,
                             uint16_t *exc_ids, uint16_t *exc_cnt) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(exc_build_kernel, dim3((nblocks + 3) / 4), dim3(64), 0, st, sg, nblocks,
-                     rowpos, exc_off, exc_n, exc_ids, exc_cnt);
+  if (rowpos)
+    hipLaunchKernelGGL(exc_build_kernel, dim3((nblocks + 3) / 4), dim3(64), 0, st, sg, nblocks,
+                       rowpos, exc_off, exc_n, exc_ids, exc_cnt);
+  else
+    hipLaunchKernelGGL(exc_build_rows_kernel, dim3(nblocks), dim3(64), 0, st, sg, exc_off, exc_n,
+                       exc_ids, exc_cnt);
   return hipGetLastError();
 }
 

@@ -227,13 +227,33 @@ def served_job(seq: np.random.SeedSequence, nmin: int = 64, nmax: int = 8192) ->
     return families(rng, N, F, lens, rates, name=f"job-{N}", B=max(1, N // 256))
 
 
+def _served_job_default(seq):
+    return served_job(seq)
+
+
+def served_jobs(seed: int = 5, njobs: int = 1000, workers: int = 1):
+    """The jobs of the served workload (independent of the arrival rate)."""
+    job_seqs = np.random.SeedSequence(seed).spawn(njobs + 1)[1:]
+    if workers <= 1 or njobs < 2 * workers:
+        return [served_job(s) for s in job_seqs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_served_job_default, job_seqs, chunksize=max(1, njobs // (8 * workers)))
+
+
+def served_arrivals(seed: int = 5, njobs: int = 1000, rate: float = 100.0) -> np.ndarray:
+    """Poisson arrival times (seconds) of the served workload at `rate` jobs/s."""
+    arr_seq = np.random.SeedSequence(seed).spawn(njobs + 1)[0]
+    rng = np.random.default_rng(arr_seq)
+    return np.cumsum(rng.exponential(1.0 / rate, size=njobs))
+
+
 def served_stream(seed: int = 5, njobs: int = 1000, rate: float = 100.0,
                   nmin: int = 64, nmax: int = 8192):
     """Poisson request stream: list of (arrival_seconds, SeqSet)."""
     ss = np.random.SeedSequence(seed)
-    arr_seq, *job_seqs = ss.spawn(njobs + 1)
-    rng = np.random.default_rng(arr_seq)
-    t = np.cumsum(rng.exponential(1.0 / rate, size=njobs))
+    job_seqs = ss.spawn(njobs + 1)[1:]
+    t = served_arrivals(seed, njobs, rate)
     return [(float(t[i]), served_job(job_seqs[i], nmin, nmax)) for i in range(njobs)]
 
 

@@ -1,0 +1,158 @@
+"""GPU: the request server.  Every served job's results must be bit-identical
+to the same job run alone through the single-set calls; admission must keep
+the reserved bytes within the budget; bad jobs fail alone; cancellation of
+queued jobs; one-job-at-a-time mode."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kd():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0905_1744_amd as kd
+    kd.lib()
+    return kd
+
+
+@pytest.fixture(scope="module")
+def ctx(kd):
+    c = kd.Context()
+    yield c
+    c.synchronize()
+
+
+@pytest.fixture(scope="module")
+def jobs():
+    ss = np.random.SeedSequence(77).spawn(16)
+    out = [synth.served_job(s, 64, 1500) for s in ss]
+    rng = np.random.default_rng(8)
+    out.append(synth.random_tiny(rng, 3, 6, 40))   # B = 1
+    out.append(synth.random_tiny(rng, 70, 6, 90))
+    return out
+
+
+def alone(ctx, kd, x, delta):
+    ks = ctx.kmer_count(x.residues, x.offsets.view(np.int64))
+    R = ctx.kmer_rank(ks, delta)
+    p = ctx.sample_partition(R, x.B)
+    return dict(ranks=R.cpu().numpy(), bucket=kd.u32(p["bucket"]), order=kd.u32(p["order"]),
+                offsets=kd.u32(p["offsets"]))
+
+
+def drain(srv, n, timeout=60.0):
+    recs, t0 = [], time.monotonic()
+    while len(recs) < n:
+        recs += srv.poll(64, wait_s=0.05)
+        assert time.monotonic() - t0 < timeout, f"only {len(recs)} of {n} records"
+    return {r["ticket"]: r for r in recs}
+
+
+def check_same(rec, want):
+    assert rec["status"] == 0, rec["status"]
+    for k in ("ranks", "bucket", "order", "offsets"):
+        assert np.array_equal(rec[k], want[k]), k
+
+
+def test_server_matches_alone(kd, ctx, jobs):
+    srv = kd.Server(0)
+    say("server", len(jobs))
+    tickets = []
+    for q, x in enumerate(jobs):
+        delta = 0.1 if q % 3 else 0.05
+        tickets.append((srv.submit(x.residues, x.offsets, x.B, delta), q, delta))
+    recs = drain(srv, len(tickets))
+    batched = 0
+    for t, q, delta in tickets:
+        check_same(recs[t], alone(ctx, kd, jobs[q], delta))
+        assert recs[t]["t_submit_ns"] <= recs[t]["t_start_ns"] <= recs[t]["t_done_ns"]
+        batched += recs[t]["batch_jobs"] > 1
+    assert batched > 0  # jobs submitted together share batches
+    srv.close()
+
+
+def test_server_bad_job_fails_alone(kd, ctx, jobs):
+    srv = kd.Server(0)
+    bad = jobs[1].residues.copy()
+    bad[int(jobs[1].offsets[5]) + 2] = ord("B")
+    short = synth.from_strings(["ACDEFGH", "ACD"])
+    t0 = srv.submit(jobs[0].residues, jobs[0].offsets, jobs[0].B)
+    t1 = srv.submit(bad, jobs[1].offsets, jobs[1].B)
+    t2 = srv.submit(short.residues, short.offsets, 1)
+    t3 = srv.submit(jobs[2].residues, jobs[2].offsets, jobs[2].B)
+    recs = drain(srv, 4)
+    assert recs[t1]["status"] == -2
+    assert recs[t2]["status"] == -3
+    check_same(recs[t0], alone(ctx, kd, jobs[0], 0.1))
+    check_same(recs[t3], alone(ctx, kd, jobs[2], 0.1))
+    with pytest.raises(kd.KdError):  # inconsistent offsets are refused at submit
+        srv.submit(jobs[0].residues[:-1], jobs[0].offsets, jobs[0].B)
+    with pytest.raises(kd.KdError):
+        srv.submit(jobs[0].residues, jobs[0].offsets, jobs[0].n + 1)
+    srv.close()
+
+
+def test_server_budget_and_fifo(kd, ctx, jobs):
+    sizes = [kd.job_bytes(x.residues.size, x.n) for x in jobs]
+    budget = 2 * max(sizes)
+    srv = kd.Server(0, hbm_budget=budget)
+    say("server-budget", budget)
+    with pytest.raises(kd.KdError) as e:  # a job that can never fit
+        big = synth.served_job(np.random.SeedSequence(5), 4000, 4000)
+        srv2 = kd.Server(0, hbm_budget=kd.job_bytes(big.residues.size, big.n) - 1)
+        try:
+            srv2.submit(big.residues, big.offsets, big.B)
+        finally:
+            srv2.close()
+    assert e.value.status == -6
+    tickets = [(srv.submit(x.residues, x.offsets, x.B), q) for q, x in enumerate(jobs)]
+    peak = 0
+    recs = {}
+    t0 = time.monotonic()
+    while len(recs) < len(tickets):
+        st = srv.status()
+        assert st["reserved"] <= budget
+        peak = max(peak, st["reserved"])
+        for r in srv.poll(64, wait_s=0.01):
+            recs[r["ticket"]] = r
+        assert time.monotonic() - t0 < 60
+    assert srv.status()["reserved"] == 0
+    for t, q in tickets:
+        check_same(recs[t], alone(ctx, kd, jobs[q], 0.1))
+    srv.close()
+    # one job at a time
+    srv = kd.Server(0, max_batch_jobs=1)
+    tickets = [(srv.submit(x.residues, x.offsets, x.B), q) for q, x in enumerate(jobs[:6])]
+    recs = drain(srv, len(tickets))
+    for t, q in tickets:
+        assert recs[t]["batch_jobs"] == 1
+        check_same(recs[t], alone(ctx, kd, jobs[q], 0.1))
+    srv.close()
+
+
+def test_server_cancel(kd, ctx, jobs):
+    # budget for one job: the rest queue, so cancelling the last is possible
+    srv = kd.Server(0, hbm_budget=max(kd.job_bytes(x.residues.size, x.n) for x in jobs[:4]))
+    ts = [srv.submit(x.residues, x.offsets, x.B) for x in jobs[:4]]
+    rc = srv.cancel(ts[-1])
+    assert rc in (0, -6)  # KD_EBUSY only if it already started
+    assert srv.cancel(10 ** 9) == -1
+    recs = drain(srv, 4)
+    if rc == 0:
+        assert recs[ts[-1]]["status"] == -8
+    for q, t in enumerate(ts[:3]):
+        check_same(recs[t], alone(ctx, kd, jobs[q], 0.1))
+    srv.close()
