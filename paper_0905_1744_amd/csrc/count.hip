@@ -136,7 +136,8 @@ __device__ __forceinline__ void count_one(const uint8_t *__restrict__ res, uint3
 // those of at most 1024 words (LDS sized for them), and queues longer ones
 // for the 4096-word kernel or the dense-histogram one.
 __global__ __launch_bounds__(64) void count_short_kernel(
-    const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint32_t N, uint64_t nres,
+    const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint64_t *__restrict__ in_off,
+    uint32_t N, uint64_t nres,
     uint64_t cap, uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt,
     uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout, uint32_t *__restrict__ nhiout,
     uint32_t *__restrict__ mid_list, uint32_t *__restrict__ nmid, uint32_t *__restrict__ long_list,
@@ -151,6 +152,10 @@ __global__ __launch_bounds__(64) void count_short_kernel(
   if (code != kErrNone) {
     if (lane == 0) atomicMin(err, pack_err(i, code, 0));
     return;
+  }
+  if (lane == 0) {
+    in_off[i] = o0;
+    if (i + 1 == N) in_off[N] = o1;
   }
   const uint32_t n = (uint32_t)(o1 - o0);
   const uint32_t K = n - (kK - 1);
@@ -255,13 +260,13 @@ __global__ __launch_bounds__(1024) void count_long_kernel(
   }
 }
 
-hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off, uint32_t N,
-                        uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
+hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off, uint64_t *in_off,
+                        uint32_t N, uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
                         uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig, uint32_t *mid_list,
                         uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
                         unsigned long long *err, int cus) {
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(count_short_kernel, dim3(N), dim3(64), 0, st, res, off, N, nres, cap, cap_ids,
+  hipLaunchKernelGGL(count_short_kernel, dim3(N), dim3(64), 0, st, res, off, in_off, N, nres, cap, cap_ids,
                      cap_cnt, Dorig, Korig, nhi_orig, mid_list, nmid, long_list, nlong, err);
   KD_HIP(hipGetLastError());
   const uint32_t grid = (uint32_t)(cus > 0 ? cus : 256);

@@ -334,6 +334,16 @@ void make_tasks(uint32_t N, uint32_t set_index, std::vector<PairTask> &out) {
   out.insert(out.end(), t.begin(), t.end());
 }
 
+uint64_t ntasks_of(uint32_t nsets, const uint32_t *first) {
+  uint64_t t = 0;
+  for (uint32_t q = 0; q < nsets; q++) {
+    const uint32_t N = first[q + 1] - first[q], RB = (N + 15) / 16, G = (N + 63) / 64;
+    for (uint32_t g0 = 0; g0 < G; g0 += kGroupsPerTask)
+      t += (RB - std::min(RB, 4u * g0) + kRowBlocksPerTask - 1) / kRowBlocksPerTask;
+  }
+  return t;
+}
+
 // number of 16 x 64 tiles of a task (its share of the triangle)
 uint64_t task_tiles(const PairTask &t, uint32_t G) {
   uint64_t n = 0;
@@ -404,21 +414,23 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint32_t *exc_n = set_alloc<uint32_t>(s, RB);
   long long *acc = set_alloc<long long>(s, 3ull * N);
   uint32_t *segb = set_alloc<uint32_t>(s, 3ull * (nsets + 1));
-  SetView *d_view = set_alloc<SetView>(s, nsets);
+
   // temporaries
   uint32_t *Korig = tmp.get<uint32_t>(N);
   uint32_t *hcount = tmp.get<uint32_t>(N);
   uint32_t *nhi_orig = tmp.get<uint32_t>(N);
   uint32_t *long_list = tmp.get<uint32_t>(N);
   uint32_t *mid_list = tmp.get<uint32_t>(N);
-  uint32_t *sortk = tmp.get<uint32_t>(2ull * N);
-  uint32_t *sortv = tmp.get<uint32_t>(2ull * N);
-  unsigned long long *small = tmp.get<unsigned long long>(8);  // [0] err, [1] nlong
-  LayoutMeta *meta = tmp.get<LayoutMeta>(1);
+  uint32_t max_n = 0;
+  for (uint32_t q = 0; q < nsets; q++) max_n = std::max(max_n, first[q + 1] - first[q]);
+  void *sort_tmp = tmp.get<char>(sort_scratch_bytes(max_n));
+  // [0] err, [1] nlong | nmid, [8 ..] LayoutMeta: cleared by one launch
+  unsigned long long *small = tmp.get<unsigned long long>(8 + (sizeof(LayoutMeta) + 7) / 8);
+  LayoutMeta *meta = reinterpret_cast<LayoutMeta *>(small + 8);
   void *meta_tmp = tmp.get<char>(layout_meta_scratch_bytes(N, RB));
   if (!in_off || !cap_ids || !cap_cnt || !Dorig || !perm || !inv || !K || !D || !invK || !hi_off || !hcount ||
-      !grp_off || !grp_len || !ghi_off || !ghi_len || !exc_off || !exc_n || !acc || !segb || !d_view ||
-      !Korig || !nhi_orig || !long_list || !mid_list || !sortk || !sortv || !small || !meta || !meta_tmp) {
+      !grp_off || !grp_len || !ghi_off || !ghi_len || !exc_off || !exc_n || !acc || !segb ||
+      !Korig || !nhi_orig || !long_list || !mid_list || !sort_tmp || !small || !meta || !meta_tmp) {
     set_free(s);
     return KD_ENOMEM;
   }
@@ -431,24 +443,24 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   sg.seq = segb;
   sg.grp = segb + (nsets + 1);
   sg.rb = segb + 2 * (nsets + 1);
-  sg.views = d_view;
   unsigned long long *err = small;
   uint32_t *nlong = reinterpret_cast<uint32_t *>(small + 1);  // [0] long, [1] mid
   uint32_t *nmid = nlong + 1;
   hipError_t e = upload(ctx, segb, hb.data(), sizeof(uint32_t) * hb.size());
-  if (e == hipSuccess) e = launch_fill_u64(st, small, 1, ~0ull);
-  if (e == hipSuccess) e = launch_fill_u64(st, small + 1, 1, 0ull);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(in_off, offsets, sizeof(uint64_t) * (N + 1), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) {
+    FillJobs f{};
+    f.j[0] = {small, 1, ~0ull};
+    f.j[1] = {small + 1, 7 + (sizeof(LayoutMeta) + 7) / 8, 0ull};
+    f.n = 2;
+    e = launch_fills(st, f);
+  }
   StageTimer t_count(ctx, KD_STAGE_COUNT);
   if (e == hipSuccess)
-    e = launch_count(st, residues, offsets, N, n_residues, cap, cap_ids, cap_cnt, Dorig, Korig,
+    e = launch_count(st, residues, offsets, in_off, N, n_residues, cap, cap_ids, cap_cnt, Dorig, Korig,
                      nhi_orig, mid_list, nmid, long_list, nlong, err, ctx->cus);
   t_count.done();
   StageTimer t_layout(ctx, KD_STAGE_LAYOUT);
-  uint32_t max_n = 0;
-  for (uint32_t q = 0; q < nsets; q++) max_n = std::max(max_n, first[q + 1] - first[q]);
-  if (e == hipSuccess) e = launch_sort_u32_index(st, Dorig, sg, max_n, 16, perm, sortk, sortv, N);
+  if (e == hipSuccess) e = launch_sort_u32_index(st, Dorig, sg, first, perm, sort_tmp);
   if (e == hipSuccess)
     e = launch_layout_meta(st, sg, N, G, RB, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hcount,
                            hi_off, grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta, meta_tmp);
@@ -479,7 +491,11 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint16_t *exc_ids = set_alloc<uint16_t>(s, s->n_exc);
   uint16_t *exc_cnt = set_alloc<uint16_t>(s, 16ull * s->n_exc);
   uint32_t *ghi = set_alloc<uint32_t>(s, hm->n_ghi + 2);
-  if (!gids || !hi_ids || !hi_cnt || !exc_ids || !exc_cnt || !ghi) {
+  // per-set views, then the rank work list (one upload)
+  const size_t view_bytes = (sizeof(SetView) * nsets + 255) & ~(size_t)255;
+  const uint64_t task_cap = ntasks_of(nsets, first);
+  char *vt = set_alloc<char>(s, view_bytes + sizeof(PairTask) * (size_t)(task_cap + 1));
+  if (!gids || !hi_ids || !hi_cnt || !exc_ids || !exc_cnt || !ghi || !vt) {
     set_free(s);
     return KD_ENOMEM;
   }
@@ -530,7 +546,9 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   s->cap_cnt = cap_cnt;
   s->Dorig = Dorig;
   s->in_off = in_off;
+  SetView *d_view = reinterpret_cast<SetView *>(vt);
   s->d_view = d_view;
+  sg.views = d_view;
   // rank work list of every set; with several sets the largest tasks go
   // first (the per-set lists keep their own order otherwise)
   s->h_tasks.clear();
@@ -547,17 +565,27 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     s->h_tasks.swap(sorted);
   }
   s->ntasks = (uint32_t)s->h_tasks.size();
-  s->tasks = set_alloc<PairTask>(s, s->ntasks + 1);
-  if (!s->tasks) {
+  if (s->ntasks > task_cap) {  // cannot happen: ntasks_of counts what make_tasks emits
     set_free(s);
-    return KD_ENOMEM;
+    return KD_EINVAL;
   }
+  s->tasks = reinterpret_cast<PairTask *>(vt + view_bytes);
   StageTimer t_fill(ctx, KD_STAGE_LAYOUT);
-  e = upload(ctx, d_view, s->views.data(), sizeof(SetView) * nsets);
-  if (e == hipSuccess) e = upload(ctx, s->tasks, s->h_tasks.data(), sizeof(PairTask) * s->ntasks);
-  // sentinel slack after the last group: the pair kernel reads ahead into it
-  if (e == hipSuccess) e = launch_fill_u64(st, gids + s->n_gids, kGidsSlack / 4, 0xB640B640B640B640ull);
-  if (e == hipSuccess) e = launch_fill_u64(st, ghi, (hm->n_ghi + 1) / 2, 0ull);
+  {
+    std::vector<char> hv(view_bytes + sizeof(PairTask) * s->ntasks);
+    std::memcpy(hv.data(), s->views.data(), sizeof(SetView) * nsets);
+    std::memcpy(hv.data() + view_bytes, s->h_tasks.data(), sizeof(PairTask) * s->ntasks);
+    e = upload(ctx, vt, hv.data(), hv.size());
+  }
+  if (e == hipSuccess) {
+    // sentinel slack after the last group (the pair kernel reads ahead into
+    // it) and the zero padding of the grouped count>=2 lists
+    FillJobs f{};
+    f.j[0] = {reinterpret_cast<unsigned long long *>(gids + s->n_gids), kGidsSlack / 4, 0xB640B640B640B640ull};
+    f.j[1] = {reinterpret_cast<unsigned long long *>(ghi), (hm->n_ghi + 1) / 2, 0ull};
+    f.n = 2;
+    e = launch_fills(st, f);
+  }
   if (e == hipSuccess)
     e = launch_layout_fill(st, sg, v, in_off, cap_ids, cap_cnt, gids, hi_ids, hi_cnt, ghi,
                            (uint32_t)hm->max_len);

@@ -158,18 +158,20 @@ namespace kd {
 
 // ------------------------------------------------------------ launchers
 
-hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off, uint32_t N,
-                        uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
+// also copies the offsets into in_off (N+1 entries)
+hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off, uint64_t *in_off,
+                        uint32_t N, uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
                         uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig, uint32_t *mid_list,
                         uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
                         unsigned long long *err, int cus);
 
-// per set s: stable sort of (key u32 < 2^bits, bits <= 16, value = local
-// index) over the set's range of keys; writes perm (local indices) over the
-// same range.  max_n = largest set; scratch_* hold 2N entries each.
+// per set s: stable sort of (key u32 < 2^16, value = local index) over the
+// set's range of keys; writes perm (local indices) over the same range.
+// host_first = the set bounds on the host; scratch holds
+// sort_scratch_bytes(largest set) bytes.
 hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, const Segs &sg,
-                                 uint32_t max_n, int bits, uint32_t *perm, uint32_t *scratch_keys,
-                                 uint32_t *scratch_vals, uint32_t N);
+                                 const uint32_t *host_first, uint32_t *perm, void *scratch);
+size_t sort_scratch_bytes(uint32_t max_n);
 
 struct LayoutMeta {  // totals written by layout_meta, read by the host
   unsigned long long err;
@@ -189,7 +191,7 @@ hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32
                               uint32_t *hi_off, uint64_t *grp_off, uint32_t *grp_len,
                               uint64_t *ghi_off, uint32_t *ghi_len,
                               uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta,
-                              void *scratch);
+                              void *scratch);  // meta must be zeroed beforehand
 // scratch bytes launch_layout_meta needs
 size_t layout_meta_scratch_bytes(uint32_t N, uint32_t RB);
 
@@ -211,6 +213,16 @@ hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairT
 hipError_t launch_rank_finalize(hipStream_t st, const Segs &sg, uint32_t N, double delta,
                                 double *ranks);
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);
+struct FillJob {  // n 64-bit words at p set to v
+  unsigned long long *p;
+  uint64_t n;
+  unsigned long long v;
+};
+struct FillJobs {
+  FillJob j[4];
+  uint32_t n;
+};
+hipError_t launch_fills(hipStream_t st, const FillJobs &jobs);  // all jobs in one launch
 
 hipError_t launch_similarity(hipStream_t st, const SetView &v, const uint32_t *rowpos,
                              uint32_t nr, const uint32_t *colpos, uint32_t nc,

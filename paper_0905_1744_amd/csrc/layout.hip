@@ -10,7 +10,10 @@
 //  * entries with count >= 2 are kept in a separate short CSR list;
 //  * every row block of 16 sequences gets the merged, sorted set of words
 //    that some row of the block holds at least twice, with the 16 counts.
+#include <algorithm>
+
 #include "radix.h"
+#include "tilerank.h"
 
 namespace kd {
 
@@ -59,49 +62,42 @@ __global__ __launch_bounds__(1024) void sort_small_kernel(const uint32_t *__rest
   for (uint32_t t = threadIdx.x; t < n; t += 1024) perm[a + t] = sk[t] & 0x7FFFu;
 }
 
-// Larger sets: one workgroup per set, stable radix sort of the keys with
-// their local indices as values.
-__global__ __launch_bounds__(1024) void sort_u32_index_kernel(const uint32_t *__restrict__ keys,
-                                                              const uint32_t *__restrict__ seq,
-                                                              int bits,
-                                                              uint32_t *__restrict__ perm,
-                                                              uint32_t *k0, uint32_t *v0,
-                                                              uint32_t *k1, uint32_t *v1) {
-  __shared__ RadixShared<1024> sh;
-  const uint32_t a = seq[blockIdx.x], N = seq[blockIdx.x + 1] - a;
-  if (N <= kBitonicSortMax) return;
-  keys += a;
-  perm += a;
-  k0 += a;
-  v0 += a;
-  k1 += a;
-  v1 += a;
-  for (uint32_t i = threadIdx.x; i < N; i += 1024) {
-    k0[i] = keys[i];
-    v0[i] = i;
-  }
-  __syncthreads();
-  const int where = block_radix_sort<1024, uint32_t>(k0, v0, k1, v1, N, 0, bits, sh);
-  const uint32_t *src = where ? v1 : v0;
-  for (uint32_t i = threadIdx.x; i < N; i += 1024) perm[i] = src[i];
+// Larger sets: each key's position in the stable order comes from ranking
+// it against sorted tiles of the set's keys (tilerank.h), then a scatter.
+struct SetKeyOf {
+  const uint32_t *keys;
+  __device__ unsigned long long operator()(uint32_t i) const { return keys[i]; }
+};
+
+__global__ __launch_bounds__(256) void scatter_perm_kernel(uint32_t n, const uint32_t *__restrict__ rank,
+                                                           uint32_t *__restrict__ perm) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i < n) perm[rank[i]] = i;
 }
 
 hipError_t launch_sort_u32_index(hipStream_t st, const uint32_t *keys, const Segs &sg,
-                                 uint32_t max_n, int bits, uint32_t *perm, uint32_t *scratch_keys,
-                                 uint32_t *scratch_vals, uint32_t N) {
-  if (N == 0) return hipSuccess;
-  if (bits > 16) return hipErrorInvalidValue;  // the bitonic keys hold 16 bits of key
+                                 const uint32_t *host_first, uint32_t *perm, void *scratch) {
+  uint32_t max_n = 0;
+  for (uint32_t q = 0; q < sg.nsets; q++) max_n = std::max(max_n, host_first[q + 1] - host_first[q]);
+  if (max_n == 0) return hipSuccess;
   const uint32_t small_max = max_n < kBitonicSortMax ? max_n : kBitonicSortMax;
   hipLaunchKernelGGL(sort_small_kernel, dim3(sg.nsets), dim3(1024),
                      sizeof(uint32_t) * pow2_at_least(small_max), st, keys, sg.seq, perm);
   KD_HIP(hipGetLastError());
-  if (max_n > kBitonicSortMax) {
-    hipLaunchKernelGGL(sort_u32_index_kernel, dim3(sg.nsets), dim3(1024), 0, st, keys, sg.seq,
-                       bits, perm, scratch_keys, scratch_vals, scratch_keys + N, scratch_vals + N);
+  if (max_n <= kBitonicSortMax) return hipSuccess;
+  KeyIdx *sorted = static_cast<KeyIdx *>(scratch);
+  uint32_t *rank = reinterpret_cast<uint32_t *>(sorted + max_n);
+  for (uint32_t q = 0; q < sg.nsets; q++) {
+    const uint32_t a = host_first[q], n = host_first[q + 1] - a;
+    if (n <= kBitonicSortMax) continue;
+    KD_HIP(launch_tile_rank(st, SetKeyOf{keys + a}, n, sorted, rank));
+    hipLaunchKernelGGL(scatter_perm_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, rank, perm + a);
     KD_HIP(hipGetLastError());
   }
   return hipSuccess;
 }
+
+size_t sort_scratch_bytes(uint32_t max_n) { return (sizeof(KeyIdx) + 4) * (size_t)max_n + 256; }
 
 // Per sorted position: inverse permutation, K, 1/K, D and the count of
 // entries seen at least twice (into hcount).  perm and inv hold indices
@@ -274,7 +270,6 @@ hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32
   J.j[1] = {grp_len, G, 64u, nullptr, grp_off};
   J.j[2] = {ghi_len, G, 64u, nullptr, ghi_off};
   J.j[3] = {rbcnt, RB, 1u, exc_off, nullptr};
-  KD_HIP(launch_fill_u64(st, meta, sizeof(LayoutMeta) / 8, 0ull));
   hipLaunchKernelGGL(layout_gather_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, perm,
                      Dorig, Korig, nhi_orig, inv, K, D, invK, hcount, err);
   KD_HIP(hipGetLastError());
@@ -577,6 +572,23 @@ __global__ void fill_u64_kernel(unsigned long long *p, uint64_t n, unsigned long
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (uint64_t)gridDim.x * blockDim.x)
     p[t] = value;
+}
+
+__global__ void fill_multi_kernel(FillJobs J) {
+  const FillJob f = J.j[blockIdx.y];
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < f.n;
+       t += (uint64_t)gridDim.x * blockDim.x)
+    f.p[t] = f.v;
+}
+
+hipError_t launch_fills(hipStream_t st, const FillJobs &J) {
+  uint64_t mx = 0;
+  for (uint32_t q = 0; q < J.n; q++) mx = std::max<uint64_t>(mx, J.j[q].n);
+  if (mx == 0) return hipSuccess;
+  uint64_t blocks = (mx + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_multi_kernel, dim3((uint32_t)blocks, J.n), dim3(256), 0, st, J);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value) {

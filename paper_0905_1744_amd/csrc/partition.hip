@@ -16,18 +16,16 @@
 //  5. bucket = number of pivots with smaller rho; bucket b starts at
 //     rho(pivot_{b-1}) + 1 in the key order.
 //
-// Sets of at most kCountRankMax keys take a fully parallel route instead:
-// rho_i = #{j : (R_j, j) < (R_i, i)} is counted directly by a 2-D grid over
-// all (i, j) tiles (n^2 comparisons spread over the whole GPU), the local
-// rank of i inside its virtual block is the number of block members with
-// smaller rho, and samples / pivots / buckets follow from rho exactly as
-// above.
+// A single set takes a fully parallel route instead (up to 8192 samples):
+// rho_i = #{j : (R_j, j) < (R_i, i)} comes from ranking against sorted
+// tiles of keys (tilerank.h); ranking the keys (block(i), rho_i) the same
+// way gives each key its slot in the concatenation of the locally sorted
+// blocks; samples / pivots / buckets then follow from rho exactly as above.
 #include "radix.h"
+#include "tilerank.h"
 
 namespace kd {
 
-constexpr uint32_t kCountRankMax = 32768;
-constexpr uint32_t kRhoChunk = 2048;  // j values per workgroup of the counting grid
 
 __device__ __forceinline__ unsigned long long rank_key(double r) {
   if (r == 0.0) r = 0.0;  // -0 and +0 are the same rank
@@ -163,52 +161,30 @@ hipError_t launch_partition_batch(hipStream_t st, const PartDesc *desc, uint32_t
   return hipGetLastError();
 }
 
-// rho[i] += #{j in this workgroup's chunk : key_j < key_i, or key_j == key_i
-// and j < i}.  A wave whose 64 indices lie wholly above (below) the chunk
-// counts key_j <= key_i (key_j < key_i) with one compare per j.
-__global__ __launch_bounds__(256) void rho_count_kernel(const double *__restrict__ R, uint32_t n,
-                                                        uint32_t *__restrict__ rho) {
-  __shared__ unsigned long long sk[kRhoChunk];
-  const uint32_t tid = threadIdx.x;
-  const uint32_t j0 = blockIdx.y * kRhoChunk, j1 = min(j0 + kRhoChunk, n);
-  for (uint32_t j = j0 + tid; j < j1; j += 256) sk[j - j0] = rank_key(R[j]);
-  __syncthreads();
-  const uint32_t i = blockIdx.x * 256u + tid;
-  const uint32_t iw0 = __builtin_amdgcn_readfirstlane(blockIdx.x * 256u + (tid & ~63u));
-  const unsigned long long ki = i < n ? rank_key(R[i]) : ~0ull;
-  const uint32_t m = j1 - j0;
-  uint32_t c = 0;
-  if (j1 <= iw0) {  // every j below every i of the wave
-    for (uint32_t q = 0; q < m; q++) c += sk[q] <= ki;
-  } else if (j0 >= iw0 + 64u) {  // every j above
-    for (uint32_t q = 0; q < m; q++) c += sk[q] < ki;
-  } else {
-    for (uint32_t q = 0; q < m; q++) {
-      const unsigned long long kj = sk[q];
-      c += (kj < ki) | ((kj == ki) & (j0 + q < i));
-    }
-  }
-  if (i < n && c) atomicAdd(&rho[i], c);
-}
+struct RankKeyOf {  // order-preserving image of the rank
+  const double *R;
+  __device__ unsigned long long operator()(uint32_t i) const { return rank_key(R[i]); }
+};
 
-// order[rho_i] = i; local rank of i in its virtual block = number of block
-// members with smaller rho; loc[lo_b + local rank] = i (the block in key
-// order, i.e. the paper's locally sorted processor list).
-__global__ __launch_bounds__(256) void local_rank_kernel(uint32_t n, uint32_t B,
-                                                         const uint32_t *__restrict__ rho,
-                                                         uint32_t *__restrict__ order,
-                                                         uint32_t *__restrict__ loc) {
+struct BlockRhoOf {  // (virtual block, rho): the locally sorted blocks, concatenated
+  const uint32_t *rho;
+  uint32_t n, B;
+  __device__ unsigned long long operator()(uint32_t i) const {
+    const uint32_t b = (uint32_t)(((unsigned long long)(i + 1) * B - 1) / n);
+    return ((unsigned long long)b << 32) | rho[i];
+  }
+};
+
+// order[rho_i] = i (the key order); loc[slot_i] = i (block by block, each
+// in key order); with a single block loc is the key order itself.
+__global__ __launch_bounds__(256) void scatter_order_kernel(uint32_t n, const uint32_t *__restrict__ rho,
+                                                            const uint32_t *__restrict__ slot,
+                                                            uint32_t *__restrict__ order,
+                                                            uint32_t *__restrict__ loc) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= n) return;
-  const uint32_t r = rho[i];
-  order[r] = i;
-  if (B == 1) return;
-  const uint32_t b = (uint32_t)(((unsigned long long)(i + 1) * B - 1) / n);
-  const uint32_t lo = (uint32_t)((unsigned long long)b * n / B);
-  const uint32_t hi = (uint32_t)((unsigned long long)(b + 1) * n / B);
-  uint32_t lr = 0;
-  for (uint32_t j = lo; j < hi; j++) lr += rho[j] < r;
-  loc[lo + lr] = i;
+  order[rho[i]] = i;
+  if (slot) loc[slot[i]] = i;
 }
 
 // Samples, their order, and the pivots / offsets (one workgroup).  The
@@ -290,22 +266,29 @@ hipError_t launch_partition(hipStream_t st, const double *ranks, uint32_t n, uin
                             uint32_t *bucket, uint32_t *order, uint32_t *offsets,
                             double *pivot_rank, uint32_t *pivot_idx, void *scratch) {
   const uint64_t S = (uint64_t)B * (B - 1);
-  if (n > kCountRankMax || S > kBitonicSamples) {
+  if (S > kBitonicSamples) {
     hipLaunchKernelGGL(partition_kernel, dim3(1), dim3(1024), 0, st, ranks, n, B, bucket, order,
                        offsets, pivot_rank, pivot_idx, scratch);
     return hipGetLastError();
   }
-  uint32_t *rho = reinterpret_cast<uint32_t *>(scratch);
-  uint32_t *loc = rho + align256(4ull * n) / 4;
-  uint32_t *prho = loc + align256(4ull * n) / 4;
-  KD_HIP(launch_fill_u64(st, rho, (n + 1) / 2, 0));
-  const uint32_t gi = (n + 255) / 256, gj = (n + kRhoChunk - 1) / kRhoChunk;
-  hipLaunchKernelGGL(rho_count_kernel, dim3(gi, gj), dim3(256), 0, st, ranks, n, rho);
+  char *p = static_cast<char *>(scratch);
+  KeyIdx *sorted = reinterpret_cast<KeyIdx *>(p);
+  p += align256(sizeof(KeyIdx) * n);
+  uint32_t *rho = reinterpret_cast<uint32_t *>(p);
+  p += align256(4ull * n);
+  uint32_t *slot = reinterpret_cast<uint32_t *>(p);
+  p += align256(4ull * n);
+  uint32_t *loc = reinterpret_cast<uint32_t *>(p);
+  p += align256(4ull * n);
+  uint32_t *prho = reinterpret_cast<uint32_t *>(p);
+  KD_HIP(launch_tile_rank(st, RankKeyOf{ranks}, n, sorted, rho));
+  if (B > 1) KD_HIP(launch_tile_rank(st, BlockRhoOf{rho, n, B}, n, sorted, slot));
+  const uint32_t gi = (n + 255) / 256;
+  hipLaunchKernelGGL(scatter_order_kernel, dim3(gi), dim3(256), 0, st, n, rho,
+                     B > 1 ? slot : nullptr, order, loc);
   KD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(local_rank_kernel, dim3(gi), dim3(256), 0, st, n, B, rho, order, loc);
-  KD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(pivots_kernel, dim3(1), dim3(1024), 0, st, ranks, n, B, rho, order, loc, prho,
-                     offsets, pivot_rank, pivot_idx);
+  hipLaunchKernelGGL(pivots_kernel, dim3(1), dim3(1024), 0, st, ranks, n, B, rho, order,
+                     B > 1 ? loc : order, prho, offsets, pivot_rank, pivot_idx);
   KD_HIP(hipGetLastError());
   hipLaunchKernelGGL(bucket_kernel, dim3(gi), dim3(256), 0, st, n, B, rho, prho, bucket);
   return hipGetLastError();
