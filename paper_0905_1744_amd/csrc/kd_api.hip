@@ -399,6 +399,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint64_t *in_off = set_alloc<uint64_t>(s, N + 1);
   uint16_t *cap_ids = set_alloc<uint16_t>(s, cap);
   uint16_t *cap_cnt = set_alloc<uint16_t>(s, cap);
+  uint32_t *hi_cap = tmp.get<uint32_t>(cap);
   uint32_t *Dorig = set_alloc<uint32_t>(s, N);
   uint32_t *perm = set_alloc<uint32_t>(s, N);
   uint32_t *inv = set_alloc<uint32_t>(s, N);
@@ -414,6 +415,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint32_t *exc_n = set_alloc<uint32_t>(s, RB);
   long long *acc = set_alloc<long long>(s, 3ull * N);
   uint32_t *segb = set_alloc<uint32_t>(s, 3ull * (nsets + 1));
+  uint32_t *segid = nsets > 1 ? set_alloc<uint32_t>(s, (uint64_t)N + G + RB) : nullptr;
 
   // temporaries
   uint32_t *Korig = tmp.get<uint32_t>(N);
@@ -427,9 +429,9 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   // [0] err, [1] nlong | nmid, [8 ..] LayoutMeta: cleared by one launch
   unsigned long long *small = tmp.get<unsigned long long>(8 + (sizeof(LayoutMeta) + 7) / 8);
   LayoutMeta *meta = reinterpret_cast<LayoutMeta *>(small + 8);
-  void *meta_tmp = tmp.get<char>(layout_meta_scratch_bytes(N, RB));
-  if (!in_off || !cap_ids || !cap_cnt || !Dorig || !perm || !inv || !K || !D || !invK || !hi_off || !hcount ||
-      !grp_off || !grp_len || !ghi_off || !ghi_len || !exc_off || !exc_n || !acc || !segb ||
+  void *meta_tmp = tmp.get<char>(layout_meta_scratch_bytes(N, G, RB));
+  if (!in_off || !cap_ids || !cap_cnt || !hi_cap || !Dorig || !perm || !inv || !K || !D || !invK || !hi_off || !hcount ||
+      !grp_off || !grp_len || !ghi_off || !ghi_len || !exc_off || !exc_n || !acc || !segb || (nsets > 1 && !segid) ||
       !Korig || !nhi_orig || !long_list || !mid_list || !sort_tmp || !small || !meta || !meta_tmp) {
     set_free(s);
     return KD_ENOMEM;
@@ -443,10 +445,15 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   sg.seq = segb;
   sg.grp = segb + (nsets + 1);
   sg.rb = segb + 2 * (nsets + 1);
+  sg.pos_set = segid;
+  sg.grp_set = segid ? segid + N : nullptr;
+  sg.rb_set = segid ? segid + N + G : nullptr;
   unsigned long long *err = small;
   uint32_t *nlong = reinterpret_cast<uint32_t *>(small + 1);  // [0] long, [1] mid
   uint32_t *nmid = nlong + 1;
   hipError_t e = upload(ctx, segb, hb.data(), sizeof(uint32_t) * hb.size());
+  if (e == hipSuccess && nsets > 1)
+    e = launch_seg_ids(st, sg, segid, segid + N, segid + N + G);
   if (e == hipSuccess) {
     FillJobs f{};
     f.j[0] = {small, 1, ~0ull};
@@ -456,7 +463,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   }
   StageTimer t_count(ctx, KD_STAGE_COUNT);
   if (e == hipSuccess)
-    e = launch_count(st, residues, offsets, in_off, N, n_residues, cap, cap_ids, cap_cnt, Dorig, Korig,
+    e = launch_count(st, residues, offsets, in_off, N, n_residues, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig,
                      nhi_orig, mid_list, nmid, long_list, nlong, err, ctx->cus);
   t_count.done();
   StageTimer t_layout(ctx, KD_STAGE_LAYOUT);
@@ -587,7 +594,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     e = launch_fills(st, f);
   }
   if (e == hipSuccess)
-    e = launch_layout_fill(st, sg, v, in_off, cap_ids, cap_cnt, gids, hi_ids, hi_cnt, ghi,
+    e = launch_layout_fill(st, sg, v, in_off, cap_ids, hi_cap, gids, hi_ids, hi_cnt, ghi,
                            (uint32_t)hm->max_len);
   if (e == hipSuccess) e = launch_exc_build(st, sg, RB, nullptr, exc_off, exc_n, exc_ids, exc_cnt);
   t_fill.done();

@@ -80,6 +80,14 @@ struct Segs {
   const uint32_t *grp;     // device [nsets+1]
   const uint32_t *rb;      // device [nsets+1]
   const SetView *views;    // device [nsets]
+  // set of each sorted position / column group / row block (device; only
+  // built when nsets > 1)
+  const uint32_t *pos_set, *grp_set, *rb_set;
+#ifdef __HIPCC__
+  __device__ uint32_t set_of_pos(uint32_t p) const { return nsets == 1 ? 0u : pos_set[p]; }
+  __device__ uint32_t set_of_grp(uint32_t x) const { return nsets == 1 ? 0u : grp_set[x]; }
+  __device__ uint32_t set_of_rb(uint32_t x) const { return nsets == 1 ? 0u : rb_set[x]; }
+#endif
 };
 
 struct PairTask {     // one workgroup's work in the rank kernel
@@ -158,11 +166,14 @@ namespace kd {
 
 // ------------------------------------------------------------ launchers
 
-// also copies the offsets into in_off (N+1 entries)
+// Per input sequence i, at capacity offset offsets[i] - 5i: distinct words
+// (cap_ids) and counts (cap_cnt) in word order, and the entries with count
+// >= 2 packed as word | count << 16 (hi_cap); D, K and the number of such
+// entries.  Also copies the offsets into in_off (N+1 entries).
 hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off, uint64_t *in_off,
                         uint32_t N, uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
-                        uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig, uint32_t *mid_list,
-                        uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
+                        uint32_t *hi_cap, uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig,
+                        uint32_t *mid_list, uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
                         unsigned long long *err, int cus);
 
 // per set s: stable sort of (key u32 < 2^16, value = local index) over the
@@ -192,12 +203,13 @@ hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32
                               uint64_t *ghi_off, uint32_t *ghi_len,
                               uint32_t *exc_off, const unsigned long long *err, LayoutMeta *meta,
                               void *scratch);  // meta must be zeroed beforehand
+
 // scratch bytes launch_layout_meta needs
-size_t layout_meta_scratch_bytes(uint32_t N, uint32_t RB);
+size_t layout_meta_scratch_bytes(uint32_t N, uint32_t G, uint32_t RB);
 
 hipError_t launch_layout_fill(hipStream_t st, const Segs &sg, const SetView &v,
                               const uint64_t *offsets,
-                              const uint16_t *cap_ids, const uint16_t *cap_cnt,
+                              const uint16_t *cap_ids, const uint32_t *hi_cap,
                               uint16_t *gids, uint16_t *hi_ids, uint16_t *hi_cnt, uint32_t *ghi,
                               uint32_t max_len);
 
@@ -213,6 +225,9 @@ hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairT
 hipError_t launch_rank_finalize(hipStream_t st, const Segs &sg, uint32_t N, double delta,
                                 double *ranks);
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);
+// writes the set ids of sg.pos_set / grp_set / rb_set (nsets > 1)
+hipError_t launch_seg_ids(hipStream_t st, const Segs &sg, uint32_t *pos_set, uint32_t *grp_set,
+                          uint32_t *rb_set);
 struct FillJob {  // n 64-bit words at p set to v
   unsigned long long *p;
   uint64_t n;
@@ -302,18 +317,6 @@ __device__ inline double fix_to_double(long long s0, long long s1, long long s2)
   double r = hi * 0x1p64 + lo;
   r *= 0x1p-72;
   return neg ? -r : r;
-}
-
-// the set holding batch-wide item x: the largest s with first[s] <= x
-// (first[0] = 0; empty sets share their bound with the next set)
-__device__ inline uint32_t seg_of(const uint32_t *first, uint32_t nsets, uint32_t x) {
-  uint32_t lo = 0, hi = nsets - 1;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) >> 1;
-    if (first[mid] <= x) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
 }
 
 __device__ inline unsigned long long lanemask_lt() {

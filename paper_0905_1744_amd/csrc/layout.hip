@@ -111,7 +111,7 @@ __global__ void layout_gather_kernel(Segs sg, uint32_t N, const uint32_t *__rest
                                      uint32_t *__restrict__ hcount, const unsigned long long *err) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= N || *err != ~0ull) return;
-  const uint32_t a = sg.seq[seg_of(sg.seq, sg.nsets, s)];
+  const uint32_t a = sg.seq[sg.set_of_pos(s)];
   const uint32_t i = a + perm[s];
   inv[i] = s - a;
   K[s] = Korig[i];
@@ -123,37 +123,50 @@ __global__ void layout_gather_kernel(Segs sg, uint32_t N, const uint32_t *__rest
 // Per batch-wide column group (one wave each): padded list length (the
 // group's longest list, i.e. its last: D ascending, rounded to 16), longest
 // count>=2 list (rounded to 4), and the count>=2 entries of each of its
-// four row blocks; sums of D and the longest padded list go to the totals.
+// four row blocks.  Each workgroup also leaves the sum of D and the longest
+// padded list of its four groups in part_ent / part_max.
 __global__ __launch_bounds__(256) void layout_groups_meta_kernel(
     Segs sg, uint32_t G, const uint32_t *__restrict__ D, const uint32_t *__restrict__ hcount,
     uint32_t *__restrict__ grp_len, uint32_t *__restrict__ ghi_len, uint32_t *__restrict__ rbcnt,
-    const unsigned long long *err, LayoutMeta *meta) {
-  const uint32_t x = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63u;
-  if (x >= G || *err != ~0ull) return;
-  const uint32_t s = seg_of(sg.grp, sg.nsets, x);
-  const uint32_t a = sg.seq[s], n = sg.seq[s + 1] - a, g = x - sg.grp[s];
-  const bool valid = 64u * g + lane < n;
-  const uint32_t h = valid ? hcount[a + 64u * g + lane] : 0u;
-  const uint32_t d = valid ? D[a + 64u * g + lane] : 0u;
-  uint32_t mh = h, md = d, rs = h;
-  unsigned long long sd = d;
+    const unsigned long long *err, unsigned long long *part_ent, unsigned long long *part_max) {
+  __shared__ unsigned long long s_ent[4], s_max[4];
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t x = blockIdx.x * 4 + w, lane = threadIdx.x & 63u;
+  if (*err != ~0ull) return;  // the same for every workgroup
+  unsigned long long sd = 0, L = 0;
+  if (x < G) {
+    const uint32_t s = sg.set_of_grp(x);
+    const uint32_t a = sg.seq[s], n = sg.seq[s + 1] - a, g = x - sg.grp[s];
+    const bool valid = 64u * g + lane < n;
+    const uint32_t h = valid ? hcount[a + 64u * g + lane] : 0u;
+    const uint32_t d = valid ? D[a + 64u * g + lane] : 0u;
+    uint32_t mh = h, md = d, rs = h;
+    sd = d;
 #pragma unroll
-  for (int o = 32; o; o >>= 1) {
-    mh = max(mh, (uint32_t)__shfl_xor((int)mh, o, 64));
-    md = max(md, (uint32_t)__shfl_xor((int)md, o, 64));
-    sd += __shfl_xor(sd, o, 64);
+    for (int o = 32; o; o >>= 1) {
+      mh = max(mh, (uint32_t)__shfl_xor((int)mh, o, 64));
+      md = max(md, (uint32_t)__shfl_xor((int)md, o, 64));
+      sd += __shfl_xor(sd, o, 64);
+    }
+#pragma unroll
+    for (int o = 8; o; o >>= 1) rs += (uint32_t)__shfl_xor((int)rs, o, 16);
+    L = (md + 15u) & ~15u;
+    if (lane == 0) {
+      grp_len[x] = (uint32_t)L;
+      ghi_len[x] = (mh + 3u) & ~3u;
+    }
+    const uint32_t rb = 4u * g + (lane >> 4);
+    if ((lane & 15u) == 0 && 16u * rb < n) rbcnt[sg.rb[s] + rb] = rs;
   }
-#pragma unroll
-  for (int o = 8; o; o >>= 1) rs += (uint32_t)__shfl_xor((int)rs, o, 16);
-  const uint32_t L = (md + 15u) & ~15u;
   if (lane == 0) {
-    grp_len[x] = L;
-    ghi_len[x] = (mh + 3u) & ~3u;
-    atomicAdd(&meta->entries, sd);
-    atomicMax(&meta->max_len, (unsigned long long)L);
+    s_ent[w] = sd;
+    s_max[w] = L;
   }
-  const uint32_t rb = 4u * g + (lane >> 4);
-  if ((lane & 15u) == 0 && 16u * rb < n) rbcnt[sg.rb[s] + rb] = rs;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part_ent[blockIdx.x] = s_ent[0] + s_ent[1] + s_ent[2] + s_ent[3];
+    part_max[blockIdx.x] = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+  }
 }
 
 // Exclusive scans of four arrays at once (y = which): hi_off over the
@@ -173,6 +186,8 @@ struct ScanJobs {
   ScanJob j[4];
   unsigned long long *part;  // [4][nblk] tile sums, then tile offsets
   uint32_t nblk;
+  uint32_t npart;            // per-workgroup group statistics
+  const unsigned long long *part_ent, *part_max;
 };
 
 __global__ __launch_bounds__(1024) void scan_tiles_kernel(ScanJobs J, const unsigned long long *err) {
@@ -198,6 +213,22 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(ScanJobs J, const unsign
   if (*err != ~0ull) {
     if (y == 0 && threadIdx.x == 0) meta->err = *err;
     return;
+  }
+  if (y == 0) {  // totals of the per-workgroup group statistics
+    unsigned long long e = 0, m = 0;
+    for (uint32_t b = threadIdx.x; b < J.npart; b += 1024) {
+      e += J.part_ent[b];
+      m = max(m, J.part_max[b]);
+    }
+#pragma unroll
+    for (int o = 32; o; o >>= 1) {
+      e += __shfl_xor(e, o, 64);
+      m = max(m, (unsigned long long)__shfl_xor(m, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&meta->entries, e);
+      atomicMax(&meta->max_len, m);
+    }
   }
   const ScanJob jb = J.j[y];
   const uint32_t nb = (jb.n + kScanTile - 1) / kScanTile;
@@ -247,9 +278,10 @@ __global__ __launch_bounds__(1024) void scan_write_kernel(ScanJobs J, const unsi
   }
 }
 
-size_t layout_meta_scratch_bytes(uint32_t N, uint32_t RB) {
+size_t layout_meta_scratch_bytes(uint32_t N, uint32_t G, uint32_t RB) {
   const uint32_t nblk = (N + kScanTile - 1) / kScanTile;
-  return 4ull * RB + 256 + 8ull * 4 * (nblk ? nblk : 1);
+  const uint64_t npart = (G + 3) / 4;
+  return 4ull * RB + 256 + 8ull * 4 * (nblk ? nblk : 1) + 16ull * npart + 256;
 }
 
 hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32_t G,
@@ -270,11 +302,16 @@ hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32
   J.j[1] = {grp_len, G, 64u, nullptr, grp_off};
   J.j[2] = {ghi_len, G, 64u, nullptr, ghi_off};
   J.j[3] = {rbcnt, RB, 1u, exc_off, nullptr};
+  const uint32_t npart = (G + 3) / 4;
+  unsigned long long *pe = J.part + 4ull * (nblk ? nblk : 1);
+  J.npart = npart;
+  J.part_ent = pe;
+  J.part_max = pe + npart;
   hipLaunchKernelGGL(layout_gather_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, perm,
                      Dorig, Korig, nhi_orig, inv, K, D, invK, hcount, err);
   KD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(layout_groups_meta_kernel, dim3((G + 3) / 4), dim3(256), 0, st, sg, G, D,
-                     hcount, grp_len, ghi_len, rbcnt, err, meta);
+  hipLaunchKernelGGL(layout_groups_meta_kernel, dim3(npart), dim3(256), 0, st, sg, G, D,
+                     hcount, grp_len, ghi_len, rbcnt, err, pe, pe + npart);
   KD_HIP(hipGetLastError());
   hipLaunchKernelGGL(scan_tiles_kernel, dim3(nblk, 4), dim3(1024), 0, st, J, err);
   KD_HIP(hipGetLastError());
@@ -284,21 +321,20 @@ hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32
   return hipGetLastError();
 }
 
-// Grid (batch-wide column group, slice of 16 chunks), 256 threads: lane
-// l = tid % 64 writes chunks 16 y + tid / 64 + 4 k (k = 0..3) of sequence
-// 64 g + l of the group's set into the interleaved layout (the 64 lanes'
-// 16-byte chunks adjacent).
+// Grid (batch-wide column group, slice y of kGroupSlices), 256 threads:
+// lane l = tid % 64 writes chunks 4 y + tid / 64 + 4 kGroupSlices k
+// (k = 0, 1, ...) of sequence 64 g + l of the group's set into the
+// interleaved layout (the 64 lanes' 16-byte chunks adjacent).
+constexpr uint32_t kGroupSlices = 4;
 __global__ __launch_bounds__(256) void layout_groups_kernel(Segs sg,
                                                             const uint64_t *__restrict__ offsets,
                                                             const uint16_t *__restrict__ cap_ids,
                                                             uint16_t *__restrict__ gids) {
   const uint32_t x = blockIdx.x, lane = threadIdx.x & 63u, sub = threadIdx.x >> 6;
-  const uint32_t set = seg_of(sg.grp, sg.nsets, x);
+  const uint32_t set = sg.set_of_grp(x);
   const SetView &v = sg.views[set];
   const uint32_t g = x - sg.grp[set];
   const uint32_t L = v.grp_len[g];
-  const uint32_t t8_0 = blockIdx.y * 16u;
-  if (t8_0 * 8u >= L) return;
   const uint32_t s = 64u * g + lane;
   uint32_t Dl = 0;
   const uint16_t *src = nullptr;
@@ -308,10 +344,7 @@ __global__ __launch_bounds__(256) void layout_groups_kernel(Segs sg,
     Dl = v.D[s];
   }
   uint4 *dst = reinterpret_cast<uint4 *>(gids + v.grp_off[g]) + lane;
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const uint32_t t8 = t8_0 + sub + 4u * k;
-    if (t8 * 8u >= L) break;
+  for (uint32_t t8 = 4u * blockIdx.y + sub; t8 * 8u < L; t8 += 4u * kGroupSlices) {
     uint32_t e[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) {
@@ -327,57 +360,44 @@ __global__ __launch_bounds__(256) void layout_groups_kernel(Segs sg,
   }
 }
 
-// One wave per batch-wide sorted position: entries with count >= 2,
-// compacted in order.
+// One thread per batch-wide sorted position: its count>=2 entries (packed,
+// from the counting pass) into the CSR lists and the group-interleaved list.
 __global__ __launch_bounds__(256) void layout_hi_kernel(Segs sg, uint32_t N,
                                                         const uint64_t *__restrict__ offsets,
-                                                        const uint16_t *__restrict__ cap_ids,
-                                                        const uint16_t *__restrict__ cap_cnt,
+                                                        const uint32_t *__restrict__ hi_cap,
                                                         uint16_t *__restrict__ hi_ids,
                                                         uint16_t *__restrict__ hi_cnt,
                                                         uint32_t *__restrict__ ghi) {
-  const uint32_t p = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const uint32_t p = blockIdx.x * 256u + threadIdx.x;
   if (p >= N) return;
-  const uint32_t set = seg_of(sg.seq, sg.nsets, p);
+  const uint32_t set = sg.set_of_pos(p);
   const SetView &v = sg.views[set];
   const uint32_t s = p - v.base;
+  const uint32_t h0 = v.hi_off[s], nh = v.hi_off[s + 1] - h0;
+  if (nh == 0) return;
   const uint32_t i = v.base + v.perm[s];
-  const uint64_t co = offsets[i] - 5ull * i;
-  const uint32_t Dl = v.D[s];
-  const uint32_t h0 = v.hi_off[s];
-  const uint64_t gb = v.ghi_off[s >> 6];
-  uint32_t o = h0;
-  for (uint32_t b = 0; b < Dl; b += 64) {
-    const uint32_t t = b + lane;
-    uint16_t id = 0, c = 0;
-    if (t < Dl) {
-      id = cap_ids[co + t];
-      c = cap_cnt[co + t];
-    }
-    const bool f = t < Dl && c >= 2;
-    const unsigned long long m = __ballot(f);
-    if (f) {
-      const uint32_t q = o + (uint32_t)__popcll(m & lanemask_lt());
-      hi_ids[q] = id;
-      hi_cnt[q] = c;
-      ghi[gb + 64ull * (q - h0) + (s & 63u)] = (uint32_t)id | ((uint32_t)c << 16);
-    }
-    o += (uint32_t)__popcll(m);
+  const uint32_t *src = hi_cap + (offsets[i] - 5ull * i);
+  uint32_t *gdst = ghi + v.ghi_off[s >> 6] + (s & 63u);
+  for (uint32_t t = 0; t < nh; t++) {
+    const uint32_t e = src[t];
+    hi_ids[h0 + t] = (uint16_t)e;
+    hi_cnt[h0 + t] = (uint16_t)(e >> 16);
+    gdst[64ull * t] = e;
   }
 }
 
 hipError_t launch_layout_fill(hipStream_t st, const Segs &sg, const SetView &v,
                               const uint64_t *offsets,
-                              const uint16_t *cap_ids, const uint16_t *cap_cnt, uint16_t *gids,
+                              const uint16_t *cap_ids, const uint32_t *hi_cap, uint16_t *gids,
                               uint16_t *hi_ids, uint16_t *hi_cnt, uint32_t *ghi,
                               uint32_t max_len) {
+  (void)max_len;
   if (v.N == 0) return hipSuccess;
-  const uint32_t slices = (max_len / 8 + 15) / 16;
-  hipLaunchKernelGGL(layout_groups_kernel, dim3(v.G, slices > 0 ? slices : 1), dim3(256), 0, st, sg,
-                     offsets, cap_ids, gids);
+  hipLaunchKernelGGL(layout_groups_kernel, dim3(v.G, kGroupSlices), dim3(256), 0, st, sg, offsets,
+                     cap_ids, gids);
   KD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(layout_hi_kernel, dim3((v.N + 3) / 4), dim3(256), 0, st, sg, v.N, offsets,
-                     cap_ids, cap_cnt, hi_ids, hi_cnt, ghi);
+  hipLaunchKernelGGL(layout_hi_kernel, dim3((v.N + 255) / 256), dim3(256), 0, st, sg, v.N, offsets,
+                     hi_cap, hi_ids, hi_cnt, ghi);
   return hipGetLastError();
 }
 
@@ -443,7 +463,7 @@ __global__ __launch_bounds__(64) void exc_build_rows_kernel(Segs sg,
   __shared__ uint16_t ust[kExcStage];
   __shared__ uint32_t roff[17];
   const uint32_t gq = blockIdx.x, lane = threadIdx.x;
-  const uint32_t set = seg_of(sg.rb, sg.nsets, gq);
+  const uint32_t set = sg.set_of_rb(gq);
   const SetView &v = sg.views[set];
   const uint32_t n = sg.seq[set + 1] - sg.seq[set];
   const uint32_t s0 = 16u * (gq - sg.rb[set]), s1 = min(s0 + 16u, n);
@@ -572,6 +592,22 @@ __global__ void fill_u64_kernel(unsigned long long *p, uint64_t n, unsigned long
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (uint64_t)gridDim.x * blockDim.x)
     p[t] = value;
+}
+
+// one workgroup per set writes its id over its positions, groups and row blocks
+__global__ __launch_bounds__(256) void seg_ids_kernel(Segs sg, uint32_t *__restrict__ pos_set,
+                                                      uint32_t *__restrict__ grp_set,
+                                                      uint32_t *__restrict__ rb_set) {
+  const uint32_t s = blockIdx.x;
+  for (uint32_t p = sg.seq[s] + threadIdx.x; p < sg.seq[s + 1]; p += 256) pos_set[p] = s;
+  for (uint32_t x = sg.grp[s] + threadIdx.x; x < sg.grp[s + 1]; x += 256) grp_set[x] = s;
+  for (uint32_t x = sg.rb[s] + threadIdx.x; x < sg.rb[s + 1]; x += 256) rb_set[x] = s;
+}
+
+hipError_t launch_seg_ids(hipStream_t st, const Segs &sg, uint32_t *pos_set, uint32_t *grp_set,
+                          uint32_t *rb_set) {
+  hipLaunchKernelGGL(seg_ids_kernel, dim3(sg.nsets), dim3(256), 0, st, sg, pos_set, grp_set, rb_set);
+  return hipGetLastError();
 }
 
 __global__ void fill_multi_kernel(FillJobs J) {

@@ -451,7 +451,7 @@ hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairT
 __global__ void rank_finalize_kernel(Segs sg, uint32_t N, double delta, double *__restrict__ ranks) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
-  const uint32_t set = seg_of(sg.seq, sg.nsets, p);
+  const uint32_t set = sg.set_of_pos(p);
   const uint32_t a = sg.seq[set], n = sg.seq[set + 1] - a;
   const SetView &v = sg.views[set];
   const long long *acc = v.acc + 3ull * (p - a);
