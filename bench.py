@@ -99,6 +99,12 @@ def bench_batched(args):
                offsets=torch.empty(nb, dtype=torch.int32, device=dev))
     ns = np.diff(first.astype(np.int64))
     pairs = float((ns * (ns - 1) // 2).sum())
+    tune = None
+    if not args.no_autotune:  # work-list shape for batches of this size class
+        kb = ctx.kmer_count_batch(res, off, first)
+        best, ms = ctx.autotune(kb, args.delta)
+        tune = {"rows_per_workgroup": best, "ms_per_shape": ms}
+        kb.destroy()
     for _ in range(args.warmup):
         ctx.batch_run(res, off, first, Bs, args.delta, out=out)
     torch.cuda.synchronize()
@@ -145,7 +151,7 @@ def bench_batched(args):
         "config": {"workload": (f"batched: {len(sets)} sets, N log-uniform [32, 2048], 4-32 families, "
                                 "lognormal length mean 300, divergence 5-30%, B = min(8, N/32), seed 4"),
                    "sets": len(sets), "sequences": Ntot, "pairs": pairs, "delta": args.delta,
-                   "step": "kd_batch_run (count + rank + split of every set)"},
+                   "step": "kd_batch_run (count + rank + split of every set)", "autotune": tune},
         "sets_per_s": len(sets) / t_batch,
         "per_set_loop": {"ms": t_loop * 1e3, "sets_per_s": len(sets) / t_loop, "pairs_per_s": pairs / t_loop},
         "speedup_vs_per_set_loop": t_loop / t_batch,
@@ -245,6 +251,8 @@ def main():
     ap.add_argument("--delta", type=float, default=0.1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default work-list shape of the rank kernel")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
                          "(calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE against known bytes)")
@@ -293,8 +301,13 @@ def main():
         part = ctx.sample_partition(R, B)
         return kset, part
 
-    for _ in range(args.warmup):
+    tune = None
+    for w in range(args.warmup):
         kset, _ = step()
+        if w == 0 and not args.no_autotune:
+            # work-list shape for this size class; later counts use it
+            best, ms = ctx.autotune(kset, delta)
+            tune = {"rows_per_workgroup": best, "ms_per_shape": ms}
         kset.destroy()
     torch.cuda.synchronize()
     ctx.enable_timing(True)
@@ -330,7 +343,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16/f64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "N": N, "B": B, "delta": delta,
-                   "step": "kmer_count + kmer_rank + sample_partition"},
+                   "step": "kmer_count + kmer_rank + sample_partition", "autotune": tune},
         "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
         "roofline": roofline,
     }

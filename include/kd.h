@@ -146,6 +146,22 @@ kd_status kmer_similarity(kd_ctx *ctx, const kd_set *set, uint32_t r0, uint32_t 
  * Errors: KD_EINVAL for delta <= 0 or not finite. */
 kd_status kmer_rank(kd_ctx *ctx, const kd_set *set, double delta, double *ranks);
 
+/* Autotuner for the rank kernel's work-list shape (how many 16-sequence row
+ * blocks one workgroup takes against its 32 column groups: more means fewer
+ * accumulator atomics, fewer means better load balance).  Times kmer_rank on
+ * `set` for each of the KD_TUNE_CANDIDATES shapes {1, 2, 4, 8, 16} (one
+ * warm-up and three timed runs each; the stream is synchronized), checks
+ * that all shapes give bit-identical ranks (KD_EDEVICE otherwise), gives the
+ * set the fastest shape and remembers it in the context for later counted
+ * objects of the same size class (power-of-two bucket of the sequence
+ * count, single sets and batches apart).
+ *   best    receives the chosen row blocks per workgroup (may be NULL)
+ *   ms_out  NULL or double[KD_TUNE_CANDIDATES]: mean milliseconds per shape */
+#define KD_TUNE_CANDIDATES 5
+kd_status kd_autotune(kd_ctx *ctx, kd_set *set, double delta, uint32_t *best, double *ms_out);
+/* Set the shape by hand for the size class of (nsets, n); rows in 1..4096. */
+kd_status kd_ctx_set_rows_per_task(kd_ctx *ctx, uint32_t nsets, uint32_t n, uint32_t rows);
+
 /* -------------------------------------------------------- sample_partition */
 
 /* Regular-sampling split of n ranked sequences into B buckets (Section

@@ -96,6 +96,8 @@ def lib():
         "kd_set_count": (u32, [P]),
         "sample_partition_batch": (i32, [P, P, u32, P, P, P, P, P, P, P]),
         "kd_batch_run": (i32, [P, P, P, u64, u32, P, P, C.c_double, P, P, P, P]),
+        "kd_autotune": (i32, [P, P, C.c_double, C.POINTER(u32), C.POINTER(C.c_double)]),
+        "kd_ctx_set_rows_per_task": (i32, [P, u32, u32, u32]),
         "kd_server_create": (i32, [C.c_int, C.POINTER(ServerOpts), PP]),
         "kd_server_submit": (i32, [P, C.POINTER(Job), C.POINTER(u64)]),
         "kd_server_poll": (i32, [P, C.POINTER(Done), u32, C.POINTER(u32), C.c_int64]),
@@ -245,6 +247,19 @@ class Context:
         self._check(lib().kmer_similarity(self.handle, kset.handle, r0, nr, c0, nc, _ptr(S), _ptr(Dn)),
                     "kmer_similarity")
         return (S, Dn) if denom else S
+
+    TUNE_SHAPES = (1, 2, 4, 8, 16)
+
+    def autotune(self, kset: KmerSet, delta: float = 0.1):
+        """Pick the rank kernel's work-list shape for sets of this size class
+        (kd_autotune); returns (rows per workgroup, {shape: ms})."""
+        best = C.c_uint32()
+        ms = (C.c_double * len(self.TUNE_SHAPES))()
+        self._check(lib().kd_autotune(self.handle, kset.handle, float(delta), C.byref(best), ms), "kd_autotune")
+        return int(best.value), dict(zip(self.TUNE_SHAPES, list(ms)))
+
+    def set_rows_per_task(self, nsets: int, n: int, rows: int):
+        self._check(lib().kd_ctx_set_rows_per_task(self.handle, nsets, n, rows), "kd_ctx_set_rows_per_task")
 
     def kmer_rank(self, kset: KmerSet, delta: float = 0.1, out=None):
         R = out if out is not None else torch.empty(kset.n, dtype=torch.float64, device=self.device)

@@ -317,31 +317,21 @@ extern "C" void *kd_ctx_stream(kd_ctx *ctx) { return ctx ? (void *)ctx->stream :
 namespace {
 
 // Work list of the rank kernel for one set of N sequences: strips of 32
-// column groups (two per wave of a workgroup) against runs of row blocks; a
-// row block rb only meets column groups g <= rb/4 (pairs below the
+// column groups (two per wave of a workgroup) against runs of `rbt` row
+// blocks; a row block rb only meets column groups g <= rb/4 (pairs below the
 // diagonal of the sorted order).  Strips with the longest lists first.
-void make_tasks(uint32_t N, uint32_t set_index, std::vector<PairTask> &out) {
+void make_tasks(uint32_t N, uint32_t set_index, uint32_t rbt, std::vector<PairTask> &out) {
   std::vector<PairTask> t;
   const uint32_t RB = (N + 15) / 16, G = (N + 63) / 64;
   for (uint32_t g0 = 0; g0 < G; g0 += kGroupsPerTask) {
-    for (uint32_t rb0 = 4u * g0; rb0 < RB; rb0 += kRowBlocksPerTask)
-      t.push_back({set_index, rb0, std::min(rb0 + kRowBlocksPerTask, RB), g0});
+    for (uint32_t rb0 = 4u * g0; rb0 < RB; rb0 += rbt)
+      t.push_back({set_index, rb0, std::min(rb0 + rbt, RB), g0});
   }
   std::stable_sort(t.begin(), t.end(), [](const PairTask &a, const PairTask &b) {
     if (a.g0 != b.g0) return a.g0 > b.g0;
     return a.rb1 - a.rb0 > b.rb1 - b.rb0;
   });
   out.insert(out.end(), t.begin(), t.end());
-}
-
-uint64_t ntasks_of(uint32_t nsets, const uint32_t *first) {
-  uint64_t t = 0;
-  for (uint32_t q = 0; q < nsets; q++) {
-    const uint32_t N = first[q + 1] - first[q], RB = (N + 15) / 16, G = (N + 63) / 64;
-    for (uint32_t g0 = 0; g0 < G; g0 += kGroupsPerTask)
-      t += (RB - std::min(RB, 4u * g0) + kRowBlocksPerTask - 1) / kRowBlocksPerTask;
-  }
-  return t;
 }
 
 // number of 16 x 64 tiles of a task (its share of the triangle)
@@ -353,6 +343,35 @@ uint64_t task_tiles(const PairTask &t, uint32_t G) {
     if (gmax >= t.g0) n += std::min(gmax + 1, g1) - t.g0;
   }
   return n;
+}
+
+// Rank work list of every set of a counted object; with several sets the
+// largest tasks go first (a single set keeps its own order).
+void build_task_list(const std::vector<SetView> &views, uint32_t rbt, std::vector<PairTask> &out) {
+  out.clear();
+  for (uint32_t q = 0; q < views.size(); q++) make_tasks(views[q].N, q, rbt, out);
+  if (views.size() > 1) {
+    std::vector<std::pair<uint64_t, uint32_t>> key(out.size());
+    for (size_t t = 0; t < key.size(); t++) key[t] = {task_tiles(out[t], views[out[t].set].G), (uint32_t)t};
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<uint64_t, uint32_t> &a,
+                        const std::pair<uint64_t, uint32_t> &b) { return a.first > b.first; });
+    std::vector<PairTask> sorted(key.size());
+    for (size_t t = 0; t < key.size(); t++) sorted[t] = out[key[t].second];
+    out.swap(sorted);
+  }
+}
+
+// size class of a counted object for the tuned work-list shape
+uint32_t shape_class(uint32_t nsets, uint32_t N) {
+  uint32_t c = 0;
+  while ((2u << c) <= N) c++;
+  return (nsets > 1 ? 32u : 0u) + c;
+}
+
+uint32_t rows_per_task(const kd_ctx *ctx, uint32_t nsets, uint32_t N) {
+  auto it = ctx->rbt_pref.find(shape_class(nsets, N));
+  return it != ctx->rbt_pref.end() ? it->second : kRowBlocksPerTask;
 }
 
 // Counts every set of a batch (set s = sequences first[s] .. first[s+1]-1
@@ -499,9 +518,10 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint16_t *exc_cnt = set_alloc<uint16_t>(s, 16ull * s->n_exc);
   uint32_t *ghi = set_alloc<uint32_t>(s, hm->n_ghi + 2);
   // per-set views, then the rank work list (one upload)
+  build_task_list(s->views, rows_per_task(ctx, nsets, N), s->h_tasks);
+  s->ntasks = (uint32_t)s->h_tasks.size();
   const size_t view_bytes = (sizeof(SetView) * nsets + 255) & ~(size_t)255;
-  const uint64_t task_cap = ntasks_of(nsets, first);
-  char *vt = set_alloc<char>(s, view_bytes + sizeof(PairTask) * (size_t)(task_cap + 1));
+  char *vt = set_alloc<char>(s, view_bytes + sizeof(PairTask) * (size_t)(s->ntasks + 1));
   if (!gids || !hi_ids || !hi_cnt || !exc_ids || !exc_cnt || !ghi || !vt) {
     set_free(s);
     return KD_ENOMEM;
@@ -556,26 +576,6 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   SetView *d_view = reinterpret_cast<SetView *>(vt);
   s->d_view = d_view;
   sg.views = d_view;
-  // rank work list of every set; with several sets the largest tasks go
-  // first (the per-set lists keep their own order otherwise)
-  s->h_tasks.clear();
-  for (uint32_t q = 0; q < nsets; q++) make_tasks(s->views[q].N, q, s->h_tasks);
-  if (nsets > 1) {
-    std::vector<std::pair<uint64_t, uint32_t>> key(s->h_tasks.size());
-    for (size_t t = 0; t < key.size(); t++)
-      key[t] = {task_tiles(s->h_tasks[t], s->views[s->h_tasks[t].set].G), (uint32_t)t};
-    std::stable_sort(key.begin(), key.end(),
-                     [](const std::pair<uint64_t, uint32_t> &a,
-                        const std::pair<uint64_t, uint32_t> &b) { return a.first > b.first; });
-    std::vector<PairTask> sorted(key.size());
-    for (size_t t = 0; t < key.size(); t++) sorted[t] = s->h_tasks[key[t].second];
-    s->h_tasks.swap(sorted);
-  }
-  s->ntasks = (uint32_t)s->h_tasks.size();
-  if (s->ntasks > task_cap) {  // cannot happen: ntasks_of counts what make_tasks emits
-    set_free(s);
-    return KD_EINVAL;
-  }
   s->tasks = reinterpret_cast<PairTask *>(vt + view_bytes);
   StageTimer t_fill(ctx, KD_STAGE_LAYOUT);
   {
@@ -701,6 +701,96 @@ extern "C" kd_status kmer_rank(kd_ctx *ctx, const kd_set *s, double delta, doubl
   StageTimer t2(ctx, KD_STAGE_FINALIZE);
   KD_TRY(launch_rank_finalize(st, s->segs, s->v.N, delta, ranks));
   t2.done();
+  return KD_OK;
+}
+
+// ------------------------------------------------------------ autotune
+
+extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t *best,
+                                 double *ms_out) {
+  if (!ctx || !s || s->ctx != ctx) return KD_EINVAL;
+  if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
+  static const uint32_t cand[KD_TUNE_CANDIDATES] = {1, 2, 4, 8, 16};
+  const uint32_t N = s->v.N;
+  if (N == 0) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  Scope tmp(ctx);
+  double *R = tmp.get<double>(N);
+  if (!R) return KD_ENOMEM;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  KD_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return KD_EDEVICE;
+  }
+  std::vector<double> ref(N), got(N);
+  kd_status rc = KD_OK;
+  double best_ms = 1e300;
+  uint32_t best_rbt = kRowBlocksPerTask;
+  for (int c = 0; c < KD_TUNE_CANDIDATES && rc == KD_OK; c++) {
+    // this candidate's work list, in a block of its own
+    std::vector<PairTask> tl;
+    build_task_list(s->views, cand[c], tl);
+    PairTask *d = set_alloc<PairTask>(s, tl.size() + 1);
+    if (!d) {
+      rc = KD_ENOMEM;
+      break;
+    }
+    if (upload(ctx, d, tl.data(), sizeof(PairTask) * tl.size()) != hipSuccess) {
+      rc = KD_EDEVICE;
+      break;
+    }
+    s->tasks = d;
+    s->ntasks = (uint32_t)tl.size();
+    s->h_tasks.swap(tl);
+    float ms = 0.f, tot = 0.f;
+    for (int it = 0; it < 4 && rc == KD_OK; it++) {  // one warm-up, three timed
+      if (hipEventRecord(e0, st) != hipSuccess) rc = KD_EDEVICE;
+      if (rc == KD_OK) rc = kmer_rank(ctx, s, delta, R);
+      if (rc == KD_OK && hipEventRecord(e1, st) != hipSuccess) rc = KD_EDEVICE;
+      if (rc == KD_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = KD_EDEVICE;
+      if (it > 0) tot += ms;
+    }
+    if (rc != KD_OK) break;
+    const double avg = tot / 3.0;
+    if (ms_out) ms_out[c] = avg;
+    if (hipMemcpy(c == 0 ? ref.data() : got.data(), R, 8ull * N, hipMemcpyDeviceToHost) != hipSuccess) {
+      rc = KD_EDEVICE;
+      break;
+    }
+    // the accumulation is exact: every work-list shape gives the same bits
+    if (c > 0 && std::memcmp(ref.data(), got.data(), 8ull * N) != 0) {
+      rc = KD_EDEVICE;
+      break;
+    }
+    if (avg < best_ms) {
+      best_ms = avg;
+      best_rbt = cand[c];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != KD_OK) return rc;
+  ctx->rbt_pref[shape_class(s->nsets, N)] = best_rbt;
+  // the set keeps the winner's work list
+  std::vector<PairTask> tl;
+  build_task_list(s->views, best_rbt, tl);
+  PairTask *d = set_alloc<PairTask>(s, tl.size() + 1);
+  if (!d) return KD_ENOMEM;
+  KD_TRY(upload(ctx, d, tl.data(), sizeof(PairTask) * tl.size()));
+  s->tasks = d;
+  s->ntasks = (uint32_t)tl.size();
+  s->h_tasks.swap(tl);
+  if (best) *best = best_rbt;
+  return KD_OK;
+}
+
+extern "C" kd_status kd_ctx_set_rows_per_task(kd_ctx *ctx, uint32_t nsets, uint32_t n,
+                                              uint32_t rows) {
+  if (!ctx || rows == 0 || rows > 4096) return KD_EINVAL;
+  ctx->rbt_pref[shape_class(nsets, n)] = rows;
   return KD_OK;
 }
 

@@ -96,7 +96,7 @@ struct PairTask {     // one workgroup's work in the rank kernel
   uint32_t g0;        // column groups g0 .. g0+15, one per wave
 };
 constexpr uint32_t kGroupsPerTask = 32;  // two column groups per wave
-constexpr uint32_t kRowBlocksPerTask = 4;
+constexpr uint32_t kRowBlocksPerTask = 4;  // default run of row blocks per workgroup
 constexpr size_t kGidsSlack = 16384;  // sentinel words after the last group (read-ahead)
 
 // ---------------------------------------------------------- host objects
@@ -125,6 +125,8 @@ struct kd_ctx {
   uint64_t err_seq = 0, err_pos = 0;
   int cus = 256;
   void *pinned = nullptr;         // small pinned readback area
+  // tuned row blocks per rank workgroup, by size class (kd_autotune)
+  std::map<uint32_t, uint32_t> rbt_pref;
   // pinned upload buffers: host data is staged here and copied on the
   // context's stream; a buffer is reused once its copy's event completed
   struct Staged { void *p; size_t cap; hipEvent_t ev; bool used; };

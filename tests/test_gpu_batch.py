@@ -183,3 +183,27 @@ def test_batched_workload_sampled(kd, ctx, oracle_mod):
     for q in small:
         R_or, scale = oracle_mod.rank(oracle_mod.count(sets[q]), 0.1, with_scale=True)
         assert (np.abs(parts[q][0] - R_or) <= RTOL * scale).all(), q
+
+
+def test_autotune_shapes_identical(kd, ctx):
+    """Every work-list shape gives bit-identical ranks; the tuned shape is
+    used by later counts of the same size class (single set and batch)."""
+    import torch
+    ss = synth.paper20k(2, 3000)
+    say("autotune", ss.n)
+    ks = ctx.kmer_count(ss.residues, ss.offsets.view(np.int64))
+    R0 = ctx.kmer_rank(ks, 0.1).clone()
+    best, ms = ctx.autotune(ks, 0.1)
+    assert best in ctx.TUNE_SHAPES and all(v > 0 for v in ms.values())
+    assert torch.equal(ctx.kmer_rank(ks, 0.1), R0)
+    for rows in (1, 3, 32):  # any shape, set by hand, gives the same ranks
+        ctx.set_rows_per_task(1, ss.n, rows)
+        ks2 = ctx.kmer_count(ss.residues, ss.offsets.view(np.int64))
+        assert torch.equal(ctx.kmer_rank(ks2, 0.1), R0), rows
+    sets = synth.batched(4, 40)
+    res, off, first, Bs = synth.concat(sets)
+    kb = ctx.kmer_count_batch(res, off.view(np.int64), first)
+    Rb = ctx.kmer_rank(kb, 0.1).clone()
+    best, _ = ctx.autotune(kb, 0.1)
+    kb2 = ctx.kmer_count_batch(res, off.view(np.int64), first)
+    assert torch.equal(ctx.kmer_rank(kb2, 0.1), Rb)
