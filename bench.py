@@ -34,6 +34,27 @@ WORKLOADS = {
 }
 
 
+# HBM bytes per launch of rank_pairs_kernel on the paper-scale workload from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain-copy calibration
+# (profiles/rank_pairs_paper20k.md).  Reported only while the kernel's sources
+# hash to the measured version and the same work-list shape is in use.
+TRAFFIC = {"sources": ["paper_0905_1744_amd/csrc/pair.hip", "paper_0905_1744_amd/csrc/bitcount.h",
+                       "paper_0905_1744_amd/csrc/klog.h"],
+           "sha256_16": "a2e085b7d3062025", "workload": "paper20k", "rows_per_workgroup": 2,
+           "bytes_per_launch": 837040845}
+
+
+def measured_traffic(workload, rows):
+    import hashlib
+    if workload != TRAFFIC["workload"] or rows != TRAFFIC["rows_per_workgroup"]:
+        return None
+    h = hashlib.sha256()
+    for p in TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return TRAFFIC["bytes_per_launch"] if h.hexdigest()[:16] == TRAFFIC["sha256_16"] else None
+
+
 def probe_count(D):
     """sum over unordered pairs of min(D_i, D_j) (work of walking the shorter list)."""
     import numpy as np
@@ -333,8 +354,9 @@ def main():
     pair_ms, pair_n = stages["pairs"]
     t_pair = pair_ms / max(pair_n, 1) / 1e3
     achieved = probes / t_pair / 1e12
+    rows = tune["rows_per_workgroup"] if tune else 4
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
-                "frac": achieved / PEAK_TPROBE, "traffic": None,
+                "frac": achieved / PEAK_TPROBE, "traffic": measured_traffic(args.workload, rows),
                 "kernel": "rank_pairs_kernel", "kernel_ms": t_pair * 1e3,
                 "work_per_launch": {"probes": probes, "pairs": pairs}}
     line = {
