@@ -34,7 +34,8 @@ __device__ inline uint32_t check_offsets(const uint64_t *off, uint32_t i, uint32
   return kErrNone;
 }
 
-// Counts one sequence of K <= CAP words with one workgroup of NT threads.
+// Counts one sequence of K <= CAP words with one workgroup of NT threads
+// (the second pass, for sequences too long for one wave's registers).
 //
 // Every word sets its bit in a 46656-bit LDS bitmap; a word whose bit was
 // already set is appended to a list of repeats.  Thread t then owns bitmap
@@ -190,10 +191,176 @@ __device__ __forceinline__ void count_one(const uint8_t *__restrict__ res, uint6
   }
 }
 
-// First pass, one workgroup per sequence: validates every sequence, counts
-// those of at most 1024 words (LDS sized for them), and queues longer ones
-// for the 4096-word kernel or the dense-histogram one.
-__global__ __launch_bounds__(kCountThreads) void count_short_kernel(
+// ------------------------------------------------------------------------
+// Register-resident counting of one sequence of K <= 64 E words by one
+// wave: lane l forms words E l .. E l + E - 1 from its residues (and the
+// next lane's first five), the 64 E words are sorted across the wave with
+// a bitonic network (in-register stages for partners inside a lane, lane
+// shuffles otherwise), and runs of equal words give the distinct words and
+// their counts in order.  No LDS, no barriers.
+
+// 3-bit group code of the bytes 64 + x, x = 0..31 (7: not one of the 20
+// amino acids), eight per 32-bit word
+constexpr uint32_t letter_codes(int w) {
+  uint32_t t = 0;
+  for (int k = 0; k < 8; k++) {
+    const uint8_t c = dayhoff6((uint32_t)(64 + 8 * w + k));
+    t |= (uint32_t)(c == 255 ? 7 : c) << (3 * k);
+  }
+  return t;
+}
+constexpr uint32_t kCodes0 = letter_codes(0), kCodes1 = letter_codes(1);
+constexpr uint32_t kCodes2 = letter_codes(2), kCodes3 = letter_codes(3);
+
+__device__ __forceinline__ uint32_t code_of(uint32_t r) {
+  const uint32_t x = r & 31u, w = x >> 3;
+  const uint32_t t = w == 0 ? kCodes0 : w == 1 ? kCodes1 : w == 2 ? kCodes2 : kCodes3;
+  const uint32_t c = (t >> (3u * (x & 7u))) & 7u;
+  return (r >> 5) == 2u ? c : 7u;  // only bytes 64..95 can be letters
+}
+
+constexpr uint32_t kPadWord = 0xFFFFu;  // above every word: sorts last
+
+template <int E>
+__device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint32_t i, uint64_t o0,
+                                           uint32_t n, uint64_t cap, uint16_t *__restrict__ cap_ids,
+                                           uint16_t *__restrict__ cap_cnt,
+                                           uint32_t *__restrict__ hi_cap,
+                                           uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout,
+                                           uint32_t *__restrict__ nhiout, unsigned long long *err) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t K = n - (kK - 1);
+  const uint32_t t0 = lane * E;  // first word (and residue) of this lane
+  // residues t0 .. t0 + E + 4; positions past the end read the last
+  // residue (always in bounds) and are masked, so no load is conditional
+  const uint8_t *p = res + o0;
+  uint32_t c[E + 5];
+  uint32_t bad = 0xFFFFFFFFu;
+#pragma unroll
+  for (int u = 0; u < E + 5; u++) {
+    const uint32_t t = t0 + u;
+    const uint32_t code = code_of(p[min(t, n - 1)]);
+    const bool in = t < n;
+    c[u] = in ? code : 0u;
+    bad = (in && code == 7u) ? min(bad, t) : bad;
+  }
+#pragma unroll
+  for (int o = 32; o; o >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, o, 64));
+  if (bad != 0xFFFFFFFFu) {
+    if (lane == 0) atomicMin(err, pack_err(i, kErrBadResidue, bad));
+    return;
+  }
+  uint32_t v[E];
+#pragma unroll
+  for (int s = 0; s < E; s++) {
+    const uint32_t w = c[s] * 7776u + c[s + 1] * 1296u + c[s + 2] * 216u + c[s + 3] * 36u +
+                       c[s + 4] * 6u + c[s + 5];
+    v[s] = t0 + s < K ? w : kPadWord;
+  }
+  // Bitonic sort of the 64 E words, element index x = E lane + s, in the
+  // form where every comparator puts the minimum at the lower index: each
+  // merge of size k starts by comparing x with its mirror x ^ (k - 1), then
+  // halves with x ^ j.  Partners inside a lane are register pairs; others
+  // come from lane lane ^ (partner offset / E) by a shuffle.
+#pragma unroll
+  for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t m = (j == (k >> 1)) ? (k - 1) : j;  // partner = x ^ m
+      if (m < (uint32_t)E) {
+#pragma unroll
+        for (int s = 0; s < E; s++) {
+          const int t = s ^ (int)m;
+          if (s < t) {
+            const uint32_t a = v[s], b = v[t];
+            v[s] = min(a, b);
+            v[t] = max(a, b);
+          }
+        }
+      } else {
+        // partner lane = lane ^ (m / E); the pair's top differing bit is j,
+        // so this element is the lower one when lane bit j / E is clear
+        const int lm = (int)(m / E);
+        const bool lower = (lane & (j / E)) == 0;
+        uint32_t o[E];
+#pragma unroll
+        for (int s = 0; s < E; s++) o[s] = (uint32_t)__shfl_xor((int)v[(m == j) ? s : (E - 1 - s)], lm, 64);
+#pragma unroll
+        for (int s = 0; s < E; s++) v[s] = lower ? min(v[s], o[s]) : max(v[s], o[s]);
+      }
+    }
+  }
+  // runs: a start is an element unlike its predecessor (words sit in
+  // [0, K), padding after); a run ends at the next start or at K
+  const uint32_t prev_last = (uint32_t)__shfl_up((int)v[E - 1], 1, 64);
+  uint32_t st = 0;  // bit s: element s starts a run
+#pragma unroll
+  for (int s = 0; s < E; s++) {
+    const uint32_t x = t0 + s;
+    const uint32_t pv = s ? v[s - 1] : prev_last;
+    if (x < K && (x == 0 || v[s] != pv)) st |= 1u << s;
+  }
+  // first start index in lanes above this one (suffix minimum)
+  uint32_t mine = st ? t0 + (uint32_t)(__ffs(st) - 1) : K;
+  uint32_t above = (uint32_t)__shfl_down((int)mine, 1, 64);
+  if (lane == 63) above = K;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_down((int)above, o, 64);
+    if (lane + (uint32_t)o < 64u) above = min(above, y);
+  }
+  // positions of the starts and of the count >= 2 starts
+  uint32_t cnt[E];
+  uint32_t nxt = above, ns = 0, nh = 0;
+#pragma unroll
+  for (int s = E - 1; s >= 0; s--) {
+    const uint32_t x = t0 + s;
+    cnt[s] = nxt - x;
+    if ((st >> s) & 1u) {
+      nxt = x;
+      ns++;
+      nh += cnt[s] >= 2u;
+    }
+  }
+  uint32_t ps = ns, ph = nh;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t ys = (uint32_t)__shfl_up((int)ps, o, 64);
+    const uint32_t yh = (uint32_t)__shfl_up((int)ph, o, 64);
+    if (lane >= (uint32_t)o) {
+      ps += ys;
+      ph += yh;
+    }
+  }
+  const uint32_t D = (uint32_t)__shfl((int)ps, 63, 64), NH = (uint32_t)__shfl((int)ph, 63, 64);
+  uint32_t pos = ps - ns, hpos = ph - nh;
+  const uint64_t co = o0 - 5ull * i;
+  const bool ok = (o0 >= 5ull * i) && (co + K <= cap);
+#pragma unroll
+  for (int s = 0; s < E; s++) {
+    if ((st >> s) & 1u) {
+      if (ok) {
+        cap_ids[co + pos] = (uint16_t)v[s];
+        cap_cnt[co + pos] = (uint16_t)cnt[s];
+        if (cnt[s] >= 2u) hi_cap[co + hpos] = v[s] | (cnt[s] << 16);
+      }
+      pos++;
+      hpos += cnt[s] >= 2u;
+    }
+  }
+  if (lane == 0) {
+    Dout[i] = D;
+    Kout[i] = K;
+    nhiout[i] = NH;
+  }
+}
+
+// First pass, one wave per sequence (four per workgroup): validates every
+// sequence, counts those of at most 1024 words in registers, and queues
+// longer ones for the 4096-word kernel or the dense-histogram one.
+constexpr uint32_t kWaveCountMax = 1024;
+
+__global__ __launch_bounds__(256) void count_wave_kernel(
     const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint64_t *__restrict__ in_off,
     uint32_t N, uint64_t nres,
     uint64_t cap, uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt,
@@ -201,31 +368,32 @@ __global__ __launch_bounds__(kCountThreads) void count_short_kernel(
     uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout, uint32_t *__restrict__ nhiout,
     uint32_t *__restrict__ mid_list, uint32_t *__restrict__ nmid, uint32_t *__restrict__ long_list,
     uint32_t *__restrict__ nlong, unsigned long long *err) {
-  constexpr int CAP = 1024;
-  __shared__ CountShared<CAP> sh;
-  const uint32_t i = blockIdx.x, tid = threadIdx.x;
-  for (uint32_t c = tid; c < 256; c += kCountThreads) sh.lut[c] = dayhoff6(c);
+  const uint32_t i = blockIdx.x * 4u + (threadIdx.x >> 6), lane = threadIdx.x & 63u;
+  if (i >= N) return;
   uint64_t o0, o1;
   const uint32_t code = check_offsets(off, i, N, nres, o0, o1);
   if (code != kErrNone) {
-    if (tid == 0) atomicMin(err, pack_err(i, code, 0));
+    if (lane == 0) atomicMin(err, pack_err(i, code, 0));
     return;
   }
-  if (tid == 0) {
+  if (lane == 0) {
     in_off[i] = o0;
     if (i + 1 == N) in_off[N] = o1;
   }
   const uint32_t n = (uint32_t)(o1 - o0);
   const uint32_t K = n - (kK - 1);
-  if (K > (uint32_t)CAP) {
-    if (tid == 0) {
+  if (K > kWaveCountMax) {
+    if (lane == 0) {
       if (K <= (uint32_t)kShortMax) mid_list[atomicAdd(nmid, 1u)] = i;
       else long_list[atomicAdd(nlong, 1u)] = i;
     }
     return;
   }
-  __syncthreads();
-  count_one<CAP>(res, nres, i, o0, n, cap, sh, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  if (K <= 64u) count_wave<1>(res, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  else if (K <= 128u) count_wave<2>(res, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  else if (K <= 256u) count_wave<4>(res, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  else if (K <= 512u) count_wave<8>(res, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  else count_wave<16>(res, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
 }
 
 // Sequences of 1025..4096 words, queued by the first pass.
@@ -327,7 +495,7 @@ hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off,
                         uint32_t *mid_list, uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
                         unsigned long long *err, int cus) {
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(count_short_kernel, dim3(N), dim3(kCountThreads), 0, st, res, off, in_off, N,
+  hipLaunchKernelGGL(count_wave_kernel, dim3((N + 3) / 4), dim3(256), 0, st, res, off, in_off, N,
                      nres, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig, nhi_orig, mid_list, nmid,
                      long_list, nlong, err);
   KD_HIP(hipGetLastError());

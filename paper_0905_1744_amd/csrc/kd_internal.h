@@ -279,7 +279,7 @@ hipError_t launch_partition(hipStream_t st, const double *ranks, uint32_t n, uin
 
 #ifdef __HIPCC__
 
-__host__ __device__ inline uint8_t dayhoff6(uint32_t ch) {
+__host__ __device__ constexpr uint8_t dayhoff6(uint32_t ch) {
   switch (ch) {
     case 'A': case 'G': case 'P': case 'S': case 'T': return 0;
     case 'C': return 1;
