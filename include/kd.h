@@ -72,7 +72,9 @@ void *kd_ctx_stream(kd_ctx *ctx);
 /* Stage timing.  While enabled, the context records a pair of HIP events on
  * its stream around every stage it enqueues; kd_ctx_stage_time synchronizes
  * the stream and returns the summed elapsed milliseconds and the number of
- * timed launches of one stage since the last reset. */
+ * timed launches of one stage since the last reset.  kd_ctx_enable_timing
+ * takes 0 (off), 1 (every stage) or KD_TIME_MASK | (bit per stage) to time
+ * only some stages (each timed stage costs two event records). */
 #define KD_STAGE_COUNT 0      /* kmer_count: counting kernels */
 #define KD_STAGE_LAYOUT 1     /* kmer_count: sort by distinct words, layout */
 #define KD_STAGE_PAIRS 2      /* kmer_rank: the all-pairs kernel */
@@ -80,6 +82,7 @@ void *kd_ctx_stream(kd_ctx *ctx);
 #define KD_STAGE_PARTITION 4  /* sample_partition */
 #define KD_STAGE_SIMILARITY 5 /* kmer_similarity */
 #define KD_NSTAGES 6
+#define KD_TIME_MASK 0x100    /* enable argument: bits 0..5 select stages */
 kd_status kd_ctx_enable_timing(kd_ctx *ctx, int enable);
 kd_status kd_ctx_stage_time(kd_ctx *ctx, int stage, double *ms, uint64_t *launches);
 kd_status kd_ctx_reset_timing(kd_ctx *ctx);

@@ -213,8 +213,12 @@ class Context:
 
     STAGES = ("count", "layout", "pairs", "finalize", "partition", "similarity")
 
-    def enable_timing(self, on: bool = True):
-        self._check(lib().kd_ctx_enable_timing(self.handle, 1 if on else 0), "kd_ctx_enable_timing")
+    def enable_timing(self, on: bool = True, stages=None):
+        """Time every stage, or only the named ones (each costs two events)."""
+        arg = 0
+        if on:
+            arg = 1 if stages is None else 0x100 | sum(1 << self.STAGES.index(n) for n in stages)
+        self._check(lib().kd_ctx_enable_timing(self.handle, arg), "kd_ctx_enable_timing")
 
     def reset_timing(self):
         self._check(lib().kd_ctx_reset_timing(self.handle), "kd_ctx_reset_timing")

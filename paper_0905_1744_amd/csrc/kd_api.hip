@@ -141,7 +141,7 @@ struct StageTimer {
     return e;
   }
   StageTimer(kd_ctx *c, int s) : ctx(c), stage(s) {
-    if (!ctx->timing) return;
+    if (!((ctx->timing >> s) & 1u)) return;
     a = take(ctx);
     b = take(ctx);
     if (!a || !b || hipEventRecord(a, ctx->stream) != hipSuccess) {
@@ -220,7 +220,9 @@ void drain_timing(kd_ctx *ctx) {
 
 extern "C" kd_status kd_ctx_enable_timing(kd_ctx *ctx, int enable) {
   if (!ctx) return KD_EINVAL;
-  ctx->timing = enable != 0;
+  if (enable == 0) ctx->timing = 0;
+  else if (enable & KD_TIME_MASK) ctx->timing = (uint32_t)enable & ((1u << KD_NSTAGES) - 1u);
+  else ctx->timing = (1u << KD_NSTAGES) - 1u;
   return KD_OK;
 }
 
@@ -374,6 +376,30 @@ uint32_t rows_per_task(const kd_ctx *ctx, uint32_t nsets, uint32_t N) {
   return it != ctx->rbt_pref.end() ? it->second : kRowBlocksPerTask;
 }
 
+// The device work list of a single set of N sequences with `rbt` row
+// blocks per workgroup, built once per context and shape.
+kd_status cached_tasks(kd_ctx *ctx, uint32_t N, uint32_t rbt, PairTask **d, uint32_t *n) {
+  const auto key = std::make_pair(N, rbt);
+  auto it = ctx->task_cache.find(key);
+  if (it == ctx->task_cache.end()) {
+    std::vector<PairTask> tl;
+    std::vector<SetView> one(1);
+    one[0].N = N;
+    one[0].G = (N + 63) / 64;
+    build_task_list(one, rbt, tl);
+    PairTask *p = static_cast<PairTask *>(ctx->pool->alloc(sizeof(PairTask) * (tl.size() + 1)));
+    if (!p) return KD_ENOMEM;
+    if (upload(ctx, p, tl.data(), sizeof(PairTask) * tl.size()) != hipSuccess) {
+      ctx->pool->free(p);
+      return KD_EDEVICE;
+    }
+    it = ctx->task_cache.emplace(key, std::make_pair(p, (uint32_t)tl.size())).first;
+  }
+  *d = it->second.first;
+  *n = it->second.second;
+  return KD_OK;
+}
+
 // Counts every set of a batch (set s = sequences first[s] .. first[s+1]-1
 // of the input) and lays all of them out in one pass of each kernel.
 kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
@@ -477,7 +503,8 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     FillJobs f{};
     f.j[0] = {small, 1, ~0ull};
     f.j[1] = {small + 1, 7 + (sizeof(LayoutMeta) + 7) / 8, 0ull};
-    f.n = 2;
+    f.j[2] = {reinterpret_cast<unsigned long long *>(acc), 3ull * N, 0ull};  // rank accumulators
+    f.n = 3;
     e = launch_fills(st, f);
   }
   StageTimer t_count(ctx, KD_STAGE_COUNT);
@@ -491,6 +518,20 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     e = launch_layout_meta(st, sg, N, G, RB, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hcount,
                            hi_off, grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta, meta_tmp);
   t_layout.done();
+  // the rank work list depends only on the set sizes: prepare it while the
+  // device counts (a single set's comes from the context's cache)
+  const uint32_t rbt = rows_per_task(ctx, nsets, N);
+  if (e == hipSuccess && nsets == 1) {
+    const kd_status rc = cached_tasks(ctx, N, rbt, &s->tasks, &s->ntasks);
+    if (rc != KD_OK) {
+      (void)hipStreamSynchronize(st);
+      set_free(s);
+      return rc;
+    }
+  } else {
+    build_task_list(s->views, rbt, s->h_tasks);
+    s->ntasks = (uint32_t)s->h_tasks.size();
+  }
   LayoutMeta *hm = static_cast<LayoutMeta *>(ctx->pinned);
   if (e == hipSuccess) e = hipMemcpyAsync(hm, meta, sizeof(LayoutMeta), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -517,11 +558,10 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint16_t *exc_ids = set_alloc<uint16_t>(s, s->n_exc);
   uint16_t *exc_cnt = set_alloc<uint16_t>(s, 16ull * s->n_exc);
   uint32_t *ghi = set_alloc<uint32_t>(s, hm->n_ghi + 2);
-  // per-set views, then the rank work list (one upload)
-  build_task_list(s->views, rows_per_task(ctx, nsets, N), s->h_tasks);
-  s->ntasks = (uint32_t)s->h_tasks.size();
+  // per-set views, then (batches) the rank work list: one upload
   const size_t view_bytes = (sizeof(SetView) * nsets + 255) & ~(size_t)255;
-  char *vt = set_alloc<char>(s, view_bytes + sizeof(PairTask) * (size_t)(s->ntasks + 1));
+  const size_t task_bytes = nsets > 1 ? sizeof(PairTask) * (size_t)(s->ntasks + 1) : 0;
+  char *vt = set_alloc<char>(s, view_bytes + task_bytes);
   if (!gids || !hi_ids || !hi_cnt || !exc_ids || !exc_cnt || !ghi || !vt) {
     set_free(s);
     return KD_ENOMEM;
@@ -576,12 +616,13 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   SetView *d_view = reinterpret_cast<SetView *>(vt);
   s->d_view = d_view;
   sg.views = d_view;
-  s->tasks = reinterpret_cast<PairTask *>(vt + view_bytes);
+  if (nsets > 1) s->tasks = reinterpret_cast<PairTask *>(vt + view_bytes);
   StageTimer t_fill(ctx, KD_STAGE_LAYOUT);
   {
-    std::vector<char> hv(view_bytes + sizeof(PairTask) * s->ntasks);
+    const size_t used = nsets > 1 ? view_bytes + sizeof(PairTask) * s->ntasks : sizeof(SetView);
+    std::vector<char> hv(used);
     std::memcpy(hv.data(), s->views.data(), sizeof(SetView) * nsets);
-    std::memcpy(hv.data() + view_bytes, s->h_tasks.data(), sizeof(PairTask) * s->ntasks);
+    if (nsets > 1) std::memcpy(hv.data() + view_bytes, s->h_tasks.data(), sizeof(PairTask) * s->ntasks);
     e = upload(ctx, vt, hv.data(), hv.size());
   }
   if (e == hipSuccess) {
@@ -692,15 +733,21 @@ extern "C" kd_status kmer_rank(kd_ctx *ctx, const kd_set *s, double delta, doubl
   if (!ranks) return KD_EINVAL;
   KD_TRY(hipSetDevice(ctx->device));
   const hipStream_t st = ctx->stream;
-  StageTimer t0(ctx, KD_STAGE_FINALIZE);
-  KD_TRY(launch_fill_u64(st, s->v.acc, 3ull * s->v.N, 0));
-  t0.done();
+  // the accumulators are zero here: cleared when the set was counted and by
+  // every finalize; a rank call that failed half-way leaves them dirty
+  if (!s->acc_clean) {
+    StageTimer t0(ctx, KD_STAGE_FINALIZE);
+    KD_TRY(launch_fill_u64(st, s->v.acc, 3ull * s->v.N, 0));
+    t0.done();
+  }
+  s->acc_clean = false;
   StageTimer t1(ctx, KD_STAGE_PAIRS);
   KD_TRY(launch_rank_pairs(st, s->d_view, s->tasks, s->ntasks, delta));
   t1.done();
   StageTimer t2(ctx, KD_STAGE_FINALIZE);
   KD_TRY(launch_rank_finalize(st, s->segs, s->v.N, delta, ranks));
   t2.done();
+  s->acc_clean = true;
   return KD_OK;
 }
 
@@ -775,14 +822,19 @@ extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t 
   if (rc != KD_OK) return rc;
   ctx->rbt_pref[shape_class(s->nsets, N)] = best_rbt;
   // the set keeps the winner's work list
-  std::vector<PairTask> tl;
-  build_task_list(s->views, best_rbt, tl);
-  PairTask *d = set_alloc<PairTask>(s, tl.size() + 1);
-  if (!d) return KD_ENOMEM;
-  KD_TRY(upload(ctx, d, tl.data(), sizeof(PairTask) * tl.size()));
-  s->tasks = d;
-  s->ntasks = (uint32_t)tl.size();
-  s->h_tasks.swap(tl);
+  if (s->nsets == 1) {
+    rc = cached_tasks(ctx, N, best_rbt, &s->tasks, &s->ntasks);
+    if (rc != KD_OK) return rc;
+  } else {
+    std::vector<PairTask> tl;
+    build_task_list(s->views, best_rbt, tl);
+    PairTask *d = set_alloc<PairTask>(s, tl.size() + 1);
+    if (!d) return KD_ENOMEM;
+    KD_TRY(upload(ctx, d, tl.data(), sizeof(PairTask) * tl.size()));
+    s->tasks = d;
+    s->ntasks = (uint32_t)tl.size();
+    s->h_tasks.swap(tl);
+  }
   if (best) *best = best_rbt;
   return KD_OK;
 }

@@ -127,12 +127,15 @@ struct kd_ctx {
   void *pinned = nullptr;         // small pinned readback area
   // tuned row blocks per rank workgroup, by size class (kd_autotune)
   std::map<uint32_t, uint32_t> rbt_pref;
+  // rank work lists of single sets, keyed by (N, row blocks per workgroup):
+  // they hold no pointers, so sets of the same size share one device copy
+  std::map<std::pair<uint32_t, uint32_t>, std::pair<kd::PairTask *, uint32_t>> task_cache;
   // pinned upload buffers: host data is staged here and copied on the
   // context's stream; a buffer is reused once its copy's event completed
   struct Staged { void *p; size_t cap; hipEvent_t ev; bool used; };
   std::vector<Staged> staging;
   // stage timing (kd_ctx_enable_timing)
-  bool timing = false;
+  uint32_t timing = 0;  // bit per stage
   struct Pending { int stage; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> ev_free;  // recycled timing events
@@ -151,6 +154,7 @@ struct kd_set {
   kd::PairTask *tasks = nullptr;  // rank work list of all sets (device)
   uint32_t ntasks = 0;
   std::vector<kd::PairTask> h_tasks;
+  mutable bool acc_clean = true;  // rank accumulators are zero (kmer_rank keeps them so)
   uint64_t entries = 0;   // sum of D
   uint64_t cap = 0;       // sum of K
   uint64_t n_hi = 0;      // entries with count >= 2

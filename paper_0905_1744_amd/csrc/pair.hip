@@ -454,11 +454,12 @@ __global__ void rank_finalize_kernel(Segs sg, uint32_t N, double delta, double *
   const uint32_t set = sg.set_of_pos(p);
   const uint32_t a = sg.seq[set], n = sg.seq[set + 1] - a;
   const SetView &v = sg.views[set];
-  const long long *acc = v.acc + 3ull * (p - a);
+  long long *acc = v.acc + 3ull * (p - a);
   long long l0, l1, l2;
   fix_limbs(-log(delta + 1.0), l0, l1, l2);  // the j = i term: F = 1
   const double sum = fix_to_double(acc[0] + l0, acc[1] + l1, acc[2] + l2);
   ranks[a + v.perm[p - a]] = sum / (double)n;
+  acc[0] = acc[1] = acc[2] = 0;  // cleared for the next rank launch
 }
 
 hipError_t launch_rank_finalize(hipStream_t st, const Segs &sg, uint32_t N, double delta,

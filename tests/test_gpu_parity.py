@@ -309,23 +309,29 @@ def test_end_to_end_small(kd, ctx, oracle_mod):
 
 # ------------------------------------------------------- full-size sampled
 
-@pytest.mark.parametrize("which", ["paper20k"])
+@pytest.mark.parametrize("which", ["paper20k", "large100k"])
 def test_full_size_sampled(kd, ctx, oracle_mod, which):
-    ss = synth.paper20k()
+    """The workloads at full size, as bench.py runs them: word lists of every
+    sequence bit-exact, sampled rank rows within the tolerance, sampled
+    16-row similarity blocks bit-exact, and the split of the GPU's own ranks
+    bit-exact against the oracle's split of the same ranks."""
+    ss = synth.paper20k() if which == "paper20k" else synth.large100k()
+    nrows = 24 if which == "paper20k" else 8
     L = oracle_mod.count(ss)
     say("full-size count", which, ss.n)
     kset = check_lists(kd, ctx, ss, L)
     rng = np.random.default_rng(51)
-    rows = np.sort(rng.choice(ss.n, size=24, replace=False)).astype(np.uint32)
+    rows = np.sort(rng.choice(ss.n, size=nrows, replace=False)).astype(np.uint32)
     say("full-size rank", which)
     R = ctx.kmer_rank(kset, 0.1).cpu().numpy()
     R_or, scale = oracle_mod.rank(L, 0.1, rows=rows, with_scale=True)
     check_ranks(R[rows], R_or, scale)
     say("full-size similarity", which)
-    for r0 in (0, 9990, 19984):
+    for r0 in (0, ss.n // 2 - 10, ss.n - 16):
         S = kd.u16(ctx.kmer_similarity(kset, r0, 16, 0, ss.n))
         assert np.array_equal(S, oracle_mod.similarity(L, r0, 16, 0, ss.n)[0])
     say("full-size partition", which)
     p = ctx.sample_partition(R, ss.B)
     off = kd.u32(p["offsets"])
     assert off[-1] == ss.n and np.diff(off.astype(np.int64)).max() <= 2 * math.ceil(ss.n / ss.B)
+    check_partition_equal(kd, p, oracle_mod.partition(R, ss.B), ss.B)
