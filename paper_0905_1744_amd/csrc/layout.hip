@@ -321,42 +321,60 @@ hipError_t launch_layout_meta(hipStream_t st, const Segs &sg, uint32_t N, uint32
   return hipGetLastError();
 }
 
-// Grid (batch-wide column group, slice y of kGroupSlices), 256 threads:
-// lane l = tid % 64 writes chunks 4 y + tid / 64 + 4 kGroupSlices k
-// (k = 0, 1, ...) of sequence 64 g + l of the group's set into the
-// interleaved layout (the 64 lanes' 16-byte chunks adjacent).
+// Grid (batch-wide column group, slice y of kGroupSlices), 256 threads.
+// The group's 64 lists are copied in slices of 128 words through LDS: a
+// wave reads 64 consecutive words of one list per load (coalesced), then
+// lane l writes its list's 16-byte chunks into the interleaved layout (the
+// 64 lanes' chunks adjacent: coalesced 1 KB stores).  Words past a list's
+// end are the sentinel.  Workgroup y takes slices y, y + kGroupSlices, ...
 constexpr uint32_t kGroupSlices = 4;
+constexpr uint32_t kSliceWords = 128;
+
 __global__ __launch_bounds__(256) void layout_groups_kernel(Segs sg,
                                                             const uint64_t *__restrict__ offsets,
                                                             const uint16_t *__restrict__ cap_ids,
                                                             uint16_t *__restrict__ gids) {
-  const uint32_t x = blockIdx.x, lane = threadIdx.x & 63u, sub = threadIdx.x >> 6;
+  __shared__ uint16_t buf[64][kSliceWords + 8];  // padded rows: 16-byte reads stay aligned
+  __shared__ const uint16_t *src[64];
+  __shared__ uint32_t len[64];
+  const uint32_t x = blockIdx.x, tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t set = sg.set_of_grp(x);
   const SetView &v = sg.views[set];
   const uint32_t g = x - sg.grp[set];
   const uint32_t L = v.grp_len[g];
-  const uint32_t s = 64u * g + lane;
-  uint32_t Dl = 0;
-  const uint16_t *src = nullptr;
-  if (s < v.N) {
-    const uint32_t i = v.base + v.perm[s];
-    src = cap_ids + (offsets[i] - 5ull * i);
-    Dl = v.D[s];
-  }
-  uint4 *dst = reinterpret_cast<uint4 *>(gids + v.grp_off[g]) + lane;
-  for (uint32_t t8 = 4u * blockIdx.y + sub; t8 * 8u < L; t8 += 4u * kGroupSlices) {
-    uint32_t e[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      const uint32_t t = t8 * 8 + u;
-      e[u] = t < Dl ? src[t] : kSentinel;
+  if (blockIdx.y * kSliceWords >= L) return;  // uniform: nothing for this workgroup
+  if (tid < 64) {
+    const uint32_t s = 64u * g + tid;
+    src[tid] = nullptr;
+    len[tid] = 0;
+    if (s < v.N) {
+      const uint32_t i = v.base + v.perm[s];
+      src[tid] = cap_ids + (offsets[i] - 5ull * i);
+      len[tid] = v.D[s];
     }
-    uint4 q;
-    q.x = e[0] | (e[1] << 16);
-    q.y = e[2] | (e[3] << 16);
-    q.z = e[4] | (e[5] << 16);
-    q.w = e[6] | (e[7] << 16);
-    dst[(size_t)t8 * 64] = q;
+  }
+  __syncthreads();
+  uint4 *dst = reinterpret_cast<uint4 *>(gids + v.grp_off[g]);
+  for (uint32_t t0 = blockIdx.y * kSliceWords; t0 < L; t0 += kGroupSlices * kSliceWords) {
+    // wave w loads lists w, w + 4, ...: 64 words per instruction, two per list
+#pragma unroll 4
+    for (uint32_t r = wave; r < 64; r += 4) {
+      const uint16_t *sp = src[r];
+      const uint32_t n = len[r];
+#pragma unroll
+      for (uint32_t h = 0; h < kSliceWords; h += 64) {
+        const uint32_t t = t0 + h + lane;
+        buf[r][h + lane] = t < n ? sp[t] : kSentinel;
+      }
+    }
+    __syncthreads();
+    // lane l = list l; wave w writes chunks w, w + 4, ... of the slice
+    const uint32_t nch = min(kSliceWords, L - t0) / 8;  // L is a multiple of 16
+    for (uint32_t c = wave; c < nch; c += 4) {
+      const uint4 q = *reinterpret_cast<const uint4 *>(&buf[lane][8 * c]);
+      dst[(size_t)(t0 / 8 + c) * 64 + lane] = q;
+    }
+    __syncthreads();
   }
 }
 
