@@ -16,7 +16,9 @@
  *    On error nothing is returned through `out` parameters; output arrays
  *    are left unspecified only where the description says so.
  *  - One context per host thread.  Contexts are not internally synchronized
- *    (the server object below is).
+ *    (the server object below is).  A counted set belongs to the context
+ *    that counted it: every call taking a set and a context requires that
+ *    context (KD_EINVAL otherwise).
  *  - Alphabet and word length: k = 6 over the Dayhoff-6 grouping of the 20
  *    standard amino acids {AGPST}{C}{DENQ}{FWY}{HKR}{ILMV}; word w of a
  *    sequence is the base-6 number of the group codes of residues w..w+5,

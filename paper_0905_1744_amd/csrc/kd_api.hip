@@ -681,14 +681,15 @@ extern "C" void kd_set_destroy(kd_set *s) {
 
 extern "C" kd_status kd_set_export_lists(kd_ctx *ctx, const kd_set *s, uint16_t *ids,
                                          uint16_t *counts, uint64_t *off) {
-  if (!ctx || !s || !off || (s->entries && (!ids || !counts))) return KD_EINVAL;
+  if (!ctx || !s || s->ctx != ctx || !off || (s->entries && (!ids || !counts))) return KD_EINVAL;
   KD_TRY(hipSetDevice(ctx->device));
   return from_hip(launch_export_lists(ctx->stream, s, ids, counts, off));
 }
 
 extern "C" kd_status kd_set_export_dense(kd_ctx *ctx, const kd_set *s, uint32_t first,
                                          uint32_t count, uint16_t *out) {
-  if (!ctx || !s || (uint64_t)first + count > s->v.N || (count && !out)) return KD_EINVAL;
+  if (!ctx || !s || s->ctx != ctx || (uint64_t)first + count > s->v.N || (count && !out))
+    return KD_EINVAL;
   KD_TRY(hipSetDevice(ctx->device));
   return from_hip(launch_export_dense(ctx->stream, s, first, count, out));
 }
@@ -697,7 +698,7 @@ extern "C" kd_status kd_set_export_dense(kd_ctx *ctx, const kd_set *s, uint32_t 
 
 extern "C" kd_status kmer_similarity(kd_ctx *ctx, const kd_set *s, uint32_t r0, uint32_t nr,
                                      uint32_t c0, uint32_t nc, uint16_t *shared, uint16_t *denom) {
-  if (!ctx || !s || s->nsets != 1) return KD_EINVAL;
+  if (!ctx || !s || s->ctx != ctx || s->nsets != 1) return KD_EINVAL;
   const uint32_t N = s->v.N;
   if ((uint64_t)r0 + nr > N || (uint64_t)c0 + nc > N) return KD_EINVAL;
   if (nr == 0 || nc == 0) return KD_OK;
@@ -727,7 +728,7 @@ extern "C" kd_status kmer_similarity(kd_ctx *ctx, const kd_set *s, uint32_t r0, 
 // ------------------------------------------------------------- kmer_rank
 
 extern "C" kd_status kmer_rank(kd_ctx *ctx, const kd_set *s, double delta, double *ranks) {
-  if (!ctx || !s) return KD_EINVAL;
+  if (!ctx || !s || s->ctx != ctx) return KD_EINVAL;
   if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
   if (s->v.N == 0) return KD_OK;
   if (!ranks) return KD_EINVAL;

@@ -345,7 +345,8 @@ extern "C" kd_status kd_server_cancel(kd_server *s, uint64_t ticket) {
       q->erase(it);
       if (!was_admitted) s->reserved += j->bytes;  // finish_locked releases the charge
       s->finish_locked(j, KD_ECANCELLED, 0, now_ns());
-      s->admit_locked();
+      s->admit_locked();  // the freed budget may admit waiting jobs
+      s->cv_work.notify_one();
       s->cv_done.notify_all();
       return KD_OK;
     }

@@ -236,6 +236,14 @@ def test_rank_errors(kd, ctx):
     for d in (0.0, -1.0, float("inf"), float("nan")):
         with pytest.raises(kd.KdError):
             ctx.kmer_rank(kset, d)
+    other = kd.Context()  # a set belongs to the context that counted it
+    try:
+        with pytest.raises(kd.KdError):
+            other.kmer_rank(kset, 0.1)
+        with pytest.raises(kd.KdError):
+            other.kmer_similarity(kset, 0, 2, 0, 2)
+    finally:
+        other.close()
 
 
 # ------------------------------------------------------------ partition --
