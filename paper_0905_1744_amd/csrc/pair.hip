@@ -373,7 +373,8 @@ __device__ __forceinline__ void rank_tile(const SetView &v, RankShared &sh, uint
 }
 
 // One workgroup = 16 waves x 2 = 32 consecutive column groups g0..g0+31
-// (wave w takes g0 + w and g0 + 16 + w) against row blocks rb0..rb1-1, one
+// (wave w takes g0 + w and g0 + 31 - w: lists grow with g, so every wave
+// gets about the same total length) against row blocks rb0..rb1-1, one
 // row block at a time.  Row partials of a row block meet in LDS (exact
 // integer adds) and go to HBM once; column partials stay in registers
 // across the row blocks and go to HBM once at the end.
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(1024) void rank_pairs_kernel(const SetView *__restr
   if (tid < 48) sh.racc[tid] = 0;
   clear_rows(sh.row);
 
-  const uint32_t ga = tk.g0 + wave, gb = tk.g0 + 16u + wave;
+  const uint32_t ga = tk.g0 + wave, gb = tk.g0 + 31u - wave;
 #pragma unroll
   for (int k = 0; k < 6; k++) (&sh.colacc[wave][0][0][0])[k * 64 + lane] = 0;
 
