@@ -139,6 +139,13 @@ def bench_batched(args):
     stages = ctx.stage_times()
     ctx.enable_timing(False)
     print(f"[bench] batched: {t_batch * 1e3:.2f} ms per batch", file=sys.stderr, flush=True)
+    if args.no_loop_baseline:
+        line = {"metric": "batched k-mer rank + split: pair-similarities/s", "value": pairs / t_batch,
+                "unit": "pair-similarities/s", "ms_per_step": t_batch * 1e3, "sets": len(sets),
+                "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]}}
+        ctx.close()
+        print(json.dumps(line), flush=True)
+        return
     # per-set inputs prepared before timing (residue views, rebased offsets)
     per = []
     for q in range(len(sets)):
@@ -267,8 +274,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS) + ["batched", "served"])
     ap.add_argument("--sets", type=int, default=4096, help="batched workload: number of sets")
-    ap.add_argument("--jobs", type=int, default=200, help="served workload: jobs per arrival rate")
-    ap.add_argument("--rates", default="10,20,50,100,200,500", help="served workload: arrival rates (jobs/s)")
+    ap.add_argument("--jobs", type=int, default=300, help="served workload: jobs per arrival rate")
+    ap.add_argument("--rates", default="10,20,50,100,200,500,1000,2000,4000",
+                    help="served workload: arrival rates (jobs/s)")
+    ap.add_argument("--no-loop-baseline", action="store_true",
+                    help="batched workload: skip the per-set loop comparison (for profiling)")
     ap.add_argument("--delta", type=float, default=0.1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
