@@ -91,6 +91,22 @@ def test_count_long_sequences(kd, ctx, oracle_mod):
     check_lists(kd, ctx, ss, oracle_mod.count(ss))
 
 
+@pytest.mark.parametrize("alphabet", [b"ACDEFGHIKLMNPQRSTVWY", b"AC"])
+def test_count_path_boundaries(kd, ctx, oracle_mod, alphabet):
+    """Word counts K at every boundary of the counting paths: one wave with
+    1, 2, 4, 8 or 16 words per lane (K <= 64, 128, 256, 512, 1024), the
+    4096-word pass and the dense-histogram pass; the two-letter alphabet
+    makes almost every word repeat."""
+    rng = np.random.default_rng(24)
+    al = np.frombuffer(alphabet, dtype=np.uint8)
+    Ks = [1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025,
+          2048, 4095, 4096, 4097]
+    seqs = [al[rng.integers(0, len(al), size=k + 5)].tobytes() for k in Ks]
+    ss = synth.from_strings(seqs)
+    say("count-boundaries", alphabet[:4], len(seqs))
+    check_lists(kd, ctx, ss, oracle_mod.count(ss))
+
+
 def test_count_errors(kd, ctx):
     cases = [
         (["ACDEFGH", "ACDXFGH", "ACDEFGH"], -2, 1, 3),
@@ -98,6 +114,9 @@ def test_count_errors(kd, ctx):
         (["ACDEFGH", "ACDEFGH", "A" * 65541], -4, 2, None),
         (["ACDEFGH", "acdefgh"], -2, 1, 0),
         (["ACDEFGH", "B" * 5000], -2, 1, 0),   # bad residue on the long path
+        (["ACDEFGH" * 40, "ACDEFGH" * 40 + "Z"], -2, 1, 280),  # last residue, one-wave path
+        (["ACDEFGH" * 300 + "*" + "ACDEFGH"], -2, 0, 2100),  # the 4096-word path
+        (["ACDEFGHIK", "ACDEFGHIK" * 30, "ACDEFGHIK", "ACDEFG1"], -2, 3, 6),
     ]
     for seqs, code, seq, pos in cases:
         say("count-error", code, seq)
