@@ -299,8 +299,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": n, "launches": 3}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(the k-mer rank and split run on one device)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batched":
