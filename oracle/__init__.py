@@ -51,7 +51,7 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
         L = C.CDLL(_LIB)
         P = C.c_void_p
@@ -78,6 +78,13 @@ def lib():
         L.orc_rank_rows.restype = None
         L.orc_partition.argtypes = [P, C.c_uint32, C.c_uint32, P, P, P, P, P]
         L.orc_partition.restype = C.c_int
+        L.orc_local_ranks.argtypes = [P, P, P, P, C.c_uint32, C.c_uint32, C.c_double, P]
+        L.orc_local_ranks.restype = C.c_int
+        L.orc_global_samples.argtypes = [P, C.c_uint32, C.c_uint32, C.c_uint32, P]
+        L.orc_global_samples.restype = C.c_int
+        L.orc_global_rank_rows.argtypes = [P, P, P, P, P, C.c_uint32, P, C.c_uint32, C.c_double,
+                                           P, P]
+        L.orc_global_rank_rows.restype = None
         _lib = L
     return _lib
 
@@ -199,3 +206,41 @@ def partition(R: np.ndarray, B: int):
         raise OracleError(r)
     return dict(bucket=bucket[:N], order=order[:N], offsets=offsets[:B + 1],
                 pivot_rank=pr[:max(B - 1, 0)], pivot_idx=pi[:max(B - 1, 0)])
+
+
+def local_ranks(L: Lists, B: int, delta: float):
+    """Algorithm 2 steps 1-2: each of the B contiguous blocks ranked against
+    itself (Equation 3 restricted to the block)."""
+    out = np.zeros(max(L.n, 1), dtype=np.float64)
+    r = lib().orc_local_ranks(_p(L.ids), _p(L.cnt), _p(L.off), _p(L.K), L.n, B, delta, _p(out))
+    if r != 0:
+        raise OracleError(r)
+    return out[:L.n]
+
+
+def global_samples(local: np.ndarray, B: int, k: int):
+    """Algorithm 2 steps 3-5: k regular samples of each block's local-rank
+    order, gathered block by block (input indices)."""
+    local = np.ascontiguousarray(local, dtype=np.float64)
+    out = np.zeros(max(B * k, 1), dtype=np.uint32)
+    r = lib().orc_global_samples(_p(local), local.shape[0], B, k, _p(out))
+    if r != 0:
+        raise OracleError(r)
+    return out[:B * k]
+
+
+def global_rank(L: Lists, samples: np.ndarray, delta: float, rows=None, with_scale: bool = False):
+    """Algorithm 2 step 6: the globalized rank of the given rows (all by
+    default) against the gathered samples."""
+    samples = np.ascontiguousarray(samples, dtype=np.uint32)
+    rows = np.arange(L.n, dtype=np.uint32) if rows is None else np.ascontiguousarray(rows, dtype=np.uint32)
+    if samples.size == 0 or (samples.size and int(samples.max()) >= L.n):
+        raise OracleError(-1)
+    out = np.zeros(max(len(rows), 1), dtype=np.float64)
+    sc = np.zeros(max(len(rows), 1), dtype=np.float64)
+    lib().orc_global_rank_rows(_p(L.ids), _p(L.cnt), _p(L.off), _p(L.K), _p(samples), samples.size,
+                               _p(rows), len(rows), delta, _p(out), _p(sc))
+    if with_scale:
+        return out[:len(rows)], sc[:len(rows)]
+    return out[:len(rows)]
+

@@ -20,6 +20,9 @@
  *   bucket assignment .................... Section 3.1.2 ("Redistribution
  *                                          Based on Globalized k-mer Rank"),
  *                                          Algorithm 2 steps 3 and 8-11
+ *   local ranks, k samples per processor,
+ *   globalized rank ...................... Section 3.1.1 ("Globalised k-mer
+ *                                          Rank"), Algorithm 2 steps 1-6
  *
  * Readings where the paper is silent (alphabet, k, Delta, log base, sample
  * positions, pivot indices for odd p, ties) are fixed by the caller-visible
@@ -291,4 +294,88 @@ int orc_partition(const double *R, uint32_t N, uint32_t B, uint32_t *bucket, uin
 
     free(blk); free(smp); free(piv); free(fill);
     return ORC_OK;
+}
+
+/* ---- globalized k-mer rank (Section 3.1.1, Algorithm 2 steps 1-6) ---- */
+
+/* One d(i,j) term (Equations 1-2). */
+static double orc_pair_distance(const uint16_t *ids, const uint16_t *cnt, const uint64_t *off,
+                                const uint32_t *K, uint32_t i, uint32_t j, double delta)
+{
+    uint32_t s = orc_shared(ids + off[i], cnt + off[i], off[i + 1] - off[i],
+                            ids + off[j], cnt + off[j], off[j + 1] - off[j]);
+    uint32_t D = K[i] < K[j] ? K[i] : K[j];
+    return orc_distance(orc_fraction(s, D), delta);
+}
+
+/* Steps 1-2: processor b holds the contiguous input block
+ * [floor(bN/B), floor((b+1)N/B)) of w_b sequences and ranks each of them
+ * against its own block only: R_i = (1/w_b) sum_{j in block} d(i,j), j = i
+ * included, in increasing j with Neumaier-compensated addition. */
+int orc_local_ranks(const uint16_t *ids, const uint16_t *cnt, const uint64_t *off,
+                    const uint32_t *K, uint32_t N, uint32_t B, double delta, double *out)
+{
+    if (B == 0 || B > N) return ORC_EINVAL;
+    for (uint32_t b = 0; b < B; b++) {
+        uint64_t lo = (uint64_t)b * N / B, hi = (uint64_t)(b + 1) * N / B;
+        for (uint64_t i = lo; i < hi; i++) {
+            double sum = 0.0, comp = 0.0;
+            for (uint64_t j = lo; j < hi; j++) {
+                double d = orc_pair_distance(ids, cnt, off, K, (uint32_t)i, (uint32_t)j, delta);
+                double t = sum + d;
+                if (fabs(sum) >= fabs(d)) comp += (sum - t) + d;
+                else comp += (d - t) + sum;
+                sum = t;
+            }
+            out[i] = (sum + comp) / (double)(hi - lo);
+        }
+    }
+    return ORC_OK;
+}
+
+/* Steps 3-4: each processor sorts its block by key (local rank, index) and
+ * picks k sequences at the evenly spaced 0-based positions
+ * floor(t * w_b / (k+1)), t = 1..k (the regular-sampling rule of the split
+ * with k in place of B-1; with k = w_b every sequence is picked).  Step 5
+ * gathers them: samples[b*k + t-1] = input index, block by block.
+ * Requires 1 <= k <= w_b for every block. */
+int orc_global_samples(const double *local, uint32_t N, uint32_t B, uint32_t k, uint32_t *samples)
+{
+    if (B == 0 || B > N || k == 0) return ORC_EINVAL;
+    orc_key *blk = (orc_key *)malloc(sizeof(orc_key) * N);
+    if (!blk) return ORC_ENOMEM;
+    for (uint32_t b = 0; b < B; b++) {
+        uint64_t lo = (uint64_t)b * N / B, hi = (uint64_t)(b + 1) * N / B, w = hi - lo;
+        if (k > w) { free(blk); return ORC_EINVAL; }
+        for (uint64_t x = lo; x < hi; x++) { blk[x].r = local[x]; blk[x].i = (uint32_t)x; }
+        qsort(blk + lo, w, sizeof(orc_key), orc_key_cmp);
+        for (uint32_t t = 1; t <= k; t++)
+            samples[(uint64_t)b * k + t - 1] = blk[lo + (uint64_t)t * w / (k + 1)].i;
+    }
+    free(blk);
+    return ORC_OK;
+}
+
+/* Step 6: every sequence re-ranked against the S = k*B gathered samples,
+ * R_i = (1/S) sum_{s} d(i, samples[s]) in sample order (a sample is ranked
+ * against itself too), Neumaier-compensated; scale[q] = (1/S) sum |d|. */
+void orc_global_rank_rows(const uint16_t *ids, const uint16_t *cnt, const uint64_t *off,
+                          const uint32_t *K, const uint32_t *samples, uint32_t S,
+                          const uint32_t *rows, uint32_t nrows, double delta, double *out,
+                          double *scale)
+{
+    for (uint32_t q = 0; q < nrows; q++) {
+        uint32_t i = rows[q];
+        double sum = 0.0, comp = 0.0, mag = 0.0;
+        for (uint32_t x = 0; x < S; x++) {
+            double d = orc_pair_distance(ids, cnt, off, K, i, samples[x], delta);
+            double t = sum + d;
+            if (fabs(sum) >= fabs(d)) comp += (sum - t) + d;
+            else comp += (d - t) + sum;
+            sum = t;
+            mag += fabs(d);
+        }
+        out[q] = (sum + comp) / (double)S;
+        if (scale) scale[q] = mag / (double)S;
+    }
 }

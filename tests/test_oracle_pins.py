@@ -294,3 +294,123 @@ def test_partition_small_workload(oracle_mod):
     R = oracle_mod.rank(L, 0.1)
     p = oracle_mod.partition(R, s.B)
     _check_partition_invariants(R, s.B, p)
+
+
+# ------------------------------------------------------ globalized rank --
+
+def _global_cases():
+    cases, cur = [], None
+    for line in golden_lines("worked_global_rank.txt"):
+        k, *v = line.split()
+        if k == "case":
+            cur = {"name": v[0]}
+            cases.append(cur)
+        else:
+            cur[k] = v
+    return cases
+
+
+@pytest.mark.parametrize("case", _global_cases(), ids=lambda c: c["name"])
+def test_global_rank_worked(oracle_mod, case):
+    delta = 0.1
+    L1, L0 = -math.log1p(delta), -math.log(delta)
+    val = {"L1": L1, "L0": L0, "H": (L1 + L0) / 2}
+    ss = synth.from_strings(case["seqs"])
+    L = oracle_mod.count(ss)
+    B, k = int(case["B"][0]), int(case["k"][0])
+    loc = oracle_mod.local_ranks(L, B, delta)
+    smp = oracle_mod.global_samples(loc, B, k)
+    assert smp.tolist() == [int(x) for x in case["samples"]]
+    G = oracle_mod.global_rank(L, smp, delta)
+    np.testing.assert_allclose(G, [val[x] for x in case["global"]], rtol=1e-15, atol=0)
+
+
+def _block_bounds(N, B):
+    return [(b * N // B, (b + 1) * N // B) for b in range(B)]
+
+
+def test_local_ranks_vs_exact_sum_bruteforce(oracle_mod):
+    """Steps 1-2: Equation 3 over each block alone, summed exactly."""
+    rng = np.random.default_rng(21)
+    ss = synth.random_tiny(rng, 23, 6, 90, b"ACDEFGHIKL")
+    dense = [_dense_indep(ss.seq(i).decode()) for i in range(ss.n)]
+    n = ss.lengths()
+    delta = 0.05
+    L = oracle_mod.count(ss)
+    for B in (1, 2, 3, 5):
+        loc = oracle_mod.local_ranks(L, B, delta)
+        for lo, hi in _block_bounds(ss.n, B):
+            for i in range(lo, hi):
+                ds = [-math.log(delta + int(np.minimum(dense[i], dense[j]).sum()) / (min(n[i], n[j]) - 5))
+                      for j in range(lo, hi)]
+                assert loc[i] == pytest.approx(math.fsum(ds) / (hi - lo), rel=4e-16, abs=1e-300)
+
+
+def test_local_ranks_special_cases(oracle_mod):
+    """One block is the centralized rank; each block equals the centralized
+    rank of that block taken on its own."""
+    s = synth.small()
+    sub = synth.from_strings([s.seq(i) for i in range(70)])
+    L = oracle_mod.count(sub)
+    delta = 0.1
+    np.testing.assert_array_equal(oracle_mod.local_ranks(L, 1, delta), oracle_mod.rank(L, delta))
+    loc = oracle_mod.local_ranks(L, 4, delta)
+    for lo, hi in _block_bounds(70, 4):
+        part = oracle_mod.count(synth.from_strings([sub.seq(i) for i in range(lo, hi)]))
+        np.testing.assert_array_equal(loc[lo:hi], oracle_mod.rank(part, delta))
+
+
+def test_global_samples_rule(oracle_mod):
+    """Steps 3-5 against an independent selection: sort each block by (rank,
+    index) with Python's sort and take positions floor(t w / (k+1))."""
+    rng = np.random.default_rng(5)
+    for N, B, k in ((40, 3, 2), (97, 8, 7), (64, 4, 16), (10, 10, 1), (33, 2, 16)):
+        R = np.round(rng.random(N) * 8) / 8  # many ties, broken by index
+        smp = oracle_mod.global_samples(R, B, k)
+        want = []
+        for lo, hi in _block_bounds(N, B):
+            order = sorted(range(lo, hi), key=lambda i: (R[i], i))
+            want += [order[t * (hi - lo) // (k + 1)] for t in range(1, k + 1)]
+        assert smp.tolist() == want
+    # k = w_b takes every sequence of the block once
+    R = rng.random(60)
+    smp = oracle_mod.global_samples(R, 4, 15)
+    assert sorted(smp.tolist()) == list(range(60))
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.global_samples(R, 4, 16)   # k above a block's size
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.global_samples(R, 4, 0)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.global_samples(R, 61, 1)
+
+
+def test_global_rank_vs_exact_sum_bruteforce(oracle_mod):
+    """Step 6: Equation 3 with the gathered samples as the set (a sample is
+    one of its own terms), summed exactly."""
+    rng = np.random.default_rng(22)
+    ss = synth.random_tiny(rng, 31, 6, 80, b"ACDEFGHIKLMN")
+    dense = [_dense_indep(ss.seq(i).decode()) for i in range(ss.n)]
+    n = ss.lengths()
+    delta = 0.1
+    L = oracle_mod.count(ss)
+    smp = np.array([3, 17, 17, 0, 30, 9], dtype=np.uint32)   # any list, repeats allowed
+    G, sc = oracle_mod.global_rank(L, smp, delta, with_scale=True)
+    for i in range(ss.n):
+        ds = [-math.log(delta + int(np.minimum(dense[i], dense[j]).sum()) / (min(n[i], n[j]) - 5))
+              for j in smp.tolist()]
+        assert G[i] == pytest.approx(math.fsum(ds) / len(ds), rel=4e-16, abs=1e-300)
+        assert sc[i] == pytest.approx(math.fsum(abs(d) for d in ds) / len(ds), rel=1e-15)
+
+
+def test_global_rank_all_sampled_is_centralized(oracle_mod):
+    """With k = w_b every sequence is a sample, so the globalized rank is the
+    centralized rank (Equation 3) up to summation order."""
+    s = synth.small()
+    sub = synth.from_strings([s.seq(i) for i in range(96)])
+    L = oracle_mod.count(sub)
+    delta = 0.1
+    for B in (1, 3, 8):
+        loc = oracle_mod.local_ranks(L, B, delta)
+        smp = oracle_mod.global_samples(loc, B, 96 // B)
+        G = oracle_mod.global_rank(L, smp, delta)
+        np.testing.assert_allclose(G, oracle_mod.rank(L, delta), rtol=2e-15, atol=0)
