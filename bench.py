@@ -95,6 +95,133 @@ def cpu_baseline(ss, delta, budget_s):
     }
 
 
+def probe_count_cross(D, smp):
+    """sum over (sequence, sample) pairs of min(D_i, D_s)."""
+    import numpy as np
+    d = np.sort(np.asarray(D, dtype=np.int64))
+    ds = np.asarray(D, dtype=np.int64)[np.asarray(smp, dtype=np.int64)]
+    c = np.concatenate([[0], np.cumsum(d)])
+    k = np.searchsorted(d, ds, side="right")            # sequences with D_i <= D_s
+    return int((c[k] + ds * (d.size - k)).sum())
+
+
+def table1(Rc, G, bc, bg):
+    """The statistics of the paper's Table 1 (centralized against globalized
+    ranks) plus how many sequences both splits put in the same bucket."""
+    import numpy as np
+    diff = G - Rc
+    rc = np.argsort(np.argsort(Rc, kind="stable"), kind="stable").astype(np.float64)
+    rg = np.argsort(np.argsort(G, kind="stable"), kind="stable").astype(np.float64)
+    return {"centralized_max": float(Rc.max()), "centralized_min": float(Rc.min()),
+            "centralized_mean": float(Rc.mean()), "globalized_max": float(G.max()),
+            "globalized_min": float(G.min()), "globalized_mean": float(G.mean()),
+            "variance_wrt_centralized": float((diff ** 2).mean()),
+            "std_wrt_centralized": float(math.sqrt((diff ** 2).mean())),
+            "spearman": float(np.corrcoef(rc, rg)[0, 1]),
+            "same_bucket_frac": float((bc == bg).mean())}
+
+
+def bench_global(args):
+    """Algorithm 2 steps 1-11 on one device with the globalized rank: count
+    the B blocks as a batch, rank each block against itself, pick k = B - 1
+    samples per block, rank every sequence against the k*B samples, split."""
+    import numpy as np
+    import torch
+
+    import paper_0905_1744_amd as kd
+    import synth
+
+    which = {"global20k": "paper20k", "global100k": "large100k"}[args.workload]
+    ss = synth.paper20k() if which == "paper20k" else synth.large100k()
+    N, B, delta = ss.n, ss.B, args.delta
+    k = B - 1
+    print(f"[bench] globalized rank on {which}: N={N} B={B} k={k}", file=sys.stderr, flush=True)
+    dev = torch.device("cuda", 0)
+    res = torch.from_numpy(ss.residues).to(dev)
+    off = torch.from_numpy(ss.offsets.view(np.int64)).to(dev)
+    ctx = kd.Context(0)
+    first = kd.Context.block_bounds(N, B)
+    loc = torch.empty(N, dtype=torch.float64, device=dev)
+    G = torch.empty(N, dtype=torch.float64, device=dev)
+
+    def step():
+        kb = ctx.kmer_count_batch(res, off, first)
+        ctx.kmer_rank(kb, delta, out=loc)
+        _, smp = ctx.kmer_rank_global(kb, loc, k, delta, out=G)
+        part = ctx.sample_partition(G, B)
+        return kb, smp, part
+
+    tune = None
+    for w in range(args.warmup):
+        kb, smp, _ = step()
+        if w == 0 and not args.no_autotune:
+            best, ms = ctx.autotune(kb, delta)
+            tune = {"rows_per_workgroup": best, "ms_per_shape": ms}
+        kb.destroy()
+    ctx.enable_timing(True, stages=("pairs", "global"))
+    ctx.reset_timing()
+    kb = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        if kb is not None:
+            kb.destroy()
+        kb, smp, part = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = ctx.stage_times()
+    nb = min(args.steps, 5)
+    ctx.enable_timing(True)
+    ctx.reset_timing()
+    for _ in range(nb):
+        kb.destroy()
+        kb, smp, part = step()
+    stages = ctx.stage_times()
+    ctx.enable_timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    w = np.diff(first.astype(np.int64))
+    local_pairs = int((w * (w - 1) // 2).sum())
+    cross_pairs = N * k * B
+    value = (local_pairs + cross_pairs) / (ms_per_step / 1e3)
+    _, _, loff = kb.export_lists()
+    D = np.diff(loff.cpu().numpy())
+    probes_local = sum(probe_count(D[a:b]) for a, b in zip(first[:-1], first[1:]))
+    probes_cross = probe_count_cross(D, kd.u32(smp))
+    t_loc = st["pairs"][0] / max(st["pairs"][1], 1) / 1e3
+    t_cross = st["global"][0] / max(st["global"][1], 1) / 1e3
+
+    def roof(name, probes, pairs, t):
+        a = probes / t / 1e12
+        return {"bound": "alu", "achieved": a, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
+                "frac": a / PEAK_TPROBE, "traffic": None, "kernel": name, "kernel_ms": t * 1e3,
+                "work_per_launch": {"probes": probes, "pairs": pairs}}
+
+    # the comparison of the paper's Table 1, outside the timed region
+    kc = ctx.kmer_count(res, off)
+    Rc = ctx.kmer_rank(kc, delta)
+    pc = ctx.sample_partition(Rc, B)
+    cmp = table1(Rc.cpu().numpy(), G.cpu().numpy(), kd.u32(pc["bucket"]), kd.u32(part["bucket"]))
+    kc.destroy()
+    line = {
+        "metric": METRIC, "value": value, "unit": "pair-similarities/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16/f64",
+        "data": "synthetic",
+        "config": {"workload": "globalized rank, " + WORKLOADS[which], "N": N, "B": B, "k": k,
+                   "delta": delta, "pairs_per_step": {"local": local_pairs, "cross": cross_pairs},
+                   "step": ("kmer_count_batch (B blocks) + kmer_rank (local ranks) + "
+                            "kmer_rank_global + sample_partition"), "autotune": tune},
+        "stages_ms_per_step": {k_: v[0] / nb for k_, v in stages.items() if v[1]},
+        "roofline": roof("rank_pairs_kernel (local ranks)", probes_local, local_pairs, t_loc),
+        "roofline_cross": roof("rank_cross_kernel", probes_cross, cross_pairs, t_cross),
+        "table1": cmp,
+    }
+    kb.destroy()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def bench_batched(args):
     """Many independent sets in one call (kd_batch_run) against the plain
     per-set loop (kmer_count -> kmer_rank -> sample_partition, synchronizing
@@ -272,7 +399,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS) + ["batched", "served"])
+    ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS) + ["batched", "served", "global20k", "global100k"])
     ap.add_argument("--sets", type=int, default=4096, help="batched workload: number of sets")
     ap.add_argument("--jobs", type=int, default=300, help="served workload: jobs per arrival rate")
     ap.add_argument("--rates", default="10,20,50,100,200,500,1000,2000,4000",
@@ -308,6 +435,9 @@ def main():
         return
     if args.workload == "served":
         bench_served(args)
+        return
+    if args.workload in ("global20k", "global100k"):
+        bench_global(args)
         return
 
     import numpy as np

@@ -83,8 +83,11 @@ void *kd_ctx_stream(kd_ctx *ctx);
 #define KD_STAGE_FINALIZE 3   /* kmer_rank: accumulator clear + finalize */
 #define KD_STAGE_PARTITION 4  /* sample_partition */
 #define KD_STAGE_SIMILARITY 5 /* kmer_similarity */
-#define KD_NSTAGES 6
-#define KD_TIME_MASK 0x100    /* enable argument: bits 0..5 select stages */
+#define KD_STAGE_GLOBAL 6     /* kmer_rank_global: every sequence against the samples
+                                 (its sample choice is timed as partition, the samples'
+                                 layout as count + layout, its finalize as finalize) */
+#define KD_NSTAGES 7
+#define KD_TIME_MASK 0x100    /* enable argument: bits 0..6 select stages */
 kd_status kd_ctx_enable_timing(kd_ctx *ctx, int enable);
 kd_status kd_ctx_stage_time(kd_ctx *ctx, int stage, double *ms, uint64_t *launches);
 kd_status kd_ctx_reset_timing(kd_ctx *ctx);
@@ -234,6 +237,37 @@ kd_status kd_batch_run(kd_ctx *ctx, const uint8_t *residues, const uint64_t *off
                        uint64_t n_residues, uint32_t nsets, const uint32_t *set_first,
                        const uint32_t *set_B, double delta, double *ranks, uint32_t *bucket,
                        uint32_t *order, uint32_t *offsets_out);
+
+/* ------------------------------------------------------- globalized rank */
+
+/* Globalized k-mer rank (Section 3.1.1 "Globalised k-mer Rank"; Algorithm 2
+ * steps 3-6), the rank a processor can form without the other processors'
+ * sequences.  `blocks` is a counted batch whose sets are the processors'
+ * blocks (kmer_count_batch; a single counted set is one block), and
+ * local_ranks is kmer_rank(blocks): each sequence ranked against its own
+ * block only (steps 1-2).  Then:
+ *   3-4. each block is ordered by key (local rank, index) and the sequences
+ *        at 0-based positions floor(t w_b / (k+1)), t = 1..k, of its w_b
+ *        ordered sequences become its k samples (the split's regular
+ *        sampling rule with k in place of B-1);
+ *   5.   the k * nsets samples are gathered, block after block;
+ *   6.   every sequence is ranked against them:
+ *          R_i = (1 / S) sum_{s=1..S} d(i, sample_s),  S = k * nsets,
+ *        with d from Equations 1-2 (a sample meets itself as one of the S).
+ * The sum is accumulated exactly like kmer_rank's.  Feeding the result to
+ * sample_partition(ranks, N, B) with B = nsets finishes Algorithm 2 (steps
+ * 7-11).
+ *
+ *   local_ranks  device f64[N] (not NaN), indexed like the input sequences
+ *   k            samples per block, 1 <= k <= the smallest block's size
+ *   ranks        device f64[N]: the globalized ranks, indexed like the input
+ *   samples      device u32[k * nsets] or NULL: input indices of the samples
+ * Device memory: beside small arrays, a temporary of 4 bytes per residue of
+ * `blocks`; the stream is synchronized once.
+ * Errors: KD_EINVAL for a NULL argument, k out of range, delta <= 0 or not
+ * finite, or `blocks` counted on another context. */
+kd_status kmer_rank_global(kd_ctx *ctx, const kd_set *blocks, const double *local_ranks,
+                           uint32_t k, double delta, double *ranks, uint32_t *samples);
 
 /* ----------------------------------------------------------------- server */
 

@@ -98,6 +98,7 @@ def lib():
         "kd_batch_run": (i32, [P, P, P, u64, u32, P, P, C.c_double, P, P, P, P]),
         "kd_autotune": (i32, [P, P, C.c_double, C.POINTER(u32), C.POINTER(C.c_double)]),
         "kd_ctx_set_rows_per_task": (i32, [P, u32, u32, u32]),
+        "kmer_rank_global": (i32, [P, P, P, u32, C.c_double, P, P]),
         "kd_server_create": (i32, [C.c_int, C.POINTER(ServerOpts), PP]),
         "kd_server_submit": (i32, [P, C.POINTER(Job), C.POINTER(u64)]),
         "kd_server_poll": (i32, [P, C.POINTER(Done), u32, C.POINTER(u32), C.c_int64]),
@@ -211,7 +212,7 @@ class Context:
         except Exception:
             pass
 
-    STAGES = ("count", "layout", "pairs", "finalize", "partition", "similarity")
+    STAGES = ("count", "layout", "pairs", "finalize", "partition", "similarity", "global")
 
     def enable_timing(self, on: bool = True, stages=None):
         """Time every stage, or only the named ones (each costs two events)."""
@@ -282,6 +283,42 @@ class Context:
                                            _ptr(offsets), _ptr(pr), _ptr(pi)), "sample_partition")
         return dict(bucket=bucket[:n], order=order[:n], offsets=offsets, pivot_rank=pr[:max(B - 1, 0)],
                     pivot_idx=pi[:max(B - 1, 0)])
+
+    # ---------------------------------------------------- globalized rank
+    def kmer_rank_global(self, blocks: KmerSet, local_ranks, k: int, delta: float = 0.1, out=None):
+        """Globalized rank (Section 3.1.1; Algorithm 2 steps 3-6) of a set
+        counted block by block; local_ranks = kmer_rank(blocks).  Returns
+        (ranks, samples): samples are the k * nsets input indices picked."""
+        loc = _dev_tensor(local_ranks, torch.float64, self.device)
+        if loc.numel() != blocks.n:
+            raise ValueError(f"local_ranks: expected {blocks.n} entries, got {loc.numel()}")
+        R = out if out is not None else torch.empty(blocks.n, dtype=torch.float64, device=self.device)
+        smp = torch.empty(max(int(k) * blocks.nsets, 1), dtype=torch.int32, device=self.device)
+        self._check(lib().kmer_rank_global(self.handle, blocks.handle, _ptr(loc), int(k), float(delta),
+                                           _ptr(R), _ptr(smp)), "kmer_rank_global")
+        return R, smp[:int(k) * blocks.nsets]
+
+    @staticmethod
+    def block_bounds(n: int, B: int) -> np.ndarray:
+        """The B contiguous blocks [floor(bn/B), floor((b+1)n/B)) of Algorithm 2 step 1."""
+        return (np.arange(B + 1, dtype=np.uint64) * n // B).astype(np.uint32)
+
+    def globalized_rank(self, residues, offsets, B: int, k: int = None, delta: float = 0.1):
+        """Algorithm 2 steps 1-6 on one device: count the B blocks, rank each
+        against itself (local ranks), then every sequence against k samples
+        per block (k defaults to B - 1).  Returns dict(local, ranks, samples)."""
+        off = _dev_tensor(offsets, torch.int64, self.device)
+        n = off.numel() - 1
+        if not 1 <= B <= n:
+            raise ValueError("need 1 <= B <= number of sequences")
+        k = max(B - 1, 1) if k is None else int(k)
+        kb = self.kmer_count_batch(residues, off, self.block_bounds(n, B))
+        try:
+            loc = self.kmer_rank(kb, delta)
+            R, smp = self.kmer_rank_global(kb, loc, k, delta)
+        finally:
+            kb.destroy()
+        return dict(local=loc, ranks=R, samples=smp)
 
     # ------------------------------------------------------------ batches
     @staticmethod

@@ -401,12 +401,17 @@ kd_status cached_tasks(kd_ctx *ctx, uint32_t N, uint32_t rbt, PairTask **d, uint
 }
 
 // Counts every set of a batch (set s = sequences first[s] .. first[s+1]-1
-// of the input) and lays all of them out in one pass of each kernel.
+// of the input) and lays all of them out in one pass of each kernel.  With
+// a parent, the single set is made of the parent's sequences picks[0..N)
+// (device input indices, all distinct) instead: their lists are taken from
+// the parent, which must outlive the set, and no rank work list is built.
 kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
-                     uint32_t nsets, const uint32_t *first, uint64_t n_residues, kd_set **out) {
+                     uint32_t nsets, const uint32_t *first, uint64_t n_residues, kd_set **out,
+                     const kd_set *parent = nullptr, const uint32_t *picks = nullptr) {
   *out = nullptr;
   const uint32_t N = first[nsets];
-  if (N > 0 && (!offsets || (!residues && n_residues > 0))) return KD_EINVAL;
+  if (parent && (nsets != 1 || !picks)) return KD_EINVAL;
+  if (!parent && N > 0 && (!offsets || (!residues && n_residues > 0))) return KD_EINVAL;
   KD_TRY(hipSetDevice(ctx->device));
   kd_set *s = new (std::nothrow) kd_set;
   if (!s) return KD_ENOMEM;
@@ -438,12 +443,12 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   }
   const hipStream_t st = ctx->stream;
   const uint32_t G = s->v.G, RB = s->v.RB;
-  const uint64_t cap = n_residues >= 5ull * N ? n_residues - 5ull * N : 0;
+  const uint64_t cap = parent ? parent->cap : n_residues >= 5ull * N ? n_residues - 5ull * N : 0;
   Scope tmp(ctx);
   // set-owned arrays
   uint64_t *in_off = set_alloc<uint64_t>(s, N + 1);
-  uint16_t *cap_ids = set_alloc<uint16_t>(s, cap);
-  uint16_t *cap_cnt = set_alloc<uint16_t>(s, cap);
+  uint16_t *cap_ids = parent ? parent->cap_ids : set_alloc<uint16_t>(s, cap);
+  uint16_t *cap_cnt = parent ? parent->cap_cnt : set_alloc<uint16_t>(s, cap);
   uint32_t *hi_cap = tmp.get<uint32_t>(cap);
   uint32_t *Dorig = set_alloc<uint32_t>(s, N);
   uint32_t *perm = set_alloc<uint32_t>(s, N);
@@ -508,7 +513,10 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     e = launch_fills(st, f);
   }
   StageTimer t_count(ctx, KD_STAGE_COUNT);
-  if (e == hipSuccess)
+  if (e == hipSuccess && parent)
+    e = launch_gather_samples(st, parent->segs, parent->in_off, parent->Dorig, picks, N, in_off, Dorig,
+                              Korig, nhi_orig, hi_cap);
+  else if (e == hipSuccess)
     e = launch_count(st, residues, offsets, in_off, N, n_residues, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig,
                      nhi_orig, mid_list, nmid, long_list, nlong, err, ctx->cus);
   t_count.done();
@@ -521,7 +529,9 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   // the rank work list depends only on the set sizes: prepare it while the
   // device counts (a single set's comes from the context's cache)
   const uint32_t rbt = rows_per_task(ctx, nsets, N);
-  if (e == hipSuccess && nsets == 1) {
+  if (parent) {
+    s->ntasks = 0;
+  } else if (e == hipSuccess && nsets == 1) {
     const kd_status rc = cached_tasks(ctx, N, rbt, &s->tasks, &s->ntasks);
     if (rc != KD_OK) {
       (void)hipStreamSynchronize(st);
@@ -750,6 +760,94 @@ extern "C" kd_status kmer_rank(kd_ctx *ctx, const kd_set *s, double delta, doubl
   t2.done();
   s->acc_clean = true;
   return KD_OK;
+}
+
+// ------------------------------------------------------ kmer_rank_global
+
+namespace {
+
+kd_status plan_partition(uint32_t nsets, const uint32_t *first, const uint32_t *Bs,
+                         std::vector<PartDesc> &desc, uint64_t &scratch);
+
+// Work list of the globalized-rank pass: strips of 32 column groups (all
+// sets, batch-wide numbering) against runs of sample row blocks, with runs
+// long enough to keep the list near four workgroups per compute unit (each
+// workgroup flushes its 2048 column sums once).
+void make_cross_tasks(uint32_t Gtot, uint32_t RBs, int cus, std::vector<CrossTask> &out) {
+  out.clear();
+  const uint32_t strips = (Gtot + kGroupsPerTask - 1) / kGroupsPerTask;
+  const uint64_t cells = (uint64_t)strips * RBs;
+  const uint64_t target = 4ull * (uint64_t)std::max(cus, 1);
+  const uint32_t rbt = (uint32_t)std::max<uint64_t>(1, (cells + target - 1) / target);
+  for (uint32_t s = 0; s < strips; s++)
+    for (uint32_t rb0 = 0; rb0 < RBs; rb0 += rbt)
+      out.push_back({s * kGroupsPerTask, rb0, std::min(rb0 + rbt, RBs)});
+}
+
+}  // namespace
+
+extern "C" kd_status kmer_rank_global(kd_ctx *ctx, const kd_set *s, const double *local_ranks,
+                                      uint32_t k, double delta, double *ranks, uint32_t *samples) {
+  if (!ctx || !s || s->ctx != ctx || !local_ranks || !ranks) return KD_EINVAL;
+  if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
+  const uint32_t N = s->v.N, nb = s->nsets;
+  uint32_t wmin = N;
+  for (uint32_t q = 0; q < nb; q++) wmin = std::min(wmin, s->seq_first[q + 1] - s->seq_first[q]);
+  if (N == 0 || k == 0 || k > wmin) return KD_EINVAL;
+  const uint32_t S = k * nb;  // <= N
+  KD_TRY(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  Scope tmp(ctx);
+  StageTimer t_pick(ctx, KD_STAGE_PARTITION);
+  // steps 3-4: every block in key order (local rank, index), k samples each
+  uint32_t *order = tmp.get<uint32_t>(N);
+  uint32_t *bucket = tmp.get<uint32_t>(N);
+  uint32_t *boff = tmp.get<uint32_t>(2ull * nb);
+  uint32_t *smp = samples ? samples : tmp.get<uint32_t>(S);
+  if (!order || !bucket || !boff || !smp) return KD_ENOMEM;
+  if (nb == 1) {
+    void *scratch = tmp.get<char>(partition_scratch_bytes(N, 1));
+    if (!scratch) return KD_ENOMEM;
+    KD_TRY(launch_partition(st, local_ranks, N, 1, bucket, order, boff, nullptr, nullptr, scratch));
+  } else {
+    std::vector<uint32_t> ones(nb, 1u);
+    std::vector<PartDesc> desc;
+    uint64_t scratch_bytes = 0;
+    const kd_status rc = plan_partition(nb, s->seq_first.data(), ones.data(), desc, scratch_bytes);
+    if (rc != KD_OK) return rc;
+    void *scratch = tmp.get<char>(scratch_bytes);
+    PartDesc *d_desc = tmp.get<PartDesc>(nb);
+    if (!scratch || !d_desc) return KD_ENOMEM;
+    KD_TRY(upload(ctx, d_desc, desc.data(), sizeof(PartDesc) * nb));
+    KD_TRY(launch_partition_batch(st, d_desc, nb, local_ranks, bucket, order, boff, nullptr, nullptr,
+                                  scratch));
+  }
+  KD_TRY(launch_pick_samples(st, s->segs.seq, nb, k, order, smp));
+  t_pick.done();
+  // step 5: the samples as a set of their own (rows of the cross pass)
+  const uint32_t sfirst[2] = {0, S};
+  kd_set *ss = nullptr;
+  kd_status rc = build_sets(ctx, nullptr, nullptr, 1, sfirst, 0, &ss, s, smp);
+  if (rc != KD_OK) return rc;
+  // step 6: every sequence against the samples
+  std::vector<CrossTask> tl;
+  make_cross_tasks(s->v.G, ss->v.RB, ctx->cus, tl);
+  CrossTask *d_tasks = tmp.get<CrossTask>(tl.size() + 1);
+  hipError_t e = d_tasks ? upload(ctx, d_tasks, tl.data(), sizeof(CrossTask) * tl.size())
+                         : hipErrorOutOfMemory;
+  if (e == hipSuccess && !s->acc_clean) e = launch_fill_u64(st, s->v.acc, 3ull * N, 0);
+  s->acc_clean = false;
+  StageTimer t_cross(ctx, KD_STAGE_GLOBAL);
+  if (e == hipSuccess)
+    e = launch_rank_cross(st, s->segs, ss->d_view, d_tasks, (uint32_t)tl.size(), s->v.G, delta);
+  t_cross.done();
+  StageTimer t_fin(ctx, KD_STAGE_FINALIZE);
+  if (e == hipSuccess) e = launch_cross_finalize(st, s->segs, N, S, ranks);
+  t_fin.done();
+  if (e == hipSuccess) s->acc_clean = true;
+  kd_set_destroy(ss);  // its blocks return to the pool; stream order keeps them valid
+  if (!d_tasks) return KD_ENOMEM;
+  return from_hip(e);
 }
 
 // ------------------------------------------------------------ autotune

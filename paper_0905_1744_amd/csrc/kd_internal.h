@@ -96,6 +96,10 @@ struct PairTask {     // one workgroup's work in the rank kernel
   uint32_t g0;        // column groups g0 .. g0+15, one per wave
 };
 constexpr uint32_t kGroupsPerTask = 32;  // two column groups per wave
+struct CrossTask {    // one workgroup's work in the globalized-rank pass
+  uint32_t gx0;       // first of 32 consecutive column groups, batch-wide numbering
+  uint32_t rb0, rb1;  // row blocks [rb0, rb1) of the sample set
+};
 constexpr uint32_t kRowBlocksPerTask = 4;  // default run of row blocks per workgroup
 constexpr size_t kGidsSlack = 16384;  // sentinel words after the last group (read-ahead)
 
@@ -230,6 +234,25 @@ hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairT
                              uint32_t ntasks, double delta);
 hipError_t launch_rank_finalize(hipStream_t st, const Segs &sg, uint32_t N, double delta,
                                 double *ranks);
+// globalized rank: sample rows against every column group of `cols`
+hipError_t launch_rank_cross(hipStream_t st, const Segs &cols, const SetView *rows,
+                             const CrossTask *tasks, uint32_t ntasks, uint32_t Gtot, double delta);
+hipError_t launch_cross_finalize(hipStream_t st, const Segs &sg, uint32_t N, uint32_t S,
+                                 double *ranks);
+// samples[q*k + t-1] = first[q] + order[first[q] + floor(t w_q / (k+1))]
+// (order: each set's local indices in key order); first on the device
+hipError_t launch_pick_samples(hipStream_t st, const uint32_t *first, uint32_t nsets, uint32_t k,
+                               const uint32_t *order, uint32_t *samples);
+// Per-input arrays of a set made of S sequences of a counted parent (input
+// indices picks[0..S)), as the counting kernels would have left them:
+// Dorig, Korig, count>=2 entries (hi_cap, packed word | count << 16) and
+// offsets chosen so that sample s's capacity base offsets[s] - 5s is the
+// parent's base for its sequence -- its lists stay in the parent's cap_ids /
+// cap_cnt, and hi_cap must be sized like them.
+hipError_t launch_gather_samples(hipStream_t st, const Segs &parent, const uint64_t *par_in_off,
+                                 const uint32_t *par_Dorig, const uint32_t *picks, uint32_t S,
+                                 uint64_t *in_off, uint32_t *Dorig, uint32_t *Korig,
+                                 uint32_t *nhi, uint32_t *hi_cap);
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);
 // writes the set ids of sg.pos_set / grp_set / rb_set (nsets > 1)
 hipError_t launch_seg_ids(hipStream_t st, const Segs &sg, uint32_t *pos_set, uint32_t *grp_set,

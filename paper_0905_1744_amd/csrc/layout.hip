@@ -588,6 +588,64 @@ hipError_t launch_exc_offsets(hipStream_t st, const SetView &v, const uint32_t *
   return hipGetLastError();
 }
 
+// Globalized rank, Algorithm 2 step 4: the k samples of each set are the
+// sequences at 0-based positions floor(t w / (k+1)), t = 1..k, of the set's
+// w sequences in key order.
+__global__ void pick_samples_kernel(const uint32_t *__restrict__ first, uint32_t nsets, uint32_t k,
+                                    const uint32_t *__restrict__ order, uint32_t *__restrict__ samples) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nsets * k) return;
+  const uint32_t q = x / k, t = x % k + 1u;
+  const uint32_t a = first[q], w = first[q + 1] - a;
+  samples[x] = a + order[a + (uint32_t)((uint64_t)t * w / (k + 1u))];
+}
+
+hipError_t launch_pick_samples(hipStream_t st, const uint32_t *first, uint32_t nsets, uint32_t k,
+                               const uint32_t *order, uint32_t *samples) {
+  const uint32_t n = nsets * k;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pick_samples_kernel, dim3((n + 255) / 256), dim3(256), 0, st, first, nsets, k,
+                     order, samples);
+  return hipGetLastError();
+}
+
+// Step 5: the sample set's per-input arrays, one wave per sample.  Its
+// distinct-word lists are the parent's (same capacity base), its count>=2
+// entries are re-packed from the parent's sorted-order lists.
+__global__ __launch_bounds__(256) void gather_samples_kernel(
+    Segs par, const uint64_t *__restrict__ par_in_off, const uint32_t *__restrict__ par_Dorig,
+    const uint32_t *__restrict__ picks, uint32_t S, uint64_t *__restrict__ in_off,
+    uint32_t *__restrict__ Dorig, uint32_t *__restrict__ Korig, uint32_t *__restrict__ nhi,
+    uint32_t *__restrict__ hi_cap) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t s = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (s >= S) return;
+  const uint32_t i = picks[s];
+  const uint32_t q = par.set_of_pos(i), a = par.seq[q];
+  const SetView &v = par.views[q];
+  const uint32_t p = v.inv[i - a];
+  const uint32_t h0 = v.hi_off[p], nh = v.hi_off[p + 1] - h0;
+  const uint64_t co = par_in_off[i] - 5ull * i;
+  for (uint32_t t = lane; t < nh; t += 64)
+    hi_cap[co + t] = (uint32_t)v.hi_ids[h0 + t] | ((uint32_t)v.hi_cnt[h0 + t] << 16);
+  if (lane == 0) {
+    in_off[s] = co + 5ull * s;
+    Dorig[s] = par_Dorig[i];
+    Korig[s] = (uint32_t)(par_in_off[i + 1] - par_in_off[i]) - 5u;
+    nhi[s] = nh;
+  }
+}
+
+hipError_t launch_gather_samples(hipStream_t st, const Segs &parent, const uint64_t *par_in_off,
+                                 const uint32_t *par_Dorig, const uint32_t *picks, uint32_t S,
+                                 uint64_t *in_off, uint32_t *Dorig, uint32_t *Korig,
+                                 uint32_t *nhi, uint32_t *hi_cap) {
+  if (S == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_samples_kernel, dim3((S + 3) / 4), dim3(256), 0, st, parent, par_in_off,
+                     par_Dorig, picks, S, in_off, Dorig, Korig, nhi, hi_cap);
+  return hipGetLastError();
+}
+
 // pos[16 * ceil(n/16)]: sorted positions of input indices first..first+n-1,
 // padded with 0xFFFFFFFF.
 __global__ void map_positions_kernel(const uint32_t *__restrict__ inv, uint32_t first, uint32_t n,

@@ -310,11 +310,15 @@ __device__ __forceinline__ void column_counts(const uint16_t *T16, const uint4 *
 }
 
 // One 16 x 64 tile: row block rb (in LDS) against column group g (this
-// wave).  Adds the tile's row sums into sh.racc (LDS, exact) and its column
-// sums into the lane's limbs.
+// wave).  Within one set (kCross false) a pair counts only below the
+// diagonal of the sorted order and the tile's row sums go to sh.racc (LDS,
+// exact); with rows from another set (kCross true: the gathered samples of
+// the globalized rank, row_n of them) every pair counts and only the
+// columns gather sums.  Column sums go into the lane's limbs.
+template <bool kCross>
 __device__ __forceinline__ void rank_tile(const SetView &v, RankShared &sh, uint32_t rb, uint32_t g,
-                                          double delta, const uint16_t *eid, const uint16_t *ecnt,
-                                          uint32_t en, long long (&col)[3][64]) {
+                                          uint32_t row_n, double delta, const uint16_t *eid,
+                                          const uint16_t *ecnt, uint32_t en, long long (&col)[3][64]) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t L = __builtin_amdgcn_readfirstlane(v.grp_len[g]);
   const uint32_t hl = __builtin_amdgcn_readfirstlane(v.ghi_len[g]);
@@ -345,25 +349,29 @@ __device__ __forceinline__ void rank_tile(const SetView &v, RankShared &sh, uint
     for (int h = 0; h < 2; h++) {
       const uint32_t rr = r + 8 * h, sr = 16u * rb + rr;
       d[h] = 0.0;
-      if (vc && sc < sr && sr < v.N) {
+      if (vc && (kCross || sc < sr) && sr < row_n) {
         const double inv = sh.row.rowK[rr] < Kc ? sh.row.rowInv[rr] : invKc;
         d[h] = -log_tab(fma((double)cnt[rr], inv, delta), sh.logt, sh.ln2);
       }
     }
     colsum += d[0];
     colsum += d[1];
-    const double send = b5 ? d[0] : d[1];
-    const double keep = b5 ? d[1] : d[0];
-    u8[r] = keep + __shfl_xor(send, 32, 64);
+    if (!kCross) {
+      const double send = b5 ? d[0] : d[1];
+      const double keep = b5 ? d[1] : d[0];
+      u8[r] = keep + __shfl_xor(send, 32, 64);
+    }
   }
-  const double rowtot = halving_reduce8(u8, lane);
-  if ((lane & 3u) == 0) {
-    long long l0, l1, l2;
-    fix_limbs(rowtot, l0, l1, l2);
-    unsigned long long *ra = sh.racc + 3u * (lane >> 2);
-    atomicAdd(ra, (unsigned long long)l0);
-    atomicAdd(ra + 1, (unsigned long long)l1);
-    atomicAdd(ra + 2, (unsigned long long)l2);
+  if (!kCross) {
+    const double rowtot = halving_reduce8(u8, lane);
+    if ((lane & 3u) == 0) {
+      long long l0, l1, l2;
+      fix_limbs(rowtot, l0, l1, l2);
+      unsigned long long *ra = sh.racc + 3u * (lane >> 2);
+      atomicAdd(ra, (unsigned long long)l0);
+      atomicAdd(ra + 1, (unsigned long long)l1);
+      atomicAdd(ra + 2, (unsigned long long)l2);
+    }
   }
   long long l0, l1, l2;
   fix_limbs(colsum, l0, l1, l2);
@@ -419,8 +427,10 @@ __global__ __launch_bounds__(1024) void rank_pairs_kernel(const SetView *__restr
     const uint16_t *eid = lds_exc ? sh.exc_id : v.exc_ids + e0;
     const uint16_t *ecnt = lds_exc ? sh.exc_c : v.exc_cnt + 16ull * e0;
     // a tile has pairs below the diagonal only when rb >= 4 g
-    if (ga < v.G && rb >= 4u * ga) rank_tile(v, sh, rb, ga, delta, eid, ecnt, en, sh.colacc[wave][0]);
-    if (gb < v.G && rb >= 4u * gb) rank_tile(v, sh, rb, gb, delta, eid, ecnt, en, sh.colacc[wave][1]);
+    if (ga < v.G && rb >= 4u * ga)
+      rank_tile<false>(v, sh, rb, ga, v.N, delta, eid, ecnt, en, sh.colacc[wave][0]);
+    if (gb < v.G && rb >= 4u * gb)
+      rank_tile<false>(v, sh, rb, gb, v.N, delta, eid, ecnt, en, sh.colacc[wave][1]);
     __syncthreads();
   }
   if (tid < 48) {
@@ -444,6 +454,109 @@ hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairT
                              uint32_t ntasks, double delta) {
   if (ntasks == 0) return hipSuccess;
   hipLaunchKernelGGL(rank_pairs_kernel, dim3(ntasks), dim3(1024), 0, st, d_views, tasks, delta);
+  return hipGetLastError();
+}
+
+// Globalized rank, step 6 of Algorithm 2 (Section 3.1.1): every sequence of
+// the counted blocks (columns, all sets of `cols`) against the gathered
+// samples (rows: the single set *rows).  One workgroup = 32 consecutive
+// column groups of the whole batch (wave w takes groups gx0 + w and
+// gx0 + 31 - w, each belonging to whichever set holds it) against sample
+// row blocks rb0 .. rb1-1.  Each pair adds d(column, sample) to the
+// column's exact accumulator; nothing is added for the rows.
+// set and set-local index of batch-wide column group gx (wave-uniform)
+__device__ __forceinline__ uint32_t cross_set(const Segs &cols, uint32_t gx, uint32_t &gl) {
+  const uint32_t q = __builtin_amdgcn_readfirstlane(cols.set_of_grp(gx));
+  gl = gx - __builtin_amdgcn_readfirstlane(cols.grp[q]);
+  return q;
+}
+
+__global__ __launch_bounds__(1024) void rank_cross_kernel(Segs cols, const SetView *__restrict__ rows,
+                                                          const CrossTask *__restrict__ tasks,
+                                                          uint32_t Gtot, double delta) {
+  __shared__ RankShared sh;
+  const CrossTask tk = tasks[blockIdx.x];
+  const SetView rv = *rows;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (uint32_t q = tid; q < (uint32_t)kLogEntries; q += 1024) log_table_entry((int)q, sh.logt[q]);
+  if (tid == 0) sh.ln2 = log(2.0);
+  clear_rows(sh.row);
+
+  const uint32_t ga = tk.gx0 + wave, gb = tk.gx0 + 31u - wave;
+#pragma unroll
+  for (int k = 0; k < 6; k++) (&sh.colacc[wave][0][0][0])[k * 64 + lane] = 0;
+
+  for (uint32_t rb = tk.rb0; rb < tk.rb1; rb++) {
+    if (rb > tk.rb0) {
+      const uint32_t pr = rb - 1;
+      touch_rows<false>(rv, ConsecutiveRows{16u * pr, rv.N}, rv.exc_ids, rv.exc_off[pr], rv.exc_n[pr], sh.row);
+    }
+    __syncthreads();
+    const uint32_t e0 = rv.exc_off[rb], en = rv.exc_n[rb];
+    touch_rows<true>(rv, ConsecutiveRows{16u * rb, rv.N}, rv.exc_ids, e0, en, sh.row);
+    const bool lds_exc = en <= kExcLds;
+    if (lds_exc) {
+      for (uint32_t e = tid; e < en; e += 1024) sh.exc_id[e] = rv.exc_ids[e0 + e];
+      for (uint32_t e = tid; e < 16u * en; e += 1024) sh.exc_c[e] = rv.exc_cnt[16ull * e0 + e];
+    }
+    __syncthreads();
+    const uint16_t *eid = lds_exc ? sh.exc_id : rv.exc_ids + e0;
+    const uint16_t *ecnt = lds_exc ? sh.exc_c : rv.exc_cnt + 16ull * e0;
+    if (ga < Gtot) {
+      uint32_t gl;
+      const uint32_t q = cross_set(cols, ga, gl);
+      rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, eid, ecnt, en, sh.colacc[wave][0]);
+    }
+    if (gb < Gtot) {
+      uint32_t gl;
+      const uint32_t q = cross_set(cols, gb, gl);
+      rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, eid, ecnt, en, sh.colacc[wave][1]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (uint32_t h = 0; h < 2; h++) {
+    const uint32_t gx = h ? gb : ga;
+    if (gx >= Gtot) continue;
+    uint32_t gl;
+    const SetView &v = cols.views[cross_set(cols, gx, gl)];
+    const uint32_t sc = 64u * gl + lane;
+    if (sc < v.N) {
+      unsigned long long *acc = reinterpret_cast<unsigned long long *>(v.acc);
+#pragma unroll
+      for (int k = 0; k < 3; k++)
+        atomicAdd(acc + 3ull * sc + k, (unsigned long long)sh.colacc[wave][h][k][lane]);
+    }
+  }
+}
+
+hipError_t launch_rank_cross(hipStream_t st, const Segs &cols, const SetView *rows,
+                             const CrossTask *tasks, uint32_t ntasks, uint32_t Gtot, double delta) {
+  if (ntasks == 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_cross_kernel, dim3(ntasks), dim3(1024), 0, st, cols, rows, tasks, Gtot,
+                     delta);
+  return hipGetLastError();
+}
+
+// Globalized rank = (sum over the S samples) / S for every sorted position
+// of every block, written at the input index; clears the accumulators.
+__global__ void cross_finalize_kernel(Segs sg, uint32_t N, uint32_t S, double *__restrict__ ranks) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const uint32_t set = sg.set_of_pos(p);
+  const uint32_t a = sg.seq[set];
+  const SetView &v = sg.views[set];
+  long long *acc = v.acc + 3ull * (p - a);
+  ranks[a + v.perm[p - a]] = fix_to_double(acc[0], acc[1], acc[2]) / (double)S;
+  acc[0] = acc[1] = acc[2] = 0;
+}
+
+hipError_t launch_cross_finalize(hipStream_t st, const Segs &sg, uint32_t N, uint32_t S,
+                                 double *ranks) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(cross_finalize_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, S,
+                     ranks);
   return hipGetLastError();
 }
 

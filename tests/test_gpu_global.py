@@ -1,0 +1,193 @@
+"""GPU: the globalized k-mer rank (Section 3.1.1; Algorithm 2 steps 1-6)
+through the C ABI against the oracle.
+
+Local ranks (each block ranked against itself) within the rank tolerance;
+the samples bit-exact against the oracle's selection made from the GPU's own
+local ranks (the selection is a comparison of those values, so both sides
+decide on the same numbers); globalized ranks within the tolerance against
+the oracle's rank of every sequence against the GPU's samples."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kd():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0905_1744_amd as kd
+    kd.lib()
+    return kd
+
+
+@pytest.fixture(scope="module")
+def ctx(kd):
+    c = kd.Context()
+    yield c
+    c.synchronize()
+
+
+def within(R_gpu, R_or, scale):
+    err = np.abs(R_gpu - R_or)
+    bad = err > RTOL * scale
+    assert not bad.any(), (np.flatnonzero(bad)[:10], err[bad][:10], scale[bad][:10])
+
+
+def bounds(n, B):
+    return [(b * n // B, (b + 1) * n // B) for b in range(B)]
+
+
+def check_global(kd, ctx, oracle_mod, ss, B, k, delta=0.1):
+    L = oracle_mod.count(ss)
+    say("global", ss.n, B, k, delta)
+    out = ctx.globalized_rank(ss.residues, ss.offsets.view(np.int64), B, k, delta)
+    loc = out["local"].cpu().numpy()
+    G = out["ranks"].cpu().numpy()
+    smp = kd.u32(out["samples"])
+    # steps 1-2: each block alone
+    for lo, hi in bounds(ss.n, B):
+        Lb = oracle_mod.count(synth.from_strings([ss.seq(i) for i in range(lo, hi)]))
+        r, sc = oracle_mod.rank(Lb, delta, with_scale=True)
+        within(loc[lo:hi], r, sc)
+    # steps 3-5: the selection rule applied to the GPU's local ranks
+    assert np.array_equal(smp, oracle_mod.global_samples(loc, B, k))
+    # step 6
+    g, sc = oracle_mod.global_rank(L, smp, delta, with_scale=True)
+    within(G, g, sc)
+    return loc, G, smp
+
+
+@pytest.mark.parametrize("B,k", [(4, 3), (4, 1), (4, 7), (5, 11), (1, 1), (1, 9)])
+def test_global_small(kd, ctx, oracle_mod, B, k):
+    ss = synth.small()
+    check_global(kd, ctx, oracle_mod, ss, B, k)
+
+
+def test_global_ragged_blocks(kd, ctx, oracle_mod):
+    """Block sizes that are not multiples of 16 or 64, samples spanning
+    several row blocks, delta other than 0.1."""
+    rng = np.random.default_rng(31)
+    ss = synth.random_tiny(rng, 211, 6, 400)
+    check_global(kd, ctx, oracle_mod, ss, 7, 5, delta=0.05)
+    check_global(kd, ctx, oracle_mod, ss, 3, 70)
+
+
+def test_global_all_sampled_is_centralized(kd, ctx, oracle_mod):
+    """k = block size samples every sequence: the globalized rank is then the
+    centralized rank (Equation 3), here against the GPU's own kmer_rank."""
+    s = synth.small()
+    ss = synth.from_strings([s.seq(i) for i in range(192)])
+    kset = ctx.kmer_count(ss.residues, ss.offsets.view(np.int64))
+    R = ctx.kmer_rank(kset, 0.1).cpu().numpy()
+    _, sc = oracle_mod.rank(oracle_mod.count(ss), 0.1, with_scale=True)
+    for B in (1, 3, 192):
+        say("all-sampled", B)
+        out = ctx.globalized_rank(ss.residues, ss.offsets.view(np.int64), B, 192 // B)
+        assert sorted(kd.u32(out["samples"]).tolist()) == list(range(192))
+        within(out["ranks"].cpu().numpy(), R, sc)
+
+
+def test_global_tiny_and_worked(kd, ctx, oracle_mod):
+    """The worked examples and the smallest inputs.  Their local ranks hold
+    exact ties, which the GPU's rank (correct to rounding, not an exact sum)
+    may break either way: the selection is checked on the GPU's own local
+    ranks, and either tied sample gives the hand-computed values."""
+    L1, L0 = -math.log1p(0.1), -math.log(0.1)
+    H = (L1 + L0) / 2
+    ss = synth.from_strings(["AAAAAAA", "CCCCCC", "GPSTAG", "AAAAAAA", "DDDDDD"])
+    out = ctx.globalized_rank(ss.residues, ss.offsets.view(np.int64), 2, 1)
+    smp = kd.u32(out["samples"])
+    assert np.array_equal(smp, oracle_mod.global_samples(out["local"].cpu().numpy(), 2, 1))
+    assert smp[0] in (0, 1) and smp[1] in (2, 3)   # (X, Z) and (Y, U) tie
+    # distances of the five sequences, worked by hand: only X, Y, U share a word
+    share = np.array([[1, 0, 1, 1, 0], [0, 1, 0, 0, 0], [1, 0, 1, 1, 0], [1, 0, 1, 1, 0],
+                      [0, 0, 0, 0, 1]])
+    Dm = np.where(share == 1, L1, L0)
+    want = Dm[:, smp].mean(axis=1)
+    if smp.tolist() == [1, 3]:
+        assert np.allclose(want, [H, H, H, H, L0])
+    np.testing.assert_allclose(out["ranks"].cpu().numpy(), want, rtol=1e-14)
+    ss = synth.from_strings(["AAAAAAA", "GPSTAG", "CCCCCC"])
+    out = ctx.globalized_rank(ss.residues, ss.offsets.view(np.int64), 1, 1)
+    assert kd.u32(out["samples"]).tolist()[0] in (0, 1)    # X and Y tie
+    np.testing.assert_allclose(out["ranks"].cpu().numpy(), [L1, L1, L0], rtol=1e-14)
+    one = synth.from_strings(["MKVLAAGIVG"])
+    out = ctx.globalized_rank(one.residues, one.offsets.view(np.int64), 1, 1)
+    assert out["ranks"].cpu().numpy()[0] == pytest.approx(L1, rel=1e-15)
+
+
+def test_global_deterministic_and_reusable(kd, ctx, oracle_mod):
+    """Repeated calls on one counted object, interleaved with kmer_rank on
+    it (they share the accumulators), are bit-identical."""
+    ss = synth.small()
+    off = ss.offsets.view(np.int64)
+    kb = ctx.kmer_count_batch(ss.residues, off, ctx.block_bounds(ss.n, 4))
+    loc = ctx.kmer_rank(kb, 0.1)
+    G1, s1 = ctx.kmer_rank_global(kb, loc, 3, 0.1)
+    loc2 = ctx.kmer_rank(kb, 0.1)
+    G2, s2 = ctx.kmer_rank_global(kb, loc2, 3, 0.1)
+    assert np.array_equal(loc.cpu().numpy(), loc2.cpu().numpy())
+    assert np.array_equal(G1.cpu().numpy(), G2.cpu().numpy())
+    assert np.array_equal(kd.u32(s1), kd.u32(s2))
+    kb.destroy()
+
+
+def test_global_errors(kd, ctx):
+    ss = synth.small()
+    off = ss.offsets.view(np.int64)
+    kb = ctx.kmer_count_batch(ss.residues, off, ctx.block_bounds(ss.n, 4))
+    loc = ctx.kmer_rank(kb, 0.1)
+    for k, delta in ((0, 0.1), (129, 0.1), (3, 0.0), (3, float("nan"))):
+        with pytest.raises(kd.KdError) as e:
+            ctx.kmer_rank_global(kb, loc, k, delta)
+        assert e.value.status == -1
+    G, _ = ctx.kmer_rank_global(kb, loc, 128, 0.1)  # k = the block size is allowed
+    with pytest.raises(ValueError):
+        ctx.kmer_rank_global(kb, loc[:-1], 3, 0.1)
+    other = kd.Context()
+    with pytest.raises(kd.KdError):
+        other.kmer_rank_global(kb, loc, 3, 0.1)  # counted on another context
+    other.close()
+    kb.destroy()
+
+
+@pytest.mark.parametrize("which", ["paper20k", "large100k"])
+def test_global_full_size_sampled(kd, ctx, oracle_mod, which):
+    """Full size, as the benchmark runs it (B blocks, k = B - 1): sampled
+    rows of the local and globalized ranks, every sample bit-exact."""
+    ss = synth.paper20k() if which == "paper20k" else synth.large100k()
+    B, k = ss.B, ss.B - 1
+    say("global full-size", which, ss.n, B, k)
+    out = ctx.globalized_rank(ss.residues, ss.offsets.view(np.int64), B, k)
+    loc = out["local"].cpu().numpy()
+    G = out["ranks"].cpu().numpy()
+    smp = kd.u32(out["samples"])
+    assert np.array_equal(smp, oracle_mod.global_samples(loc, B, k))
+    rng = np.random.default_rng(52)
+    for b in (0, B // 2, B - 1):
+        lo, hi = b * ss.n // B, (b + 1) * ss.n // B
+        Lb = oracle_mod.count(synth.from_strings([ss.seq(i) for i in range(lo, hi)]))
+        rows = np.sort(rng.choice(hi - lo, size=6, replace=False)).astype(np.uint32)
+        r, sc = oracle_mod.rank(Lb, 0.1, rows=rows, with_scale=True)
+        within(loc[lo + rows.astype(np.int64)], r, sc)
+    L = oracle_mod.count(ss)
+    rows = np.sort(rng.choice(ss.n, size=64, replace=False)).astype(np.uint32)
+    g, sc = oracle_mod.global_rank(L, smp, 0.1, rows=rows, with_scale=True)
+    within(G[rows], g, sc)
+    p = ctx.sample_partition(out["ranks"], B)
+    off = kd.u32(p["offsets"])
+    assert off[-1] == ss.n and np.diff(off.astype(np.int64)).max() <= 2 * math.ceil(ss.n / B)
