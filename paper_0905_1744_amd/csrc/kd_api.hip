@@ -281,6 +281,7 @@ extern "C" void kd_ctx_destroy(kd_ctx *ctx) {
   }
   delete ctx->pool;  // frees task lists and anything still live
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->readback) (void)hipHostFree(ctx->readback);
   delete ctx;
 }
 
@@ -769,19 +770,86 @@ namespace {
 kd_status plan_partition(uint32_t nsets, const uint32_t *first, const uint32_t *Bs,
                          std::vector<PartDesc> &desc, uint64_t &scratch);
 
-// Work list of the globalized-rank pass: strips of 32 column groups (all
-// sets, batch-wide numbering) against runs of sample row blocks, with runs
-// long enough to keep the list near four workgroups per compute unit (each
-// workgroup flushes its 2048 column sums once).
-void make_cross_tasks(uint32_t Gtot, uint32_t RBs, int cus, std::vector<CrossTask> &out) {
+// Work list of the globalized-rank pass.
+//  * The column groups of all sets are ordered by decreasing padded list
+//    length (grp_len, read back from the device; ties by group number) into
+//    gperm, and consecutive runs of `gpt` of them form the strips, so the
+//    groups a workgroup's waves walk together are about equally long.
+//    gpt = 32 (two groups per wave) unless that leaves fewer than two
+//    workgroups per compute unit, then 16 (one group per wave).
+//  * Each strip is cut into at most one XCD's worth of runs of sample row
+//    blocks.
+//  * Placement: workgroup t runs on XCD t % 8 and an XCD starts its
+//    workgroups in order as its compute units free up.  Tasks, longest
+//    first, are assigned to the XCD whose next free compute unit (in a
+//    simulation with a cost of rows x list length per task) frees first,
+//    ties to the lowest XCD, so consecutive tasks of one strip tend to
+//    share an XCD and its L2; the list then interleaves the XCDs' queues.
+//    Positions past an XCD's queue hold empty tasks (no row blocks, no
+//    groups).
+// gperm gets gpt (strips + 1) entries, 0xFFFFFFFF past the last group.
+constexpr uint32_t kXcds = 8;
+
+uint32_t make_cross_tasks(const uint32_t *grp_len, uint32_t Gtot, uint32_t RBs, int cus,
+                          std::vector<CrossTask> &out, std::vector<uint32_t> &gperm) {
   out.clear();
-  const uint32_t strips = (Gtot + kGroupsPerTask - 1) / kGroupsPerTask;
-  const uint64_t cells = (uint64_t)strips * RBs;
-  const uint64_t target = 4ull * (uint64_t)std::max(cus, 1);
-  const uint32_t rbt = (uint32_t)std::max<uint64_t>(1, (cells + target - 1) / target);
-  for (uint32_t s = 0; s < strips; s++)
-    for (uint32_t rb0 = 0; rb0 < RBs; rb0 += rbt)
-      out.push_back({s * kGroupsPerTask, rb0, std::min(rb0 + rbt, RBs)});
+  const uint32_t ncu = (uint32_t)std::max(cus, (int)kXcds);
+  const uint32_t per_xcd = ncu / kXcds;
+  const uint32_t runs = std::max<uint32_t>(1, std::min(RBs, per_xcd));
+  const uint32_t rbt = (RBs + runs - 1) / runs;
+  const uint32_t nrun = (RBs + rbt - 1) / rbt;
+  uint32_t gpt = kGroupsPerTask;
+  if ((uint64_t)((Gtot + 31) / 32) * nrun < 2ull * ncu) gpt = kGroupsPerTask / 2;
+  const uint32_t strips = (Gtot + gpt - 1) / gpt;
+  gperm.assign((size_t)(strips + 1) * gpt, 0xFFFFFFFFu);
+  for (uint32_t g = 0; g < Gtot; g++) gperm[g] = g;
+  std::stable_sort(gperm.begin(), gperm.begin() + Gtot,
+                   [&](uint32_t a, uint32_t b) { return grp_len[a] > grp_len[b]; });
+  // per-XCD min-heaps of compute-unit free times
+  std::vector<std::vector<uint64_t>> cu(kXcds, std::vector<uint64_t>(per_xcd, 0));
+  std::vector<std::vector<CrossTask>> per(kXcds);
+  auto later = [](uint64_t a, uint64_t b) { return a > b; };
+  for (uint32_t s = 0; s < strips; s++) {
+    const uint32_t g0 = s * gpt;
+    // the wave with the most work: groups w and gpt-1-w (gpt = 32) or w
+    uint64_t wmax = 0;
+    for (uint32_t w = 0; w < 16; w++) {
+      uint64_t l = gperm[g0 + w] != 0xFFFFFFFFu ? grp_len[gperm[g0 + w]] : 0;
+      if (gpt == 32 && gperm[g0 + 31 - w] != 0xFFFFFFFFu) l += grp_len[gperm[g0 + 31 - w]];
+      wmax = std::max(wmax, l);
+    }
+    for (uint32_t rb0 = 0; rb0 < RBs; rb0 += rbt) {
+      const uint32_t rb1 = std::min(rb0 + rbt, RBs);
+      const uint64_t cost = (uint64_t)(rb1 - rb0) * (wmax + 64);
+      uint32_t bx = 0;
+      for (uint32_t x = 1; x < kXcds; x++)
+        if (cu[x].front() < cu[bx].front()) bx = x;
+      std::pop_heap(cu[bx].begin(), cu[bx].end(), later);
+      cu[bx].back() += cost;
+      std::push_heap(cu[bx].begin(), cu[bx].end(), later);
+      per[bx].push_back({g0, rb0, rb1});
+    }
+  }
+  size_t L = 0;
+  for (const auto &v : per) L = std::max(L, v.size());
+  out.assign(L * kXcds, CrossTask{strips * gpt, 0, 0});
+  for (uint32_t x = 0; x < kXcds; x++)
+    for (size_t j = 0; j < per[x].size(); j++) out[j * kXcds + x] = per[x][j];
+  return gpt;
+}
+
+// Pinned host area of at least `bytes`, valid until the next call; only
+// reallocated while no copy into it is pending (callers synchronize first).
+void *readback_area(kd_ctx *ctx, size_t bytes) {
+  if (ctx->readback_cap < bytes) {
+    if (ctx->readback) (void)hipHostFree(ctx->readback);
+    ctx->readback = nullptr;
+    ctx->readback_cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 64u << 10);
+    if (hipHostMalloc(&ctx->readback, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+    ctx->readback_cap = cap;
+  }
+  return ctx->readback;
 }
 
 }  // namespace
@@ -824,29 +892,48 @@ extern "C" kd_status kmer_rank_global(kd_ctx *ctx, const kd_set *s, const double
   }
   KD_TRY(launch_pick_samples(st, s->segs.seq, nb, k, order, smp));
   t_pick.done();
-  // step 5: the samples as a set of their own (rows of the cross pass)
+  // column group lengths for the work list, read during the sync below
+  const uint32_t G = s->v.G;
+  uint32_t *h_len = static_cast<uint32_t *>(readback_area(ctx, sizeof(uint32_t) * G));
+  if (!h_len) return KD_ENOMEM;
+  KD_TRY(hipMemcpyAsync(h_len, s->v.grp_len, sizeof(uint32_t) * G, hipMemcpyDeviceToHost, st));
+  // step 5: the samples as a set of their own (rows of the cross pass);
+  // this synchronizes the stream
   const uint32_t sfirst[2] = {0, S};
   kd_set *ss = nullptr;
   kd_status rc = build_sets(ctx, nullptr, nullptr, 1, sfirst, 0, &ss, s, smp);
-  if (rc != KD_OK) return rc;
+  if (rc != KD_OK) {
+    (void)hipStreamSynchronize(st);  // the read-back copy may still be pending
+    return rc;
+  }
   // step 6: every sequence against the samples
   std::vector<CrossTask> tl;
-  make_cross_tasks(s->v.G, ss->v.RB, ctx->cus, tl);
-  CrossTask *d_tasks = tmp.get<CrossTask>(tl.size() + 1);
-  hipError_t e = d_tasks ? upload(ctx, d_tasks, tl.data(), sizeof(CrossTask) * tl.size())
-                         : hipErrorOutOfMemory;
+  std::vector<uint32_t> gperm;
+  const uint32_t gpt = make_cross_tasks(h_len, G, ss->v.RB, ctx->cus, tl, gperm);
+  const size_t tbytes = (sizeof(CrossTask) * tl.size() + 255) & ~(size_t)255;
+  char *d_work = tmp.get<char>(tbytes + sizeof(uint32_t) * gperm.size());
+  CrossTask *d_tasks = reinterpret_cast<CrossTask *>(d_work);
+  const uint32_t *d_gperm = reinterpret_cast<const uint32_t *>(d_work + tbytes);
+  hipError_t e = hipErrorOutOfMemory;
+  if (d_work) {
+    std::vector<char> hw(tbytes + sizeof(uint32_t) * gperm.size());
+    std::memcpy(hw.data(), tl.data(), sizeof(CrossTask) * tl.size());
+    std::memcpy(hw.data() + tbytes, gperm.data(), sizeof(uint32_t) * gperm.size());
+    e = upload(ctx, d_work, hw.data(), hw.size());
+  }
   if (e == hipSuccess && !s->acc_clean) e = launch_fill_u64(st, s->v.acc, 3ull * N, 0);
   s->acc_clean = false;
   StageTimer t_cross(ctx, KD_STAGE_GLOBAL);
   if (e == hipSuccess)
-    e = launch_rank_cross(st, s->segs, ss->d_view, d_tasks, (uint32_t)tl.size(), s->v.G, delta);
+    e = launch_rank_cross(st, s->segs, ss->d_view, d_tasks, (uint32_t)tl.size(), d_gperm, gpt,
+                          delta);
   t_cross.done();
   StageTimer t_fin(ctx, KD_STAGE_FINALIZE);
   if (e == hipSuccess) e = launch_cross_finalize(st, s->segs, N, S, ranks);
   t_fin.done();
   if (e == hipSuccess) s->acc_clean = true;
   kd_set_destroy(ss);  // its blocks return to the pool; stream order keeps them valid
-  if (!d_tasks) return KD_ENOMEM;
+  if (!d_work) return KD_ENOMEM;
   return from_hip(e);
 }
 

@@ -97,7 +97,8 @@ struct PairTask {     // one workgroup's work in the rank kernel
 };
 constexpr uint32_t kGroupsPerTask = 32;  // two column groups per wave
 struct CrossTask {    // one workgroup's work in the globalized-rank pass
-  uint32_t gx0;       // first of 32 consecutive column groups, batch-wide numbering
+  uint32_t gx0;       // its column groups are gperm[gx0 .. gx0+gpt-1], gpt = 16 or
+                      // 32 (batch-wide numbering, 0xFFFFFFFF = none)
   uint32_t rb0, rb1;  // row blocks [rb0, rb1) of the sample set
 };
 constexpr uint32_t kRowBlocksPerTask = 4;  // default run of row blocks per workgroup
@@ -129,6 +130,8 @@ struct kd_ctx {
   uint64_t err_seq = 0, err_pos = 0;
   int cus = 256;
   void *pinned = nullptr;         // small pinned readback area
+  void *readback = nullptr;       // growable pinned readback area (read after a sync)
+  size_t readback_cap = 0;
   // tuned row blocks per rank workgroup, by size class (kd_autotune)
   std::map<uint32_t, uint32_t> rbt_pref;
   // rank work lists of single sets, keyed by (N, row blocks per workgroup):
@@ -236,7 +239,8 @@ hipError_t launch_rank_finalize(hipStream_t st, const Segs &sg, uint32_t N, doub
                                 double *ranks);
 // globalized rank: sample rows against every column group of `cols`
 hipError_t launch_rank_cross(hipStream_t st, const Segs &cols, const SetView *rows,
-                             const CrossTask *tasks, uint32_t ntasks, uint32_t Gtot, double delta);
+                             const CrossTask *tasks, uint32_t ntasks, const uint32_t *gperm,
+                             uint32_t gpt, double delta);
 hipError_t launch_cross_finalize(hipStream_t st, const Segs &sg, uint32_t N, uint32_t S,
                                  double *ranks);
 // samples[q*k + t-1] = first[q] + order[first[q] + floor(t w_q / (k+1))]

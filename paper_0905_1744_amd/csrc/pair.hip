@@ -459,11 +459,14 @@ hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairT
 
 // Globalized rank, step 6 of Algorithm 2 (Section 3.1.1): every sequence of
 // the counted blocks (columns, all sets of `cols`) against the gathered
-// samples (rows: the single set *rows).  One workgroup = 32 consecutive
-// column groups of the whole batch (wave w takes groups gx0 + w and
-// gx0 + 31 - w, each belonging to whichever set holds it) against sample
-// row blocks rb0 .. rb1-1.  Each pair adds d(column, sample) to the
-// column's exact accumulator; nothing is added for the rows.
+// samples (rows: the single set *rows).  One workgroup = gpt (16 or 32)
+// column groups of the whole batch, gperm[gx0 .. gx0+gpt-1], against sample
+// row blocks rb0 .. rb1-1.  gperm lists the groups by decreasing list
+// length, so the groups of a workgroup are about equally long; wave w takes
+// the w-th of them and, with 32, also the (31-w)-th.  Each group belongs to
+// whichever set holds it.
+// Each pair adds d(column, sample) to the column's exact accumulator;
+// nothing is added for the rows.
 // set and set-local index of batch-wide column group gx (wave-uniform)
 __device__ __forceinline__ uint32_t cross_set(const Segs &cols, uint32_t gx, uint32_t &gl) {
   const uint32_t q = __builtin_amdgcn_readfirstlane(cols.set_of_grp(gx));
@@ -473,7 +476,8 @@ __device__ __forceinline__ uint32_t cross_set(const Segs &cols, uint32_t gx, uin
 
 __global__ __launch_bounds__(1024) void rank_cross_kernel(Segs cols, const SetView *__restrict__ rows,
                                                           const CrossTask *__restrict__ tasks,
-                                                          uint32_t Gtot, double delta) {
+                                                          const uint32_t *__restrict__ gperm,
+                                                          uint32_t gpt, double delta) {
   __shared__ RankShared sh;
   const CrossTask tk = tasks[blockIdx.x];
   const SetView rv = *rows;
@@ -483,7 +487,9 @@ __global__ __launch_bounds__(1024) void rank_cross_kernel(Segs cols, const SetVi
   if (tid == 0) sh.ln2 = log(2.0);
   clear_rows(sh.row);
 
-  const uint32_t ga = tk.gx0 + wave, gb = tk.gx0 + 31u - wave;
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  const uint32_t ga = __builtin_amdgcn_readfirstlane(gperm[tk.gx0 + wave]);
+  const uint32_t gb = gpt == 32u ? __builtin_amdgcn_readfirstlane(gperm[tk.gx0 + 31u - wave]) : kNone;
 #pragma unroll
   for (int k = 0; k < 6; k++) (&sh.colacc[wave][0][0][0])[k * 64 + lane] = 0;
 
@@ -503,12 +509,12 @@ __global__ __launch_bounds__(1024) void rank_cross_kernel(Segs cols, const SetVi
     __syncthreads();
     const uint16_t *eid = lds_exc ? sh.exc_id : rv.exc_ids + e0;
     const uint16_t *ecnt = lds_exc ? sh.exc_c : rv.exc_cnt + 16ull * e0;
-    if (ga < Gtot) {
+    if (ga != kNone) {
       uint32_t gl;
       const uint32_t q = cross_set(cols, ga, gl);
       rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, eid, ecnt, en, sh.colacc[wave][0]);
     }
-    if (gb < Gtot) {
+    if (gb != kNone) {
       uint32_t gl;
       const uint32_t q = cross_set(cols, gb, gl);
       rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, eid, ecnt, en, sh.colacc[wave][1]);
@@ -518,7 +524,7 @@ __global__ __launch_bounds__(1024) void rank_cross_kernel(Segs cols, const SetVi
 #pragma unroll
   for (uint32_t h = 0; h < 2; h++) {
     const uint32_t gx = h ? gb : ga;
-    if (gx >= Gtot) continue;
+    if (gx == kNone) continue;
     uint32_t gl;
     const SetView &v = cols.views[cross_set(cols, gx, gl)];
     const uint32_t sc = 64u * gl + lane;
@@ -532,10 +538,12 @@ __global__ __launch_bounds__(1024) void rank_cross_kernel(Segs cols, const SetVi
 }
 
 hipError_t launch_rank_cross(hipStream_t st, const Segs &cols, const SetView *rows,
-                             const CrossTask *tasks, uint32_t ntasks, uint32_t Gtot, double delta) {
+                             const CrossTask *tasks, uint32_t ntasks, const uint32_t *gperm,
+                             uint32_t gpt, double delta) {
   if (ntasks == 0) return hipSuccess;
-  hipLaunchKernelGGL(rank_cross_kernel, dim3(ntasks), dim3(1024), 0, st, cols, rows, tasks, Gtot,
-                     delta);
+  if (gpt != 16u && gpt != 32u) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rank_cross_kernel, dim3(ntasks), dim3(1024), 0, st, cols, rows, tasks, gperm,
+                     gpt, delta);
   return hipGetLastError();
 }
 
