@@ -85,6 +85,10 @@ def lib():
         L.orc_global_rank_rows.argtypes = [P, P, P, P, P, C.c_uint32, P, C.c_uint32, C.c_double,
                                            P, P]
         L.orc_global_rank_rows.restype = None
+        L.orc_distance_matrix.argtypes = [P, P, P, P, P, C.c_uint32, C.c_double, P]
+        L.orc_distance_matrix.restype = None
+        L.orc_upgma.argtypes = [P, C.c_uint32, P, P]
+        L.orc_upgma.restype = C.c_int
         _lib = L
     return _lib
 
@@ -243,4 +247,28 @@ def global_rank(L: Lists, samples: np.ndarray, delta: float, rows=None, with_sca
     if with_scale:
         return out[:len(rows)], sc[:len(rows)]
     return out[:len(rows)]
+
+
+def distance_matrix(L: Lists, idx, delta: float):
+    """Equations 1-2 for every ordered pair of the sequences idx (n x n)."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    n = idx.size
+    out = np.zeros((max(n, 1), max(n, 1)), dtype=np.float64)
+    lib().orc_distance_matrix(_p(L.ids), _p(L.cnt), _p(L.off), _p(L.K), _p(idx), n, delta, _p(out))
+    return out[:n, :n]
+
+
+def upgma(d: np.ndarray):
+    """UPGMA guide tree of a dissimilarity matrix: (merges (n-1, 2) int32,
+    heights (n-1,) float64); see orc_upgma for the slot and tie rules."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    n = d.shape[0]
+    if d.ndim != 2 or d.shape[1] != n:
+        raise OracleError(-1)
+    merges = np.zeros((max(n - 1, 1), 2), dtype=np.int32)
+    heights = np.zeros(max(n - 1, 1), dtype=np.float64)
+    r = lib().orc_upgma(_p(d), n, _p(merges), _p(heights))
+    if r != 0:
+        raise OracleError(r)
+    return merges[:n - 1], heights[:n - 1]
 

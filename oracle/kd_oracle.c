@@ -23,6 +23,12 @@
  *   local ranks, k samples per processor,
  *   globalized rank ...................... Section 3.1.1 ("Globalised k-mer
  *                                          Rank"), Algorithm 2 steps 1-6
+ *   per-bucket distance matrix and
+ *   guide tree ........................... Section 2 (the generic scheme: a
+ *                                          pairwise similarity matrix, then
+ *                                          a guide tree) applied to each
+ *                                          bucket (Section 3.1.3); the tree
+ *                                          is UPGMA (average linkage)
  *
  * Readings where the paper is silent (alphabet, k, Delta, log base, sample
  * positions, pivot indices for odd p, ties) are fixed by the caller-visible
@@ -379,3 +385,76 @@ void orc_global_rank_rows(const uint16_t *ids, const uint16_t *cnt, const uint64
         if (scale) scale[q] = mag / (double)S;
     }
 }
+
+/* ---- per-bucket distance matrix and guide tree ---- */
+
+/* Equations 1-2 for every ordered pair of the n sequences idx[0..n):
+ * out[r*n + c] = d(idx[r], idx[c]), diagonal included (F = 1 there). */
+void orc_distance_matrix(const uint16_t *ids, const uint16_t *cnt, const uint64_t *off,
+                         const uint32_t *K, const uint32_t *idx, uint32_t n, double delta,
+                         double *out)
+{
+    for (uint32_t r = 0; r < n; r++)
+        for (uint32_t c = 0; c < n; c++)
+            out[(uint64_t)r * n + c] = orc_pair_distance(ids, cnt, off, K, idx[r], idx[c], delta);
+}
+
+/* UPGMA (unweighted pair-group method with arithmetic mean, i.e. average
+ * linkage) on an n x n dissimilarity matrix d, of which only the upper
+ * triangle (r < c) is read.
+ *
+ * Clusters live in slots: leaf i starts in slot i with id i.  Step t
+ * (t = 0 .. n-2) takes, among the active slots a < b, the pair with the
+ * smallest D[a][b], ties broken by the smallest a, then the smallest b;
+ * the merged cluster gets id n + t and slot a, slot b is retired, and for
+ * every other active slot k
+ *     D[a,k] = (n_a D[a,k] + n_b D[b,k]) / (n_a + n_b)
+ * evaluated as written in IEEE double (two products, one sum, one
+ * quotient), with n_a, n_b the cluster sizes and D[x,y] meaning the entry
+ * of the upper triangle.  Outputs per step: merges[2t] < merges[2t+1], the
+ * two ids merged, and heights[t] = D[a][b] / 2. */
+int orc_upgma(const double *d, uint32_t n, int32_t *merges, double *heights)
+{
+    if (n == 0) return ORC_EINVAL;
+    double *D = (double *)malloc(sizeof(double) * (size_t)n * n);
+    uint32_t *size = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    int32_t *id = (int32_t *)malloc(sizeof(int32_t) * n);
+    uint8_t *act = (uint8_t *)malloc(n);
+    if (!D || !size || !id || !act) { free(D); free(size); free(id); free(act); return ORC_ENOMEM; }
+    memcpy(D, d, sizeof(double) * (size_t)n * n);
+    for (uint32_t i = 0; i < n; i++) { size[i] = 1; id[i] = (int32_t)i; act[i] = 1; }
+#define UD(x, y) D[(size_t)((x) < (y) ? (x) : (y)) * n + ((x) < (y) ? (y) : (x))]
+    for (uint32_t t = 0; t + 1 < n; t++) {
+        uint32_t ba = 0, bb = 0;
+        int found = 0;
+        for (uint32_t a = 0; a < n; a++) {
+            if (!act[a]) continue;
+            for (uint32_t b = a + 1; b < n; b++) {
+                if (!act[b]) continue;
+                if (!found || D[(size_t)a * n + b] < D[(size_t)ba * n + bb]) {
+                    ba = a; bb = b; found = 1;
+                }
+            }
+        }
+        const double h = D[(size_t)ba * n + bb];
+        const int32_t x = id[ba], y = id[bb];
+        merges[2 * t] = x < y ? x : y;
+        merges[2 * t + 1] = x < y ? y : x;
+        heights[t] = h / 2.0;
+        const double na = (double)size[ba], nb = (double)size[bb];
+        for (uint32_t k = 0; k < n; k++) {
+            if (!act[k] || k == ba || k == bb) continue;
+            const double p = na * UD(ba, k);
+            const double q = nb * UD(bb, k);
+            const double sum = p + q;
+            UD(ba, k) = sum / (na + nb);
+        }
+        act[bb] = 0;
+        size[ba] += size[bb];
+        id[ba] = (int32_t)(n + t);
+    }
+#undef UD
+    free(D); free(size); free(id); free(act);
+    return ORC_OK;
+}
+

@@ -414,3 +414,125 @@ def test_global_rank_all_sampled_is_centralized(oracle_mod):
         smp = oracle_mod.global_samples(loc, B, 96 // B)
         G = oracle_mod.global_rank(L, smp, delta)
         np.testing.assert_allclose(G, oracle_mod.rank(L, delta), rtol=2e-15, atol=0)
+
+
+# ------------------------------------------- per-bucket matrices and trees --
+
+def test_upgma_worked(oracle_mod):
+    n = 5
+    d = np.zeros((n, n))
+    want = []
+    for line in golden_lines("worked_upgma.txt"):
+        k, *v = line.split()
+        if k == "d":
+            i, j, x = int(v[0]), int(v[1]), float(v[2])
+            d[i, j] = d[j, i] = x
+        else:
+            want.append((int(v[0]), int(v[1]), float(v[2])))
+    m, h = oracle_mod.upgma(d)
+    assert [tuple(x) for x in m.tolist()] == [w[:2] for w in want]
+    assert h.tolist() == [w[2] for w in want]
+
+
+def test_upgma_all_equal_ties(oracle_mod):
+    """Every distance 1: ties go to the lowest slots, so the cluster in slot
+    0 absorbs the leaves in index order."""
+    n = 6
+    m, h = oracle_mod.upgma(np.ones((n, n)))
+    assert m.tolist() == [[0, 1], [2, 6], [3, 7], [4, 8], [5, 9]]
+    assert h.tolist() == [0.5] * 5
+
+
+def _lca_height_matrix(rng, n):
+    """A random ultrametric: random binary merges of leaves with distinct
+    integer heights; D[i][j] = 2 x height of the lowest common ancestor."""
+    clusters = [[i] for i in range(n)]
+    D = np.zeros((n, n))
+    merges = []
+    for step, hgt in enumerate(range(1, n)):
+        a, b = sorted(rng.choice(len(clusters), size=2, replace=False))
+        A, Bc = clusters[a], clusters[b]
+        for i in A:
+            for j in Bc:
+                D[i, j] = D[j, i] = 2.0 * hgt
+        merges.append((frozenset(A), frozenset(Bc), float(hgt)))
+        clusters = [c for q, c in enumerate(clusters) if q not in (a, b)] + [A + Bc]
+    return D, merges
+
+
+def test_upgma_recovers_ultrametric(oracle_mod):
+    """On an ultrametric matrix UPGMA returns its tree: the same clusters
+    merge at half their LCA distance (integer heights keep every average
+    exact)."""
+    rng = np.random.default_rng(3)
+    for n in (2, 3, 9, 25):
+        D, tree = _lca_height_matrix(rng, n)
+        m, h = oracle_mod.upgma(D)
+        members = {i: frozenset([i]) for i in range(n)}
+        got = []
+        for t, (x, y) in enumerate(m.tolist()):
+            members[n + t] = members[x] | members[y]
+            got.append((frozenset([members[x], members[y]]), h[t]))
+        want = [(frozenset([A, Bc]), hgt) for A, Bc, hgt in tree]
+        assert sorted(got, key=lambda g: g[1]) == sorted(want, key=lambda g: g[1])
+
+
+def _upgma_by_leaf_means(d):
+    """Independent average linkage: the distance of two clusters is the mean
+    of the original distances over all leaf pairs across them (no update
+    formula); ties by the clusters' smallest leaves."""
+    n = d.shape[0]
+    clusters = {i: [i] for i in range(n)}
+    out = []
+    for t in range(n - 1):
+        best = None
+        keys = sorted(clusters, key=lambda c: min(clusters[c]))
+        for ia, a in enumerate(keys):
+            for b in keys[ia + 1:]:
+                v = math.fsum(d[i, j] for i in clusters[a] for j in clusters[b]) / (
+                    len(clusters[a]) * len(clusters[b]))
+                if best is None or v < best[0]:
+                    best = (v, a, b)
+        v, a, b = best
+        out.append((min(a, b), max(a, b), v / 2))
+        clusters[n + t] = clusters.pop(a) + clusters.pop(b)
+    return out
+
+
+def test_upgma_vs_leaf_means(oracle_mod):
+    rng = np.random.default_rng(11)
+    for n in (2, 4, 7, 12):
+        x = rng.random((n, n))
+        d = (x + x.T) / 2
+        m, h = oracle_mod.upgma(d)
+        want = _upgma_by_leaf_means(d)
+        assert [tuple(r) for r in m.tolist()] == [w[:2] for w in want]
+        np.testing.assert_allclose(h, [w[2] for w in want], rtol=1e-13, atol=0)
+        assert np.all(np.diff(h) >= 0)   # average linkage merges at non-decreasing heights
+
+
+def test_upgma_errors_and_one_leaf(oracle_mod):
+    m, h = oracle_mod.upgma(np.zeros((1, 1)))
+    assert m.shape == (0, 2) and h.shape == (0,)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.upgma(np.zeros((0, 0)))
+
+
+def test_distance_matrix_bruteforce(oracle_mod):
+    """Equations 1-2 from dense brute-force counts, any subset and order of
+    sequences; the diagonal is -ln(1 + Delta)."""
+    rng = np.random.default_rng(13)
+    ss = synth.random_tiny(rng, 17, 6, 70, b"ACDEFGHIK")
+    dense = [_dense_indep(ss.seq(i).decode()) for i in range(ss.n)]
+    n = ss.lengths()
+    L = oracle_mod.count(ss)
+    idx = np.array([5, 0, 16, 3, 3, 9], dtype=np.uint32)
+    delta = 0.07
+    M = oracle_mod.distance_matrix(L, idx, delta)
+    for r, i in enumerate(idx):
+        for c, j in enumerate(idx):
+            s = int(np.minimum(dense[i], dense[j]).sum())
+            want = -math.log(delta + s / (min(n[i], n[j]) - 5))
+            assert M[r, c] == pytest.approx(want, rel=1e-15, abs=1e-300)
+    np.testing.assert_allclose(np.diag(M), -math.log1p(delta), rtol=1e-15, atol=0)
+    np.testing.assert_array_equal(M, M.T)
