@@ -85,8 +85,8 @@ def lib():
         L.orc_global_rank_rows.argtypes = [P, P, P, P, P, C.c_uint32, P, C.c_uint32, C.c_double,
                                            P, P]
         L.orc_global_rank_rows.restype = None
-        L.orc_distance_matrix.argtypes = [P, P, P, P, P, C.c_uint32, C.c_double, P]
-        L.orc_distance_matrix.restype = None
+        L.orc_distance_block.argtypes = [P, P, P, P, P, C.c_uint32, P, C.c_uint32, C.c_double, P]
+        L.orc_distance_block.restype = None
         L.orc_upgma.argtypes = [P, C.c_uint32, P, P]
         L.orc_upgma.restype = C.c_int
         _lib = L
@@ -249,13 +249,19 @@ def global_rank(L: Lists, samples: np.ndarray, delta: float, rows=None, with_sca
     return out[:len(rows)]
 
 
+def distance_block(L: Lists, rows, cols, delta: float):
+    """Equations 1-2 for the pairs rows x cols (sequence indices)."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint32)
+    cols = np.ascontiguousarray(cols, dtype=np.uint32)
+    out = np.zeros((max(rows.size, 1), max(cols.size, 1)), dtype=np.float64)
+    lib().orc_distance_block(_p(L.ids), _p(L.cnt), _p(L.off), _p(L.K), _p(rows), rows.size, _p(cols),
+                             cols.size, delta, _p(out))
+    return out[:rows.size, :cols.size]
+
+
 def distance_matrix(L: Lists, idx, delta: float):
     """Equations 1-2 for every ordered pair of the sequences idx (n x n)."""
-    idx = np.ascontiguousarray(idx, dtype=np.uint32)
-    n = idx.size
-    out = np.zeros((max(n, 1), max(n, 1)), dtype=np.float64)
-    lib().orc_distance_matrix(_p(L.ids), _p(L.cnt), _p(L.off), _p(L.K), _p(idx), n, delta, _p(out))
-    return out[:n, :n]
+    return distance_block(L, idx, idx, delta)
 
 
 def upgma(d: np.ndarray):

@@ -388,15 +388,16 @@ void orc_global_rank_rows(const uint16_t *ids, const uint16_t *cnt, const uint64
 
 /* ---- per-bucket distance matrix and guide tree ---- */
 
-/* Equations 1-2 for every ordered pair of the n sequences idx[0..n):
- * out[r*n + c] = d(idx[r], idx[c]), diagonal included (F = 1 there). */
-void orc_distance_matrix(const uint16_t *ids, const uint16_t *cnt, const uint64_t *off,
-                         const uint32_t *K, const uint32_t *idx, uint32_t n, double delta,
-                         double *out)
+/* Equations 1-2 for the pairs rows[0..nr) x cols[0..nc):
+ * out[r*nc + c] = d(rows[r], cols[c]) (F = 1 when both are the same
+ * sequence). */
+void orc_distance_block(const uint16_t *ids, const uint16_t *cnt, const uint64_t *off,
+                        const uint32_t *K, const uint32_t *rows, uint32_t nr, const uint32_t *cols,
+                        uint32_t nc, double delta, double *out)
 {
-    for (uint32_t r = 0; r < n; r++)
-        for (uint32_t c = 0; c < n; c++)
-            out[(uint64_t)r * n + c] = orc_pair_distance(ids, cnt, off, K, idx[r], idx[c], delta);
+    for (uint32_t r = 0; r < nr; r++)
+        for (uint32_t c = 0; c < nc; c++)
+            out[(uint64_t)r * nc + c] = orc_pair_distance(ids, cnt, off, K, rows[r], cols[c], delta);
 }
 
 /* UPGMA (unweighted pair-group method with arithmetic mean, i.e. average
