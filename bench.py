@@ -34,25 +34,36 @@ WORKLOADS = {
 }
 
 
-# HBM bytes per launch of rank_pairs_kernel on the paper-scale workload from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain-copy calibration
-# (profiles/rank_pairs_paper20k.md).  Reported only while the kernel's sources
-# hash to the measured version and the same work-list shape is in use.
-TRAFFIC = {"sources": ["paper_0905_1744_amd/csrc/pair.hip", "paper_0905_1744_amd/csrc/bitcount.h",
-                       "paper_0905_1744_amd/csrc/klog.h"],
-           "sha256_16": "a2e085b7d3062025", "workload": "paper20k", "rows_per_workgroup": 2,
-           "bytes_per_launch": 837040845}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by
+# a plain-copy calibration (profiles/rank_pairs_paper20k.md,
+# profiles/rank_cross_global100k.md).  Reported only while the kernel's
+# sources hash to the measured version and the same work-list shape is in use.
+RANK_SOURCES = ["paper_0905_1744_amd/csrc/pair.hip", "paper_0905_1744_amd/csrc/tile.h",
+                "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h"]
+TRAFFIC = {
+    "rank_pairs_kernel": {"sources": RANK_SOURCES, "sha256_16": "2f650a120323f405",
+                          "workload": "paper20k", "rows_per_workgroup": 2, "bytes_per_launch": 839851227},
+    "rank_cross_kernel": {"sources": ["paper_0905_1744_amd/csrc/cross.hip", "paper_0905_1744_amd/csrc/tile.h",
+                                      "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h"],
+                          "sha256_16": None, "workload": "global100k", "rows_per_workgroup": None,
+                          "bytes_per_launch": 2832240965},
+}
 
 
-def measured_traffic(workload, rows):
+def sources_hash(paths):
     import hashlib
-    if workload != TRAFFIC["workload"] or rows != TRAFFIC["rows_per_workgroup"]:
-        return None
     h = hashlib.sha256()
-    for p in TRAFFIC["sources"]:
+    for p in paths:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
-    return TRAFFIC["bytes_per_launch"] if h.hexdigest()[:16] == TRAFFIC["sha256_16"] else None
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, rows):
+    t = TRAFFIC[kernel]
+    if workload != t["workload"] or rows != t["rows_per_workgroup"]:
+        return None
+    return t["bytes_per_launch"] if sources_hash(t["sources"]) == t["sha256_16"] else None
 
 
 def probe_count(D):
@@ -218,6 +229,85 @@ def bench_global(args):
         "table1": cmp,
     }
     kb.destroy()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def bench_trees(args):
+    """The step after the split (Section 3.1.3's input): the B buckets'
+    sequences gathered, each bucket's k-mer distance matrix and its UPGMA
+    guide tree.  The ranks come from the centralized rank, computed before
+    the timed region."""
+    import numpy as np
+    import torch
+
+    import paper_0905_1744_amd as kd
+    import synth
+
+    which = {"trees20k": "paper20k", "trees100k": "large100k"}[args.workload]
+    ss = synth.paper20k() if which == "paper20k" else synth.large100k()
+    N, B, delta = ss.n, ss.B, args.delta
+    print(f"[bench] bucket guide trees on {which}: N={N} B={B}", file=sys.stderr, flush=True)
+    dev = torch.device("cuda", 0)
+    res = torch.from_numpy(ss.residues).to(dev)
+    off = torch.from_numpy(ss.offsets.view(np.int64)).to(dev)
+    ctx = kd.Context(0)
+    ks = ctx.kmer_count(res, off)
+    R = ctx.kmer_rank(ks, delta)
+    ks.destroy()
+
+    def step():
+        return ctx.bucket_trees(res, off, R, B, delta)
+
+    for _ in range(args.warmup):
+        out = step()
+    torch.cuda.synchronize()
+    ctx.enable_timing(True, stages=("dist", "tree"))
+    ctx.reset_timing()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = ctx.stage_times()
+    nb = min(args.steps, 3)
+    ctx.enable_timing(True)
+    ctx.reset_timing()
+    for _ in range(nb):
+        out = step()
+    stages = ctx.stage_times()
+    ctx.enable_timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    first = out["set_first"].astype(np.int64)
+    n = np.diff(first)
+    pairs = int((n * (n - 1) // 2).sum())
+    t_dist = st["dist"][0] / max(st["dist"][1], 1) / 1e3
+    t_tree = st["tree"][0] / max(st["tree"][1], 1) / 1e3
+    # the bucket matrices' pairs: lists of both sequences; work = sum of min(D)
+    kb = ctx.kmer_count_batch(*ctx.gather_sequences(res, off, out["order"]), first.astype(np.uint32))
+    _, _, loff = kb.export_lists()
+    D = np.diff(loff.cpu().numpy())
+    kb.destroy()
+    probes = sum(probe_count(D[a:b]) for a, b in zip(first[:-1], first[1:]))
+    a = probes / t_dist / 1e12
+    line = {
+        "metric": METRIC, "value": pairs / (ms_per_step / 1e3), "unit": "pair-similarities/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16/f64",
+        "data": "synthetic",
+        "config": {"workload": "bucket guide trees, " + WORKLOADS[which], "N": N, "B": B, "delta": delta,
+                   "bucket_sizes": {"min": int(n.min()), "max": int(n.max())}, "pairs_per_step": pairs,
+                   "step": ("sample_partition + kd_gather_sequences + kmer_count_batch (buckets) + "
+                            "kmer_distance_matrices + upgma_trees")},
+        "stages_ms_per_step": {k: v[0] / nb for k, v in stages.items() if v[1]},
+        "roofline": {"bound": "alu", "achieved": a, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
+                     "frac": a / PEAK_TPROBE, "traffic": None, "kernel": "dist_pairs_kernel",
+                     "kernel_ms": t_dist * 1e3, "work_per_launch": {"probes": probes, "pairs": pairs}},
+        "upgma": {"kernel": "upgma_kernel", "ms": t_tree * 1e3, "merges": int((n - 1).sum()),
+                  "us_per_merge_step": t_tree * 1e6 / max(int(n.max()) - 1, 1),
+                  "note": "one workgroup per bucket; merge steps are sequential, so the time is "
+                          "the largest bucket's steps x the latency of one step"},
+    }
     ctx.close()
     print(json.dumps(line), flush=True)
 
@@ -399,7 +489,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS) + ["batched", "served", "global20k", "global100k"])
+    ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS) + ["batched", "served", "global20k", "global100k",
+                                                     "trees20k", "trees100k"])
     ap.add_argument("--sets", type=int, default=4096, help="batched workload: number of sets")
     ap.add_argument("--jobs", type=int, default=300, help="served workload: jobs per arrival rate")
     ap.add_argument("--rates", default="10,20,50,100,200,500,1000,2000,4000",
@@ -438,6 +529,9 @@ def main():
         return
     if args.workload in ("global20k", "global100k"):
         bench_global(args)
+        return
+    if args.workload in ("trees20k", "trees100k"):
+        bench_trees(args)
         return
 
     import numpy as np
@@ -504,7 +598,7 @@ def main():
     achieved = probes / t_pair / 1e12
     rows = tune["rows_per_workgroup"] if tune else 4
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
-                "frac": achieved / PEAK_TPROBE, "traffic": measured_traffic(args.workload, rows),
+                "frac": achieved / PEAK_TPROBE, "traffic": measured_traffic("rank_pairs_kernel", args.workload, rows),
                 "kernel": "rank_pairs_kernel", "kernel_ms": t_pair * 1e3,
                 "work_per_launch": {"probes": probes, "pairs": pairs}}
     line = {

@@ -86,8 +86,11 @@ void *kd_ctx_stream(kd_ctx *ctx);
 #define KD_STAGE_GLOBAL 6     /* kmer_rank_global: every sequence against the samples
                                  (its sample choice is timed as partition, the samples'
                                  layout as count + layout, its finalize as finalize) */
-#define KD_NSTAGES 7
-#define KD_TIME_MASK 0x100    /* enable argument: bits 0..6 select stages */
+#define KD_STAGE_GATHER 7     /* kd_gather_sequences */
+#define KD_STAGE_DIST 8       /* kmer_distance_matrices */
+#define KD_STAGE_TREE 9       /* upgma_trees */
+#define KD_NSTAGES 10
+#define KD_TIME_MASK 0x10000  /* enable argument: bits 0..9 select stages */
 kd_status kd_ctx_enable_timing(kd_ctx *ctx, int enable);
 kd_status kd_ctx_stage_time(kd_ctx *ctx, int stage, double *ms, uint64_t *launches);
 kd_status kd_ctx_reset_timing(kd_ctx *ctx);
@@ -217,6 +220,10 @@ kd_status kmer_count_batch(kd_ctx *ctx, const uint8_t *residues, const uint64_t 
                            uint64_t n_residues, uint32_t nsets, const uint32_t *set_first,
                            kd_set **out);
 uint32_t kd_set_count(const kd_set *set); /* number of sets it holds */
+/* The bounds of its sets: first receives kd_set_count + 1 host u32 values
+ * (set s = sequences first[s] .. first[s+1]-1).  Errors: KD_EINVAL for
+ * NULL. */
+kd_status kd_set_first(const kd_set *set, uint32_t *first);
 
 /* sample_partition of every set, one workgroup per set.
  *   ranks, bucket, order  device f64/u32/u32[set_first[nsets]]; set s uses
@@ -268,6 +275,55 @@ kd_status kd_batch_run(kd_ctx *ctx, const uint8_t *residues, const uint64_t *off
  * finite, or `blocks` counted on another context. */
 kd_status kmer_rank_global(kd_ctx *ctx, const kd_set *blocks, const double *local_ranks,
                            uint32_t k, double delta, double *ranks, uint32_t *samples);
+
+/* ------------------------------------------------- buckets and guide trees */
+
+/* Redistribution on one device (Section 3.1.2: bucket i's sequences go to
+ * processor i; Algorithm 2 step 11): sequences order[0..n) of `residues`
+ * (input indices, e.g. sample_partition's order) written back to back.
+ *   residues, offsets  device u8[n_residues], u64[n_seqs+1] as for kmer_count
+ *   out_residues       device u8[out_capacity]
+ *   out_offsets        device u64[n+1]: sequence x of the output is
+ *                      out_residues[out_offsets[x] .. out_offsets[x+1])
+ * The stream is synchronized once (to check the size before copying).
+ * Errors: KD_EINVAL for a NULL argument, an entry of order >= n_seqs, a
+ * gathered sequence whose offsets decrease or pass n_residues, or a total
+ * length above out_capacity (no residue is copied then). */
+kd_status kd_gather_sequences(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                              uint32_t n_seqs, uint64_t n_residues, const uint32_t *order,
+                              uint32_t n, uint8_t *out_residues, uint64_t out_capacity,
+                              uint64_t *out_offsets);
+
+/* The k-mer distance matrix of every set of a counted object: Equations
+ * 1-2 for every ordered pair of sequences of the set, the pairwise
+ * similarity matrix that a bucket's local alignment starts from (the
+ * generic scheme of Section 2, run per bucket in Section 3.1.3).
+ *   dist  device f64[sum_s n_s^2]: set s's n_s x n_s matrix, row-major in
+ *         the set's input order, starts after the matrices of sets 0..s-1;
+ *         the diagonal holds -ln(1 + delta) (F = 1)
+ * Errors: KD_EINVAL for delta <= 0 or not finite, a NULL argument, or a set
+ * counted on another context. */
+kd_status kmer_distance_matrices(kd_ctx *ctx, const kd_set *set, double delta, double *dist);
+
+/* UPGMA (average linkage) guide tree of each of nsets dissimilarity
+ * matrices laid out as kmer_distance_matrices writes them (set s has
+ * n_s = set_first[s+1] - set_first[s] members; only the upper triangle is
+ * read; dist is not modified).  Leaf i of a set is its i-th member; step t
+ * merges the two clusters whose slots a < b hold the smallest D[a][b]
+ * (ties: smallest a, then smallest b), gives the result id n_s + t and slot
+ * a, and sets D[a][k] = (n_a D[a][k] + n_b D[b][k]) / (n_a + n_b) for the
+ * other clusters k (rounded after each product, the sum and the quotient).
+ *   set_first  host u32[nsets+1], set_first[0] = 0, every set non-empty
+ *   merges     device i32[2 * (set_first[nsets] - nsets)]: set s's n_s - 1
+ *              steps start at 2 (set_first[s] - s), each the two merged
+ *              ids, smaller first
+ *   heights    device f64[set_first[nsets] - nsets]: D[a][b] / 2 per step
+ * Device memory: a working copy of dist.  The stream is synchronized once.
+ * Errors: KD_EINVAL for a NULL argument, a malformed set_first, a set of
+ * more than 4096 members, or a matrix whose remaining entries cannot be
+ * ordered (NaN). */
+kd_status upgma_trees(kd_ctx *ctx, uint32_t nsets, const uint32_t *set_first, const double *dist,
+                      int32_t *merges, double *heights);
 
 /* ----------------------------------------------------------------- server */
 

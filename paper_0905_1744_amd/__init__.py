@@ -94,11 +94,15 @@ def lib():
         "sample_partition": (i32, [P, P, u32, u32, P, P, P, P, P]),
         "kmer_count_batch": (i32, [P, P, P, u64, u32, P, PP]),
         "kd_set_count": (u32, [P]),
+        "kd_set_first": (i32, [P, P]),
         "sample_partition_batch": (i32, [P, P, u32, P, P, P, P, P, P, P]),
         "kd_batch_run": (i32, [P, P, P, u64, u32, P, P, C.c_double, P, P, P, P]),
         "kd_autotune": (i32, [P, P, C.c_double, C.POINTER(u32), C.POINTER(C.c_double)]),
         "kd_ctx_set_rows_per_task": (i32, [P, u32, u32, u32]),
         "kmer_rank_global": (i32, [P, P, P, u32, C.c_double, P, P]),
+        "kd_gather_sequences": (i32, [P, P, P, u32, u64, P, u32, P, u64, P]),
+        "kmer_distance_matrices": (i32, [P, P, C.c_double, P]),
+        "upgma_trees": (i32, [P, u32, P, P, P, P]),
         "kd_server_create": (i32, [C.c_int, C.POINTER(ServerOpts), PP]),
         "kd_server_submit": (i32, [P, C.POINTER(Job), C.POINTER(u64)]),
         "kd_server_poll": (i32, [P, C.POINTER(Done), u32, C.POINTER(u32), C.c_int64]),
@@ -146,6 +150,14 @@ class KmerSet:
     @property
     def entries(self) -> int:
         return int(lib().kd_set_entries(self.handle))
+
+    def set_first(self) -> np.ndarray:
+        """Bounds of the sets it holds (nsets + 1 entries)."""
+        f = np.zeros(self.nsets + 1, dtype=np.uint32)
+        st = lib().kd_set_first(self.handle, f.ctypes.data_as(C.c_void_p))
+        if st != KD_OK:
+            raise KdError(st, "kd_set_first")
+        return f
 
     def export_lists(self):
         """(ids u16, counts u16, off u64) as CUDA tensors (int16/int16/int64 storage)."""
@@ -212,13 +224,14 @@ class Context:
         except Exception:
             pass
 
-    STAGES = ("count", "layout", "pairs", "finalize", "partition", "similarity", "global")
+    STAGES = ("count", "layout", "pairs", "finalize", "partition", "similarity", "global", "gather",
+              "dist", "tree")
 
     def enable_timing(self, on: bool = True, stages=None):
         """Time every stage, or only the named ones (each costs two events)."""
         arg = 0
         if on:
-            arg = 1 if stages is None else 0x100 | sum(1 << self.STAGES.index(n) for n in stages)
+            arg = 1 if stages is None else 0x10000 | sum(1 << self.STAGES.index(n) for n in stages)
         self._check(lib().kd_ctx_enable_timing(self.handle, arg), "kd_ctx_enable_timing")
 
     def reset_timing(self):
@@ -319,6 +332,61 @@ class Context:
         finally:
             kb.destroy()
         return dict(local=loc, ranks=R, samples=smp)
+
+    # ------------------------------------------- buckets and guide trees
+    def gather_sequences(self, residues, offsets, order):
+        """Sequences order[0..n) written back to back (redistribution):
+        returns (residues, offsets) of the gathered set on the device."""
+        res = _dev_tensor(residues, torch.uint8, self.device)
+        off = _dev_tensor(offsets, torch.int64, self.device)
+        idx = _dev_tensor(order, torch.int32, self.device)
+        n = idx.numel()
+        out = torch.empty(max(res.numel(), 1), dtype=torch.uint8, device=self.device)
+        out_off = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        self._check(lib().kd_gather_sequences(self.handle, _ptr(res), _ptr(off), off.numel() - 1,
+                                              res.numel(), _ptr(idx), n, _ptr(out), out.numel(),
+                                              _ptr(out_off)), "kd_gather_sequences")
+        return out[:res.numel()], out_off
+
+    def distance_matrices(self, kset: KmerSet, delta: float = 0.1):
+        """Equations 1-2 for every pair of every set: one flat f64 tensor,
+        set s's n_s x n_s matrix after those of the sets before it."""
+        first = kset.set_first()
+        sizes = np.diff(first.astype(np.int64))
+        D = torch.empty(max(int((sizes * sizes).sum()), 1), dtype=torch.float64, device=self.device)
+        self._check(lib().kmer_distance_matrices(self.handle, kset.handle, float(delta), _ptr(D)),
+                    "kmer_distance_matrices")
+        return D[:int((sizes * sizes).sum())]
+
+    def upgma(self, set_first, dist):
+        """UPGMA guide tree of each set's matrix (layout of
+        distance_matrices): (merges (sum n_s - 1, 2) int32, heights)."""
+        sf = np.ascontiguousarray(np.asarray(set_first, dtype=np.uint32))
+        D = _dev_tensor(dist, torch.float64, self.device)
+        sizes = np.diff(sf.astype(np.int64))
+        if sf.ndim != 1 or sf.size < 2 or D.numel() != int((sizes * sizes).sum()):
+            raise ValueError("dist must hold the sets' n_s x n_s matrices back to back")
+        m = int(sf[-1]) - (sf.size - 1)
+        merges = torch.empty((max(m, 1), 2), dtype=torch.int32, device=self.device)
+        heights = torch.empty(max(m, 1), dtype=torch.float64, device=self.device)
+        self._check(lib().upgma_trees(self.handle, sf.size - 1, sf.ctypes.data_as(C.c_void_p), _ptr(D),
+                                      _ptr(merges), _ptr(heights)), "upgma_trees")
+        return merges[:m], heights[:m]
+
+    def bucket_trees(self, residues, offsets, ranks, B: int, delta: float = 0.1):
+        """The step after the split: the B buckets' sequences gathered, each
+        bucket's distance matrix and UPGMA guide tree.  Returns dict(order,
+        set_first (bucket bounds), dist, merges, heights)."""
+        part = self.sample_partition(ranks, B)
+        res, off = self.gather_sequences(residues, offsets, part["order"])
+        first = u32(part["offsets"])
+        kb = self.kmer_count_batch(res, off, first)
+        try:
+            D = self.distance_matrices(kb, delta)
+        finally:
+            kb.destroy()
+        merges, heights = self.upgma(first, D)
+        return dict(order=part["order"], set_first=first, dist=D, merges=merges, heights=heights)
 
     # ------------------------------------------------------------ batches
     @staticmethod

@@ -2,6 +2,9 @@
 // step 6): every sequence of a counted batch of blocks against the samples
 // gathered from all blocks, with the tile machinery of the all-pairs rank
 // kernel (tile.h).
+#include <algorithm>
+#include <vector>
+
 #include "tile.h"
 
 namespace kd {
@@ -115,6 +118,74 @@ hipError_t launch_cross_finalize(hipStream_t st, const Segs &sg, uint32_t N, uin
   hipLaunchKernelGGL(cross_finalize_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, S,
                      ranks);
   return hipGetLastError();
+}
+
+// Work list of the globalized-rank pass.
+//  * The column groups of all sets are ordered by decreasing padded list
+//    length (grp_len, read back from the device; ties by group number) into
+//    gperm, and consecutive runs of `gpt` of them form the strips, so the
+//    groups a workgroup's waves walk together are about equally long.
+//    gpt = 32 (two groups per wave) unless that leaves fewer than two
+//    workgroups per compute unit, then 16 (one group per wave).
+//  * Each strip is cut into at most one XCD's worth of runs of sample row
+//    blocks.
+//  * Placement: workgroup t runs on XCD t % 8 and an XCD starts its
+//    workgroups in order as its compute units free up.  Tasks, longest
+//    first, are assigned to the XCD whose next free compute unit (in a
+//    simulation with a cost of rows x list length per task) frees first,
+//    ties to the lowest XCD, so consecutive tasks of one strip tend to
+//    share an XCD and its L2; the list then interleaves the XCDs' queues.
+//    Positions past an XCD's queue hold empty tasks (no row blocks, no
+//    groups).
+// gperm gets gpt (strips + 1) entries, 0xFFFFFFFF past the last group.
+constexpr uint32_t kXcds = 8;
+
+uint32_t make_cross_tasks(const uint32_t *grp_len, uint32_t Gtot, uint32_t RBs, int cus,
+                          std::vector<CrossTask> &out, std::vector<uint32_t> &gperm) {
+  out.clear();
+  const uint32_t ncu = (uint32_t)std::max(cus, (int)kXcds);
+  const uint32_t per_xcd = ncu / kXcds;
+  const uint32_t runs = std::max<uint32_t>(1, std::min(RBs, per_xcd));
+  const uint32_t rbt = (RBs + runs - 1) / runs;
+  const uint32_t nrun = (RBs + rbt - 1) / rbt;
+  uint32_t gpt = kGroupsPerTask;
+  if ((uint64_t)((Gtot + 31) / 32) * nrun < 2ull * ncu) gpt = kGroupsPerTask / 2;
+  const uint32_t strips = (Gtot + gpt - 1) / gpt;
+  gperm.assign((size_t)(strips + 1) * gpt, 0xFFFFFFFFu);
+  for (uint32_t g = 0; g < Gtot; g++) gperm[g] = g;
+  std::stable_sort(gperm.begin(), gperm.begin() + Gtot,
+                   [&](uint32_t a, uint32_t b) { return grp_len[a] > grp_len[b]; });
+  // per-XCD min-heaps of compute-unit free times
+  std::vector<std::vector<uint64_t>> cu(kXcds, std::vector<uint64_t>(per_xcd, 0));
+  std::vector<std::vector<CrossTask>> per(kXcds);
+  auto later = [](uint64_t a, uint64_t b) { return a > b; };
+  for (uint32_t s = 0; s < strips; s++) {
+    const uint32_t g0 = s * gpt;
+    // the wave with the most work: groups w and gpt-1-w (gpt = 32) or w
+    uint64_t wmax = 0;
+    for (uint32_t w = 0; w < 16; w++) {
+      uint64_t l = gperm[g0 + w] != 0xFFFFFFFFu ? grp_len[gperm[g0 + w]] : 0;
+      if (gpt == 32 && gperm[g0 + 31 - w] != 0xFFFFFFFFu) l += grp_len[gperm[g0 + 31 - w]];
+      wmax = std::max(wmax, l);
+    }
+    for (uint32_t rb0 = 0; rb0 < RBs; rb0 += rbt) {
+      const uint32_t rb1 = std::min(rb0 + rbt, RBs);
+      const uint64_t cost = (uint64_t)(rb1 - rb0) * (wmax + 64);
+      uint32_t bx = 0;
+      for (uint32_t x = 1; x < kXcds; x++)
+        if (cu[x].front() < cu[bx].front()) bx = x;
+      std::pop_heap(cu[bx].begin(), cu[bx].end(), later);
+      cu[bx].back() += cost;
+      std::push_heap(cu[bx].begin(), cu[bx].end(), later);
+      per[bx].push_back({g0, rb0, rb1});
+    }
+  }
+  size_t L = 0;
+  for (const auto &v : per) L = std::max(L, v.size());
+  out.assign(L * kXcds, CrossTask{strips * gpt, 0, 0});
+  for (uint32_t x = 0; x < kXcds; x++)
+    for (size_t j = 0; j < per[x].size(); j++) out[j * kXcds + x] = per[x][j];
+  return gpt;
 }
 
 }  // namespace kd

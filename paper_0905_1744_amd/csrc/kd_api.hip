@@ -681,6 +681,12 @@ extern "C" kd_status kmer_count_batch(kd_ctx *ctx, const uint8_t *residues,
 
 extern "C" uint32_t kd_set_count(const kd_set *s) { return s ? s->nsets : 0; }
 
+extern "C" kd_status kd_set_first(const kd_set *s, uint32_t *first) {
+  if (!s || !first) return KD_EINVAL;
+  std::memcpy(first, s->seq_first.data(), sizeof(uint32_t) * s->seq_first.size());
+  return KD_OK;
+}
+
 extern "C" uint32_t kd_set_size(const kd_set *s) { return s ? s->v.N : 0; }
 extern "C" uint64_t kd_set_entries(const kd_set *s) { return s ? s->entries : 0; }
 
@@ -769,74 +775,6 @@ namespace {
 
 kd_status plan_partition(uint32_t nsets, const uint32_t *first, const uint32_t *Bs,
                          std::vector<PartDesc> &desc, uint64_t &scratch);
-
-// Work list of the globalized-rank pass.
-//  * The column groups of all sets are ordered by decreasing padded list
-//    length (grp_len, read back from the device; ties by group number) into
-//    gperm, and consecutive runs of `gpt` of them form the strips, so the
-//    groups a workgroup's waves walk together are about equally long.
-//    gpt = 32 (two groups per wave) unless that leaves fewer than two
-//    workgroups per compute unit, then 16 (one group per wave).
-//  * Each strip is cut into at most one XCD's worth of runs of sample row
-//    blocks.
-//  * Placement: workgroup t runs on XCD t % 8 and an XCD starts its
-//    workgroups in order as its compute units free up.  Tasks, longest
-//    first, are assigned to the XCD whose next free compute unit (in a
-//    simulation with a cost of rows x list length per task) frees first,
-//    ties to the lowest XCD, so consecutive tasks of one strip tend to
-//    share an XCD and its L2; the list then interleaves the XCDs' queues.
-//    Positions past an XCD's queue hold empty tasks (no row blocks, no
-//    groups).
-// gperm gets gpt (strips + 1) entries, 0xFFFFFFFF past the last group.
-constexpr uint32_t kXcds = 8;
-
-uint32_t make_cross_tasks(const uint32_t *grp_len, uint32_t Gtot, uint32_t RBs, int cus,
-                          std::vector<CrossTask> &out, std::vector<uint32_t> &gperm) {
-  out.clear();
-  const uint32_t ncu = (uint32_t)std::max(cus, (int)kXcds);
-  const uint32_t per_xcd = ncu / kXcds;
-  const uint32_t runs = std::max<uint32_t>(1, std::min(RBs, per_xcd));
-  const uint32_t rbt = (RBs + runs - 1) / runs;
-  const uint32_t nrun = (RBs + rbt - 1) / rbt;
-  uint32_t gpt = kGroupsPerTask;
-  if ((uint64_t)((Gtot + 31) / 32) * nrun < 2ull * ncu) gpt = kGroupsPerTask / 2;
-  const uint32_t strips = (Gtot + gpt - 1) / gpt;
-  gperm.assign((size_t)(strips + 1) * gpt, 0xFFFFFFFFu);
-  for (uint32_t g = 0; g < Gtot; g++) gperm[g] = g;
-  std::stable_sort(gperm.begin(), gperm.begin() + Gtot,
-                   [&](uint32_t a, uint32_t b) { return grp_len[a] > grp_len[b]; });
-  // per-XCD min-heaps of compute-unit free times
-  std::vector<std::vector<uint64_t>> cu(kXcds, std::vector<uint64_t>(per_xcd, 0));
-  std::vector<std::vector<CrossTask>> per(kXcds);
-  auto later = [](uint64_t a, uint64_t b) { return a > b; };
-  for (uint32_t s = 0; s < strips; s++) {
-    const uint32_t g0 = s * gpt;
-    // the wave with the most work: groups w and gpt-1-w (gpt = 32) or w
-    uint64_t wmax = 0;
-    for (uint32_t w = 0; w < 16; w++) {
-      uint64_t l = gperm[g0 + w] != 0xFFFFFFFFu ? grp_len[gperm[g0 + w]] : 0;
-      if (gpt == 32 && gperm[g0 + 31 - w] != 0xFFFFFFFFu) l += grp_len[gperm[g0 + 31 - w]];
-      wmax = std::max(wmax, l);
-    }
-    for (uint32_t rb0 = 0; rb0 < RBs; rb0 += rbt) {
-      const uint32_t rb1 = std::min(rb0 + rbt, RBs);
-      const uint64_t cost = (uint64_t)(rb1 - rb0) * (wmax + 64);
-      uint32_t bx = 0;
-      for (uint32_t x = 1; x < kXcds; x++)
-        if (cu[x].front() < cu[bx].front()) bx = x;
-      std::pop_heap(cu[bx].begin(), cu[bx].end(), later);
-      cu[bx].back() += cost;
-      std::push_heap(cu[bx].begin(), cu[bx].end(), later);
-      per[bx].push_back({g0, rb0, rb1});
-    }
-  }
-  size_t L = 0;
-  for (const auto &v : per) L = std::max(L, v.size());
-  out.assign(L * kXcds, CrossTask{strips * gpt, 0, 0});
-  for (uint32_t x = 0; x < kXcds; x++)
-    for (size_t j = 0; j < per[x].size(); j++) out[j * kXcds + x] = per[x][j];
-  return gpt;
-}
 
 // Pinned host area of at least `bytes`, valid until the next call; only
 // reallocated while no copy into it is pending (callers synchronize first).
@@ -935,6 +873,106 @@ extern "C" kd_status kmer_rank_global(kd_ctx *ctx, const kd_set *s, const double
   kd_set_destroy(ss);  // its blocks return to the pool; stream order keeps them valid
   if (!d_work) return KD_ENOMEM;
   return from_hip(e);
+}
+
+// ------------------------------------------------ buckets and guide trees
+
+extern "C" kd_status kd_gather_sequences(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                                         uint32_t n_seqs, uint64_t n_residues, const uint32_t *order,
+                                         uint32_t n, uint8_t *out_residues, uint64_t out_capacity,
+                                         uint64_t *out_offsets) {
+  if (!ctx || !offsets || !out_offsets || (n > 0 && !order)) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  Scope tmp(ctx);
+  unsigned long long *err = tmp.get<unsigned long long>(1);
+  if (!err) return KD_ENOMEM;
+  StageTimer t(ctx, KD_STAGE_GATHER);
+  KD_TRY(launch_fill_u64(st, err, 1, ~0ull));
+  // sizes first (no bytes move while the capacity is unchecked)
+  KD_TRY(launch_gather(st, residues, offsets, n_seqs, n_residues, order, n, nullptr, 0, out_offsets,
+                       err));
+  unsigned long long *hm = static_cast<unsigned long long *>(ctx->pinned);
+  KD_TRY(hipMemcpyAsync(hm, err, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  KD_TRY(hipMemcpyAsync(hm + 1, out_offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  KD_TRY(hipStreamSynchronize(st));
+  if (hm[0] != ~0ull || hm[1] > out_capacity) return KD_EINVAL;
+  if (hm[1] > 0 && (!residues || !out_residues)) return KD_EINVAL;
+  KD_TRY(launch_gather(st, residues, offsets, n_seqs, n_residues, order, n, out_residues, out_capacity,
+                       out_offsets, err));
+  t.done();
+  return KD_OK;
+}
+
+namespace {
+
+// first element of each set's n x n matrix; false if a count overflows
+bool matrix_offsets(uint32_t nsets, const uint32_t *first, std::vector<uint64_t> &doff) {
+  doff.resize(nsets + 1);
+  doff[0] = 0;
+  for (uint32_t q = 0; q < nsets; q++) {
+    const uint64_t n = first[q + 1] - first[q];
+    doff[q + 1] = doff[q] + n * n;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" kd_status kmer_distance_matrices(kd_ctx *ctx, const kd_set *s, double delta, double *dist) {
+  if (!ctx || !s || s->ctx != ctx) return KD_EINVAL;
+  if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
+  if (s->v.N == 0) return KD_OK;
+  if (!dist) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  std::vector<uint64_t> doff;
+  matrix_offsets(s->nsets, s->seq_first.data(), doff);
+  Scope tmp(ctx);
+  uint64_t *d_off = tmp.get<uint64_t>(s->nsets);
+  if (!d_off) return KD_ENOMEM;
+  KD_TRY(upload(ctx, d_off, doff.data(), sizeof(uint64_t) * s->nsets));
+  StageTimer t(ctx, KD_STAGE_DIST);
+  KD_TRY(launch_distances(ctx->stream, s->segs, s->v.N, s->d_view, s->tasks, s->ntasks, d_off, delta,
+                          dist));
+  t.done();
+  return KD_OK;
+}
+
+extern "C" kd_status upgma_trees(kd_ctx *ctx, uint32_t nsets, const uint32_t *set_first,
+                                 const double *dist, int32_t *merges, double *heights) {
+  if (!ctx || !set_first || nsets == 0 || !dist) return KD_EINVAL;
+  if (set_first[0] != 0) return KD_EINVAL;
+  for (uint32_t q = 0; q < nsets; q++) {
+    const uint32_t n = set_first[q + 1] - set_first[q];
+    if (set_first[q + 1] <= set_first[q] || n > kTreeMaxSeqs) return KD_EINVAL;
+  }
+  const uint32_t N = set_first[nsets];
+  if (N > nsets && (!merges || !heights)) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  std::vector<uint64_t> doff;
+  matrix_offsets(nsets, set_first, doff);
+  Scope tmp(ctx);
+  const size_t hb = sizeof(uint64_t) * nsets + sizeof(uint32_t) * (nsets + 1);
+  char *d_meta = tmp.get<char>(hb);
+  double *work = tmp.get<double>(doff[nsets]);
+  unsigned long long *err = tmp.get<unsigned long long>(1);
+  if (!d_meta || !work || !err) return KD_ENOMEM;
+  std::vector<char> h(hb);
+  std::memcpy(h.data(), doff.data(), sizeof(uint64_t) * nsets);
+  std::memcpy(h.data() + sizeof(uint64_t) * nsets, set_first, sizeof(uint32_t) * (nsets + 1));
+  KD_TRY(upload(ctx, d_meta, h.data(), hb));
+  const uint64_t *d_off = reinterpret_cast<const uint64_t *>(d_meta);
+  const uint32_t *d_first = reinterpret_cast<const uint32_t *>(d_meta + sizeof(uint64_t) * nsets);
+  StageTimer t(ctx, KD_STAGE_TREE);
+  KD_TRY(launch_fill_u64(st, err, 1, ~0ull));
+  KD_TRY(hipMemcpyAsync(work, dist, sizeof(double) * doff[nsets], hipMemcpyDeviceToDevice, st));
+  KD_TRY(launch_upgma(st, nsets, d_first, d_off, work, merges, heights, err));
+  t.done();
+  unsigned long long *hm = static_cast<unsigned long long *>(ctx->pinned);
+  KD_TRY(hipMemcpyAsync(hm, err, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  KD_TRY(hipStreamSynchronize(st));
+  return hm[0] == ~0ull ? KD_OK : KD_EINVAL;
 }
 
 // ------------------------------------------------------------ autotune

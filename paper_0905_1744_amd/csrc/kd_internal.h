@@ -243,6 +243,10 @@ hipError_t launch_rank_cross(hipStream_t st, const Segs &cols, const SetView *ro
                              uint32_t gpt, double delta);
 hipError_t launch_cross_finalize(hipStream_t st, const Segs &sg, uint32_t N, uint32_t S,
                                  double *ranks);
+// host: the cross pass's work list and column-group permutation from the
+// groups' padded list lengths; returns the groups per task (16 or 32)
+uint32_t make_cross_tasks(const uint32_t *grp_len, uint32_t Gtot, uint32_t RBs, int cus,
+                          std::vector<CrossTask> &out, std::vector<uint32_t> &gperm);
 // samples[q*k + t-1] = first[q] + order[first[q] + floor(t w_q / (k+1))]
 // (order: each set's local indices in key order); first on the device
 hipError_t launch_pick_samples(hipStream_t st, const uint32_t *first, uint32_t nsets, uint32_t k,
@@ -257,6 +261,23 @@ hipError_t launch_gather_samples(hipStream_t st, const Segs &parent, const uint6
                                  const uint32_t *par_Dorig, const uint32_t *picks, uint32_t S,
                                  uint64_t *in_off, uint32_t *Dorig, uint32_t *Korig,
                                  uint32_t *nhi, uint32_t *hi_cap);
+// redistribution: out_off = exclusive sums of the lengths of order[0..n)
+// (n+1 entries), then (out != nullptr) the bytes; entries of order >=
+// n_seqs or with offsets decreasing or past nres set *err, sequences past
+// cap are not copied
+hipError_t launch_gather(hipStream_t st, const uint8_t *res, const uint64_t *off, uint32_t n_seqs,
+                         uint64_t nres, const uint32_t *order, uint32_t n, uint8_t *out, uint64_t cap,
+                         uint64_t *out_off, unsigned long long *err);
+// Equations 1-2 for every pair of every set, set q's n_q x n_q matrix at
+// dist + doff[q] (input order)
+hipError_t launch_distances(hipStream_t st, const Segs &sg, uint32_t N, const SetView *d_views,
+                            const PairTask *tasks, uint32_t ntasks, const uint64_t *doff, double delta,
+                            double *dist);
+constexpr uint32_t kTreeMaxSeqs = 4096;  // largest set upgma_trees accepts
+// UPGMA of each set's matrix at work + doff[q] (overwritten), first[] on
+// the device; a set with no comparable pair left records its index in *err
+hipError_t launch_upgma(hipStream_t st, uint32_t nsets, const uint32_t *first, const uint64_t *doff,
+                        double *work, int32_t *merges, double *heights, unsigned long long *err);
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);
 // writes the set ids of sg.pos_set / grp_set / rb_set (nsets > 1)
 hipError_t launch_seg_ids(hipStream_t st, const Segs &sg, uint32_t *pos_set, uint32_t *grp_set,

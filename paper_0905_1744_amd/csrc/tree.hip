@@ -1,0 +1,372 @@
+// After the split: each bucket's sequences are gathered together (the
+// redistribution of Section 3.1.2, Algorithm 2 step 11, done on one
+// device), their pairwise k-mer distances form one matrix per bucket
+// (Equations 1-2 for every pair of the bucket), and each matrix gives a
+// UPGMA guide tree -- the similarity matrix and guide tree of the generic
+// alignment scheme the paper's local alignment stage runs (Section 2,
+// Section 3.1.3).
+#include "radix.h"
+#include "tile.h"
+
+namespace kd {
+
+// ------------------------------------------------------ redistribution
+
+// length of sequence i when it is a valid entry, else 0 (and invalid)
+__device__ __forceinline__ uint64_t seq_len(const uint64_t *off, uint32_t n_seqs, uint64_t nres,
+                                            uint32_t i, bool &ok) {
+  ok = i < n_seqs && off[i] <= off[i + 1] && off[i + 1] <= nres;
+  return ok ? off[i + 1] - off[i] : 0;
+}
+
+// out_off[i] = sum of the lengths of order[0..i) (exclusive), one
+// workgroup; entries of order outside [0, n_seqs), or whose offsets are
+// decreasing or past nres, set *err (and count as empty).
+__global__ __launch_bounds__(1024) void gather_offsets_kernel(const uint64_t *__restrict__ off,
+                                                              uint32_t n_seqs, uint64_t nres,
+                                                              const uint32_t *__restrict__ order,
+                                                              uint32_t n, uint64_t *__restrict__ out_off,
+                                                              unsigned long long *err) {
+  __shared__ unsigned long long wsum[16];
+  const uint32_t per = (n + 1023) / 1024;
+  const uint32_t x0 = min(n, threadIdx.x * per), x1 = min(n, x0 + per);
+  unsigned long long s = 0;
+  bool bad = false;
+  for (uint32_t x = x0; x < x1; x++) {
+    bool ok;
+    s += seq_len(off, n_seqs, nres, order[x], ok);
+    bad |= !ok;
+  }
+  if (bad) atomicMin(err, 1ull);
+  unsigned long long tot;
+  unsigned long long run = block_exclusive_scan64<1024>(s, wsum, tot);
+  for (uint32_t x = x0; x < x1; x++) {
+    out_off[x] = run;
+    bool ok;
+    run += seq_len(off, n_seqs, nres, order[x], ok);
+  }
+  if (threadIdx.x == 0) out_off[n] = tot;
+}
+
+// one wave per sequence: bytes of sequence order[x] to out + out_off[x]
+__global__ __launch_bounds__(256) void gather_copy_kernel(const uint8_t *__restrict__ res,
+                                                          const uint64_t *__restrict__ off,
+                                                          uint32_t n_seqs, uint64_t nres,
+                                                          const uint32_t *__restrict__ order, uint32_t n,
+                                                          const uint64_t *__restrict__ out_off,
+                                                          uint64_t cap, uint8_t *__restrict__ out) {
+  const uint32_t x = blockIdx.x * 4u + (threadIdx.x >> 6), lane = threadIdx.x & 63u;
+  if (x >= n) return;
+  bool ok;
+  const uint32_t i = order[x];
+  const uint64_t len = seq_len(off, n_seqs, nres, i, ok), o = out_off[x];
+  if (!ok || o + len > cap) return;  // the host reports these errors
+  const uint64_t a = off[i];
+  for (uint64_t t = lane; t < len; t += 64) out[o + t] = res[a + t];
+}
+
+hipError_t launch_gather(hipStream_t st, const uint8_t *res, const uint64_t *off, uint32_t n_seqs,
+                         uint64_t nres, const uint32_t *order, uint32_t n, uint8_t *out, uint64_t cap,
+                         uint64_t *out_off, unsigned long long *err) {
+  hipLaunchKernelGGL(gather_offsets_kernel, dim3(1), dim3(1024), 0, st, off, n_seqs, nres, order, n,
+                     out_off, err);
+  KD_HIP(hipGetLastError());
+  if (n == 0 || !out) return hipSuccess;
+  hipLaunchKernelGGL(gather_copy_kernel, dim3((n + 3) / 4), dim3(256), 0, st, res, off, n_seqs, nres,
+                     order, n, out_off, cap, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- distance matrices
+
+struct DistShared {
+  RowShared row;
+  LogEntry logt[kLogEntries];
+  double ln2;
+  uint32_t rowIn[16];  // input index (within the set) of each row
+  uint16_t exc_id[kExcLds];
+  uint16_t exc_c[kExcLds * 16];
+};
+
+// d for the pairs of one 16 x 64 tile below the diagonal, written at both
+// (row, column) and (column, row) of the set's matrix (input order).
+__device__ __forceinline__ void dist_tile(const SetView &v, DistShared &sh, uint32_t rb, uint32_t g,
+                                          double delta, const uint16_t *eid, const uint16_t *ecnt,
+                                          uint32_t en, double *__restrict__ M) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t L = __builtin_amdgcn_readfirstlane(v.grp_len[g]);
+  const uint32_t hl = __builtin_amdgcn_readfirstlane(v.ghi_len[g]);
+  const uint32_t sc = 64u * g + lane;
+  const bool vc = sc < v.N;
+  const uint4 *p = reinterpret_cast<const uint4 *>(v.gids + v.grp_off[g]) + lane;
+  const uint32_t *hp = v.ghi + v.ghi_off[g] + lane;
+  uint32_t q0[4] = {0u, 0u, 0u, 0u};
+  if (hl > 0) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) q0[k] = hp[(size_t)k * 64];
+  }
+  uint32_t cnt[16];
+  column_counts(reinterpret_cast<const uint16_t *>(sh.row.T32), p, L, cnt);
+  column_excess_grouped(hp, hl, q0, sh.row.BM, eid, ecnt, en, cnt);
+  if (!vc) return;
+  const uint32_t Kc = v.K[sc];
+  const double invKc = v.invK[sc];
+  const uint64_t n = v.N, ci = v.perm[sc];
+#pragma unroll
+  for (int r = 0; r < 16; r++) {
+    const uint32_t sr = 16u * rb + r;
+    if (sc < sr && sr < v.N) {
+      const double inv = sh.row.rowK[r] < Kc ? sh.row.rowInv[r] : invKc;
+      const double d = -log_tab(fma((double)cnt[r], inv, delta), sh.logt, sh.ln2);
+      const uint64_t ri = sh.rowIn[r];
+      M[ri * n + ci] = d;
+      M[ci * n + ri] = d;
+    }
+  }
+}
+
+// The rank kernel's work list (strips of 32 column groups against runs of
+// row blocks, pairs below the diagonal only), with the pair terms stored
+// instead of summed.  doff[set] = first element of the set's matrix.
+__global__ __launch_bounds__(1024) void dist_pairs_kernel(const SetView *__restrict__ views,
+                                                          const PairTask *__restrict__ tasks,
+                                                          const uint64_t *__restrict__ doff,
+                                                          double delta, double *__restrict__ dist) {
+  __shared__ DistShared sh;
+  const PairTask tk = tasks[blockIdx.x];
+  const SetView &v = views[tk.set];
+  double *M = dist + doff[tk.set];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (uint32_t q = tid; q < (uint32_t)kLogEntries; q += 1024) log_table_entry((int)q, sh.logt[q]);
+  if (tid == 0) sh.ln2 = log(2.0);
+  clear_rows(sh.row);
+  const uint32_t ga = tk.g0 + wave, gb = tk.g0 + 31u - wave;
+  for (uint32_t rb = tk.rb0; rb < tk.rb1; rb++) {
+    if (rb > tk.rb0) {
+      const uint32_t pr = rb - 1;
+      touch_rows<false>(v, ConsecutiveRows{16u * pr, v.N}, v.exc_ids, v.exc_off[pr], v.exc_n[pr], sh.row);
+    }
+    __syncthreads();
+    const uint32_t e0 = v.exc_off[rb], en = v.exc_n[rb];
+    touch_rows<true>(v, ConsecutiveRows{16u * rb, v.N}, v.exc_ids, e0, en, sh.row);
+    if (tid < 16) sh.rowIn[tid] = 16u * rb + tid < v.N ? v.perm[16u * rb + tid] : 0u;
+    const bool lds_exc = en <= kExcLds;
+    if (lds_exc) {
+      for (uint32_t e = tid; e < en; e += 1024) sh.exc_id[e] = v.exc_ids[e0 + e];
+      for (uint32_t e = tid; e < 16u * en; e += 1024) sh.exc_c[e] = v.exc_cnt[16ull * e0 + e];
+    }
+    __syncthreads();
+    const uint16_t *eid = lds_exc ? sh.exc_id : v.exc_ids + e0;
+    const uint16_t *ecnt = lds_exc ? sh.exc_c : v.exc_cnt + 16ull * e0;
+    if (ga < v.G && rb >= 4u * ga) dist_tile(v, sh, rb, ga, delta, eid, ecnt, en, M);
+    if (gb < v.G && rb >= 4u * gb) dist_tile(v, sh, rb, gb, delta, eid, ecnt, en, M);
+    __syncthreads();
+  }
+}
+
+// the diagonal: F(i, i) = 1, d = -ln(delta + 1)
+__global__ void dist_diag_kernel(Segs sg, uint32_t N, const uint64_t *__restrict__ doff, double delta,
+                                 double *__restrict__ dist) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const uint32_t set = sg.set_of_pos(p);
+  const uint64_t a = sg.seq[set], n = sg.seq[set + 1] - a, i = p - a;
+  dist[doff[set] + i * n + i] = -log(delta + 1.0);
+}
+
+hipError_t launch_distances(hipStream_t st, const Segs &sg, uint32_t N, const SetView *d_views,
+                            const PairTask *tasks, uint32_t ntasks, const uint64_t *doff, double delta,
+                            double *dist) {
+  if (N == 0) return hipSuccess;
+  if (ntasks) {
+    hipLaunchKernelGGL(dist_pairs_kernel, dim3(ntasks), dim3(1024), 0, st, d_views, tasks, doff, delta,
+                       dist);
+    KD_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(dist_diag_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, doff, delta, dist);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ UPGMA
+//
+// One workgroup per set, on a full symmetric copy D of its matrix (n x n,
+// n <= kTreeMax).  The slot rule, tie rule and update arithmetic are those
+// of the definition (merge the active slots a < b with the smallest
+// D[a][b], ties to the smallest a then b; the merged cluster keeps slot a;
+// D[a][k] = (n_a D[a][k] + n_b D[b][k]) / (n_a + n_b) rounded step by step
+// in double), so the same matrix gives the same merges and heights.
+//
+// To find the pair, row k keeps the minimum of D[k][j] over active j > k
+// and its smallest argument.  After merging a and b: row a is recomputed
+// while its entries are updated; a row k < a takes the new D[k][a] if it
+// is smaller (or equal with a smaller column); rows k < b whose minimum sat
+// at column a or b are rescanned (one wave per row).
+
+constexpr uint32_t kTreeMax = kTreeMaxSeqs;
+constexpr uint16_t kNone16 = 0xFFFFu;
+
+struct TreeShared {
+  double rowmin[kTreeMax];
+  uint16_t rowarg[kTreeMax];
+  uint16_t size[kTreeMax];
+  uint16_t id[kTreeMax];
+  uint16_t redo[kTreeMax];
+  uint8_t act[kTreeMax];
+  double wv[16];
+  uint32_t wi[16];
+  uint32_t nredo;
+  uint32_t best_a;
+};
+
+// lexicographic (value, index) minimum
+__device__ __forceinline__ void lex_min(double &v, uint32_t &i, double v2, uint32_t i2) {
+  if (v2 < v || (v2 == v && i2 < i)) {
+    v = v2;
+    i = i2;
+  }
+}
+
+__device__ __forceinline__ void wave_lex_min(double &v, uint32_t &i) {
+#pragma unroll
+  for (int o = 32; o; o >>= 1) {
+    const double v2 = __shfl_xor(v, o, 64);
+    const uint32_t i2 = (uint32_t)__shfl_xor((int)i, o, 64);
+    lex_min(v, i, v2, i2);
+  }
+}
+
+// row k's minimum over active columns j > k (one wave)
+__device__ __forceinline__ void scan_row(TreeShared &sh, const double *D, uint32_t n, uint32_t k) {
+  const uint32_t lane = threadIdx.x & 63u;
+  double v = __builtin_inf();
+  uint32_t i = 0xFFFFFFFFu;
+  for (uint32_t j = k + 1 + lane; j < n; j += 64)
+    if (sh.act[j]) lex_min(v, i, D[(size_t)k * n + j], j);
+  wave_lex_min(v, i);
+  if (lane == 0) {
+    sh.rowmin[k] = v;
+    sh.rowarg[k] = i == 0xFFFFFFFFu ? kNone16 : (uint16_t)i;
+  }
+}
+
+#pragma clang fp contract(off)
+__device__ __forceinline__ double merge_mean(double na, double x, double nb, double y) {
+  const double p = na * x;
+  const double q = nb * y;
+  const double s = p + q;
+  return s / (na + nb);
+}
+
+// A set whose remaining pairs compare false with everything (NaN
+// distances) stops there and records its index in *err.
+__global__ __launch_bounds__(1024) void upgma_kernel(const uint32_t *__restrict__ first,
+                                                     const uint64_t *__restrict__ doff,
+                                                     double *__restrict__ work,
+                                                     int32_t *__restrict__ merges,
+                                                     double *__restrict__ heights,
+                                                     unsigned long long *err) {
+  __shared__ TreeShared sh;
+  const uint32_t set = blockIdx.x;
+  const uint32_t n = first[set + 1] - first[set];
+  double *D = work + doff[set];
+  int32_t *mg = merges + 2ull * (first[set] - set);
+  double *ht = heights + (first[set] - set);
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  for (uint32_t k = tid; k < n; k += 1024) {
+    sh.size[k] = 1;
+    sh.id[k] = (uint16_t)k;
+    sh.act[k] = 1;
+  }
+  __syncthreads();
+  for (uint32_t k = wave; k < n; k += 16) scan_row(sh, D, n, k);
+  __syncthreads();
+  for (uint32_t t = 0; t + 1 < n; t++) {
+    // the pair: lexicographic minimum of (rowmin[a], a) over active a
+    double v = __builtin_inf();
+    uint32_t i = 0xFFFFFFFFu;
+    for (uint32_t a = tid; a < n; a += 1024)
+      if (sh.act[a]) lex_min(v, i, sh.rowmin[a], a);
+    wave_lex_min(v, i);
+    if (lane == 0) {
+      sh.wv[wave] = v;
+      sh.wi[wave] = i;
+    }
+    if (tid == 0) sh.nredo = 0;
+    __syncthreads();
+    if (tid < 64) {
+      v = tid < 16 ? sh.wv[tid] : __builtin_inf();
+      i = tid < 16 ? sh.wi[tid] : 0xFFFFFFFFu;
+      wave_lex_min(v, i);
+      if (tid == 0) sh.best_a = i;
+    }
+    __syncthreads();
+    const uint32_t a = sh.best_a;
+    if (a >= n || sh.rowarg[a] == kNone16) {
+      if (tid == 0) atomicMin(err, (unsigned long long)set);
+      return;
+    }
+    const uint32_t b = sh.rowarg[a];
+    const double h = sh.rowmin[a];
+    const double na = (double)sh.size[a], nb = (double)sh.size[b];
+    if (tid == 0) {
+      const int32_t x = sh.id[a], y = sh.id[b];
+      mg[2 * t] = x < y ? x : y;
+      mg[2 * t + 1] = x < y ? y : x;
+      ht[t] = h / 2.0;
+    }
+    // update row and column a; row a's new minimum; rows that must rescan
+    v = __builtin_inf();
+    i = 0xFFFFFFFFu;
+    for (uint32_t k = tid; k < n; k += 1024) {
+      if (!sh.act[k] || k == a || k == b) continue;
+      const double nv = merge_mean(na, D[(size_t)a * n + k], nb, D[(size_t)b * n + k]);
+      D[(size_t)a * n + k] = nv;
+      D[(size_t)k * n + a] = nv;
+      if (k > a) {
+        lex_min(v, i, nv, k);
+        if (k < b && sh.rowarg[k] == b) sh.redo[atomicAdd(&sh.nredo, 1u)] = (uint16_t)k;
+      } else {
+        const uint16_t ra = sh.rowarg[k];
+        if (ra == a || ra == b) sh.redo[atomicAdd(&sh.nredo, 1u)] = (uint16_t)k;
+        else if (nv < sh.rowmin[k] || (nv == sh.rowmin[k] && a < ra)) {
+          sh.rowmin[k] = nv;
+          sh.rowarg[k] = (uint16_t)a;
+        }
+      }
+    }
+    wave_lex_min(v, i);
+    if (lane == 0) {
+      sh.wv[wave] = v;
+      sh.wi[wave] = i;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      v = tid < 16 ? sh.wv[tid] : __builtin_inf();
+      i = tid < 16 ? sh.wi[tid] : 0xFFFFFFFFu;
+      wave_lex_min(v, i);
+      if (tid == 0) {
+        sh.rowmin[a] = v;
+        sh.rowarg[a] = i == 0xFFFFFFFFu ? kNone16 : (uint16_t)i;
+        sh.act[b] = 0;
+        sh.rowmin[b] = __builtin_inf();
+        sh.size[a] = (uint16_t)(sh.size[a] + sh.size[b]);
+        sh.id[a] = (uint16_t)(n + t);
+      }
+    }
+    __syncthreads();
+    const uint32_t nr = sh.nredo;
+    for (uint32_t q = wave; q < nr; q += 16) scan_row(sh, D, n, sh.redo[q]);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_upgma(hipStream_t st, uint32_t nsets, const uint32_t *first, const uint64_t *doff,
+                        double *work, int32_t *merges, double *heights, unsigned long long *err) {
+  if (nsets == 0) return hipSuccess;
+  hipLaunchKernelGGL(upgma_kernel, dim3(nsets), dim3(1024), 0, st, first, doff, work, merges, heights,
+                     err);
+  return hipGetLastError();
+}
+
+}  // namespace kd
