@@ -956,8 +956,10 @@ extern "C" kd_status upgma_trees(kd_ctx *ctx, uint32_t nsets, const uint32_t *se
   const size_t hb = sizeof(uint64_t) * nsets + sizeof(uint32_t) * (nsets + 1);
   char *d_meta = tmp.get<char>(hb);
   double *work = tmp.get<double>(doff[nsets]);
+  double *rmin = tmp.get<double>(N);
+  uint32_t *rarg = tmp.get<uint32_t>(N);
   unsigned long long *err = tmp.get<unsigned long long>(1);
-  if (!d_meta || !work || !err) return KD_ENOMEM;
+  if (!d_meta || !work || !rmin || !rarg || !err) return KD_ENOMEM;
   std::vector<char> h(hb);
   std::memcpy(h.data(), doff.data(), sizeof(uint64_t) * nsets);
   std::memcpy(h.data() + sizeof(uint64_t) * nsets, set_first, sizeof(uint32_t) * (nsets + 1));
@@ -967,7 +969,7 @@ extern "C" kd_status upgma_trees(kd_ctx *ctx, uint32_t nsets, const uint32_t *se
   StageTimer t(ctx, KD_STAGE_TREE);
   KD_TRY(launch_fill_u64(st, err, 1, ~0ull));
   KD_TRY(hipMemcpyAsync(work, dist, sizeof(double) * doff[nsets], hipMemcpyDeviceToDevice, st));
-  KD_TRY(launch_upgma(st, nsets, d_first, d_off, work, merges, heights, err));
+  KD_TRY(launch_upgma(st, nsets, N, d_first, d_off, work, rmin, rarg, merges, heights, err));
   t.done();
   unsigned long long *hm = static_cast<unsigned long long *>(ctx->pinned);
   KD_TRY(hipMemcpyAsync(hm, err, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));

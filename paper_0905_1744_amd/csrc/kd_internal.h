@@ -275,9 +275,11 @@ hipError_t launch_distances(hipStream_t st, const Segs &sg, uint32_t N, const Se
                             double *dist);
 constexpr uint32_t kTreeMaxSeqs = 4096;  // largest set upgma_trees accepts
 // UPGMA of each set's matrix at work + doff[q] (overwritten), first[] on
-// the device; a set with no comparable pair left records its index in *err
-hipError_t launch_upgma(hipStream_t st, uint32_t nsets, const uint32_t *first, const uint64_t *doff,
-                        double *work, int32_t *merges, double *heights, unsigned long long *err);
+// the device (N = first[nsets] members in all); rmin/rarg: N entries of
+// scratch; a set with no comparable pair left records its index in *err
+hipError_t launch_upgma(hipStream_t st, uint32_t nsets, uint32_t N, const uint32_t *first,
+                        const uint64_t *doff, double *work, double *rmin, uint32_t *rarg,
+                        int32_t *merges, double *heights, unsigned long long *err);
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);
 // writes the set ids of sg.pos_set / grp_set / rb_set (nsets > 1)
 hipError_t launch_seg_ids(hipStream_t st, const Segs &sg, uint32_t *pos_set, uint32_t *grp_set,

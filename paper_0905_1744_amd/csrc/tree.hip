@@ -213,8 +213,8 @@ struct TreeShared {
   uint16_t id[kTreeMax];
   uint16_t redo[kTreeMax];
   uint8_t act[kTreeMax];
-  double wv[16];
-  uint32_t wi[16];
+  double wv[16], wv2[16];  // wave results: the pair, row a's new minimum
+  uint32_t wi[16], wi2[16];
   uint32_t nredo;
   uint32_t best_a;
 };
@@ -236,19 +236,41 @@ __device__ __forceinline__ void wave_lex_min(double &v, uint32_t &i) {
   }
 }
 
-// row k's minimum over active columns j > k (one wave)
-__device__ __forceinline__ void scan_row(TreeShared &sh, const double *D, uint32_t n, uint32_t k) {
+// Minimum of D[k][j] over columns j > k that are active and not `skip`,
+// with its smallest argument, over the columns of part p of W parts (one
+// wave per part, eight loads in flight per lane; W = 1: the whole row).
+template <class Active>
+__device__ __forceinline__ void row_min(const double *D, uint32_t n, uint32_t k, uint32_t skip,
+                                        Active active, double &v, uint32_t &i, uint32_t p = 0,
+                                        uint32_t W = 1) {
   const uint32_t lane = threadIdx.x & 63u;
-  double v = __builtin_inf();
-  uint32_t i = 0xFFFFFFFFu;
-  for (uint32_t j = k + 1 + lane; j < n; j += 64)
-    if (sh.act[j]) lex_min(v, i, D[(size_t)k * n + j], j);
-  wave_lex_min(v, i);
-  if (lane == 0) {
-    sh.rowmin[k] = v;
-    sh.rowarg[k] = i == 0xFFFFFFFFu ? kNone16 : (uint16_t)i;
+  v = __builtin_inf();
+  i = 0xFFFFFFFFu;
+  const double *row = D + (size_t)k * n;
+  const uint32_t stride = 64u * W;
+  for (uint32_t j0 = k + 1 + 64u * p; j0 < n; j0 += 8u * stride) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const uint32_t j = j0 + stride * u + lane;
+      x[u] = j < n ? row[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const uint32_t j = j0 + stride * u + lane;
+      if (j < n && j != skip && active(j)) lex_min(v, i, x[u], j);
+    }
   }
+  wave_lex_min(v, i);
 }
+
+struct AllActive {
+  __device__ bool operator()(uint32_t) const { return true; }
+};
+struct LdsActive {
+  const uint8_t *act;
+  __device__ bool operator()(uint32_t j) const { return act[j] != 0; }
+};
 
 #pragma clang fp contract(off)
 __device__ __forceinline__ double merge_mean(double na, double x, double nb, double y) {
@@ -258,31 +280,60 @@ __device__ __forceinline__ double merge_mean(double na, double x, double nb, dou
   return s / (na + nb);
 }
 
+// Initial row minima of every set, one wave per row, all sets at once.
+__global__ __launch_bounds__(256) void upgma_init_kernel(const uint32_t *__restrict__ first,
+                                                         uint32_t nsets,
+                                                         const uint64_t *__restrict__ doff,
+                                                         const double *__restrict__ work,
+                                                         double *__restrict__ rmin,
+                                                         uint32_t *__restrict__ rarg) {
+  const uint32_t p = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (p >= first[nsets]) return;
+  uint32_t lo = 0, hi = nsets;  // set of row p: last set with first[set] <= p
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (first[mid] <= p) lo = mid;
+    else hi = mid;
+  }
+  const uint32_t n = first[lo + 1] - first[lo], k = p - first[lo];
+  double v;
+  uint32_t i;
+  row_min(work + doff[lo], n, k, 0xFFFFFFFFu, AllActive{}, v, i);
+  if ((threadIdx.x & 63u) == 0) {
+    rmin[p] = v;
+    rarg[p] = i;
+  }
+}
+
 // A set whose remaining pairs compare false with everything (NaN
 // distances) stops there and records its index in *err.
 __global__ __launch_bounds__(1024) void upgma_kernel(const uint32_t *__restrict__ first,
                                                      const uint64_t *__restrict__ doff,
                                                      double *__restrict__ work,
+                                                     const double *__restrict__ rmin,
+                                                     const uint32_t *__restrict__ rarg,
                                                      int32_t *__restrict__ merges,
                                                      double *__restrict__ heights,
                                                      unsigned long long *err) {
   __shared__ TreeShared sh;
   const uint32_t set = blockIdx.x;
-  const uint32_t n = first[set + 1] - first[set];
+  const uint32_t f0 = first[set], n = first[set + 1] - f0;
   double *D = work + doff[set];
-  int32_t *mg = merges + 2ull * (first[set] - set);
-  double *ht = heights + (first[set] - set);
+  int32_t *mg = merges + 2ull * (f0 - set);
+  double *ht = heights + (f0 - set);
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   for (uint32_t k = tid; k < n; k += 1024) {
     sh.size[k] = 1;
     sh.id[k] = (uint16_t)k;
     sh.act[k] = 1;
+    sh.rowmin[k] = rmin[f0 + k];
+    sh.rowarg[k] = rarg[f0 + k] == 0xFFFFFFFFu ? kNone16 : (uint16_t)rarg[f0 + k];
   }
-  __syncthreads();
-  for (uint32_t k = wave; k < n; k += 16) scan_row(sh, D, n, k);
+  if (tid == 0) sh.nredo = 0;
   __syncthreads();
   for (uint32_t t = 0; t + 1 < n; t++) {
-    // the pair: lexicographic minimum of (rowmin[a], a) over active a
+    // the pair: lexicographic minimum of (rowmin[a], a) over active a;
+    // every wave reduces the 16 wave results itself (no second barrier)
     double v = __builtin_inf();
     uint32_t i = 0xFFFFFFFFu;
     for (uint32_t a = tid; a < n; a += 1024)
@@ -292,16 +343,11 @@ __global__ __launch_bounds__(1024) void upgma_kernel(const uint32_t *__restrict_
       sh.wv[wave] = v;
       sh.wi[wave] = i;
     }
-    if (tid == 0) sh.nredo = 0;
     __syncthreads();
-    if (tid < 64) {
-      v = tid < 16 ? sh.wv[tid] : __builtin_inf();
-      i = tid < 16 ? sh.wi[tid] : 0xFFFFFFFFu;
-      wave_lex_min(v, i);
-      if (tid == 0) sh.best_a = i;
-    }
-    __syncthreads();
-    const uint32_t a = sh.best_a;
+    v = lane < 16 ? sh.wv[lane] : __builtin_inf();
+    i = lane < 16 ? sh.wi[lane] : 0xFFFFFFFFu;
+    wave_lex_min(v, i);
+    const uint32_t a = i;
     if (a >= n || sh.rowarg[a] == kNone16) {
       if (tid == 0) atomicMin(err, (unsigned long long)set);
       return;
@@ -315,12 +361,24 @@ __global__ __launch_bounds__(1024) void upgma_kernel(const uint32_t *__restrict_
       mg[2 * t + 1] = x < y ? y : x;
       ht[t] = h / 2.0;
     }
-    // update row and column a; row a's new minimum; rows that must rescan
+    // update row and column a (loads first, then the arithmetic); row a's
+    // new minimum; rows that must rescan
+    constexpr int kPer = kTreeMax / 1024;
+    double xa[kPer], xb[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+      const uint32_t k = tid + 1024u * u;
+      const bool use = k < n && sh.act[k] && k != a && k != b;
+      xa[u] = use ? D[(size_t)a * n + k] : 0.0;
+      xb[u] = use ? D[(size_t)b * n + k] : 0.0;
+    }
     v = __builtin_inf();
     i = 0xFFFFFFFFu;
-    for (uint32_t k = tid; k < n; k += 1024) {
-      if (!sh.act[k] || k == a || k == b) continue;
-      const double nv = merge_mean(na, D[(size_t)a * n + k], nb, D[(size_t)b * n + k]);
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+      const uint32_t k = tid + 1024u * u;
+      if (!(k < n && sh.act[k] && k != a && k != b)) continue;
+      const double nv = merge_mean(na, xa[u], nb, xb[u]);
       D[(size_t)a * n + k] = nv;
       D[(size_t)k * n + a] = nv;
       if (k > a) {
@@ -336,16 +394,17 @@ __global__ __launch_bounds__(1024) void upgma_kernel(const uint32_t *__restrict_
       }
     }
     wave_lex_min(v, i);
-    if (lane == 0) {
-      sh.wv[wave] = v;
-      sh.wi[wave] = i;
+    if (lane == 0) {  // a second buffer: slower waves may still read wv
+      sh.wv2[wave] = v;
+      sh.wi2[wave] = i;
     }
-    __syncthreads();
-    if (tid < 64) {
-      v = tid < 16 ? sh.wv[tid] : __builtin_inf();
-      i = tid < 16 ? sh.wi[tid] : 0xFFFFFFFFu;
+    __syncthreads();  // row a's parts, D and the redo list are complete
+    const uint32_t nr = sh.nredo;
+    if (wave == 0) {
+      v = lane < 16 ? sh.wv2[lane] : __builtin_inf();
+      i = lane < 16 ? sh.wi2[lane] : 0xFFFFFFFFu;
       wave_lex_min(v, i);
-      if (tid == 0) {
+      if (lane == 0) {
         sh.rowmin[a] = v;
         sh.rowarg[a] = i == 0xFFFFFFFFu ? kNone16 : (uint16_t)i;
         sh.act[b] = 0;
@@ -354,18 +413,51 @@ __global__ __launch_bounds__(1024) void upgma_kernel(const uint32_t *__restrict_
         sh.id[a] = (uint16_t)(n + t);
       }
     }
+    // rescans skip b explicitly (its slot is retired by wave 0 meanwhile).
+    // Up to 16 rows: W = 16 / rows waves share each row and their parts
+    // meet in LDS; more rows: one wave per row.
+    if (nr > 0 && nr <= 16) {
+      const uint32_t W = 16u / nr, q = wave / W;
+      if (q < nr) {
+        row_min(D, n, sh.redo[q], b, LdsActive{sh.act}, v, i, wave % W, W);
+        if (lane == 0) {
+          sh.wv[wave] = v;
+          sh.wi[wave] = i;
+        }
+      }
+      __syncthreads();
+      if (tid < nr) {
+        v = __builtin_inf();
+        i = 0xFFFFFFFFu;
+        for (uint32_t w = tid * W; w < (tid + 1) * W; w++) lex_min(v, i, sh.wv[w], sh.wi[w]);
+        const uint32_t k = sh.redo[tid];
+        sh.rowmin[k] = v;
+        sh.rowarg[k] = i == 0xFFFFFFFFu ? kNone16 : (uint16_t)i;
+      }
+    } else {
+      for (uint32_t q = wave; q < nr; q += 16) {
+        const uint32_t k = sh.redo[q];
+        row_min(D, n, k, b, LdsActive{sh.act}, v, i);
+        if (lane == 0) {
+          sh.rowmin[k] = v;
+          sh.rowarg[k] = i == 0xFFFFFFFFu ? kNone16 : (uint16_t)i;
+        }
+      }
+    }
     __syncthreads();
-    const uint32_t nr = sh.nredo;
-    for (uint32_t q = wave; q < nr; q += 16) scan_row(sh, D, n, sh.redo[q]);
-    __syncthreads();
+    if (tid == 0) sh.nredo = 0;
   }
 }
 
-hipError_t launch_upgma(hipStream_t st, uint32_t nsets, const uint32_t *first, const uint64_t *doff,
-                        double *work, int32_t *merges, double *heights, unsigned long long *err) {
-  if (nsets == 0) return hipSuccess;
-  hipLaunchKernelGGL(upgma_kernel, dim3(nsets), dim3(1024), 0, st, first, doff, work, merges, heights,
-                     err);
+hipError_t launch_upgma(hipStream_t st, uint32_t nsets, uint32_t N, const uint32_t *first,
+                        const uint64_t *doff, double *work, double *rmin, uint32_t *rarg,
+                        int32_t *merges, double *heights, unsigned long long *err) {
+  if (nsets == 0 || N == 0) return hipSuccess;
+  hipLaunchKernelGGL(upgma_init_kernel, dim3((N + 3) / 4), dim3(256), 0, st, first, nsets, doff, work,
+                     rmin, rarg);
+  KD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(upgma_kernel, dim3(nsets), dim3(1024), 0, st, first, doff, work, rmin, rarg, merges,
+                     heights, err);
   return hipGetLastError();
 }
 
