@@ -89,6 +89,12 @@ def lib():
         L.orc_distance_block.restype = None
         L.orc_upgma.argtypes = [P, C.c_uint32, P, P]
         L.orc_upgma.restype = C.c_int
+        L.orc_profile.argtypes = [P, C.c_uint32, C.c_uint32, P, P]
+        L.orc_profile.restype = C.c_int
+        L.orc_psp.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P]
+        L.orc_psp.restype = None
+        L.orc_psp_matrix.argtypes = [P, P]
+        L.orc_psp_matrix.restype = C.c_int
         _lib = L
     return _lib
 
@@ -277,4 +283,40 @@ def upgma(d: np.ndarray):
     if r != 0:
         raise OracleError(r)
     return merges[:n - 1], heights[:n - 1]
+
+
+AMINO = b"ACDEFGHIKLMNPQRSTVWY"
+
+
+def profile(aln: np.ndarray):
+    """Column frequencies of the 20 amino acids (order AMINO) of an m x L
+    alignment (uint8 rows; '-' and '.' are gaps): (L, 20) float64."""
+    aln = np.ascontiguousarray(aln, dtype=np.uint8)
+    m, L = aln.shape
+    f = np.zeros((max(L, 1), 20), dtype=np.float64)
+    bad = C.c_uint64(0)
+    r = lib().orc_profile(_p(aln), m, L, _p(f), C.byref(bad))
+    if r != 0:
+        raise OracleError(r, pos=int(bad.value))
+    return f[:L]
+
+
+def psp(fx: np.ndarray, fy: np.ndarray, M: np.ndarray):
+    """Equation 4 for every column pair of two profiles: (Lx, Ly)."""
+    fx = np.ascontiguousarray(fx, dtype=np.float64)
+    fy = np.ascontiguousarray(fy, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    S = np.zeros((max(fx.shape[0], 1), max(fy.shape[0], 1)), dtype=np.float64)
+    lib().orc_psp(_p(fx), fx.shape[0], _p(fy), fy.shape[0], _p(M), _p(S))
+    return S[:fx.shape[0], :fy.shape[0]]
+
+
+def psp_matrix(P: np.ndarray):
+    """log(P_ij / (p_i p_j)) with p_i = sum_j P_ij (Equation 4's log term)."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    M = np.zeros((20, 20), dtype=np.float64)
+    r = lib().orc_psp_matrix(_p(P), _p(M))
+    if r != 0:
+        raise OracleError(r)
+    return M
 

@@ -23,6 +23,7 @@
  *   local ranks, k samples per processor,
  *   globalized rank ...................... Section 3.1.1 ("Globalised k-mer
  *                                          Rank"), Algorithm 2 steps 1-6
+ *   profile of an alignment, PSP score ... Section 3.1.3, Equation 4
  *   per-bucket distance matrix and
  *   guide tree ........................... Section 2 (the generic scheme: a
  *                                          pairwise similarity matrix, then
@@ -456,6 +457,71 @@ int orc_upgma(const double *d, uint32_t n, int32_t *merges, double *heights)
     }
 #undef UD
     free(D); free(size); free(id); free(act);
+    return ORC_OK;
+}
+
+/* ---- profiles and the profile sum of pairs score (Section 3.1.3, Equation 4) ---- */
+
+/* The 20 amino acids of a profile column, in the order of their one-letter
+ * codes ACDEFGHIKLMNPQRSTVWY; -1 for anything else. */
+static int orc_aa_index(uint8_t ch)
+{
+    static const char order[] = "ACDEFGHIKLMNPQRSTVWY";
+    for (int a = 0; a < 20; a++)
+        if (order[a] == ch) return a;
+    return -1;
+}
+
+/* Profile of an alignment of m rows of L columns (aln row-major): f[x*20+a]
+ * = (rows holding amino acid a in column x) / m; the gap characters '-' and
+ * '.' count toward no amino acid (the column's gap frequency is 1 minus the
+ * sum).  Any other byte returns ORC_EBADRESIDUE with its position in *bad. */
+int orc_profile(const uint8_t *aln, uint32_t m, uint32_t L, double *f, uint64_t *bad)
+{
+    if (m == 0) return ORC_EINVAL;
+    for (uint64_t q = 0; q < (uint64_t)L * 20; q++) f[q] = 0.0;
+    for (uint32_t r = 0; r < m; r++) {
+        for (uint32_t x = 0; x < L; x++) {
+            const uint8_t ch = aln[(uint64_t)r * L + x];
+            if (ch == '-' || ch == '.') continue;
+            const int a = orc_aa_index(ch);
+            if (a < 0) { if (bad) *bad = (uint64_t)r * L + x; return ORC_EBADRESIDUE; }
+            f[(uint64_t)x * 20 + a] += 1.0;
+        }
+    }
+    for (uint64_t q = 0; q < (uint64_t)L * 20; q++) f[q] /= (double)m;
+    return ORC_OK;
+}
+
+/* Equation 4 for every column pair: S[x*Ly + y] = sum_i sum_j fx[x][i]
+ * fy[y][j] M[i][j], the double sum taken as written (i outer, j inner). */
+void orc_psp(const double *fx, uint32_t Lx, const double *fy, uint32_t Ly, const double *M, double *S)
+{
+    for (uint32_t x = 0; x < Lx; x++)
+        for (uint32_t y = 0; y < Ly; y++) {
+            double sum = 0.0;
+            for (int i = 0; i < 20; i++)
+                for (int j = 0; j < 20; j++)
+                    sum += fx[(uint64_t)x * 20 + i] * fy[(uint64_t)y * 20 + j] * M[i * 20 + j];
+            S[(uint64_t)x * Ly + y] = sum;
+        }
+}
+
+/* The log-odds term of Equation 4 from a joint distribution P of aligned
+ * amino-acid pairs: M[i][j] = log(P[i][j] / (p_i p_j)) with the background
+ * probabilities p_i = sum_j P[i][j] (P summing to 1, every entry > 0). */
+int orc_psp_matrix(const double *P, double *M)
+{
+    double p[20];
+    for (int i = 0; i < 20; i++) {
+        p[i] = 0.0;
+        for (int j = 0; j < 20; j++) {
+            if (!(P[i * 20 + j] > 0.0)) return ORC_EINVAL;
+            p[i] += P[i * 20 + j];
+        }
+    }
+    for (int i = 0; i < 20; i++)
+        for (int j = 0; j < 20; j++) M[i * 20 + j] = log(P[i * 20 + j] / (p[i] * p[j]));
     return ORC_OK;
 }
 

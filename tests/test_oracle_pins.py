@@ -536,3 +536,68 @@ def test_distance_matrix_bruteforce(oracle_mod):
             assert M[r, c] == pytest.approx(want, rel=1e-15, abs=1e-300)
     np.testing.assert_allclose(np.diag(M), -math.log1p(delta), rtol=1e-15, atol=0)
     np.testing.assert_array_equal(M, M.T)
+
+
+# --------------------------------------------------- profiles and PSP (Eq. 4) --
+
+def _joint(rng):
+    """A symmetric joint distribution of aligned amino-acid pairs."""
+    x = rng.random((20, 20)) + 0.05
+    P = x + x.T
+    return P / P.sum()
+
+
+def test_profile_worked(oracle_mod):
+    """Three rows: column 0 = A, A, C -> A 2/3, C 1/3; column 1 = -, G, G ->
+    G 2/3 (one gap); column 2 = W, ., - -> W 1/3; column 3 = Y, Y, Y."""
+    aln = np.frombuffer(b"A-WY" b"AG.Y" b"CG-Y", dtype=np.uint8).reshape(3, 4)
+    f = oracle_mod.profile(aln)
+    idx = {chr(c): i for i, c in enumerate(oracle_mod.AMINO)}
+    want = np.zeros((4, 20))
+    want[0, idx["A"]] = 2 / 3
+    want[0, idx["C"]] = 1 / 3
+    want[1, idx["G"]] = 2 / 3
+    want[2, idx["W"]] = 1 / 3
+    want[3, idx["Y"]] = 1.0
+    np.testing.assert_allclose(f, want, rtol=1e-15, atol=0)
+    assert oracle_mod.AMINO == b"".join(sorted(oracle_mod.AMINO[i:i + 1] for i in range(20)))
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.profile(np.frombuffer(b"AB-", dtype=np.uint8).reshape(1, 3))
+    assert e.value.pos == 1
+
+
+def test_psp_one_hot_and_bilinear(oracle_mod):
+    """A column holding only amino acid i against one holding only j scores
+    M[i][j]; the score is linear in each column's frequencies."""
+    rng = np.random.default_rng(17)
+    M = oracle_mod.psp_matrix(_joint(rng))
+    E = np.eye(20)
+    np.testing.assert_allclose(oracle_mod.psp(E, E, M), M, rtol=1e-15, atol=1e-15)
+    fx = rng.random((3, 20))
+    fy = rng.random((4, 20))
+    S = oracle_mod.psp(fx, fy, M)
+    for x in range(3):
+        for y in range(4):
+            terms = [fx[x, i] * fy[y, j] * M[i, j] for i in range(20) for j in range(20)]
+            assert S[x, y] == pytest.approx(math.fsum(terms), rel=1e-13, abs=1e-13)
+    a, b = rng.random(2)
+    mix = oracle_mod.psp(a * fx[:1] + b * fx[1:2], fy, M)
+    np.testing.assert_allclose(mix, a * S[:1] + b * S[1:2], rtol=1e-12, atol=1e-13)
+    # symmetric M: swapping the profiles transposes the scores
+    np.testing.assert_allclose(oracle_mod.psp(fy, fx, M), S.T, rtol=1e-13, atol=1e-14)
+
+
+def test_psp_matrix_definition(oracle_mod):
+    """Independent pairs (P = p p^T) give log 1 = 0 everywhere; doubling one
+    diagonal weight and renormalising gives a closed form."""
+    p = np.arange(1, 21, dtype=np.float64)
+    p /= p.sum()
+    np.testing.assert_allclose(oracle_mod.psp_matrix(np.outer(p, p)), 0.0, atol=1e-13)
+    P = np.full((20, 20), 1.0)
+    P[0, 0] = 2.0
+    P /= P.sum()           # p_0 = 21/401, others 20/401
+    M = oracle_mod.psp_matrix(P)
+    assert M[0, 0] == pytest.approx(math.log((2 / 401) / (21 / 401) ** 2), rel=1e-14)
+    assert M[1, 2] == pytest.approx(math.log((1 / 401) / (20 / 401) ** 2), rel=1e-14)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.psp_matrix(np.zeros((20, 20)))
