@@ -312,6 +312,71 @@ def bench_trees(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_psp(args):
+    """Profile sum of pairs scores (Equation 4) for a batch of profile pairs:
+    npairs pairs with lengths uniform in [200, 2000] columns (the range of
+    the workloads' sequences), profiles of random alignments with 15% gaps,
+    M = log(p_ij / (p_i p_j)) of a random symmetric joint distribution (the
+    paper's PAM 200 / VTML 240 tables are not available).  One step = every
+    pair's score matrix.  The kernel writes 8 bytes per score and reads
+    160 bytes per column, so it is bound by HBM bandwidth."""
+    import numpy as np
+    import torch
+
+    import paper_0905_1744_amd as kd
+
+    rng = np.random.default_rng(11)
+    npairs = args.pairs
+    lens = rng.integers(200, 2001, size=(npairs, 2))
+    x = rng.random((20, 20)) + 0.05
+    P = x + x.T
+    P /= P.sum()
+    pm = P.sum(axis=1)
+    M = np.log(P / np.outer(pm, pm))
+    dev = torch.device("cuda", 0)
+
+    def prof(L):
+        return rng.dirichlet(np.ones(20), size=L) * (1 - rng.random((L, 1)) * 0.3)
+    FX = torch.from_numpy(np.concatenate([prof(int(a)) for a in lens[:, 0]])).to(dev)
+    FY = torch.from_numpy(np.concatenate([prof(int(b)) for b in lens[:, 1]])).to(dev)
+    ctx = kd.Context(0)
+    print(f"[bench] psp: {npairs} profile pairs", file=sys.stderr, flush=True)
+    Md = torch.from_numpy(M).to(dev)
+    S, _ = ctx.psp_scores_packed(Md, FX, lens[:, 0], FY, lens[:, 1])
+    for _ in range(args.warmup):
+        ctx.psp_scores_packed(Md, FX, lens[:, 0], FY, lens[:, 1], S)
+    torch.cuda.synchronize()
+    ctx.enable_timing(True, stages=("psp",))
+    ctx.reset_timing()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.psp_scores_packed(Md, FX, lens[:, 0], FY, lens[:, 1], S)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_k, n_k = ctx.stage_times()["psp"]
+    ctx.enable_timing(False)
+    t_k = ms_k / max(n_k, 1) / 1e3
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    scores = int((lens[:, 0] * lens[:, 1]).sum())
+    nbytes = 8 * scores + 160 * int(lens.sum()) + 3200 * npairs
+    gbs = nbytes / t_k / 1e9
+    line = {
+        "metric": "PSP column-pair scores/sec (Equation 4)", "value": scores / (ms_per_step / 1e3),
+        "unit": "scores/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"psp: {npairs} profile pairs, lengths uniform [200, 2000], random "
+                                f"profiles, log-odds of a random symmetric joint distribution, seed 11"),
+                   "scores_per_step": scores},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                     "traffic": None, "kernel": "psp_scores_kernel", "kernel_ms": t_k * 1e3,
+                     "bytes_per_launch": nbytes,
+                     "flops_per_launch": 2 * 20 * scores + 2 * 400 * int(lens[:, 0].sum())},
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def bench_batched(args):
     """Many independent sets in one call (kd_batch_run) against the plain
     per-set loop (kmer_count -> kmer_rank -> sample_partition, synchronizing
@@ -490,9 +555,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS) + ["batched", "served", "global20k", "global100k",
-                                                     "trees20k", "trees100k"])
+                                                     "trees20k", "trees100k", "psp"])
     ap.add_argument("--sets", type=int, default=4096, help="batched workload: number of sets")
     ap.add_argument("--jobs", type=int, default=300, help="served workload: jobs per arrival rate")
+    ap.add_argument("--pairs", type=int, default=256, help="psp workload: profile pairs")
     ap.add_argument("--rates", default="10,20,50,100,200,500,1000,2000,4000",
                     help="served workload: arrival rates (jobs/s)")
     ap.add_argument("--no-loop-baseline", action="store_true",
@@ -532,6 +598,9 @@ def main():
         return
     if args.workload in ("trees20k", "trees100k"):
         bench_trees(args)
+        return
+    if args.workload == "psp":
+        bench_psp(args)
         return
 
     import numpy as np

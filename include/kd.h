@@ -89,8 +89,9 @@ void *kd_ctx_stream(kd_ctx *ctx);
 #define KD_STAGE_GATHER 7     /* kd_gather_sequences */
 #define KD_STAGE_DIST 8       /* kmer_distance_matrices */
 #define KD_STAGE_TREE 9       /* upgma_trees */
-#define KD_NSTAGES 10
-#define KD_TIME_MASK 0x10000  /* enable argument: bits 0..9 select stages */
+#define KD_STAGE_PSP 10       /* psp_profile, psp_scores */
+#define KD_NSTAGES 11
+#define KD_TIME_MASK 0x10000  /* enable argument: bits 0..10 select stages */
 kd_status kd_ctx_enable_timing(kd_ctx *ctx, int enable);
 kd_status kd_ctx_stage_time(kd_ctx *ctx, int stage, double *ms, uint64_t *launches);
 kd_status kd_ctx_reset_timing(kd_ctx *ctx);
@@ -324,6 +325,39 @@ kd_status kmer_distance_matrices(kd_ctx *ctx, const kd_set *set, double delta, d
  * ordered (NaN). */
 kd_status upgma_trees(kd_ctx *ctx, uint32_t nsets, const uint32_t *set_first, const double *dist,
                       int32_t *merges, double *heights);
+
+/* ------------------------------------------------- profiles and PSP scores */
+
+/* Profile of an alignment (Section 3.1.3): for each of its L columns the
+ * frequencies of the 20 amino acids, in the order of their one-letter
+ * codes ACDEFGHIKLMNPQRSTVWY, over its m rows; '-' and '.' are gaps and
+ * count toward no amino acid.
+ *   aln  device u8[m x L], row-major (row r = one aligned sequence)
+ *   f    device f64[L x 20]: f[x*20 + a] = (rows with amino acid a in
+ *        column x) / m
+ * Errors: KD_EINVAL for a NULL argument or m == 0; KD_EBADRESIDUE for any
+ * other byte (kd_last_error_info: seq = row, pos = column of the first
+ * one in row-major order).  The stream is synchronized once. */
+kd_status psp_profile(kd_ctx *ctx, const uint8_t *aln, uint32_t m, uint32_t L, double *f);
+
+/* One profile pair for psp_scores (device pointers). */
+typedef struct kd_psp_pair {
+  const double *fx;  /* f64[lx x 20], profile X */
+  uint32_t lx;
+  uint32_t ly;
+  const double *fy;  /* f64[ly x 20], profile Y */
+  double *scores;    /* f64[lx x ly], row-major: scores[x*ly + y] */
+} kd_psp_pair;
+
+/* Profile sum of pairs scores (Equation 4) for every column pair of each
+ * profile pair: scores[x][y] = sum_i sum_j fx[x][i] fy[y][j] M[i][j], with
+ * M[i][j] = log(p_ij / (p_i p_j)) from the caller's substitution model
+ * (the paper names PAM 200 and VTML 240; none ships with this library).
+ * FP64 throughout (matrix cores).
+ *   M      device f64[20 x 20], row-major, amino acids in profile order
+ *   pairs  host array of npairs descriptors, npairs <= 65535
+ * Errors: KD_EINVAL for a NULL argument or too many pairs. */
+kd_status psp_scores(kd_ctx *ctx, const double *M, uint32_t npairs, const kd_psp_pair *pairs);
 
 /* ----------------------------------------------------------------- server */
 

@@ -103,6 +103,8 @@ def lib():
         "kd_gather_sequences": (i32, [P, P, P, u32, u64, P, u32, P, u64, P]),
         "kmer_distance_matrices": (i32, [P, P, C.c_double, P]),
         "upgma_trees": (i32, [P, u32, P, P, P, P]),
+        "psp_profile": (i32, [P, P, u32, u32, P]),
+        "psp_scores": (i32, [P, P, u32, P]),
         "kd_server_create": (i32, [C.c_int, C.POINTER(ServerOpts), PP]),
         "kd_server_submit": (i32, [P, C.POINTER(Job), C.POINTER(u64)]),
         "kd_server_poll": (i32, [P, C.POINTER(Done), u32, C.POINTER(u32), C.c_int64]),
@@ -188,6 +190,11 @@ class KmerSet:
             pass
 
 
+class PspPair(C.Structure):
+    _fields_ = [("fx", C.c_void_p), ("lx", C.c_uint32), ("ly", C.c_uint32), ("fy", C.c_void_p),
+                ("scores", C.c_void_p)]
+
+
 class Context:
     """A library context bound to one GPU and one HIP stream."""
 
@@ -225,7 +232,7 @@ class Context:
             pass
 
     STAGES = ("count", "layout", "pairs", "finalize", "partition", "similarity", "global", "gather",
-              "dist", "tree")
+              "dist", "tree", "psp")
 
     def enable_timing(self, on: bool = True, stages=None):
         """Time every stage, or only the named ones (each costs two events)."""
@@ -387,6 +394,79 @@ class Context:
             kb.destroy()
         merges, heights = self.upgma(first, D)
         return dict(order=part["order"], set_first=first, dist=D, merges=merges, heights=heights)
+
+    # ------------------------------------------------ profiles and PSP
+    def psp_profile(self, aln):
+        """Column frequencies of the 20 amino acids (ACDEFGHIKLMNPQRSTVWY) of
+        an m x L alignment (uint8; '-' and '.' are gaps): (L, 20) f64."""
+        A = _dev_tensor(aln, torch.uint8, self.device)
+        if A.dim() != 2:
+            raise ValueError("aln must be an m x L array")
+        m, L = A.shape
+        A = A.contiguous()
+        f = torch.empty((max(L, 1), 20), dtype=torch.float64, device=self.device)
+        self._check(lib().psp_profile(self.handle, _ptr(A), m, L, _ptr(f)), "psp_profile")
+        return f[:L]
+
+    def psp_scores(self, M, pairs, outs=None):
+        """Equation 4 for every column pair of each (fx, fy) profile pair:
+        a list of (lx, ly) f64 score tensors (written into `outs` when
+        given)."""
+        Md = _dev_tensor(M, torch.float64, self.device).contiguous()
+        if Md.numel() != 400:
+            raise ValueError("M must be 20 x 20")
+        keep, res = [], []
+        arr = (PspPair * max(len(pairs), 1))()
+        for q, (fx, fy) in enumerate(pairs):
+            X = _dev_tensor(fx, torch.float64, self.device).contiguous()
+            Y = _dev_tensor(fy, torch.float64, self.device).contiguous()
+            if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != 20 or Y.shape[1] != 20:
+                raise ValueError("profiles must be L x 20")
+            if outs is not None:
+                S = outs[q]
+                if (S.dtype != torch.float64 or tuple(S.shape) != (X.shape[0], Y.shape[0])
+                        or not S.is_contiguous() or S.device != self.device):
+                    raise ValueError("outs[%d] must be a contiguous (lx, ly) float64 device tensor" % q)
+            else:
+                S = torch.empty((X.shape[0], Y.shape[0]), dtype=torch.float64, device=self.device)
+            keep += [X, Y]
+            res.append(S)
+            arr[q] = PspPair(X.data_ptr(), X.shape[0], Y.shape[0], Y.data_ptr(), S.data_ptr())
+        self._check(lib().psp_scores(self.handle, _ptr(Md), len(pairs), C.cast(arr, C.c_void_p)),
+                    "psp_scores")
+        return res
+
+    def psp_scores_packed(self, M, FX, lx, FY, ly, S=None):
+        """psp_scores for profiles packed back to back: pair q is rows
+        sum(lx[:q]) .. of FX (sum lx x 20) against rows sum(ly[:q]) .. of FY;
+        its lx[q] x ly[q] scores go to S (flat, pair after pair).  Returns
+        (S, offsets of each pair's scores)."""
+        Md = _dev_tensor(M, torch.float64, self.device).contiguous()
+        X = _dev_tensor(FX, torch.float64, self.device).contiguous()
+        Y = _dev_tensor(FY, torch.float64, self.device).contiguous()
+        lx = np.asarray(lx, dtype=np.int64)
+        ly = np.asarray(ly, dtype=np.int64)
+        if (Md.numel() != 400 or lx.shape != ly.shape or X.shape != (int(lx.sum()), 20)
+                or Y.shape != (int(ly.sum()), 20) or (lx < 0).any() or (ly < 0).any()):
+            raise ValueError("FX, FY must hold sum(lx), sum(ly) rows of 20; M must be 20 x 20")
+        so = np.concatenate([[0], np.cumsum(lx * ly)])
+        if S is None:
+            S = torch.empty(max(int(so[-1]), 1), dtype=torch.float64, device=self.device)
+        elif S.dtype != torch.float64 or S.numel() < int(so[-1]) or not S.is_contiguous():
+            raise ValueError("S must be a contiguous float64 tensor of sum(lx * ly) entries")
+        xo = np.concatenate([[0], np.cumsum(lx)[:-1]])
+        yo = np.concatenate([[0], np.cumsum(ly)[:-1]])
+        n = lx.size
+        arr = np.zeros(max(n, 1), dtype=np.dtype([("fx", np.uint64), ("lx", np.uint32), ("ly", np.uint32),
+                                                 ("fy", np.uint64), ("scores", np.uint64)]))
+        arr["fx"][:n] = X.data_ptr() + 160 * xo
+        arr["fy"][:n] = Y.data_ptr() + 160 * yo
+        arr["lx"][:n] = lx
+        arr["ly"][:n] = ly
+        arr["scores"][:n] = S.data_ptr() + 8 * so[:-1]
+        self._check(lib().psp_scores(self.handle, _ptr(Md), n, arr.ctypes.data_as(C.c_void_p)),
+                    "psp_scores")
+        return S, so
 
     # ------------------------------------------------------------ batches
     @staticmethod

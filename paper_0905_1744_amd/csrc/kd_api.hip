@@ -977,6 +977,67 @@ extern "C" kd_status upgma_trees(kd_ctx *ctx, uint32_t nsets, const uint32_t *se
   return hm[0] == ~0ull ? KD_OK : KD_EINVAL;
 }
 
+// ------------------------------------------------- profiles and PSP scores
+
+extern "C" kd_status psp_profile(kd_ctx *ctx, const uint8_t *aln, uint32_t m, uint32_t L, double *f) {
+  if (!ctx || m == 0) return KD_EINVAL;
+  if (L == 0) return KD_OK;
+  if (!aln || !f) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  Scope tmp(ctx);
+  unsigned long long *bad = tmp.get<unsigned long long>(1);
+  if (!bad) return KD_ENOMEM;
+  StageTimer t(ctx, KD_STAGE_PSP);
+  KD_TRY(launch_fill_u64(st, bad, 1, ~0ull));
+  KD_TRY(launch_psp_profile(st, aln, m, L, f, bad));
+  t.done();
+  unsigned long long *hm = static_cast<unsigned long long *>(ctx->pinned);
+  KD_TRY(hipMemcpyAsync(hm, bad, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  KD_TRY(hipStreamSynchronize(st));
+  if (hm[0] != ~0ull) {
+    ctx->err_seq = hm[0] / L;
+    ctx->err_pos = hm[0] % L;
+    return KD_EBADRESIDUE;
+  }
+  return KD_OK;
+}
+
+extern "C" kd_status psp_scores(kd_ctx *ctx, const double *M, uint32_t npairs, const kd_psp_pair *pairs) {
+  if (!ctx || !M || (npairs > 0 && !pairs) || npairs > 65535) return KD_EINVAL;
+  uint32_t mx = 0, my = 0;
+  for (uint32_t q = 0; q < npairs; q++) {
+    const kd_psp_pair &p = pairs[q];
+    if (p.lx > 0 && p.ly > 0 && (!p.fx || !p.fy || !p.scores)) return KD_EINVAL;
+    if (p.lx > 0 && p.ly > 0) {
+      mx = std::max(mx, p.lx);
+      my = std::max(my, p.ly);
+    }
+  }
+  if (mx == 0) return KD_OK;
+  KD_TRY(hipSetDevice(ctx->device));
+  Scope tmp(ctx);
+  uint64_t gsz = 0;
+  for (uint32_t q = 0; q < npairs; q++)
+    if (pairs[q].ly > 0) gsz += 20ull * pairs[q].lx;
+  PspWork *d_w = tmp.get<PspWork>(npairs);
+  double *g = tmp.get<double>(gsz);
+  if (!d_w || !g) return KD_ENOMEM;
+  std::vector<PspWork> h(npairs);
+  uint64_t go = 0;
+  for (uint32_t q = 0; q < npairs; q++) {
+    const kd_psp_pair &p = pairs[q];
+    const bool any = p.lx > 0 && p.ly > 0;  // empty pairs write nothing
+    h[q] = PspWork{p.fx, p.fy, p.scores, g + go, any ? p.lx : 0u, any ? p.ly : 0u};
+    if (any) go += 20ull * p.lx;
+  }
+  KD_TRY(upload(ctx, d_w, h.data(), sizeof(PspWork) * npairs));
+  StageTimer t(ctx, KD_STAGE_PSP);
+  KD_TRY(launch_psp_scores(ctx->stream, d_w, npairs, mx, my, M));
+  t.done();
+  return KD_OK;
+}
+
 // ------------------------------------------------------------ autotune
 
 extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t *best,

@@ -280,6 +280,18 @@ constexpr uint32_t kTreeMaxSeqs = 4096;  // largest set upgma_trees accepts
 hipError_t launch_upgma(hipStream_t st, uint32_t nsets, uint32_t N, const uint32_t *first,
                         const uint64_t *doff, double *work, double *rmin, uint32_t *rarg,
                         int32_t *merges, double *heights, unsigned long long *err);
+// PSP (Equation 4): profiles of alignments and score matrices of pairs
+struct PspWork {  // one pair: the caller's descriptor and its G = fX M scratch
+  const double *fx;
+  const double *fy;
+  double *scores;
+  double *g;  // [lx x 20]
+  uint32_t lx, ly;
+};
+hipError_t launch_psp_profile(hipStream_t st, const uint8_t *aln, uint32_t m, uint32_t L, double *f,
+                              unsigned long long *bad);
+hipError_t launch_psp_scores(hipStream_t st, const PspWork *w, uint32_t npairs, uint32_t max_lx,
+                             uint32_t max_ly, const double *M);
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);
 // writes the set ids of sg.pos_set / grp_set / rb_set (nsets > 1)
 hipError_t launch_seg_ids(hipStream_t st, const Segs &sg, uint32_t *pos_set, uint32_t *grp_set,

@@ -1,0 +1,136 @@
+// Profiles and the profile sum of pairs score (paper Section 3.1.3,
+// Equation 4): PSP(x, y) = sum_i sum_j fX[x][i] fY[y][j] M[i][j] for every
+// column x of profile X and column y of profile Y, M[i][j] = log(p_ij /
+// (p_i p_j)) supplied by the caller.  As matrices, S = fX M fY^T: a dense
+// contraction with K = 20, done on the matrix cores in FP64
+// (v_mfma_f64_16x16x4_f64, five K-steps of 4).
+#include <algorithm>
+
+#include "kd_internal.h"
+
+namespace kd {
+
+// --------------------------------------------------------------- profiles
+
+// one thread per column; counts in LDS ([amino acid][thread], no bank
+// conflicts); f = count / m.  A byte that is neither an amino acid nor a
+// gap records its row-major position in *bad (smallest wins).
+__global__ __launch_bounds__(256) void psp_profile_kernel(const uint8_t *__restrict__ aln, uint32_t m,
+                                                          uint32_t L, double *__restrict__ f,
+                                                          unsigned long long *bad) {
+  __shared__ uint32_t cnt[20][256];
+  __shared__ int8_t code[256];
+  const uint32_t t = threadIdx.x;
+  {
+    // 20 amino acids in the order of their one-letter codes; gaps -2
+    const char *order = "ACDEFGHIKLMNPQRSTVWY";
+    int8_t c = -1;
+    for (int a = 0; a < 20; a++)
+      if ((uint32_t)(uint8_t)order[a] == t) c = (int8_t)a;
+    if (t == '-' || t == '.') c = -2;
+    code[t] = c;
+  }
+  for (int a = 0; a < 20; a++) cnt[a][t] = 0;
+  __syncthreads();
+  const uint32_t x = blockIdx.x * 256u + t;
+  if (x >= L) return;
+  for (uint32_t r = 0; r < m; r++) {
+    const uint64_t pos = (uint64_t)r * L + x;
+    const int c = code[aln[pos]];
+    if (c >= 0) cnt[c][t]++;
+    else if (c == -1) {
+      atomicMin(bad, (unsigned long long)pos);
+      break;
+    }
+  }
+  for (int a = 0; a < 20; a++) f[(uint64_t)x * 20 + a] = (double)cnt[a][t] / (double)m;
+}
+
+hipError_t launch_psp_profile(hipStream_t st, const uint8_t *aln, uint32_t m, uint32_t L, double *f,
+                              unsigned long long *bad) {
+  if (L == 0) return hipSuccess;
+  hipLaunchKernelGGL(psp_profile_kernel, dim3((L + 255) / 256), dim3(256), 0, st, aln, m, L, f, bad);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scores
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kPspRows = 16;   // rows per wave (one MFMA block high)
+constexpr uint32_t kPspCols = 512;  // columns per wave (32 MFMA blocks, in groups of 4)
+
+// G = fX M for every row of every pair (the first factor of the
+// contraction), i inner in fixed order; one thread per element.
+__global__ __launch_bounds__(256) void psp_g_kernel(const PspWork *__restrict__ w, uint32_t npairs,
+                                                    const double *__restrict__ M) {
+  __shared__ double sM[400];
+  for (uint32_t q = threadIdx.x; q < 400; q += 256) sM[q] = M[q];
+  __syncthreads();
+  const PspWork pr = w[blockIdx.y];
+  for (uint32_t e = blockIdx.x * 256u + threadIdx.x; e < pr.lx * 20u; e += gridDim.x * 256u) {
+    const uint32_t x = e / 20u, j = e % 20u;
+    double g = 0.0;
+#pragma unroll
+    for (int i = 0; i < 20; i++) g = fma(pr.fx[(uint64_t)x * 20 + i], sM[i * 20 + j], g);
+    pr.g[e] = g;
+  }
+}
+
+// One wave = 16 rows of one pair against up to 512 columns, 64 columns
+// (four 16 x 16 blocks) at a time on the matrix cores: lane l supplies
+// A[l%16][l/16] = G[row][4k + l/16] and B[l/16][l%16] = fY[col][4k + l/16]
+// (read straight from memory; the 64 x 20 slice of fY is 10 KB and stays
+// in cache) and holds D[l/16 + 4r][l%16], r = 0..3, of each block.
+__global__ __launch_bounds__(256) void psp_scores_kernel(const PspWork *__restrict__ w) {
+  const PspWork pr = w[blockIdx.z];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t x0 = (blockIdx.y * 4u + wave) * kPspRows, yb = blockIdx.x * kPspCols;
+  if (x0 >= pr.lx || yb >= pr.ly) return;
+  const uint32_t li = lane & 15u, lk = lane >> 4;
+  double a[5];
+  {
+    const uint32_t x = min(x0 + li, pr.lx - 1u);  // rows past the end: any valid row, not stored
+#pragma unroll
+    for (int k = 0; k < 5; k++) a[k] = pr.g[(uint64_t)x * 20 + 4 * k + lk];
+  }
+  const uint32_t ye = min(pr.ly, yb + kPspCols);
+  for (uint32_t y0 = yb; y0 < ye; y0 += 64) {
+    double b[4][5];
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++) {
+      const uint32_t y = min(y0 + 16u * cb + li, pr.ly - 1u);
+#pragma unroll
+      for (int k = 0; k < 5; k++) b[cb][k] = pr.fy[(uint64_t)y * 20 + 4 * k + lk];
+    }
+    v4d acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++) {
+      acc[cb] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 5; k++) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], b[cb][k], acc[cb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++) {
+      const uint32_t y = y0 + 16u * cb + li;
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const uint32_t x = x0 + lk + 4u * r;
+        if (x < pr.lx && y < pr.ly) pr.scores[(uint64_t)x * pr.ly + y] = acc[cb][r];
+      }
+    }
+  }
+}
+
+hipError_t launch_psp_scores(hipStream_t st, const PspWork *w, uint32_t npairs, uint32_t max_lx,
+                             uint32_t max_ly, const double *M) {
+  if (npairs == 0 || max_lx == 0 || max_ly == 0) return hipSuccess;
+  const uint32_t gx = std::min<uint32_t>((max_lx * 20u + 255u) / 256u, 64u);
+  hipLaunchKernelGGL(psp_g_kernel, dim3(gx, npairs), dim3(256), 0, st, w, npairs, M);
+  KD_HIP(hipGetLastError());
+  const dim3 grid((max_ly + kPspCols - 1) / kPspCols, (max_lx + 4 * kPspRows - 1) / (4 * kPspRows), npairs);
+  hipLaunchKernelGGL(psp_scores_kernel, grid, dim3(256), 0, st, w);
+  return hipGetLastError();
+}
+
+}  // namespace kd
