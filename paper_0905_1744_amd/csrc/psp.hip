@@ -61,19 +61,25 @@ constexpr uint32_t kPspRows = 16;   // rows per wave (one MFMA block high)
 constexpr uint32_t kPspCols = 512;  // columns per wave (32 MFMA blocks, in groups of 4)
 
 // G = fX M for every row of every pair (the first factor of the
-// contraction), i inner in fixed order; one thread per element.
+// contraction): one thread per row, its 20 frequencies in registers, M in
+// LDS, each G[x][j] summed over i in fixed order.
 __global__ __launch_bounds__(256) void psp_g_kernel(const PspWork *__restrict__ w, uint32_t npairs,
                                                     const double *__restrict__ M) {
   __shared__ double sM[400];
   for (uint32_t q = threadIdx.x; q < 400; q += 256) sM[q] = M[q];
   __syncthreads();
   const PspWork pr = w[blockIdx.y];
-  for (uint32_t e = blockIdx.x * 256u + threadIdx.x; e < pr.lx * 20u; e += gridDim.x * 256u) {
-    const uint32_t x = e / 20u, j = e % 20u;
-    double g = 0.0;
+  for (uint32_t x = blockIdx.x * 256u + threadIdx.x; x < pr.lx; x += gridDim.x * 256u) {
+    double f[20];
 #pragma unroll
-    for (int i = 0; i < 20; i++) g = fma(pr.fx[(uint64_t)x * 20 + i], sM[i * 20 + j], g);
-    pr.g[e] = g;
+    for (int i = 0; i < 20; i++) f[i] = pr.fx[(uint64_t)x * 20 + i];
+#pragma unroll 1
+    for (int j = 0; j < 20; j++) {
+      double g = 0.0;
+#pragma unroll
+      for (int i = 0; i < 20; i++) g = fma(f[i], sM[i * 20 + j], g);
+      pr.g[(uint64_t)x * 20 + j] = g;
+    }
   }
 }
 
@@ -81,8 +87,11 @@ __global__ __launch_bounds__(256) void psp_g_kernel(const PspWork *__restrict__ 
 // (four 16 x 16 blocks) at a time on the matrix cores: lane l supplies
 // A[l%16][l/16] = G[row][4k + l/16] and B[l/16][l%16] = fY[col][4k + l/16]
 // (read straight from memory; the 64 x 20 slice of fY is 10 KB and stays
-// in cache) and holds D[l/16 + 4r][l%16], r = 0..3, of each block.
+// in cache) and holds D[l/16 + 4r][l%16], r = 0..3, of each block.  The
+// 16 x 64 results pass through the wave's LDS tile so that each store
+// writes one row's 64 consecutive scores (512 bytes).
 __global__ __launch_bounds__(256) void psp_scores_kernel(const PspWork *__restrict__ w) {
+  __shared__ double tile[4][16][65];  // per wave; +1 column against bank conflicts
   const PspWork pr = w[blockIdx.z];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t x0 = (blockIdx.y * 4u + wave) * kPspRows, yb = blockIdx.x * kPspCols;
@@ -111,21 +120,29 @@ __global__ __launch_bounds__(256) void psp_scores_kernel(const PspWork *__restri
       for (int k = 0; k < 5; k++) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], b[cb][k], acc[cb], 0, 0, 0);
     }
 #pragma unroll
-    for (int cb = 0; cb < 4; cb++) {
-      const uint32_t y = y0 + 16u * cb + li;
+    for (int cb = 0; cb < 4; cb++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const uint32_t x = x0 + lk + 4u * r;
-        if (x < pr.lx && y < pr.ly) pr.scores[(uint64_t)x * pr.ly + y] = acc[cb][r];
-      }
+      for (int r = 0; r < 4; r++) tile[wave][lk + 4 * r][16 * cb + li] = acc[cb][r];
+    // the wave's own tile: order its writes before its reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t y = y0 + lane;
+#pragma unroll
+    for (int row = 0; row < 16; row++) {
+      const uint32_t x = x0 + row;
+      if (x < pr.lx && y < pr.ly) pr.scores[(uint64_t)x * pr.ly + y] = tile[wave][row][lane];
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // reads done before the next writes
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
 hipError_t launch_psp_scores(hipStream_t st, const PspWork *w, uint32_t npairs, uint32_t max_lx,
                              uint32_t max_ly, const double *M) {
   if (npairs == 0 || max_lx == 0 || max_ly == 0) return hipSuccess;
-  const uint32_t gx = std::min<uint32_t>((max_lx * 20u + 255u) / 256u, 64u);
+  const uint32_t gx = std::min<uint32_t>((max_lx + 255u) / 256u, 64u);
   hipLaunchKernelGGL(psp_g_kernel, dim3(gx, npairs), dim3(256), 0, st, w, npairs, M);
   KD_HIP(hipGetLastError());
   const dim3 grid((max_ly + kPspCols - 1) / kPspCols, (max_lx + 4 * kPspRows - 1) / (4 * kPspRows), npairs);
