@@ -355,8 +355,11 @@ typedef struct kd_psp_pair {
  * (the paper names PAM 200 and VTML 240; none ships with this library).
  * FP64 throughout (matrix cores).
  *   M      device f64[20 x 20], row-major, amino acids in profile order
- *   pairs  host array of npairs descriptors, npairs <= 65535
- * Errors: KD_EINVAL for a NULL argument or too many pairs. */
+ *   pairs  host array of npairs descriptors (pairs with lx or ly 0 are
+ *          skipped)
+ * Device memory: a temporary of 160 bytes per row of the fx profiles.
+ * Errors: KD_EINVAL for a NULL argument, or more than 2^31 tiles of
+ * 64 x 512 scores in one call. */
 kd_status psp_scores(kd_ctx *ctx, const double *M, uint32_t npairs, const kd_psp_pair *pairs);
 
 /* ----------------------------------------------------------------- server */

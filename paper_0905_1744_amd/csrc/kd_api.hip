@@ -1004,36 +1004,36 @@ extern "C" kd_status psp_profile(kd_ctx *ctx, const uint8_t *aln, uint32_t m, ui
 }
 
 extern "C" kd_status psp_scores(kd_ctx *ctx, const double *M, uint32_t npairs, const kd_psp_pair *pairs) {
-  if (!ctx || !M || (npairs > 0 && !pairs) || npairs > 65535) return KD_EINVAL;
-  uint32_t mx = 0, my = 0;
+  if (!ctx || !M || (npairs > 0 && !pairs)) return KD_EINVAL;
+  // descriptors of the pairs that have scores, with their grid offsets
+  std::vector<PspWork> h;
+  uint64_t gsz = 0, gblks = 0, tiles = 0;
   for (uint32_t q = 0; q < npairs; q++) {
     const kd_psp_pair &p = pairs[q];
-    if (p.lx > 0 && p.ly > 0 && (!p.fx || !p.fy || !p.scores)) return KD_EINVAL;
-    if (p.lx > 0 && p.ly > 0) {
-      mx = std::max(mx, p.lx);
-      my = std::max(my, p.ly);
-    }
+    if (p.lx == 0 || p.ly == 0) continue;  // empty pairs write nothing
+    if (!p.fx || !p.fy || !p.scores) return KD_EINVAL;
+    const uint64_t rt = (p.lx + kPspRowsPerTile - 1) / kPspRowsPerTile;
+    const uint64_t ct = (p.ly + kPspColsPerTile - 1) / kPspColsPerTile;
+    h.push_back(PspWork{p.fx, p.fy, p.scores, nullptr, p.lx, p.ly, (uint32_t)gblks, (uint32_t)tiles});
+    gsz += 20ull * p.lx;
+    gblks += rt;
+    tiles += rt * ct;
+    if (tiles > 0x7FFFFFFFull) return KD_EINVAL;  // beyond one launch's grid
   }
-  if (mx == 0) return KD_OK;
+  if (h.empty()) return KD_OK;
   KD_TRY(hipSetDevice(ctx->device));
   Scope tmp(ctx);
-  uint64_t gsz = 0;
-  for (uint32_t q = 0; q < npairs; q++)
-    if (pairs[q].ly > 0) gsz += 20ull * pairs[q].lx;
-  PspWork *d_w = tmp.get<PspWork>(npairs);
+  PspWork *d_w = tmp.get<PspWork>(h.size());
   double *g = tmp.get<double>(gsz);
   if (!d_w || !g) return KD_ENOMEM;
-  std::vector<PspWork> h(npairs);
   uint64_t go = 0;
-  for (uint32_t q = 0; q < npairs; q++) {
-    const kd_psp_pair &p = pairs[q];
-    const bool any = p.lx > 0 && p.ly > 0;  // empty pairs write nothing
-    h[q] = PspWork{p.fx, p.fy, p.scores, g + go, any ? p.lx : 0u, any ? p.ly : 0u};
-    if (any) go += 20ull * p.lx;
+  for (auto &p : h) {
+    p.g = g + go;
+    go += 20ull * p.lx;
   }
-  KD_TRY(upload(ctx, d_w, h.data(), sizeof(PspWork) * npairs));
+  KD_TRY(upload(ctx, d_w, h.data(), sizeof(PspWork) * h.size()));
   StageTimer t(ctx, KD_STAGE_PSP);
-  KD_TRY(launch_psp_scores(ctx->stream, d_w, npairs, mx, my, M));
+  KD_TRY(launch_psp_scores(ctx->stream, d_w, (uint32_t)h.size(), (uint32_t)gblks, (uint32_t)tiles, M));
   t.done();
   return KD_OK;
 }

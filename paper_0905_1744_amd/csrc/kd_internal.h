@@ -285,13 +285,18 @@ struct PspWork {  // one pair: the caller's descriptor and its G = fX M scratch
   const double *fx;
   const double *fy;
   double *scores;
-  double *g;  // [lx x 20]
+  double *g;        // [lx x 20]
   uint32_t lx, ly;
+  uint32_t gblk0;   // first 64-row block of the pair in the G kernel's grid
+  uint32_t tile0;   // first (64-row x 512-column) tile of the pair in the score kernel's grid
 };
 hipError_t launch_psp_profile(hipStream_t st, const uint8_t *aln, uint32_t m, uint32_t L, double *f,
                               unsigned long long *bad);
-hipError_t launch_psp_scores(hipStream_t st, const PspWork *w, uint32_t npairs, uint32_t max_lx,
-                             uint32_t max_ly, const double *M);
+// w: npairs descriptors with gblk0 / tile0 set (exclusive prefix sums of
+// ceil(lx/64) and ceil(lx/64) ceil(ly/512)); gblks, tiles: the totals
+constexpr uint32_t kPspRowsPerTile = 64, kPspColsPerTile = 512;
+hipError_t launch_psp_scores(hipStream_t st, const PspWork *w, uint32_t npairs, uint32_t gblks,
+                             uint32_t tiles, const double *M);
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);
 // writes the set ids of sg.pos_set / grp_set / rb_set (nsets > 1)
 hipError_t launch_seg_ids(hipStream_t st, const Segs &sg, uint32_t *pos_set, uint32_t *grp_set,

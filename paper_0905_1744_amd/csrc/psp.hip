@@ -4,8 +4,6 @@
 // (p_i p_j)) supplied by the caller.  As matrices, S = fX M fY^T: a dense
 // contraction with K = 20, done on the matrix cores in FP64
 // (v_mfma_f64_16x16x4_f64, five K-steps of 4).
-#include <algorithm>
-
 #include "kd_internal.h"
 
 namespace kd {
@@ -57,45 +55,63 @@ hipError_t launch_psp_profile(hipStream_t st, const uint8_t *aln, uint32_t m, ui
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr uint32_t kPspRows = 16;   // rows per wave (one MFMA block high)
-constexpr uint32_t kPspCols = 512;  // columns per wave (32 MFMA blocks, in groups of 4)
+constexpr uint32_t kPspRows = 16;                // rows per wave (one MFMA block high)
+constexpr uint32_t kPspCols = kPspColsPerTile;  // columns per wave
+
+// the pair whose range [first, next first) holds global block id b
+template <class FirstOf>
+__device__ __forceinline__ uint32_t pair_of(uint32_t npairs, uint32_t b, FirstOf first) {
+  uint32_t lo = 0, hi = npairs;  // last pair with first(q) <= b
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (first(mid) <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
 
 // G = fX M for every row of every pair (the first factor of the
-// contraction): one thread per row, its 20 frequencies in registers, M in
-// LDS, each G[x][j] summed over i in fixed order.
+// contraction): a workgroup takes 64 rows of one pair (compact grid over
+// all pairs' row blocks), stages their frequencies in LDS with coalesced
+// loads and writes the 64 x 20 block of G contiguously; each G[x][j] is
+// summed over i in fixed order.
 __global__ __launch_bounds__(256) void psp_g_kernel(const PspWork *__restrict__ w, uint32_t npairs,
                                                     const double *__restrict__ M) {
   __shared__ double sM[400];
-  for (uint32_t q = threadIdx.x; q < 400; q += 256) sM[q] = M[q];
+  __shared__ double sF[64 * 20];
+  const uint32_t q = pair_of(npairs, blockIdx.x, [&](uint32_t i) { return w[i].gblk0; });
+  const PspWork pr = w[q];
+  const uint32_t r0 = (blockIdx.x - pr.gblk0) * 64u;
+  const uint32_t n = min(64u, pr.lx - r0) * 20u;
+  for (uint32_t e = threadIdx.x; e < 400; e += 256) sM[e] = M[e];
+  for (uint32_t e = threadIdx.x; e < n; e += 256) sF[e] = pr.fx[(uint64_t)r0 * 20 + e];
   __syncthreads();
-  const PspWork pr = w[blockIdx.y];
-  for (uint32_t x = blockIdx.x * 256u + threadIdx.x; x < pr.lx; x += gridDim.x * 256u) {
-    double f[20];
+  for (uint32_t e = threadIdx.x; e < n; e += 256) {
+    const uint32_t x = e / 20u, j = e % 20u;
+    double g = 0.0;
 #pragma unroll
-    for (int i = 0; i < 20; i++) f[i] = pr.fx[(uint64_t)x * 20 + i];
-#pragma unroll 1
-    for (int j = 0; j < 20; j++) {
-      double g = 0.0;
-#pragma unroll
-      for (int i = 0; i < 20; i++) g = fma(f[i], sM[i * 20 + j], g);
-      pr.g[(uint64_t)x * 20 + j] = g;
-    }
+    for (int i = 0; i < 20; i++) g = fma(sF[x * 20 + i], sM[i * 20 + j], g);
+    pr.g[(uint64_t)r0 * 20 + e] = g;
   }
 }
 
-// One wave = 16 rows of one pair against up to 512 columns, 64 columns
-// (four 16 x 16 blocks) at a time on the matrix cores: lane l supplies
-// A[l%16][l/16] = G[row][4k + l/16] and B[l/16][l%16] = fY[col][4k + l/16]
-// (read straight from memory; the 64 x 20 slice of fY is 10 KB and stays
-// in cache) and holds D[l/16 + 4r][l%16], r = 0..3, of each block.  The
-// 16 x 64 results pass through the wave's LDS tile so that each store
-// writes one row's 64 consecutive scores (512 bytes).
-__global__ __launch_bounds__(256) void psp_scores_kernel(const PspWork *__restrict__ w) {
+// One workgroup = one tile of one pair (compact grid over all pairs'
+// tiles): 64 rows x up to 512 columns, wave w taking rows 16w .. 16w+15,
+// 64 columns (four 16 x 16 blocks) at a time on the matrix cores: lane l
+// supplies A[l%16][l/16] = G[row][4k + l/16] and B[l/16][l%16] =
+// fY[col][4k + l/16] (read straight from memory; the 64 x 20 slice of fY is
+// 10 KB and stays in cache) and holds D[l/16 + 4r][l%16], r = 0..3, of each
+// block.  The 16 x 64 results pass through the wave's LDS tile so that each
+// store writes one row's 64 consecutive scores (512 bytes).
+__global__ __launch_bounds__(256) void psp_scores_kernel(const PspWork *__restrict__ w, uint32_t npairs) {
   __shared__ double tile[4][16][65];  // per wave; +1 column against bank conflicts
-  const PspWork pr = w[blockIdx.z];
+  const uint32_t q = pair_of(npairs, blockIdx.x, [&](uint32_t i) { return w[i].tile0; });
+  const PspWork pr = w[q];
+  const uint32_t nty = (pr.ly + kPspCols - 1) / kPspCols;
+  const uint32_t t = blockIdx.x - pr.tile0;
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const uint32_t x0 = (blockIdx.y * 4u + wave) * kPspRows, yb = blockIdx.x * kPspCols;
-  if (x0 >= pr.lx || yb >= pr.ly) return;
+  const uint32_t x0 = (t / nty) * kPspRowsPerTile + wave * kPspRows, yb = (t % nty) * kPspCols;
+  if (x0 >= pr.lx) return;  // the last row tile of a pair may have fewer than 64 rows
   const uint32_t li = lane & 15u, lk = lane >> 4;
   double a[5];
   {
@@ -139,14 +155,12 @@ __global__ __launch_bounds__(256) void psp_scores_kernel(const PspWork *__restri
   }
 }
 
-hipError_t launch_psp_scores(hipStream_t st, const PspWork *w, uint32_t npairs, uint32_t max_lx,
-                             uint32_t max_ly, const double *M) {
-  if (npairs == 0 || max_lx == 0 || max_ly == 0) return hipSuccess;
-  const uint32_t gx = std::min<uint32_t>((max_lx + 255u) / 256u, 64u);
-  hipLaunchKernelGGL(psp_g_kernel, dim3(gx, npairs), dim3(256), 0, st, w, npairs, M);
+hipError_t launch_psp_scores(hipStream_t st, const PspWork *w, uint32_t npairs, uint32_t gblks,
+                             uint32_t tiles, const double *M) {
+  if (npairs == 0 || tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(psp_g_kernel, dim3(gblks), dim3(256), 0, st, w, npairs, M);
   KD_HIP(hipGetLastError());
-  const dim3 grid((max_ly + kPspCols - 1) / kPspCols, (max_lx + 4 * kPspRows - 1) / (4 * kPspRows), npairs);
-  hipLaunchKernelGGL(psp_scores_kernel, grid, dim3(256), 0, st, w);
+  hipLaunchKernelGGL(psp_scores_kernel, dim3(tiles), dim3(256), 0, st, w, npairs);
   return hipGetLastError();
 }
 
