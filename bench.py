@@ -40,13 +40,23 @@ WORKLOADS = {
 # sources hash to the measured version and the same work-list shape is in use.
 RANK_SOURCES = ["paper_0905_1744_amd/csrc/pair.hip", "paper_0905_1744_amd/csrc/tile.h",
                 "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h"]
+TREE_SOURCES = ["paper_0905_1744_amd/csrc/tree.hip", "paper_0905_1744_amd/csrc/tile.h",
+                "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h",
+                "paper_0905_1744_amd/csrc/radix.h"]
 TRAFFIC = {
     "rank_pairs_kernel": {"sources": RANK_SOURCES, "sha256_16": "2f650a120323f405",
                           "workload": "paper20k", "rows_per_workgroup": 2, "bytes_per_launch": 839851227},
     "rank_cross_kernel": {"sources": ["paper_0905_1744_amd/csrc/cross.hip", "paper_0905_1744_amd/csrc/tile.h",
                                       "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h"],
-                          "sha256_16": None, "workload": "global100k", "rows_per_workgroup": None,
-                          "bytes_per_launch": 2832240965},
+                          "sha256_16": "6f4d6a4f4effdd3f", "workload": "global100k", "rows_per_workgroup": None,
+                          "bytes_per_launch": 2843834059},
+    "dist_pairs_kernel": {"sources": TREE_SOURCES, "sha256_16": "559ccfbdf50020fd", "workload": "trees20k",
+                          "rows_per_workgroup": None, "bytes_per_launch": 1194144355},
+    "upgma_kernel": {"sources": TREE_SOURCES, "sha256_16": "559ccfbdf50020fd", "workload": "trees20k",
+                     "rows_per_workgroup": None, "bytes_per_launch": 998879408},
+    # psp_g_kernel + psp_scores_kernel, the two launches of one psp_scores call
+    "psp": {"sources": ["paper_0905_1744_amd/csrc/psp.hip"], "sha256_16": "d93f5d45b5f90bda", "workload": "psp",
+            "rows_per_workgroup": None, "bytes_per_launch": 94291360 + 2983557472},
 }
 
 
@@ -202,10 +212,10 @@ def bench_global(args):
     t_loc = st["pairs"][0] / max(st["pairs"][1], 1) / 1e3
     t_cross = st["global"][0] / max(st["global"][1], 1) / 1e3
 
-    def roof(name, probes, pairs, t):
+    def roof(name, probes, pairs, t, traffic=None):
         a = probes / t / 1e12
         return {"bound": "alu", "achieved": a, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
-                "frac": a / PEAK_TPROBE, "traffic": None, "kernel": name, "kernel_ms": t * 1e3,
+                "frac": a / PEAK_TPROBE, "traffic": traffic, "kernel": name, "kernel_ms": t * 1e3,
                 "work_per_launch": {"probes": probes, "pairs": pairs}}
 
     # the comparison of the paper's Table 1, outside the timed region
@@ -225,7 +235,8 @@ def bench_global(args):
                             "kmer_rank_global + sample_partition"), "autotune": tune},
         "stages_ms_per_step": {k_: v[0] / nb for k_, v in stages.items() if v[1]},
         "roofline": roof("rank_pairs_kernel (local ranks)", probes_local, local_pairs, t_loc),
-        "roofline_cross": roof("rank_cross_kernel", probes_cross, cross_pairs, t_cross),
+        "roofline_cross": roof("rank_cross_kernel", probes_cross, cross_pairs, t_cross,
+                               measured_traffic("rank_cross_kernel", args.workload, None)),
         "table1": cmp,
     }
     kb.destroy()
@@ -301,9 +312,12 @@ def bench_trees(args):
                             "kmer_distance_matrices + upgma_trees")},
         "stages_ms_per_step": {k: v[0] / nb for k, v in stages.items() if v[1]},
         "roofline": {"bound": "alu", "achieved": a, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
-                     "frac": a / PEAK_TPROBE, "traffic": None, "kernel": "dist_pairs_kernel",
+                     "frac": a / PEAK_TPROBE,
+                     "traffic": measured_traffic("dist_pairs_kernel", args.workload, None),
+                     "kernel": "dist_pairs_kernel",
                      "kernel_ms": t_dist * 1e3, "work_per_launch": {"probes": probes, "pairs": pairs}},
         "upgma": {"kernel": "upgma_kernel", "ms": t_tree * 1e3, "merges": int((n - 1).sum()),
+                  "traffic": measured_traffic("upgma_kernel", args.workload, None),
                   "us_per_merge_step": t_tree * 1e6 / max(int(n.max()) - 1, 1),
                   "note": "one workgroup per bucket; merge steps are sequential, so the time is "
                           "the largest bucket's steps x the latency of one step"},
@@ -369,12 +383,23 @@ def bench_psp(args):
                                 f"profiles, log-odds of a random symmetric joint distribution, seed 11"),
                    "scores_per_step": scores},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-                     "traffic": None, "kernel": "psp_scores_kernel", "kernel_ms": t_k * 1e3,
+                     "traffic": measured_traffic("psp", args.workload, None),
+                     "kernel": "psp_g_kernel + psp_scores_kernel (one psp_scores call)", "kernel_ms": t_k * 1e3,
                      "bytes_per_launch": nbytes,
                      "flops_per_launch": 2 * 20 * scores + 2 * 400 * int(lens[:, 0].sum())},
     }
     ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def batch_roofline(probes, pairs, stages):
+    """Probe roofline of the one rank launch of a batch (all sets)."""
+    ms, n = stages["pairs"]
+    t = ms / max(n, 1) / 1e3
+    a = probes / t / 1e12
+    return {"bound": "alu", "achieved": a, "peak": PEAK_TPROBE, "unit": "Tprobe/s", "frac": a / PEAK_TPROBE,
+            "traffic": None, "kernel": "rank_pairs_kernel (all sets in one launch)", "kernel_ms": t * 1e3,
+            "work_per_launch": {"probes": probes, "pairs": pairs}}
 
 
 def bench_batched(args):
@@ -403,11 +428,14 @@ def bench_batched(args):
     ns = np.diff(first.astype(np.int64))
     pairs = float((ns * (ns - 1) // 2).sum())
     tune = None
+    kb = ctx.kmer_count_batch(res, off, first)
     if not args.no_autotune:  # work-list shape for batches of this size class
-        kb = ctx.kmer_count_batch(res, off, first)
         best, ms = ctx.autotune(kb, args.delta)
         tune = {"rows_per_workgroup": best, "ms_per_shape": ms}
-        kb.destroy()
+    _, _, loff = kb.export_lists()
+    D = np.diff(loff.cpu().numpy())
+    probes = sum(probe_count(D[a:b]) for a, b in zip(first[:-1].astype(np.int64), first[1:].astype(np.int64)))
+    kb.destroy()
     for _ in range(args.warmup):
         ctx.batch_run(res, off, first, Bs, args.delta, out=out)
     torch.cuda.synchronize()
@@ -424,7 +452,8 @@ def bench_batched(args):
     if args.no_loop_baseline:
         line = {"metric": "batched k-mer rank + split: pair-similarities/s", "value": pairs / t_batch,
                 "unit": "pair-similarities/s", "ms_per_step": t_batch * 1e3, "sets": len(sets),
-                "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]}}
+                "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
+                "roofline": batch_roofline(probes, pairs, stages)}
         ctx.close()
         print(json.dumps(line), flush=True)
         return
@@ -467,6 +496,7 @@ def bench_batched(args):
         "speedup_vs_per_set_loop": t_loop / t_batch,
         "identical_outputs": same,
         "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
+        "roofline": batch_roofline(probes, pairs, stages),
     }
     ctx.close()
     print(json.dumps(line), flush=True)

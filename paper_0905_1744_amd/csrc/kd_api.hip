@@ -1012,15 +1012,11 @@ extern "C" kd_status psp_scores(kd_ctx *ctx, const double *M, uint32_t npairs, c
     const kd_psp_pair &p = pairs[q];
     if (p.lx == 0 || p.ly == 0) continue;  // empty pairs write nothing
     if (!p.fx || !p.fy || !p.scores) return KD_EINVAL;
-    const uint64_t rt = (p.lx + kPspRowsPerTile - 1) / kPspRowsPerTile;
-    const uint64_t ct = (p.ly + kPspColsPerTile - 1) / kPspColsPerTile;
-    h.push_back(PspWork{p.fx, p.fy, p.scores, nullptr, p.lx, p.ly, (uint32_t)gblks, (uint32_t)tiles});
+    h.push_back(PspWork{p.fx, p.fy, p.scores, nullptr, p.lx, p.ly, 0, 0});
     gsz += 20ull * p.lx;
-    gblks += rt;
-    tiles += rt * ct;
-    if (tiles > 0x7FFFFFFFull) return KD_EINVAL;  // beyond one launch's grid
   }
   if (h.empty()) return KD_OK;
+  if (!psp_plan(h, gblks, tiles)) return KD_EINVAL;
   KD_TRY(hipSetDevice(ctx->device));
   Scope tmp(ctx);
   PspWork *d_w = tmp.get<PspWork>(h.size());

@@ -292,9 +292,10 @@ struct PspWork {  // one pair: the caller's descriptor and its G = fX M scratch
 };
 hipError_t launch_psp_profile(hipStream_t st, const uint8_t *aln, uint32_t m, uint32_t L, double *f,
                               unsigned long long *bad);
-// w: npairs descriptors with gblk0 / tile0 set (exclusive prefix sums of
-// ceil(lx/64) and ceil(lx/64) ceil(ly/512)); gblks, tiles: the totals
-constexpr uint32_t kPspRowsPerTile = 64, kPspColsPerTile = 512;
+// host: sets each descriptor's gblk0 / tile0 (its first block in the two
+// kernels' compact grids) and returns the totals; false if a grid would be
+// too large for one launch
+bool psp_plan(std::vector<PspWork> &w, uint64_t &gblks, uint64_t &tiles);
 hipError_t launch_psp_scores(hipStream_t st, const PspWork *w, uint32_t npairs, uint32_t gblks,
                              uint32_t tiles, const double *M);
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);

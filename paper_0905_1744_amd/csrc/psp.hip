@@ -4,6 +4,8 @@
 // (p_i p_j)) supplied by the caller.  As matrices, S = fX M fY^T: a dense
 // contraction with K = 20, done on the matrix cores in FP64
 // (v_mfma_f64_16x16x4_f64, five K-steps of 4).
+#include <vector>
+
 #include "kd_internal.h"
 
 namespace kd {
@@ -55,8 +57,23 @@ hipError_t launch_psp_profile(hipStream_t st, const uint8_t *aln, uint32_t m, ui
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr uint32_t kPspRows = 16;                // rows per wave (one MFMA block high)
-constexpr uint32_t kPspCols = kPspColsPerTile;  // columns per wave
+constexpr uint32_t kPspRowsPerTile = 64;  // rows per score workgroup (4 waves)
+constexpr uint32_t kPspRows = 16;         // rows per wave (one MFMA block high)
+constexpr uint32_t kPspCols = 512;        // columns per wave
+
+bool psp_plan(std::vector<PspWork> &w, uint64_t &gblks, uint64_t &tiles) {
+  gblks = tiles = 0;
+  for (auto &p : w) {
+    const uint64_t rt = (p.lx + kPspRowsPerTile - 1) / kPspRowsPerTile;
+    const uint64_t ct = (p.ly + kPspCols - 1) / kPspCols;
+    p.gblk0 = (uint32_t)gblks;
+    p.tile0 = (uint32_t)tiles;
+    gblks += rt;
+    tiles += rt * ct;
+    if (tiles > 0x7FFFFFFFull) return false;  // beyond one launch's grid
+  }
+  return true;
+}
 
 // the pair whose range [first, next first) holds global block id b
 template <class FirstOf>
