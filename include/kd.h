@@ -277,6 +277,26 @@ kd_status kd_batch_run(kd_ctx *ctx, const uint8_t *residues, const uint64_t *off
 kd_status kmer_rank_global(kd_ctx *ctx, const kd_set *blocks, const double *local_ranks,
                            uint32_t k, double delta, double *ranks, uint32_t *samples);
 
+/* ------------------------------------------------------------ decompose */
+
+/* The decomposition front end of Algorithm 2 on one device, in one call:
+ * every sequence ranked, then split into B buckets by regular sampling
+ * (sample_partition).  The rank is either
+ *   KD_RANK_CENTRALIZED  Equation 3 over all n sequences (kmer_rank), or
+ *   KD_RANK_GLOBALIZED   the globalized rank of Section 3.1.1: the B blocks
+ *                        [floor(bn/B), floor((b+1)n/B)) counted as a batch,
+ *                        ranked locally, k = max(1, B-1) samples per block
+ *                        (kmer_rank_global).
+ * Outputs as for sample_partition, plus ranks (device f64[n]); the results
+ * are bit-identical to making those calls one by one.
+ * Errors: those of the calls it makes; KD_EINVAL for an unknown mode or a
+ * block smaller than k. */
+#define KD_RANK_CENTRALIZED 0
+#define KD_RANK_GLOBALIZED 1
+kd_status kd_decompose(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                       uint32_t n_seqs, uint64_t n_residues, uint32_t B, int mode, double delta,
+                       double *ranks, uint32_t *bucket, uint32_t *order, uint32_t *bucket_offsets);
+
 /* ------------------------------------------------- buckets and guide trees */
 
 /* Redistribution on one device (Section 3.1.2: bucket i's sequences go to

@@ -104,6 +104,7 @@ def lib():
         "kmer_distance_matrices": (i32, [P, P, C.c_double, P]),
         "upgma_trees": (i32, [P, u32, P, P, P, P]),
         "psp_profile": (i32, [P, P, u32, u32, P]),
+        "kd_decompose": (i32, [P, P, P, u32, u64, u32, C.c_int, C.c_double, P, P, P, P]),
         "psp_scores": (i32, [P, P, u32, P]),
         "kd_server_create": (i32, [C.c_int, C.POINTER(ServerOpts), PP]),
         "kd_server_submit": (i32, [P, C.POINTER(Job), C.POINTER(u64)]),
@@ -339,6 +340,23 @@ class Context:
         finally:
             kb.destroy()
         return dict(local=loc, ranks=R, samples=smp)
+
+    # ---------------------------------------------------------- decompose
+    def decompose(self, residues, offsets, B: int, globalized: bool = False, delta: float = 0.1):
+        """Algorithm 2's front end in one call: ranks (centralized, or
+        globalized with k = B - 1 samples per block) and the split into B
+        buckets.  Returns dict(ranks, bucket, order, offsets)."""
+        res = _dev_tensor(residues, torch.uint8, self.device)
+        off = _dev_tensor(offsets, torch.int64, self.device)
+        n = off.numel() - 1
+        R = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+        bucket = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        order = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        boff = torch.empty(B + 1 if B > 0 else 1, dtype=torch.int32, device=self.device)
+        self._check(lib().kd_decompose(self.handle, _ptr(res), _ptr(off), n, res.numel(), B, int(bool(globalized)),
+                                       float(delta), _ptr(R), _ptr(bucket), _ptr(order), _ptr(boff)),
+                    "kd_decompose")
+        return dict(ranks=R[:n], bucket=bucket[:n], order=order[:n], offsets=boff)
 
     # ------------------------------------------- buckets and guide trees
     def gather_sequences(self, residues, offsets, order):

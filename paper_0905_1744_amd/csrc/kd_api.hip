@@ -875,6 +875,35 @@ extern "C" kd_status kmer_rank_global(kd_ctx *ctx, const kd_set *s, const double
   return from_hip(e);
 }
 
+// ------------------------------------------------------------ decompose
+
+extern "C" kd_status kd_decompose(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                                  uint32_t n_seqs, uint64_t n_residues, uint32_t B, int mode,
+                                  double delta, double *ranks, uint32_t *bucket, uint32_t *order,
+                                  uint32_t *bucket_offsets) {
+  if (!ctx || !ranks || !bucket || !order || !bucket_offsets) return KD_EINVAL;
+  if (mode != KD_RANK_CENTRALIZED && mode != KD_RANK_GLOBALIZED) return KD_EINVAL;
+  if (n_seqs == 0 || B == 0 || B > n_seqs || B > kMaxBuckets) return KD_EINVAL;
+  kd_set *s = nullptr;
+  kd_status rc;
+  if (mode == KD_RANK_CENTRALIZED) {
+    rc = kmer_count(ctx, residues, offsets, n_seqs, n_residues, &s);
+    if (rc == KD_OK) rc = kmer_rank(ctx, s, delta, ranks);
+  } else {
+    std::vector<uint32_t> first(B + 1);
+    for (uint32_t b = 0; b <= B; b++) first[b] = (uint32_t)((uint64_t)b * n_seqs / B);
+    rc = kmer_count_batch(ctx, residues, offsets, n_residues, B, first.data(), &s);
+    Scope tmp(ctx);
+    double *local = rc == KD_OK ? tmp.get<double>(n_seqs) : nullptr;
+    if (rc == KD_OK && !local) rc = KD_ENOMEM;
+    if (rc == KD_OK) rc = kmer_rank(ctx, s, delta, local);
+    if (rc == KD_OK) rc = kmer_rank_global(ctx, s, local, B > 1 ? B - 1 : 1, delta, ranks, nullptr);
+  }
+  if (s) kd_set_destroy(s);  // stream order keeps its blocks valid for the launches above
+  if (rc != KD_OK) return rc;
+  return sample_partition(ctx, ranks, n_seqs, B, bucket, order, bucket_offsets, nullptr, nullptr);
+}
+
 // ------------------------------------------------ buckets and guide trees
 
 extern "C" kd_status kd_gather_sequences(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,

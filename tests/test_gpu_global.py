@@ -191,3 +191,23 @@ def test_global_full_size_sampled(kd, ctx, oracle_mod, which):
     p = ctx.sample_partition(out["ranks"], B)
     off = kd.u32(p["offsets"])
     assert off[-1] == ss.n and np.diff(off.astype(np.int64)).max() <= 2 * math.ceil(ss.n / B)
+
+
+@pytest.mark.parametrize("globalized", [False, True])
+def test_decompose_matches_calls(kd, ctx, oracle_mod, globalized):
+    """kd_decompose equals the calls it stands for, bit for bit."""
+    ss = synth.small()
+    off = ss.offsets.view(np.int64)
+    out = ctx.decompose(ss.residues, off, ss.B, globalized=globalized)
+    if globalized:
+        R = ctx.globalized_rank(ss.residues, off, ss.B, ss.B - 1)["ranks"]
+    else:
+        ks = ctx.kmer_count(ss.residues, off)
+        R = ctx.kmer_rank(ks, 0.1)
+        ks.destroy()
+    p = ctx.sample_partition(R, ss.B)
+    assert np.array_equal(out["ranks"].cpu().numpy(), R.cpu().numpy())
+    for k in ("bucket", "order", "offsets"):
+        assert np.array_equal(kd.u32(out[k]), kd.u32(p[k])), k
+    with pytest.raises(kd.KdError):
+        ctx.decompose(ss.residues, off, ss.n + 1)
