@@ -55,8 +55,8 @@ TRAFFIC = {
     "upgma_kernel": {"sources": TREE_SOURCES, "sha256_16": "559ccfbdf50020fd", "workload": "trees20k",
                      "rows_per_workgroup": None, "bytes_per_launch": 998879408},
     # psp_g_kernel + psp_scores_kernel, the two launches of one psp_scores call
-    "psp": {"sources": ["paper_0905_1744_amd/csrc/psp.hip"], "sha256_16": "d93f5d45b5f90bda", "workload": "psp",
-            "rows_per_workgroup": None, "bytes_per_launch": 94291360 + 2983557472},
+    "psp": {"sources": ["paper_0905_1744_amd/csrc/psp.hip"], "sha256_16": "641050ec05ed3fe7", "workload": "psp",
+            "rows_per_workgroup": None, "bytes_per_launch": 94292377 + 2872391142},
 }
 
 

@@ -288,7 +288,7 @@ struct PspWork {  // one pair: the caller's descriptor and its G = fX M scratch
   double *g;        // [lx x 20]
   uint32_t lx, ly;
   uint32_t gblk0;   // first 64-row block of the pair in the G kernel's grid
-  uint32_t tile0;   // first (64-row x 512-column) tile of the pair in the score kernel's grid
+  uint32_t tile0;   // first (64-row x 4-piece) tile of the pair in the score kernel's grid
 };
 hipError_t launch_psp_profile(hipStream_t st, const uint8_t *aln, uint32_t m, uint32_t L, double *f,
                               unsigned long long *bad);

@@ -56,20 +56,29 @@ hipError_t launch_psp_profile(hipStream_t st, const uint8_t *aln, uint32_t m, ui
 // ------------------------------------------------------------------ scores
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+// the work list's pointers name global memory: loads and stores through
+// them are global (not flat) instructions, whose completion counts in order
+typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(1))) double gdouble;
 
-constexpr uint32_t kPspRowsPerTile = 64;  // rows per score workgroup (4 waves)
-constexpr uint32_t kPspRows = 16;         // rows per wave (one MFMA block high)
-constexpr uint32_t kPspCols = 512;        // columns per wave
+constexpr uint32_t kPspRowsPerTile = 64;  // rows per score workgroup; each wave takes all of them, 16 at a time
+constexpr uint32_t kPspRows = 16;         // rows per step (one MFMA block high)
+constexpr uint32_t kPspPieces = 4;        // 64-column pieces per workgroup, one per wave
+constexpr uint32_t kPspSpan = 80;         // columns a wave computes: its piece's 64 and the 16 before
+
+// 64-column pieces of a row of ly scores: the row is cut on 128-byte lines
+// 16 columns before each multiple of 64 (see psp_scores_kernel)
+__host__ __device__ inline uint32_t psp_pieces(uint32_t ly) { return (ly + 16 + 63) / 64; }
 
 bool psp_plan(std::vector<PspWork> &w, uint64_t &gblks, uint64_t &tiles) {
   gblks = tiles = 0;
   for (auto &p : w) {
     const uint64_t rt = (p.lx + kPspRowsPerTile - 1) / kPspRowsPerTile;
-    const uint64_t ct = (p.ly + kPspCols - 1) / kPspCols;
+    const uint64_t ct = (psp_pieces(p.ly) + kPspPieces - 1) / kPspPieces;
     p.gblk0 = (uint32_t)gblks;
     p.tile0 = (uint32_t)tiles;
     gblks += rt;
-    tiles += rt * ct;
+    tiles += p.ly ? rt * ct : 0;
     if (tiles > 0x7FFFFFFFull) return false;  // beyond one launch's grid
   }
   return true;
@@ -101,74 +110,115 @@ __global__ __launch_bounds__(256) void psp_g_kernel(const PspWork *__restrict__ 
   const uint32_t r0 = (blockIdx.x - pr.gblk0) * 64u;
   const uint32_t n = min(64u, pr.lx - r0) * 20u;
   for (uint32_t e = threadIdx.x; e < 400; e += 256) sM[e] = M[e];
-  for (uint32_t e = threadIdx.x; e < n; e += 256) sF[e] = pr.fx[(uint64_t)r0 * 20 + e];
+  gcdouble *fx = (gcdouble *)pr.fx + (uint64_t)r0 * 20;
+  gdouble *g = (gdouble *)pr.g + (uint64_t)r0 * 20;
+  for (uint32_t e = threadIdx.x; e < n; e += 256) sF[e] = fx[e];
   __syncthreads();
   for (uint32_t e = threadIdx.x; e < n; e += 256) {
     const uint32_t x = e / 20u, j = e % 20u;
-    double g = 0.0;
+    double acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < 20; i++) g = fma(sF[x * 20 + i], sM[i * 20 + j], g);
-    pr.g[(uint64_t)r0 * 20 + e] = g;
+    for (int i = 0; i < 20; i++) acc = fma(sF[x * 20 + i], sM[i * 20 + j], acc);
+    g[e] = acc;
   }
 }
 
-// One workgroup = one tile of one pair (compact grid over all pairs'
-// tiles): 64 rows x up to 512 columns, wave w taking rows 16w .. 16w+15,
-// 64 columns (four 16 x 16 blocks) at a time on the matrix cores: lane l
-// supplies A[l%16][l/16] = G[row][4k + l/16] and B[l/16][l%16] =
-// fY[col][4k + l/16] (read straight from memory; the 64 x 20 slice of fY is
-// 10 KB and stays in cache) and holds D[l/16 + 4r][l%16], r = 0..3, of each
-// block.  The 16 x 64 results pass through the wave's LDS tile so that each
-// store writes one row's 64 consecutive scores (512 bytes).
+// orders a wave's LDS accesses around its own tile
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One workgroup = 64 rows x 4 pieces of one pair (compact grid over all
+// pairs' tiles); wave w takes piece p = 4 tc + w of every row.
+//
+// The stores are shaped for HBM.  Every store writes 64 consecutive scores
+// of one row starting on a 128-byte line, so no line is written in parts by
+// two stores: with s the first column of row x on a line boundary, piece p of
+// the row is columns [64p + s - 16, 64p + s + 48) clipped to the row (the
+// pieces tile the row; an extra piece finishes rows whose end lies past the
+// last multiple of 64).  A wave computes the 80 columns 64p - 16 .. 64p + 63,
+// which hold piece p of every row, and writes them row by row into its LDS
+// tile; lane l then stores column lo + min(l, n) of the piece [lo, lo + n],
+// so lanes past the piece repeat its last element, an empty piece repeats
+// the row's last element, and rows past the end of the profile repeat its
+// last row: every store is whole and writes only correct values.
+//
+// The matrix-core operands (fY of the 80 columns, G of the 64 rows) are
+// loaded once, before the first store: inside the loop the wave issues only
+// stores and LDS traffic, so no wait ever waits on its stores (a load after
+// them would complete only after them).  Lane l supplies A[l%16][l/16] =
+// G[row][4k + l/16] and B[l/16][l%16] = fY[col][4k + l/16] and holds
+// D[l/16 + 4r][l%16] of each 16 x 16 block.
 __global__ __launch_bounds__(256) void psp_scores_kernel(const PspWork *__restrict__ w, uint32_t npairs) {
-  __shared__ double tile[4][16][65];  // per wave; +1 column against bank conflicts
+  __shared__ double tiles[4][kPspRows][kPspSpan];
   const uint32_t q = pair_of(npairs, blockIdx.x, [&](uint32_t i) { return w[i].tile0; });
   const PspWork pr = w[q];
-  const uint32_t nty = (pr.ly + kPspCols - 1) / kPspCols;
+  const uint32_t lane = threadIdx.x & 63u, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t ly = pr.ly, npieces = psp_pieces(ly), nct = (npieces + kPspPieces - 1) / kPspPieces;
   const uint32_t t = blockIdx.x - pr.tile0;
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const uint32_t x0 = (t / nty) * kPspRowsPerTile + wave * kPspRows, yb = (t % nty) * kPspCols;
-  if (x0 >= pr.lx) return;  // the last row tile of a pair may have fewer than 64 rows
+  const uint32_t p = (t % nct) * kPspPieces + wave, xb = (t / nct) * kPspRowsPerTile;
+  if (p >= npieces) return;
   const uint32_t li = lane & 15u, lk = lane >> 4;
-  double a[5];
-  {
-    const uint32_t x = min(x0 + li, pr.lx - 1u);  // rows past the end: any valid row, not stored
+  const int64_t yc = 64 * (int64_t)p - 16;  // first computed column (piece 0: columns -16 .. -1 unused)
+  double b[5][5];
 #pragma unroll
-    for (int k = 0; k < 5; k++) a[k] = pr.g[(uint64_t)x * 20 + 4 * k + lk];
+  for (int cb = 0; cb < 5; cb++) {  // columns outside the row: any valid column, never stored
+    const uint32_t y = (uint32_t)min(max(yc + 16 * cb + li, (int64_t)0), (int64_t)ly - 1);
+    gcdouble *fy = (gcdouble *)pr.fy + (uint64_t)y * 20 + lk;
+#pragma unroll
+    for (int k = 0; k < 5; k++) b[cb][k] = fy[4 * k];
   }
-  const uint32_t ye = min(pr.ly, yb + kPspCols);
-  for (uint32_t y0 = yb; y0 < ye; y0 += 64) {
-    double b[4][5];
+  double a[4][5];
 #pragma unroll
-    for (int cb = 0; cb < 4; cb++) {
-      const uint32_t y = min(y0 + 16u * cb + li, pr.ly - 1u);
+  for (int rb = 0; rb < 4; rb++) {  // rows past the end: the last row
+    const uint32_t x = min(xb + 16u * rb + li, pr.lx - 1u);
+    gcdouble *g = (gcdouble *)pr.g + (uint64_t)x * 20 + lk;
 #pragma unroll
-      for (int k = 0; k < 5; k++) b[cb][k] = pr.fy[(uint64_t)y * 20 + 4 * k + lk];
+    for (int k = 0; k < 5; k++) a[rb][k] = g[4 * k];
+  }
+  const uint64_t base8 = (uint64_t)(uintptr_t)pr.scores >> 3;  // address of S in doubles
+  double(*tile)[kPspSpan] = tiles[wave];
+#pragma unroll
+  for (int rb = 0; rb < 4; rb++) {
+    const uint32_t x0 = xb + 16u * rb;
+    if (x0 >= pr.lx) break;
+    v4d acc[5];
+#pragma unroll
+    for (int cb = 0; cb < 5; cb++) acc[cb] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 5; k++)
+#pragma unroll
+      for (int cb = 0; cb < 5; cb++) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][k], b[cb][k], acc[cb], 0, 0, 0);
+    wave_sync();  // the previous step's reads of the tile are done
+#pragma unroll
+    for (int cb = 0; cb < 5; cb++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) tile[lk + 4 * r][16 * cb + li] = acc[cb][r];
+    wave_sync();
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      double v[8];
+      uint32_t off[8];
+#pragma unroll
+      for (int r = 0; r < 8; r++) {  // piece p of row x: [lo, lo + n]
+        const uint32_t x = min(x0 + 8 * h + r, pr.lx - 1u);
+        const uint32_t s = (16u - (uint32_t)((base8 + (uint64_t)x * ly) & 15u)) & 15u;
+        const uint32_t lo0 = 64u * p + s > 16u ? 64u * p + s - 16u : 0u;
+        const uint32_t hi = min(64u * p + s + 48u, ly);
+        const uint32_t lo = lo0 < hi ? lo0 : ly - 1u;
+        const uint32_t n = lo0 < hi ? hi - 1u - lo : 0u;
+        const uint32_t d = min(lane, n);
+        off[r] = lo + d;
+        v[r] = tile[x - x0][(uint32_t)((int64_t)lo - yc) + d];
+      }
+#pragma unroll
+      for (int r = 0; r < 8; r++) {
+        gdouble *row = (gdouble *)pr.scores + (uint64_t)min(x0 + 8 * h + r, pr.lx - 1u) * ly;
+        row[off[r]] = v[r];
+      }
     }
-    v4d acc[4];
-#pragma unroll
-    for (int cb = 0; cb < 4; cb++) {
-      acc[cb] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int k = 0; k < 5; k++) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], b[cb][k], acc[cb], 0, 0, 0);
-    }
-#pragma unroll
-    for (int cb = 0; cb < 4; cb++)
-#pragma unroll
-      for (int r = 0; r < 4; r++) tile[wave][lk + 4 * r][16 * cb + li] = acc[cb][r];
-    // the wave's own tile: order its writes before its reads
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint32_t y = y0 + lane;
-#pragma unroll
-    for (int row = 0; row < 16; row++) {
-      const uint32_t x = x0 + row;
-      if (x < pr.lx && y < pr.ly) pr.scores[(uint64_t)x * pr.ly + y] = tile[wave][row][lane];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // reads done before the next writes
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 

@@ -123,3 +123,34 @@ def test_psp_packed_matches_pairs(kd, ctx, oracle_mod):
         assert np.array_equal(got, each[q].cpu().numpy())
         check_scores(oracle_mod, M, fx[q], fy[q], got)
 
+
+
+def test_psp_scores_row_pieces_and_guards(kd, ctx, oracle_mod):
+    """Row lengths around every 16- and 64-column boundary, row counts that
+    leave rows past the end of a 64-row tile, outputs at offsets that put
+    rows on every position within a 128-byte line: every score matches the
+    oracle and no byte outside the pairs' outputs is written."""
+    import torch
+    rng = np.random.default_rng(76)
+    M = oracle_mod.psp_matrix(joint(rng))
+    ly_set = [1, 2, 15, 16, 17, 47, 48, 49, 63, 64, 65, 79, 80, 81, 127, 128, 129, 333, 2001]
+    lx_set = [1, 3, 16, 17, 33, 63, 64, 65, 70]
+    shapes = [(lx_set[i % len(lx_set)], ly) for i, ly in enumerate(ly_set)]
+    fx = [rng.random((lx, 20)) for lx, _ in shapes]
+    fy = [rng.random((ly, 20)) for _, ly in shapes]
+    gap = 37  # doubles between outputs: starts drift through every line position
+    total = sum(lx * ly + gap for lx, ly in shapes) + gap
+    buf = torch.full((total,), float("nan"), dtype=torch.float64, device="cuda")
+    outs, spans, o = [], [], gap
+    for lx, ly in shapes:
+        outs.append(buf[o:o + lx * ly].view(lx, ly))
+        spans.append((o, o + lx * ly))
+        o += lx * ly + gap
+    say("psp pieces", shapes)
+    ctx.psp_scores(M, list(zip(fx, fy)), outs)
+    host = buf.cpu().numpy()
+    inside = np.zeros(total, dtype=bool)
+    for (a, b), (lx, ly), x, y in zip(spans, shapes, fx, fy):
+        inside[a:b] = True
+        check_scores(oracle_mod, M, x, y, host[a:b].reshape(lx, ly))
+    assert np.isnan(host[~inside]).all(), np.flatnonzero(~np.isnan(host) & ~inside)[:10]
