@@ -221,19 +221,38 @@ struct TreeShared {
 
 // lexicographic (value, index) minimum
 __device__ __forceinline__ void lex_min(double &v, uint32_t &i, double v2, uint32_t i2) {
-  if (v2 < v || (v2 == v && i2 < i)) {
-    v = v2;
-    i = i2;
-  }
+  const bool take = (v2 < v) | ((v2 == v) & (i2 < i));  // no short circuit: selects, not branches
+  v = take ? v2 : v;
+  i = take ? i2 : i;
 }
 
+// one step of the wave reduction: combine with the lane that the DPP control
+// CTRL names, in the rows of ROWS (other rows keep their value)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void dpp_lex_step(double &v, uint32_t &i) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+  const int i2 = __builtin_amdgcn_update_dpp((int)i, (int)i, CTRL, ROWS, 0xF, false);
+  lex_min(v, i, __hiloint2double(hi2, lo2), (uint32_t)i2);
+}
+
+// lexicographic (value, index) minimum over the 64 lanes, in every lane
+// (all lanes active).  Register-to-register moves instead of LDS permutes:
+// quad swaps (1 0 3 2, 2 3 0 1), then the half-row and row mirrors leave
+// each 16-lane row's minimum in all its lanes; row 15 broadcast into rows 1
+// and 3 and row 31 broadcast into rows 2 and 3 leave the wave's in lane 63.
+// The minimum of a total order does not depend on the combining order.
 __device__ __forceinline__ void wave_lex_min(double &v, uint32_t &i) {
-#pragma unroll
-  for (int o = 32; o; o >>= 1) {
-    const double v2 = __shfl_xor(v, o, 64);
-    const uint32_t i2 = (uint32_t)__shfl_xor((int)i, o, 64);
-    lex_min(v, i, v2, i2);
-  }
+  dpp_lex_step<0xB1, 0xF>(v, i);   // quad_perm 1 0 3 2
+  dpp_lex_step<0x4E, 0xF>(v, i);   // quad_perm 2 3 0 1
+  dpp_lex_step<0x141, 0xF>(v, i);  // row_half_mirror
+  dpp_lex_step<0x140, 0xF>(v, i);  // row_mirror
+  dpp_lex_step<0x142, 0xA>(v, i);  // row_bcast:15
+  dpp_lex_step<0x143, 0xC>(v, i);  // row_bcast:31
+  v = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                       __builtin_amdgcn_readlane(__double2loint(v), 63));
+  i = (uint32_t)__builtin_amdgcn_readlane((int)i, 63);
 }
 
 // Minimum of D[k][j] over columns j > k that are active and not `skip`,
