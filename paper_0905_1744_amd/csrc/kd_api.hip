@@ -956,13 +956,32 @@ extern "C" kd_status kmer_distance_matrices(kd_ctx *ctx, const kd_set *s, double
   KD_TRY(hipSetDevice(ctx->device));
   std::vector<uint64_t> doff;
   matrix_offsets(s->nsets, s->seq_first.data(), doff);
+  // the sorted-order scratch matrices: rows rounded up to whole lines
+  std::vector<uint64_t> offs(2 * s->nsets);
+  uint64_t stot = 0;
+  uint32_t max_n = 0;
+  for (uint32_t q = 0; q < s->nsets; q++) {
+    const uint64_t n = s->seq_first[q + 1] - s->seq_first[q];
+    offs[q] = stot;
+    offs[s->nsets + q] = doff[q];
+    stot += n * ((n + 15) & ~(uint64_t)15);
+    max_n = std::max(max_n, (uint32_t)n);
+  }
+  // its own work list: one row block per workgroup (the pair terms are
+  // stored, so there are no accumulators whose flush a longer run would
+  // share), the largest first
+  std::vector<PairTask> tl;
+  build_task_list(s->views, 1, tl);
   Scope tmp(ctx);
-  uint64_t *d_off = tmp.get<uint64_t>(s->nsets);
-  if (!d_off) return KD_ENOMEM;
-  KD_TRY(upload(ctx, d_off, doff.data(), sizeof(uint64_t) * s->nsets));
+  uint64_t *d_off = tmp.get<uint64_t>(2 * s->nsets);
+  PairTask *d_tasks = tmp.get<PairTask>(tl.size() + 1);
+  double *scratch = tmp.get<double>(std::max<uint64_t>(stot, 1));
+  if (!d_off || !d_tasks || !scratch) return KD_ENOMEM;
+  KD_TRY(upload(ctx, d_off, offs.data(), sizeof(uint64_t) * 2 * s->nsets));
+  if (!tl.empty()) KD_TRY(upload(ctx, d_tasks, tl.data(), sizeof(PairTask) * tl.size()));
   StageTimer t(ctx, KD_STAGE_DIST);
-  KD_TRY(launch_distances(ctx->stream, s->segs, s->v.N, s->d_view, s->tasks, s->ntasks, d_off, delta,
-                          dist));
+  KD_TRY(launch_distances(ctx->stream, s->segs, s->v.N, max_n, s->d_view, d_tasks, (uint32_t)tl.size(), d_off,
+                          d_off + s->nsets, delta, scratch, dist));
   t.done();
   return KD_OK;
 }

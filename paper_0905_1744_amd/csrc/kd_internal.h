@@ -270,9 +270,12 @@ hipError_t launch_gather(hipStream_t st, const uint8_t *res, const uint64_t *off
                          uint64_t *out_off, unsigned long long *err);
 // Equations 1-2 for every pair of every set, set q's n_q x n_q matrix at
 // dist + doff[q] (input order)
-hipError_t launch_distances(hipStream_t st, const Segs &sg, uint32_t N, const SetView *d_views,
-                            const PairTask *tasks, uint32_t ntasks, const uint64_t *doff, double delta,
-                            double *dist);
+constexpr uint32_t kDistLdsRow = 4096;  // larger sets: permutation reads the scratch row in memory
+// scratch: each set's matrix in sorted order, rows of dist_ld(n) = n rounded
+// up to 16 doubles, set q at soff[q]; dist: input order, set q at doff[q]
+hipError_t launch_distances(hipStream_t st, const Segs &sg, uint32_t N, uint32_t max_n, const SetView *d_views,
+                            const PairTask *tasks, uint32_t ntasks, const uint64_t *soff, const uint64_t *doff,
+                            double delta, double *scratch, double *dist);
 constexpr uint32_t kTreeMaxSeqs = 4096;  // largest set upgma_trees accepts
 // UPGMA of each set's matrix at work + doff[q] (overwritten), first[] on
 // the device (N = first[nsets] members in all); rmin/rarg: N entries of

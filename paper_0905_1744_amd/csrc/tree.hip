@@ -83,13 +83,18 @@ struct DistShared {
   RowShared row;
   LogEntry logt[kLogEntries];
   double ln2;
-  uint32_t rowIn[16];  // input index (within the set) of each row
   uint16_t exc_id[kExcLds];
   uint16_t exc_c[kExcLds * 16];
 };
 
+// Row stride of a set's sorted-order scratch matrix: whole 128-byte lines.
+__host__ __device__ inline uint64_t dist_ld(uint64_t n) { return (n + 15) & ~(uint64_t)15; }
+
 // d for the pairs of one 16 x 64 tile below the diagonal, written at both
-// (row, column) and (column, row) of the set's matrix (input order).
+// (row, column) and (column, row) of the set's scratch matrix in sorted
+// order (row stride dist_ld(N)): a row's 64 columns are one line-aligned
+// 512-byte store, and each lane's 16 rows fill one 128-byte line of its
+// column's row.  dist_permute_kernel puts them in input order.
 __device__ __forceinline__ void dist_tile(const SetView &v, DistShared &sh, uint32_t rb, uint32_t g,
                                           double delta, const uint16_t *eid, const uint16_t *ecnt,
                                           uint32_t en, double *__restrict__ M) {
@@ -111,31 +116,30 @@ __device__ __forceinline__ void dist_tile(const SetView &v, DistShared &sh, uint
   if (!vc) return;
   const uint32_t Kc = v.K[sc];
   const double invKc = v.invK[sc];
-  const uint64_t n = v.N, ci = v.perm[sc];
+  const uint64_t ld = dist_ld(v.N);
 #pragma unroll
   for (int r = 0; r < 16; r++) {
     const uint32_t sr = 16u * rb + r;
     if (sc < sr && sr < v.N) {
       const double inv = sh.row.rowK[r] < Kc ? sh.row.rowInv[r] : invKc;
       const double d = -log_tab(fma((double)cnt[r], inv, delta), sh.logt, sh.ln2);
-      const uint64_t ri = sh.rowIn[r];
-      M[ri * n + ci] = d;
-      M[ci * n + ri] = d;
+      M[sr * ld + sc] = d;
+      M[(uint64_t)sc * ld + sr] = d;
     }
   }
 }
 
 // The rank kernel's work list (strips of 32 column groups against runs of
 // row blocks, pairs below the diagonal only), with the pair terms stored
-// instead of summed.  doff[set] = first element of the set's matrix.
+// instead of summed.  soff[set] = first element of the set's scratch matrix.
 __global__ __launch_bounds__(1024) void dist_pairs_kernel(const SetView *__restrict__ views,
                                                           const PairTask *__restrict__ tasks,
-                                                          const uint64_t *__restrict__ doff,
-                                                          double delta, double *__restrict__ dist) {
+                                                          const uint64_t *__restrict__ soff,
+                                                          double delta, double *__restrict__ scratch) {
   __shared__ DistShared sh;
   const PairTask tk = tasks[blockIdx.x];
   const SetView &v = views[tk.set];
-  double *M = dist + doff[tk.set];
+  double *M = scratch + soff[tk.set];
   const uint32_t tid = threadIdx.x;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (uint32_t q = tid; q < (uint32_t)kLogEntries; q += 1024) log_table_entry((int)q, sh.logt[q]);
@@ -150,7 +154,6 @@ __global__ __launch_bounds__(1024) void dist_pairs_kernel(const SetView *__restr
     __syncthreads();
     const uint32_t e0 = v.exc_off[rb], en = v.exc_n[rb];
     touch_rows<true>(v, ConsecutiveRows{16u * rb, v.N}, v.exc_ids, e0, en, sh.row);
-    if (tid < 16) sh.rowIn[tid] = 16u * rb + tid < v.N ? v.perm[16u * rb + tid] : 0u;
     const bool lds_exc = en <= kExcLds;
     if (lds_exc) {
       for (uint32_t e = tid; e < en; e += 1024) sh.exc_id[e] = v.exc_ids[e0 + e];
@@ -165,26 +168,51 @@ __global__ __launch_bounds__(1024) void dist_pairs_kernel(const SetView *__restr
   }
 }
 
-// the diagonal: F(i, i) = 1, d = -ln(delta + 1)
-__global__ void dist_diag_kernel(Segs sg, uint32_t N, const uint64_t *__restrict__ doff, double delta,
-                                 double *__restrict__ dist) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
+// Input order: row r of a set's matrix is row inv[r] of its scratch matrix
+// with the columns permuted, M[r][c] = scratch[inv[r]][inv[c]]; the
+// diagonal (F(i, i) = 1) is d = -ln(delta + 1).  One workgroup per row: the
+// scratch row is read whole (coalesced) into LDS, the matrix row written
+// whole.  ROWS_IN_LDS false (sets beyond the LDS): the columns are read from
+// the scratch row in memory.
+template <bool ROWS_IN_LDS>
+__global__ __launch_bounds__(256) void dist_permute_kernel(Segs sg, const SetView *__restrict__ views,
+                                                           const uint64_t *__restrict__ soff,
+                                                           const uint64_t *__restrict__ doff, double delta,
+                                                           const double *__restrict__ scratch,
+                                                           double *__restrict__ dist) {
+  extern __shared__ double row[];
+  const uint32_t p = blockIdx.x;
   const uint32_t set = sg.set_of_pos(p);
-  const uint64_t a = sg.seq[set], n = sg.seq[set + 1] - a, i = p - a;
-  dist[doff[set] + i * n + i] = -log(delta + 1.0);
+  const SetView &v = views[set];
+  const uint32_t n = v.N, r = p - v.base;
+  const double *src = scratch + soff[set] + (uint64_t)v.inv[r] * dist_ld(n);
+  if (ROWS_IN_LDS) {
+    for (uint32_t c = threadIdx.x; c < n; c += 256) row[c] = src[c];
+    __syncthreads();
+  }
+  const double diag = -log(delta + 1.0);
+  double *dst = dist + doff[set] + (uint64_t)r * n;
+  for (uint32_t c = threadIdx.x; c < n; c += 256) {
+    const uint32_t sc = v.inv[c];
+    dst[c] = c == r ? diag : (ROWS_IN_LDS ? row[sc] : src[sc]);
+  }
 }
 
-hipError_t launch_distances(hipStream_t st, const Segs &sg, uint32_t N, const SetView *d_views,
-                            const PairTask *tasks, uint32_t ntasks, const uint64_t *doff, double delta,
-                            double *dist) {
+hipError_t launch_distances(hipStream_t st, const Segs &sg, uint32_t N, uint32_t max_n, const SetView *d_views,
+                            const PairTask *tasks, uint32_t ntasks, const uint64_t *soff, const uint64_t *doff,
+                            double delta, double *scratch, double *dist) {
   if (N == 0) return hipSuccess;
   if (ntasks) {
-    hipLaunchKernelGGL(dist_pairs_kernel, dim3(ntasks), dim3(1024), 0, st, d_views, tasks, doff, delta,
-                       dist);
+    hipLaunchKernelGGL(dist_pairs_kernel, dim3(ntasks), dim3(1024), 0, st, d_views, tasks, soff, delta,
+                       scratch);
     KD_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(dist_diag_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, doff, delta, dist);
+  if (max_n <= kDistLdsRow)
+    hipLaunchKernelGGL(dist_permute_kernel<true>, dim3(N), dim3(256), sizeof(double) * max_n, st, sg, d_views,
+                       soff, doff, delta, scratch, dist);
+  else
+    hipLaunchKernelGGL(dist_permute_kernel<false>, dim3(N), dim3(256), 0, st, sg, d_views, soff, doff, delta,
+                       scratch, dist);
   return hipGetLastError();
 }
 
