@@ -215,3 +215,25 @@ def test_bucket_trees_paper20k(kd, ctx, oracle_mod):
     R = ctx.kmer_rank(ks, 0.1)
     say("bucket trees 20k")
     check_bucket_trees(kd, ctx, oracle_mod, ss, R, ss.B, full_buckets=[7])
+
+
+def test_distance_matrices_large_set(kd, ctx, oracle_mod):
+    """A set larger than the permutation's LDS row (4,096) beside a small
+    one: sampled rows against the oracle (all columns), symmetry and the
+    diagonal everywhere."""
+    rng = np.random.default_rng(64)
+    big = synth.from_strings([synth.small(5).seq(i % 512) + b"ACDEFGHIKLMNPQRSTVWY"[i % 20:i % 20 + 3] * (1 + i % 3)
+                              for i in range(4200)])
+    sets = [big, synth.random_tiny(rng, 70, 6, 300)]
+    res, off, first, _ = synth.concat(sets)
+    say("distances large", [x.n for x in sets])
+    kb = ctx.kmer_count_batch(res, off.view(np.int64), first)
+    mats = split_mats(ctx.distance_matrices(kb, 0.1), first)
+    kb.destroy()
+    M = mats[0]
+    L = oracle_mod.count(big)
+    rows = np.unique(np.concatenate([[0, 1, 4095, 4096, 4199], rng.integers(0, big.n, 27)]))
+    close(M[rows], oracle_mod.distance_block(L, rows, np.arange(big.n), 0.1))
+    assert np.array_equal(M, M.T)
+    close(np.diag(M), np.full(big.n, -np.log(1.1)))
+    close(mats[1], oracle_mod.distance_matrix(oracle_mod.count(sets[1]), np.arange(70), 0.1))
