@@ -154,3 +154,32 @@ def test_psp_scores_row_pieces_and_guards(kd, ctx, oracle_mod):
         inside[a:b] = True
         check_scores(oracle_mod, M, x, y, host[a:b].reshape(lx, ly))
     assert np.isnan(host[~inside]).all(), np.flatnonzero(~np.isnan(host) & ~inside)[:10]
+
+
+def test_psp_bench_workload_sampled(kd, ctx, oracle_mod):
+    """The benchmark's call at its full size: 256 profile pairs of 200 to
+    2,000 columns (the same seeded recipe), one packed launch; six pairs
+    checked whole, every other pair on three sampled rows."""
+    import torch
+    rng = np.random.default_rng(11)
+    lens = rng.integers(200, 2001, size=(256, 2))
+    M = oracle_mod.psp_matrix(joint(rng))
+
+    def prof(L):
+        return rng.dirichlet(np.ones(20), size=L) * (1 - rng.random((L, 1)) * 0.3)
+    FX = [prof(int(a)) for a in lens[:, 0]]
+    FY = [prof(int(b)) for b in lens[:, 1]]
+    say("psp bench workload", int((lens[:, 0] * lens[:, 1]).sum()), "scores")
+    S, so = ctx.psp_scores_packed(M, np.concatenate(FX), lens[:, 0], np.concatenate(FY), lens[:, 1])
+    pick = np.random.default_rng(12)
+    for q in range(256):
+        lx, ly = int(lens[q, 0]), int(lens[q, 1])
+        Sq = S[int(so[q]):int(so[q + 1])].view(lx, ly)
+        if q % 43 == 0:
+            check_scores(oracle_mod, M, FX[q], FY[q], Sq.cpu().numpy())
+        else:
+            rows = np.sort(pick.choice(lx, 3, replace=False))
+            got = Sq[torch.from_numpy(rows).to(Sq.device)].cpu().numpy()
+            check_scores(oracle_mod, M, FX[q][rows], FY[q], got)
+    del S
+    torch.cuda.empty_cache()
