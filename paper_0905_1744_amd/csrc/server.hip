@@ -141,21 +141,25 @@ kd_status kd_server::run_batch(std::vector<Job *> &b, std::vector<kd_status> &st
     const uint32_t N = first[ns];
     uint64_t nb = 0;
     for (uint32_t k = 0; k < ns; k++) nb += Bs[k] + 1;
-    // input: offsets (N+1 u64) then residues; output: ranks, bucket, order, offsets
+    // input: offsets (N+1 u64, rebased and staged in pinned memory) then
+    // residues (each job's copy goes straight to its place, no host staging);
+    // output: ranks, bucket, order, offsets
     const size_t in_bytes = 8ull * (N + 1) + nres;
     const size_t out_bytes = 8ull * N + 4ull * N + 4ull * N + 4ull * nb;
-    if (h_in.reserve(in_bytes) != hipSuccess || h_out.reserve(out_bytes) != hipSuccess ||
+    if (h_in.reserve(8ull * (N + 1)) != hipSuccess || h_out.reserve(out_bytes) != hipSuccess ||
         d_in.reserve(in_bytes) != hipSuccess || d_out.reserve(out_bytes + 256) != hipSuccess) {
       for (uint32_t q : live) st[q] = KD_ENOMEM;
       return KD_ENOMEM;
     }
     uint64_t *off = static_cast<uint64_t *>(h_in.p);
-    uint8_t *res = static_cast<uint8_t *>(h_in.p) + 8ull * (N + 1);
+    uint8_t *d_resw = static_cast<uint8_t *>(d_in.p) + 8ull * (N + 1);
     uint64_t r0 = 0;
+    bool copied = true;
     for (uint32_t k = 0; k < ns; k++) {
       const Job *j = b[live[k]];
       for (uint32_t i = 0; i < j->out.n_seqs; i++) off[first[k] + i] = r0 + j->offsets[i];
-      std::memcpy(res + r0, j->residues.data(), j->out.n_residues);
+      copied = copied && hipMemcpyAsync(d_resw + r0, j->residues.data(), j->out.n_residues, hipMemcpyHostToDevice,
+                                        stream) == hipSuccess;
       r0 += j->out.n_residues;
     }
     off[N] = r0;
@@ -164,9 +168,9 @@ kd_status kd_server::run_batch(std::vector<Job *> &b, std::vector<kd_status> &st
     uint32_t *d_bucket = reinterpret_cast<uint32_t *>(dout + 8ull * N);
     uint32_t *d_order = d_bucket + N;
     uint32_t *d_offs = d_order + N;
-    const uint8_t *d_res = static_cast<const uint8_t *>(d_in.p) + 8ull * (N + 1);
+    const uint8_t *d_res = d_resw;
     const uint64_t *d_off = static_cast<const uint64_t *>(d_in.p);
-    if (hipMemcpyAsync(d_in.p, h_in.p, in_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) {
+    if (!copied || hipMemcpyAsync(d_in.p, h_in.p, 8ull * (N + 1), hipMemcpyHostToDevice, stream) != hipSuccess) {
       for (uint32_t q : live) st[q] = KD_EDEVICE;
       return KD_EDEVICE;
     }
