@@ -529,7 +529,8 @@ def bench_served(args):
     for mode in ("batched", "fifo"):
         for lam in rates:
             arr = synth.served_arrivals(5, len(jobs), lam)
-            srv = kd.Server(0, hbm_budget=200 << 30, max_batch_jobs=0 if mode == "batched" else 1)
+            srv = kd.Server(0, hbm_budget=200 << 30, max_batch_jobs=0 if mode == "batched" else 1,
+                            host_arena_bytes=256 << 20)
             for x in jobs[:2]:  # first-call costs out of the way
                 srv.submit(x.residues, x.offsets, x.B, args.delta)
             got = 0

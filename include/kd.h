@@ -400,6 +400,10 @@ typedef struct kd_server_opts {
                               peak device memory inside a batch */
   uint32_t max_batch_jobs; /* jobs per batch; 0 = no limit, 1 = one job at a time */
   uint32_t max_batch_seqs; /* sequences per batch; 0 = no limit */
+  uint64_t host_arena_bytes; /* pinned host memory for the jobs' input copies, set up at
+                                creation (64 MB chunks, kept and reused; more are pinned
+                                as jobs need them; a job no chunk can hold keeps a
+                                pageable copy) */
 } kd_server_opts;
 
 #define KD_JOB_BYTES(n_residues, n_seqs) (8ull * (n_residues) + 256ull * (n_seqs) + 65536ull)

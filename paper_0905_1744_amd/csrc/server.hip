@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <new>
@@ -33,10 +34,61 @@ uint64_t now_ns() {
 struct Job {
   uint64_t ticket = 0;
   kd_job out{};                    // caller's output pointers (inputs copied below)
-  std::vector<uint8_t> residues;
+  uint8_t *res = nullptr;          // the residues: in arena chunk `chunk`, or in `own`
+  int chunk = -1;
+  std::vector<uint8_t> own;
   std::vector<uint64_t> offsets;
   uint64_t bytes = 0;              // admission charge
   uint64_t t_submit = 0, t_start = 0;
+};
+
+// Pinned host memory for the jobs' residues, so that a batch's input goes to
+// the device by asynchronous DMA straight from each job's copy: chunks of
+// kChunk bytes that stay with the server, bump allocation, a chunk reused
+// once every job placed in it has finished.  Non-coherent pinned memory:
+// the CPU writes it through its caches (the default, coherent kind was much
+// slower to fill), and the device only reads it by copies issued after the
+// job's data is in place.  Guarded by the server's mutex.
+struct Arena {
+  static constexpr size_t kChunk = 64ull << 20;
+  struct Chunk {
+    uint8_t *p = nullptr;
+    size_t used = 0;
+    uint32_t refs = 0;
+  };
+  std::vector<Chunk> chunks;
+  size_t cur = 0;
+  bool add_chunk(bool touch) {
+    void *v = nullptr;
+    if (hipHostMalloc(&v, kChunk, hipHostMallocNonCoherent) != hipSuccess) return false;
+    uint8_t *p = static_cast<uint8_t *>(v);
+    if (touch) std::memset(p, 0, kChunk);
+    chunks.push_back(Chunk{p, 0, 0});
+    return true;
+  }
+  // n bytes; the chunk index, or -1 when the job must hold its own copy
+  int alloc(size_t n, uint8_t *&p) {
+    const size_t a = (n + 255) & ~(size_t)255;
+    if (n == 0 || a > kChunk) return -1;
+    if (cur >= chunks.size() || chunks[cur].used + a > kChunk) {
+      size_t k = 0;
+      while (k < chunks.size() && chunks[k].refs) k++;  // a chunk no job uses any more
+      if (k == chunks.size() && !add_chunk(false)) return -1;
+      chunks[k].used = 0;
+      cur = k;
+    }
+    Chunk &c = chunks[cur];
+    p = c.p + c.used;
+    c.used += a;
+    c.refs++;
+    return (int)cur;
+  }
+  void release(int k) {
+    if (k >= 0 && --chunks[(size_t)k].refs == 0 && (size_t)k != cur) chunks[(size_t)k].used = 0;
+  }
+  ~Arena() {
+    for (auto &c : chunks) (void)hipHostFree(c.p);
+  }
 };
 
 // grow-only buffers
@@ -92,6 +144,7 @@ struct kd_server {
   std::unordered_map<uint64_t, Job *> running;
   std::deque<kd_done> done;
   uint64_t reserved = 0;
+  Arena arena;  // the jobs' residues (pinned)
   // staging, used by the worker only
   HostBuf h_in, h_out;
   DevBuf d_in, d_out;
@@ -114,6 +167,7 @@ struct kd_server {
     d.t_done_ns = t_done;
     done.push_back(d);
     reserved -= j->bytes;
+    arena.release(j->chunk);
     delete j;
   }
 
@@ -158,7 +212,7 @@ kd_status kd_server::run_batch(std::vector<Job *> &b, std::vector<kd_status> &st
     for (uint32_t k = 0; k < ns; k++) {
       const Job *j = b[live[k]];
       for (uint32_t i = 0; i < j->out.n_seqs; i++) off[first[k] + i] = r0 + j->offsets[i];
-      copied = copied && hipMemcpyAsync(d_resw + r0, j->residues.data(), j->out.n_residues, hipMemcpyHostToDevice,
+      copied = copied && hipMemcpyAsync(d_resw + r0, j->res, j->out.n_residues, hipMemcpyHostToDevice,
                                         stream) == hipSuccess;
       r0 += j->out.n_residues;
     }
@@ -266,6 +320,8 @@ extern "C" kd_status kd_server_create(int device, const kd_server_opts *opts, kd
   if (!s) return KD_ENOMEM;
   s->device = device;
   s->opts = *opts;
+  for (uint64_t b = 0; b < opts->host_arena_bytes; b += Arena::kChunk)
+    if (!s->arena.add_chunk(true)) break;  // fewer up front: more chunks are taken as jobs need them
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
     delete s;
     return KD_EDEVICE;
@@ -301,10 +357,21 @@ extern "C" kd_status kd_server_submit(kd_server *s, const kd_job *job, uint64_t 
   if (bytes > s->opts.hbm_budget) return KD_EBUSY;
   Job *j = new (std::nothrow) Job;
   if (!j) return KD_ENOMEM;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    j->chunk = s->arena.alloc(job->n_residues, j->res);
+  }
   try {
-    j->residues.assign(job->residues, job->residues + job->n_residues);
+    if (j->chunk < 0) {
+      j->own.assign(job->residues, job->residues + job->n_residues);
+      j->res = j->own.data();
+    } else {
+      std::memcpy(j->res, job->residues, job->n_residues);
+    }
     j->offsets.assign(job->offsets, job->offsets + N + 1);
   } catch (...) {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->arena.release(j->chunk);
     delete j;
     return KD_ENOMEM;
   }
