@@ -575,6 +575,9 @@ def bench_served(args):
                                 "divergence 5-30%, B = max(1, N/256), seed 5, budget 200 GiB"),
                    "delta": args.delta},
         "rates": results, "identical_to_alone": identical,
+        # throughput of continuous batching over one job at a time, per offered rate
+        "batched_over_one_at_a_time": {r: results["batched"][r]["jobs_per_s"] / results["fifo"][r]["jobs_per_s"]
+                                       for r in results["batched"]},
     }
     ctx.close()
     print(json.dumps(line), flush=True)
@@ -590,7 +593,7 @@ def main():
     ap.add_argument("--sets", type=int, default=4096, help="batched workload: number of sets")
     ap.add_argument("--jobs", type=int, default=300, help="served workload: jobs per arrival rate")
     ap.add_argument("--pairs", type=int, default=256, help="psp workload: profile pairs")
-    ap.add_argument("--rates", default="10,20,50,100,200,500,1000,2000,4000",
+    ap.add_argument("--rates", default="10,20,50,100,200,500,1000,2000,4000,100000",
                     help="served workload: arrival rates (jobs/s)")
     ap.add_argument("--no-loop-baseline", action="store_true",
                     help="batched workload: skip the per-set loop comparison (for profiling)")
