@@ -379,12 +379,18 @@ __global__ __launch_bounds__(1024) void upgma_kernel(const uint32_t *__restrict_
   if (tid == 0) sh.nredo = 0;
   __syncthreads();
   for (uint32_t t = 0; t + 1 < n; t++) {
-    // the pair: lexicographic minimum of (rowmin[a], a) over active a;
-    // every wave reduces the 16 wave results itself (no second barrier)
+    // the pair: lexicographic minimum of (rowmin[a], a) over active a
+    // (a retired row's minimum is NaN, which no comparison selects: no
+    // test of act, and the rows' reads go out together); every wave
+    // reduces the 16 wave results itself (no second barrier)
+    constexpr int kPer = kTreeMax / 1024;
     double v = __builtin_inf();
     uint32_t i = 0xFFFFFFFFu;
-    for (uint32_t a = tid; a < n; a += 1024)
-      if (sh.act[a]) lex_min(v, i, sh.rowmin[a], a);
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+      const uint32_t a = tid + 1024u * u;
+      if (a < n) lex_min(v, i, sh.rowmin[a], a);
+    }
     wave_lex_min(v, i);
     if (lane == 0) {
       sh.wv[wave] = v;
@@ -410,7 +416,6 @@ __global__ __launch_bounds__(1024) void upgma_kernel(const uint32_t *__restrict_
     }
     // update row and column a (loads first, then the arithmetic); row a's
     // new minimum; rows that must rescan
-    constexpr int kPer = kTreeMax / 1024;
     double xa[kPer], xb[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; u++) {
@@ -455,7 +460,7 @@ __global__ __launch_bounds__(1024) void upgma_kernel(const uint32_t *__restrict_
         sh.rowmin[a] = v;
         sh.rowarg[a] = i == 0xFFFFFFFFu ? kNone16 : (uint16_t)i;
         sh.act[b] = 0;
-        sh.rowmin[b] = __builtin_inf();
+        sh.rowmin[b] = __builtin_nan("");  // never the pair's minimum
         sh.size[a] = (uint16_t)(sh.size[a] + sh.size[b]);
         sh.id[a] = (uint16_t)(n + t);
       }
