@@ -50,10 +50,10 @@ TRAFFIC = {
                                       "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h"],
                           "sha256_16": "6f4d6a4f4effdd3f", "workload": "global100k", "rows_per_workgroup": None,
                           "bytes_per_launch": 2843834059},
-    "dist_pairs_kernel": {"sources": TREE_SOURCES, "sha256_16": "8cd2174f3929af38", "workload": "trees20k",
-                          "rows_per_workgroup": None, "bytes_per_launch": 493989376},
-    "upgma_kernel": {"sources": TREE_SOURCES, "sha256_16": "8cd2174f3929af38", "workload": "trees20k",
-                     "rows_per_workgroup": None, "bytes_per_launch": 998615552},
+    "dist_pairs_kernel": {"sources": TREE_SOURCES, "sha256_16": "dadf40f2d4dcd576", "workload": "trees20k",
+                          "rows_per_workgroup": None, "bytes_per_launch": 492756992},
+    "upgma_kernel": {"sources": TREE_SOURCES, "sha256_16": "dadf40f2d4dcd576", "workload": "trees20k",
+                     "rows_per_workgroup": None, "bytes_per_launch": 998621184},
     # psp_g_kernel + psp_scores_kernel, the two launches of one psp_scores call
     "psp": {"sources": ["paper_0905_1744_amd/csrc/psp.hip"], "sha256_16": "641050ec05ed3fe7", "workload": "psp",
             "rows_per_workgroup": None, "bytes_per_launch": 94292377 + 2872391142},
