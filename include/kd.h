@@ -403,7 +403,11 @@ typedef struct kd_server_opts {
   uint64_t host_arena_bytes; /* pinned host memory for the jobs' input copies, set up at
                                 creation (64 MB chunks, kept and reused; more are pinned
                                 as jobs need them; a job no chunk can hold keeps a
-                                pageable copy) */
+                                pageable copy).  When nonzero, the batch buffers (pinned
+                                offsets and results, device input and output) are also
+                                set up at creation, for a batch of that many residues in
+                                max_batch_seqs sequences (0: a mean length of 128); they
+                                grow when a batch needs more */
 } kd_server_opts;
 
 #define KD_JOB_BYTES(n_residues, n_seqs) (8ull * (n_residues) + 256ull * (n_seqs) + 65536ull)

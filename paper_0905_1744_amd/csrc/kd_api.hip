@@ -24,15 +24,18 @@ static size_t size_class(size_t b) {
   return (b + m - 1) / m * m;
 }
 
+// A cached block of the smallest class that holds the request, up to twice
+// its class (calls whose sizes vary from one to the next, as a server's
+// batches do, then reuse blocks instead of allocating new ones).
 void *Pool::alloc(size_t bytes) {
   const size_t c = size_class(bytes);
   {
     std::lock_guard<std::mutex> g(mu_);
-    auto it = free_.find(c);
-    if (it != free_.end() && !it->second.empty()) {
+    for (auto it = free_.lower_bound(c); it != free_.end() && it->first <= 2 * c; ++it) {
+      if (it->second.empty()) continue;
       void *p = it->second.back();
       it->second.pop_back();
-      live_ += c;
+      live_ += it->first;
       return p;
     }
   }

@@ -91,7 +91,9 @@ struct Arena {
   }
 };
 
-// grow-only buffers
+// grow-only buffers; the host ones are non-coherent pinned memory, which
+// the CPU reads and writes through its caches (the batch's offsets are
+// written there, its results read back from there)
 struct HostBuf {
   void *p = nullptr;
   size_t cap = 0;
@@ -101,7 +103,7 @@ struct HostBuf {
     if (p) (void)hipHostFree(p);
     p = nullptr;
     cap = 0;
-    hipError_t e = hipHostMalloc(&p, c, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(&p, c, hipHostMallocNonCoherent);
     if (e == hipSuccess) cap = c;
     return e;
   }
@@ -322,6 +324,19 @@ extern "C" kd_status kd_server_create(int device, const kd_server_opts *opts, kd
   s->opts = *opts;
   for (uint64_t b = 0; b < opts->host_arena_bytes; b += Arena::kChunk)
     if (!s->arena.add_chunk(true)) break;  // fewer up front: more chunks are taken as jobs need them
+  if (opts->host_arena_bytes) {
+    // the batch buffers, sized for a batch whose residues fill the arena
+    // (max_batch_seqs sequences, else a mean length of 128) and the host
+    // ones written once: a batch then pays neither their allocation nor
+    // their first touch (they still grow when a batch needs more)
+    const uint64_t nres = opts->host_arena_bytes;
+    const uint64_t n = opts->max_batch_seqs ? opts->max_batch_seqs : std::max<uint64_t>(nres / 128, 1);
+    const uint64_t outb = 24 * n;  // ranks, bucket, order and at most 2 n bucket offsets
+    if (s->h_in.reserve(8 * (n + 1)) == hipSuccess) std::memset(s->h_in.p, 0, s->h_in.cap);
+    if (s->h_out.reserve(outb) == hipSuccess) std::memset(s->h_out.p, 0, s->h_out.cap);
+    (void)s->d_in.reserve(8 * (n + 1) + nres);
+    (void)s->d_out.reserve(outb + 256);
+  }
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
     delete s;
     return KD_EDEVICE;
