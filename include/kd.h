@@ -403,7 +403,10 @@ typedef struct kd_server_opts {
   uint64_t host_arena_bytes; /* pinned host memory for the jobs' input copies, set up at
                                 creation (64 MB chunks, kept and reused; more are pinned
                                 as jobs need them; a job no chunk can hold keeps a
-                                pageable copy).  When nonzero, the batch buffers (pinned
+                                pageable copy).  Each chunk has a device mirror of the
+                                same size (outside hbm_budget), which a job's residues
+                                reach at submit, on a copy stream of the server's, while
+                                earlier batches run.  When nonzero, the batch buffers (pinned
                                 offsets and results, device input and output) are also
                                 set up at creation, for a batch of that many residues in
                                 max_batch_seqs sequences (0: a mean length of 128); they
@@ -437,8 +440,10 @@ typedef struct kd_done {
 
 /* Errors: KD_EINVAL for a bad device or NULL arguments, KD_EDEVICE. */
 kd_status kd_server_create(int device, const kd_server_opts *opts, kd_server **out);
-/* Queue a job; its inputs are copied before this returns, its output
- * buffers must stay valid until its kd_done has been polled.  Errors:
+/* Queue a job; its inputs are copied before this returns (and its residues
+ * sent on to the device), its output buffers must stay valid until its
+ * kd_done has been polled.  Sets the server's device current for the call
+ * and restores the caller's.  Errors:
  * KD_EINVAL (bad offsets, B or delta; detected here), KD_EBUSY (the job
  * alone exceeds the budget). */
 kd_status kd_server_submit(kd_server *srv, const kd_job *job, uint64_t *ticket);

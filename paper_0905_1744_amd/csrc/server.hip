@@ -8,7 +8,9 @@
 // of the oldest one (within the batch limits), concatenates them into one
 // input, and runs count -> rank -> split for all of them at once; jobs
 // arriving meanwhile wait for the next batch.  A job with bad input fails
-// alone: the batch is re-run without it.
+// alone: the batch is re-run without it.  A job's residues go to the
+// device when it is submitted (a copy stream of their own), so a batch
+// finds its input there and only gathers it into one buffer.
 #include <time.h>
 
 #include <algorithm>
@@ -31,10 +33,24 @@ uint64_t now_ns() {
   return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
 }
 
+// The server's device current for the scope, the caller's restored after.
+struct DeviceScope {
+  int prev = -1;
+  explicit DeviceScope(int d) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != d) (void)hipSetDevice(d);
+  }
+  ~DeviceScope() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
 struct Job {
   uint64_t ticket = 0;
   kd_job out{};                    // caller's output pointers (inputs copied below)
   uint8_t *res = nullptr;          // the residues: in arena chunk `chunk`, or in `own`
+  const uint8_t *dres = nullptr;   // their device copy (the chunk's mirror), or null
   int chunk = -1;
   std::vector<uint8_t> own;
   std::vector<uint64_t> offsets;
@@ -48,11 +64,15 @@ struct Job {
 // once every job placed in it has finished.  Non-coherent pinned memory:
 // the CPU writes it through its caches (the default, coherent kind was much
 // slower to fill), and the device only reads it by copies issued after the
-// job's data is in place.  Guarded by the server's mutex.
+// job's data is in place.  Each chunk has a device mirror at the same
+// offsets (null if device memory ran out), which the job's copy at submit
+// fills.  Guarded by the server's mutex; chunks are added with the server's
+// device current.
 struct Arena {
   static constexpr size_t kChunk = 64ull << 20;
   struct Chunk {
     uint8_t *p = nullptr;
+    uint8_t *d = nullptr;
     size_t used = 0;
     uint32_t refs = 0;
   };
@@ -63,8 +83,17 @@ struct Arena {
     if (hipHostMalloc(&v, kChunk, hipHostMallocNonCoherent) != hipSuccess) return false;
     uint8_t *p = static_cast<uint8_t *>(v);
     if (touch) std::memset(p, 0, kChunk);
-    chunks.push_back(Chunk{p, 0, 0});
+    void *d = nullptr;
+    if (hipMalloc(&d, kChunk) != hipSuccess) {
+      (void)hipGetLastError();
+      d = nullptr;
+    }
+    chunks.push_back(Chunk{p, static_cast<uint8_t *>(d), 0, 0});
     return true;
+  }
+  uint8_t *mirror(int k, const uint8_t *p) const {
+    const Chunk &c = chunks[(size_t)k];
+    return c.d ? c.d + (p - c.p) : nullptr;
   }
   // n bytes; the chunk index, or -1 when the job must hold its own copy
   int alloc(size_t n, uint8_t *&p) {
@@ -87,9 +116,44 @@ struct Arena {
     if (k >= 0 && --chunks[(size_t)k].refs == 0 && (size_t)k != cur) chunks[(size_t)k].used = 0;
   }
   ~Arena() {
-    for (auto &c : chunks) (void)hipHostFree(c.p);
+    for (auto &c : chunks) {
+      (void)hipHostFree(c.p);
+      if (c.d) (void)hipFree(c.d);
+    }
   }
 };
+
+// Pieces of the jobs' device copies to gather into a batch's input: one
+// workgroup per piece of at most kPiece bytes, byte copies (the source and
+// destination offsets have no common alignment), eight loads in flight per
+// thread.
+struct Piece {
+  const uint8_t *src;
+  uint64_t dst;  // byte offset in the batch's residues
+  uint64_t len;  // 1 .. kPiece
+};
+constexpr uint64_t kPiece = 64ull << 10;
+
+__global__ __launch_bounds__(256) void gather_pieces_kernel(const Piece *__restrict__ pieces,
+                                                            uint8_t *__restrict__ out) {
+  const Piece pc = pieces[blockIdx.x];
+  const uint8_t *__restrict__ src = pc.src;
+  uint8_t *__restrict__ dst = out + pc.dst;
+  const uint32_t len = (uint32_t)pc.len;
+  for (uint32_t t0 = threadIdx.x; t0 < len; t0 += 256u * 8u) {
+    uint8_t v[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; u++) {
+      const uint32_t t = t0 + 256u * u;
+      v[u] = t < len ? src[t] : 0;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 8; u++) {
+      const uint32_t t = t0 + 256u * u;
+      if (t < len) dst[t] = v[u];
+    }
+  }
+}
 
 // grow-only buffers; the host ones are non-coherent pinned memory, which
 // the CPU reads and writes through its caches (the batch's offsets are
@@ -136,6 +200,8 @@ struct kd_server {
   int device = 0;
   kd_server_opts opts{};
   hipStream_t stream = nullptr;
+  hipStream_t copy_stream = nullptr;  // the jobs' copies at submit
+  hipEvent_t copy_ev = nullptr;       // recorded after each of them (under mu)
   kd_ctx *ctx = nullptr;
   std::thread worker;
   std::mutex mu;
@@ -195,28 +261,40 @@ kd_status kd_server::run_batch(std::vector<Job *> &b, std::vector<kd_status> &st
       nres += j->out.n_residues;
     }
     const uint32_t N = first[ns];
-    uint64_t nb = 0;
-    for (uint32_t k = 0; k < ns; k++) nb += Bs[k] + 1;
-    // input: offsets (N+1 u64, rebased and staged in pinned memory) then
-    // residues (each job's copy goes straight to its place, no host staging);
+    uint64_t nb = 0, npc = 0;
+    for (uint32_t k = 0; k < ns; k++) {
+      nb += Bs[k] + 1;
+      const Job *j = b[live[k]];
+      if (j->dres) npc += (j->out.n_residues + kPiece - 1) / kPiece;
+    }
+    // input: offsets (N+1 u64, rebased) and the gather pieces, staged in
+    // pinned memory, then the residues (gathered from the jobs' device
+    // copies; a job without one is sent from its host copy);
     // output: ranks, bucket, order, offsets
-    const size_t in_bytes = 8ull * (N + 1) + nres;
+    const size_t tab_at = (8ull * (N + 1) + 15) & ~(size_t)15;
+    const size_t head = tab_at + sizeof(Piece) * npc;
+    const size_t in_bytes = head + nres;
     const size_t out_bytes = 8ull * N + 4ull * N + 4ull * N + 4ull * nb;
-    if (h_in.reserve(8ull * (N + 1)) != hipSuccess || h_out.reserve(out_bytes) != hipSuccess ||
+    if (h_in.reserve(head) != hipSuccess || h_out.reserve(out_bytes) != hipSuccess ||
         d_in.reserve(in_bytes) != hipSuccess || d_out.reserve(out_bytes + 256) != hipSuccess) {
       for (uint32_t q : live) st[q] = KD_ENOMEM;
       return KD_ENOMEM;
     }
     uint64_t *off = static_cast<uint64_t *>(h_in.p);
-    uint8_t *d_resw = static_cast<uint8_t *>(d_in.p) + 8ull * (N + 1);
-    uint64_t r0 = 0;
+    Piece *pcs = reinterpret_cast<Piece *>(static_cast<char *>(h_in.p) + tab_at);
+    uint8_t *d_resw = static_cast<uint8_t *>(d_in.p) + head;
+    uint64_t r0 = 0, pq = 0;
     bool copied = true;
     for (uint32_t k = 0; k < ns; k++) {
       const Job *j = b[live[k]];
+      const uint64_t n = j->out.n_residues;
       for (uint32_t i = 0; i < j->out.n_seqs; i++) off[first[k] + i] = r0 + j->offsets[i];
-      copied = copied && hipMemcpyAsync(d_resw + r0, j->res, j->out.n_residues, hipMemcpyHostToDevice,
-                                        stream) == hipSuccess;
-      r0 += j->out.n_residues;
+      if (j->dres) {
+        for (uint64_t a = 0; a < n; a += kPiece) pcs[pq++] = Piece{j->dres + a, r0 + a, std::min(kPiece, n - a)};
+      } else {
+        copied = copied && hipMemcpyAsync(d_resw + r0, j->res, n, hipMemcpyHostToDevice, stream) == hipSuccess;
+      }
+      r0 += n;
     }
     off[N] = r0;
     char *dout = static_cast<char *>(d_out.p);
@@ -226,8 +304,14 @@ kd_status kd_server::run_batch(std::vector<Job *> &b, std::vector<kd_status> &st
     uint32_t *d_offs = d_order + N;
     const uint8_t *d_res = d_resw;
     const uint64_t *d_off = static_cast<const uint64_t *>(d_in.p);
-    if (!copied || hipMemcpyAsync(d_in.p, h_in.p, 8ull * (N + 1), hipMemcpyHostToDevice, stream) != hipSuccess) {
-      for (uint32_t q : live) st[q] = KD_EDEVICE;
+    copied = copied && hipMemcpyAsync(d_in.p, h_in.p, head, hipMemcpyHostToDevice, stream) == hipSuccess;
+    if (copied && npc) {
+      hipLaunchKernelGGL(gather_pieces_kernel, dim3((uint32_t)npc), dim3(256), 0, stream,
+                         reinterpret_cast<const Piece *>(static_cast<char *>(d_in.p) + tab_at), d_resw);
+      copied = hipGetLastError() == hipSuccess;
+    }
+    if (!copied) {
+      for (uint32_t x : live) st[x] = KD_EDEVICE;
       return KD_EDEVICE;
     }
     kd_set *set = nullptr;
@@ -294,11 +378,22 @@ void kd_server::loop() {
       it = admitted.erase(it);
     }
     const uint64_t t0 = now_ns();
+    bool on_dev = false;
     for (Job *j : b) {
       j->t_start = t0;
       running[j->ticket] = j;
+      on_dev = on_dev || j->dres;
+    }
+    // the batch's device copies: a job is queued (under mu) only after the
+    // event was recorded behind its copy, so the event's last record covers
+    // the copies of every queued job
+    bool wait_copies = false;
+    if (on_dev && hipStreamWaitEvent(stream, copy_ev, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      wait_copies = true;
     }
     lk.unlock();
+    if (wait_copies) (void)hipStreamSynchronize(copy_stream);
     std::vector<kd_status> st(b.size(), KD_OK);
     run_batch(b, st);
     const uint64_t t1 = now_ns();
@@ -332,17 +427,27 @@ extern "C" kd_status kd_server_create(int device, const kd_server_opts *opts, kd
     const uint64_t nres = opts->host_arena_bytes;
     const uint64_t n = opts->max_batch_seqs ? opts->max_batch_seqs : std::max<uint64_t>(nres / 128, 1);
     const uint64_t outb = 24 * n;  // ranks, bucket, order and at most 2 n bucket offsets
-    if (s->h_in.reserve(8 * (n + 1)) == hipSuccess) std::memset(s->h_in.p, 0, s->h_in.cap);
+    const uint64_t head = 8 * (n + 1) + 16 + sizeof(Piece) * (nres / kPiece + 4096);  // 4,096 jobs
+    if (s->h_in.reserve(head) == hipSuccess) std::memset(s->h_in.p, 0, s->h_in.cap);
     if (s->h_out.reserve(outb) == hipSuccess) std::memset(s->h_out.p, 0, s->h_out.cap);
-    (void)s->d_in.reserve(8 * (n + 1) + nres);
+    (void)s->d_in.reserve(head + nres);
     (void)s->d_out.reserve(outb + 256);
   }
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
     delete s;
     return KD_EDEVICE;
   }
+  if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->copy_ev, hipEventDisableTiming) != hipSuccess) {
+    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+    (void)hipStreamDestroy(s->stream);
+    delete s;
+    return KD_EDEVICE;
+  }
   kd_status rc = kd_ctx_create(device, s->stream, &s->ctx);
   if (rc != KD_OK) {
+    (void)hipEventDestroy(s->copy_ev);
+    (void)hipStreamDestroy(s->copy_stream);
     (void)hipStreamDestroy(s->stream);
     delete s;
     return rc;
@@ -351,6 +456,8 @@ extern "C" kd_status kd_server_create(int device, const kd_server_opts *opts, kd
     s->worker = std::thread([s] { s->loop(); });
   } catch (...) {
     kd_ctx_destroy(s->ctx);
+    (void)hipEventDestroy(s->copy_ev);
+    (void)hipStreamDestroy(s->copy_stream);
     (void)hipStreamDestroy(s->stream);
     delete s;
     return KD_ENOMEM;
@@ -372,9 +479,11 @@ extern "C" kd_status kd_server_submit(kd_server *s, const kd_job *job, uint64_t 
   if (bytes > s->opts.hbm_budget) return KD_EBUSY;
   Job *j = new (std::nothrow) Job;
   if (!j) return KD_ENOMEM;
+  DeviceScope dev(s->device);  // a new chunk's mirror, the copy to it
   {
     std::lock_guard<std::mutex> g(s->mu);
     j->chunk = s->arena.alloc(job->n_residues, j->res);
+    if (j->chunk >= 0) j->dres = s->arena.mirror(j->chunk, j->res);
   }
   try {
     if (j->chunk < 0) {
@@ -390,12 +499,22 @@ extern "C" kd_status kd_server_submit(kd_server *s, const kd_job *job, uint64_t 
     delete j;
     return KD_ENOMEM;
   }
+  // the residues start for the device now, overlapping running batches
+  if (j->dres && hipMemcpyAsync(const_cast<uint8_t *>(j->dres), j->res, job->n_residues, hipMemcpyHostToDevice,
+                                s->copy_stream) != hipSuccess) {
+    (void)hipGetLastError();
+    j->dres = nullptr;  // the batch sends them from the host copy
+  }
   j->out = *job;
   j->out.residues = nullptr;
   j->out.offsets = nullptr;
   j->bytes = bytes;
   j->t_submit = now_ns();
   std::lock_guard<std::mutex> g(s->mu);
+  if (j->dres && hipEventRecord(s->copy_ev, s->copy_stream) != hipSuccess) {
+    (void)hipGetLastError();
+    j->dres = nullptr;
+  }
   j->ticket = s->next_ticket++;
   *ticket = j->ticket;
   s->waiting.push_back(j);
@@ -464,9 +583,12 @@ extern "C" void kd_server_destroy(kd_server *s) {
   for (Job *j : s->admitted) delete j;
   (void)hipSetDevice(s->device);
   kd_ctx_destroy(s->ctx);  // synchronizes the stream
+  (void)hipStreamSynchronize(s->copy_stream);  // copies of jobs that never ran
   if (s->d_in.p) (void)hipFree(s->d_in.p);
   if (s->d_out.p) (void)hipFree(s->d_out.p);
   s->d_in.p = s->d_out.p = nullptr;
+  (void)hipEventDestroy(s->copy_ev);
+  (void)hipStreamDestroy(s->copy_stream);
   (void)hipStreamDestroy(s->stream);
-  delete s;
+  delete s;  // the arena: pinned chunks and their device mirrors
 }
