@@ -411,6 +411,10 @@ typedef struct kd_server_opts {
                                 set up at creation, for a batch of that many residues in
                                 max_batch_seqs sequences (0: a mean length of 128); they
                                 grow when a batch needs more */
+  uint32_t no_mirror;        /* 1: no device mirrors (no device memory beyond the batch
+                                buffers); each batch sends its jobs' residues from
+                                their host copies */
+  uint32_t reserved0;        /* 0 */
 } kd_server_opts;
 
 #define KD_JOB_BYTES(n_residues, n_seqs) (8ull * (n_residues) + 256ull * (n_seqs) + 65536ull)

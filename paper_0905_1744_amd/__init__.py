@@ -43,7 +43,7 @@ class KdError(RuntimeError):
 
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("max_batch_jobs", C.c_uint32), ("max_batch_seqs", C.c_uint32),
-                ("host_arena_bytes", C.c_uint64)]
+                ("host_arena_bytes", C.c_uint64), ("no_mirror", C.c_uint32), ("reserved0", C.c_uint32)]
 
 
 class Job(C.Structure):
@@ -565,9 +565,10 @@ class Server:
     numpy arrays owned by this object until the job's record is polled."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 200 << 30, max_batch_jobs: int = 0,
-                 max_batch_seqs: int = 0, host_arena_bytes: int = 0):
+                 max_batch_seqs: int = 0, host_arena_bytes: int = 0, device_mirror: bool = True):
         L = lib()
-        opts = ServerOpts(hbm_budget, max_batch_jobs, max_batch_seqs, host_arena_bytes)
+        opts = ServerOpts(hbm_budget, max_batch_jobs, max_batch_seqs, host_arena_bytes,
+                          0 if device_mirror else 1, 0)
         out = C.c_void_p()
         st = L.kd_server_create(device, C.byref(opts), C.byref(out))
         if st != KD_OK:

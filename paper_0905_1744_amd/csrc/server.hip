@@ -78,13 +78,14 @@ struct Arena {
   };
   std::vector<Chunk> chunks;
   size_t cur = 0;
+  bool mirrored = true;  // chunks get device mirrors
   bool add_chunk(bool touch) {
     void *v = nullptr;
     if (hipHostMalloc(&v, kChunk, hipHostMallocNonCoherent) != hipSuccess) return false;
     uint8_t *p = static_cast<uint8_t *>(v);
     if (touch) std::memset(p, 0, kChunk);
     void *d = nullptr;
-    if (hipMalloc(&d, kChunk) != hipSuccess) {
+    if (mirrored && hipMalloc(&d, kChunk) != hipSuccess) {
       (void)hipGetLastError();
       d = nullptr;
     }
@@ -417,6 +418,7 @@ extern "C" kd_status kd_server_create(int device, const kd_server_opts *opts, kd
   if (!s) return KD_ENOMEM;
   s->device = device;
   s->opts = *opts;
+  s->arena.mirrored = opts->no_mirror == 0;
   for (uint64_t b = 0; b < opts->host_arena_bytes; b += Arena::kChunk)
     if (!s->arena.add_chunk(true)) break;  // fewer up front: more chunks are taken as jobs need them
   if (opts->host_arena_bytes) {

@@ -60,3 +60,29 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(kd, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         kd.lib()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the ctypes binding passes through the ABI has the size and
+    field offsets the C compiler gives the header's declaration."""
+    import ctypes
+    import paper_0905_1744_amd as kdm
+    pairs = {"kd_server_opts": kdm.ServerOpts, "kd_job": kdm.Job, "kd_done": kdm.Done,
+             "kd_psp_pair": kdm.PspPair}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "kd.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                           text=True).stdout.splitlines())
+    for cname, py in pairs.items():
+        assert int(got[f"{cname} size"]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname} {f}"]) == getattr(py, f).offset, (cname, f)

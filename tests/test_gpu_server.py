@@ -67,9 +67,12 @@ def check_same(rec, want):
         assert np.array_equal(rec[k], want[k]), k
 
 
-def test_server_matches_alone(kd, ctx, jobs):
-    srv = kd.Server(0)
-    say("server", len(jobs))
+@pytest.mark.parametrize("mirror", [True, False], ids=["device-copies", "host-copies"])
+def test_server_matches_alone(kd, ctx, jobs, mirror):
+    """Batches gather their input from the jobs' device copies (sent at
+    submit) or, without mirrors, send it from the host copies."""
+    srv = kd.Server(0, device_mirror=mirror)
+    say("server", len(jobs), "mirror", mirror)
     tickets = []
     for q, x in enumerate(jobs):
         delta = 0.1 if q % 3 else 0.05
@@ -84,8 +87,9 @@ def test_server_matches_alone(kd, ctx, jobs):
     srv.close()
 
 
-def test_server_bad_job_fails_alone(kd, ctx, jobs):
-    srv = kd.Server(0)
+@pytest.mark.parametrize("mirror", [True, False], ids=["device-copies", "host-copies"])
+def test_server_bad_job_fails_alone(kd, ctx, jobs, mirror):
+    srv = kd.Server(0, device_mirror=mirror)
     bad = jobs[1].residues.copy()
     bad[int(jobs[1].offsets[5]) + 2] = ord("B")
     short = synth.from_strings(["ACDEFGH", "ACD"])
