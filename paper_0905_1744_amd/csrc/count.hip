@@ -221,6 +221,76 @@ __device__ __forceinline__ uint32_t code_of(uint32_t r) {
 
 constexpr uint32_t kPadWord = 0xFFFFu;  // above every word: sorts last
 
+// Two 16-bit words per register: one packed min or max orders two pairs.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 swap16(u16x2 x) { return __builtin_shufflevector(x, x, 1, 0); }
+__device__ __forceinline__ u16x2 shfl_xor16(u16x2 x, int m) {
+  return __builtin_bit_cast(u16x2, __shfl_xor(__builtin_bit_cast(int, x), m, 64));
+}
+
+// The bitonic network of count_wave on 64 E words (E >= 2) held two per
+// register: element s of a lane sits in register s mod E/2, in the low half
+// when s < E/2.  In-lane partners that differ in the E/2 bit of s meet
+// across halves (one register's halves swapped, then the low half of the
+// minimum and the high half of the maximum kept); all others meet half to
+// half.  A partner in another lane arrives by one shuffle per register,
+// halves swapped when the partner is the mirror element E - 1 - s.
+template <int E>
+__device__ __forceinline__ void bitonic_packed(uint32_t (&v)[E], uint32_t lane) {
+  constexpr int H = E / 2;
+  u16x2 P[H];
+#pragma unroll
+  for (int h = 0; h < H; h++) P[h] = u16x2{(unsigned short)v[h], (unsigned short)v[h + H]};
+#pragma unroll
+  for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t m = (j == (k >> 1)) ? (k - 1) : j;  // partner = x ^ m
+      if (m < (uint32_t)E) {
+        if ((m & (uint32_t)H) == 0) {
+#pragma unroll
+          for (int h = 0; h < H; h++) {
+            const int g = h ^ (int)m;
+            if (h < g) {
+              const u16x2 a = P[h], b = P[g];
+              P[h] = __builtin_elementwise_min(a, b);
+              P[g] = __builtin_elementwise_max(a, b);
+            }
+          }
+        } else {
+          const int mp = (int)m ^ H;
+#pragma unroll
+          for (int h = 0; h < H; h++) {
+            const int g = h ^ mp;
+            if (h <= g) {
+              const u16x2 a = P[h], sw = swap16(P[g]);
+              const u16x2 mn = __builtin_elementwise_min(a, sw), mx = __builtin_elementwise_max(a, sw);
+              P[h] = __builtin_shufflevector(mn, mx, 0, 3);
+              if (h < g) P[g] = __builtin_shufflevector(mn, mx, 1, 2);
+            }
+          }
+        }
+      } else {
+        const int lm = (int)(m / E);
+        const bool lower = (lane & (j / E)) == 0;
+        u16x2 o[H];
+#pragma unroll
+        for (int h = 0; h < H; h++)
+          o[h] = (m == j) ? shfl_xor16(P[h], lm) : swap16(shfl_xor16(P[H - 1 - h], lm));
+#pragma unroll
+        for (int h = 0; h < H; h++)
+          P[h] = lower ? __builtin_elementwise_min(P[h], o[h]) : __builtin_elementwise_max(P[h], o[h]);
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < H; h++) {
+    v[h] = P[h].x;
+    v[h + H] = P[h].y;
+  }
+}
+
 template <int E>
 __device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint32_t i, uint64_t o0,
                                            uint32_t n, uint64_t cap, uint16_t *__restrict__ cap_ids,
@@ -260,33 +330,19 @@ __device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint
   // Bitonic sort of the 64 E words, element index x = E lane + s, in the
   // form where every comparator puts the minimum at the lower index: each
   // merge of size k starts by comparing x with its mirror x ^ (k - 1), then
-  // halves with x ^ j.  Partners inside a lane are register pairs; others
-  // come from lane lane ^ (partner offset / E) by a shuffle.
+  // halves with x ^ j.
+  if constexpr (E >= 2) {
+    bitonic_packed<E>(v, lane);
+  } else {
+    // one word per lane: every partner is in another lane
 #pragma unroll
-  for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
+    for (uint32_t k = 2; k <= 64u; k <<= 1) {
 #pragma unroll
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t m = (j == (k >> 1)) ? (k - 1) : j;  // partner = x ^ m
-      if (m < (uint32_t)E) {
-#pragma unroll
-        for (int s = 0; s < E; s++) {
-          const int t = s ^ (int)m;
-          if (s < t) {
-            const uint32_t a = v[s], b = v[t];
-            v[s] = min(a, b);
-            v[t] = max(a, b);
-          }
-        }
-      } else {
-        // partner lane = lane ^ (m / E); the pair's top differing bit is j,
-        // so this element is the lower one when lane bit j / E is clear
-        const int lm = (int)(m / E);
-        const bool lower = (lane & (j / E)) == 0;
-        uint32_t o[E];
-#pragma unroll
-        for (int s = 0; s < E; s++) o[s] = (uint32_t)__shfl_xor((int)v[(m == j) ? s : (E - 1 - s)], lm, 64);
-#pragma unroll
-        for (int s = 0; s < E; s++) v[s] = lower ? min(v[s], o[s]) : max(v[s], o[s]);
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        const uint32_t m = (j == (k >> 1)) ? (k - 1) : j;
+        const bool lower = (lane & j) == 0;
+        const uint32_t o = (uint32_t)__shfl_xor((int)v[0], (int)m, 64);
+        v[0] = lower ? min(v[0], o) : max(v[0], o);
       }
     }
   }
