@@ -779,6 +779,13 @@ namespace {
 kd_status plan_partition(uint32_t nsets, const uint32_t *first, const uint32_t *Bs,
                          std::vector<PartDesc> &desc, uint64_t &scratch);
 
+// the most keys one set of a split batch sorts: its n, or its B(B-1) samples
+uint32_t max_part_keys(const std::vector<PartDesc> &desc) {
+  uint32_t m = 0;
+  for (const PartDesc &d : desc) m = std::max(m, std::max(d.n, d.B * (d.B - 1)));
+  return m;
+}
+
 // Pinned host area of at least `bytes`, valid until the next call; only
 // reallocated while no copy into it is pending (callers synchronize first).
 void *readback_area(kd_ctx *ctx, size_t bytes) {
@@ -828,8 +835,8 @@ extern "C" kd_status kmer_rank_global(kd_ctx *ctx, const kd_set *s, const double
     PartDesc *d_desc = tmp.get<PartDesc>(nb);
     if (!scratch || !d_desc) return KD_ENOMEM;
     KD_TRY(upload(ctx, d_desc, desc.data(), sizeof(PartDesc) * nb));
-    KD_TRY(launch_partition_batch(st, d_desc, nb, local_ranks, bucket, order, boff, nullptr, nullptr,
-                                  scratch));
+    KD_TRY(launch_partition_batch(st, d_desc, nb, max_part_keys(desc), local_ranks, bucket, order, boff,
+                                  nullptr, nullptr, scratch));
   }
   KD_TRY(launch_pick_samples(st, s->segs.seq, nb, k, order, smp));
   t_pick.done();
@@ -1245,8 +1252,8 @@ extern "C" kd_status sample_partition_batch(kd_ctx *ctx, const double *ranks, ui
   if (!scratch || !d_desc) return KD_ENOMEM;
   KD_TRY(upload(ctx, d_desc, desc.data(), sizeof(PartDesc) * nsets));
   StageTimer t(ctx, KD_STAGE_PARTITION);
-  KD_TRY(launch_partition_batch(ctx->stream, d_desc, nsets, ranks, bucket, order, offsets,
-                                pivot_rank, pivot_idx, scratch));
+  KD_TRY(launch_partition_batch(ctx->stream, d_desc, nsets, max_part_keys(desc), ranks, bucket, order,
+                                offsets, pivot_rank, pivot_idx, scratch));
   t.done();
   return KD_OK;
 }

@@ -339,10 +339,11 @@ struct PartDesc {
   uint32_t off_base;     // first entry of the set's B+1 offsets
   uint32_t piv_base;     // first entry of the set's B-1 pivots
 };
+// max_keys: the largest n or B(B-1) of the sets (picks the workgroup size)
 hipError_t launch_partition_batch(hipStream_t st, const PartDesc *desc, uint32_t nsets,
-                                  const double *ranks, uint32_t *bucket, uint32_t *order,
-                                  uint32_t *offsets, double *pivot_rank, uint32_t *pivot_idx,
-                                  void *scratch);
+                                  uint32_t max_keys, const double *ranks, uint32_t *bucket,
+                                  uint32_t *order, uint32_t *offsets, double *pivot_rank,
+                                  uint32_t *pivot_idx, void *scratch);
 
 // scratch needed by launch_partition for n keys and B buckets (bytes)
 size_t partition_scratch_bytes(uint32_t n, uint32_t B);

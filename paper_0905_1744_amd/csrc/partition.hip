@@ -63,21 +63,23 @@ size_t partition_scratch_bytes(uint32_t n, uint32_t B) {
          align256(4ull * B) + 256;
 }
 
+// One set with a workgroup of NT threads.
+template <int NT>
 __device__ void partition_one(const double *__restrict__ R, uint32_t n, uint32_t B,
                               uint32_t *__restrict__ bucket, uint32_t *__restrict__ order,
                               uint32_t *__restrict__ offsets, double *__restrict__ piv_r,
-                              uint32_t *__restrict__ piv_i, PartScratch s, RadixShared<1024> &sh,
+                              uint32_t *__restrict__ piv_i, PartScratch s, RadixShared<NT> &sh,
                               uint32_t *s_prho) {
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < n; i += 1024) {
+  for (uint32_t i = tid; i < n; i += NT) {
     s.k0[i] = rank_key(R[i]);
     s.v0[i] = i;
   }
   __syncthreads();
   // 1. global key order
-  const int w1 = block_radix_sort<1024, unsigned long long>(s.k0, s.v0, s.k1, s.v1, n, 0, 64, sh);
+  const int w1 = block_radix_sort<NT, unsigned long long>(s.k0, s.v0, s.k1, s.v1, n, 0, 64, sh);
   const uint32_t *vs = w1 ? s.v1 : s.v0;
-  for (uint32_t p = tid; p < n; p += 1024) {
+  for (uint32_t p = tid; p < n; p += NT) {
     const uint32_t idx = vs[p];
     order[p] = idx;
     s.rho[idx] = p;
@@ -87,11 +89,11 @@ __device__ void partition_one(const double *__restrict__ R, uint32_t n, uint32_t
   }
   __syncthreads();
   // 2. local sorts: stable split of the key order by block
-  const int w2 = block_radix_sort<1024, uint32_t>(s.bk0, s.bv0, s.bk1, s.bv1, n, 0, (int)bitlen(B - 1), sh);
+  const int w2 = block_radix_sort<NT, uint32_t>(s.bk0, s.bv0, s.bk1, s.bv1, n, 0, (int)bitlen(B - 1), sh);
   const uint32_t *bs = w2 ? s.bv1 : s.bv0;
   // 3. regular samples
   const uint32_t S = B * (B - 1);
-  for (uint32_t q = tid; q < S; q += 1024) {
+  for (uint32_t q = tid; q < S; q += NT) {
     const uint32_t b = q / (B - 1), t = q % (B - 1) + 1;
     const uint32_t lo = (uint32_t)((unsigned long long)b * n / B);
     const uint32_t w = (uint32_t)((unsigned long long)(b + 1) * n / B) - lo;
@@ -101,10 +103,10 @@ __device__ void partition_one(const double *__restrict__ R, uint32_t n, uint32_t
   }
   __syncthreads();
   // 4. pivots
-  const int w3 = block_radix_sort<1024, uint32_t>(s.sk0, s.sv0, s.sk1, s.sv1, S, 0, (int)bitlen(n - 1), sh);
+  const int w3 = block_radix_sort<NT, uint32_t>(s.sk0, s.sv0, s.sk1, s.sv1, S, 0, (int)bitlen(n - 1), sh);
   const uint32_t *ss = w3 ? s.sk1 : s.sk0;
   const uint32_t *sv = w3 ? s.sv1 : s.sv0;
-  for (uint32_t i = tid; i + 1 < B; i += 1024) {
+  for (uint32_t i = tid; i + 1 < B; i += NT) {
     const uint32_t pos = i * B + B / 2 - 1;
     s_prho[i] = ss[pos];
     if (piv_i) piv_i[i] = sv[pos];
@@ -117,7 +119,7 @@ __device__ void partition_one(const double *__restrict__ R, uint32_t n, uint32_t
   }
   __syncthreads();
   // 5. buckets
-  for (uint32_t i = tid; i < n; i += 1024) {
+  for (uint32_t i = tid; i < n; i += NT) {
     const uint32_t r = s.rho[i];
     uint32_t lo = 0, hi = B - 1;  // count pivots with prho < r
     while (lo < hi) {
@@ -135,29 +137,39 @@ __global__ __launch_bounds__(1024) void partition_kernel(const double *R, uint32
                                                          uint32_t *piv_i, void *scratch) {
   __shared__ RadixShared<1024> sh;
   __shared__ uint32_t prho[kMaxBuckets];
-  partition_one(R, n, B, bucket, order, offsets, piv_r, piv_i, carve(scratch, n, B), sh, prho);
+  partition_one<1024>(R, n, B, bucket, order, offsets, piv_r, piv_i, carve(scratch, n, B), sh, prho);
 }
 
-__global__ __launch_bounds__(1024) void partition_batch_kernel(const PartDesc *__restrict__ desc,
-                                                               const double *R, uint32_t *bucket,
-                                                               uint32_t *order, uint32_t *offsets,
-                                                               double *piv_r, uint32_t *piv_i,
-                                                               char *scratch) {
-  __shared__ RadixShared<1024> sh;
+template <int NT>
+__global__ __launch_bounds__(NT) void partition_batch_kernel(const PartDesc *__restrict__ desc,
+                                                             const double *R, uint32_t *bucket,
+                                                             uint32_t *order, uint32_t *offsets,
+                                                             double *piv_r, uint32_t *piv_i,
+                                                             char *scratch) {
+  __shared__ RadixShared<NT> sh;
   __shared__ uint32_t prho[kMaxBuckets];
   const PartDesc d = desc[blockIdx.x];
-  partition_one(R + d.first, d.n, d.B, bucket + d.first, order + d.first, offsets + d.off_base,
-                piv_r ? piv_r + d.piv_base : nullptr, piv_i ? piv_i + d.piv_base : nullptr,
-                carve(scratch + d.scratch_off, d.n, d.B), sh, prho);
+  partition_one<NT>(R + d.first, d.n, d.B, bucket + d.first, order + d.first, offsets + d.off_base,
+                    piv_r ? piv_r + d.piv_base : nullptr, piv_i ? piv_i + d.piv_base : nullptr,
+                    carve(scratch + d.scratch_off, d.n, d.B), sh, prho);
 }
 
+// A set's sorts are a chain of passes and barriers, so a batch of small
+// sets runs faster with small workgroups, several sets per compute unit at
+// once (LDS ~18 KB per 256-thread workgroup against ~42 KB per 1,024).
+constexpr uint32_t kSmallPartition = 4096;  // keys or samples per set
+
 hipError_t launch_partition_batch(hipStream_t st, const PartDesc *desc, uint32_t nsets,
-                                  const double *ranks, uint32_t *bucket, uint32_t *order,
-                                  uint32_t *offsets, double *pivot_rank, uint32_t *pivot_idx,
-                                  void *scratch) {
+                                  uint32_t max_keys, const double *ranks, uint32_t *bucket,
+                                  uint32_t *order, uint32_t *offsets, double *pivot_rank,
+                                  uint32_t *pivot_idx, void *scratch) {
   if (nsets == 0) return hipSuccess;
-  hipLaunchKernelGGL(partition_batch_kernel, dim3(nsets), dim3(1024), 0, st, desc, ranks, bucket,
-                     order, offsets, pivot_rank, pivot_idx, (char *)scratch);
+  if (max_keys <= kSmallPartition)
+    hipLaunchKernelGGL(partition_batch_kernel<256>, dim3(nsets), dim3(256), 0, st, desc, ranks, bucket,
+                       order, offsets, pivot_rank, pivot_idx, (char *)scratch);
+  else
+    hipLaunchKernelGGL(partition_batch_kernel<1024>, dim3(nsets), dim3(1024), 0, st, desc, ranks, bucket,
+                       order, offsets, pivot_rank, pivot_idx, (char *)scratch);
   return hipGetLastError();
 }
 

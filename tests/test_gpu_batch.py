@@ -106,8 +106,12 @@ def test_batch_lists_and_ranks_vs_oracle(kd, ctx, oracle_mod):
         assert (err <= RTOL * scale).all(), (q, x.n, err.max())
 
 
-def test_partition_batch_vs_oracle(kd, ctx, oracle_mod):
-    cases = [(20000, 16), (4096, 1024), (33, 7), (1, 1), (17, 17), (1000, 1), (5000, 3), (777, 8)]
+@pytest.mark.parametrize("cases", [
+    [(20000, 16), (4096, 1024), (33, 7), (1, 1), (17, 17), (1000, 1), (5000, 3), (777, 8)],
+    # every set at most 4,096 keys and samples: the small-workgroup kernel
+    [(4096, 64), (33, 7), (1, 1), (17, 17), (1000, 1), (2000, 3), (777, 8), (4000, 40), (64, 64)],
+], ids=["large-sets", "small-sets"])
+def test_partition_batch_vs_oracle(kd, ctx, oracle_mod, cases):
     Rs = []
     for q, (n, B) in enumerate(cases):
         R = synth.rank_like(n, 100 + q)
