@@ -131,7 +131,10 @@ def _dev_tensor(x, dtype, device):
     if isinstance(x, torch.Tensor):
         t = x
     else:
-        t = torch.from_numpy(np.ascontiguousarray(x))
+        a = np.ascontiguousarray(x)
+        if not a.flags.writeable:  # torch.from_numpy wants writable memory (the copy is only read)
+            a = a.copy()
+        t = torch.from_numpy(a)
     if t.dtype != dtype:
         t = t.view(dtype) if t.element_size() == torch.empty((), dtype=dtype).element_size() else t.to(dtype)
     return t.to(device, non_blocking=False).contiguous()
