@@ -221,6 +221,20 @@ __device__ __forceinline__ uint32_t code_of(uint32_t r) {
 
 constexpr uint32_t kPadWord = 0xFFFFu;  // above every word: sorts last
 
+// Inclusive prefix sum over the wave by DPP moves (no LDS): shifts by 1, 2,
+// 4 and 8 inside each 16-lane row, then row 0's total into row 1 and row
+// 2's into row 3 (row_bcast:15), then rows 0-1's total into rows 2 and 3
+// (row_bcast:31).  Lanes whose source is outside the row add 0.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return x;
+}
+
 // Two 16-bit words per register: one packed min or max orders two pairs.
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
@@ -314,9 +328,9 @@ __device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint
     c[u] = in ? code : 0u;
     bad = (in && code == 7u) ? min(bad, t) : bad;
   }
+  if (__ballot(bad != 0xFFFFFFFFu)) {  // rare: reduce to the first bad position
 #pragma unroll
-  for (int o = 32; o; o >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, o, 64));
-  if (bad != 0xFFFFFFFFu) {
+    for (int o = 32; o; o >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, o, 64));
     if (lane == 0) atomicMin(err, pack_err(i, kErrBadResidue, bad));
     return;
   }
@@ -348,7 +362,7 @@ __device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint
   }
   // runs: a start is an element unlike its predecessor (words sit in
   // [0, K), padding after); a run ends at the next start or at K
-  const uint32_t prev_last = (uint32_t)__shfl_up((int)v[E - 1], 1, 64);
+  const uint32_t prev_last = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[E - 1], 0x138, 0xF, 0xF, false);  // wave_shr:1
   uint32_t st = 0;  // bit s: element s starts a run
 #pragma unroll
   for (int s = 0; s < E; s++) {
@@ -356,15 +370,13 @@ __device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint
     const uint32_t pv = s ? v[s - 1] : prev_last;
     if (x < K && (x == 0 || v[s] != pv)) st |= 1u << s;
   }
-  // first start index in lanes above this one (suffix minimum)
-  uint32_t mine = st ? t0 + (uint32_t)(__ffs(st) - 1) : K;
-  uint32_t above = (uint32_t)__shfl_down((int)mine, 1, 64);
-  if (lane == 63) above = K;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = (uint32_t)__shfl_down((int)above, o, 64);
-    if (lane + (uint32_t)o < 64u) above = min(above, y);
-  }
+  // first start index in lanes above this one: the lowest such lane's own
+  // first start, or K when none
+  const uint32_t mine = st ? t0 + (uint32_t)(__ffs(st) - 1) : K;
+  const unsigned long long higher = __ballot(st != 0) & ~((2ull << lane) - 1ull);  // lane 63: 0
+  const int la = higher ? (int)__builtin_ctzll(higher) : (int)lane;
+  const uint32_t from = (uint32_t)__shfl((int)mine, la, 64);
+  const uint32_t above = higher ? from : K;
   // positions of the starts and of the count >= 2 starts
   uint32_t cnt[E];
   uint32_t nxt = above, ns = 0, nh = 0;
@@ -378,17 +390,9 @@ __device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint
       nh += cnt[s] >= 2u;
     }
   }
-  uint32_t ps = ns, ph = nh;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t ys = (uint32_t)__shfl_up((int)ps, o, 64);
-    const uint32_t yh = (uint32_t)__shfl_up((int)ph, o, 64);
-    if (lane >= (uint32_t)o) {
-      ps += ys;
-      ph += yh;
-    }
-  }
-  const uint32_t D = (uint32_t)__shfl((int)ps, 63, 64), NH = (uint32_t)__shfl((int)ph, 63, 64);
+  const uint32_t ps = wave_incl_sum(ns), ph = wave_incl_sum(nh);
+  const uint32_t D = (uint32_t)__builtin_amdgcn_readlane((int)ps, 63);
+  const uint32_t NH = (uint32_t)__builtin_amdgcn_readlane((int)ph, 63);
   uint32_t pos = ps - ns, hpos = ph - nh;
   const uint64_t co = o0 - 5ull * i;
   const bool ok = (o0 >= 5ull * i) && (co + K <= cap);
