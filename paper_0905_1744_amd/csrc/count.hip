@@ -239,8 +239,22 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ u16x2 swap16(u16x2 x) { return __builtin_shufflevector(x, x, 1, 0); }
+// The value of lane (lane ^ m).  With m known at compile time (the sort's
+// loops are unrolled) the partners inside a quad or a row come by DPP moves
+// (quad permutations for 1, 2 and 3, the half-row and row mirrors for 7
+// and 15: register to register); the others by a lane shuffle.
+__device__ __forceinline__ int lane_xor(int x, int m) {
+  switch (m) {
+    case 1: return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);   // quad_perm 1 0 3 2
+    case 2: return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);   // quad_perm 2 3 0 1
+    case 3: return __builtin_amdgcn_mov_dpp(x, 0x1B, 0xF, 0xF, false);   // quad_perm 3 2 1 0
+    case 7: return __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    case 15: return __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false); // row_mirror
+    default: return __shfl_xor(x, m, 64);
+  }
+}
 __device__ __forceinline__ u16x2 shfl_xor16(u16x2 x, int m) {
-  return __builtin_bit_cast(u16x2, __shfl_xor(__builtin_bit_cast(int, x), m, 64));
+  return __builtin_bit_cast(u16x2, lane_xor(__builtin_bit_cast(int, x), m));
 }
 
 // The bitonic network of count_wave on 64 E words (E >= 2) held two per
@@ -355,7 +369,7 @@ __device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint
       for (uint32_t j = k >> 1; j > 0; j >>= 1) {
         const uint32_t m = (j == (k >> 1)) ? (k - 1) : j;
         const bool lower = (lane & j) == 0;
-        const uint32_t o = (uint32_t)__shfl_xor((int)v[0], (int)m, 64);
+        const uint32_t o = (uint32_t)lane_xor((int)v[0], (int)m);
         v[0] = lower ? min(v[0], o) : max(v[0], o);
       }
     }
