@@ -334,10 +334,12 @@ __global__ __launch_bounds__(256) void layout_groups_kernel(Segs sg,
                                                             const uint64_t *__restrict__ offsets,
                                                             const uint16_t *__restrict__ cap_ids,
                                                             uint16_t *__restrict__ gids) {
+  typedef __attribute__((address_space(1))) const uint16_t gcu16;  // global loads, not flat
   __shared__ uint16_t buf[64][kSliceWords + 8];  // padded rows: 16-byte reads stay aligned
   __shared__ const uint16_t *src[64];
   __shared__ uint32_t len[64];
-  const uint32_t x = blockIdx.x, tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint32_t x = blockIdx.x, tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t set = sg.set_of_grp(x);
   const SetView &v = sg.views[set];
   const uint32_t g = x - sg.grp[set];
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(256) void layout_groups_kernel(Segs sg,
   if (blockIdx.y * kSliceWords >= L) return;  // uniform: nothing for this workgroup
   if (tid < 64) {
     const uint32_t s = 64u * g + tid;
-    src[tid] = nullptr;
+    src[tid] = cap_ids;  // an empty list: any valid address, never used
     len[tid] = 0;
     if (s < v.N) {
       const uint32_t i = v.base + v.perm[s];
@@ -356,15 +358,28 @@ __global__ __launch_bounds__(256) void layout_groups_kernel(Segs sg,
   __syncthreads();
   uint4 *dst = reinterpret_cast<uint4 *>(gids + v.grp_off[g]);
   for (uint32_t t0 = blockIdx.y * kSliceWords; t0 < L; t0 += kGroupSlices * kSliceWords) {
-    // wave w loads lists w, w + 4, ...: 64 words per instruction, two per list
-#pragma unroll 4
-    for (uint32_t r = wave; r < 64; r += 4) {
-      const uint16_t *sp = src[r];
-      const uint32_t n = len[r];
+    // wave w loads lists w, w + 4, ..., w + 60: 64 words per instruction,
+    // two per list, all 32 loads issued before the first LDS write (indices
+    // clamped into the list, so no load is conditional)
+    constexpr uint32_t kHalves = kSliceWords / 64;
+    uint32_t val[16][kHalves], n[16];
 #pragma unroll
-      for (uint32_t h = 0; h < kSliceWords; h += 64) {
-        const uint32_t t = t0 + h + lane;
-        buf[r][h + lane] = t < n ? sp[t] : kSentinel;
+    for (uint32_t k = 0; k < 16; k++) {
+      const uint32_t r = wave + 4u * k;
+      gcu16 *sp = (gcu16 *)src[r];
+      n[k] = len[r];
+#pragma unroll
+      for (uint32_t h = 0; h < kHalves; h++) {
+        const uint32_t t = t0 + 64u * h + lane;
+        val[k][h] = sp[t < n[k] ? t : 0u];
+      }
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < 16; k++) {
+#pragma unroll
+      for (uint32_t h = 0; h < kHalves; h++) {
+        const uint32_t t = t0 + 64u * h + lane;
+        buf[wave + 4u * k][64u * h + lane] = t < n[k] ? (uint16_t)val[k][h] : (uint16_t)kSentinel;
       }
     }
     __syncthreads();
