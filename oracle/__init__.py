@@ -22,7 +22,6 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "kd_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 EPS = 46656
@@ -38,12 +37,37 @@ class OracleError(RuntimeError):
         self.code, self.seq, self.pos = code, seq, pos
 
 
+def _host_tag() -> str:
+    """Short tag of the host CPU: the library is built with -march=native,
+    so a copy built on one machine is never loaded on another."""
+    import hashlib
+    import platform
+    sig = platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith(("model name", "flags")):
+                    sig += line
+                if line.startswith("flags"):
+                    break
+    except OSError:
+        pass
+    return hashlib.sha1(sig.encode()).hexdigest()[:12]
+
+
+_LIB = os.path.join(_HERE, "liboracle-%s.so" % _host_tag())
+
+# -O2 -march=native for the host it runs on; -ffp-contract=off keeps every
+# multiply and add separately rounded (no FMA contraction), so the oracle's
+# arithmetic is the same on every host.
+CFLAGS = ["-O2", "-march=native", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, single-threaded)."""
+    """Compile the oracle with gcc (single-threaded C, flags in CFLAGS)."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-                               "-o", tmp, _SRC, "-lm"])
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc"] + CFLAGS + ["-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

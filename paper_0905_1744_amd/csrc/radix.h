@@ -6,7 +6,10 @@
 // all passes are taken in one read (they do not depend on the order); each
 // pass then moves the elements in tiles of 4 x NT with a wave-level
 // multi-split (ballots on the digit bits) so equal digits keep their input
-// order.  A pass whose digit is the same for every key is skipped.
+// order.  A pass whose digit is the same for every key is skipped; the
+// skip decisions of all passes are taken once, right after the histograms,
+// and stay read-only while the passes run, so every wave takes the same
+// branches and meets the same barriers.
 #pragma once
 
 #include "kd_internal.h"
@@ -21,7 +24,7 @@ struct RadixShared {
   uint32_t base[256];
   uint32_t tot[256];
   uint16_t wcnt[SUB][NW][256];    // per (sub-tile, wave, digit) counts, then prefixes
-  uint32_t flag;
+  uint32_t skip[8];               // pass q moves nothing (one digit value holds all n keys)
   uint32_t wsum[NW];
 };
 
@@ -89,6 +92,7 @@ __device__ int block_radix_sort(KeyT *k0, uint32_t *v0, KeyT *k1, uint32_t *v1, 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int npass = (bit_hi - bit_lo + 7) / 8;
   for (int x = tid; x < npass * 256; x += NT) (&sh.hist[0][0])[x] = 0;
+  if (tid < 8) sh.skip[tid] = 0;
   __syncthreads();
   for (uint32_t i = tid; i < n; i += NT) {
     const KeyT key = k0[i];
@@ -97,6 +101,9 @@ __device__ int block_radix_sort(KeyT *k0, uint32_t *v0, KeyT *k1, uint32_t *v1, 
       atomicAdd(&sh.hist[q][(uint32_t)(key >> sh_q) & ((1u << nb_q) - 1u)], 1u);
     }
   }
+  __syncthreads();
+  for (int x = tid; x < npass * 256; x += NT)
+    if ((&sh.hist[0][0])[x] == n) sh.skip[x >> 8] = 1;
   __syncthreads();
   int cur = 0;
   for (int q = 0; q < npass; q++) {
@@ -107,12 +114,7 @@ __device__ int block_radix_sort(KeyT *k0, uint32_t *v0, KeyT *k1, uint32_t *v1, 
     uint32_t *vin = cur ? v1 : v0;
     KeyT *kout = cur ? k0 : k1;
     uint32_t *vout = cur ? v0 : v1;
-    if (tid == 0) sh.flag = 0;
-    __syncthreads();
-    for (int d = tid; d < 256; d += NT)
-      if (sh.hist[q][d] == n) sh.flag = 1;
-    __syncthreads();
-    if (sh.flag) continue;  // identical digit everywhere: the pass is the identity
+    if (sh.skip[q]) continue;  // identical digit everywhere: the pass is the identity
     if (wave == 0) {
       const uint32_t a0 = sh.hist[q][lane * 4], a1 = sh.hist[q][lane * 4 + 1];
       const uint32_t a2 = sh.hist[q][lane * 4 + 2], a3 = sh.hist[q][lane * 4 + 3];

@@ -1,7 +1,12 @@
-"""GPU: the request server.  Every served job's results must be bit-identical
-to the same job run alone through the single-set calls; admission must keep
-the reserved bytes within the budget; bad jobs fail alone; cancellation of
-queued jobs; one-job-at-a-time mode."""
+"""GPU: the request server.  Every served job's results must match the CPU
+oracle (ranks within 1e-12 of the tolerance scale, Equation 3; the split
+bit-exact on the served ranks and, against the oracle's own ranks, identical
+except next to a pivot, Section 3.1.2) and be bit-identical to the same job
+run alone through the single-set calls; admission must keep the reserved
+bytes within the budget; bad jobs fail alone; cancellation of queued jobs;
+one-job-at-a-time mode."""
+import concurrent.futures as cf
+import os
 import sys
 import time
 
@@ -43,6 +48,73 @@ def jobs():
     out.append(synth.random_tiny(rng, 3, 6, 40))   # B = 1
     out.append(synth.random_tiny(rng, 70, 6, 90))
     return out
+
+
+@pytest.fixture(scope="module")
+def oracle_jobs():
+    """Served-shape jobs (the served workload's generator: N log-uniform,
+    B = max(1, N/256)) for the oracle comparison, one of them with N > 4096
+    and B = 16 so that its split runs on the large-workgroup radix path."""
+    ss = np.random.SeedSequence(91).spawn(6)
+    out = [synth.served_job(ss[0], 4200, 4400)]
+    out += [synth.served_job(s, 64, 1400) for s in ss[1:]]
+    rng = np.random.default_rng(9)
+    out.append(synth.random_tiny(rng, 5, 6, 50))
+    return out
+
+
+def oracle_rank(oracle, L, delta):
+    """Equation 3 for every row, the rows split over host threads (the
+    oracle's C runs outside the interpreter lock); returns ranks, scale."""
+    n = L.n
+    nt = max(1, min(16, os.cpu_count() or 1))
+    chunks = [np.arange(a, min(n, a + 64), dtype=np.uint32) for a in range(0, n, 64)]
+    with cf.ThreadPoolExecutor(nt) as ex:
+        parts = list(ex.map(lambda r: oracle.rank(L, delta, rows=r, with_scale=True), chunks))
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
+
+
+@pytest.fixture(scope="module")
+def oracle_results(oracle_mod, oracle_jobs):
+    out = []
+    for q, x in enumerate(oracle_jobs):
+        delta = 0.1 if q % 2 == 0 else 0.05
+        L = oracle_mod.count(x)
+        R, scale = oracle_rank(oracle_mod, L, delta)
+        out.append(dict(delta=delta, R=R, scale=scale, part=oracle_mod.partition(R, x.B)))
+    return out
+
+
+@pytest.mark.parametrize("mirror", [True, False], ids=["device-copies", "host-copies"])
+def test_server_matches_oracle(kd, oracle_mod, oracle_jobs, oracle_results, mirror):
+    """Every served job against the CPU oracle: ranks within 1e-12 x the
+    scale (1/N) sum_j |d(i,j)|; the split of the served ranks bit-exact
+    against the oracle's split of those same ranks; buckets against the
+    oracle's own split identical except for a rank within twice the
+    tolerance of a pivot."""
+    srv = kd.Server(0, device_mirror=mirror)
+    say("server-oracle", [x.n for x in oracle_jobs], "mirror", mirror)
+    tickets = [(srv.submit(x.residues, x.offsets, x.B, oracle_results[q]["delta"]), q)
+               for q, x in enumerate(oracle_jobs)]
+    recs = drain(srv, len(tickets), timeout=120.0)
+    assert any(recs[t]["batch_jobs"] > 1 for t, _ in tickets)
+    for t, q in tickets:
+        x, want, rec = oracle_jobs[q], oracle_results[q], recs[t]
+        assert rec["status"] == 0, (q, rec["status"])
+        err = np.abs(rec["ranks"] - want["R"]) / want["scale"]
+        assert float(err.max()) <= 1e-12, (q, x.n, float(err.max()))
+        own = oracle_mod.partition(rec["ranks"], x.B)
+        for k in ("bucket", "order", "offsets"):
+            assert np.array_equal(rec[k], own[k]), (q, k)
+        pr = want["part"]
+        diff = np.flatnonzero(rec["bucket"] != pr["bucket"])
+        for i in diff:
+            gap = np.min(np.abs(pr["pivot_rank"] - want["R"][i]))
+            assert gap <= 2e-12 * want["scale"][i], (q, int(i), gap)
+        if diff.size == 0:
+            assert np.array_equal(rec["order"], pr["order"]) and np.array_equal(rec["offsets"], pr["offsets"])
+        assert x.B == max(1, x.n // 256)
+    srv.close()
 
 
 def alone(ctx, kd, x, delta):

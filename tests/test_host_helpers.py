@@ -23,3 +23,21 @@ def test_helpers_on_host(tmp_path):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "OK" in r.stdout
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    """The oracle's C built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (any report aborts), driven through every entry point and edge case."""
+    exe = str(tmp_path / "oracle_sanitize")
+    r = subprocess.run(["gcc", "-O1", "-g", "-std=c11", "-Wall", "-Wextra", "-Werror",
+                        "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        "-fno-omit-frame-pointer",
+                        os.path.join(ROOT, "oracle", "kd_oracle.c"),
+                        os.path.join(ROOT, "tests", "host", "oracle_sanitize.c"), "-o", exe, "-lm"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "OK" in r.stdout

@@ -109,6 +109,39 @@ def test_shared_vs_dense_bruteforce(oracle_mod, alphabet, seed):
     assert oracle_mod.shared_dense(cx, cy) == S[0, 1]
 
 
+def test_count_dense_bin_for_bin(oracle_mod):
+    """The literal 46,656-bin count vector (the reference for the dense
+    export) equals the independent base-6 histogram in every bin, not only
+    in its min-sum with another vector."""
+    rng = np.random.default_rng(13)
+    for alphabet in (AA, "AC", "ACDFHI"):
+        for _ in range(6):
+            s = "".join(rng.choice(list(alphabet), size=int(rng.integers(6, 300))))
+            assert np.array_equal(oracle_mod.count_dense(s.encode()), _dense_indep(s)), s
+    s = "A" * (65535 + 5)
+    d = oracle_mod.count_dense(s.encode())
+    assert d[0] == 65535 and int(d.sum()) == 65535
+
+
+def test_similarity_offset_blocks_bruteforce(oracle_mod):
+    """Section 3 shared counts and Equation 1 denominators on blocks that
+    start away from the origin (rows r0.., columns c0..), against the dense
+    brute force: a transposed or mis-offset block fails here."""
+    rng = np.random.default_rng(14)
+    ss = synth.random_tiny(rng, 29, 6, 110, b"ACDEFGH")
+    L = oracle_mod.count(ss)
+    dense = [_dense_indep(ss.seq(i).decode()) for i in range(ss.n)]
+    n = ss.lengths()
+    for r0, nr, c0, nc in ((3, 7, 11, 5), (0, 29, 17, 12), (20, 9, 0, 4), (28, 1, 28, 1), (5, 13, 2, 27)):
+        S, D = oracle_mod.similarity(L, r0, nr, c0, nc)
+        assert S.shape == (nr, nc)
+        for a in range(nr):
+            for b in range(nc):
+                i, j = r0 + a, c0 + b
+                assert S[a, b] == int(np.minimum(dense[i], dense[j]).sum()), (r0, c0, a, b)
+                assert D[a, b] == min(n[i], n[j]) - 5
+
+
 def test_shared_invariants(oracle_mod):
     rng = np.random.default_rng(5)
     ss = synth.random_tiny(rng, 16, 6, 200, b"ACDEFGHIK")
@@ -206,6 +239,25 @@ def test_rank_vs_exact_sum_bruteforce(oracle_mod):
               for j in range(ss.n)]
         ref = math.fsum(ds) / ss.n
         assert R[i] == pytest.approx(ref, rel=4e-16, abs=1e-300)
+
+
+def test_rank_row_subsets_vs_exact_sum(oracle_mod):
+    """Equation 3 for a subset of rows (any order, repeats): each row sums
+    over all N columns, exactly as for the full set."""
+    rng = np.random.default_rng(17)
+    ss = synth.random_tiny(rng, 26, 6, 90, b"ACDEFGHIKL")
+    dense = [_dense_indep(ss.seq(i).decode()) for i in range(ss.n)]
+    n = ss.lengths()
+    delta = 0.07
+    L = oracle_mod.count(ss)
+    rows = np.array([25, 3, 3, 0, 17, 9], dtype=np.uint32)
+    R, sc = oracle_mod.rank(L, delta, rows=rows, with_scale=True)
+    assert R.shape == (len(rows),)
+    for a, i in enumerate(rows.tolist()):
+        ds = [-math.log(delta + int(np.minimum(dense[i], dense[j]).sum()) / (min(n[i], n[j]) - 5))
+              for j in range(ss.n)]
+        assert R[a] == pytest.approx(math.fsum(ds) / ss.n, rel=4e-16, abs=1e-300)
+        assert sc[a] == pytest.approx(math.fsum(abs(d) for d in ds) / ss.n, rel=1e-15)
 
 
 def test_rank_bounds_and_permutation(oracle_mod):
@@ -400,6 +452,24 @@ def test_global_rank_vs_exact_sum_bruteforce(oracle_mod):
               for j in smp.tolist()]
         assert G[i] == pytest.approx(math.fsum(ds) / len(ds), rel=4e-16, abs=1e-300)
         assert sc[i] == pytest.approx(math.fsum(abs(d) for d in ds) / len(ds), rel=1e-15)
+
+
+def test_global_rank_row_subsets_vs_exact_sum(oracle_mod):
+    """Step 6 for a subset of rows: the same samples, summed exactly."""
+    rng = np.random.default_rng(23)
+    ss = synth.random_tiny(rng, 27, 6, 85, b"ACDEFGHIKLMN")
+    dense = [_dense_indep(ss.seq(i).decode()) for i in range(ss.n)]
+    n = ss.lengths()
+    delta = 0.1
+    L = oracle_mod.count(ss)
+    smp = np.array([4, 26, 11, 11, 0], dtype=np.uint32)
+    rows = np.array([26, 0, 13, 13, 5], dtype=np.uint32)
+    G, sc = oracle_mod.global_rank(L, smp, delta, rows=rows, with_scale=True)
+    for a, i in enumerate(rows.tolist()):
+        ds = [-math.log(delta + int(np.minimum(dense[i], dense[j]).sum()) / (min(n[i], n[j]) - 5))
+              for j in smp.tolist()]
+        assert G[a] == pytest.approx(math.fsum(ds) / len(ds), rel=4e-16, abs=1e-300)
+        assert sc[a] == pytest.approx(math.fsum(abs(d) for d in ds) / len(ds), rel=1e-15)
 
 
 def test_global_rank_all_sampled_is_centralized(oracle_mod):
