@@ -161,12 +161,11 @@ def bench_global(args):
     res = torch.from_numpy(ss.residues).to(dev)
     off = torch.from_numpy(ss.offsets.view(np.int64)).to(dev)
     ctx = kd.Context(0)
-    first = kd.Context.block_bounds(N, B)
     loc = torch.empty(N, dtype=torch.float64, device=dev)
     G = torch.empty(N, dtype=torch.float64, device=dev)
 
     def step():
-        kb = ctx.kmer_count_batch(res, off, first)
+        kb = ctx.kmer_count_blocks(res, off, B)
         ctx.kmer_rank(kb, delta, out=loc)
         _, smp = ctx.kmer_rank_global(kb, loc, k, delta, out=G)
         part = ctx.sample_partition(G, B)
@@ -201,6 +200,7 @@ def bench_global(args):
     ctx.enable_timing(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
+    first = kb.set_first()  # the library's Algorithm 2 step 1 blocks
     w = np.diff(first.astype(np.int64))
     local_pairs = int((w * (w - 1) // 2).sum())
     cross_pairs = N * k * B

@@ -246,6 +246,15 @@ kd_status kd_batch_run(kd_ctx *ctx, const uint8_t *residues, const uint64_t *off
                        const uint32_t *set_B, double delta, double *ranks, uint32_t *bucket,
                        uint32_t *order, uint32_t *offsets_out);
 
+/* Algorithm 2 step 1 on one device: the n sequences split into the B
+ * contiguous blocks [floor(bn/B), floor((b+1)n/B)) the paper's processors
+ * start from, each counted as its own set (kmer_count_batch with those
+ * bounds).  kmer_rank on the result gives the local ranks of step 2.
+ * Inputs as for kmer_count.  Errors: those of kmer_count_batch; KD_EINVAL
+ * for B == 0 or B > n. */
+kd_status kmer_count_blocks(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                            uint32_t n_seqs, uint64_t n_residues, uint32_t B, kd_set **out);
+
 /* ------------------------------------------------------- globalized rank */
 
 /* Globalized k-mer rank (Section 3.1.1 "Globalised k-mer Rank"; Algorithm 2

@@ -94,6 +94,7 @@ def lib():
         "kmer_rank": (i32, [P, P, C.c_double, P]),
         "sample_partition": (i32, [P, P, u32, u32, P, P, P, P, P]),
         "kmer_count_batch": (i32, [P, P, P, u64, u32, P, PP]),
+        "kmer_count_blocks": (i32, [P, P, P, u32, u64, u32, PP]),
         "kd_set_count": (u32, [P]),
         "kd_set_first": (i32, [P, P]),
         "sample_partition_batch": (i32, [P, P, u32, P, P, P, P, P, P, P]),
@@ -323,11 +324,6 @@ class Context:
                                            _ptr(R), _ptr(smp)), "kmer_rank_global")
         return R, smp[:int(k) * blocks.nsets]
 
-    @staticmethod
-    def block_bounds(n: int, B: int) -> np.ndarray:
-        """The B contiguous blocks [floor(bn/B), floor((b+1)n/B)) of Algorithm 2 step 1."""
-        return (np.arange(B + 1, dtype=np.uint64) * n // B).astype(np.uint32)
-
     def globalized_rank(self, residues, offsets, B: int, k: int = None, delta: float = 0.1):
         """Algorithm 2 steps 1-6 on one device: count the B blocks, rank each
         against itself (local ranks), then every sequence against k samples
@@ -337,7 +333,7 @@ class Context:
         if not 1 <= B <= n:
             raise ValueError("need 1 <= B <= number of sequences")
         k = max(B - 1, 1) if k is None else int(k)
-        kb = self.kmer_count_batch(residues, off, self.block_bounds(n, B))
+        kb = self.kmer_count_blocks(residues, off, B)
         try:
             loc = self.kmer_rank(kb, delta)
             R, smp = self.kmer_rank_global(kb, loc, k, delta)
@@ -515,6 +511,16 @@ class Context:
         self._check(lib().kmer_count_batch(self.handle, _ptr(res), _ptr(off), res.numel(), sf.size - 1,
                                            sf.ctypes.data_as(C.c_void_p), C.byref(out)),
                     "kmer_count_batch")
+        return KmerSet(self, out)
+
+    def kmer_count_blocks(self, residues, offsets, B: int) -> KmerSet:
+        """Algorithm 2 step 1: the B contiguous blocks of the input, each
+        counted as its own set (the library computes the block bounds)."""
+        res = _dev_tensor(residues, torch.uint8, self.device)
+        off = _dev_tensor(offsets, torch.int64, self.device)
+        out = C.c_void_p()
+        self._check(lib().kmer_count_blocks(self.handle, _ptr(res), _ptr(off), off.numel() - 1, res.numel(),
+                                            int(B), C.byref(out)), "kmer_count_blocks")
         return KmerSet(self, out)
 
     def sample_partition_batch(self, ranks, set_first, set_B, pivots: bool = True):

@@ -682,6 +682,17 @@ extern "C" kd_status kmer_count_batch(kd_ctx *ctx, const uint8_t *residues,
   return build_sets(ctx, residues, offsets, nsets, set_first, n_residues, out);
 }
 
+extern "C" kd_status kmer_count_blocks(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                                       uint32_t n_seqs, uint64_t n_residues, uint32_t B, kd_set **out) {
+  if (!ctx || !out) return KD_EINVAL;
+  *out = nullptr;
+  if (B == 0 || B > n_seqs) return KD_EINVAL;
+  // Algorithm 2 step 1: block b = [floor(b n / B), floor((b+1) n / B))
+  std::vector<uint32_t> first(B + 1);
+  for (uint32_t b = 0; b <= B; b++) first[b] = (uint32_t)((uint64_t)b * n_seqs / B);
+  return build_sets(ctx, residues, offsets, B, first.data(), n_residues, out);
+}
+
 extern "C" uint32_t kd_set_count(const kd_set *s) { return s ? s->nsets : 0; }
 
 extern "C" kd_status kd_set_first(const kd_set *s, uint32_t *first) {
@@ -900,9 +911,7 @@ extern "C" kd_status kd_decompose(kd_ctx *ctx, const uint8_t *residues, const ui
     rc = kmer_count(ctx, residues, offsets, n_seqs, n_residues, &s);
     if (rc == KD_OK) rc = kmer_rank(ctx, s, delta, ranks);
   } else {
-    std::vector<uint32_t> first(B + 1);
-    for (uint32_t b = 0; b <= B; b++) first[b] = (uint32_t)((uint64_t)b * n_seqs / B);
-    rc = kmer_count_batch(ctx, residues, offsets, n_residues, B, first.data(), &s);
+    rc = kmer_count_blocks(ctx, residues, offsets, n_seqs, n_residues, B, &s);
     Scope tmp(ctx);
     double *local = rc == KD_OK ? tmp.get<double>(n_seqs) : nullptr;
     if (rc == KD_OK && !local) rc = KD_ENOMEM;

@@ -135,7 +135,7 @@ def test_global_deterministic_and_reusable(kd, ctx, oracle_mod):
     it (they share the accumulators), are bit-identical."""
     ss = synth.small()
     off = ss.offsets.view(np.int64)
-    kb = ctx.kmer_count_batch(ss.residues, off, ctx.block_bounds(ss.n, 4))
+    kb = ctx.kmer_count_blocks(ss.residues, off, 4)
     loc = ctx.kmer_rank(kb, 0.1)
     G1, s1 = ctx.kmer_rank_global(kb, loc, 3, 0.1)
     loc2 = ctx.kmer_rank(kb, 0.1)
@@ -149,7 +149,7 @@ def test_global_deterministic_and_reusable(kd, ctx, oracle_mod):
 def test_global_errors(kd, ctx):
     ss = synth.small()
     off = ss.offsets.view(np.int64)
-    kb = ctx.kmer_count_batch(ss.residues, off, ctx.block_bounds(ss.n, 4))
+    kb = ctx.kmer_count_blocks(ss.residues, off, 4)
     loc = ctx.kmer_rank(kb, 0.1)
     for k, delta in ((0, 0.1), (129, 0.1), (3, 0.0), (3, float("nan"))):
         with pytest.raises(kd.KdError) as e:
