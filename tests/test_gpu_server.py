@@ -112,7 +112,12 @@ def test_server_matches_oracle(kd, oracle_mod, oracle_jobs, oracle_results, mirr
             gap = np.min(np.abs(pr["pivot_rank"] - want["R"][i]))
             assert gap <= 2e-12 * want["scale"][i], (q, int(i), gap)
         if diff.size == 0:
-            assert np.array_equal(rec["order"], pr["order"]) and np.array_equal(rec["offsets"], pr["offsets"])
+            assert np.array_equal(rec["offsets"], pr["offsets"]), q
+        # the served order is the oracle's key order up to near-ties (ranks
+        # within twice the tolerance may swap, e.g. exactly tied ranks)
+        Ro = want["R"][rec["order"].astype(np.int64)]
+        so = want["scale"][rec["order"].astype(np.int64)]
+        assert np.all(Ro[:-1] <= Ro[1:] + 2e-12 * np.maximum(so[:-1], so[1:])), q
         assert x.B == max(1, x.n // 256)
     srv.close()
 
