@@ -46,6 +46,7 @@ typedef int32_t kd_status;
 #define KD_EBUSY (-6)         /* server: job does not fit the HBM budget right now */
 #define KD_EDEVICE (-7)       /* a HIP runtime error */
 #define KD_ECANCELLED (-8)    /* server: job was cancelled */
+#define KD_ETOOLARGE (-9)     /* input beyond a call's fixed maximum size */
 
 #define KD_K 6
 #define KD_WORDS 46656        /* 6^6 distinct words */
@@ -199,6 +200,27 @@ kd_status kd_ctx_set_rows_per_task(kd_ctx *ctx, uint32_t nsets, uint32_t n, uint
 kd_status sample_partition(kd_ctx *ctx, const double *ranks, uint32_t n, uint32_t B,
                            uint32_t *bucket, uint32_t *order, uint32_t *offsets,
                            double *pivot_rank, uint32_t *pivot_idx);
+
+/* sample_partition for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, outputs (bit for bit) and errors as
+ * sample_partition, plus KD_ETOOLARGE for n > KD_NOALLOC_MAX_KEYS.
+ *  - Its working memory is one fixed array of KD_NOALLOC_SCRATCH_BYTES in the
+ *    library's device code: each GPU the library runs on holds its own copy
+ *    from its first kd_ctx_create until the process ends.  The call makes no
+ *    allocation (no hipMalloc, no pool, no pinned staging) and records no
+ *    stage timing.
+ *  - Nothing in the array has to start at zero: every kernel of the split
+ *    writes what it later reads, so a call never depends on what an earlier
+ *    call left there.
+ *  - Every call on one GPU works in that GPU's one array: calls that overlap
+ *    on one GPU (two streams, two contexts, two host threads) race and give
+ *    undefined results.  Serialize them, e.g. on one stream. */
+#define KD_NOALLOC_MAX_KEYS 1048576u
+#define KD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+kd_status sample_partition_noalloc(kd_ctx *ctx, const double *ranks, uint32_t n, uint32_t B,
+                                   uint32_t *bucket, uint32_t *order, uint32_t *offsets,
+                                   double *pivot_rank, uint32_t *pivot_idx);
 
 /* ---------------------------------------------------------------- batches */
 

@@ -28,7 +28,7 @@ _lib = None
 KD_OK = 0
 STATUS = {0: "KD_OK", -1: "KD_EINVAL", -2: "KD_EBADRESIDUE", -3: "KD_ESHORTSEQ",
           -4: "KD_ETOOLONG", -5: "KD_ENOMEM", -6: "KD_EBUSY", -7: "KD_EDEVICE",
-          -8: "KD_ECANCELLED"}
+          -8: "KD_ECANCELLED", -9: "KD_ETOOLARGE"}
 WORDS = 46656
 
 
@@ -93,6 +93,7 @@ def lib():
         "kmer_similarity": (i32, [P, P, u32, u32, u32, u32, P, P]),
         "kmer_rank": (i32, [P, P, C.c_double, P]),
         "sample_partition": (i32, [P, P, u32, u32, P, P, P, P, P]),
+        "sample_partition_noalloc": (i32, [P, P, u32, u32, P, P, P, P, P]),
         "kmer_count_batch": (i32, [P, P, P, u64, u32, P, PP]),
         "kmer_count_blocks": (i32, [P, P, P, u32, u64, u32, PP]),
         "kd_set_count": (u32, [P]),
@@ -309,6 +310,19 @@ class Context:
                                            _ptr(offsets), _ptr(pr), _ptr(pi)), "sample_partition")
         return dict(bucket=bucket[:n], order=order[:n], offsets=offsets, pivot_rank=pr[:max(B - 1, 0)],
                     pivot_idx=pi[:max(B - 1, 0)])
+
+    def sample_partition_noalloc(self, ranks, B: int, out):
+        """sample_partition through the entry point that allocates no device
+        memory.  `ranks` is a device f64 tensor and `out` a dict of
+        preallocated device tensors (bucket, order: int32[n]; offsets:
+        int32[B+1]; pivot_rank f64[B-1] and pivot_idx int32[B-1], each may be
+        None) which receive the results."""
+        n = ranks.numel()
+        self._check(lib().sample_partition_noalloc(
+            self.handle, _ptr(ranks), n, B, _ptr(out["bucket"]), _ptr(out["order"]),
+            _ptr(out["offsets"]), _ptr(out.get("pivot_rank")), _ptr(out.get("pivot_idx"))),
+            "sample_partition_noalloc")
+        return out
 
     # ---------------------------------------------------- globalized rank
     def kmer_rank_global(self, blocks: KmerSet, local_ranks, k: int, delta: float = 0.1, out=None):

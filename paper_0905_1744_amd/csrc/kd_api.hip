@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 
 #include "kd_internal.h"
@@ -249,6 +251,39 @@ extern "C" kd_status kd_ctx_reset_timing(kd_ctx *ctx) {
   return KD_OK;
 }
 
+// Working memory of sample_partition_noalloc: one fixed array per GPU in
+// the code object.  In host code `noalloc::scratch` only names the symbol;
+// its device address on each GPU comes from hipGetSymbolAddress, taken once
+// per device (with that device current) when the first context is created
+// there, and every use goes through that address.
+namespace kd {
+namespace noalloc {
+static_assert(KD_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) char scratch[KD_NOALLOC_SCRATCH_BYTES];
+static std::mutex mu;
+static std::map<int, void *> addr;  // device -> device address of its copy
+}  // namespace noalloc
+}  // namespace kd
+
+namespace {
+
+// Device address of `device`'s copy of the array; resolved on first use,
+// with `device` current (the caller has set it).  nullptr on a HIP error.
+void *noalloc_scratch_resolve(int device) {
+  std::lock_guard<std::mutex> lk(noalloc::mu);
+  auto it = noalloc::addr.find(device);
+  if (it != noalloc::addr.end()) return it->second;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc::scratch)) != hipSuccess || ptr == nullptr) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  noalloc::addr[device] = ptr;
+  return ptr;
+}
+
+}  // namespace
+
 extern "C" kd_status kd_ctx_create(int device, void *hip_stream, kd_ctx **out) {
   if (!out) return KD_EINVAL;
   *out = nullptr;
@@ -262,6 +297,10 @@ extern "C" kd_status kd_ctx_create(int device, void *hip_stream, kd_ctx **out) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->cus = cus;
+  if (noalloc_scratch_resolve(device) == nullptr) {
+    delete c;
+    return KD_EDEVICE;
+  }
   c->pool = new kd::Pool();
   if (hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
     delete c->pool;
@@ -299,6 +338,7 @@ extern "C" const char *kd_strerror(kd_status s) {
     case KD_EBUSY: return "HBM budget exhausted";
     case KD_EDEVICE: return "HIP runtime error";
     case KD_ECANCELLED: return "cancelled";
+    case KD_ETOOLARGE: return "input larger than the call's fixed maximum";
     default: return "unknown status";
   }
 }
@@ -1211,6 +1251,27 @@ extern "C" kd_status sample_partition(kd_ctx *ctx, const double *ranks, uint32_t
   KD_TRY(launch_partition(ctx->stream, ranks, n, B, bucket, order, offsets, pivot_rank, pivot_idx,
                           scratch));
   t.done();
+  return KD_OK;
+}
+
+extern "C" kd_status sample_partition_noalloc(kd_ctx *ctx, const double *ranks, uint32_t n,
+                                              uint32_t B, uint32_t *bucket, uint32_t *order,
+                                              uint32_t *offsets, double *pivot_rank,
+                                              uint32_t *pivot_idx) {
+  if (!ctx || !ranks || !bucket || !order || !offsets) return KD_EINVAL;
+  if (n == 0 || B == 0 || B > n || B > kMaxBuckets) return KD_EINVAL;
+  if (n > KD_NOALLOC_MAX_KEYS) return KD_ETOOLARGE;
+  if (partition_scratch_bytes(n, B) > KD_NOALLOC_SCRATCH_BYTES) return KD_ETOOLARGE;
+  KD_TRY(hipSetDevice(ctx->device));
+  void *scratch_dev = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(noalloc::mu);
+    auto it = noalloc::addr.find(ctx->device);
+    if (it != noalloc::addr.end()) scratch_dev = it->second;
+  }
+  if (!scratch_dev) return KD_EDEVICE;  // kd_ctx_create resolved it for this device
+  KD_TRY(launch_partition(ctx->stream, ranks, n, B, bucket, order, offsets, pivot_rank, pivot_idx,
+                          scratch_dev));
   return KD_OK;
 }
 
