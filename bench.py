@@ -45,7 +45,7 @@ TREE_SOURCES = ["paper_0905_1744_amd/csrc/tree.hip", "paper_0905_1744_amd/csrc/t
                 "paper_0905_1744_amd/csrc/radix.h"]
 TRAFFIC = {
     "rank_pairs_kernel": {"sources": RANK_SOURCES, "sha256_16": "2f650a120323f405",
-                          "workload": "paper20k", "rows_per_workgroup": 2, "bytes_per_launch": 839851227},
+                          "workload": "paper20k", "rows_per_workgroup": -1, "bytes_per_launch": 839851227},
     "rank_cross_kernel": {"sources": ["paper_0905_1744_amd/csrc/cross.hip", "paper_0905_1744_amd/csrc/tile.h",
                                       "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h"],
                           "sha256_16": "6f4d6a4f4effdd3f", "workload": "global100k", "rows_per_workgroup": None,
@@ -116,6 +116,66 @@ def cpu_baseline(ss, delta, budget_s):
     }
 
 
+def cpu_baseline_all_cores(ss, delta, budget_s, L=None):
+    """The same oracle on every core the run may use: rows dealt round-robin
+    to P threads (ctypes releases the GIL during the oracle's C calls, so the
+    threads run in parallel), timed on the wall clock and extrapolated to the
+    whole job like the single-thread leg."""
+    import concurrent.futures as cf
+    import numpy as np
+    import oracle
+    nproc = os.cpu_count() or 1
+    P = max(1, min(nproc, int(os.environ.get("KD_CPU_THREADS", "16"))))
+    t0 = time.perf_counter()
+    if L is None:
+        L = oracle.count(ss)
+    t_count = time.perf_counter() - t0
+    N = ss.n
+    probe = np.arange(min(8, N), dtype=np.uint32)
+    t0 = time.perf_counter()
+    oracle.rank(L, delta, rows=probe)
+    per_row = (time.perf_counter() - t0) / len(probe)
+    M = int(min(N, max(P, P * budget_s / max(per_row, 1e-9))))
+    chunks = [np.arange(p, M, P, dtype=np.uint32) for p in range(P)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=P) as ex:
+        list(ex.map(lambda r: oracle.rank(L, delta, rows=r), chunks))
+    t_rows = time.perf_counter() - t0
+    job_s = t_count + t_rows * N / M
+    pairs = N * (N - 1) / 2
+    return {
+        "value": pairs / job_s,
+        "unit": "pair-similarities/s",
+        "cores": P,
+        "host_nproc": nproc,
+        "kind": "oracle",
+        "sample": (f"oracle k-mer counting of all {N} sequences (one thread, {t_count:.2f} s) + rank "
+                   f"rows 0..{M - 1} against all {N} sequences on {P} threads ({t_rows:.2f} s wall, "
+                   f"{M * N} pair similarities); job time extrapolated to all {N} rows = {job_s:.1f} s"),
+    }
+
+
+def rank_lookups(D):
+    """64-lane LDS mask lookups of one rank_pairs launch: column group g
+    (64 consecutive sequences in ascending-D order) walks its padded list,
+    max D rounded up to 16, once against each of the row blocks rb >= 4g."""
+    import numpy as np
+    d = np.sort(np.asarray(D, dtype=np.int64))
+    n = d.size
+    G, RB = (n + 63) // 64, (n + 15) // 16
+    g = np.arange(G)
+    L = (d[np.minimum(64 * g + 63, n - 1)] + 15) // 16 * 16
+    return int((L * np.maximum(RB - 4 * g, 0)).sum())
+
+
+def lds_ceiling(ctx, workgroups=1024, steps=64):
+    """Measured rate of random 16-bit LDS reads (32 in flight per lane) over
+    the whole chip, in 64-lane reads per second (kd_calibrate_lds)."""
+    ctx.calibrate_lds(workgroups, 4, 32)  # warm-up
+    ms, n = ctx.calibrate_lds(workgroups, steps, 32)
+    return n / (ms / 1e3)
+
+
 def probe_count_cross(D, smp):
     """sum over (sequence, sample) pairs of min(D_i, D_s)."""
     import numpy as np
@@ -176,7 +236,7 @@ def bench_global(args):
         kb, smp, _ = step()
         if w == 0 and not args.no_autotune:
             best, ms = ctx.autotune(kb, delta)
-            tune = {"rows_per_workgroup": best, "ms_per_shape": ms}
+            tune = {"tasks_per_cu": best, "ms_per_shape": ms}
         kb.destroy()
     ctx.enable_timing(True, stages=("pairs", "global"))
     ctx.reset_timing()
@@ -431,7 +491,7 @@ def bench_batched(args):
     kb = ctx.kmer_count_batch(res, off, first)
     if not args.no_autotune:  # work-list shape for batches of this size class
         best, ms = ctx.autotune(kb, args.delta)
-        tune = {"rows_per_workgroup": best, "ms_per_shape": ms}
+        tune = {"tasks_per_cu": best, "ms_per_shape": ms}
     _, _, loff = kb.export_lists()
     D = np.diff(loff.cpu().numpy())
     probes = sum(probe_count(D[a:b]) for a, b in zip(first[:-1].astype(np.int64), first[1:].astype(np.int64)))
@@ -605,7 +665,22 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
                          "(calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE against known bytes)")
+    ap.add_argument("--lds-probe", action="store_true",
+                    help="only time the random 16-bit LDS read probe (2, 8 and 32 reads in flight "
+                         "per lane): the ceiling of the rank kernels' mask lookups")
     args = ap.parse_args()
+    if args.lds_probe:
+        import paper_0905_1744_amd as kd
+        ctx = kd.Context(0)
+        out = {}
+        for batch in (2, 8, 32):
+            ctx.calibrate_lds(1024, 4, batch)
+            ms, n = ctx.calibrate_lds(1024, 64, batch)
+            out[str(batch)] = {"ms": ms, "wave_reads": n, "wave_reads_per_s": n / (ms / 1e3),
+                               "cu_cycles_per_wave_read_at_2.4GHz": 256 * 2.4e9 * (ms / 1e3) / n}
+        ctx.close()
+        print(json.dumps({"lds_probe": out, "workgroups": 1024, "reads_per_lane": 64 * 32}))
+        return
     if args.copy_probe:
         import torch
         n = args.copy_probe << 20
@@ -665,7 +740,7 @@ def main():
         if w == 0 and not args.no_autotune:
             # work-list shape for this size class; later counts use it
             best, ms = ctx.autotune(kset, delta)
-            tune = {"rows_per_workgroup": best, "ms_per_shape": ms}
+            tune = {"tasks_per_cu": best, "ms_per_shape": ms}
         kset.destroy()
     torch.cuda.synchronize()
     # timed region: only the rank kernel carries events (for the roofline)
@@ -699,11 +774,24 @@ def main():
     probes = probe_count(D)
     t_pair = pair_ms / max(pair_n, 1) / 1e3
     achieved = probes / t_pair / 1e12
-    rows = tune["rows_per_workgroup"] if tune else 4
+    rows = tune["tasks_per_cu"] if tune else 4
+    lookups = rank_lookups(D)
+    ceiling = lds_ceiling(ctx)
+    traffic = measured_traffic("rank_pairs_kernel", args.workload, rows)
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
-                "frac": achieved / PEAK_TPROBE, "traffic": measured_traffic("rank_pairs_kernel", args.workload, rows),
+                "frac": achieved / PEAK_TPROBE, "traffic": traffic,
                 "kernel": "rank_pairs_kernel", "kernel_ms": t_pair * 1e3,
-                "work_per_launch": {"probes": probes, "pairs": pairs}}
+                "work_per_launch": {"probes": probes, "pairs": pairs, "wave_lds_lookups": lookups,
+                                    "algorithmic_bytes": int(D.sum()) * 2 + 8 * N},
+                "achieved_note": ("algorithm-equivalent rate: the pairs' merge probes "
+                                  "sum_{i<j} min(D_i, D_j) per second against one probe per lane-cycle; "
+                                  "the kernel does them as bit-sliced table lookups, 16 rows per lookup"),
+                "lds": {"bound": "lds", "achieved": lookups / t_pair, "peak": ceiling,
+                        "unit": "wave-reads/s", "frac": lookups / t_pair / ceiling,
+                        "note": ("the kernel's own ceiling: random 16-bit LDS reads, 32 in flight per "
+                                 "lane, measured live by kd_calibrate_lds on this device")},
+                "hbm": {"bytes_per_launch": traffic,
+                        "frac": (traffic / t_pair / 8e12) if traffic else None}}
     line = {
         "metric": METRIC, "value": value, "unit": "pair-similarities/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -718,6 +806,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(ss, delta, args.cpu_seconds)
+        line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(ss, delta, args.cpu_seconds / 2)
     kset.destroy()
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -159,21 +159,24 @@ kd_status kmer_similarity(kd_ctx *ctx, const kd_set *set, uint32_t r0, uint32_t 
  * Errors: KD_EINVAL for delta <= 0 or not finite. */
 kd_status kmer_rank(kd_ctx *ctx, const kd_set *set, double delta, double *ranks);
 
-/* Autotuner for the rank kernel's work-list shape (how many 16-sequence row
- * blocks one workgroup takes against its 32 column groups: more means fewer
- * accumulator atomics, fewer means better load balance).  Times kmer_rank on
- * `set` for each of the KD_TUNE_CANDIDATES shapes {1, 2, 4, 8, 16} (one
- * warm-up and three timed runs each; the stream is synchronized), checks
- * that all shapes give bit-identical ranks (KD_EDEVICE otherwise), gives the
- * set the fastest shape and remembers it in the context for later counted
- * objects of the same size class (power-of-two bucket of the sequence
- * count, single sets and batches apart).
- *   best    receives the chosen row blocks per workgroup (may be NULL)
+/* Autotuner for the rank kernel's work-list shape.  The all-pairs work of a
+ * counted object is cut into about T = t x (compute units) workgroups of
+ * equal estimated cost (runs of row blocks against strips of 2,048
+ * sequences); more workgroups balance better, fewer flush fewer column sums
+ * to the accumulators.  Times kmer_rank on `set` for each of the
+ * KD_TUNE_CANDIDATES values t = {1, 2, 4, 8, 16} (one warm-up and three
+ * timed runs each; the stream is synchronized), checks that all shapes give
+ * bit-identical ranks (KD_EDEVICE otherwise), gives the set the fastest
+ * shape and remembers t in the context for later counted objects of the
+ * same size class (power-of-two bucket of the sequence count, single sets
+ * and batches apart).
+ *   best    receives the chosen t (may be NULL)
  *   ms_out  NULL or double[KD_TUNE_CANDIDATES]: mean milliseconds per shape */
 #define KD_TUNE_CANDIDATES 5
 kd_status kd_autotune(kd_ctx *ctx, kd_set *set, double delta, uint32_t *best, double *ms_out);
-/* Set the shape by hand for the size class of (nsets, n); rows in 1..4096. */
-kd_status kd_ctx_set_rows_per_task(kd_ctx *ctx, uint32_t nsets, uint32_t n, uint32_t rows);
+/* Set t (rank workgroups per compute unit, 1..4096) by hand for the size
+ * class of (nsets, n); it applies to objects counted afterwards. */
+kd_status kd_ctx_set_tasks_per_cu(kd_ctx *ctx, uint32_t nsets, uint32_t n, uint32_t tasks);
 
 /* -------------------------------------------------------- sample_partition */
 
@@ -412,6 +415,21 @@ typedef struct kd_psp_pair {
  * Errors: KD_EINVAL for a NULL argument, or more than 2^31 tiles of
  * 64 x 512 scores in one call. */
 kd_status psp_scores(kd_ctx *ctx, const double *M, uint32_t npairs, const kd_psp_pair *pairs);
+
+/* ------------------------------------------------------------ calibration */
+
+/* Rate of random 16-bit LDS reads, the elementary operation of the rank
+ * kernels' mask lookups (measurement support: computes nothing of the
+ * method).  Launches `workgroups` workgroups of 1024 threads; every lane
+ * makes steps x 32 reads at pseudo-random indices of a 32,768-entry LDS
+ * table, `batch` (2, 8 or 32) of them issued together before their values
+ * are used.  Synchronizes the stream; returns the kernel's time from HIP
+ * events on the context's stream and the number of 64-lane read
+ * instructions executed.  Device memory: 4 bytes per thread (freed on
+ * return).  Errors: KD_EINVAL for another batch, 0 workgroups or steps,
+ * or NULL outputs. */
+kd_status kd_calibrate_lds(kd_ctx *ctx, uint32_t workgroups, uint32_t steps, uint32_t batch,
+                           double *ms, uint64_t *wave_reads);
 
 /* ----------------------------------------------------------------- server */
 

@@ -101,7 +101,7 @@ def lib():
         "sample_partition_batch": (i32, [P, P, u32, P, P, P, P, P, P, P]),
         "kd_batch_run": (i32, [P, P, P, u64, u32, P, P, C.c_double, P, P, P, P]),
         "kd_autotune": (i32, [P, P, C.c_double, C.POINTER(u32), C.POINTER(C.c_double)]),
-        "kd_ctx_set_rows_per_task": (i32, [P, u32, u32, u32]),
+        "kd_ctx_set_tasks_per_cu": (i32, [P, u32, u32, u32]),
         "kmer_rank_global": (i32, [P, P, P, u32, C.c_double, P, P]),
         "kd_gather_sequences": (i32, [P, P, P, u32, u64, P, u32, P, u64, P]),
         "kmer_distance_matrices": (i32, [P, P, C.c_double, P]),
@@ -109,6 +109,7 @@ def lib():
         "psp_profile": (i32, [P, P, u32, u32, P]),
         "kd_decompose": (i32, [P, P, P, u32, u64, u32, C.c_int, C.c_double, P, P, P, P]),
         "psp_scores": (i32, [P, P, u32, P]),
+        "kd_calibrate_lds": (i32, [P, u32, u32, u32, C.POINTER(C.c_double), C.POINTER(u64)]),
         "kd_server_create": (i32, [C.c_int, C.POINTER(ServerOpts), PP]),
         "kd_server_submit": (i32, [P, C.POINTER(Job), C.POINTER(u64)]),
         "kd_server_poll": (i32, [P, C.POINTER(Done), u32, C.POINTER(u32), C.c_int64]),
@@ -284,14 +285,14 @@ class Context:
 
     def autotune(self, kset: KmerSet, delta: float = 0.1):
         """Pick the rank kernel's work-list shape for sets of this size class
-        (kd_autotune); returns (rows per workgroup, {shape: ms})."""
+        (kd_autotune); returns (workgroups per compute unit, {shape: ms})."""
         best = C.c_uint32()
         ms = (C.c_double * len(self.TUNE_SHAPES))()
         self._check(lib().kd_autotune(self.handle, kset.handle, float(delta), C.byref(best), ms), "kd_autotune")
         return int(best.value), dict(zip(self.TUNE_SHAPES, list(ms)))
 
-    def set_rows_per_task(self, nsets: int, n: int, rows: int):
-        self._check(lib().kd_ctx_set_rows_per_task(self.handle, nsets, n, rows), "kd_ctx_set_rows_per_task")
+    def set_tasks_per_cu(self, nsets: int, n: int, tasks: int):
+        self._check(lib().kd_ctx_set_tasks_per_cu(self.handle, nsets, n, tasks), "kd_ctx_set_tasks_per_cu")
 
     def kmer_rank(self, kset: KmerSet, delta: float = 0.1, out=None):
         R = out if out is not None else torch.empty(kset.n, dtype=torch.float64, device=self.device)
@@ -323,6 +324,13 @@ class Context:
             _ptr(out["offsets"]), _ptr(out.get("pivot_rank")), _ptr(out.get("pivot_idx"))),
             "sample_partition_noalloc")
         return out
+
+    def calibrate_lds(self, workgroups: int, steps: int, batch: int):
+        """(milliseconds, 64-lane LDS reads) of the random-read probe."""
+        ms, n = C.c_double(), C.c_uint64()
+        self._check(lib().kd_calibrate_lds(self.handle, workgroups, steps, batch, C.byref(ms),
+                                           C.byref(n)), "kd_calibrate_lds")
+        return float(ms.value), int(n.value)
 
     # ---------------------------------------------------- globalized rank
     def kmer_rank_global(self, blocks: KmerSet, local_ranks, k: int, delta: float = 0.1, out=None):

@@ -25,7 +25,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
-SOURCES = ["kd_api.hip", "count.hip", "layout.hip", "pair.hip", "cross.hip", "tree.hip", "psp.hip", "partition.hip", "server.hip"]
+SOURCES = ["kd_api.hip", "count.hip", "layout.hip", "pair.hip", "cross.hip", "tree.hip", "psp.hip", "partition.hip", "server.hip", "probe.hip"]
 
 
 def _compile(src: str) -> str:

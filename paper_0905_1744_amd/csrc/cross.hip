@@ -38,12 +38,13 @@ __global__ __launch_bounds__(1024) void rank_cross_kernel(Segs cols, const SetVi
   for (uint32_t q = tid; q < (uint32_t)kLogEntries; q += 1024) log_table_entry((int)q, sh.logt[q]);
   if (tid == 0) sh.ln2 = log(2.0);
   clear_rows(sh.row);
+  const int fix = fix_bits(rv.N, delta);
 
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t ga = __builtin_amdgcn_readfirstlane(gperm[tk.gx0 + wave]);
   const uint32_t gb = gpt == 32u ? __builtin_amdgcn_readfirstlane(gperm[tk.gx0 + 31u - wave]) : kNone;
-#pragma unroll
-  for (int k = 0; k < 6; k++) (&sh.colacc[wave][0][0][0])[k * 64 + lane] = 0;
+  sh.colacc[wave][lane] = 0;
+  sh.colacc[31u - wave][lane] = 0;
 
   for (uint32_t rb = tk.rb0; rb < tk.rb1; rb++) {
     if (rb > tk.rb0) {
@@ -64,12 +65,12 @@ __global__ __launch_bounds__(1024) void rank_cross_kernel(Segs cols, const SetVi
     if (ga != kNone) {
       uint32_t gl;
       const uint32_t q = cross_set(cols, ga, gl);
-      rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, eid, ecnt, en, sh.colacc[wave][0]);
+      rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, fix, eid, ecnt, en, sh.colacc[wave]);
     }
     if (gb != kNone) {
       uint32_t gl;
       const uint32_t q = cross_set(cols, gb, gl);
-      rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, eid, ecnt, en, sh.colacc[wave][1]);
+      rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, fix, eid, ecnt, en, sh.colacc[31u - wave]);
     }
     __syncthreads();
   }
@@ -80,12 +81,9 @@ __global__ __launch_bounds__(1024) void rank_cross_kernel(Segs cols, const SetVi
     uint32_t gl;
     const SetView &v = cols.views[cross_set(cols, gx, gl)];
     const uint32_t sc = 64u * gl + lane;
-    if (sc < v.N) {
-      unsigned long long *acc = reinterpret_cast<unsigned long long *>(v.acc);
-#pragma unroll
-      for (int k = 0; k < 3; k++)
-        atomicAdd(acc + 3ull * sc + k, (unsigned long long)sh.colacc[wave][h][k][lane]);
-    }
+    if (sc < v.N)
+      atomicAdd(reinterpret_cast<unsigned long long *>(v.acc) + sc,
+                (unsigned long long)sh.colacc[h ? 31u - wave : wave][lane]);
   }
 }
 
@@ -101,22 +99,23 @@ hipError_t launch_rank_cross(hipStream_t st, const Segs &cols, const SetView *ro
 
 // Globalized rank = (sum over the S samples) / S for every sorted position
 // of every block, written at the input index; clears the accumulators.
-__global__ void cross_finalize_kernel(Segs sg, uint32_t N, uint32_t S, double *__restrict__ ranks) {
+__global__ void cross_finalize_kernel(Segs sg, uint32_t N, uint32_t S, double delta,
+                                      double *__restrict__ ranks) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
   const uint32_t set = sg.set_of_pos(p);
   const uint32_t a = sg.seq[set];
   const SetView &v = sg.views[set];
-  long long *acc = v.acc + 3ull * (p - a);
-  ranks[a + v.perm[p - a]] = fix_to_double(acc[0], acc[1], acc[2]) / (double)S;
-  acc[0] = acc[1] = acc[2] = 0;
+  long long *acc = v.acc + (p - a);
+  ranks[a + v.perm[p - a]] = fix_value(*acc, fix_bits(S, delta)) / (double)S;
+  *acc = 0;
 }
 
 hipError_t launch_cross_finalize(hipStream_t st, const Segs &sg, uint32_t N, uint32_t S,
-                                 double *ranks) {
+                                 double delta, double *ranks) {
   if (N == 0) return hipSuccess;
   hipLaunchKernelGGL(cross_finalize_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, S,
-                     ranks);
+                     delta, ranks);
   return hipGetLastError();
 }
 

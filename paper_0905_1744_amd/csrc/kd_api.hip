@@ -362,10 +362,11 @@ extern "C" void *kd_ctx_stream(kd_ctx *ctx) { return ctx ? (void *)ctx->stream :
 
 namespace {
 
-// Work list of the rank kernel for one set of N sequences: strips of 32
-// column groups (two per wave of a workgroup) against runs of `rbt` row
-// blocks; a row block rb only meets column groups g <= rb/4 (pairs below the
-// diagonal of the sorted order).  Strips with the longest lists first.
+// Plain work list of one set of N sequences: strips of 32 column groups
+// (two per wave of a workgroup) against runs of `rbt` row blocks; a row
+// block rb only meets column groups g <= rb/4 (pairs below the diagonal of
+// the sorted order).  Largest first.  (The distance-matrix pass, which has
+// no accumulators to flush, uses it with one row block per workgroup.)
 void make_tasks(uint32_t N, uint32_t set_index, uint32_t rbt, std::vector<PairTask> &out) {
   std::vector<PairTask> t;
   const uint32_t RB = (N + 15) / 16, G = (N + 63) / 64;
@@ -391,8 +392,6 @@ uint64_t task_tiles(const PairTask &t, uint32_t G) {
   return n;
 }
 
-// Rank work list of every set of a counted object; with several sets the
-// largest tasks go first (a single set keeps its own order).
 void build_task_list(const std::vector<SetView> &views, uint32_t rbt, std::vector<PairTask> &out) {
   out.clear();
   for (uint32_t q = 0; q < views.size(); q++) make_tasks(views[q].N, q, rbt, out);
@@ -408,6 +407,89 @@ void build_task_list(const std::vector<SetView> &views, uint32_t rbt, std::vecto
   }
 }
 
+// Cost model of the rank kernel, in units of one 32-word lookup step of a
+// wave: a tile (row block, column group) costs its group's padded list
+// length / 32 plus kTileCost (counts transpose, FP64 epilogue, flushes); a
+// row block of a strip costs the busiest wave's tiles (wave w holds groups
+// g0 + w and g0 + 31 - w) plus kRowBlockCost (table fill and clear, two
+// barriers).
+constexpr double kTileCost = 4.0;
+constexpr double kRowBlockCost = 6.0;
+
+// Rank work list of every set of a counted object.
+//  - The row blocks of all strips (32 column groups) of all sets, strip
+//    after strip, form one sequence of units with an estimated cost.  It is
+//    cut into 8 contiguous pieces of equal cost, one per XCD, so that the
+//    strips an XCD works on (their column lists) stay in its own L2.
+//  - Each piece is cut into about T / 8 runs of equal cost (T = tasks_per_cu
+//    x compute units), never across a strip: fewer, longer runs flush fewer
+//    column sums (one 64-bit atomic per column per workgroup), more runs
+//    balance better.
+//  - The pieces become the per-XCD queues of the persistent rank launch
+//    (out[beg[x] .. beg[x+1]), largest first); a workgroup takes from its
+//    own XCD's queue and steals from the others once it is empty.
+// grp_len: host copy of every column group's padded list length
+// (batch-wide numbering).
+void build_costed_tasks(const std::vector<SetView> &views, const std::vector<uint32_t> &grp_first,
+                        const std::vector<uint32_t> &grp_len, uint32_t tasks_per_cu, int cus,
+                        std::vector<PairTask> &out, uint32_t (&beg)[kXcdQueues + 1]) {
+  out.clear();
+  for (uint32_t x = 0; x <= kXcdQueues; x++) beg[x] = 0;
+  struct Unit { uint32_t set, g0, rb; double cost; };
+  std::vector<Unit> units;
+  double all = 0.0;
+  for (uint32_t q = 0; q < views.size(); q++) {
+    const uint32_t N = views[q].N, RB = (N + 15) / 16, G = (N + 63) / 64;
+    const uint32_t *L = grp_len.data() + grp_first[q];
+    for (uint32_t g0 = 0; g0 < G; g0 += kGroupsPerTask) {
+      double wave_cost[16] = {0.0};
+      double worst = 0.0;
+      for (uint32_t rb = 4u * g0; rb < RB; rb++) {
+        if ((rb & 3u) == 0) {  // group rb / 4 starts to meet the row blocks
+          const uint32_t g = rb >> 2;
+          if (g < G && g < g0 + kGroupsPerTask) {
+            const uint32_t j = g - g0, w = j < 16 ? j : 31u - j;
+            wave_cost[w] += L[g] / 32.0 + kTileCost;
+            worst = std::max(worst, wave_cost[w]);
+          }
+        }
+        units.push_back({q, g0, rb, worst + kRowBlockCost});
+        all += worst + kRowBlockCost;
+      }
+    }
+  }
+  if (units.empty()) return;
+  const double T = std::max<double>(kXcdQueues, (double)tasks_per_cu * (double)std::max(cus, 1));
+  const double per_task = all / T, per_xcd = all / kXcdQueues;
+  std::vector<std::vector<std::pair<double, PairTask>>> xq(kXcdQueues);
+  double cum = 0.0, tcost = 0.0;
+  size_t start = 0;
+  uint32_t xcd = 0;
+  for (size_t i = 0; i < units.size(); i++) {
+    const Unit &u = units[i];
+    tcost += u.cost;
+    cum += u.cost;
+    const bool last = i + 1 == units.size();
+    const bool strip_end = last || units[i + 1].set != u.set || units[i + 1].g0 != u.g0;
+    const uint32_t next_xcd = std::min<uint32_t>(kXcdQueues - 1, (uint32_t)(cum / per_xcd));
+    if (strip_end || tcost >= per_task || next_xcd != xcd) {
+      const Unit &f = units[start];
+      xq[xcd].push_back({tcost, PairTask{f.set, f.rb, u.rb + 1, f.g0}});
+      start = i + 1;
+      tcost = 0.0;
+      xcd = next_xcd;
+    }
+  }
+  for (uint32_t x = 0; x < kXcdQueues; x++) {
+    auto &q = xq[x];
+    std::stable_sort(q.begin(), q.end(), [](const std::pair<double, PairTask> &a,
+                                            const std::pair<double, PairTask> &b) { return a.first > b.first; });
+    beg[x] = (uint32_t)out.size();
+    for (const auto &t : q) out.push_back(t.second);
+  }
+  beg[kXcdQueues] = (uint32_t)out.size();
+}
+
 // size class of a counted object for the tuned work-list shape
 uint32_t shape_class(uint32_t nsets, uint32_t N) {
   uint32_t c = 0;
@@ -415,34 +497,12 @@ uint32_t shape_class(uint32_t nsets, uint32_t N) {
   return (nsets > 1 ? 32u : 0u) + c;
 }
 
-uint32_t rows_per_task(const kd_ctx *ctx, uint32_t nsets, uint32_t N) {
-  auto it = ctx->rbt_pref.find(shape_class(nsets, N));
-  return it != ctx->rbt_pref.end() ? it->second : kRowBlocksPerTask;
+uint32_t tasks_per_cu(const kd_ctx *ctx, uint32_t nsets, uint32_t N) {
+  auto it = ctx->tpc_pref.find(shape_class(nsets, N));
+  return it != ctx->tpc_pref.end() ? it->second : kTasksPerCu;
 }
 
-// The device work list of a single set of N sequences with `rbt` row
-// blocks per workgroup, built once per context and shape.
-kd_status cached_tasks(kd_ctx *ctx, uint32_t N, uint32_t rbt, PairTask **d, uint32_t *n) {
-  const auto key = std::make_pair(N, rbt);
-  auto it = ctx->task_cache.find(key);
-  if (it == ctx->task_cache.end()) {
-    std::vector<PairTask> tl;
-    std::vector<SetView> one(1);
-    one[0].N = N;
-    one[0].G = (N + 63) / 64;
-    build_task_list(one, rbt, tl);
-    PairTask *p = static_cast<PairTask *>(ctx->pool->alloc(sizeof(PairTask) * (tl.size() + 1)));
-    if (!p) return KD_ENOMEM;
-    if (upload(ctx, p, tl.data(), sizeof(PairTask) * tl.size()) != hipSuccess) {
-      ctx->pool->free(p);
-      return KD_EDEVICE;
-    }
-    it = ctx->task_cache.emplace(key, std::make_pair(p, (uint32_t)tl.size())).first;
-  }
-  *d = it->second.first;
-  *n = it->second.second;
-  return KD_OK;
-}
+void *readback_area(kd_ctx *ctx, size_t bytes);
 
 // Counts every set of a batch (set s = sequences first[s] .. first[s+1]-1
 // of the input) and lays all of them out in one pass of each kernel.  With
@@ -507,7 +567,8 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint32_t *ghi_len = set_alloc<uint32_t>(s, G);
   uint32_t *exc_off = set_alloc<uint32_t>(s, RB + 1);
   uint32_t *exc_n = set_alloc<uint32_t>(s, RB);
-  long long *acc = set_alloc<long long>(s, 3ull * N);
+  long long *acc = set_alloc<long long>(s, N);
+  uint32_t *qhead = set_alloc<uint32_t>(s, kXcdQueues);
   uint32_t *segb = set_alloc<uint32_t>(s, 3ull * (nsets + 1));
   uint32_t *segid = nsets > 1 ? set_alloc<uint32_t>(s, (uint64_t)N + G + RB) : nullptr;
 
@@ -525,7 +586,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   LayoutMeta *meta = reinterpret_cast<LayoutMeta *>(small + 8);
   void *meta_tmp = tmp.get<char>(layout_meta_scratch_bytes(N, G, RB));
   if (!in_off || !cap_ids || !cap_cnt || !hi_cap || !Dorig || !perm || !inv || !K || !D || !invK || !hi_off || !hcount ||
-      !grp_off || !grp_len || !ghi_off || !ghi_len || !exc_off || !exc_n || !acc || !segb || (nsets > 1 && !segid) ||
+      !grp_off || !grp_len || !ghi_off || !ghi_len || !exc_off || !exc_n || !acc || !qhead || !segb || (nsets > 1 && !segid) ||
       !Korig || !nhi_orig || !long_list || !mid_list || !sort_tmp || !small || !meta || !meta_tmp) {
     set_free(s);
     return KD_ENOMEM;
@@ -552,8 +613,9 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     FillJobs f{};
     f.j[0] = {small, 1, ~0ull};
     f.j[1] = {small + 1, 7 + (sizeof(LayoutMeta) + 7) / 8, 0ull};
-    f.j[2] = {reinterpret_cast<unsigned long long *>(acc), 3ull * N, 0ull};  // rank accumulators
-    f.n = 3;
+    f.j[2] = {reinterpret_cast<unsigned long long *>(acc), (uint64_t)N, 0ull};  // rank accumulators
+    f.j[3] = {reinterpret_cast<unsigned long long *>(qhead), kXcdQueues / 2, 0ull};  // rank queues
+    f.n = 4;
     e = launch_fills(st, f);
   }
   StageTimer t_count(ctx, KD_STAGE_COUNT);
@@ -570,23 +632,19 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     e = launch_layout_meta(st, sg, N, G, RB, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hcount,
                            hi_off, grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta, meta_tmp);
   t_layout.done();
-  // the rank work list depends only on the set sizes: prepare it while the
-  // device counts (a single set's comes from the context's cache)
-  const uint32_t rbt = rows_per_task(ctx, nsets, N);
-  if (parent) {
-    s->ntasks = 0;
-  } else if (e == hipSuccess && nsets == 1) {
-    const kd_status rc = cached_tasks(ctx, N, rbt, &s->tasks, &s->ntasks);
-    if (rc != KD_OK) {
+  // the padded list lengths come back with the totals: the rank work list
+  // is cut by their estimated cost
+  LayoutMeta *hm = static_cast<LayoutMeta *>(ctx->pinned);
+  uint32_t *h_len = nullptr;
+  if (!parent && G > 0) {
+    h_len = static_cast<uint32_t *>(readback_area(ctx, 4ull * G));
+    if (!h_len) {
       (void)hipStreamSynchronize(st);
       set_free(s);
-      return rc;
+      return KD_ENOMEM;
     }
-  } else {
-    build_task_list(s->views, rbt, s->h_tasks);
-    s->ntasks = (uint32_t)s->h_tasks.size();
+    if (e == hipSuccess) e = hipMemcpyAsync(h_len, grp_len, 4ull * G, hipMemcpyDeviceToHost, st);
   }
-  LayoutMeta *hm = static_cast<LayoutMeta *>(ctx->pinned);
   if (e == hipSuccess) e = hipMemcpyAsync(hm, meta, sizeof(LayoutMeta), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
@@ -601,6 +659,12 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     set_free(s);
     return map_err(code);
   }
+  if (!parent) {
+    s->h_grp_len.assign(h_len, h_len + G);
+    build_costed_tasks(s->views, s->grp_first, s->h_grp_len, tasks_per_cu(ctx, nsets, N), ctx->cus,
+                       s->h_tasks, s->queues.beg);
+  }
+  s->ntasks = (uint32_t)s->h_tasks.size();
   s->entries = hm->entries;
   s->cap = cap;
   s->n_hi = hm->n_hi;
@@ -614,7 +678,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint32_t *ghi = set_alloc<uint32_t>(s, hm->n_ghi + 2);
   // per-set views, then (batches) the rank work list: one upload
   const size_t view_bytes = (sizeof(SetView) * nsets + 255) & ~(size_t)255;
-  const size_t task_bytes = nsets > 1 ? sizeof(PairTask) * (size_t)(s->ntasks + 1) : 0;
+  const size_t task_bytes = sizeof(PairTask) * (size_t)(s->ntasks + 1);
   char *vt = set_alloc<char>(s, view_bytes + task_bytes);
   if (!gids || !hi_ids || !hi_cnt || !exc_ids || !exc_cnt || !ghi || !vt) {
     set_free(s);
@@ -640,6 +704,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   v.exc_ids = exc_ids;
   v.exc_cnt = exc_cnt;
   v.acc = acc;
+  s->queues.head = qhead;
   for (uint32_t q = 0; q < nsets; q++) {
     SetView &w = s->views[q];
     const uint32_t a = first[q], ga = s->grp_first[q], ra = s->rb_first[q];
@@ -661,7 +726,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     w.exc_n = exc_n + ra;
     w.exc_ids = exc_ids;
     w.exc_cnt = exc_cnt;
-    w.acc = acc + 3ull * a;
+    w.acc = acc + a;
   }
   s->cap_ids = cap_ids;
   s->cap_cnt = cap_cnt;
@@ -670,13 +735,13 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   SetView *d_view = reinterpret_cast<SetView *>(vt);
   s->d_view = d_view;
   sg.views = d_view;
-  if (nsets > 1) s->tasks = reinterpret_cast<PairTask *>(vt + view_bytes);
+  s->tasks = reinterpret_cast<PairTask *>(vt + view_bytes);
   StageTimer t_fill(ctx, KD_STAGE_LAYOUT);
   {
-    const size_t used = nsets > 1 ? view_bytes + sizeof(PairTask) * s->ntasks : sizeof(SetView);
+    const size_t used = view_bytes + sizeof(PairTask) * s->ntasks;
     std::vector<char> hv(used);
     std::memcpy(hv.data(), s->views.data(), sizeof(SetView) * nsets);
-    if (nsets > 1) std::memcpy(hv.data() + view_bytes, s->h_tasks.data(), sizeof(PairTask) * s->ntasks);
+    if (s->ntasks) std::memcpy(hv.data() + view_bytes, s->h_tasks.data(), sizeof(PairTask) * s->ntasks);
     e = upload(ctx, vt, hv.data(), hv.size());
   }
   if (e == hipSuccess) {
@@ -809,15 +874,16 @@ extern "C" kd_status kmer_rank(kd_ctx *ctx, const kd_set *s, double delta, doubl
   // every finalize; a rank call that failed half-way leaves them dirty
   if (!s->acc_clean) {
     StageTimer t0(ctx, KD_STAGE_FINALIZE);
-    KD_TRY(launch_fill_u64(st, s->v.acc, 3ull * s->v.N, 0));
+    KD_TRY(launch_fill_u64(st, s->v.acc, s->v.N, 0));
+    KD_TRY(launch_fill_u64(st, s->queues.head, kXcdQueues / 2, 0));
     t0.done();
   }
   s->acc_clean = false;
   StageTimer t1(ctx, KD_STAGE_PAIRS);
-  KD_TRY(launch_rank_pairs(st, s->d_view, s->tasks, s->ntasks, delta));
+  KD_TRY(launch_rank_pairs(st, s->d_view, s->tasks, s->ntasks, s->queues, (uint32_t)ctx->cus, delta));
   t1.done();
   StageTimer t2(ctx, KD_STAGE_FINALIZE);
-  KD_TRY(launch_rank_finalize(st, s->segs, s->v.N, delta, ranks));
+  KD_TRY(launch_rank_finalize(st, s->segs, s->v.N, delta, ranks, s->queues.head));
   t2.done();
   s->acc_clean = true;
   return KD_OK;
@@ -920,7 +986,7 @@ extern "C" kd_status kmer_rank_global(kd_ctx *ctx, const kd_set *s, const double
     std::memcpy(hw.data() + tbytes, gperm.data(), sizeof(uint32_t) * gperm.size());
     e = upload(ctx, d_work, hw.data(), hw.size());
   }
-  if (e == hipSuccess && !s->acc_clean) e = launch_fill_u64(st, s->v.acc, 3ull * N, 0);
+  if (e == hipSuccess && !s->acc_clean) e = launch_fill_u64(st, s->v.acc, N, 0);
   s->acc_clean = false;
   StageTimer t_cross(ctx, KD_STAGE_GLOBAL);
   if (e == hipSuccess)
@@ -928,7 +994,7 @@ extern "C" kd_status kmer_rank_global(kd_ctx *ctx, const kd_set *s, const double
                           delta);
   t_cross.done();
   StageTimer t_fin(ctx, KD_STAGE_FINALIZE);
-  if (e == hipSuccess) e = launch_cross_finalize(st, s->segs, N, S, ranks);
+  if (e == hipSuccess) e = launch_cross_finalize(st, s->segs, N, S, delta, ranks);
   t_fin.done();
   if (e == hipSuccess) s->acc_clean = true;
   kd_set_destroy(ss);  // its blocks return to the pool; stream order keeps them valid
@@ -1149,7 +1215,7 @@ extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t 
   if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
   static const uint32_t cand[KD_TUNE_CANDIDATES] = {1, 2, 4, 8, 16};
   const uint32_t N = s->v.N;
-  if (N == 0) return KD_EINVAL;
+  if (N == 0 || s->h_grp_len.size() != s->v.G) return KD_EINVAL;
   KD_TRY(hipSetDevice(ctx->device));
   const hipStream_t st = ctx->stream;
   Scope tmp(ctx);
@@ -1164,11 +1230,11 @@ extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t 
   std::vector<double> ref(N), got(N);
   kd_status rc = KD_OK;
   double best_ms = 1e300;
-  uint32_t best_rbt = kRowBlocksPerTask;
+  uint32_t best_tpc = kTasksPerCu;
   for (int c = 0; c < KD_TUNE_CANDIDATES && rc == KD_OK; c++) {
     // this candidate's work list, in a block of its own
     std::vector<PairTask> tl;
-    build_task_list(s->views, cand[c], tl);
+    build_costed_tasks(s->views, s->grp_first, s->h_grp_len, cand[c], ctx->cus, tl, s->queues.beg);
     PairTask *d = set_alloc<PairTask>(s, tl.size() + 1);
     if (!d) {
       rc = KD_ENOMEM;
@@ -1204,35 +1270,29 @@ extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t 
     }
     if (avg < best_ms) {
       best_ms = avg;
-      best_rbt = cand[c];
+      best_tpc = cand[c];
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != KD_OK) return rc;
-  ctx->rbt_pref[shape_class(s->nsets, N)] = best_rbt;
+  ctx->tpc_pref[shape_class(s->nsets, N)] = best_tpc;
   // the set keeps the winner's work list
-  if (s->nsets == 1) {
-    rc = cached_tasks(ctx, N, best_rbt, &s->tasks, &s->ntasks);
-    if (rc != KD_OK) return rc;
-  } else {
-    std::vector<PairTask> tl;
-    build_task_list(s->views, best_rbt, tl);
-    PairTask *d = set_alloc<PairTask>(s, tl.size() + 1);
-    if (!d) return KD_ENOMEM;
-    KD_TRY(upload(ctx, d, tl.data(), sizeof(PairTask) * tl.size()));
-    s->tasks = d;
-    s->ntasks = (uint32_t)tl.size();
-    s->h_tasks.swap(tl);
-  }
-  if (best) *best = best_rbt;
+  std::vector<PairTask> tl;
+  build_costed_tasks(s->views, s->grp_first, s->h_grp_len, best_tpc, ctx->cus, tl, s->queues.beg);
+  PairTask *d = set_alloc<PairTask>(s, tl.size() + 1);
+  if (!d) return KD_ENOMEM;
+  KD_TRY(upload(ctx, d, tl.data(), sizeof(PairTask) * tl.size()));
+  s->tasks = d;
+  s->ntasks = (uint32_t)tl.size();
+  s->h_tasks.swap(tl);
+  if (best) *best = best_tpc;
   return KD_OK;
 }
 
-extern "C" kd_status kd_ctx_set_rows_per_task(kd_ctx *ctx, uint32_t nsets, uint32_t n,
-                                              uint32_t rows) {
-  if (!ctx || rows == 0 || rows > 4096) return KD_EINVAL;
-  ctx->rbt_pref[shape_class(nsets, n)] = rows;
+extern "C" kd_status kd_ctx_set_tasks_per_cu(kd_ctx *ctx, uint32_t nsets, uint32_t n, uint32_t tasks) {
+  if (!ctx || tasks == 0 || tasks > 4096) return KD_EINVAL;
+  ctx->tpc_pref[shape_class(nsets, n)] = tasks;
   return KD_OK;
 }
 
@@ -1350,4 +1410,35 @@ extern "C" kd_status kd_batch_run(kd_ctx *ctx, const uint8_t *residues, const ui
                                 nullptr, nullptr);
   kd_set_destroy(s);  // its blocks return to the pool; stream order keeps them valid
   return rc;
+}
+
+// ---------------------------------------------------------- calibration
+
+extern "C" kd_status kd_calibrate_lds(kd_ctx *ctx, uint32_t workgroups, uint32_t steps,
+                                      uint32_t batch, double *ms, uint64_t *wave_reads) {
+  if (!ctx || !ms || !wave_reads || workgroups == 0 || steps == 0) return KD_EINVAL;
+  if (batch != 2 && batch != 8 && batch != 32) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  Scope tmp(ctx);
+  uint32_t *sink = tmp.get<uint32_t>(1024ull * workgroups);
+  if (!sink) return KD_ENOMEM;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess) return KD_EDEVICE;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return KD_EDEVICE;
+  }
+  kd_status rc = KD_OK;
+  float t = 0.f;
+  if (hipEventRecord(a, ctx->stream) != hipSuccess ||
+      launch_lds_probe(ctx->stream, workgroups, steps, batch, sink) != hipSuccess ||
+      hipEventRecord(b, ctx->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+      hipEventElapsedTime(&t, a, b) != hipSuccess)
+    rc = KD_EDEVICE;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc != KD_OK) return rc;
+  *ms = t;
+  *wave_reads = 16ull * workgroups * steps * 32ull;  // 16 waves per workgroup
+  return KD_OK;
 }

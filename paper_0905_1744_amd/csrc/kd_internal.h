@@ -25,7 +25,6 @@ constexpr int kBitmapWords = 1458;    // 46656 bits
 constexpr int kRowsPerBlock = 16;     // rows sharing one LDS presence table
 constexpr int kGroup = 64;            // columns per interleaved group (one per lane)
 constexpr int kShortMax = 4096;       // words per sequence handled by the one-wave counter
-constexpr int kFixFrac = 72;          // fractional bits of the exact rank accumulator
 constexpr uint32_t kMaxBuckets = 1024; // sample_partition: B(B-1) samples stay small
 
 // error word written by the counting kernels: (seq << 32) | (code << 28) | pos
@@ -69,7 +68,7 @@ struct SetView {
   const uint32_t *exc_n;       // [RB] used entries in the block's range
   const uint16_t *exc_ids;     // [cap] sorted words
   const uint16_t *exc_cnt;     // [cap*16] count of the word in each of the 16 rows
-  long long *acc;              // [3*N] exact rank accumulators (40-bit limbs)
+  long long *acc;              // [N] exact rank accumulators (fixed point, fix_bits)
 };
 
 // Batch-wide numbering: set s holds sequences seq[s] .. seq[s+1]-1, column
@@ -96,12 +95,19 @@ struct PairTask {     // one workgroup's work in the rank kernel
   uint32_t g0;        // column groups g0 .. g0+15, one per wave
 };
 constexpr uint32_t kGroupsPerTask = 32;  // two column groups per wave
+// Per-XCD queues of a rank work list: queue x is tasks[beg[x] .. beg[x+1]),
+// head[x] counts the tasks taken from it (zero before every launch).
+constexpr uint32_t kXcdQueues = 8;
+struct TaskQueues {
+  uint32_t beg[kXcdQueues + 1];
+  uint32_t *head;  // device [kXcdQueues]
+};
 struct CrossTask {    // one workgroup's work in the globalized-rank pass
   uint32_t gx0;       // its column groups are gperm[gx0 .. gx0+gpt-1], gpt = 16 or
                       // 32 (batch-wide numbering, 0xFFFFFFFF = none)
   uint32_t rb0, rb1;  // row blocks [rb0, rb1) of the sample set
 };
-constexpr uint32_t kRowBlocksPerTask = 4;  // default run of row blocks per workgroup
+constexpr uint32_t kTasksPerCu = 4;  // default rank workgroups per compute unit (kd_autotune)
 constexpr size_t kGidsSlack = 16384;  // sentinel words after the last group (read-ahead)
 
 // ---------------------------------------------------------- host objects
@@ -132,11 +138,8 @@ struct kd_ctx {
   void *pinned = nullptr;         // small pinned readback area
   void *readback = nullptr;       // growable pinned readback area (read after a sync)
   size_t readback_cap = 0;
-  // tuned row blocks per rank workgroup, by size class (kd_autotune)
-  std::map<uint32_t, uint32_t> rbt_pref;
-  // rank work lists of single sets, keyed by (N, row blocks per workgroup):
-  // they hold no pointers, so sets of the same size share one device copy
-  std::map<std::pair<uint32_t, uint32_t>, std::pair<kd::PairTask *, uint32_t>> task_cache;
+  // tuned rank workgroups per compute unit, by size class (kd_autotune)
+  std::map<uint32_t, uint32_t> tpc_pref;
   // pinned upload buffers: host data is staged here and copied on the
   // context's stream; a buffer is reused once its copy's event completed
   struct Staged { void *p; size_t cap; hipEvent_t ev; bool used; };
@@ -161,6 +164,8 @@ struct kd_set {
   kd::PairTask *tasks = nullptr;  // rank work list of all sets (device)
   uint32_t ntasks = 0;
   std::vector<kd::PairTask> h_tasks;
+  kd::TaskQueues queues{};  // per-XCD queues over tasks (head: device, in the set's blocks)
+  std::vector<uint32_t> h_grp_len;  // padded list length of every column group (host copy)
   mutable bool acc_clean = true;  // rank accumulators are zero (kmer_rank keeps them so)
   uint64_t entries = 0;   // sum of D
   uint64_t cap = 0;       // sum of K
@@ -234,15 +239,16 @@ hipError_t launch_exc_build(hipStream_t st, const Segs &sg, uint32_t nblocks,
                             uint16_t *exc_ids, uint16_t *exc_cnt);
 
 hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairTask *tasks,
-                             uint32_t ntasks, double delta);
+                             uint32_t ntasks, const TaskQueues &q, uint32_t workgroups, double delta);
+// also clears the queue heads of the rank launch before it
 hipError_t launch_rank_finalize(hipStream_t st, const Segs &sg, uint32_t N, double delta,
-                                double *ranks);
+                                double *ranks, uint32_t *qhead);
 // globalized rank: sample rows against every column group of `cols`
 hipError_t launch_rank_cross(hipStream_t st, const Segs &cols, const SetView *rows,
                              const CrossTask *tasks, uint32_t ntasks, const uint32_t *gperm,
                              uint32_t gpt, double delta);
 hipError_t launch_cross_finalize(hipStream_t st, const Segs &sg, uint32_t N, uint32_t S,
-                                 double *ranks);
+                                 double delta, double *ranks);
 // host: the cross pass's work list and column-group permutation from the
 // groups' padded list lengths; returns the groups per task (16 or 32)
 uint32_t make_cross_tasks(const uint32_t *grp_len, uint32_t Gtot, uint32_t RBs, int cus,
@@ -301,6 +307,9 @@ hipError_t launch_psp_profile(hipStream_t st, const uint8_t *aln, uint32_t m, ui
 bool psp_plan(std::vector<PspWork> &w, uint64_t &gblks, uint64_t &tiles);
 hipError_t launch_psp_scores(hipStream_t st, const PspWork *w, uint32_t npairs, uint32_t gblks,
                              uint32_t tiles, const double *M);
+// calibration: steps x 32 random 16-bit LDS reads per lane, `batch` at a time
+hipError_t launch_lds_probe(hipStream_t st, uint32_t workgroups, uint32_t steps, uint32_t batch,
+                            uint32_t *sink);
 hipError_t launch_fill_u64(hipStream_t st, void *p, uint64_t n_words, uint64_t value);
 // writes the set ids of sg.pos_set / grp_set / rb_set (nsets > 1)
 hipError_t launch_seg_ids(hipStream_t st, const Segs &sg, uint32_t *pos_set, uint32_t *grp_set,
@@ -367,35 +376,22 @@ __host__ __device__ constexpr uint8_t dayhoff6(uint32_t ch) {
   }
 }
 
-// Split trunc(v * 2^72) (two's complement, |v| < 2^47) into 40-bit limbs
-// l0, l1 >= 0 and signed l2 with value = l0 + l1*2^40 + l2*2^80.  Sums of
-// limbs are exact integer sums, so accumulating them is order independent.
-__device__ inline void fix_limbs(double v, long long &l0, long long &l1, long long &l2) {
-  unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-  unsigned e = (unsigned)((bits >> 52) & 0x7ff);
-  if (e == 0) { l0 = l1 = l2 = 0; return; }
-  unsigned long long m = (bits & ((1ull << 52) - 1)) | (1ull << 52);
-  int sh = (int)e - 1075 + kFixFrac;
-  unsigned __int128 T;
-  if (sh >= 0) T = (unsigned __int128)m << sh;
-  else if (sh > -64) T = (unsigned __int128)(m >> (-sh));
-  else T = 0;
-  __int128 S = (bits >> 63) ? -(__int128)T : (__int128)T;
-  l0 = (long long)(S & (__int128)0xFFFFFFFFFFll);
-  l1 = (long long)((S >> 40) & (__int128)0xFFFFFFFFFFll);
-  l2 = (long long)(S >> 80);
+// Rank accumulators.  Every tile's FP64 row and column sums are rounded to
+// integer multiples of 2^-F and added as 64-bit integers, so a total does
+// not depend on the order of its additions (scheduling, tiling, batching).
+// F is the largest value with n * dmax * 2^F < 2^62, n the number of terms
+// of a rank sum and dmax = max(|ln delta|, ln(1 + delta)) >= |d| for every
+// d = -ln(delta + F_xy) with 0 <= F_xy <= 1 (Equation 2), so neither a tile
+// sum nor any partial total can overflow.  Every kernel that touches an
+// accumulator derives F with this same function.
+__device__ inline int fix_bits(uint32_t n, double delta) {
+  const double dmax = fmax(fabs(log(delta)), log1p(delta));
+  return 61 - ilogb((double)n * dmax);
 }
 
-__device__ inline double fix_to_double(long long s0, long long s1, long long s2) {
-  __int128 T = ((__int128)s2 << 80) + ((__int128)s1 << 40) + (__int128)s0;
-  bool neg = T < 0;
-  unsigned __int128 M = neg ? (unsigned __int128)(-T) : (unsigned __int128)T;
-  double hi = (double)(unsigned long long)(M >> 64);
-  double lo = (double)(unsigned long long)M;
-  double r = hi * 0x1p64 + lo;
-  r *= 0x1p-72;
-  return neg ? -r : r;
-}
+__device__ inline long long fix_q(double v, int F) { return (long long)rint(ldexp(v, F)); }
+
+__device__ inline double fix_value(long long s, int F) { return ldexp((double)s, -F); }
 
 __device__ inline unsigned long long lanemask_lt() {
   return (1ull << __lane_id()) - 1ull;

@@ -24,47 +24,43 @@
 // Ranks.  For each pair the fused epilogue forms F = shared / (min(n,m) - 5)
 // (Equation 1) and d = -ln(delta + F) (Equation 2) in FP64; the 16x64 tile
 // reduces d per row (fixed butterfly) and per column (fixed row order) and
-// adds the partial sums to the rows' and columns' accumulators as exact
-// 120-bit fixed-point integers (three 40-bit limbs).  Integer addition is
-// associative, so R_i (Equation 3) is independent of tiling, scheduling and
-// co-running work.  Each unordered pair is computed once (column position
+// adds the partial sums to the rows' and columns' accumulators as 64-bit
+// fixed-point integers (fix_bits).  Integer addition is associative, so R_i
+// (Equation 3) is independent of tiling, scheduling and co-running work.  Each unordered pair is computed once (column position
 // below row position in the sorted order), and the j = i term is added by
 // the finalize kernel.
 #include "tile.h"
 
 namespace kd {
 
-// One workgroup = 16 waves x 2 = 32 consecutive column groups g0..g0+31
-// (wave w takes g0 + w and g0 + 31 - w: lists grow with g, so every wave
-// gets about the same total length) against row blocks rb0..rb1-1, one
-// row block at a time.  Row partials of a row block meet in LDS (exact
-// integer adds) and go to HBM once; column partials stay in registers
-// across the row blocks and go to HBM once at the end.
-__global__ __launch_bounds__(1024) void rank_pairs_kernel(const SetView *__restrict__ views,
-                                                          const PairTask *__restrict__ tasks,
-                                                          double delta) {
-  __shared__ RankShared sh;
-  const PairTask tk = tasks[blockIdx.x];
-  const SetView v = views[tk.set];
+// One task = 16 waves x 2 = 32 consecutive column groups g0..g0+31 (wave w
+// takes g0 + w and g0 + 31 - w: lists grow with g, so every wave gets about
+// the same total length) against row blocks rb0..rb1-1, one row block at a
+// time.  Row partials of a row block meet in LDS (exact integer adds) and
+// go to HBM once; column partials stay in LDS across the row blocks and go
+// to HBM once at the end of the task.  On entry the table is empty; on
+// exit it is empty again.
+__device__ __forceinline__ void run_pair_task(const SetView &v, const PairTask &tk, RankShared &sh,
+                                              double delta) {
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  for (uint32_t q = tid; q < (uint32_t)kLogEntries; q += 1024) log_table_entry((int)q, sh.logt[q]);
-  if (tid == 0) sh.ln2 = log(2.0);
-  if (tid < 48) sh.racc[tid] = 0;
-  clear_rows(sh.row);
-
-  const uint32_t ga = tk.g0 + wave, gb = tk.g0 + 31u - wave;
-#pragma unroll
-  for (int k = 0; k < 6; k++) (&sh.colacc[wave][0][0][0])[k * 64 + lane] = 0;
+  const int fix = fix_bits(v.N, delta);
+  const uint32_t ja = wave, jb = 31u - wave;  // the wave's groups in the strip
+  const uint32_t ga = tk.g0 + ja, gb = tk.g0 + jb;
+  if (tid < 16) sh.racc[tid] = 0;
+  sh.colacc[ja][lane] = 0;
+  sh.colacc[jb][lane] = 0;
+  // lists of the first group: a strip whose row blocks meet few groups only
+  // splits them over several waves when each slice keeps >= kSplitMinWords
+  const uint32_t Lfirst = __builtin_amdgcn_readfirstlane(v.grp_len[tk.g0]);
 
   for (uint32_t rb = tk.rb0; rb < tk.rb1; rb++) {
     if (rb > tk.rb0) {
       // previous row block: flush its row sums, then remove it from the table
       const uint32_t pr = rb - 1;
-      if (tid < 48) {
-        const uint32_t s = 16u * pr + tid / 3u;
-        if (s < v.N)
-          atomicAdd(reinterpret_cast<unsigned long long *>(v.acc) + 3ull * s + tid % 3u, sh.racc[tid]);
+      if (tid < 16) {
+        const uint32_t s = 16u * pr + tid;
+        if (s < v.N) atomicAdd(reinterpret_cast<unsigned long long *>(v.acc) + s, sh.racc[tid]);
         sh.racc[tid] = 0;
       }
       touch_rows<false>(v, ConsecutiveRows{16u * pr, v.N}, v.exc_ids, v.exc_off[pr], v.exc_n[pr], sh.row);
@@ -80,58 +76,144 @@ __global__ __launch_bounds__(1024) void rank_pairs_kernel(const SetView *__restr
     __syncthreads();
     const uint16_t *eid = lds_exc ? sh.exc_id : v.exc_ids + e0;
     const uint16_t *ecnt = lds_exc ? sh.exc_c : v.exc_cnt + 16ull * e0;
-    // a tile has pairs below the diagonal only when rb >= 4 g
-    if (ga < v.G && rb >= 4u * ga)
-      rank_tile<false>(v, sh, rb, ga, v.N, delta, eid, ecnt, en, sh.colacc[wave][0]);
-    if (gb < v.G && rb >= 4u * gb)
-      rank_tile<false>(v, sh, rb, gb, v.N, delta, eid, ecnt, en, sh.colacc[wave][1]);
+    // a tile has pairs below the diagonal only when rb >= 4 g: the strip's
+    // groups g0 .. g0 + nact - 1 meet this row block
+    const uint32_t glast = min(min(tk.g0 + 31u, v.G - 1u), rb >> 2);
+    const uint32_t nact = glast + 1u - tk.g0;  // tasks start at rb >= 4 g0
+    // Few groups: k waves per group, each counting a 16-word-aligned slice
+    // of the group's lists; the counts meet in LDS and the group's first
+    // wave finishes the tile with the same arithmetic as a whole tile.
+    // Otherwise every wave takes its two groups whole.
+    const uint32_t kmax = nact <= 16u ? 16u / nact : 1u;
+    const uint32_t k = min(kmax, max(1u, Lfirst / kSplitMinWords));
+    const bool split = k > 1u;
+    const uint32_t part = wave % k;
+#pragma nounroll
+    for (uint32_t it = 0; it < (split ? 1u : 2u); it++) {
+      const uint32_t j = split ? wave / k : (it ? jb : ja);
+      const uint32_t g = tk.g0 + j;
+      const bool has = split ? j < nact : (g < v.G && rb >= 4u * g);
+      const bool owner = has && part == 0;
+      uint32_t cnt[16];
+      TileCol tc;
+      if (owner) tc = tile_col(v, g);
+      if (has) {
+        const uint32_t Lq = __builtin_amdgcn_readfirstlane(v.grp_len[g]) >> 4;
+        const uint32_t a = 16u * (part * Lq / k), b = 16u * ((part + 1u) * Lq / k);
+        if (b > a) {
+          slice_counts(v, sh, g, a, b - a, cnt);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; r++) cnt[r] = 0u;
+        }
+        if (!owner) {
+#pragma unroll
+          for (int r = 0; r < 16; r++) sh.xcnt[wave][r][lane] = (uint16_t)cnt[r];
+        }
+      }
+      if (split) {
+        __syncthreads();
+        if (owner) {
+          for (uint32_t q = 1; q < k; q++) {
+#pragma unroll
+            for (int r = 0; r < 16; r++) cnt[r] += sh.xcnt[wave + q][r][lane];
+          }
+        }
+      }
+      if (owner) tile_finish<false>(v, sh, rb, g, v.N, delta, fix, eid, ecnt, en, tc, cnt, sh.colacc[j]);
+    }
     __syncthreads();
   }
-  if (tid < 48) {
-    const uint32_t s = 16u * (tk.rb1 - 1) + tid / 3u;
-    if (s < v.N)
-      atomicAdd(reinterpret_cast<unsigned long long *>(v.acc) + 3ull * s + tid % 3u, sh.racc[tid]);
-  }
+  // last row block: row sums out, rows out of the table; column sums out
+  const uint32_t pr = tk.rb1 - 1;
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(v.acc);
+  if (tid < 16) {
+    const uint32_t s = 16u * pr + tid;
+    if (s < v.N) atomicAdd(acc + s, sh.racc[tid]);
+  }
+  touch_rows<false>(v, ConsecutiveRows{16u * pr, v.N}, v.exc_ids, v.exc_off[pr], v.exc_n[pr], sh.row);
 #pragma unroll
   for (uint32_t gi = 0; gi < 2; gi++) {
     const uint32_t g = gi ? gb : ga, sc = 64u * g + lane;
-    if (g < v.G && sc < v.N && tk.rb1 > 4u * g) {
-#pragma unroll
-      for (int k = 0; k < 3; k++)
-        atomicAdd(acc + 3ull * sc + k, (unsigned long long)sh.colacc[wave][gi][k][lane]);
-    }
+    if (g < v.G && sc < v.N && tk.rb1 > 4u * g)
+      atomicAdd(acc + sc, (unsigned long long)sh.colacc[gi ? jb : ja][lane]);
+  }
+  __syncthreads();
+}
+
+// Next task for a workgroup on XCD `home`: from its own XCD's queue while it
+// lasts, then from the others in turn; kNoTask when all are empty.
+constexpr uint32_t kNoTask = 0xFFFFFFFFu;
+__device__ __forceinline__ uint32_t take_task(const TaskQueues &q, uint32_t home, uint32_t &empty) {
+  for (uint32_t i = 0; i < kXcdQueues; i++) {
+    const uint32_t x = (home + i) % kXcdQueues;
+    if ((empty >> x) & 1u) continue;
+    const uint32_t n = q.beg[x + 1] - q.beg[x];
+    const uint32_t t = n ? atomicAdd(q.head + x, 1u) : n;
+    if (t < n) return q.beg[x] + t;
+    empty |= 1u << x;
+  }
+  return kNoTask;
+}
+
+// Persistent launch: one workgroup per compute unit; each takes tasks from
+// the queue of the XCD it runs on (hardware register XCC_ID), so the strips
+// an XCD works on keep their column lists in its L2, and steals from the
+// other queues when its own is empty.  Every task is taken exactly once
+// (one atomic per take); a workgroup exits when all queues are empty.
+__global__ __launch_bounds__(1024) void rank_pairs_kernel(const SetView *__restrict__ views,
+                                                          const PairTask *__restrict__ tasks,
+                                                          TaskQueues q, double delta) {
+  __shared__ RankShared sh;
+  __shared__ uint32_t s_task;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t x = tid; x < (uint32_t)kLogEntries; x += 1024) log_table_entry((int)x, sh.logt[x]);
+  if (tid == 0) sh.ln2 = log(2.0);
+  clear_rows(sh.row);
+  // XCC_ID: bits 3:0 of hardware register 20
+  const uint32_t home = (uint32_t)__builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11)) % kXcdQueues;
+  uint32_t empty = 0;
+  for (;;) {
+    if (tid == 0) s_task = take_task(q, home, empty);
+    __syncthreads();
+    const uint32_t t = s_task;
+    __syncthreads();
+    if (t == kNoTask) break;
+    const PairTask tk = tasks[t];
+    run_pair_task(views[tk.set], tk, sh, delta);
   }
 }
 
 hipError_t launch_rank_pairs(hipStream_t st, const SetView *d_views, const PairTask *tasks,
-                             uint32_t ntasks, double delta) {
+                             uint32_t ntasks, const TaskQueues &q, uint32_t workgroups, double delta) {
   if (ntasks == 0) return hipSuccess;
-  hipLaunchKernelGGL(rank_pairs_kernel, dim3(ntasks), dim3(1024), 0, st, d_views, tasks, delta);
+  hipLaunchKernelGGL(rank_pairs_kernel, dim3(min(workgroups, ntasks)), dim3(1024), 0, st, d_views,
+                     tasks, q, delta);
   return hipGetLastError();
 }
 
 // R = (sum of the pair terms + the j = i term) / N for every sorted
 // position of every set; written at the sequence's input index.
-__global__ void rank_finalize_kernel(Segs sg, uint32_t N, double delta, double *__restrict__ ranks) {
+__global__ void rank_finalize_kernel(Segs sg, uint32_t N, double delta, double *__restrict__ ranks,
+                                     uint32_t *__restrict__ qhead) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < kXcdQueues) qhead[p] = 0;  // the rank launch's queues, for the next one
   if (p >= N) return;
   const uint32_t set = sg.set_of_pos(p);
   const uint32_t a = sg.seq[set], n = sg.seq[set + 1] - a;
   const SetView &v = sg.views[set];
-  long long *acc = v.acc + 3ull * (p - a);
-  long long l0, l1, l2;
-  fix_limbs(-log(delta + 1.0), l0, l1, l2);  // the j = i term: F = 1
-  const double sum = fix_to_double(acc[0] + l0, acc[1] + l1, acc[2] + l2);
-  ranks[a + v.perm[p - a]] = sum / (double)n;
-  acc[0] = acc[1] = acc[2] = 0;  // cleared for the next rank launch
+  long long *acc = v.acc + (p - a);
+  const int fix = fix_bits(n, delta);
+  const long long self = fix_q(-log(delta + 1.0), fix);  // the j = i term: F = 1
+  ranks[a + v.perm[p - a]] = fix_value(*acc + self, fix) / (double)n;
+  *acc = 0;  // cleared for the next rank launch
 }
 
 hipError_t launch_rank_finalize(hipStream_t st, const Segs &sg, uint32_t N, double delta,
-                                double *ranks) {
+                                double *ranks, uint32_t *qhead) {
   if (N == 0) return hipSuccess;
   hipLaunchKernelGGL(rank_finalize_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sg, N, delta,
-                     ranks);
+                     ranks, qhead);
   return hipGetLastError();
 }
 

@@ -49,11 +49,34 @@ __device__ __forceinline__ void planes_to_counts(uint32_t (&P)[16], uint32_t (&c
     cnt[r] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, P[r]), ones, 0u, false);
 }
 
+// Loads through a global-address-space pointer: they count only as vector
+// memory operations, so a wait for LDS results does not also wait for them
+// (a generic-pointer load counts as both).
+__device__ __forceinline__ uint4 gld(const uint4 *p) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(1))) const v4u gv4u;
+  const v4u v = *(gv4u *)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// 2k masks of the words in x[0..k) (low half first): all 2k LDS reads are
+// issued before the first use, so their latencies overlap
+template <int K>
+__device__ __forceinline__ void lookup_batch(const uint16_t *T16, const uint32_t (&x)[K],
+                                             uint32_t (&lo)[K], uint32_t (&hi)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    lo[k] = T16[x[k] & 0xFFFFu];
+    hi[k] = T16[x[k] >> 16];
+  }
+}
+
 // Level-1 counts of this lane's column (list length L, a multiple of 16,
 // the same for the whole wave) against the 16 rows of the LDS table.
-// Chunk k of the column (8 words) is p[64 k].  Loads run up to two 32-word
-// steps ahead; the word buffer carries enough sentinel slack after the last
-// group for that.
+// Chunk k of the column (8 words) is p[64 k].  Per 32-word step: the 32
+// lookups are issued together, then the next step's four chunks are
+// loaded, then the masks are summed; the load after the last step reads
+// into the sentinel slack behind the last group.
 template <int NP>
 __device__ __forceinline__ void column_counts_uniform(const uint16_t *T16, const uint4 *__restrict__ p,
                                                       uint32_t L, uint32_t (&cnt)[16]) {
@@ -61,27 +84,34 @@ __device__ __forceinline__ void column_counts_uniform(const uint16_t *T16, const
 #pragma unroll
   for (int k = 0; k < 16; k++) P[k] = 0;
   const uint32_t n32 = L >> 5;
-  uint4 a0 = p[0], a1 = p[64], a2 = p[128], a3 = p[192];
-  uint32_t it = 0;
-  for (; it + 2 <= n32; it += 2) {
+  uint4 c0 = gld(p), c1 = gld(p + 64), c2 = gld(p + 128), c3 = gld(p + 192);
+  for (uint32_t it = 0; it < n32; it++) {
+    const uint32_t x[16] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w,
+                            c2.x, c2.y, c2.z, c2.w, c3.x, c3.y, c3.z, c3.w};
+    uint32_t lo[16], hi[16];
+    lookup_batch<16>(T16, x, lo, hi);
+    __builtin_amdgcn_sched_barrier(0);
     const uint4 *q = p + (size_t)(it + 1) * 256;
-    const uint4 b0 = q[0], b1 = q[64], b2 = q[128], b3 = q[192];
-    step32<NP>(T16, P, a0, a1, a2, a3);
-    q += 256;
-    a0 = q[0];
-    a1 = q[64];
-    a2 = q[128];
-    a3 = q[192];
-    step32<NP>(T16, P, b0, b1, b2, b3);
+    c0 = gld(q);
+    c1 = gld(q + 64);
+    c2 = gld(q + 128);
+    c3 = gld(q + 192);
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t w[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) w[k] = __builtin_amdgcn_perm(hi[k], lo[k], 0x05040100u);
+    add16<NP>(P, w);
   }
-  if (it < n32) {
-    const uint4 *q = p + (size_t)(it + 1) * 256;
-    const uint4 b0 = q[0], b1 = q[64];
-    step32<NP>(T16, P, a0, a1, a2, a3);
-    a0 = b0;
-    a1 = b1;
+  if (L & 16u) {
+    const uint32_t x[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    uint32_t lo[8], hi[8];
+    lookup_batch<8>(T16, x, lo, hi);
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) w[k] = __builtin_amdgcn_perm(hi[k], lo[k], 0x05040100u);
+    add8<NP>(P, w);
   }
-  if (L & 16u) step16<NP>(T16, P, a0, a1);
   planes_to_counts(P, cnt);
 }
 
@@ -259,15 +289,17 @@ struct ListedRows {
 };
 
 constexpr uint32_t kExcLds = 256;  // merged count>=2 words of a row block kept in LDS
+constexpr uint32_t kSplitMinWords = 64;  // shortest list slice worth a wave of its own
 
 struct RankShared {
   RowShared row;
   LogEntry logt[kLogEntries];
   double ln2;
-  unsigned long long racc[48];  // 16 rows x 3 limbs of the current row block
+  unsigned long long racc[16];  // row sums of the current row block (fixed point)
   uint16_t exc_id[kExcLds];
   uint16_t exc_c[kExcLds * 16];
-  long long colacc[16][2][3][64];  // [wave][group of the wave][limb][lane]
+  long long colacc[32][64];     // [group of the strip][lane] column sums (fixed point)
+  uint16_t xcnt[16][16][64];    // [wave][row][lane] level-1 counts of a list slice
 };
 
 // Level-1 counts for this lane's column, dispatching on the plane bucket.
@@ -288,27 +320,63 @@ __device__ __forceinline__ void column_counts(const uint16_t *T16, const uint4 *
 // exact); with rows from another set (kCross true: the gathered samples of
 // the globalized rank, row_n of them) every pair counts and only the
 // columns gather sums.  Column sums go into the lane's limbs.
-template <bool kCross>
-__device__ __forceinline__ void rank_tile(const SetView &v, RankShared &sh, uint32_t rb, uint32_t g,
-                                          uint32_t row_n, double delta, const uint16_t *eid,
-                                          const uint16_t *ecnt, uint32_t en, long long (&col)[3][64]) {
+// Level-1 counts of words [w0, w0 + len) of this lane's column in group g
+// (w0 and len multiples of 16) against the row block in the LDS table.
+__device__ __forceinline__ void slice_counts(const SetView &v, const RankShared &sh, uint32_t g,
+                                             uint32_t w0, uint32_t len, uint32_t (&cnt)[16]) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t L = __builtin_amdgcn_readfirstlane(v.grp_len[g]);
-  const uint32_t hl = __builtin_amdgcn_readfirstlane(v.ghi_len[g]);
+  const uint4 *p = reinterpret_cast<const uint4 *>(v.gids + v.grp_off[g]) + lane + (size_t)(w0 >> 3) * 64;
+  column_counts(reinterpret_cast<const uint16_t *>(sh.row.T32), p, len, cnt);
+}
+
+// One 16 x 64 tile: row block rb (in LDS) against column group g (this
+// wave).  Within one set (kCross false) a pair counts only below the
+// diagonal of the sorted order and the tile's row sums go to sh.racc (LDS,
+// exact); with rows from another set (kCross true: the gathered samples of
+// the globalized rank, row_n of them) every pair counts and only the
+// columns gather sums.  Column sums go into the lane's entry of col.
+// tile_finish takes the level-1 counts of the whole column list (however
+// they were summed) and does the rest; rank_tile does both parts.
+// Per-column data of a tile, loaded before the counting so that its
+// latency overlaps the lookups: the column's count>=2 list (length hl per
+// lane, first four entries q0) and its word count.
+struct TileCol {
+  const uint32_t *hp;
+  uint32_t hl;
+  uint32_t q0[4];
+  uint32_t Kc;
+  double invKc;
+};
+
+__device__ __forceinline__ TileCol tile_col(const SetView &v, uint32_t g) {
+  const uint32_t lane = threadIdx.x & 63u;
+  TileCol c;
+  c.hl = __builtin_amdgcn_readfirstlane(v.ghi_len[g]);
   const uint32_t sc = 64u * g + lane;
   const bool vc = sc < v.N;
-  const uint4 *p = reinterpret_cast<const uint4 *>(v.gids + v.grp_off[g]) + lane;
-  const uint32_t *hp = v.ghi + v.ghi_off[g] + lane;
-  uint32_t q0[4] = {0u, 0u, 0u, 0u};
-  if (hl > 0) {
+  c.hp = v.ghi + v.ghi_off[g] + lane;
 #pragma unroll
-    for (int k = 0; k < 4; k++) q0[k] = hp[(size_t)k * 64];
+  for (int k = 0; k < 4; k++) c.q0[k] = 0u;
+  if (c.hl > 0) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) c.q0[k] = c.hp[(size_t)k * 64];
   }
-  const uint32_t Kc = vc ? v.K[sc] : 1u;
-  const double invKc = vc ? v.invK[sc] : 0.0;
-  uint32_t cnt[16];
-  column_counts(reinterpret_cast<const uint16_t *>(sh.row.T32), p, L, cnt);
-  column_excess_grouped(hp, hl, q0, sh.row.BM, eid, ecnt, en, cnt);
+  c.Kc = vc ? v.K[sc] : 1u;
+  c.invKc = vc ? v.invK[sc] : 0.0;
+  return c;
+}
+
+template <bool kCross>
+__device__ __forceinline__ void tile_finish(const SetView &v, RankShared &sh, uint32_t rb, uint32_t g,
+                                            uint32_t row_n, double delta, int fix, const uint16_t *eid,
+                                            const uint16_t *ecnt, uint32_t en, const TileCol &tc,
+                                            uint32_t (&cnt)[16], long long (&col)[64]) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t sc = 64u * g + lane;
+  const bool vc = sc < v.N;
+  const uint32_t Kc = tc.Kc;
+  const double invKc = tc.invKc;
+  column_excess_grouped(tc.hp, tc.hl, tc.q0, sh.row.BM, eid, ecnt, en, cnt);
   // F = shared / min(K_r, K_c) (Equation 1), d = -ln(delta + F) (Equation 2);
   // rows r and r + 8 are formed together and immediately folded across
   // lanes l and l ^ 32 (first step of the halving butterfly)
@@ -337,20 +405,20 @@ __device__ __forceinline__ void rank_tile(const SetView &v, RankShared &sh, uint
   }
   if (!kCross) {
     const double rowtot = halving_reduce8(u8, lane);
-    if ((lane & 3u) == 0) {
-      long long l0, l1, l2;
-      fix_limbs(rowtot, l0, l1, l2);
-      unsigned long long *ra = sh.racc + 3u * (lane >> 2);
-      atomicAdd(ra, (unsigned long long)l0);
-      atomicAdd(ra + 1, (unsigned long long)l1);
-      atomicAdd(ra + 2, (unsigned long long)l2);
-    }
+    if ((lane & 3u) == 0) atomicAdd(sh.racc + (lane >> 2), (unsigned long long)fix_q(rowtot, fix));
   }
-  long long l0, l1, l2;
-  fix_limbs(colsum, l0, l1, l2);
-  col[0][lane] += l0;
-  col[1][lane] += l1;
-  col[2][lane] += l2;
+  col[lane] += fix_q(colsum, fix);
+}
+
+template <bool kCross>
+__device__ __forceinline__ void rank_tile(const SetView &v, RankShared &sh, uint32_t rb, uint32_t g,
+                                          uint32_t row_n, double delta, int fix, const uint16_t *eid,
+                                          const uint16_t *ecnt, uint32_t en, long long (&col)[64]) {
+  const uint32_t L = __builtin_amdgcn_readfirstlane(v.grp_len[g]);
+  const TileCol tc = tile_col(v, g);
+  uint32_t cnt[16];
+  slice_counts(v, sh, g, 0u, L, cnt);
+  tile_finish<kCross>(v, sh, rb, g, row_n, delta, fix, eid, ecnt, en, tc, cnt, col);
 }
 
 }  // namespace kd

@@ -200,10 +200,10 @@ def test_autotune_shapes_identical(kd, ctx):
     best, ms = ctx.autotune(ks, 0.1)
     assert best in ctx.TUNE_SHAPES and all(v > 0 for v in ms.values())
     assert torch.equal(ctx.kmer_rank(ks, 0.1), R0)
-    for rows in (1, 3, 32):  # any shape, set by hand, gives the same ranks
-        ctx.set_rows_per_task(1, ss.n, rows)
+    for t in (1, 3, 64):  # any shape, set by hand, gives the same ranks
+        ctx.set_tasks_per_cu(1, ss.n, t)
         ks2 = ctx.kmer_count(ss.residues, ss.offsets.view(np.int64))
-        assert torch.equal(ctx.kmer_rank(ks2, 0.1), R0), rows
+        assert torch.equal(ctx.kmer_rank(ks2, 0.1), R0), t
     sets = synth.batched(4, 40)
     res, off, first, Bs = synth.concat(sets)
     kb = ctx.kmer_count_batch(res, off.view(np.int64), first)
