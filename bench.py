@@ -462,6 +462,32 @@ def batch_roofline(probes, pairs, stages):
             "work_per_launch": {"probes": probes, "pairs": pairs}}
 
 
+def bench_batch_graph(ctx, res, off, first, Bs, args, out, t_eager):
+    """The same batch as one HIP graph (kd_batch_plan): replays timed like
+    the eager calls; every replay's outputs compared with the eager ones."""
+    import torch
+    plan = ctx.batch_plan(res, off, first, Bs, args.delta)
+    for _ in range(max(args.warmup, 1)):
+        plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / args.steps
+    same = all(torch.equal(plan.out[k][:out[k].numel()].view(torch.int64) if k == "ranks" else plan.out[k][:out[k].numel()],
+                           out[k].view(torch.int64) if k == "ranks" else out[k]) for k in out)
+    g = {"ms_per_step": t_graph * 1e3, "kernel_launches_per_replay": plan.launches,
+         "identical_outputs": bool(same), "eager_ms_per_step": t_eager * 1e3,
+         "launch_overhead_saved_ms": (t_eager - t_graph) * 1e3,
+         "note": ("kd_batch_plan: the batch's kernels captured once into a HIP graph and replayed with "
+                  "hipGraphLaunch (no host synchronization, no allocation per replay); the eager call "
+                  "synchronizes once to size the layout and builds the work list on the host")}
+    plan.destroy()
+    print(f"[bench] batched as a graph: {t_graph * 1e3:.2f} ms per replay", file=sys.stderr, flush=True)
+    return g
+
+
 def bench_batched(args):
     """Many independent sets in one call (kd_batch_run) against the plain
     per-set loop (kmer_count -> kmer_rank -> sample_partition, synchronizing
@@ -509,11 +535,12 @@ def bench_batched(args):
     stages = ctx.stage_times()
     ctx.enable_timing(False)
     print(f"[bench] batched: {t_batch * 1e3:.2f} ms per batch", file=sys.stderr, flush=True)
+    graph = bench_batch_graph(ctx, res, off, first, Bs, args, out, t_batch)
     if args.no_loop_baseline:
         line = {"metric": "batched k-mer rank + split: pair-similarities/s", "value": pairs / t_batch,
                 "unit": "pair-similarities/s", "ms_per_step": t_batch * 1e3, "sets": len(sets),
                 "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
-                "roofline": batch_roofline(probes, pairs, stages)}
+                "roofline": batch_roofline(probes, pairs, stages), "graph": graph}
         ctx.close()
         print(json.dumps(line), flush=True)
         return
@@ -557,6 +584,7 @@ def bench_batched(args):
         "identical_outputs": same,
         "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
         "roofline": batch_roofline(probes, pairs, stages),
+        "graph": graph,
     }
     ctx.close()
     print(json.dumps(line), flush=True)

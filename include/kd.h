@@ -164,7 +164,7 @@ kd_status kmer_rank(kd_ctx *ctx, const kd_set *set, double delta, double *ranks)
  * equal estimated cost (runs of row blocks against strips of 2,048
  * sequences); more workgroups balance better, fewer flush fewer column sums
  * to the accumulators.  Times kmer_rank on `set` for each of the
- * KD_TUNE_CANDIDATES values t = {1, 2, 4, 8, 16} (one warm-up and three
+ * KD_TUNE_CANDIDATES values t = {2, 4, 8, 16, 32} (one warm-up and three
  * timed runs each; the stream is synchronized), checks that all shapes give
  * bit-identical ranks (KD_EDEVICE otherwise), gives the set the fastest
  * shape and remembers t in the context for later counted objects of the
@@ -270,6 +270,30 @@ kd_status kd_batch_run(kd_ctx *ctx, const uint8_t *residues, const uint64_t *off
                        uint64_t n_residues, uint32_t nsets, const uint32_t *set_first,
                        const uint32_t *set_B, double delta, double *ranks, uint32_t *bucket,
                        uint32_t *order, uint32_t *offsets_out);
+
+/* A batch set up once and replayed as one HIP graph (the batching pattern
+ * of the workloads: all sets in one pass, launched without host work).
+ * kd_batch_plan_create takes kd_batch_run's arguments, copies the inputs
+ * into device memory of its own, runs the batch once (outputs written; the
+ * count's sizing synchronization happens here) while recording each of its
+ * kernel launches, and captures them into a graph: counting, layout, the
+ * rank launch over every set's work, finalize and the split of every set.
+ * kd_batch_plan_launch enqueues the graph on the context's stream: it
+ * recomputes the batch from the plan's copy of the inputs and writes the
+ * outputs again (bit-identical), with no host synchronization and no
+ * allocation.  The plan holds all device memory of the batch until
+ * kd_batch_plan_destroy (which synchronizes the stream).  A plan belongs to
+ * its context and must be destroyed before it; the output buffers must stay
+ * valid while the plan can be launched.  Errors: those of kd_batch_run;
+ * KD_EDEVICE if the graph cannot be captured. */
+typedef struct kd_batch_plan kd_batch_plan;
+kd_status kd_batch_plan_create(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                               uint64_t n_residues, uint32_t nsets, const uint32_t *set_first,
+                               const uint32_t *set_B, double delta, double *ranks, uint32_t *bucket,
+                               uint32_t *order, uint32_t *offsets_out, kd_batch_plan **out);
+kd_status kd_batch_plan_launch(kd_batch_plan *plan);
+uint32_t kd_batch_plan_launches(const kd_batch_plan *plan); /* nodes (kernels) of the graph */
+void kd_batch_plan_destroy(kd_batch_plan *plan);
 
 /* Algorithm 2 step 1 on one device: the n sequences split into the B
  * contiguous blocks [floor(bn/B), floor((b+1)n/B)) the paper's processors

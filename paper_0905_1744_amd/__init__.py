@@ -110,6 +110,10 @@ def lib():
         "kd_decompose": (i32, [P, P, P, u32, u64, u32, C.c_int, C.c_double, P, P, P, P]),
         "psp_scores": (i32, [P, P, u32, P]),
         "kd_calibrate_lds": (i32, [P, u32, u32, u32, C.POINTER(C.c_double), C.POINTER(u64)]),
+        "kd_batch_plan_create": (i32, [P, P, P, u64, u32, P, P, C.c_double, P, P, P, P, PP]),
+        "kd_batch_plan_launch": (i32, [P]),
+        "kd_batch_plan_launches": (u32, [P]),
+        "kd_batch_plan_destroy": (None, [P]),
         "kd_server_create": (i32, [C.c_int, C.POINTER(ServerOpts), PP]),
         "kd_server_submit": (i32, [P, C.POINTER(Job), C.POINTER(u64)]),
         "kd_server_poll": (i32, [P, C.POINTER(Done), u32, C.POINTER(u32), C.c_int64]),
@@ -281,7 +285,7 @@ class Context:
                     "kmer_similarity")
         return (S, Dn) if denom else S
 
-    TUNE_SHAPES = (1, 2, 4, 8, 16)
+    TUNE_SHAPES = (2, 4, 8, 16, 32)
 
     def autotune(self, kset: KmerSet, delta: float = 0.1):
         """Pick the rank kernel's work-list shape for sets of this size class
@@ -589,6 +593,56 @@ class Context:
                                        float(delta), _ptr(out["ranks"]), _ptr(out["bucket"]),
                                        _ptr(out["order"]), _ptr(out["offsets"])), "kd_batch_run")
         return out
+
+    def batch_plan(self, residues, offsets, set_first, set_B, delta: float = 0.1, out=None) -> "BatchPlan":
+        """kd_batch_plan_create: the batch run once (outputs written) and
+        captured as a graph; BatchPlan.launch() replays it."""
+        res = _dev_tensor(residues, torch.uint8, self.device)
+        off = _dev_tensor(offsets, torch.int64, self.device)
+        sf = self._set_first(set_first, off)
+        nsets = sf.size - 1
+        Bs = self._host_u32(set_B, nsets, "set_B")
+        n = off.numel() - 1
+        nb = int(Bs.astype(np.int64).sum()) + nsets
+        if out is None:
+            out = dict(ranks=torch.empty(max(n, 1), dtype=torch.float64, device=self.device),
+                       bucket=torch.empty(max(n, 1), dtype=torch.int32, device=self.device),
+                       order=torch.empty(max(n, 1), dtype=torch.int32, device=self.device),
+                       offsets=torch.empty(max(nb, 1), dtype=torch.int32, device=self.device))
+        h = C.c_void_p()
+        self._check(lib().kd_batch_plan_create(self.handle, _ptr(res), _ptr(off), res.numel(), nsets,
+                                               sf.ctypes.data_as(C.c_void_p), Bs.ctypes.data_as(C.c_void_p),
+                                               float(delta), _ptr(out["ranks"]), _ptr(out["bucket"]),
+                                               _ptr(out["order"]), _ptr(out["offsets"]), C.byref(h)),
+                    "kd_batch_plan_create")
+        return BatchPlan(self, h, out)
+
+
+class BatchPlan:
+    """A batch captured as one HIP graph (kd_batch_plan_*): launch() replays
+    count, rank and split of every set into the output tensors it holds."""
+
+    def __init__(self, ctx: "Context", handle: C.c_void_p, out: dict):
+        self.ctx, self.handle, self.out = ctx, handle, out
+
+    @property
+    def launches(self) -> int:
+        return int(lib().kd_batch_plan_launches(self.handle))
+
+    def launch(self):
+        self.ctx._check(lib().kd_batch_plan_launch(self.handle), "kd_batch_plan_launch")
+        return self.out
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().kd_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 class Server:

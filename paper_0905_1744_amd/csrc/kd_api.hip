@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -93,9 +94,21 @@ struct Scope {  // pool blocks released at scope exit (stream order makes reuse 
     return static_cast<T *>(p);
   }
   ~Scope() {
-    for (void *p : blocks) ctx->pool->free(p);
+    for (void *p : blocks) {
+      if (ctx->rec_keep) ctx->rec_keep->push_back(p);  // a batch plan keeps its temporaries
+      else ctx->pool->free(p);
+    }
   }
 };
+
+// Enqueues one launch on the context's stream; while a batch plan is made
+// the launch is also recorded for replay (its arguments captured by value).
+template <class F>
+hipError_t issue(kd_ctx *ctx, F f) {
+  const hipError_t e = f(ctx->stream);
+  if (e == hipSuccess && ctx->rec) ctx->rec->emplace_back(f);
+  return e;
+}
 
 kd_status from_hip(hipError_t e) { return e == hipSuccess ? KD_OK : KD_EDEVICE; }
 
@@ -490,6 +503,16 @@ void build_costed_tasks(const std::vector<SetView> &views, const std::vector<uin
   beg[kXcdQueues] = (uint32_t)out.size();
 }
 
+// Most tasks build_costed_tasks can make: a run ends when its cost reaches
+// the per-task share (at most T such runs), at a strip's end or at an XCD
+// boundary.
+uint64_t max_pair_tasks(const std::vector<SetView> &views, uint32_t tasks_per_cu, int cus) {
+  uint64_t strips = 0;
+  for (const SetView &w : views) strips += ((w.N + 63) / 64 + kGroupsPerTask - 1) / kGroupsPerTask;
+  const uint64_t T = std::max<uint64_t>(kXcdQueues, (uint64_t)tasks_per_cu * (uint64_t)std::max(cus, 1));
+  return T + strips + kXcdQueues + 1;
+}
+
 // size class of a counted object for the tuned work-list shape
 uint32_t shape_class(uint32_t nsets, uint32_t N) {
   uint32_t c = 0;
@@ -608,7 +631,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint32_t *nmid = nlong + 1;
   hipError_t e = upload(ctx, segb, hb.data(), sizeof(uint32_t) * hb.size());
   if (e == hipSuccess && nsets > 1)
-    e = launch_seg_ids(st, sg, segid, segid + N, segid + N + G);
+    e = issue(ctx, [=](hipStream_t q) { return launch_seg_ids(q, sg, segid, segid + N, segid + N + G); });
   if (e == hipSuccess) {
     FillJobs f{};
     f.j[0] = {small, 1, ~0ull};
@@ -616,21 +639,27 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     f.j[2] = {reinterpret_cast<unsigned long long *>(acc), (uint64_t)N, 0ull};  // rank accumulators
     f.j[3] = {reinterpret_cast<unsigned long long *>(qhead), kXcdQueues / 2, 0ull};  // rank queues
     f.n = 4;
-    e = launch_fills(st, f);
+    e = issue(ctx, [=](hipStream_t q) { return launch_fills(q, f); });
   }
   StageTimer t_count(ctx, KD_STAGE_COUNT);
   if (e == hipSuccess && parent)
     e = launch_gather_samples(st, parent->segs, parent->in_off, parent->Dorig, picks, N, in_off, Dorig,
-                              Korig, nhi_orig, hi_cap);
+                              Korig, nhi_orig, hi_cap);  // (sample sets are not made under a plan)
   else if (e == hipSuccess)
-    e = launch_count(st, residues, offsets, in_off, N, n_residues, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig,
-                     nhi_orig, mid_list, nmid, long_list, nlong, err, ctx->cus);
+    e = issue(ctx, [=](hipStream_t q) {
+      return launch_count(q, residues, offsets, in_off, N, n_residues, cap, cap_ids, cap_cnt, hi_cap, Dorig,
+                          Korig, nhi_orig, mid_list, nmid, long_list, nlong, err, ctx->cus);
+    });
   t_count.done();
   StageTimer t_layout(ctx, KD_STAGE_LAYOUT);
-  if (e == hipSuccess) e = launch_sort_u32_index(st, Dorig, sg, first, perm, sort_tmp);
+  const std::vector<uint32_t> first_h(first, first + nsets + 1);
   if (e == hipSuccess)
-    e = launch_layout_meta(st, sg, N, G, RB, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hcount,
-                           hi_off, grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta, meta_tmp);
+    e = issue(ctx, [=](hipStream_t q) { return launch_sort_u32_index(q, Dorig, sg, first_h.data(), perm, sort_tmp); });
+  if (e == hipSuccess)
+    e = issue(ctx, [=](hipStream_t q) {
+      return launch_layout_meta(q, sg, N, G, RB, perm, Dorig, Korig, nhi_orig, inv, K, D, invK, hcount, hi_off,
+                                grp_off, grp_len, ghi_off, ghi_len, exc_off, err, meta, meta_tmp);
+    });
   t_layout.done();
   // the padded list lengths come back with the totals: the rank work list
   // is cut by their estimated cost
@@ -659,12 +688,13 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     set_free(s);
     return map_err(code);
   }
+  // the rank work list is cut on the host while the device lays the lists
+  // out (below); its size is bounded by max_pair_tasks
+  uint64_t task_cap = 0;
   if (!parent) {
     s->h_grp_len.assign(h_len, h_len + G);
-    build_costed_tasks(s->views, s->grp_first, s->h_grp_len, tasks_per_cu(ctx, nsets, N), ctx->cus,
-                       s->h_tasks, s->queues.beg);
+    task_cap = max_pair_tasks(s->views, tasks_per_cu(ctx, nsets, N), ctx->cus);
   }
-  s->ntasks = (uint32_t)s->h_tasks.size();
   s->entries = hm->entries;
   s->cap = cap;
   s->n_hi = hm->n_hi;
@@ -678,7 +708,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint32_t *ghi = set_alloc<uint32_t>(s, hm->n_ghi + 2);
   // per-set views, then (batches) the rank work list: one upload
   const size_t view_bytes = (sizeof(SetView) * nsets + 255) & ~(size_t)255;
-  const size_t task_bytes = sizeof(PairTask) * (size_t)(s->ntasks + 1);
+  const size_t task_bytes = sizeof(PairTask) * (size_t)(task_cap + 1);
   char *vt = set_alloc<char>(s, view_bytes + task_bytes);
   if (!gids || !hi_ids || !hi_cnt || !exc_ids || !exc_cnt || !ghi || !vt) {
     set_free(s);
@@ -737,13 +767,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   sg.views = d_view;
   s->tasks = reinterpret_cast<PairTask *>(vt + view_bytes);
   StageTimer t_fill(ctx, KD_STAGE_LAYOUT);
-  {
-    const size_t used = view_bytes + sizeof(PairTask) * s->ntasks;
-    std::vector<char> hv(used);
-    std::memcpy(hv.data(), s->views.data(), sizeof(SetView) * nsets);
-    if (s->ntasks) std::memcpy(hv.data() + view_bytes, s->h_tasks.data(), sizeof(PairTask) * s->ntasks);
-    e = upload(ctx, vt, hv.data(), hv.size());
-  }
+  e = upload(ctx, vt, s->views.data(), sizeof(SetView) * nsets);
   if (e == hipSuccess) {
     // sentinel slack after the last group (the pair kernel reads ahead into
     // it) and the zero padding of the grouped count>=2 lists
@@ -751,14 +775,29 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     f.j[0] = {reinterpret_cast<unsigned long long *>(gids + s->n_gids), kGidsSlack / 4, 0xB640B640B640B640ull};
     f.j[1] = {reinterpret_cast<unsigned long long *>(ghi), (hm->n_ghi + 1) / 2, 0ull};
     f.n = 2;
-    e = launch_fills(st, f);
+    e = issue(ctx, [=](hipStream_t q) { return launch_fills(q, f); });
   }
   if (e == hipSuccess)
-    e = launch_layout_fill(st, sg, v, in_off, cap_ids, hi_cap, gids, hi_ids, hi_cnt, ghi,
-                           (uint32_t)hm->max_len);
-  if (e == hipSuccess) e = launch_exc_build(st, sg, RB, nullptr, exc_off, exc_n, exc_ids, exc_cnt);
+  {
+    const SetView vv = v;
+    const uint32_t ml = (uint32_t)hm->max_len;
+    if (e == hipSuccess)
+      e = issue(ctx, [=](hipStream_t q) {
+        return launch_layout_fill(q, sg, vv, in_off, cap_ids, hi_cap, gids, hi_ids, hi_cnt, ghi, ml);
+      });
+  }
+  if (e == hipSuccess)
+    e = issue(ctx, [=](hipStream_t q) { return launch_exc_build(q, sg, RB, nullptr, exc_off, exc_n, exc_ids, exc_cnt); });
   t_fill.done();
+  if (e == hipSuccess && !parent) {
+    build_costed_tasks(s->views, s->grp_first, s->h_grp_len, tasks_per_cu(ctx, nsets, N), ctx->cus,
+                       s->h_tasks, s->queues.beg);
+    s->ntasks = (uint32_t)s->h_tasks.size();
+    if (s->ntasks > task_cap) e = hipErrorInvalidValue;  // not expected: bounded above
+    else if (s->ntasks) e = upload(ctx, s->tasks, s->h_tasks.data(), sizeof(PairTask) * s->ntasks);
+  }
   if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
     set_free(s);
     return KD_EDEVICE;
   }
@@ -880,10 +919,21 @@ extern "C" kd_status kmer_rank(kd_ctx *ctx, const kd_set *s, double delta, doubl
   }
   s->acc_clean = false;
   StageTimer t1(ctx, KD_STAGE_PAIRS);
-  KD_TRY(launch_rank_pairs(st, s->d_view, s->tasks, s->ntasks, s->queues, (uint32_t)ctx->cus, delta));
+  {
+    const SetView *dv = s->d_view;
+    const PairTask *tk = s->tasks;
+    const uint32_t nt = s->ntasks, wg = (uint32_t)ctx->cus;
+    const TaskQueues tq = s->queues;
+    KD_TRY(issue(ctx, [=](hipStream_t q) { return launch_rank_pairs(q, dv, tk, nt, tq, wg, delta); }));
+  }
   t1.done();
   StageTimer t2(ctx, KD_STAGE_FINALIZE);
-  KD_TRY(launch_rank_finalize(st, s->segs, s->v.N, delta, ranks, s->queues.head));
+  {
+    const Segs sg = s->segs;
+    const uint32_t N = s->v.N;
+    uint32_t *qh = s->queues.head;
+    KD_TRY(issue(ctx, [=](hipStream_t q) { return launch_rank_finalize(q, sg, N, delta, ranks, qh); }));
+  }
   t2.done();
   s->acc_clean = true;
   return KD_OK;
@@ -1213,7 +1263,7 @@ extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t 
                                  double *ms_out) {
   if (!ctx || !s || s->ctx != ctx) return KD_EINVAL;
   if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
-  static const uint32_t cand[KD_TUNE_CANDIDATES] = {1, 2, 4, 8, 16};
+  static const uint32_t cand[KD_TUNE_CANDIDATES] = {2, 4, 8, 16, 32};
   const uint32_t N = s->v.N;
   if (N == 0 || s->h_grp_len.size() != s->v.G) return KD_EINVAL;
   KD_TRY(hipSetDevice(ctx->device));
@@ -1382,8 +1432,11 @@ extern "C" kd_status sample_partition_batch(kd_ctx *ctx, const double *ranks, ui
   if (!scratch || !d_desc) return KD_ENOMEM;
   KD_TRY(upload(ctx, d_desc, desc.data(), sizeof(PartDesc) * nsets));
   StageTimer t(ctx, KD_STAGE_PARTITION);
-  KD_TRY(launch_partition_batch(ctx->stream, d_desc, nsets, max_part_keys(desc), ranks, bucket, order,
-                                offsets, pivot_rank, pivot_idx, scratch));
+  const uint32_t mk = max_part_keys(desc);
+  KD_TRY(issue(ctx, [=](hipStream_t q) {
+    return launch_partition_batch(q, d_desc, nsets, mk, ranks, bucket, order, offsets, pivot_rank, pivot_idx,
+                                  scratch);
+  }));
   t.done();
   return KD_OK;
 }
@@ -1411,6 +1464,125 @@ extern "C" kd_status kd_batch_run(kd_ctx *ctx, const uint8_t *residues, const ui
   kd_set_destroy(s);  // its blocks return to the pool; stream order keeps them valid
   return rc;
 }
+
+// ---------------------------------------------------------- batch plans
+
+struct kd_batch_plan {
+  kd_ctx *ctx = nullptr;
+  kd_set *set = nullptr;
+  std::vector<void *> blocks;  // input copies and the batch's temporaries (pool blocks)
+  std::vector<std::function<hipError_t(hipStream_t)>> launches;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void plan_free(kd_batch_plan *p) {
+  if (!p) return;
+  kd_ctx *ctx = p->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);  // no replay may still use the blocks
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->set) kd_set_destroy(p->set);
+  for (void *b : p->blocks) ctx->pool->free(b);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" kd_status kd_batch_plan_create(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offsets,
+                                          uint64_t n_residues, uint32_t nsets, const uint32_t *set_first,
+                                          const uint32_t *set_B, double delta, double *ranks,
+                                          uint32_t *bucket, uint32_t *order, uint32_t *offsets_out,
+                                          kd_batch_plan **out) {
+  if (!out) return KD_EINVAL;
+  *out = nullptr;
+  if (!ctx || !set_first || !set_B || nsets == 0 || !ranks || !bucket || !order || !offsets_out)
+    return KD_EINVAL;
+  if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
+  if (set_first[0] != 0) return KD_EINVAL;
+  for (uint32_t q = 0; q < nsets; q++) {
+    const uint32_t n = set_first[q + 1] - set_first[q];
+    if (set_first[q + 1] < set_first[q] || set_B[q] == 0 || set_B[q] > n || set_B[q] > kMaxBuckets)
+      return KD_EINVAL;
+  }
+  const uint32_t N = set_first[nsets];
+  if (N > 0 && (!offsets || (!residues && n_residues > 0))) return KD_EINVAL;
+  KD_TRY(hipSetDevice(ctx->device));
+  kd_batch_plan *p = new (std::nothrow) kd_batch_plan;
+  if (!p) return KD_ENOMEM;
+  p->ctx = ctx;
+  // the plan's own copies of the inputs: every replay reads the same batch
+  uint8_t *res = static_cast<uint8_t *>(ctx->pool->alloc(std::max<uint64_t>(n_residues, 1)));
+  if (res) p->blocks.push_back(res);
+  uint64_t *off = static_cast<uint64_t *>(ctx->pool->alloc(8ull * (N + 1)));
+  if (off) p->blocks.push_back(off);
+  if (!res || !off) {
+    plan_free(p);
+    return KD_ENOMEM;
+  }
+  hipError_t e = hipMemcpyAsync(res, residues, n_residues, hipMemcpyDefault, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(off, offsets, 8ull * (N + 1), hipMemcpyDefault, ctx->stream);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return KD_EDEVICE;
+  }
+  // the batch once, eagerly, with every kernel launch recorded
+  ctx->rec = &p->launches;
+  ctx->rec_keep = &p->blocks;
+  kd_status rc = kmer_count_batch(ctx, res, off, n_residues, nsets, set_first, &p->set);
+  if (rc == KD_OK) rc = kmer_rank(ctx, p->set, delta, ranks);
+  if (rc == KD_OK)
+    rc = sample_partition_batch(ctx, ranks, nsets, set_first, set_B, bucket, order, offsets_out, nullptr,
+                                nullptr);
+  ctx->rec = nullptr;
+  ctx->rec_keep = nullptr;
+  if (rc == KD_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = KD_EDEVICE;
+  // the recorded launches, replayed into a graph on a capture stream of the
+  // default priority
+  hipStream_t cs = nullptr;
+  if (rc == KD_OK && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) rc = KD_EDEVICE;
+  if (rc == KD_OK) {
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (size_t i = 0; e == hipSuccess && i < p->launches.size(); i++) e = p->launches[i](cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    p->graph = g;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      rc = KD_EDEVICE;
+    }
+  }
+  if (cs) (void)hipStreamDestroy(cs);
+  if (rc != KD_OK) {
+    plan_free(p);
+    return rc;
+  }
+  *out = p;
+  return KD_OK;
+}
+
+extern "C" kd_status kd_batch_plan_launch(kd_batch_plan *p) {
+  if (!p || !p->exec) return KD_EINVAL;
+  KD_TRY(hipSetDevice(p->ctx->device));
+  return from_hip(hipGraphLaunch(p->exec, p->ctx->stream));
+}
+
+extern "C" uint32_t kd_batch_plan_launches(const kd_batch_plan *p) {
+  if (!p || !p->graph) return 0u;
+  size_t n = 0;
+  if (hipGraphGetNodes(p->graph, nullptr, &n) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0u;
+  }
+  return (uint32_t)n;
+}
+
+extern "C" void kd_batch_plan_destroy(kd_batch_plan *p) { plan_free(p); }
 
 // ---------------------------------------------------------- calibration
 

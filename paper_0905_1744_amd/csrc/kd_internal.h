@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -151,6 +152,11 @@ struct kd_ctx {
   std::vector<hipEvent_t> ev_free;  // recycled timing events
   double stage_ms[KD_NSTAGES] = {0};
   uint64_t stage_n[KD_NSTAGES] = {0};
+  // while a batch plan is made: every kernel launch of the batch is also
+  // kept here (to be replayed into a HIP graph), and pool blocks that would
+  // be released at the end of a call are handed to the plan instead
+  std::vector<std::function<hipError_t(hipStream_t)>> *rec = nullptr;
+  std::vector<void *> *rec_keep = nullptr;
 };
 
 struct kd_set {

@@ -211,3 +211,31 @@ def test_autotune_shapes_identical(kd, ctx):
     best, _ = ctx.autotune(kb, 0.1)
     kb2 = ctx.kmer_count_batch(res, off.view(np.int64), first)
     assert torch.equal(ctx.kmer_rank(kb2, 0.1), Rb)
+
+
+def test_batch_plan_graph_replays(kd, ctx):
+    """The batch captured as one HIP graph (kd_batch_plan): every replay, with
+    eager work and synchronizations between replays, writes the eager
+    kd_batch_run outputs again bit for bit."""
+    import torch
+    sets = synth.batched(4, 60)
+    res, off, first, Bs = synth.concat(sets)
+    say("batch plan", len(sets), "sets", int(first[-1]), "sequences")
+    want = {k: v.clone() for k, v in ctx.batch_run(res, off.view(np.int64), first, Bs, 0.1).items()}
+    plan = ctx.batch_plan(res, off.view(np.int64), first, Bs, 0.1)
+    assert plan.launches >= 8
+    other = synth.paper20k(9, 700)
+    for rep in range(3):
+        for k, t in plan.out.items():
+            t.fill_(-1)
+        plan.launch()
+        ks = ctx.kmer_count(other.residues, other.offsets.view(np.int64))  # eager work in between
+        ctx.kmer_rank(ks, 0.1)
+        ks.destroy()
+        ctx.synchronize()
+        for k, w in want.items():
+            g = plan.out[k][:w.numel()]
+            if k == "ranks":
+                g, w = g.view(torch.int64), w.view(torch.int64)
+            assert torch.equal(g, w), (rep, k)
+    plan.destroy()
