@@ -458,13 +458,17 @@ kd_status kd_calibrate_lds(kd_ctx *ctx, uint32_t workgroups, uint32_t steps, uin
 /* ----------------------------------------------------------------- server */
 
 /* A request server for many independent jobs (each job = one sequence set
- * to count, rank and split).  A worker thread with its own context and
- * stream on `device` serves them: a job is admitted once the device memory
- * it will need fits the budget next to the other admitted jobs, and every
- * time the device becomes free the worker runs all admitted jobs (of one
- * delta, within the batch limits) as one batch through kd_batch_run's path.
- * Each job's results are bit-for-bit those of running it alone.  All calls
- * are internally synchronized and may come from any thread. */
+ * to count, rank and split).  A worker thread serves them on `device`: a
+ * job is admitted once the device memory it will need fits the budget next
+ * to the other admitted jobs and the input mirrors; admitted jobs (of one
+ * delta, within the batch limits) are taken together as one batch through
+ * kd_batch_run's path, in two stages on two streams of the default
+ * priority: (A) gather, count and lay out every set; (B) rank, split and
+ * copy the results back.  While a batch is in stage B, the jobs admitted
+ * meanwhile start stage A as the next batch, so their counting overlaps
+ * the running batch's rank on the device.  Each job's results are
+ * bit-for-bit those of running it alone.  All calls are internally
+ * synchronized and may come from any thread. */
 typedef struct kd_server kd_server;
 
 typedef struct kd_server_opts {
@@ -476,10 +480,14 @@ typedef struct kd_server_opts {
   uint64_t host_arena_bytes; /* pinned host memory for the jobs' input copies, set up at
                                 creation (64 MB chunks, kept and reused; more are pinned
                                 as jobs need them; a job no chunk can hold keeps a
-                                pageable copy).  Each chunk has a device mirror of the
-                                same size (outside hbm_budget), which a job's residues
-                                reach at submit, on a copy stream of the server's, while
-                                earlier batches run.  When nonzero, the batch buffers (pinned
+                                pageable copy).  A chunk gets a device mirror of the same
+                                size while the mirrors stay within half of hbm_budget;
+                                the mirrors' bytes count against the budget (admission
+                                leaves room for them).  A job's residues reach its
+                                chunk's mirror at submit, on a copy stream of the
+                                server's, while earlier batches run; a job in a chunk
+                                without a mirror is sent from the host copy by its
+                                batch.  When nonzero, the batch buffers (pinned
                                 offsets and results, device input and output) are also
                                 set up at creation, for a batch of that many residues in
                                 max_batch_seqs sequences (0: a mean length of 128); they
@@ -487,7 +495,8 @@ typedef struct kd_server_opts {
   uint32_t no_mirror;        /* 1: no device mirrors (no device memory beyond the batch
                                 buffers); each batch sends its jobs' residues from
                                 their host copies */
-  uint32_t reserved0;        /* 0 */
+  uint32_t timeline;         /* 1: record HIP events around each batch's two stages
+                                (kd_server_timeline) */
 } kd_server_opts;
 
 #define KD_JOB_BYTES(n_residues, n_seqs) (8ull * (n_residues) + 256ull * (n_seqs) + 65536ull)
@@ -531,9 +540,24 @@ kd_status kd_server_poll(kd_server *srv, kd_done *out, uint32_t max, uint32_t *n
  * KD_EBUSY if it is running, KD_EINVAL if the ticket is unknown or done. */
 kd_status kd_server_cancel(kd_server *srv, uint64_t ticket);
 /* Jobs queued, admitted-and-waiting, running; completion records not yet
- * polled; device bytes reserved by admitted jobs. */
+ * polled; device bytes reserved: the admitted and running jobs' charges
+ * plus the input mirrors (never more than hbm_budget). */
 kd_status kd_server_status(kd_server *srv, uint32_t *waiting, uint32_t *admitted,
                            uint32_t *running, uint32_t *done, uint64_t *reserved);
+/* One batch's stages on the device (kd_server_opts.timeline): milliseconds
+ * from a fixed event recorded at creation to the starts and ends of stage A
+ * (gather, count, layout; stream A) and stage B (rank, split, results
+ * copied back; stream B).  A batch's stage A may overlap the previous
+ * batch's stage B. */
+typedef struct kd_server_stage {
+  double count_start_ms, count_end_ms;
+  double rank_start_ms, rank_end_ms;
+  uint32_t jobs;       /* jobs in the batch */
+  uint32_t reserved0;
+} kd_server_stage;
+/* Moves up to `max` records of completed batches, oldest first, into
+ * out[0 .. *n). */
+kd_status kd_server_timeline(kd_server *srv, kd_server_stage *out, uint32_t max, uint32_t *n);
 /* Finishes the running batch, drops queued jobs, joins the worker. */
 void kd_server_destroy(kd_server *srv);
 

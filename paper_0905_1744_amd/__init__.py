@@ -43,7 +43,12 @@ class KdError(RuntimeError):
 
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("max_batch_jobs", C.c_uint32), ("max_batch_seqs", C.c_uint32),
-                ("host_arena_bytes", C.c_uint64), ("no_mirror", C.c_uint32), ("reserved0", C.c_uint32)]
+                ("host_arena_bytes", C.c_uint64), ("no_mirror", C.c_uint32), ("timeline", C.c_uint32)]
+
+
+class ServerStage(C.Structure):
+    _fields_ = [("count_start_ms", C.c_double), ("count_end_ms", C.c_double), ("rank_start_ms", C.c_double),
+                ("rank_end_ms", C.c_double), ("jobs", C.c_uint32), ("reserved0", C.c_uint32)]
 
 
 class Job(C.Structure):
@@ -121,6 +126,7 @@ def lib():
         "kd_server_status": (i32, [P, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32), C.POINTER(u32),
                                    C.POINTER(u64)]),
         "kd_server_destroy": (None, [P]),
+        "kd_server_timeline": (i32, [P, C.POINTER(ServerStage), u32, C.POINTER(u32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -650,10 +656,11 @@ class Server:
     numpy arrays owned by this object until the job's record is polled."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 200 << 30, max_batch_jobs: int = 0,
-                 max_batch_seqs: int = 0, host_arena_bytes: int = 0, device_mirror: bool = True):
+                 max_batch_seqs: int = 0, host_arena_bytes: int = 0, device_mirror: bool = True,
+                 timeline: bool = False):
         L = lib()
         opts = ServerOpts(hbm_budget, max_batch_jobs, max_batch_seqs, host_arena_bytes,
-                          0 if device_mirror else 1, 0)
+                          0 if device_mirror else 1, 1 if timeline else 0)
         out = C.c_void_p()
         st = L.kd_server_create(device, C.byref(opts), C.byref(out))
         if st != KD_OK:
@@ -701,6 +708,16 @@ class Server:
     def cancel(self, ticket: int) -> int:
         """KD_OK, or the status code (KD_EBUSY: already running)."""
         return int(lib().kd_server_cancel(self.handle, ticket))
+
+    def timeline(self, max_records: int = 65536):
+        """Stage records of completed batches (kd_server_timeline), oldest first."""
+        buf = (ServerStage * max_records)()
+        n = C.c_uint32()
+        st = lib().kd_server_timeline(self.handle, buf, max_records, C.byref(n))
+        if st != KD_OK:
+            raise KdError(st, "kd_server_timeline")
+        return [dict(count=(b.count_start_ms, b.count_end_ms), rank=(b.rank_start_ms, b.rank_end_ms), jobs=b.jobs)
+                for b in buf[:n.value]]
 
     def status(self):
         w, a, r, d = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()

@@ -1,19 +1,28 @@
 // Request server (kd_server_*): admission against a device-memory budget
 // and continuous batching of independent jobs onto the batched path.
 //
-// One worker thread owns a context and a stream.  Jobs move
-//   waiting --(fits the budget)--> admitted --(picked by a batch)--> running
-//   --> done (a completion record waits for kd_server_poll).
-// Whenever the worker is free it takes every admitted job with the delta
-// of the oldest one (within the batch limits), concatenates them into one
-// input, and runs count -> rank -> split for all of them at once; jobs
-// arriving meanwhile wait for the next batch.  A job with bad input fails
-// alone: the batch is re-run without it.  A job's residues go to the
-// device when it is submitted (a copy stream of their own), so a batch
-// finds its input there and only gathers it into one buffer.
+// Jobs move  waiting --(fits the budget)--> admitted --(picked by a batch)-->
+// running --> done (a completion record waits for kd_server_poll).
+//
+// One worker thread runs batches through two stages on two streams of the
+// same (default) priority, each with a context of its own:
+//   stage A (count stream): gather the batch's input, count and lay out
+//            every set (kmer_count_batch, which synchronizes stream A once);
+//   stage B (rank stream):  rank and split every set, copy the results back.
+// While batch k is in stage B, the worker already takes the jobs that
+// arrived meanwhile as batch k+1 and runs its stage A, so the counting of
+// arriving jobs overlaps the rank launch of the running batch on the device
+// and the host work (gather tables, layout sizing, work lists) overlaps both.
+// Batch k's results are written, and batch k+1's stage B enqueued (behind
+// an event on stream A), once batch k's stage B has completed.  A job with
+// bad input fails alone: its batch is counted again without it.  A job's
+// residues go to the device when it is submitted (a copy stream of their
+// own), so a batch finds its input there and only gathers it into one
+// buffer.
 #include <time.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstdlib>
@@ -78,16 +87,22 @@ struct Arena {
   };
   std::vector<Chunk> chunks;
   size_t cur = 0;
-  bool mirrored = true;  // chunks get device mirrors
+  bool mirrored = true;       // chunks get device mirrors ...
+  uint64_t mirror_limit = 0;  // ... while their bytes stay within this
+  uint64_t mirror_bytes = 0;  // device bytes held by mirrors (charged to the budget)
   bool add_chunk(bool touch) {
     void *v = nullptr;
     if (hipHostMalloc(&v, kChunk, hipHostMallocNonCoherent) != hipSuccess) return false;
     uint8_t *p = static_cast<uint8_t *>(v);
     if (touch) std::memset(p, 0, kChunk);
     void *d = nullptr;
-    if (mirrored && hipMalloc(&d, kChunk) != hipSuccess) {
-      (void)hipGetLastError();
-      d = nullptr;
+    if (mirrored && mirror_bytes + kChunk <= mirror_limit) {
+      if (hipMalloc(&d, kChunk) != hipSuccess) {
+        (void)hipGetLastError();
+        d = nullptr;
+      } else {
+        mirror_bytes += kChunk;
+      }
     }
     chunks.push_back(Chunk{p, static_cast<uint8_t *>(d), 0, 0});
     return true;
@@ -197,13 +212,31 @@ struct DevBuf {
 
 }  // namespace
 
+// A batch between its two stages: counted on stream A, ranked on stream B.
+struct Flight {
+  std::vector<Job *> b;            // the batch's jobs
+  std::vector<kd_status> st;       // per job; KD_OK while it is live
+  std::vector<uint32_t> live;      // indices into b of the jobs in the counted set
+  std::vector<uint32_t> first, Bs;
+  uint32_t N = 0;
+  uint64_t nb = 0;                 // bucket offsets of all sets
+  kd_set *set = nullptr;           // counted on ctx_a
+  hipEvent_t ev[4] = {};           // timeline: count start/end (A), rank start/end (B)
+  hipEvent_t done_ev = nullptr;    // stage B complete
+  bool timed = false;
+};
+
 struct kd_server {
   int device = 0;
   kd_server_opts opts{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // stage B: rank, split, results back
+  hipStream_t stream_a = nullptr;     // stage A: gather, count, layout
   hipStream_t copy_stream = nullptr;  // the jobs' copies at submit
   hipEvent_t copy_ev = nullptr;       // recorded after each of them (under mu)
-  kd_ctx *ctx = nullptr;
+  hipEvent_t counted_ev = nullptr;    // stage A of the next batch done (stream A)
+  hipEvent_t base_ev = nullptr;       // timeline origin (stream A, at creation)
+  kd_ctx *ctx = nullptr;              // stage B
+  kd_ctx *ctx_a = nullptr;            // stage A
   std::thread worker;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -212,14 +245,18 @@ struct kd_server {
   std::deque<Job *> waiting, admitted;
   std::unordered_map<uint64_t, Job *> running;
   std::deque<kd_done> done;
-  uint64_t reserved = 0;
-  Arena arena;  // the jobs' residues (pinned)
-  // staging, used by the worker only
+  uint64_t reserved = 0;  // charges of the admitted and running jobs
+  Arena arena;  // the jobs' residues (pinned) and their device mirrors
+  // staging, used by the worker only: inputs (stage A), outputs (stage B)
   HostBuf h_in, h_out;
   DevBuf d_in, d_out;
+  // timeline (opts.timeline): device milliseconds since base_ev of each
+  // batch's stages, guarded by mu
+  std::vector<kd_server_stage> stages;
 
   void admit_locked() {  // FIFO: the oldest waiting job goes first
-    while (!waiting.empty() && reserved + waiting.front()->bytes <= opts.hbm_budget) {
+    while (!waiting.empty() &&
+           reserved + arena.mirror_bytes + waiting.front()->bytes <= opts.hbm_budget) {
       reserved += waiting.front()->bytes;
       admitted.push_back(waiting.front());
       waiting.pop_front();
@@ -240,45 +277,58 @@ struct kd_server {
     delete j;
   }
 
-  kd_status run_batch(std::vector<Job *> &b, std::vector<kd_status> &st);
+  void release_streams() {
+    for (hipEvent_t e : {copy_ev, counted_ev, base_ev})
+      if (e) (void)hipEventDestroy(e);
+    for (hipStream_t t : {copy_stream, stream_a, stream})
+      if (t) (void)hipStreamDestroy(t);
+  }
+  kd_status count_stage(Flight &f);
+  kd_status rank_stage(Flight &f);
+  void results(Flight &f);
   void loop();
 };
 
-// Runs the jobs of b (all st[q] == KD_OK on entry) as one batch; on return
-// st[q] is each job's status and its outputs are written when KD_OK.
-kd_status kd_server::run_batch(std::vector<Job *> &b, std::vector<kd_status> &st) {
+// Stage A of a batch (every st[q] KD_OK on entry): its input gathered and
+// every set counted and laid out on stream A (ctx_a).  A job with bad input
+// is marked and the batch counted again without it.  On return f.set holds
+// the live jobs' sets (null when none is left or on a device error, with
+// st[] set accordingly).
+kd_status kd_server::count_stage(Flight &f) {
+  std::vector<Job *> &b = f.b;
+  std::vector<kd_status> &st = f.st;
   for (;;) {
-    std::vector<uint32_t> live;
+    f.live.clear();
     for (uint32_t q = 0; q < b.size(); q++)
-      if (st[q] == KD_OK) live.push_back(q);
-    if (live.empty()) return KD_OK;
-    const uint32_t ns = (uint32_t)live.size();
-    std::vector<uint32_t> first(ns + 1, 0), Bs(ns);
+      if (st[q] == KD_OK) f.live.push_back(q);
+    if (f.live.empty()) return KD_OK;
+    const uint32_t ns = (uint32_t)f.live.size();
+    f.first.assign(ns + 1, 0);
+    f.Bs.assign(ns, 0);
     uint64_t nres = 0;
     for (uint32_t k = 0; k < ns; k++) {
-      const Job *j = b[live[k]];
-      first[k + 1] = first[k] + j->out.n_seqs;
-      Bs[k] = j->out.B;
+      const Job *j = b[f.live[k]];
+      f.first[k + 1] = f.first[k] + j->out.n_seqs;
+      f.Bs[k] = j->out.B;
       nres += j->out.n_residues;
     }
-    const uint32_t N = first[ns];
-    uint64_t nb = 0, npc = 0;
+    const uint32_t N = f.first[ns];
+    f.N = N;
+    uint64_t npc = 0;
+    f.nb = 0;
     for (uint32_t k = 0; k < ns; k++) {
-      nb += Bs[k] + 1;
-      const Job *j = b[live[k]];
+      f.nb += f.Bs[k] + 1;
+      const Job *j = b[f.live[k]];
       if (j->dres) npc += (j->out.n_residues + kPiece - 1) / kPiece;
     }
     // input: offsets (N+1 u64, rebased) and the gather pieces, staged in
     // pinned memory, then the residues (gathered from the jobs' device
-    // copies; a job without one is sent from its host copy);
-    // output: ranks, bucket, order, offsets
+    // copies; a job without one is sent from its host copy)
     const size_t tab_at = (8ull * (N + 1) + 15) & ~(size_t)15;
     const size_t head = tab_at + sizeof(Piece) * npc;
     const size_t in_bytes = head + nres;
-    const size_t out_bytes = 8ull * N + 4ull * N + 4ull * N + 4ull * nb;
-    if (h_in.reserve(head) != hipSuccess || h_out.reserve(out_bytes) != hipSuccess ||
-        d_in.reserve(in_bytes) != hipSuccess || d_out.reserve(out_bytes + 256) != hipSuccess) {
-      for (uint32_t q : live) st[q] = KD_ENOMEM;
+    if (h_in.reserve(head) != hipSuccess || d_in.reserve(in_bytes) != hipSuccess) {
+      for (uint32_t q : f.live) st[q] = KD_ENOMEM;
       return KD_ENOMEM;
     }
     uint64_t *off = static_cast<uint64_t *>(h_in.p);
@@ -287,124 +337,237 @@ kd_status kd_server::run_batch(std::vector<Job *> &b, std::vector<kd_status> &st
     uint64_t r0 = 0, pq = 0;
     bool copied = true;
     for (uint32_t k = 0; k < ns; k++) {
-      const Job *j = b[live[k]];
+      const Job *j = b[f.live[k]];
       const uint64_t n = j->out.n_residues;
-      for (uint32_t i = 0; i < j->out.n_seqs; i++) off[first[k] + i] = r0 + j->offsets[i];
+      for (uint32_t i = 0; i < j->out.n_seqs; i++) off[f.first[k] + i] = r0 + j->offsets[i];
       if (j->dres) {
         for (uint64_t a = 0; a < n; a += kPiece) pcs[pq++] = Piece{j->dres + a, r0 + a, std::min(kPiece, n - a)};
       } else {
-        copied = copied && hipMemcpyAsync(d_resw + r0, j->res, n, hipMemcpyHostToDevice, stream) == hipSuccess;
+        copied = copied && hipMemcpyAsync(d_resw + r0, j->res, n, hipMemcpyHostToDevice, stream_a) == hipSuccess;
       }
       r0 += n;
     }
     off[N] = r0;
-    char *dout = static_cast<char *>(d_out.p);
-    double *d_ranks = reinterpret_cast<double *>(dout);
-    uint32_t *d_bucket = reinterpret_cast<uint32_t *>(dout + 8ull * N);
-    uint32_t *d_order = d_bucket + N;
-    uint32_t *d_offs = d_order + N;
-    const uint8_t *d_res = d_resw;
     const uint64_t *d_off = static_cast<const uint64_t *>(d_in.p);
-    copied = copied && hipMemcpyAsync(d_in.p, h_in.p, head, hipMemcpyHostToDevice, stream) == hipSuccess;
+    copied = copied && hipMemcpyAsync(d_in.p, h_in.p, head, hipMemcpyHostToDevice, stream_a) == hipSuccess;
     if (copied && npc) {
-      hipLaunchKernelGGL(gather_pieces_kernel, dim3((uint32_t)npc), dim3(256), 0, stream,
+      hipLaunchKernelGGL(gather_pieces_kernel, dim3((uint32_t)npc), dim3(256), 0, stream_a,
                          reinterpret_cast<const Piece *>(static_cast<char *>(d_in.p) + tab_at), d_resw);
       copied = hipGetLastError() == hipSuccess;
     }
     if (!copied) {
-      for (uint32_t x : live) st[x] = KD_EDEVICE;
+      for (uint32_t x : f.live) st[x] = KD_EDEVICE;
       return KD_EDEVICE;
     }
-    kd_set *set = nullptr;
-    kd_status rc = kmer_count_batch(ctx, d_res, d_off, nres, ns, first.data(), &set);
+    // the jobs' device copies and the input are read by stream A only, and
+    // the next batch's input is written only after this count's own
+    // synchronization of stream A
+    kd_status rc = kmer_count_batch(ctx_a, d_resw, d_off, nres, ns, f.first.data(), &f.set);
     if (rc == KD_EBADRESIDUE || rc == KD_ESHORTSEQ || rc == KD_ETOOLONG) {
-      // the job holding the offending sequence fails; the others run again
+      // the job holding the offending sequence fails; the others are counted again
       uint64_t seq = 0, pos = 0;
-      kd_last_error_info(ctx, &seq, &pos);
-      const uint32_t k = (uint32_t)(std::upper_bound(first.begin(), first.end(), (uint32_t)seq) - first.begin()) - 1;
-      st[live[std::min(k, ns - 1)]] = rc;
+      kd_last_error_info(ctx_a, &seq, &pos);
+      const uint32_t k =
+          (uint32_t)(std::upper_bound(f.first.begin(), f.first.end(), (uint32_t)seq) - f.first.begin()) - 1;
+      st[f.live[std::min(k, ns - 1)]] = rc;
+      f.set = nullptr;
       continue;
     }
-    if (rc == KD_OK) rc = kmer_rank(ctx, set, b[live[0]]->out.delta, d_ranks);
-    if (rc == KD_OK)
-      rc = sample_partition_batch(ctx, d_ranks, ns, first.data(), Bs.data(), d_bucket, d_order,
-                                  d_offs, nullptr, nullptr);
-    if (rc == KD_OK && hipMemcpyAsync(h_out.p, d_out.p, out_bytes, hipMemcpyDeviceToHost, stream) != hipSuccess)
-      rc = KD_EDEVICE;
-    if (rc == KD_OK && hipStreamSynchronize(stream) != hipSuccess) rc = KD_EDEVICE;
-    if (set) kd_set_destroy(set);
     if (rc != KD_OK) {
-      for (uint32_t q : live) st[q] = rc;
-      return rc;
+      for (uint32_t q : f.live) st[q] = rc;
+      f.set = nullptr;
     }
-    const char *hout = static_cast<const char *>(h_out.p);
-    const double *h_ranks = reinterpret_cast<const double *>(hout);
-    const uint32_t *h_bucket = reinterpret_cast<const uint32_t *>(hout + 8ull * N);
-    const uint32_t *h_order = h_bucket + N;
-    const uint32_t *h_offs = h_order + N;
-    uint64_t ob = 0;
-    for (uint32_t k = 0; k < ns; k++) {
-      const kd_job &o = b[live[k]]->out;
-      const uint32_t a = first[k], n = o.n_seqs;
-      if (o.ranks) std::memcpy(o.ranks, h_ranks + a, 8ull * n);
-      if (o.bucket) std::memcpy(o.bucket, h_bucket + a, 4ull * n);
-      if (o.order) std::memcpy(o.order, h_order + a, 4ull * n);
-      if (o.bucket_offsets) std::memcpy(o.bucket_offsets, h_offs + ob, 4ull * (o.B + 1));
-      ob += o.B + 1;
+    return rc;
+  }
+}
+
+// Stage B, enqueued on stream B behind stage A's completion: rank and split
+// of every set, results to the pinned host buffer, then the batch's done
+// event.  The set was counted on ctx_a; it is ranked on ctx (its blocks stay
+// with ctx_a's pool, which gets them back when the set is destroyed after
+// stage B has completed).
+kd_status kd_server::rank_stage(Flight &f) {
+  if (!f.done_ev) {
+    for (uint32_t q : f.live) f.st[q] = KD_EDEVICE;
+    return KD_EDEVICE;
+  }
+  const uint32_t N = f.N, ns = (uint32_t)f.live.size();
+  const size_t out_bytes = 8ull * N + 4ull * N + 4ull * N + 4ull * f.nb;
+  kd_status rc = KD_OK;
+  if (h_out.reserve(out_bytes) != hipSuccess || d_out.reserve(out_bytes + 256) != hipSuccess) rc = KD_ENOMEM;
+  if (rc == KD_OK && (hipEventRecord(counted_ev, stream_a) != hipSuccess ||
+                      hipStreamWaitEvent(stream, counted_ev, 0) != hipSuccess))
+    rc = KD_EDEVICE;
+  if (rc == KD_OK && f.timed && hipEventRecord(f.ev[2], stream) != hipSuccess) rc = KD_EDEVICE;
+  char *dout = static_cast<char *>(d_out.p);
+  double *d_ranks = reinterpret_cast<double *>(dout);
+  uint32_t *d_bucket = reinterpret_cast<uint32_t *>(dout + 8ull * N);
+  uint32_t *d_order = d_bucket + N;
+  uint32_t *d_offs = d_order + N;
+  f.set->ctx = ctx;
+  if (rc == KD_OK) rc = kmer_rank(ctx, f.set, f.b[f.live[0]]->out.delta, d_ranks);
+  if (rc == KD_OK)
+    rc = sample_partition_batch(ctx, d_ranks, ns, f.first.data(), f.Bs.data(), d_bucket, d_order, d_offs,
+                                nullptr, nullptr);
+  f.set->ctx = ctx_a;
+  if (rc == KD_OK && hipMemcpyAsync(h_out.p, d_out.p, out_bytes, hipMemcpyDeviceToHost, stream) != hipSuccess)
+    rc = KD_EDEVICE;
+  if (rc == KD_OK && f.timed && hipEventRecord(f.ev[3], stream) != hipSuccess) rc = KD_EDEVICE;
+  if (rc == KD_OK && hipEventRecord(f.done_ev, stream) != hipSuccess) rc = KD_EDEVICE;
+  if (rc != KD_OK)
+    for (uint32_t q : f.live) f.st[q] = rc;
+  return rc;
+}
+
+// After stage B: waits for it, writes the live jobs' results into their
+// buffers and releases the set.
+void kd_server::results(Flight &f) {
+  const bool ok = hipStreamSynchronize(stream) == hipSuccess;
+  if (f.set) {
+    kd_set_destroy(f.set);
+    f.set = nullptr;
+  }
+  if (!ok) {
+    for (uint32_t q : f.live) f.st[q] = KD_EDEVICE;
+    return;
+  }
+  const uint32_t N = f.N;
+  const char *hout = static_cast<const char *>(h_out.p);
+  const double *h_ranks = reinterpret_cast<const double *>(hout);
+  const uint32_t *h_bucket = reinterpret_cast<const uint32_t *>(hout + 8ull * N);
+  const uint32_t *h_order = h_bucket + N;
+  const uint32_t *h_offs = h_order + N;
+  uint64_t ob = 0;
+  for (uint32_t k = 0; k < f.live.size(); k++) {
+    if (f.st[f.live[k]] != KD_OK) continue;
+    const kd_job &o = f.b[f.live[k]]->out;
+    const uint32_t a = f.first[k], n = o.n_seqs;
+    if (o.ranks) std::memcpy(o.ranks, h_ranks + a, 8ull * n);
+    if (o.bucket) std::memcpy(o.bucket, h_bucket + a, 4ull * n);
+    if (o.order) std::memcpy(o.order, h_order + a, 4ull * n);
+    if (o.bucket_offsets) std::memcpy(o.bucket_offsets, h_offs + ob, 4ull * (o.B + 1));
+    ob += o.B + 1;
+  }
+  if (f.timed) {
+    kd_server_stage t{};
+    float ms[4] = {0.f, 0.f, 0.f, 0.f};
+    bool good = true;
+    for (int i = 0; i < 4; i++) good = good && hipEventElapsedTime(&ms[i], base_ev, f.ev[i]) == hipSuccess;
+    if (good) {
+      t.count_start_ms = ms[0];
+      t.count_end_ms = ms[1];
+      t.rank_start_ms = ms[2];
+      t.rank_end_ms = ms[3];
+      t.jobs = (uint32_t)f.b.size();
+      std::lock_guard<std::mutex> g(mu);
+      stages.push_back(t);
+    } else {
+      (void)hipGetLastError();
     }
-    return KD_OK;
   }
 }
 
 void kd_server::loop() {
   (void)hipSetDevice(device);
+  Flight fl[2];
+  for (Flight &f : fl) {
+    for (hipEvent_t &e : f.ev)
+      if (opts.timeline && hipEventCreate(&e) != hipSuccess) e = nullptr;
+    if (hipEventCreateWithFlags(&f.done_ev, hipEventDisableTiming) != hipSuccess) f.done_ev = nullptr;
+  }
+  Flight *busy = nullptr;  // the batch in stage B
+  int next = 0;
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    cv_work.wait(lk, [&] { return stop || !admitted.empty(); });
-    if (stop) break;
-    // the batch: admitted jobs of the oldest job's delta, in FIFO order
-    const double delta = admitted.front()->out.delta;
-    std::vector<Job *> b;
-    uint64_t seqs = 0;
-    for (auto it = admitted.begin(); it != admitted.end();) {
-      Job *j = *it;
-      if (opts.max_batch_jobs && b.size() >= opts.max_batch_jobs) break;
-      if (j->out.delta != delta) {
-        ++it;
-        continue;
+    cv_work.wait(lk, [&] { return stop || !admitted.empty() || busy; });
+    // while a batch is in stage B, jobs arriving before it completes start
+    // their stage A at once (short waits, the event polled in between)
+    while (busy && !stop && admitted.empty() && hipEventQuery(busy->done_ev) == hipErrorNotReady)
+      cv_work.wait_for(lk, std::chrono::microseconds(50), [&] { return stop || !admitted.empty(); });
+    if (stop && !busy) break;
+    Flight *f = nullptr;
+    if (!stop && !admitted.empty()) {
+      // the batch: admitted jobs of the oldest job's delta, in FIFO order
+      f = &fl[next];
+      next ^= 1;
+      f->b.clear();
+      const double delta = admitted.front()->out.delta;
+      uint64_t seqs = 0;
+      for (auto it = admitted.begin(); it != admitted.end();) {
+        Job *j = *it;
+        if (opts.max_batch_jobs && f->b.size() >= opts.max_batch_jobs) break;
+        if (j->out.delta != delta) {
+          ++it;
+          continue;
+        }
+        if (!f->b.empty() && opts.max_batch_seqs && seqs + j->out.n_seqs > opts.max_batch_seqs) break;
+        seqs += j->out.n_seqs;
+        f->b.push_back(j);
+        it = admitted.erase(it);
       }
-      if (!b.empty() && opts.max_batch_seqs && seqs + j->out.n_seqs > opts.max_batch_seqs) break;
-      seqs += j->out.n_seqs;
-      b.push_back(j);
-      it = admitted.erase(it);
+      const uint64_t t0 = now_ns();
+      bool on_dev = false;
+      for (Job *j : f->b) {
+        j->t_start = t0;
+        running[j->ticket] = j;
+        on_dev = on_dev || j->dres;
+      }
+      // the batch's device copies: a job is queued (under mu) only after the
+      // event was recorded behind its copy, so the event's last record covers
+      // the copies of every queued job
+      bool wait_copies = false;
+      if (on_dev && hipStreamWaitEvent(stream_a, copy_ev, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        wait_copies = true;
+      }
+      lk.unlock();
+      if (wait_copies) (void)hipStreamSynchronize(copy_stream);
+      f->st.assign(f->b.size(), KD_OK);
+      f->timed = opts.timeline && f->ev[0] && f->ev[1] && f->ev[2] && f->ev[3];
+      if (f->timed && hipEventRecord(f->ev[0], stream_a) != hipSuccess) f->timed = false;
+      count_stage(*f);  // overlaps the running batch's stage B
+      if (f->timed && hipEventRecord(f->ev[1], stream_a) != hipSuccess) f->timed = false;
+    } else {
+      lk.unlock();
     }
-    const uint64_t t0 = now_ns();
-    bool on_dev = false;
-    for (Job *j : b) {
-      j->t_start = t0;
-      running[j->ticket] = j;
-      on_dev = on_dev || j->dres;
+    // the running batch: results out, jobs done
+    if (busy) {
+      results(*busy);
+      const uint64_t t1 = now_ns();
+      lk.lock();
+      for (uint32_t q = 0; q < busy->b.size(); q++) {
+        running.erase(busy->b[q]->ticket);
+        finish_locked(busy->b[q], busy->st[q], (uint32_t)busy->b.size(), t1);
+      }
+      admit_locked();
+      cv_done.notify_all();
+      lk.unlock();
+      busy = nullptr;
     }
-    // the batch's device copies: a job is queued (under mu) only after the
-    // event was recorded behind its copy, so the event's last record covers
-    // the copies of every queued job
-    bool wait_copies = false;
-    if (on_dev && hipStreamWaitEvent(stream, copy_ev, 0) != hipSuccess) {
-      (void)hipGetLastError();
-      wait_copies = true;
+    // the new batch's stage B (or, with nothing to rank, its jobs are done)
+    if (f) {
+      if (f->set && rank_stage(*f) == KD_OK) {
+        busy = f;
+      } else {
+        if (f->set) results(*f);
+        const uint64_t t1 = now_ns();
+        lk.lock();
+        for (uint32_t q = 0; q < f->b.size(); q++) {
+          running.erase(f->b[q]->ticket);
+          finish_locked(f->b[q], f->st[q], (uint32_t)f->b.size(), t1);
+        }
+        admit_locked();
+        cv_done.notify_all();
+        lk.unlock();
+      }
     }
-    lk.unlock();
-    if (wait_copies) (void)hipStreamSynchronize(copy_stream);
-    std::vector<kd_status> st(b.size(), KD_OK);
-    run_batch(b, st);
-    const uint64_t t1 = now_ns();
     lk.lock();
-    for (uint32_t q = 0; q < b.size(); q++) {
-      running.erase(b[q]->ticket);
-      finish_locked(b[q], st[q], (uint32_t)b.size(), t1);
-    }
-    admit_locked();
-    cv_done.notify_all();
+  }
+  lk.unlock();
+  for (Flight &f : fl) {
+    for (hipEvent_t e : f.ev)
+      if (e) (void)hipEventDestroy(e);
+    if (f.done_ev) (void)hipEventDestroy(f.done_ev);
   }
 }
 
@@ -419,6 +582,7 @@ extern "C" kd_status kd_server_create(int device, const kd_server_opts *opts, kd
   s->device = device;
   s->opts = *opts;
   s->arena.mirrored = opts->no_mirror == 0;
+  s->arena.mirror_limit = opts->hbm_budget / 2;  // the rest of the budget stays for jobs
   for (uint64_t b = 0; b < opts->host_arena_bytes; b += Arena::kChunk)
     if (!s->arena.add_chunk(true)) break;  // fewer up front: more chunks are taken as jobs need them
   if (opts->host_arena_bytes) {
@@ -440,17 +604,19 @@ extern "C" kd_status kd_server_create(int device, const kd_server_opts *opts, kd
     return KD_EDEVICE;
   }
   if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&s->copy_ev, hipEventDisableTiming) != hipSuccess) {
-    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
-    (void)hipStreamDestroy(s->stream);
+      hipStreamCreateWithFlags(&s->stream_a, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->copy_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->counted_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&s->base_ev) != hipSuccess || hipEventRecord(s->base_ev, s->stream_a) != hipSuccess) {
+    s->release_streams();
     delete s;
     return KD_EDEVICE;
   }
   kd_status rc = kd_ctx_create(device, s->stream, &s->ctx);
+  if (rc == KD_OK) rc = kd_ctx_create(device, s->stream_a, &s->ctx_a);
   if (rc != KD_OK) {
-    (void)hipEventDestroy(s->copy_ev);
-    (void)hipStreamDestroy(s->copy_stream);
-    (void)hipStreamDestroy(s->stream);
+    if (s->ctx) kd_ctx_destroy(s->ctx);
+    s->release_streams();
     delete s;
     return rc;
   }
@@ -458,9 +624,8 @@ extern "C" kd_status kd_server_create(int device, const kd_server_opts *opts, kd
     s->worker = std::thread([s] { s->loop(); });
   } catch (...) {
     kd_ctx_destroy(s->ctx);
-    (void)hipEventDestroy(s->copy_ev);
-    (void)hipStreamDestroy(s->copy_stream);
-    (void)hipStreamDestroy(s->stream);
+    kd_ctx_destroy(s->ctx_a);
+    s->release_streams();
     delete s;
     return KD_ENOMEM;
   }
@@ -569,7 +734,17 @@ extern "C" kd_status kd_server_status(kd_server *s, uint32_t *waiting, uint32_t 
   if (admitted) *admitted = (uint32_t)s->admitted.size();
   if (running) *running = (uint32_t)s->running.size();
   if (done) *done = (uint32_t)s->done.size();
-  if (reserved) *reserved = s->reserved;
+  if (reserved) *reserved = s->reserved + s->arena.mirror_bytes;
+  return KD_OK;
+}
+
+extern "C" kd_status kd_server_timeline(kd_server *s, kd_server_stage *out, uint32_t max, uint32_t *n) {
+  if (!s || !n || (max && !out)) return KD_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
+  const uint32_t k = (uint32_t)std::min<size_t>(max, s->stages.size());
+  for (uint32_t i = 0; i < k; i++) out[i] = s->stages[i];
+  s->stages.erase(s->stages.begin(), s->stages.begin() + k);
+  *n = k;
   return KD_OK;
 }
 
@@ -584,13 +759,12 @@ extern "C" void kd_server_destroy(kd_server *s) {
   for (Job *j : s->waiting) delete j;
   for (Job *j : s->admitted) delete j;
   (void)hipSetDevice(s->device);
-  kd_ctx_destroy(s->ctx);  // synchronizes the stream
+  kd_ctx_destroy(s->ctx);    // synchronizes stream B
+  kd_ctx_destroy(s->ctx_a);  // synchronizes stream A
   (void)hipStreamSynchronize(s->copy_stream);  // copies of jobs that never ran
   if (s->d_in.p) (void)hipFree(s->d_in.p);
   if (s->d_out.p) (void)hipFree(s->d_out.p);
   s->d_in.p = s->d_out.p = nullptr;
-  (void)hipEventDestroy(s->copy_ev);
-  (void)hipStreamDestroy(s->copy_stream);
-  (void)hipStreamDestroy(s->stream);
+  s->release_streams();
   delete s;  // the arena: pinned chunks and their device mirrors
 }

@@ -68,6 +68,7 @@ def test_binding_structs_match_the_header(tmp_path):
     import ctypes
     import paper_0905_1744_amd as kdm
     pairs = {"kd_server_opts": kdm.ServerOpts, "kd_job": kdm.Job, "kd_done": kdm.Done,
+             "kd_server_stage": kdm.ServerStage,
              "kd_psp_pair": kdm.PspPair}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "kd.h"', "int main(void) {"]
     for cname, py in pairs.items():

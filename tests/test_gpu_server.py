@@ -237,3 +237,55 @@ def test_server_cancel(kd, ctx, jobs):
     for q, t in enumerate(ts[:3]):
         check_same(recs[t], alone(ctx, kd, jobs[q], 0.1))
     srv.close()
+
+
+def overlap_ms(tl):
+    """Device time during which a batch's stage A (count, layout) ran while
+    the previous batch's stage B (rank, split, copy back) was running."""
+    tot = 0.0
+    for prev, cur in zip(tl, tl[1:]):
+        a0, a1 = cur["count"]
+        b0, b1 = prev["rank"]
+        tot += max(0.0, min(a1, b1) - max(a0, b0))
+    return tot
+
+
+def test_server_pipeline_timeline(kd, ctx, jobs):
+    """Batches of at most 4 jobs through the two stages: every job is
+    bit-identical to running it alone, each batch's stages are ordered on the
+    device (its stage B starts after its stage A ends), and the records
+    report how much of each stage A ran during the previous stage B."""
+    srv = kd.Server(0, max_batch_jobs=4, timeline=True)
+    say("server-pipeline", len(jobs))
+    tickets = [(srv.submit(x.residues, x.offsets, x.B), q) for q, x in enumerate(jobs)]
+    recs = drain(srv, len(tickets))
+    for t, q in tickets:
+        check_same(recs[t], alone(ctx, kd, jobs[q], 0.1))
+    tl = srv.timeline()
+    assert len(tl) >= (len(jobs) + 3) // 4 - 1 and sum(b["jobs"] for b in tl) <= len(jobs)
+    for b in tl:
+        assert b["count"][0] <= b["count"][1] <= b["rank"][0] <= b["rank"][1]
+    for prev, cur in zip(tl, tl[1:]):
+        assert prev["rank"][0] <= cur["rank"][0]
+    say("stage A overlapping stage B: %.3f ms over %d batches" % (overlap_ms(tl), len(tl)))
+    srv.close()
+
+
+def test_server_mirrors_within_budget(kd, ctx, jobs):
+    """The input mirrors count against the budget: with room for them, the
+    reserved bytes (jobs + mirrors) never pass the budget during a burst and
+    every job still matches running it alone."""
+    sizes = [kd.job_bytes(x.residues.size, x.n) for x in jobs]
+    budget = (64 << 20) * 2 + 2 * max(sizes)   # one mirror chunk fits (half the budget)
+    srv = kd.Server(0, hbm_budget=budget, max_batch_jobs=3)
+    tickets = [(srv.submit(x.residues, x.offsets, x.B), q) for q, x in enumerate(jobs) for _ in range(2)]
+    recs, t0 = {}, time.monotonic()
+    while len(recs) < len(tickets):
+        assert srv.status()["reserved"] <= budget
+        for r in srv.poll(64, wait_s=0.005):
+            recs[r["ticket"]] = r
+        assert time.monotonic() - t0 < 60
+    assert srv.status()["reserved"] <= 64 << 20  # the mirror stays; the jobs' charges are gone
+    for t, q in tickets:
+        check_same(recs[t], alone(ctx, kd, jobs[q], 0.1))
+    srv.close()
