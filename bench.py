@@ -168,6 +168,34 @@ def rank_lookups(D):
     return int((L * np.maximum(RB - 4 * g, 0)).sum())
 
 
+def rank_roofline(probes, pairs, lookups, t_kernel, ceiling, traffic, alg_bytes, kernel="rank_pairs_kernel"):
+    """Roofline of an all-pairs rank launch.  The kernel is bound by its LDS
+    mask lookups: one 64-lane random 16-bit read of the row block's table
+    answers 16 rows x 64 columns of (word, pair) probes.  achieved = the
+    algorithmic probes sum_{i<j} min(D_i, D_j) per second; peak = the
+    lookup ceiling measured on this device (kd_calibrate_lds, random reads)
+    times the 1,024 probe slots of a lookup."""
+    peak = ceiling * 1024 / 1e12
+    achieved = probes / t_kernel / 1e12
+    return {"bound": "lds", "achieved": achieved, "peak": peak, "unit": "Tprobe/s",
+            "frac": achieved / peak, "traffic": traffic, "kernel": kernel, "kernel_ms": t_kernel * 1e3,
+            "work_per_launch": {"probes": probes, "pairs": pairs, "wave_lds_lookups": lookups,
+                                "probe_slots_used": probes / (lookups * 1024.0),
+                                "algorithmic_bytes": alg_bytes},
+            "peak_note": ("no published rate exists for random 16-bit LDS reads: the peak is the rate "
+                          "kd_calibrate_lds measures live (random indices, 32 reads in flight per lane; "
+                          "bank conflicts hold it near 8 CU-cycles per 64-lane read), times 16 rows x 64 "
+                          "columns per lookup; conflict-free reads at the published 128 B/clk/CU would "
+                          "allow 8x that"),
+            "lookups": {"achieved": lookups / t_kernel, "peak": ceiling, "unit": "64-lane reads/s",
+                        "frac": lookups / t_kernel / ceiling},
+            "probe_per_lane_cycle": {"achieved": achieved, "peak": PEAK_TPROBE,
+                                     "ratio": achieved / PEAK_TPROBE,
+                                     "note": "the probes against one per VALU lane-cycle (256 CUs x 64 lanes x 2.4 GHz)"},
+            "hbm": {"bytes_per_launch": traffic, "frac": (traffic / t_kernel / 8e12) if traffic else None,
+                    "algorithmic_bytes": alg_bytes}}
+
+
 def lds_ceiling(ctx, workgroups=1024, steps=64):
     """Measured rate of random 16-bit LDS reads (32 in flight per lane) over
     the whole chip, in 64-lane reads per second (kd_calibrate_lds)."""
@@ -452,14 +480,12 @@ def bench_psp(args):
     print(json.dumps(line), flush=True)
 
 
-def batch_roofline(probes, pairs, stages):
-    """Probe roofline of the one rank launch of a batch (all sets)."""
+def batch_roofline(probes, pairs, lookups, ceiling, stages, alg_bytes):
+    """Roofline of the one rank launch of a batch (all sets), as for one set."""
     ms, n = stages["pairs"]
     t = ms / max(n, 1) / 1e3
-    a = probes / t / 1e12
-    return {"bound": "alu", "achieved": a, "peak": PEAK_TPROBE, "unit": "Tprobe/s", "frac": a / PEAK_TPROBE,
-            "traffic": None, "kernel": "rank_pairs_kernel (all sets in one launch)", "kernel_ms": t * 1e3,
-            "work_per_launch": {"probes": probes, "pairs": pairs}}
+    return rank_roofline(probes, pairs, lookups, t, ceiling, None, alg_bytes,
+                         kernel="rank_pairs_kernel (all sets in one launch)")
 
 
 def bench_batch_graph(ctx, res, off, first, Bs, args, out, t_eager):
@@ -520,7 +546,11 @@ def bench_batched(args):
         tune = {"tasks_per_cu": best, "ms_per_shape": ms}
     _, _, loff = kb.export_lists()
     D = np.diff(loff.cpu().numpy())
-    probes = sum(probe_count(D[a:b]) for a, b in zip(first[:-1].astype(np.int64), first[1:].astype(np.int64)))
+    bounds = list(zip(first[:-1].astype(np.int64), first[1:].astype(np.int64)))
+    probes = sum(probe_count(D[a:b]) for a, b in bounds)
+    lookups = sum(rank_lookups(D[a:b]) for a, b in bounds if b > a)
+    alg_bytes = int(D.sum()) * 2 + 8 * Ntot
+    ceiling = lds_ceiling(ctx)
     kb.destroy()
     for _ in range(args.warmup):
         ctx.batch_run(res, off, first, Bs, args.delta, out=out)
@@ -540,7 +570,7 @@ def bench_batched(args):
         line = {"metric": "batched k-mer rank + split: pair-similarities/s", "value": pairs / t_batch,
                 "unit": "pair-similarities/s", "ms_per_step": t_batch * 1e3, "sets": len(sets),
                 "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
-                "roofline": batch_roofline(probes, pairs, stages), "graph": graph}
+                "roofline": batch_roofline(probes, pairs, lookups, ceiling, stages, alg_bytes), "graph": graph}
         ctx.close()
         print(json.dumps(line), flush=True)
         return
@@ -583,89 +613,152 @@ def bench_batched(args):
         "speedup_vs_per_set_loop": t_loop / t_batch,
         "identical_outputs": same,
         "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
-        "roofline": batch_roofline(probes, pairs, stages),
+        "roofline": batch_roofline(probes, pairs, lookups, ceiling, stages, alg_bytes),
         "graph": graph,
     }
     ctx.close()
     print(json.dumps(line), flush=True)
 
 
+def plain_loop(ctx, kd, pool, pick, arr, ref, delta):
+    """The plain per-job launch loop under the same arrivals: job i starts at
+    max(its arrival, the previous job's end) and runs count -> rank -> split
+    from host arrays with a synchronization at its end."""
+    import numpy as np
+    import torch
+    n = len(pick)
+    done = np.zeros(n)
+    ok = True
+    start = time.monotonic()
+    for i in range(n):
+        wait = start + arr[i] - time.monotonic()
+        if wait > 0:
+            time.sleep(wait)
+        x = pool[pick[i]]
+        ks = ctx.kmer_count(x.residues, x.offsets.view(np.int64))
+        R = ctx.kmer_rank(ks, delta)
+        p = ctx.sample_partition(R, x.B)
+        got = (R.cpu().numpy(), kd.u32(p["bucket"]), kd.u32(p["order"]), kd.u32(p["offsets"]))
+        ks.destroy()
+        done[i] = time.monotonic() - start
+        w = ref[pick[i]]
+        ok = ok and all(np.array_equal(a, b) for a, b in zip(got, w))
+    lat = done - arr[:n]
+    return {"jobs": n, "jobs_per_s": n / done[-1], "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "identical_to_alone": bool(ok)}
+
+
 def bench_served(args):
-    """Poisson request streams through the server (continuous batching) and
-    through the same server limited to one job at a time (the FIFO loop);
-    latency = completion - scheduled arrival.  Every served result is
-    compared bit for bit with the job run alone through the single-set calls."""
+    """Poisson request streams through the server (continuous batching,
+    two-stage pipeline) and through the same server limited to one job at a
+    time (the FIFO loop); latency = completion - scheduled arrival.  Each
+    rate offers args.jobs arrivals or args.rate_seconds of them, whichever is
+    fewer (the FIFO loop at most args.fifo_seconds); arrival i carries job
+    pool[k_i] of a seeded pool of distinct jobs.  Every served result is
+    compared bit for bit with its job run alone through the single-set calls."""
     import numpy as np
     import synth
     rates = [float(x) for x in args.rates.split(",")]
     t0 = time.perf_counter()
-    jobs = synth.served_jobs(5, args.jobs, workers=min(16, os.cpu_count() or 1))
-    print(f"[bench] served workload: {len(jobs)} jobs, {sum(j.n for j in jobs)} sequences, "
+    pool = synth.served_jobs(5, args.job_pool, workers=min(16, os.cpu_count() or 1))
+    print(f"[bench] served workload: pool of {len(pool)} jobs, {sum(j.n for j in pool)} sequences, "
           f"generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     import paper_0905_1744_amd as kd
     ctx = kd.Context(0)
     ref = []
-    for x in jobs:  # each job alone through the single-set calls
+    for x in pool:  # each job alone through the single-set calls
         ks = ctx.kmer_count(x.residues, x.offsets.view(np.int64))
         R = ctx.kmer_rank(ks, args.delta)
         p = ctx.sample_partition(R, x.B)
         ref.append((R.cpu().numpy(), kd.u32(p["bucket"]), kd.u32(p["order"]), kd.u32(p["offsets"])))
         ks.destroy()
-    pairs = np.array([x.n * (x.n - 1) / 2 for x in jobs])
-    results = {}
+    pick_all = np.random.default_rng(55).integers(0, len(pool), size=args.jobs)
+    results, overlap = {}, {}
     identical = True
-    for mode in ("batched", "fifo"):
+    for mode in ("batched", "loop"):
         for lam in rates:
-            arr = synth.served_arrivals(5, len(jobs), lam)
-            srv = kd.Server(0, hbm_budget=200 << 30, max_batch_jobs=0 if mode == "batched" else 1,
-                            host_arena_bytes=256 << 20)
-            for x in jobs[:2]:  # first-call costs out of the way
+            cap_s = args.rate_seconds if mode == "batched" else args.fifo_seconds
+            n = int(max(50, min(args.jobs, cap_s * lam)))
+            pick = pick_all[:n]
+            arr = synth.served_arrivals(5, n, lam)
+            if mode == "loop":
+                results.setdefault(mode, {})[str(int(lam) if lam.is_integer() else lam)] = \
+                    plain_loop(ctx, kd, pool, pick, arr, ref, args.delta)
+                r = results[mode][str(int(lam) if lam.is_integer() else lam)]
+                identical = identical and r["identical_to_alone"]
+                print(f"[bench] served plain loop rate {lam:g}/s, {n} jobs: p50 {r['p50_ms']:.2f} ms "
+                      f"p99 {r['p99_ms']:.2f} ms, {r['jobs_per_s']:.0f} jobs/s", file=sys.stderr, flush=True)
+                continue
+            srv = kd.Server(0, hbm_budget=200 << 30, max_batch_seqs=args.max_batch_seqs,
+                            host_arena_bytes=256 << 20, timeline=True)
+            for x in pool[:2]:  # first-call costs out of the way
                 srv.submit(x.residues, x.offsets, x.B, args.delta)
             got = 0
             while got < 2:
                 got += len(srv.poll(8, wait_s=0.1))
+            srv.timeline()
             recs, tick = {}, {}
             i = 0
             start = time.monotonic_ns()
-            while len(recs) < len(jobs):
+            while len(recs) < n:
                 now = time.monotonic_ns()
-                while i < len(jobs) and start + int(arr[i] * 1e9) <= now:
-                    tick[srv.submit(jobs[i].residues, jobs[i].offsets, jobs[i].B, args.delta)] = i
+                while i < n and start + int(arr[i] * 1e9) <= now:
+                    x = pool[pick[i]]
+                    tick[srv.submit(x.residues, x.offsets, x.B, args.delta)] = i
                     i += 1
-                wait = (start + int(arr[i] * 1e9) - time.monotonic_ns()) / 1e9 if i < len(jobs) else 0.05
+                wait = (start + int(arr[i] * 1e9) - time.monotonic_ns()) / 1e9 if i < n else 0.05
                 for r in srv.poll(256, wait_s=min(max(wait, 0.0), 0.002)):
-                    recs[tick[r["ticket"]]] = r
+                    q = tick[r["ticket"]]
+                    w = ref[pick[q]]
+                    ok = r["status"] == 0 and np.array_equal(r["ranks"], w[0]) and np.array_equal(r["bucket"], w[1]) \
+                        and np.array_equal(r["order"], w[2]) and np.array_equal(r["offsets"], w[3])
+                    recs[q] = (r["t_done_ns"], r["batch_jobs"], ok)
+            tl = srv.timeline()
             srv.close()
-            lat = np.array([(recs[q]["t_done_ns"] - start) / 1e9 - arr[q] for q in range(len(jobs))])
-            end = max(r["t_done_ns"] for r in recs.values())
-            ok = all(recs[q]["status"] == 0 for q in range(len(jobs)))
-            for q in range(len(jobs)):
-                r = recs[q]
-                ok = ok and np.array_equal(r["ranks"], ref[q][0]) and np.array_equal(r["bucket"], ref[q][1]) \
-                    and np.array_equal(r["order"], ref[q][2]) and np.array_equal(r["offsets"], ref[q][3])
+            lat = np.array([(recs[q][0] - start) / 1e9 - arr[q] for q in range(n)])
+            end = max(v[0] for v in recs.values())
+            ok = all(v[2] for v in recs.values())
             identical = identical and ok
             span = (end - start) / 1e9
-            results.setdefault(mode, {})[str(int(lam) if lam.is_integer() else lam)] = {
-                "jobs_per_s": len(jobs) / span, "pairs_per_s": float(pairs.sum()) / span,
+            pairs = float(sum(pool[k].n * (pool[k].n - 1) / 2 for k in pick))
+            key = str(int(lam) if lam.is_integer() else lam)
+            results.setdefault(mode, {})[key] = {
+                "jobs": n, "jobs_per_s": n / span, "pairs_per_s": pairs / span,
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                "mean_batch_jobs": float(np.mean([recs[q]["batch_jobs"] for q in range(len(jobs))])),
+                "mean_batch_jobs": float(np.mean([v[1] for v in recs.values()])),
                 "identical_to_alone": ok}
-            print(f"[bench] served {mode} rate {lam:g}/s: p50 {results[mode][str(int(lam) if lam.is_integer() else lam)]['p50_ms']:.2f} ms "
-                  f"p99 {np.percentile(lat, 99) * 1e3:.2f} ms", file=sys.stderr, flush=True)
+            if tl:
+                a_ms = sum(b["count"][1] - b["count"][0] for b in tl)
+                ov = 0.0
+                for prev, cur in zip(tl, tl[1:]):
+                    ov += max(0.0, min(cur["count"][1], prev["rank"][1]) - max(cur["count"][0], prev["rank"][0]))
+                overlap[key] = {"batches": len(tl), "stage_a_ms": a_ms,
+                                "stage_b_ms": sum(b["rank"][1] - b["rank"][0] for b in tl),
+                                "stage_a_during_previous_stage_b_ms": ov,
+                                "batches_started_during_previous_stage_b": sum(
+                                    1 for prev, cur in zip(tl, tl[1:]) if cur["count"][0] < prev["rank"][1])}
+            print(f"[bench] served {mode} rate {lam:g}/s, {n} jobs: p50 {results[mode][key]['p50_ms']:.2f} ms "
+                  f"p99 {results[mode][key]['p99_ms']:.2f} ms, {n / span:.0f} jobs/s", file=sys.stderr, flush=True)
     top = str(int(rates[-1]) if rates[-1].is_integer() else rates[-1])
     line = {
         "metric": "served k-mer rank + split: p50/p99 request latency and jobs/s per arrival rate",
         "value": results["batched"][top]["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1,
-        "steps": len(jobs), "warmup": 2, "ms_per_step": None, "higher_is_better": True,
+        "steps": args.jobs, "warmup": 2, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u16/f64", "data": "synthetic",
-        "config": {"workload": (f"served: {len(jobs)} jobs per rate, Poisson arrivals at {args.rates}/s, "
-                                "N log-uniform [64, 8192], 4-32 families, lognormal length mean 300, "
-                                "divergence 5-30%, B = max(1, N/256), seed 5, budget 200 GiB"),
-                   "delta": args.delta},
+        "config": {"workload": (f"served: per rate min({args.jobs} arrivals, {args.rate_seconds:g} s of them) "
+                                f"(plain per-job loop: at most {args.fifo_seconds:g} s), Poisson arrivals at "
+                                f"{args.rates}/s, each a job drawn from a pool of {len(pool)}: N log-uniform "
+                                "[64, 8192], 4-32 families, lognormal length mean 300, divergence 5-30%, "
+                                "B = max(1, N/256), seed 5, budget 200 GiB"),
+                   "delta": args.delta, "max_batch_seqs": args.max_batch_seqs},
         "rates": results, "identical_to_alone": identical,
-        # throughput of continuous batching over one job at a time, per offered rate
-        "batched_over_one_at_a_time": {r: results["batched"][r]["jobs_per_s"] / results["fifo"][r]["jobs_per_s"]
-                                       for r in results["batched"]},
+        # throughput of the server over the plain per-job launch loop, per offered rate
+        "batched_over_plain_loop": {r: results["batched"][r]["jobs_per_s"] / results["loop"][r]["jobs_per_s"]
+                                    for r in results["batched"]},
+        "plain_loop_note": ("each arrival, in arrival order and not before its arrival time, through "
+                            "kmer_count -> kmer_rank -> sample_partition on one context from its host arrays, "
+                            "results copied back, the stream synchronized before the next job"),
+        "pipeline_overlap": overlap,
     }
     ctx.close()
     print(json.dumps(line), flush=True)
@@ -679,7 +772,14 @@ def main():
     ap.add_argument("--workload", default="paper20k", choices=sorted(WORKLOADS) + ["batched", "served", "global20k", "global100k",
                                                      "trees20k", "trees100k", "psp"])
     ap.add_argument("--sets", type=int, default=4096, help="batched workload: number of sets")
-    ap.add_argument("--jobs", type=int, default=300, help="served workload: jobs per arrival rate")
+    ap.add_argument("--jobs", type=int, default=10000, help="served workload: arrivals per rate (at most)")
+    ap.add_argument("--job-pool", type=int, default=1000, help="served workload: distinct jobs")
+    ap.add_argument("--rate-seconds", type=float, default=60.0,
+                    help="served workload: at most this many seconds of arrivals per rate")
+    ap.add_argument("--fifo-seconds", type=float, default=20.0,
+                    help="served workload: the same for the plain per-job loop")
+    ap.add_argument("--max-batch-seqs", type=int, default=1 << 20,
+                    help="served workload: sequences per batch")
     ap.add_argument("--pairs", type=int, default=256, help="psp workload: profile pairs")
     ap.add_argument("--rates", default="10,20,50,100,200,500,1000,2000,4000,100000",
                     help="served workload: arrival rates (jobs/s)")
@@ -806,20 +906,8 @@ def main():
     lookups = rank_lookups(D)
     ceiling = lds_ceiling(ctx)
     traffic = measured_traffic("rank_pairs_kernel", args.workload, rows)
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
-                "frac": achieved / PEAK_TPROBE, "traffic": traffic,
-                "kernel": "rank_pairs_kernel", "kernel_ms": t_pair * 1e3,
-                "work_per_launch": {"probes": probes, "pairs": pairs, "wave_lds_lookups": lookups,
-                                    "algorithmic_bytes": int(D.sum()) * 2 + 8 * N},
-                "achieved_note": ("algorithm-equivalent rate: the pairs' merge probes "
-                                  "sum_{i<j} min(D_i, D_j) per second against one probe per lane-cycle; "
-                                  "the kernel does them as bit-sliced table lookups, 16 rows per lookup"),
-                "lds": {"bound": "lds", "achieved": lookups / t_pair, "peak": ceiling,
-                        "unit": "wave-reads/s", "frac": lookups / t_pair / ceiling,
-                        "note": ("the kernel's own ceiling: random 16-bit LDS reads, 32 in flight per "
-                                 "lane, measured live by kd_calibrate_lds on this device")},
-                "hbm": {"bytes_per_launch": traffic,
-                        "frac": (traffic / t_pair / 8e12) if traffic else None}}
+    roofline = rank_roofline(probes, pairs, lookups, t_pair, ceiling, traffic,
+                             int(D.sum()) * 2 + 8 * N)
     line = {
         "metric": METRIC, "value": value, "unit": "pair-similarities/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
