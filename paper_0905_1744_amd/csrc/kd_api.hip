@@ -440,7 +440,9 @@ constexpr double kRowBlockCost = 6.0;
 //    balance better.
 //  - The pieces become the per-XCD queues of the persistent rank launch
 //    (out[beg[x] .. beg[x+1]), largest first); a workgroup takes from its
-//    own XCD's queue and steals from the others once it is empty.
+//    own XCD's queue and steals from the others once it is empty.  (Kept in
+//    strip order instead, the 20k launch took 1.28 ms instead of 1.23 and
+//    fetched no fewer bytes.)
 // grp_len: host copy of every column group's padded list length
 // (batch-wide numbering).
 void build_costed_tasks(const std::vector<SetView> &views, const std::vector<uint32_t> &grp_first,

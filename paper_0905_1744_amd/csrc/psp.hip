@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void psp_scores_kernel(const PspWork *__restri
 #pragma unroll
       for (int r = 0; r < 8; r++) {
         gdouble *row = (gdouble *)pr.scores + (uint64_t)min(x0 + 8 * h + r, pr.lx - 1u) * ly;
-        row[off[r]] = v[r];
+        __builtin_nontemporal_store(v[r], row + off[r]);  // streamed: never read back here
       }
     }
   }
