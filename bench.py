@@ -35,7 +35,7 @@ WORKLOADS = {
 
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by
-# a plain-copy calibration (profiles/rank_pairs_paper20k.md,
+# a plain-copy calibration (profiles/rank_pairs_paper20k.md, rank_pairs_large100k.md,
 # profiles/rank_cross_global100k.md).  Reported only while the kernel's
 # sources hash to the measured version and the same work-list shape is in use.
 RANK_SOURCES = ["paper_0905_1744_amd/csrc/pair.hip", "paper_0905_1744_amd/csrc/tile.h",
@@ -44,19 +44,25 @@ TREE_SOURCES = ["paper_0905_1744_amd/csrc/tree.hip", "paper_0905_1744_amd/csrc/t
                 "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h",
                 "paper_0905_1744_amd/csrc/radix.h"]
 TRAFFIC = {
-    "rank_pairs_kernel": {"sources": RANK_SOURCES, "sha256_16": "2f650a120323f405",
-                          "workload": "paper20k", "rows_per_workgroup": -1, "bytes_per_launch": 839851227},
-    "rank_cross_kernel": {"sources": ["paper_0905_1744_amd/csrc/cross.hip", "paper_0905_1744_amd/csrc/tile.h",
-                                      "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h"],
-                          "sha256_16": "6f4d6a4f4effdd3f", "workload": "global100k", "rows_per_workgroup": None,
-                          "bytes_per_launch": 2843834059},
-    "dist_pairs_kernel": {"sources": TREE_SOURCES, "sha256_16": "dadf40f2d4dcd576", "workload": "trees20k",
-                          "rows_per_workgroup": None, "bytes_per_launch": 492756992},
-    "upgma_kernel": {"sources": TREE_SOURCES, "sha256_16": "dadf40f2d4dcd576", "workload": "trees20k",
-                     "rows_per_workgroup": None, "bytes_per_launch": 998621184},
+    # key: (kernel, workload); "shape" is the work-list shape the counters were
+    # taken at (workgroups per CU for the rank kernel), None where there is none
+    ("rank_pairs_kernel", "paper20k"): {"sources": RANK_SOURCES, "sha256_16": "173c0a370af077d8",
+                                        "shape": 32, "bytes_per_launch": 250051584},
+    ("rank_pairs_kernel", "large100k"): {"sources": RANK_SOURCES, "sha256_16": "173c0a370af077d8",
+                                         "shape": 32, "bytes_per_launch": 6307022165},
+    ("rank_cross_kernel", "global100k"): {"sources": ["paper_0905_1744_amd/csrc/cross.hip",
+                                                      "paper_0905_1744_amd/csrc/tile.h",
+                                                      "paper_0905_1744_amd/csrc/bitcount.h",
+                                                      "paper_0905_1744_amd/csrc/klog.h"],
+                                          "sha256_16": "6f4d6a4f4effdd3f", "shape": None,
+                                          "bytes_per_launch": 2843834059},
+    ("dist_pairs_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "dadf40f2d4dcd576",
+                                        "shape": None, "bytes_per_launch": 492756992},
+    ("upgma_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "dadf40f2d4dcd576",
+                                   "shape": None, "bytes_per_launch": 998621184},
     # psp_g_kernel + psp_scores_kernel, the two launches of one psp_scores call
-    "psp": {"sources": ["paper_0905_1744_amd/csrc/psp.hip"], "sha256_16": "641050ec05ed3fe7", "workload": "psp",
-            "rows_per_workgroup": None, "bytes_per_launch": 94292377 + 2872391142},
+    ("psp", "psp"): {"sources": ["paper_0905_1744_amd/csrc/psp.hip"], "sha256_16": "27c995852957b595",
+                     "shape": None, "bytes_per_launch": 94294016 + 2873273344},
 }
 
 
@@ -69,9 +75,9 @@ def sources_hash(paths):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, rows):
-    t = TRAFFIC[kernel]
-    if workload != t["workload"] or rows != t["rows_per_workgroup"]:
+def measured_traffic(kernel, workload, shape):
+    t = TRAFFIC.get((kernel, workload))
+    if t is None or shape != t["shape"]:
         return None
     return t["bytes_per_launch"] if sources_hash(t["sources"]) == t["sha256_16"] else None
 
@@ -902,10 +908,10 @@ def main():
     probes = probe_count(D)
     t_pair = pair_ms / max(pair_n, 1) / 1e3
     achieved = probes / t_pair / 1e12
-    rows = tune["tasks_per_cu"] if tune else 4
+    tpc = tune["tasks_per_cu"] if tune else 4
     lookups = rank_lookups(D)
     ceiling = lds_ceiling(ctx)
-    traffic = measured_traffic("rank_pairs_kernel", args.workload, rows)
+    traffic = measured_traffic("rank_pairs_kernel", args.workload, tpc)
     roofline = rank_roofline(probes, pairs, lookups, t_pair, ceiling, traffic,
                              int(D.sum()) * 2 + 8 * N)
     line = {

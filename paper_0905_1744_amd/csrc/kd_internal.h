@@ -390,14 +390,14 @@ __host__ __device__ constexpr uint8_t dayhoff6(uint32_t ch) {
 // d = -ln(delta + F_xy) with 0 <= F_xy <= 1 (Equation 2), so neither a tile
 // sum nor any partial total can overflow.  Every kernel that touches an
 // accumulator derives F with this same function.
-__device__ inline int fix_bits(uint32_t n, double delta) {
+__host__ __device__ inline int fix_bits(uint32_t n, double delta) {
   const double dmax = fmax(fabs(log(delta)), log1p(delta));
   return 61 - ilogb((double)n * dmax);
 }
 
-__device__ inline long long fix_q(double v, int F) { return (long long)rint(ldexp(v, F)); }
+__host__ __device__ inline long long fix_q(double v, int F) { return (long long)rint(ldexp(v, F)); }
 
-__device__ inline double fix_value(long long s, int F) { return ldexp((double)s, -F); }
+__host__ __device__ inline double fix_value(long long s, int F) { return ldexp((double)s, -F); }
 
 __device__ inline unsigned long long lanemask_lt() {
   return (1ull << __lane_id()) - 1ull;

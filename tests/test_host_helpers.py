@@ -1,7 +1,8 @@
 """CPU checks of the device helpers that are plain arithmetic (compiled with
 hipcc as host code, no GPU needed): the table-driven log used for the
 Equation 2 distance against the C library log, and the bit-sliced
-carry-save counting + plane transpose against direct counting."""
+carry-save counting + plane transpose against direct counting; the rank
+launch's host logic (work lists, per-XCD queues, fixed-point scale)."""
 import os
 import subprocess
 
@@ -20,6 +21,23 @@ def test_helpers_on_host(tmp_path):
                     os.path.join(ROOT, "tests", "host", "helpers_check.cpp"), "-o", exe],
                    check=True, capture_output=True)
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "OK" in r.stdout
+
+
+def test_worklists_on_host(tmp_path):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "worklist_check")
+    r = subprocess.run([hipcc, "-x", "hip", "--cuda-host-only", "-O2", "-std=c++17",
+                        "-I", os.path.join(ROOT, "include"),
+                        "-I", os.path.join(ROOT, "paper_0905_1744_amd", "csrc"),
+                        os.path.join(ROOT, "tests", "host", "worklist_check.cpp"), "-o", exe],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "OK" in r.stdout
