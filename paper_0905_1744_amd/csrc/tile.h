@@ -208,29 +208,72 @@ __device__ __forceinline__ void column_excess_grouped(const uint32_t *__restrict
   }
 }
 
+// Lane exchanges of the row-sum butterfly, all register to register (no
+// LDS): the two halves of a double move as 32-bit words.
+__device__ __forceinline__ uint32_t dlo(double x) { return (uint32_t)__double_as_longlong(x); }
+__device__ __forceinline__ uint32_t dhi(double x) { return (uint32_t)((unsigned long long)__double_as_longlong(x) >> 32); }
+__device__ __forceinline__ double dmk(uint32_t lo, uint32_t hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One butterfly step across lanes l and l ^ 32 for two values: lanes below
+// 32 return a(l) + a(l + 32), lanes from 32 on b(l - 32) + b(l).
+// v_permlane32_swap exchanges the upper half of its first operand with the
+// lower half of its second.
+__device__ __forceinline__ double fold32(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(dlo(a), dlo(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(dhi(a), dhi(b), false, false);
+  return dmk(lo[0], hi[0]) + dmk(lo[1], hi[1]);
+}
+
+// The same across lanes l and l ^ 16: v_permlane16_swap exchanges the odd
+// 16-lane rows of its first operand with the even rows of its second.
+__device__ __forceinline__ double fold16(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(dlo(a), dlo(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(dhi(a), dhi(b), false, false);
+  return dmk(lo[0], hi[0]) + dmk(lo[1], hi[1]);
+}
+
+// x from lane l ^ m, m in {1, 2, 4, 8}, by DPP moves inside 16-lane rows:
+// quad permutations for 1 and 2, rotation by 8 for 8, and for 4 two shifts
+// by 4 written to alternate groups of four lanes (bank masks).
+template <int M>
+__device__ __forceinline__ uint32_t xor_dpp(uint32_t x) {
+  if constexpr (M == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // quad_perm 1 0 3 2
+  if constexpr (M == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // quad_perm 2 3 0 1
+  if constexpr (M == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);  // row_ror:8
+  if constexpr (M == 4) {
+    const int t = __builtin_amdgcn_update_dpp((int)x, (int)x, 0x104, 0xF, 0x5, false);  // row_shl:4, lanes 0-3, 8-11
+    return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)x, 0x114, 0xF, 0xA, false);   // row_shr:4, lanes 4-7, 12-15
+  }
+}
+template <int M>
+__device__ __forceinline__ double xor_lane(double x) {
+  return dmk(xor_dpp<M>(dlo(x)), xor_dpp<M>(dhi(x)));
+}
+
 // Finishes a fixed halving butterfly over the 64 lanes.  On entry lane l
 // holds u8[i] = the pair sum (lanes l, l^32) of value i + 8 (l >> 5); on
-// exit lanes 4r..4r+3 return the total of value r over all 64 lanes.
+// exit lanes 4r..4r+3 return the total of value r over all 64 lanes.  At
+// every step a lane adds its own value to its partner's, so the result does
+// not depend on how the values travel.
 __device__ __forceinline__ double halving_reduce8(const double (&u8)[8], uint32_t lane) {
   double u4[4], u2[2];
-  const bool b4 = lane & 16u, b3 = lane & 8u, b2 = lane & 4u;
+  const bool b3 = lane & 8u, b2 = lane & 4u;
+  // lanes with bit 4 clear keep value i, the others value i + 4
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
-    const double send = b4 ? u8[i] : u8[i + 4];
-    const double keep = b4 ? u8[i + 4] : u8[i];
-    u4[i] = keep + __shfl_xor(send, 16, 64);
-  }
+  for (int i = 0; i < 4; i++) u4[i] = fold16(u8[i], u8[i + 4]);
 #pragma unroll
   for (int i = 0; i < 2; i++) {
     const double send = b3 ? u4[i] : u4[i + 2];
     const double keep = b3 ? u4[i + 2] : u4[i];
-    u2[i] = keep + __shfl_xor(send, 8, 64);
+    u2[i] = keep + xor_lane<8>(send);
   }
   const double send = b2 ? u2[0] : u2[1];
   const double keep = b2 ? u2[1] : u2[0];
-  double u1 = keep + __shfl_xor(send, 4, 64);
-  u1 += __shfl_xor(u1, 2, 64);
-  u1 += __shfl_xor(u1, 1, 64);
+  double u1 = keep + xor_lane<4>(send);
+  u1 += xor_lane<2>(u1);
+  u1 += xor_lane<1>(u1);
   return u1;
 }
 
@@ -339,12 +382,11 @@ __device__ __forceinline__ void slice_counts(const SetView &v, const RankShared 
 // they were summed) and does the rest; rank_tile does both parts.
 // Per-column data of a tile, loaded before the counting so that its
 // latency overlaps the lookups: the column's count>=2 list (length hl per
-// lane, first four entries q0) and its word count.
+// lane, first four entries q0) and the reciprocal of its k-mer count K.
 struct TileCol {
   const uint32_t *hp;
   uint32_t hl;
   uint32_t q0[4];
-  uint32_t Kc;
   double invKc;
 };
 
@@ -361,7 +403,6 @@ __device__ __forceinline__ TileCol tile_col(const SetView &v, uint32_t g) {
 #pragma unroll
     for (int k = 0; k < 4; k++) c.q0[k] = c.hp[(size_t)k * 64];
   }
-  c.Kc = vc ? v.K[sc] : 1u;
   c.invKc = vc ? v.invK[sc] : 0.0;
   return c;
 }
@@ -374,34 +415,32 @@ __device__ __forceinline__ void tile_finish(const SetView &v, RankShared &sh, ui
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t sc = 64u * g + lane;
   const bool vc = sc < v.N;
-  const uint32_t Kc = tc.Kc;
   const double invKc = tc.invKc;
   column_excess_grouped(tc.hp, tc.hl, tc.q0, sh.row.BM, eid, ecnt, en, cnt);
   // F = shared / min(K_r, K_c) (Equation 1), d = -ln(delta + F) (Equation 2);
   // rows r and r + 8 are formed together and immediately folded across
-  // lanes l and l ^ 32 (first step of the halving butterfly)
+  // lanes l and l ^ 32 (first step of the halving butterfly).  Every lane
+  // evaluates all 16 rows without branching (the argument of the logarithm
+  // is at least delta > 0 even for pairs outside the triangle or the set)
+  // and keeps 0 where the pair does not count.  The reciprocal of the
+  // shorter K is the larger of the two rounded reciprocals (rounding is
+  // monotonic; padding rows and columns hold 0).
   double u8[8];
   double colsum = 0.0;
-  const bool b5 = lane & 32u;
 #pragma unroll
   for (int r = 0; r < 8; r++) {
     double d[2];
 #pragma unroll
     for (int h = 0; h < 2; h++) {
       const uint32_t rr = r + 8 * h, sr = 16u * rb + rr;
-      d[h] = 0.0;
-      if (vc && (kCross || sc < sr) && sr < row_n) {
-        const double inv = sh.row.rowK[rr] < Kc ? sh.row.rowInv[rr] : invKc;
-        d[h] = -log_tab(fma((double)cnt[rr], inv, delta), sh.logt, sh.ln2);
-      }
+      const bool ok = vc && (kCross || sc < sr) && sr < row_n;
+      const double inv = fmax(sh.row.rowInv[rr], invKc);
+      const double lg = log_tab(fma((double)cnt[rr], inv, delta), sh.logt, sh.ln2);
+      d[h] = ok ? -lg : 0.0;
     }
     colsum += d[0];
     colsum += d[1];
-    if (!kCross) {
-      const double send = b5 ? d[0] : d[1];
-      const double keep = b5 ? d[1] : d[0];
-      u8[r] = keep + __shfl_xor(send, 32, 64);
-    }
+    if (!kCross) u8[r] = fold32(d[0], d[1]);
   }
   if (!kCross) {
     const double rowtot = halving_reduce8(u8, lane);
