@@ -160,10 +160,11 @@ kd_status kmer_similarity(kd_ctx *ctx, const kd_set *set, uint32_t r0, uint32_t 
 kd_status kmer_rank(kd_ctx *ctx, const kd_set *set, double delta, double *ranks);
 
 /* Autotuner for the rank kernel's work-list shape.  The all-pairs work of a
- * counted object is cut into about T = t x (compute units) workgroups of
- * equal estimated cost (runs of row blocks against strips of 2,048
- * sequences); more workgroups balance better, fewer flush fewer column sums
- * to the accumulators.  Times kmer_rank on `set` for each of the
+ * counted object is cut into about T = t x (compute units) tasks of equal
+ * estimated cost (runs of row blocks against strips of 2,048 sequences),
+ * which one persistent workgroup per compute unit takes from per-XCD
+ * queues; more tasks balance better, fewer flush fewer column sums to the
+ * accumulators.  Times kmer_rank on `set` for each of the
  * KD_TUNE_CANDIDATES values t = {2, 4, 8, 16, 32} (one warm-up and three
  * timed runs each; the stream is synchronized), checks that all shapes give
  * bit-identical ranks (KD_EDEVICE otherwise), gives the set the fastest
@@ -174,7 +175,7 @@ kd_status kmer_rank(kd_ctx *ctx, const kd_set *set, double delta, double *ranks)
  *   ms_out  NULL or double[KD_TUNE_CANDIDATES]: mean milliseconds per shape */
 #define KD_TUNE_CANDIDATES 5
 kd_status kd_autotune(kd_ctx *ctx, kd_set *set, double delta, uint32_t *best, double *ms_out);
-/* Set t (rank workgroups per compute unit, 1..4096) by hand for the size
+/* Set t (rank tasks per compute unit, 1..4096) by hand for the size
  * class of (nsets, n); it applies to objects counted afterwards. */
 kd_status kd_ctx_set_tasks_per_cu(kd_ctx *ctx, uint32_t nsets, uint32_t n, uint32_t tasks);
 

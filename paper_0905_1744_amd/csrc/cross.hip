@@ -56,21 +56,19 @@ __global__ __launch_bounds__(1024) void rank_cross_kernel(Segs cols, const SetVi
     touch_rows<true>(rv, ConsecutiveRows{16u * rb, rv.N}, rv.exc_ids, e0, en, sh.row);
     const bool lds_exc = en <= kExcLds;
     if (lds_exc) {
-      for (uint32_t e = tid; e < en; e += 1024) sh.exc_id[e] = rv.exc_ids[e0 + e];
       for (uint32_t e = tid; e < 16u * en; e += 1024) sh.exc_c[e] = rv.exc_cnt[16ull * e0 + e];
     }
     __syncthreads();
-    const uint16_t *eid = lds_exc ? sh.exc_id : rv.exc_ids + e0;
     const uint16_t *ecnt = lds_exc ? sh.exc_c : rv.exc_cnt + 16ull * e0;
     if (ga != kNone) {
       uint32_t gl;
       const uint32_t q = cross_set(cols, ga, gl);
-      rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, fix, eid, ecnt, en, sh.colacc[wave]);
+      rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, fix, ecnt, sh.colacc[wave]);
     }
     if (gb != kNone) {
       uint32_t gl;
       const uint32_t q = cross_set(cols, gb, gl);
-      rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, fix, eid, ecnt, en, sh.colacc[31u - wave]);
+      rank_tile<true>(cols.views[q], sh, rb, gl, rv.N, delta, fix, ecnt, sh.colacc[31u - wave]);
     }
     __syncthreads();
   }

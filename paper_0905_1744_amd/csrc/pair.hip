@@ -70,11 +70,9 @@ __device__ __forceinline__ void run_pair_task(const SetView &v, const PairTask &
     touch_rows<true>(v, ConsecutiveRows{16u * rb, v.N}, v.exc_ids, e0, en, sh.row);
     const bool lds_exc = en <= kExcLds;
     if (lds_exc) {
-      for (uint32_t e = tid; e < en; e += 1024) sh.exc_id[e] = v.exc_ids[e0 + e];
       for (uint32_t e = tid; e < 16u * en; e += 1024) sh.exc_c[e] = v.exc_cnt[16ull * e0 + e];
     }
     __syncthreads();
-    const uint16_t *eid = lds_exc ? sh.exc_id : v.exc_ids + e0;
     const uint16_t *ecnt = lds_exc ? sh.exc_c : v.exc_cnt + 16ull * e0;
     // a tile has pairs below the diagonal only when rb >= 4 g: the strip's
     // groups g0 .. g0 + nact - 1 meet this row block
@@ -120,7 +118,7 @@ __device__ __forceinline__ void run_pair_task(const SetView &v, const PairTask &
           }
         }
       }
-      if (owner) tile_finish<false>(v, sh, rb, g, v.N, delta, fix, eid, ecnt, en, tc, cnt, sh.colacc[j]);
+      if (owner) tile_finish<false>(v, sh, rb, g, v.N, delta, fix, ecnt, tc, cnt, sh.colacc[j]);
     }
     __syncthreads();
   }
@@ -253,7 +251,7 @@ __global__ __launch_bounds__(1024) void similarity_kernel(
     default: column_counts_ragged<16>(T16, p, L, Lw, cnt); break;
   }
   if (!vc) return;
-  column_excess(v, sc, sh.BM, exc_ids, exc_cnt, e0, en, cnt);
+  column_excess(v, sc, sh.BM, sh.BP, exc_cnt, e0, cnt);
   const uint32_t Kc = v.K[sc];
 #pragma unroll
   for (int r = 0; r < 16; r++) {

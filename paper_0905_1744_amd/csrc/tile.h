@@ -148,25 +148,25 @@ __device__ __forceinline__ int np_bucket(uint32_t L) {
   return need <= 8 ? 8 : need <= 10 ? 10 : need <= 12 ? 12 : need <= 14 ? 14 : 16;
 }
 
+// Position of word id in the row block's merged count>=2 list (ascending,
+// distinct words): the entries before id's bitmap word (BP) plus the set
+// bits below id in that word.  Valid only where id's bit is set.
+__device__ __forceinline__ uint32_t merged_index(const uint16_t *BP, uint32_t bw, uint32_t id) {
+  return (uint32_t)BP[id >> 5] + (uint32_t)__builtin_popcount(bw & ((1u << (id & 31u)) - 1u));
+}
+
 // Levels >= 2 for one column: the column's count>=2 words against the row
-// block's merged list (bitmap BM in LDS; exc_* in global memory).
+// block's merged list (bitmap BM and its word offsets BP in LDS; the
+// list's counts exc_cnt in global memory from entry e0 on).
 __device__ __forceinline__ void column_excess(const SetView &v, uint32_t sc, const uint32_t *BM,
-                                              const uint16_t *__restrict__ exc_ids,
-                                              const uint16_t *__restrict__ exc_cnt, uint32_t e0,
-                                              uint32_t en, uint32_t (&cnt)[16]) {
+                                              const uint16_t *BP, const uint16_t *__restrict__ exc_cnt,
+                                              uint32_t e0, uint32_t (&cnt)[16]) {
   const uint32_t h0 = v.hi_off[sc], h1 = v.hi_off[sc + 1];
   for (uint32_t h = h0; h < h1; h++) {
-    const uint32_t id = v.hi_ids[h];
-    if (!((BM[id >> 5] >> (id & 31u)) & 1u)) continue;
+    const uint32_t id = v.hi_ids[h], bw = BM[id >> 5];
+    if (!((bw >> (id & 31u)) & 1u)) continue;
     const uint32_t cj = v.hi_cnt[h];
-    uint32_t lo = e0, hi = e0 + en;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (exc_ids[mid] < id) lo = mid + 1;
-      else hi = mid;
-    }
-    if (lo >= e0 + en || exc_ids[lo] != id) continue;  // not expected: bitmap built from the list
-    const uint16_t *c = exc_cnt + (size_t)lo * 16;
+    const uint16_t *c = exc_cnt + (size_t)(e0 + merged_index(BP, bw, id)) * 16;
 #pragma unroll
     for (int r = 0; r < 16; r++) {
       const uint32_t cr = c[r];
@@ -177,31 +177,27 @@ __device__ __forceinline__ void column_excess(const SetView &v, uint32_t sc, con
 
 // Levels >= 2 for one column of the rank kernel: the column's count>=2
 // entries come from the group-interleaved list (q0..q3 are its first four,
-// loaded before the level-1 loop); hits in the row block's bitmap are
-// looked up in the block's merged list (eid/ecnt: LDS copy or HBM).
+// loaded before the level-1 loop); a hit in the row block's bitmap finds
+// its entry of the block's merged list by merged_index, and ecnt (LDS copy
+// or HBM, 16 counts per entry) gives the rows' counts.
 __device__ __forceinline__ void column_excess_grouped(const uint32_t *__restrict__ hp, uint32_t hl,
                                                       const uint32_t (&q0)[4], const uint32_t *BM,
-                                                      const uint16_t *eid, const uint16_t *ecnt,
-                                                      uint32_t en, uint32_t (&cnt)[16]) {
+                                                      const uint16_t *BP, const uint16_t *ecnt,
+                                                      uint32_t (&cnt)[16]) {
   for (uint32_t t = 0; t < hl; t += 4) {
     uint32_t q[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) q[k] = t == 0 ? q0[k] : hp[(size_t)(t + k) * 64];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      const uint32_t id = q[k] & 0xFFFFu, cj = q[k] >> 16;
-      if (cj < 2u || !((BM[id >> 5] >> (id & 31u)) & 1u)) continue;
-      uint32_t lo = 0, hi = en;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (eid[mid] < id) lo = mid + 1;
-        else hi = mid;
-      }
-      if (lo >= en || eid[lo] != id) continue;
-      const uint16_t *c = ecnt + (size_t)lo * 16;
+      const uint32_t id = q[k] & 0xFFFFu, cj = q[k] >> 16, bw = BM[id >> 5];
+      if (cj < 2u || !((bw >> (id & 31u)) & 1u)) continue;
+      const uint4 *c4 = reinterpret_cast<const uint4 *>(ecnt + (size_t)merged_index(BP, bw, id) * 16);
+      const uint4 lo = c4[0], hi = c4[1];
+      const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
       for (int r = 0; r < 16; r++) {
-        const uint32_t cr = c[r];
+        const uint32_t cr = (w[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
         cnt[r] += cr >= 2u ? min(cr, cj) - 1u : 0u;
       }
     }
@@ -277,10 +273,12 @@ __device__ __forceinline__ double halving_reduce8(const double (&u8)[8], uint32_
   return u1;
 }
 
-// LDS state of one row block: presence table, count>=2 bitmap, row data.
+// LDS state of one row block: presence table, count>=2 bitmap with the
+// merged-list offset of each of its words, row data.
 struct RowShared {
   uint32_t T32[kTableWords];
   uint32_t BM[kBitmapWords];
+  uint16_t BP[kBitmapWords];  // entries of the merged list before word w (set words only)
   uint32_t rowK[16];
   double rowInv[16];
 };
@@ -311,8 +309,13 @@ __device__ __forceinline__ void touch_rows(const SetView &v, RowPos rowpos,
   }
   for (uint32_t e = tid; e < en; e += 1024) {
     const uint32_t id = exc_ids[e0 + e];
-    if (kSet) atomicOr(&sh.BM[id >> 5], 1u << (id & 31u));
-    else sh.BM[id >> 5] = 0;
+    if (kSet) {
+      atomicOr(&sh.BM[id >> 5], 1u << (id & 31u));
+      // the list ascends: the first entry of each bitmap word records its offset
+      if (e == 0 || (uint32_t)(exc_ids[e0 + e - 1] >> 5) != (id >> 5)) sh.BP[id >> 5] = (uint16_t)e;
+    } else {
+      sh.BM[id >> 5] = 0;
+    }
   }
 }
 
@@ -339,8 +342,7 @@ struct RankShared {
   LogEntry logt[kLogEntries];
   double ln2;
   unsigned long long racc[16];  // row sums of the current row block (fixed point)
-  uint16_t exc_id[kExcLds];
-  uint16_t exc_c[kExcLds * 16];
+  alignas(16) uint16_t exc_c[kExcLds * 16];  // the row block's merged counts when they fit
   long long colacc[32][64];     // [group of the strip][lane] column sums (fixed point)
   uint16_t xcnt[16][16][64];    // [wave][row][lane] level-1 counts of a list slice
 };
@@ -409,14 +411,14 @@ __device__ __forceinline__ TileCol tile_col(const SetView &v, uint32_t g) {
 
 template <bool kCross>
 __device__ __forceinline__ void tile_finish(const SetView &v, RankShared &sh, uint32_t rb, uint32_t g,
-                                            uint32_t row_n, double delta, int fix, const uint16_t *eid,
-                                            const uint16_t *ecnt, uint32_t en, const TileCol &tc,
+                                            uint32_t row_n, double delta, int fix, const uint16_t *ecnt,
+                                            const TileCol &tc,
                                             uint32_t (&cnt)[16], long long (&col)[64]) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t sc = 64u * g + lane;
   const bool vc = sc < v.N;
   const double invKc = tc.invKc;
-  column_excess_grouped(tc.hp, tc.hl, tc.q0, sh.row.BM, eid, ecnt, en, cnt);
+  column_excess_grouped(tc.hp, tc.hl, tc.q0, sh.row.BM, sh.row.BP, ecnt, cnt);
   // F = shared / min(K_r, K_c) (Equation 1), d = -ln(delta + F) (Equation 2);
   // rows r and r + 8 are formed together and immediately folded across
   // lanes l and l ^ 32 (first step of the halving butterfly).  Every lane
@@ -451,13 +453,13 @@ __device__ __forceinline__ void tile_finish(const SetView &v, RankShared &sh, ui
 
 template <bool kCross>
 __device__ __forceinline__ void rank_tile(const SetView &v, RankShared &sh, uint32_t rb, uint32_t g,
-                                          uint32_t row_n, double delta, int fix, const uint16_t *eid,
-                                          const uint16_t *ecnt, uint32_t en, long long (&col)[64]) {
+                                          uint32_t row_n, double delta, int fix, const uint16_t *ecnt,
+                                          long long (&col)[64]) {
   const uint32_t L = __builtin_amdgcn_readfirstlane(v.grp_len[g]);
   const TileCol tc = tile_col(v, g);
   uint32_t cnt[16];
   slice_counts(v, sh, g, 0u, L, cnt);
-  tile_finish<kCross>(v, sh, rb, g, row_n, delta, fix, eid, ecnt, en, tc, cnt, col);
+  tile_finish<kCross>(v, sh, rb, g, row_n, delta, fix, ecnt, tc, cnt, col);
 }
 
 }  // namespace kd

@@ -83,8 +83,7 @@ struct DistShared {
   RowShared row;
   LogEntry logt[kLogEntries];
   double ln2;
-  uint16_t exc_id[kExcLds];
-  uint16_t exc_c[kExcLds * 16];
+  alignas(16) uint16_t exc_c[kExcLds * 16];
 };
 
 // Row stride of a set's sorted-order scratch matrix: whole 128-byte lines.
@@ -96,8 +95,7 @@ __host__ __device__ inline uint64_t dist_ld(uint64_t n) { return (n + 15) & ~(ui
 // 512-byte store, and each lane's 16 rows fill one 128-byte line of its
 // column's row.  dist_permute_kernel puts them in input order.
 __device__ __forceinline__ void dist_tile(const SetView &v, DistShared &sh, uint32_t rb, uint32_t g,
-                                          double delta, const uint16_t *eid, const uint16_t *ecnt,
-                                          uint32_t en, double *__restrict__ M) {
+                                          double delta, const uint16_t *ecnt, double *__restrict__ M) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t L = __builtin_amdgcn_readfirstlane(v.grp_len[g]);
   const uint32_t hl = __builtin_amdgcn_readfirstlane(v.ghi_len[g]);
@@ -112,7 +110,7 @@ __device__ __forceinline__ void dist_tile(const SetView &v, DistShared &sh, uint
   }
   uint32_t cnt[16];
   column_counts(reinterpret_cast<const uint16_t *>(sh.row.T32), p, L, cnt);
-  column_excess_grouped(hp, hl, q0, sh.row.BM, eid, ecnt, en, cnt);
+  column_excess_grouped(hp, hl, q0, sh.row.BM, sh.row.BP, ecnt, cnt);
   if (!vc) return;
   const uint32_t Kc = v.K[sc];
   const double invKc = v.invK[sc];
@@ -156,14 +154,12 @@ __global__ __launch_bounds__(1024) void dist_pairs_kernel(const SetView *__restr
     touch_rows<true>(v, ConsecutiveRows{16u * rb, v.N}, v.exc_ids, e0, en, sh.row);
     const bool lds_exc = en <= kExcLds;
     if (lds_exc) {
-      for (uint32_t e = tid; e < en; e += 1024) sh.exc_id[e] = v.exc_ids[e0 + e];
       for (uint32_t e = tid; e < 16u * en; e += 1024) sh.exc_c[e] = v.exc_cnt[16ull * e0 + e];
     }
     __syncthreads();
-    const uint16_t *eid = lds_exc ? sh.exc_id : v.exc_ids + e0;
     const uint16_t *ecnt = lds_exc ? sh.exc_c : v.exc_cnt + 16ull * e0;
-    if (ga < v.G && rb >= 4u * ga) dist_tile(v, sh, rb, ga, delta, eid, ecnt, en, M);
-    if (gb < v.G && rb >= 4u * gb) dist_tile(v, sh, rb, gb, delta, eid, ecnt, en, M);
+    if (ga < v.G && rb >= 4u * ga) dist_tile(v, sh, rb, ga, delta, ecnt, M);
+    if (gb < v.G && rb >= 4u * gb) dist_tile(v, sh, rb, gb, delta, ecnt, M);
     __syncthreads();
   }
 }
