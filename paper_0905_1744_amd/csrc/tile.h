@@ -184,10 +184,14 @@ __device__ __forceinline__ void column_excess_grouped(const uint32_t *__restrict
                                                       const uint32_t (&q0)[4], const uint32_t *BM,
                                                       const uint16_t *BP, const uint16_t *ecnt,
                                                       uint32_t (&cnt)[16]) {
+  uint32_t q[4] = {q0[0], q0[1], q0[2], q0[3]};
   for (uint32_t t = 0; t < hl; t += 4) {
-    uint32_t q[4];
+    // the next four entries are in flight while these four are looked up
+    uint32_t qn[4] = {0u, 0u, 0u, 0u};
+    if (t + 4u < hl) {
 #pragma unroll
-    for (int k = 0; k < 4; k++) q[k] = t == 0 ? q0[k] : hp[(size_t)(t + k) * 64];
+      for (int k = 0; k < 4; k++) qn[k] = hp[(size_t)(t + 4u + k) * 64];
+    }
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       const uint32_t id = q[k] & 0xFFFFu, cj = q[k] >> 16, bw = BM[id >> 5];
@@ -201,6 +205,8 @@ __device__ __forceinline__ void column_excess_grouped(const uint32_t *__restrict
         cnt[r] += cr >= 2u ? min(cr, cj) - 1u : 0u;
       }
     }
+#pragma unroll
+    for (int k = 0; k < 4; k++) q[k] = qn[k];
   }
 }
 
@@ -437,8 +443,8 @@ __device__ __forceinline__ void tile_finish(const SetView &v, RankShared &sh, ui
       const uint32_t rr = r + 8 * h, sr = 16u * rb + rr;
       const bool ok = vc && (kCross || sc < sr) && sr < row_n;
       const double inv = fmax(sh.row.rowInv[rr], invKc);
-      const double lg = log_tab(fma((double)cnt[rr], inv, delta), sh.logt, sh.ln2);
-      d[h] = ok ? -lg : 0.0;
+      const double nl = log_tab<true>(fma((double)cnt[rr], inv, delta), sh.logt, sh.ln2);
+      d[h] = ok ? nl : 0.0;
     }
     colsum += d[0];
     colsum += d[1];

@@ -120,7 +120,7 @@ __device__ __forceinline__ void dist_tile(const SetView &v, DistShared &sh, uint
     const uint32_t sr = 16u * rb + r;
     if (sc < sr && sr < v.N) {
       const double inv = sh.row.rowK[r] < Kc ? sh.row.rowInv[r] : invKc;
-      const double d = -log_tab(fma((double)cnt[r], inv, delta), sh.logt, sh.ln2);
+      const double d = log_tab<true>(fma((double)cnt[r], inv, delta), sh.logt, sh.ln2);
       M[sr * ld + sc] = d;
       M[(uint64_t)sc * ld + sr] = d;
     }
