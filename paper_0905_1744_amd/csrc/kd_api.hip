@@ -5,6 +5,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <chrono>
 #include <mutex>
 #include <new>
 
@@ -112,6 +113,23 @@ hipError_t issue(kd_ctx *ctx, F f) {
 }
 
 kd_status from_hip(hipError_t e) { return e == hipSuccess ? KD_OK : KD_EDEVICE; }
+
+// Waits for the work enqueued so far on `st` by polling an event: the
+// sizing read-back of a count is short, and a blocking wait wakes the host
+// tens of microseconds after the device is done.  After kSpinMs of polling
+// it blocks like hipStreamSynchronize.
+constexpr double kSpinMs = 2.0;
+hipError_t wait_stream(kd_ctx *ctx, hipStream_t st) {
+  hipError_t e = hipEventRecord(ctx->wait_ev, st);
+  if (e != hipSuccess) return e;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    e = hipEventQuery(ctx->wait_ev);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > kSpinMs)
+      return hipEventSynchronize(ctx->wait_ev);
+  }
+}
 
 #define KD_TRY(x)                             \
   do {                                        \
@@ -321,6 +339,12 @@ extern "C" kd_status kd_ctx_create(int device, void *hip_stream, kd_ctx **out) {
     delete c;
     return KD_EDEVICE;
   }
+  if (hipEventCreateWithFlags(&c->wait_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipHostFree(c->pinned);
+    delete c->pool;
+    delete c;
+    return KD_EDEVICE;
+  }
   *out = c;
   return KD_OK;
 }
@@ -336,6 +360,7 @@ extern "C" void kd_ctx_destroy(kd_ctx *ctx) {
     (void)hipHostFree(b.p);
   }
   delete ctx->pool;  // frees task lists and anything still live
+  if (ctx->wait_ev) (void)hipEventDestroy(ctx->wait_ev);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->readback) (void)hipHostFree(ctx->readback);
   delete ctx;
@@ -538,7 +563,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
     if (e == hipSuccess) e = hipMemcpyAsync(h_len, grp_len, 4ull * G, hipMemcpyDeviceToHost, st);
   }
   if (e == hipSuccess) e = hipMemcpyAsync(hm, meta, sizeof(LayoutMeta), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = wait_stream(ctx, st);
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(st);
     set_free(s);

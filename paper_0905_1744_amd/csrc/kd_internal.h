@@ -157,6 +157,7 @@ struct kd_ctx {
   // be released at the end of a call are handed to the plan instead
   std::vector<std::function<hipError_t(hipStream_t)>> *rec = nullptr;
   std::vector<void *> *rec_keep = nullptr;
+  hipEvent_t wait_ev = nullptr;  // polled by the count's sizing wait
 };
 
 struct kd_set {

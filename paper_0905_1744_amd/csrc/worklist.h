@@ -80,16 +80,24 @@ constexpr double kRowBlockCost = 6.0;
 //    (out[beg[x] .. beg[x+1]), largest first); a workgroup takes from its
 //    own XCD's queue and steals from the others once it is empty.  (Kept in
 //    strip order instead, the 20k launch took 1.28 ms instead of 1.23 and
-//    fetched no fewer bytes.)
+//    fetched no fewer bytes.)  "Largest first" is a stable counting sort on
+//    the cost quantized to kCostLevels levels of the largest task: it runs
+//    in linear time while the device lays the lists out.
 // grp_len: host copy of every column group's padded list length
 // (batch-wide numbering).
+constexpr uint32_t kCostLevels = 1024;
+
 inline void build_costed_tasks(const std::vector<SetView> &views, const std::vector<uint32_t> &grp_first,
-                        const std::vector<uint32_t> &grp_len, uint32_t tasks_per_cu, int cus,
-                        std::vector<PairTask> &out, uint32_t (&beg)[kXcdQueues + 1]) {
+                               const std::vector<uint32_t> &grp_len, uint32_t tasks_per_cu, int cus,
+                               std::vector<PairTask> &out, uint32_t (&beg)[kXcdQueues + 1]) {
   out.clear();
   for (uint32_t x = 0; x <= kXcdQueues; x++) beg[x] = 0;
-  struct Unit { uint32_t set, g0, rb; double cost; };
-  std::vector<Unit> units;
+  struct Strip { uint32_t set, g0, rb0, rb1; };
+  std::vector<Strip> strips;
+  std::vector<double> cost;
+  size_t nunits = 0;
+  for (const SetView &w : views) nunits += (w.N + 15) / 16 * (size_t)(((w.N + 63) / 64 + kGroupsPerTask - 1) / kGroupsPerTask);
+  cost.reserve(nunits);
   double all = 0.0;
   for (uint32_t q = 0; q < views.size(); q++) {
     const uint32_t N = views[q].N, RB = (N + 15) / 16, G = (N + 63) / 64;
@@ -97,6 +105,7 @@ inline void build_costed_tasks(const std::vector<SetView> &views, const std::vec
     for (uint32_t g0 = 0; g0 < G; g0 += kGroupsPerTask) {
       double wave_cost[16] = {0.0};
       double worst = 0.0;
+      if (4u * g0 < RB) strips.push_back({q, g0, 4u * g0, RB});
       for (uint32_t rb = 4u * g0; rb < RB; rb++) {
         if ((rb & 3u) == 0) {  // group rb / 4 starts to meet the row blocks
           const uint32_t g = rb >> 2;
@@ -106,39 +115,68 @@ inline void build_costed_tasks(const std::vector<SetView> &views, const std::vec
             worst = std::max(worst, wave_cost[w]);
           }
         }
-        units.push_back({q, g0, rb, worst + kRowBlockCost});
+        cost.push_back(worst + kRowBlockCost);
         all += worst + kRowBlockCost;
       }
     }
   }
-  if (units.empty()) return;
+  if (cost.empty()) return;
   const double T = std::max<double>(kXcdQueues, (double)tasks_per_cu * (double)std::max(cus, 1));
   const double per_task = all / T, per_xcd = all / kXcdQueues;
-  std::vector<std::vector<std::pair<double, PairTask>>> xq(kXcdQueues);
-  double cum = 0.0, tcost = 0.0;
-  size_t start = 0;
+  std::vector<PairTask> tk[kXcdQueues];
+  std::vector<double> tc[kXcdQueues];
+  for (uint32_t x = 0; x < kXcdQueues; x++) {
+    tk[x].reserve((size_t)(T / kXcdQueues) + strips.size() / kXcdQueues + 8);
+    tc[x].reserve((size_t)(T / kXcdQueues) + strips.size() / kXcdQueues + 8);
+  }
+  double cum = 0.0, tcost = 0.0, cmax = 0.0;
   uint32_t xcd = 0;
-  for (size_t i = 0; i < units.size(); i++) {
-    const Unit &u = units[i];
-    tcost += u.cost;
-    cum += u.cost;
-    const bool last = i + 1 == units.size();
-    const bool strip_end = last || units[i + 1].set != u.set || units[i + 1].g0 != u.g0;
-    const uint32_t next_xcd = std::min<uint32_t>(kXcdQueues - 1, (uint32_t)(cum / per_xcd));
-    if (strip_end || tcost >= per_task || next_xcd != xcd) {
-      const Unit &f = units[start];
-      xq[xcd].push_back({tcost, PairTask{f.set, f.rb, u.rb + 1, f.g0}});
-      start = i + 1;
-      tcost = 0.0;
-      xcd = next_xcd;
+  // the next XCD boundary, a hair low: the exact test divides only near it
+  double thr = per_xcd * (1.0 - 1e-9);
+  size_t i = 0;
+  for (const Strip &st : strips) {
+    uint32_t start = st.rb0;
+    for (uint32_t rb = st.rb0; rb < st.rb1; rb++, i++) {
+      tcost += cost[i];
+      cum += cost[i];
+      uint32_t next_xcd = xcd;
+      if (cum >= thr) next_xcd = std::min<uint32_t>(kXcdQueues - 1, (uint32_t)(cum / per_xcd));
+      if (rb + 1 == st.rb1 || tcost >= per_task || next_xcd != xcd) {
+        tk[xcd].push_back(PairTask{st.set, start, rb + 1, st.g0});
+        tc[xcd].push_back(tcost);
+        cmax = std::max(cmax, tcost);
+        start = rb + 1;
+        tcost = 0.0;
+        if (next_xcd != xcd) {
+          xcd = next_xcd;
+          thr = per_xcd * (double)(xcd + 1) * (1.0 - 1e-9);
+        }
+      }
     }
   }
+  // levels: kCostLevels, fewer for short queues (a finer grid than the
+  // tasks per queue changes nothing but the time to clear it)
+  uint32_t levels = 16;
+  while (levels < kCostLevels && levels < 4 * (uint32_t)(i / kXcdQueues + 1)) levels *= 2;
+  levels = std::min(levels, kCostLevels);
+  const double scale = cmax > 0.0 ? (levels - 1) / cmax : 0.0;
+  std::vector<uint32_t> cnt(levels + 1);
+  std::vector<uint16_t> key;
+  out.reserve(i);
   for (uint32_t x = 0; x < kXcdQueues; x++) {
-    auto &q = xq[x];
-    std::stable_sort(q.begin(), q.end(), [](const std::pair<double, PairTask> &a,
-                                            const std::pair<double, PairTask> &b) { return a.first > b.first; });
+    const std::vector<double> &c = tc[x];
+    std::fill(cnt.begin(), cnt.end(), 0u);
+    key.resize(c.size());
+    for (size_t k = 0; k < c.size(); k++) {
+      const uint32_t lv = std::min(levels - 1, (uint32_t)(c[k] * scale));
+      key[k] = (uint16_t)(levels - 1 - lv);
+      cnt[key[k] + 1u]++;
+    }
+    for (uint32_t q = 0; q < levels; q++) cnt[q + 1] += cnt[q];
     beg[x] = (uint32_t)out.size();
-    for (const auto &t : q) out.push_back(t.second);
+    out.resize(out.size() + c.size());
+    PairTask *o = out.data() + beg[x];
+    for (size_t k = 0; k < c.size(); k++) o[cnt[key[k]]++] = tk[x][k];
   }
   beg[kXcdQueues] = (uint32_t)out.size();
 }
