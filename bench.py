@@ -44,25 +44,26 @@ TREE_SOURCES = ["paper_0905_1744_amd/csrc/tree.hip", "paper_0905_1744_amd/csrc/t
                 "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h",
                 "paper_0905_1744_amd/csrc/radix.h"]
 TRAFFIC = {
-    # key: (kernel, workload); "shape" is the work-list shape the counters were
-    # taken at (workgroups per CU for the rank kernel), None where there is none
-    ("rank_pairs_kernel", "paper20k"): {"sources": RANK_SOURCES, "sha256_16": "173c0a370af077d8",
-                                        "shape": 32, "bytes_per_launch": 250051584},
-    ("rank_pairs_kernel", "large100k"): {"sources": RANK_SOURCES, "sha256_16": "173c0a370af077d8",
-                                         "shape": 32, "bytes_per_launch": 6307022165},
+    # key: (kernel, workload).  bytes_per_launch: one number, or for the rank
+    # kernel a dict keyed by the work-list shape (tasks per compute unit) the
+    # counters were taken at
+    ("rank_pairs_kernel", "paper20k"): {"sources": RANK_SOURCES, "sha256_16": "0ebbc92f3c550ca3",
+                                        "bytes_per_launch": {16: 209310720, 32: 204222805}},
+    ("rank_pairs_kernel", "large100k"): {"sources": RANK_SOURCES, "sha256_16": "0ebbc92f3c550ca3",
+                                         "bytes_per_launch": {32: 6209227435}},
     ("rank_cross_kernel", "global100k"): {"sources": ["paper_0905_1744_amd/csrc/cross.hip",
                                                       "paper_0905_1744_amd/csrc/tile.h",
                                                       "paper_0905_1744_amd/csrc/bitcount.h",
                                                       "paper_0905_1744_amd/csrc/klog.h"],
-                                          "sha256_16": "6f4d6a4f4effdd3f", "shape": None,
-                                          "bytes_per_launch": 2843834059},
-    ("dist_pairs_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "dadf40f2d4dcd576",
-                                        "shape": None, "bytes_per_launch": 492756992},
-    ("upgma_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "dadf40f2d4dcd576",
-                                   "shape": None, "bytes_per_launch": 998621184},
+                                          "sha256_16": "a24f7da4dc1db0fa",
+                                          "bytes_per_launch": 2042262869},
+    ("dist_pairs_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "3510e296fdf7e0dd",
+                                        "bytes_per_launch": 567085397},
+    ("upgma_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "3510e296fdf7e0dd",
+                                   "bytes_per_launch": 998823595},
     # psp_g_kernel + psp_scores_kernel, the two launches of one psp_scores call
     ("psp", "psp"): {"sources": ["paper_0905_1744_amd/csrc/psp.hip"], "sha256_16": "27c995852957b595",
-                     "shape": None, "bytes_per_launch": 94294016 + 2873273344},
+                     "bytes_per_launch": 94294016 + 2873273344},
 }
 
 
@@ -77,9 +78,10 @@ def sources_hash(paths):
 
 def measured_traffic(kernel, workload, shape):
     t = TRAFFIC.get((kernel, workload))
-    if t is None or shape != t["shape"]:
+    if t is None or sources_hash(t["sources"]) != t["sha256_16"]:
         return None
-    return t["bytes_per_launch"] if sources_hash(t["sources"]) == t["sha256_16"] else None
+    b = t["bytes_per_launch"]
+    return b.get(shape) if isinstance(b, dict) else b
 
 
 def probe_count(D):
@@ -161,17 +163,34 @@ def cpu_baseline_all_cores(ss, delta, budget_s, L=None):
     }
 
 
-def rank_lookups(D):
-    """64-lane LDS mask lookups of one rank_pairs launch: column group g
-    (64 consecutive sequences in ascending-D order) walks its padded list,
-    max D rounded up to 16, once against each of the row blocks rb >= 4g."""
+def group_lengths(D):
+    """Padded list length of every column group of one set: group g holds
+    the 64 consecutive sequences g*64 .. g*64+63 in ascending-D order and
+    its lanes walk max D rounded up to 16 words."""
     import numpy as np
     d = np.sort(np.asarray(D, dtype=np.int64))
     n = d.size
-    G, RB = (n + 63) // 64, (n + 15) // 16
-    g = np.arange(G)
-    L = (d[np.minimum(64 * g + 63, n - 1)] + 15) // 16 * 16
-    return int((L * np.maximum(RB - 4 * g, 0)).sum())
+    if n == 0:
+        return np.zeros(0, dtype=np.int64)
+    g = np.arange((n + 63) // 64)
+    return (d[np.minimum(64 * g + 63, n - 1)] + 15) // 16 * 16
+
+
+def rank_lookups(D):
+    """64-lane LDS mask lookups of one all-pairs launch over one set (the
+    rank kernel, the distance kernel): column group g walks its padded list
+    once against each of the 16-row blocks rb >= 4g."""
+    import numpy as np
+    L = group_lengths(D)
+    RB = (len(D) + 15) // 16
+    return int((L * np.maximum(RB - 4 * np.arange(L.size), 0)).sum())
+
+
+def cross_lookups(D, first, S):
+    """Lookups of the globalized rank's cross pass: every column group of
+    every block walks its padded list once against each 16-row block of the
+    S gathered samples."""
+    return int(sum(int(group_lengths(D[a:b]).sum()) for a, b in zip(first[:-1], first[1:]))) * ((S + 15) // 16)
 
 
 def rank_roofline(probes, pairs, lookups, t_kernel, ceiling, traffic, alg_bytes, kernel="rank_pairs_kernel"):
@@ -305,12 +324,10 @@ def bench_global(args):
     probes_cross = probe_count_cross(D, kd.u32(smp))
     t_loc = st["pairs"][0] / max(st["pairs"][1], 1) / 1e3
     t_cross = st["global"][0] / max(st["global"][1], 1) / 1e3
-
-    def roof(name, probes, pairs, t, traffic=None):
-        a = probes / t / 1e12
-        return {"bound": "alu", "achieved": a, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
-                "frac": a / PEAK_TPROBE, "traffic": traffic, "kernel": name, "kernel_ms": t * 1e3,
-                "work_per_launch": {"probes": probes, "pairs": pairs}}
+    bounds = list(zip(first[:-1], first[1:]))
+    lookups_local = sum(rank_lookups(D[a:b]) for a, b in bounds if b > a)
+    lookups_cross = cross_lookups(D, first, int(len(smp)))
+    ceiling = lds_ceiling(ctx)
 
     # the comparison of the paper's Table 1, outside the timed region
     kc = ctx.kmer_count(res, off)
@@ -328,9 +345,11 @@ def bench_global(args):
                    "step": ("kmer_count_batch (B blocks) + kmer_rank (local ranks) + "
                             "kmer_rank_global + sample_partition"), "autotune": tune},
         "stages_ms_per_step": {k_: v[0] / nb for k_, v in stages.items() if v[1]},
-        "roofline": roof("rank_pairs_kernel (local ranks)", probes_local, local_pairs, t_loc),
-        "roofline_cross": roof("rank_cross_kernel", probes_cross, cross_pairs, t_cross,
-                               measured_traffic("rank_cross_kernel", args.workload, None)),
+        "roofline": rank_roofline(probes_local, local_pairs, lookups_local, t_loc, ceiling, None,
+                                  int(D.sum()) * 2 + 8 * N, kernel="rank_pairs_kernel (local ranks)"),
+        "roofline_cross": rank_roofline(probes_cross, cross_pairs, lookups_cross, t_cross, ceiling,
+                                        measured_traffic("rank_cross_kernel", args.workload, None),
+                                        int(D.sum()) * 2 + 8 * N, kernel="rank_cross_kernel"),
         "table1": cmp,
     }
     kb.destroy()
@@ -394,7 +413,8 @@ def bench_trees(args):
     D = np.diff(loff.cpu().numpy())
     kb.destroy()
     probes = sum(probe_count(D[a:b]) for a, b in zip(first[:-1], first[1:]))
-    a = probes / t_dist / 1e12
+    lookups = sum(rank_lookups(D[a:b]) for a, b in zip(first[:-1], first[1:]) if b > a)
+    ceiling = lds_ceiling(ctx)
     line = {
         "metric": METRIC, "value": pairs / (ms_per_step / 1e3), "unit": "pair-similarities/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -405,11 +425,9 @@ def bench_trees(args):
                    "step": ("sample_partition + kd_gather_sequences + kmer_count_batch (buckets) + "
                             "kmer_distance_matrices + upgma_trees")},
         "stages_ms_per_step": {k: v[0] / nb for k, v in stages.items() if v[1]},
-        "roofline": {"bound": "alu", "achieved": a, "peak": PEAK_TPROBE, "unit": "Tprobe/s",
-                     "frac": a / PEAK_TPROBE,
-                     "traffic": measured_traffic("dist_pairs_kernel", args.workload, None),
-                     "kernel": "dist_pairs_kernel",
-                     "kernel_ms": t_dist * 1e3, "work_per_launch": {"probes": probes, "pairs": pairs}},
+        "roofline": rank_roofline(probes, pairs, lookups, t_dist, ceiling,
+                                  measured_traffic("dist_pairs_kernel", args.workload, None),
+                                  int(D.sum()) * 2 + 8 * pairs, kernel="dist_pairs_kernel"),
         "upgma": {"kernel": "upgma_kernel", "ms": t_tree * 1e3, "merges": int((n - 1).sum()),
                   "traffic": measured_traffic("upgma_kernel", args.workload, None),
                   "us_per_merge_step": t_tree * 1e6 / max(int(n.max()) - 1, 1),
@@ -789,6 +807,8 @@ def main():
     ap.add_argument("--pairs", type=int, default=256, help="psp workload: profile pairs")
     ap.add_argument("--rates", default="10,20,50,100,200,500,1000,2000,4000,100000",
                     help="served workload: arrival rates (jobs/s)")
+    ap.add_argument("--tasks-per-cu", type=int, default=0,
+                    help="rank work-list shape set by hand instead of autotuned (single-set workloads)")
     ap.add_argument("--no-loop-baseline", action="store_true",
                     help="batched workload: skip the per-set loop comparison (for profiling)")
     ap.add_argument("--delta", type=float, default=0.1)
@@ -869,9 +889,12 @@ def main():
         return kset, part
 
     tune = None
+    if args.tasks_per_cu:  # work-list shape set by hand (profiling a given shape)
+        ctx.set_tasks_per_cu(1, N, args.tasks_per_cu)
+        tune = {"tasks_per_cu": args.tasks_per_cu, "set_by_hand": True}
     for w in range(args.warmup):
         kset, _ = step()
-        if w == 0 and not args.no_autotune:
+        if w == 0 and not args.no_autotune and not args.tasks_per_cu:
             # work-list shape for this size class; later counts use it
             best, ms = ctx.autotune(kset, delta)
             tune = {"tasks_per_cu": best, "ms_per_shape": ms}

@@ -167,10 +167,11 @@ kd_status kmer_rank(kd_ctx *ctx, const kd_set *set, double delta, double *ranks)
  * accumulators.  Times kmer_rank on `set` for each of the
  * KD_TUNE_CANDIDATES values t = {2, 4, 8, 16, 32} (one warm-up and three
  * timed runs each; the stream is synchronized), checks that all shapes give
- * bit-identical ranks (KD_EDEVICE otherwise), gives the set the fastest
- * shape and remembers t in the context for later counted objects of the
- * same size class (power-of-two bucket of the sequence count, single sets
- * and batches apart).
+ * bit-identical ranks (KD_EDEVICE otherwise), gives the set the smallest t
+ * whose time is within 1% of the fastest (shapes that time alike are told
+ * apart by noise; the smaller flushes fewer sums) and remembers t in the
+ * context for later counted objects of the same size class (power-of-two
+ * bucket of the sequence count, single sets and batches apart).
  *   best    receives the chosen t (may be NULL)
  *   ms_out  NULL or double[KD_TUNE_CANDIDATES]: mean milliseconds per shape */
 #define KD_TUNE_CANDIDATES 5

@@ -295,7 +295,7 @@ class Context:
 
     def autotune(self, kset: KmerSet, delta: float = 0.1):
         """Pick the rank kernel's work-list shape for sets of this size class
-        (kd_autotune); returns (workgroups per compute unit, {shape: ms})."""
+        (kd_autotune); returns (tasks per compute unit, {shape: ms})."""
         best = C.c_uint32()
         ms = (C.c_double * len(self.TUNE_SHAPES))()
         self._check(lib().kd_autotune(self.handle, kset.handle, float(delta), C.byref(best), ms), "kd_autotune")

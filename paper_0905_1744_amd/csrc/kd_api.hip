@@ -114,6 +114,8 @@ hipError_t issue(kd_ctx *ctx, F f) {
 
 kd_status from_hip(hipError_t e) { return e == hipSuccess ? KD_OK : KD_EDEVICE; }
 
+constexpr double kTuneSlack = 0.01;  // kd_autotune: shapes within 1% of the fastest time alike
+
 // Waits for the work enqueued so far on `st` by polling an event: the
 // sizing read-back of a count is short, and a blocking wait wakes the host
 // tens of microseconds after the device is done.  After kSpinMs of polling
@@ -1169,6 +1171,7 @@ extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t 
   kd_status rc = KD_OK;
   double best_ms = 1e300;
   uint32_t best_tpc = kTasksPerCu;
+  double avg_ms[KD_TUNE_CANDIDATES];
   for (int c = 0; c < KD_TUNE_CANDIDATES && rc == KD_OK; c++) {
     // this candidate's work list, in a block of its own
     std::vector<PairTask> tl;
@@ -1196,6 +1199,7 @@ extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t 
     }
     if (rc != KD_OK) break;
     const double avg = tot / 3.0;
+    avg_ms[c] = avg;
     if (ms_out) ms_out[c] = avg;
     if (hipMemcpy(c == 0 ? ref.data() : got.data(), R, 8ull * N, hipMemcpyDeviceToHost) != hipSuccess) {
       rc = KD_EDEVICE;
@@ -1206,14 +1210,15 @@ extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t 
       rc = KD_EDEVICE;
       break;
     }
-    if (avg < best_ms) {
-      best_ms = avg;
-      best_tpc = cand[c];
-    }
+    best_ms = std::min(best_ms, avg);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != KD_OK) return rc;
+  // the fewest tasks (fewest column flushes) within kTuneSlack of the
+  // fastest: shapes that time alike would otherwise win by noise
+  for (int c = KD_TUNE_CANDIDATES - 1; c >= 0; c--)
+    if (avg_ms[c] <= best_ms * (1.0 + kTuneSlack)) best_tpc = cand[c];
   ctx->tpc_pref[shape_class(s->nsets, N)] = best_tpc;
   // the set keeps the winner's work list
   std::vector<PairTask> tl;

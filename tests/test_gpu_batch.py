@@ -199,6 +199,10 @@ def test_autotune_shapes_identical(kd, ctx):
     R0 = ctx.kmer_rank(ks, 0.1).clone()
     best, ms = ctx.autotune(ks, 0.1)
     assert best in ctx.TUNE_SHAPES and all(v > 0 for v in ms.values())
+    # the fewest tasks within 1% of the fastest
+    fastest = min(ms.values())
+    assert ms[best] <= fastest * 1.01
+    assert all(ms[t] > fastest * 1.01 for t in ctx.TUNE_SHAPES if t < best)
     assert torch.equal(ctx.kmer_rank(ks, 0.1), R0)
     for t in (1, 3, 64):  # any shape, set by hand, gives the same ranks
         ctx.set_tasks_per_cu(1, ss.n, t)
