@@ -67,6 +67,25 @@ TRAFFIC = {
 }
 
 
+# Unit occupancy of the rank kernel from rocprofv3 SQ counters (the 20k
+# profile: SQ_INSTS_VALU, SQ_LDS_IDX_ACTIVE and SQ_LDS_BANK_CONFLICT per
+# compute unit over GRBM_GUI_ACTIVE cycles per XCC), reported while the
+# kernel's sources hash to the profiled version.
+COUNTERS = {
+    ("rank_pairs_kernel", "paper20k"): {"sources": RANK_SOURCES, "sha256_16": "0ebbc92f3c550ca3",
+                                        "valu_busy": 0.56, "lds_busy": 0.61,
+                                        "lds_bank_conflict_share_of_lds_busy": 0.63,
+                                        "source": "profiles/rank_pairs_paper20k.md"},
+}
+
+
+def profiled_counters(kernel, workload):
+    c = COUNTERS.get((kernel, workload))
+    if c is None or sources_hash(c["sources"]) != c["sha256_16"]:
+        return None
+    return {k: v for k, v in c.items() if k not in ("sources", "sha256_16")}
+
+
 def sources_hash(paths):
     import hashlib
     h = hashlib.sha256()
@@ -193,7 +212,8 @@ def cross_lookups(D, first, S):
     return int(sum(int(group_lengths(D[a:b]).sum()) for a, b in zip(first[:-1], first[1:]))) * ((S + 15) // 16)
 
 
-def rank_roofline(probes, pairs, lookups, t_kernel, ceiling, traffic, alg_bytes, kernel="rank_pairs_kernel"):
+def rank_roofline(probes, pairs, lookups, t_kernel, ceiling, traffic, alg_bytes, kernel="rank_pairs_kernel",
+                  counters=None):
     """Roofline of an all-pairs rank launch.  The kernel is bound by its LDS
     mask lookups: one 64-lane random 16-bit read of the row block's table
     answers 16 rows x 64 columns of (word, pair) probes.  achieved = the
@@ -218,7 +238,8 @@ def rank_roofline(probes, pairs, lookups, t_kernel, ceiling, traffic, alg_bytes,
                                      "ratio": achieved / PEAK_TPROBE,
                                      "note": "the probes against one per VALU lane-cycle (256 CUs x 64 lanes x 2.4 GHz)"},
             "hbm": {"bytes_per_launch": traffic, "frac": (traffic / t_kernel / 8e12) if traffic else None,
-                    "algorithmic_bytes": alg_bytes}}
+                    "algorithmic_bytes": alg_bytes},
+            "unit_occupancy_from_counters": counters}
 
 
 def lds_ceiling(ctx, workgroups=1024, steps=64):
@@ -936,7 +957,8 @@ def main():
     ceiling = lds_ceiling(ctx)
     traffic = measured_traffic("rank_pairs_kernel", args.workload, tpc)
     roofline = rank_roofline(probes, pairs, lookups, t_pair, ceiling, traffic,
-                             int(D.sum()) * 2 + 8 * N)
+                             int(D.sum()) * 2 + 8 * N,
+                             counters=profiled_counters("rank_pairs_kernel", args.workload))
     line = {
         "metric": METRIC, "value": value, "unit": "pair-similarities/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
