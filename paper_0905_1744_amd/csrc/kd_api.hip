@@ -1055,9 +1055,11 @@ extern "C" kd_status upgma_trees(kd_ctx *ctx, uint32_t nsets, const uint32_t *se
                                  const double *dist, int32_t *merges, double *heights) {
   if (!ctx || !set_first || nsets == 0 || !dist) return KD_EINVAL;
   if (set_first[0] != 0) return KD_EINVAL;
+  uint32_t max_n = 0;
   for (uint32_t q = 0; q < nsets; q++) {
     const uint32_t n = set_first[q + 1] - set_first[q];
     if (set_first[q + 1] <= set_first[q] || n > kTreeMaxSeqs) return KD_EINVAL;
+    max_n = std::max(max_n, n);
   }
   const uint32_t N = set_first[nsets];
   if (N > nsets && (!merges || !heights)) return KD_EINVAL;
@@ -1082,7 +1084,7 @@ extern "C" kd_status upgma_trees(kd_ctx *ctx, uint32_t nsets, const uint32_t *se
   StageTimer t(ctx, KD_STAGE_TREE);
   KD_TRY(launch_fill_u64(st, err, 1, ~0ull));
   KD_TRY(hipMemcpyAsync(work, dist, sizeof(double) * doff[nsets], hipMemcpyDeviceToDevice, st));
-  KD_TRY(launch_upgma(st, nsets, N, d_first, d_off, work, rmin, rarg, merges, heights, err));
+  KD_TRY(launch_upgma(st, nsets, N, max_n, d_first, d_off, work, rmin, rarg, merges, heights, err));
   t.done();
   unsigned long long *hm = static_cast<unsigned long long *>(ctx->pinned);
   KD_TRY(hipMemcpyAsync(hm, err, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));

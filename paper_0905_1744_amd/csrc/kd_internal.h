@@ -291,9 +291,10 @@ hipError_t launch_distances(hipStream_t st, const Segs &sg, uint32_t N, uint32_t
                             double delta, double *scratch, double *dist);
 constexpr uint32_t kTreeMaxSeqs = 4096;  // largest set upgma_trees accepts
 // UPGMA of each set's matrix at work + doff[q] (overwritten), first[] on
-// the device (N = first[nsets] members in all); rmin/rarg: N entries of
-// scratch; a set with no comparable pair left records its index in *err
-hipError_t launch_upgma(hipStream_t st, uint32_t nsets, uint32_t N, const uint32_t *first,
+// the device (N = first[nsets] members in all, max_n in the largest set);
+// rmin/rarg: N entries of scratch; a set with no comparable pair left
+// records its index in *err
+hipError_t launch_upgma(hipStream_t st, uint32_t nsets, uint32_t N, uint32_t max_n, const uint32_t *first,
                         const uint64_t *doff, double *work, double *rmin, uint32_t *rarg,
                         int32_t *merges, double *heights, unsigned long long *err);
 // PSP (Equation 4): profiles of alignments and score matrices of pairs

@@ -225,22 +225,56 @@ hipError_t launch_distances(hipStream_t st, const Segs &sg, uint32_t N, uint32_t
 // and its smallest argument.  After merging a and b: row a is recomputed
 // while its entries are updated; a row k < a takes the new D[k][a] if it
 // is smaller (or equal with a smaller column); rows k < b whose minimum sat
-// at column a or b are rescanned (one wave per row).
+// at column a or b are rescanned, reading the old row with columns a and b
+// left out (the new D[k][a] is added to the result).
+//
+// Thread tid owns rows tid, tid + 1024, ...: only it keeps their minima.
+// A merge has two barriers.  Before the first, each thread loads its rows'
+// entries of rows a and b and lists its rows that need a rescan; after it
+// the waves start the rescans' loads (W = 16 / rows waves per row), store
+// the new entries while those loads are in flight, and leave partial
+// minima in LDS: row a's, the next pair's over the other rows, and the
+// rescans' parts, all keyed by (minimum, row << 16 | argument) so that the
+// argument travels with the row.  After the second barrier every wave
+// reduces them to the next pair itself, and the owners take their rows'
+// new minima from them.
 
 constexpr uint32_t kTreeMax = kTreeMaxSeqs;
 constexpr uint16_t kNone16 = 0xFFFFu;
+constexpr int kTreeWaves = 16;  // waves of the merge kernel
+constexpr int kTreeRowWaves = 8;       // of which own rows (the rest rescan)
+constexpr int kTreeRowWavesSmall = 8;  // the same for sets of up to 1024
+
+// a row's state in one 16-byte record: one address per row, the fields at
+// immediate offsets
+struct TreeRow {
+  double min;     // minimum of the row's entries right of the diagonal
+  uint16_t arg;   // its smallest column (kNone16: no entry)
+  uint16_t size;  // the cluster's size and id
+  uint16_t id;
+  uint16_t pad;
+};
 
 struct TreeShared {
-  double rowmin[kTreeMax];
-  uint16_t rowarg[kTreeMax];
-  uint16_t size[kTreeMax];
-  uint16_t id[kTreeMax];
-  uint16_t redo[kTreeMax];
-  uint8_t act[kTreeMax];
-  double wv[16], wv2[16];  // wave results: the pair, row a's new minimum
-  uint32_t wi[16], wi2[16];
-  uint32_t nredo;
-  uint32_t best_a;
+  TreeRow row[kTreeMax];
+  uint32_t act[kTreeMax / 32];  // bit k: slot k still in use
+  uint16_t redo[kTreeMax];   // rows rescanned in this merge
+  double partv[kTreeMax];    // the rescans' keyed parts
+  uint32_t parti[kTreeMax];
+  // wave partials, two buffers by merge parity: the next pair, row a
+  double pv[2][16], av[2][16];
+  uint32_t pi[2][16], ai[2][16];
+  uint32_t nredo[2];         // by merge parity
+  uint32_t cur[2];           // the pair (a, b), for the rescanning waves
+  uint32_t stop;             // no comparable pair left
+};
+
+__device__ __forceinline__ bool slot_active(const uint32_t *act, uint32_t j) {
+  return (act[j >> 5] >> (j & 31u)) & 1u;
+}
+struct BitActive {
+  const uint32_t *act;
+  __device__ bool operator()(uint32_t j) const { return slot_active(act, j); }
 };
 
 // lexicographic (value, index) minimum
@@ -250,58 +284,102 @@ __device__ __forceinline__ void lex_min(double &v, uint32_t &i, double v2, uint3
   i = take ? i2 : i;
 }
 
-// one step of the wave reduction: combine with the lane that the DPP control
-// CTRL names, in the rows of ROWS (other rows keep their value)
+// The wave reductions below find the smallest value first (v_min_f64, two
+// moves and a minimum per step), then the smallest index among the lanes
+// holding it (one move and a minimum per step): half the instructions of
+// carrying (value, index) pairs through every step.  Neither is ever NaN
+// here (lex_min never takes a NaN), so the value found is some lane's
+// value; the result's value is read from the winning lane (so that a zero
+// keeps the sign of the winner's).
+
+// the lane that the DPP control CTRL names, in the rows of ROWS (other
+// rows read their own value)
 template <int CTRL, int ROWS>
-__device__ __forceinline__ void dpp_lex_step(double &v, uint32_t &i) {
+__device__ __forceinline__ double dpp_fmin(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
   const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
   const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
-  const int i2 = __builtin_amdgcn_update_dpp((int)i, (int)i, CTRL, ROWS, 0xF, false);
-  lex_min(v, i, __hiloint2double(hi2, lo2), (uint32_t)i2);
+  return __builtin_fmin(v, __hiloint2double(hi2, lo2));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_umin(uint32_t i) {
+  const uint32_t i2 = (uint32_t)__builtin_amdgcn_update_dpp((int)i, (int)i, CTRL, ROWS, 0xF, false);
+  return i < i2 ? i : i2;
 }
 
-// lexicographic (value, index) minimum over the 64 lanes, in every lane
-// (all lanes active).  Register-to-register moves instead of LDS permutes:
-// quad swaps (1 0 3 2, 2 3 0 1), then the half-row and row mirrors leave
-// each 16-lane row's minimum in all its lanes; row 15 broadcast into rows 1
-// and 3 and row 31 broadcast into rows 2 and 3 leave the wave's in lane 63.
-// The minimum of a total order does not depend on the combining order.
+__device__ __forceinline__ double read_lane(double v, uint32_t l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// the index pass and the winner's value, given the value minimum m (uniform)
+__device__ __forceinline__ void lex_finish(double &v, uint32_t &i, double m, uint32_t j,
+                                           unsigned long long lanes) {
+  const unsigned long long w = __ballot(v == m && i == j) & lanes;
+  v = w ? read_lane(v, (uint32_t)__builtin_ctzll(w)) : m;
+  i = j;
+}
+
+// lexicographic (value, index) minimum over lanes 0-15, returned in every
+// lane: quad swaps (1 0 3 2, 2 3 0 1), then the half-row and row mirrors
+__device__ __forceinline__ void row_lex_min(double &v, uint32_t &i) {
+  double m = dpp_fmin<0xB1, 0xF>(v);  // quad_perm 1 0 3 2
+  m = dpp_fmin<0x4E, 0xF>(m);         // quad_perm 2 3 0 1
+  m = dpp_fmin<0x141, 0xF>(m);        // row_half_mirror
+  m = dpp_fmin<0x140, 0xF>(m);        // row_mirror
+  m = read_lane(m, 0);
+  uint32_t j = v == m ? i : 0xFFFFFFFFu;
+  j = dpp_umin<0xB1, 0xF>(j);
+  j = dpp_umin<0x4E, 0xF>(j);
+  j = dpp_umin<0x141, 0xF>(j);
+  j = dpp_umin<0x140, 0xF>(j);
+  j = (uint32_t)__builtin_amdgcn_readlane((int)j, 0);
+  lex_finish(v, i, m, j, 0xFFFFull);
+}
+
+// the same over the 64 lanes (all lanes active): after the row steps, row
+// 15 broadcast into rows 1 and 3, then row 31 broadcast into rows 2 and 3
+// leave the wave's minimum in lane 63.  The minimum of a total order does
+// not depend on the combining order.
 __device__ __forceinline__ void wave_lex_min(double &v, uint32_t &i) {
-  dpp_lex_step<0xB1, 0xF>(v, i);   // quad_perm 1 0 3 2
-  dpp_lex_step<0x4E, 0xF>(v, i);   // quad_perm 2 3 0 1
-  dpp_lex_step<0x141, 0xF>(v, i);  // row_half_mirror
-  dpp_lex_step<0x140, 0xF>(v, i);  // row_mirror
-  dpp_lex_step<0x142, 0xA>(v, i);  // row_bcast:15
-  dpp_lex_step<0x143, 0xC>(v, i);  // row_bcast:31
-  v = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
-                       __builtin_amdgcn_readlane(__double2loint(v), 63));
-  i = (uint32_t)__builtin_amdgcn_readlane((int)i, 63);
+  double m = dpp_fmin<0xB1, 0xF>(v);
+  m = dpp_fmin<0x4E, 0xF>(m);
+  m = dpp_fmin<0x141, 0xF>(m);
+  m = dpp_fmin<0x140, 0xF>(m);
+  m = dpp_fmin<0x142, 0xA>(m);  // row_bcast:15
+  m = dpp_fmin<0x143, 0xC>(m);  // row_bcast:31
+  m = read_lane(m, 63);
+  uint32_t j = v == m ? i : 0xFFFFFFFFu;
+  j = dpp_umin<0xB1, 0xF>(j);
+  j = dpp_umin<0x4E, 0xF>(j);
+  j = dpp_umin<0x141, 0xF>(j);
+  j = dpp_umin<0x140, 0xF>(j);
+  j = dpp_umin<0x142, 0xA>(j);
+  j = dpp_umin<0x143, 0xC>(j);
+  j = (uint32_t)__builtin_amdgcn_readlane((int)j, 63);
+  lex_finish(v, i, m, j, ~0ull);
 }
 
-// Minimum of D[k][j] over columns j > k that are active and not `skip`,
-// with its smallest argument, over the columns of part p of W parts (one
-// wave per part, eight loads in flight per lane; W = 1: the whole row).
-template <class Active>
-__device__ __forceinline__ void row_min(const double *D, uint32_t n, uint32_t k, uint32_t skip,
-                                        Active active, double &v, uint32_t &i, uint32_t p = 0,
-                                        uint32_t W = 1) {
+// Minimum of D[k][j] over active columns j > k other than s1 and s2, with
+// its smallest argument, in every lane (U loads in flight per lane).
+template <int U = 8, class Active>
+__device__ __forceinline__ void row_min(const double *D, uint32_t n, uint32_t k, uint32_t s1, uint32_t s2,
+                                        Active active, double &v, uint32_t &i) {
   const uint32_t lane = threadIdx.x & 63u;
   v = __builtin_inf();
   i = 0xFFFFFFFFu;
-  const double *row = D + (size_t)k * n;
-  const uint32_t stride = 64u * W;
-  for (uint32_t j0 = k + 1 + 64u * p; j0 < n; j0 += 8u * stride) {
-    double x[8];
+  const char *row = reinterpret_cast<const char *>(D + (size_t)k * n);  // k uniform: a scalar base
+  for (uint32_t j0 = k + 1; j0 < n; j0 += 64u * U) {
+    double x[U];
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
-      const uint32_t j = j0 + stride * u + lane;
-      x[u] = j < n ? row[j] : 0.0;
+    for (int u = 0; u < U; u++) {  // clamped, not branched: every load goes out at once
+      const uint32_t j = min(j0 + 64u * u + lane, n - 1);
+      x[u] = *reinterpret_cast<const double *>(row + 8u * j);
     }
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
-      const uint32_t j = j0 + stride * u + lane;
-      if (j < n && j != skip && active(j)) lex_min(v, i, x[u], j);
+    for (int u = 0; u < U; u++) {
+      const uint32_t j = j0 + 64u * u + lane;
+      if (j < n && j != s1 && j != s2 && active(j)) lex_min(v, i, x[u], j);
     }
   }
   wave_lex_min(v, i);
@@ -309,10 +387,6 @@ __device__ __forceinline__ void row_min(const double *D, uint32_t n, uint32_t k,
 
 struct AllActive {
   __device__ bool operator()(uint32_t) const { return true; }
-};
-struct LdsActive {
-  const uint8_t *act;
-  __device__ bool operator()(uint32_t j) const { return act[j] != 0; }
 };
 
 #pragma clang fp contract(off)
@@ -341,171 +415,299 @@ __global__ __launch_bounds__(256) void upgma_init_kernel(const uint32_t *__restr
   const uint32_t n = first[lo + 1] - first[lo], k = p - first[lo];
   double v;
   uint32_t i;
-  row_min(work + doff[lo], n, k, 0xFFFFFFFFu, AllActive{}, v, i);
+  row_min(work + doff[lo], n, k, 0xFFFFFFFFu, 0xFFFFFFFFu, AllActive{}, v, i);
   if ((threadIdx.x & 63u) == 0) {
     rmin[p] = v;
     rarg[p] = i;
   }
 }
 
+// pair key of row k: its minimum's argument (kNone16 when it has none) in
+// the low half, the row above it
+__device__ __forceinline__ uint32_t pair_key(uint32_t k, uint32_t arg) {
+  return (k << 16) | (arg < kNone16 ? arg : kNone16);
+}
+
 // A set whose remaining pairs compare false with everything (NaN
 // distances) stops there and records its index in *err.
-__global__ __launch_bounds__(1024) void upgma_kernel(const uint32_t *__restrict__ first,
-                                                     const uint64_t *__restrict__ doff,
-                                                     double *__restrict__ work,
-                                                     const double *__restrict__ rmin,
-                                                     const uint32_t *__restrict__ rarg,
-                                                     int32_t *__restrict__ merges,
-                                                     double *__restrict__ heights,
-                                                     unsigned long long *err) {
+//
+// Waves 0 .. RW-1 own the rows (thread tid: rows tid, tid + 64 RW, ...;
+// PER of them); the other waves only rescan.
+template <int RW, int PER>
+__global__ __launch_bounds__(64 * kTreeWaves) void upgma_kernel(const uint32_t *__restrict__ first,
+                                                                const uint64_t *__restrict__ doff,
+                                                                double *__restrict__ work,
+                                                                const double *__restrict__ rmin,
+                                                                const uint32_t *__restrict__ rarg,
+                                                                int32_t *__restrict__ merges,
+                                                                double *__restrict__ heights,
+                                                                unsigned long long *err) {
+  constexpr uint32_t RT = 64u * RW;  // threads that own rows
+  constexpr uint32_t RS = kTreeWaves - RW;  // rescanning waves
+  constexpr uint32_t kLogRS = __builtin_ctz(RS);
+  static_assert((RS & (RS - 1)) == 0 && RS <= 16 && RW <= 16, "wave partials hold 16 entries");
+  constexpr int kRescanLoads = 8;  // loads in flight per lane in a rescan
+  constexpr uint32_t kNo = 0xFFFFFFFFu;
   __shared__ TreeShared sh;
   const uint32_t set = blockIdx.x;
   const uint32_t f0 = first[set], n = first[set + 1] - f0;
   double *D = work + doff[set];
   int32_t *mg = merges + 2ull * (f0 - set);
   double *ht = heights + (f0 - set);
-  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-  for (uint32_t k = tid; k < n; k += 1024) {
-    sh.size[k] = 1;
-    sh.id[k] = (uint16_t)k;
-    sh.act[k] = 1;
-    sh.rowmin[k] = rmin[f0 + k];
-    sh.rowarg[k] = rarg[f0 + k] == 0xFFFFFFFFu ? kNone16 : (uint16_t)rarg[f0 + k];
-  }
-  if (tid == 0) sh.nredo = 0;
-  __syncthreads();
-  for (uint32_t t = 0; t + 1 < n; t++) {
-    // the pair: lexicographic minimum of (rowmin[a], a) over active a
-    // (a retired row's minimum is NaN, which no comparison selects: no
-    // test of act, and the rows' reads go out together); every wave
-    // reduces the 16 wave results itself (no second barrier)
-    constexpr int kPer = kTreeMax / 1024;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool rows = wave < RW;
+  if (n < 2) return;
+  // state, and the first pair's partials (buffer 0; no merged row or
+  // rescans yet)
+  for (uint32_t w = tid; w < kTreeMax / 32; w += 64u * kTreeWaves)
+    sh.act[w] = 32 * w + 32 <= n ? ~0u : (32 * w < n ? (1u << (n - 32 * w)) - 1u : 0u);
+  if (rows) {
     double v = __builtin_inf();
-    uint32_t i = 0xFFFFFFFFu;
-#pragma unroll
-    for (int u = 0; u < kPer; u++) {
-      const uint32_t a = tid + 1024u * u;
-      if (a < n) lex_min(v, i, sh.rowmin[a], a);
+    uint32_t i = kNo;
+    for (uint32_t k = tid; k < n; k += RT) {
+      const double m = rmin[f0 + k];
+      const uint32_t r = rarg[f0 + k];
+      sh.row[k].size = 1;
+      sh.row[k].id = (uint16_t)k;
+      sh.row[k].min = m;
+      sh.row[k].arg = r < kNone16 ? (uint16_t)r : kNone16;
+      lex_min(v, i, m, pair_key(k, r));
     }
     wave_lex_min(v, i);
     if (lane == 0) {
-      sh.wv[wave] = v;
-      sh.wi[wave] = i;
+      sh.pv[0][wave] = v;
+      sh.pi[0][wave] = i;
     }
-    __syncthreads();
-    v = lane < 16 ? sh.wv[lane] : __builtin_inf();
-    i = lane < 16 ? sh.wi[lane] : 0xFFFFFFFFu;
-    wave_lex_min(v, i);
-    const uint32_t a = i;
-    if (a >= n || sh.rowarg[a] == kNone16) {
+    if (tid == 0) sh.nredo[0] = sh.nredo[1] = 0;
+  }
+  __syncthreads();
+  uint32_t pa = kNo, pb = kNo;  // the previous merge's slots
+  double npa = 0.0;             // and the merged cluster's size
+  uint32_t np = 0, pw = 1;      // its rescans: parts, parts per row
+  // this thread's rows rescanned in the previous merge (bit u) and their
+  // places in the list (the entry a row adds to its rescan waits in its
+  // own minimum's slot)
+  uint32_t redo = 0;
+  uint32_t qpos[PER];
+#pragma unroll
+  for (int u = 0; u < PER; u++) qpos[u] = 0;
+  for (uint32_t t = 0; t + 1 < n; t++) {
+    const uint32_t buf = t & 1u;
+    uint32_t a = 0, b = 0;
+    double na = 1.0, nb = 1.0, h = 0.0;
+    double xa[PER], xb[PER], rm[PER];  // the rows' values, from one barrier to the next
+    uint32_t ra[PER];
+    bool use[PER];
+    if (rows) {
+      // the pair: the wave partials over the rows other than pa, row pa's
+      // partials and the rescans' parts (each keyed as its row)
+      double v = __builtin_inf();
+      uint32_t i = kNo;
+      if (lane < RW) {
+        v = sh.pv[buf][lane];
+        i = sh.pi[buf][lane];
+        if (pa != kNo) lex_min(v, i, sh.av[buf][lane], pair_key(pa, sh.ai[buf][lane]));
+      }
+      for (uint32_t p = lane; p < np; p += 64) lex_min(v, i, sh.partv[p], sh.parti[p]);
+      if (np <= 16) row_lex_min(v, i);  // everything in lanes 0-15
+      else wave_lex_min(v, i);
+      h = v;
+      a = i >> 16;
+      b = i & 0xFFFFu;
+      const bool bad = a >= n || b >= n;
+      if (tid == 0) {
+        sh.cur[0] = a;
+        sh.cur[1] = b;
+        sh.stop = bad;
+      }
+      if (!bad) {
+        // this thread's entries of rows a and b, out first
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+          const uint32_t k = tid + RT * u;
+          xa[u] = k < n ? D[(size_t)a * n + k] : 0.0;
+          xb[u] = k < n ? D[(size_t)b * n + k] : 0.0;
+        }
+        if (pa != kNo) {
+          // the previous merge's bookkeeping: row pa's minimum and the
+          // rescanned rows' minima (their owners keep them), slot pb
+          // retired, the merged cluster's size and id, the previous
+          // rescan count cleared
+          if (wave == (pa % RT) >> 6) {
+            double va = lane < RW ? sh.av[buf][lane] : __builtin_inf();
+            uint32_t ia = lane < RW ? sh.ai[buf][lane] : kNo;
+            row_lex_min(va, ia);
+            if (lane == pa % 64u) {
+              sh.row[pa].min = va;
+              sh.row[pa].arg = ia < kNone16 ? (uint16_t)ia : kNone16;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < PER; u++) {
+            if (!((redo >> u) & 1u)) continue;
+            const uint32_t k = tid + RT * u;
+            double rv = sh.row[k].min;
+            uint32_t ri = pair_key(k, sh.row[k].arg);
+            for (uint32_t p = qpos[u] * pw; p < (qpos[u] + 1) * pw; p++) lex_min(rv, ri, sh.partv[p], sh.parti[p]);
+            sh.row[k].min = rv;
+            sh.row[k].arg = (uint16_t)(ri & 0xFFFFu);
+          }
+          if (tid == pb % RT) atomicAnd(&sh.act[pb >> 5], ~(1u << (pb & 31u)));
+          if (tid == 0) {
+            sh.row[pa].size = (uint16_t)npa;
+            sh.row[pa].id = (uint16_t)(n + t - 1);
+            sh.nredo[buf ^ 1u] = 0;
+          }
+        }
+        // this thread's rows' minima, and the rows that need a rescan listed
+        redo = 0;
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+          const uint32_t k = tid + RT * u;
+          use[u] = k < n && slot_active(sh.act, k) && k != a && k != b;
+          rm[u] = use[u] ? sh.row[k].min : 0.0;
+          ra[u] = use[u] ? sh.row[k].arg : kNone16;
+          if (use[u] && (k < a ? (ra[u] == a || ra[u] == b) : (k < b && ra[u] == b))) {
+            redo |= 1u << u;
+            qpos[u] = atomicAdd(&sh.nredo[buf], 1u);
+            sh.redo[qpos[u]] = (uint16_t)k;
+          }
+        }
+      }
+    }
+    __syncthreads();  // the pair and the rescan list are complete
+    if (sh.stop) {
       if (tid == 0) atomicMin(err, (unsigned long long)set);
       return;
     }
-    const uint32_t b = sh.rowarg[a];
-    const double h = sh.rowmin[a];
-    const double na = (double)sh.size[a], nb = (double)sh.size[b];
-    if (tid == 0) {
-      const int32_t x = sh.id[a], y = sh.id[b];
-      mg[2 * t] = x < y ? x : y;
-      mg[2 * t + 1] = x < y ? y : x;
-      ht[t] = h / 2.0;
-    }
-    // update row and column a (loads first, then the arithmetic); row a's
-    // new minimum; rows that must rescan
-    double xa[kPer], xb[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; u++) {
-      const uint32_t k = tid + 1024u * u;
-      const bool use = k < n && sh.act[k] && k != a && k != b;
-      xa[u] = use ? D[(size_t)a * n + k] : 0.0;
-      xb[u] = use ? D[(size_t)b * n + k] : 0.0;
-    }
-    v = __builtin_inf();
-    i = 0xFFFFFFFFu;
-#pragma unroll
-    for (int u = 0; u < kPer; u++) {
-      const uint32_t k = tid + 1024u * u;
-      if (!(k < n && sh.act[k] && k != a && k != b)) continue;
-      const double nv = merge_mean(na, xa[u], nb, xb[u]);
-      D[(size_t)a * n + k] = nv;
-      D[(size_t)k * n + a] = nv;
-      if (k > a) {
-        lex_min(v, i, nv, k);
-        if (k < b && sh.rowarg[k] == b) sh.redo[atomicAdd(&sh.nredo, 1u)] = (uint16_t)k;
-      } else {
-        const uint16_t ra = sh.rowarg[k];
-        if (ra == a || ra == b) sh.redo[atomicAdd(&sh.nredo, 1u)] = (uint16_t)k;
-        else if (nv < sh.rowmin[k] || (nv == sh.rowmin[k] && a < ra)) {
-          sh.rowmin[k] = nv;
-          sh.rowarg[k] = (uint16_t)a;
-        }
+    const uint32_t nr = sh.nredo[buf];
+    if (rows) {
+      na = a == pa ? npa : (double)sh.row[a].size;
+      nb = b == pa ? npa : (double)sh.row[b].size;
+      if (tid == 0) {
+        const int32_t x = a == pa ? (int32_t)(n + t - 1) : sh.row[a].id;
+        const int32_t y = b == pa ? (int32_t)(n + t - 1) : sh.row[b].id;
+        mg[2 * t] = x < y ? x : y;
+        mg[2 * t + 1] = x < y ? y : x;
+        ht[t] = h / 2.0;
       }
-    }
-    wave_lex_min(v, i);
-    if (lane == 0) {  // a second buffer: slower waves may still read wv
-      sh.wv2[wave] = v;
-      sh.wi2[wave] = i;
-    }
-    __syncthreads();  // row a's parts, D and the redo list are complete
-    const uint32_t nr = sh.nredo;
-    if (wave == 0) {
-      v = lane < 16 ? sh.wv2[lane] : __builtin_inf();
-      i = lane < 16 ? sh.wi2[lane] : 0xFFFFFFFFu;
-      wave_lex_min(v, i);
+      // the merged row's entries; row a's minimum, and the next pair's over
+      // the other rows not rescanned (a rescanned row k < a adds its new
+      // entry at column a)
+      double av = __builtin_inf(), pv = __builtin_inf();
+      uint32_t ai = kNo, pi = kNo;
+#pragma unroll
+      for (int u = 0; u < PER; u++) {
+        const uint32_t k = tid + RT * u;
+        if (!use[u]) continue;
+        const double nv = merge_mean(na, xa[u], nb, xb[u]);
+        D[(size_t)a * n + k] = nv;
+        D[(size_t)k * n + a] = nv;
+        if (k > a) lex_min(av, ai, nv, k);
+        if ((redo >> u) & 1u) {
+          const double cv = k < a ? nv : __builtin_inf();
+          const uint32_t ca = k < a ? a : kNone16;
+          sh.row[k].min = cv;
+          sh.row[k].arg = (uint16_t)ca;
+          lex_min(pv, pi, cv, pair_key(k, ca));
+          continue;
+        }
+        if (k < a) {
+          if (nv < rm[u] || (nv == rm[u] && a < ra[u])) {
+            rm[u] = nv;
+            ra[u] = a;
+          }
+          sh.row[k].min = rm[u];
+          sh.row[k].arg = (uint16_t)ra[u];
+        }
+        lex_min(pv, pi, rm[u], pair_key(k, ra[u]));
+      }
+      wave_lex_min(av, ai);
+      wave_lex_min(pv, pi);
       if (lane == 0) {
-        sh.rowmin[a] = v;
-        sh.rowarg[a] = i == 0xFFFFFFFFu ? kNone16 : (uint16_t)i;
-        sh.act[b] = 0;
-        sh.rowmin[b] = __builtin_nan("");  // never the pair's minimum
-        sh.size[a] = (uint16_t)(sh.size[a] + sh.size[b]);
-        sh.id[a] = (uint16_t)(n + t);
+        sh.av[buf ^ 1u][wave] = av;
+        sh.ai[buf ^ 1u][wave] = ai;
+        sh.pv[buf ^ 1u][wave] = pv;
+        sh.pi[buf ^ 1u][wave] = pi;
       }
-    }
-    // rescans skip b explicitly (its slot is retired by wave 0 meanwhile).
-    // Up to 16 rows: W = 16 / rows waves share each row and their parts
-    // meet in LDS; more rows: one wave per row.
-    if (nr > 0 && nr <= 16) {
-      const uint32_t W = 16u / nr, q = wave / W;
-      if (q < nr) {
-        row_min(D, n, sh.redo[q], b, LdsActive{sh.act}, v, i, wave % W, W);
-        if (lane == 0) {
-          sh.wv[wave] = v;
-          sh.wi[wave] = i;
+    } else if (nr > 0) {
+      // the rescans, of the old rows without columns a and b: up to RS
+      // rows, W waves per row (RS / rows rounded down to a power of two),
+      // else whole rows in turn
+      a = sh.cur[0];
+      b = sh.cur[1];
+      const uint32_t rw = wave - RW;
+      if (nr <= RS) {
+        const uint32_t lw = nr == 1 ? kLogRS : kLogRS - (32u - __builtin_clz(nr - 1));
+        const uint32_t W = 1u << lw, q = rw >> lw, part = rw & (W - 1u);
+        if (q < nr) {
+          const uint32_t rk = sh.redo[q];
+          const char *rrow = reinterpret_cast<const char *>(D + (size_t)rk * n);
+          double v2 = __builtin_inf();
+          uint32_t i2 = kNo;
+          for (uint32_t j0 = rk + 1 + 64u * part; j0 < n; j0 += 64u * W * kRescanLoads) {
+            double rx[kRescanLoads];
+#pragma unroll
+            for (int u = 0; u < kRescanLoads; u++) {
+              const uint32_t j = min(j0 + 64u * W * u + lane, n - 1);
+              rx[u] = *reinterpret_cast<const double *>(rrow + 8u * j);
+            }
+#pragma unroll
+            for (int u = 0; u < kRescanLoads; u++) {
+              const uint32_t j = j0 + 64u * W * u + lane;
+              if (j < n && j != a && j != b && slot_active(sh.act, j)) lex_min(v2, i2, rx[u], j);
+            }
+          }
+          wave_lex_min(v2, i2);
+          if (lane == 0) {
+            sh.partv[rw] = v2;
+            sh.parti[rw] = pair_key(rk, i2);
+          }
+        }
+      } else {
+        for (uint32_t q = rw; q < nr; q += RS) {
+          const uint32_t k = sh.redo[q];
+          double v2;
+          uint32_t i2;
+          row_min<kRescanLoads>(D, n, k, a, b, BitActive{sh.act}, v2, i2);
+          if (lane == 0) {
+            sh.partv[q] = v2;
+            sh.parti[q] = pair_key(k, i2);
+          }
         }
       }
-      __syncthreads();
-      if (tid < nr) {
-        v = __builtin_inf();
-        i = 0xFFFFFFFFu;
-        for (uint32_t w = tid * W; w < (tid + 1) * W; w++) lex_min(v, i, sh.wv[w], sh.wi[w]);
-        const uint32_t k = sh.redo[tid];
-        sh.rowmin[k] = v;
-        sh.rowarg[k] = i == 0xFFFFFFFFu ? kNone16 : (uint16_t)i;
-      }
-    } else {
-      for (uint32_t q = wave; q < nr; q += 16) {
-        const uint32_t k = sh.redo[q];
-        row_min(D, n, k, b, LdsActive{sh.act}, v, i);
-        if (lane == 0) {
-          sh.rowmin[k] = v;
-          sh.rowarg[k] = i == 0xFFFFFFFFu ? kNone16 : (uint16_t)i;
-        }
-      }
     }
-    __syncthreads();
-    if (tid == 0) sh.nredo = 0;
+    __syncthreads();  // D, the rows' minima, the partials and the parts are complete
+    const uint32_t lw = nr <= 1 ? kLogRS : (nr <= RS ? kLogRS - (32u - __builtin_clz(nr - 1)) : 0u);
+    pw = nr > 0 && nr <= RS ? (1u << lw) : 1u;
+    np = nr > 0 && nr <= RS ? nr << lw : nr;
+    pa = a;
+    pb = b;
+    npa = na + nb;
   }
 }
 
-hipError_t launch_upgma(hipStream_t st, uint32_t nsets, uint32_t N, const uint32_t *first,
+hipError_t launch_upgma(hipStream_t st, uint32_t nsets, uint32_t N, uint32_t max_n, const uint32_t *first,
                         const uint64_t *doff, double *work, double *rmin, uint32_t *rarg,
                         int32_t *merges, double *heights, unsigned long long *err) {
   if (nsets == 0 || N == 0) return hipSuccess;
+  if (max_n > kTreeMax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(upgma_init_kernel, dim3((N + 3) / 4), dim3(256), 0, st, first, nsets, doff, work,
                      rmin, rarg);
   KD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(upgma_kernel, dim3(nsets), dim3(1024), 0, st, first, doff, work, rmin, rarg, merges,
-                     heights, err);
+  // the rows' owners and the rows per thread sized to the largest set
+  // (registers for the most rows only where needed)
+  const dim3 grid(nsets), block(64 * kTreeWaves);
+  if (max_n <= 1024)
+    hipLaunchKernelGGL((upgma_kernel<kTreeRowWavesSmall, 2>), grid, block, 0, st, first, doff, work, rmin, rarg,
+                       merges, heights, err);
+  else if (max_n <= 2048)
+    hipLaunchKernelGGL((upgma_kernel<kTreeRowWaves, 4>), grid, block, 0, st, first, doff, work, rmin, rarg, merges,
+                       heights, err);
+  else
+    hipLaunchKernelGGL((upgma_kernel<kTreeRowWaves, (kTreeMax + 64 * kTreeRowWaves - 1) / (64 * kTreeRowWaves)>),
+                       grid, block, 0, st, first, doff, work, rmin, rarg, merges, heights, err);
   return hipGetLastError();
 }
 

@@ -119,6 +119,17 @@ def _ultrametric(rng, n):
     return D, tree
 
 
+def _hubs(rng, n, hubs):
+    """Every row before hub column c has its minimum there (value v plus a
+    little noise): merging two hubs leaves hundreds of rows to rescan at
+    once, more than the merge kernel has waves."""
+    x = rng.random((n, n)) + 2.0
+    for c, v in hubs:
+        x[:c, c] = v + rng.random(c) * 1e-3
+    x = np.triu(x, 1)
+    return x + x.T
+
+
 def test_upgma_given_matrices(kd, ctx, oracle_mod):
     rng = np.random.default_rng(63)
     mats = []
@@ -134,6 +145,8 @@ def test_upgma_given_matrices(kd, ctx, oracle_mod):
         w[i, j] = w[j, i] = v
     mats.append(w)                                      # the worked example
     mats.append(_ultrametric(rng, 64)[0])
+    mats.append(_hubs(rng, 200, [(150, 0.5), (151, 0.6), (160, 0.1)]))
+    mats.append(_hubs(rng, 1500, [(900, 0.2), (901, 0.21), (1400, 0.3), (1401, 0.31)]))  # two rows per thread
     say("upgma", [m.shape[0] for m in mats])
     for mat, (m, h) in zip(mats, gpu_tree(ctx, kd, mats)):
         om, oh = oracle_mod.upgma(mat)
