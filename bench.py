@@ -57,9 +57,9 @@ TRAFFIC = {
                                                       "paper_0905_1744_amd/csrc/klog.h"],
                                           "sha256_16": "a24f7da4dc1db0fa",
                                           "bytes_per_launch": 2042262869},
-    ("dist_pairs_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "af0a1a19189c3909",
+    ("dist_pairs_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "d11a4ff3326eb917",
                                         "bytes_per_launch": 571903424},
-    ("upgma_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "af0a1a19189c3909",
+    ("upgma_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "d11a4ff3326eb917",
                                    "bytes_per_launch": 1006388171},
     # psp_g_kernel + psp_scores_kernel, the two launches of one psp_scores call
     ("psp", "psp"): {"sources": ["paper_0905_1744_amd/csrc/psp.hip"], "sha256_16": "27c995852957b595",

@@ -228,22 +228,22 @@ hipError_t launch_distances(hipStream_t st, const Segs &sg, uint32_t N, uint32_t
 // at column a or b are rescanned, reading the old row with columns a and b
 // left out (the new D[k][a] is added to the result).
 //
-// Thread tid owns rows tid, tid + 1024, ...: only it keeps their minima.
-// A merge has two barriers.  Before the first, each thread loads its rows'
-// entries of rows a and b and lists its rows that need a rescan; after it
-// the waves start the rescans' loads (W = 16 / rows waves per row), store
-// the new entries while those loads are in flight, and leave partial
-// minima in LDS: row a's, the next pair's over the other rows, and the
-// rescans' parts, all keyed by (minimum, row << 16 | argument) so that the
-// argument travels with the row.  After the second barrier every wave
-// reduces them to the next pair itself, and the owners take their rows'
+// Waves 0-7 own the rows (thread tid: rows tid, tid + 512, ...; only the
+// owner keeps a row's minimum); waves 8-15 rescan.  A merge has two
+// barriers.  Before the first, each owner wave reduces the pair itself,
+// loads its rows' entries of rows a and b, and lists its rows that need a
+// rescan; after it the rescanning waves take the listed rows (8 / rows
+// waves per row) while the owners store the new entries, and all leave
+// partial minima in LDS: row a's, the next pair's over the owners' other
+// rows, and the rescans' parts, all keyed by (minimum, row << 16 |
+// argument) so that the argument travels with the row.  After the second
+// barrier the owners reduce them to the next pair and take their rows'
 // new minima from them.
 
 constexpr uint32_t kTreeMax = kTreeMaxSeqs;
 constexpr uint16_t kNone16 = 0xFFFFu;
 constexpr int kTreeWaves = 16;  // waves of the merge kernel
-constexpr int kTreeRowWaves = 8;       // of which own rows (the rest rescan)
-constexpr int kTreeRowWavesSmall = 8;  // the same for sets of up to 1024
+constexpr int kTreeRowWaves = 8;  // of which own rows (the rest rescan)
 
 // a row's state in one 16-byte record: one address per row, the fields at
 // immediate offsets
@@ -696,17 +696,18 @@ hipError_t launch_upgma(hipStream_t st, uint32_t nsets, uint32_t N, uint32_t max
   hipLaunchKernelGGL(upgma_init_kernel, dim3((N + 3) / 4), dim3(256), 0, st, first, nsets, doff, work,
                      rmin, rarg);
   KD_HIP(hipGetLastError());
-  // the rows' owners and the rows per thread sized to the largest set
-  // (registers for the most rows only where needed)
+  // rows per owner thread sized to the largest set (registers for the
+  // most rows only where needed)
+  constexpr uint32_t RT = 64u * kTreeRowWaves;
   const dim3 grid(nsets), block(64 * kTreeWaves);
-  if (max_n <= 1024)
-    hipLaunchKernelGGL((upgma_kernel<kTreeRowWavesSmall, 2>), grid, block, 0, st, first, doff, work, rmin, rarg,
+  if (max_n <= 2 * RT)
+    hipLaunchKernelGGL((upgma_kernel<kTreeRowWaves, 2>), grid, block, 0, st, first, doff, work, rmin, rarg,
                        merges, heights, err);
-  else if (max_n <= 2048)
+  else if (max_n <= 4 * RT)
     hipLaunchKernelGGL((upgma_kernel<kTreeRowWaves, 4>), grid, block, 0, st, first, doff, work, rmin, rarg, merges,
                        heights, err);
   else
-    hipLaunchKernelGGL((upgma_kernel<kTreeRowWaves, (kTreeMax + 64 * kTreeRowWaves - 1) / (64 * kTreeRowWaves)>),
+    hipLaunchKernelGGL((upgma_kernel<kTreeRowWaves, (kTreeMax + RT - 1) / RT>),
                        grid, block, 0, st, first, doff, work, rmin, rarg, merges, heights, err);
   return hipGetLastError();
 }
