@@ -53,7 +53,7 @@ struct SetView {
   const uint32_t *D;           // [N] distinct words, sorted order
   const double *invK;          // [N] 1 / K, sorted order
   const uint64_t *grp_off;     // [G+1] u16-element offset of each group in gids
-  const uint32_t *grp_len;     // [G] padded list length of the group (multiple of 8)
+  const uint32_t *grp_len;     // [G] padded list length of the group (multiple of 16)
   const uint16_t *gids;        // interleaved distinct words: element t of the
                                // sequence in lane l of group g lives at
                                // grp_off[g] + ((t/8)*64 + l)*8 + t%8
