@@ -40,6 +40,7 @@ WORKLOADS = {
 # sources hash to the measured version and the same work-list shape is in use.
 RANK_SOURCES = ["paper_0905_1744_amd/csrc/pair.hip", "paper_0905_1744_amd/csrc/tile.h",
                 "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h"]
+BATCH_SOURCES = RANK_SOURCES + ["paper_0905_1744_amd/csrc/worklist.h"]  # the batch's work-list order
 TREE_SOURCES = ["paper_0905_1744_amd/csrc/tree.hip", "paper_0905_1744_amd/csrc/tile.h",
                 "paper_0905_1744_amd/csrc/bitcount.h", "paper_0905_1744_amd/csrc/klog.h",
                 "paper_0905_1744_amd/csrc/radix.h"]
@@ -61,6 +62,9 @@ TRAFFIC = {
                                         "bytes_per_launch": 571903424},
     ("upgma_kernel", "trees20k"): {"sources": TREE_SOURCES, "sha256_16": "d11a4ff3326eb917",
                                    "bytes_per_launch": 1006388171},
+    # the 4,096-set batch's one rank launch (profiles/batched_4096sets.md)
+    ("rank_pairs_kernel", "batched"): {"sources": BATCH_SOURCES, "sha256_16": "7ed972ae344349a1",
+                                       "bytes_per_launch": {64: 2631491243}},
     # psp_g_kernel + psp_scores_kernel, the two launches of one psp_scores call
     ("psp", "psp"): {"sources": ["paper_0905_1744_amd/csrc/psp.hip"], "sha256_16": "27c995852957b595",
                      "bytes_per_launch": 94294016 + 2873273344},
@@ -525,12 +529,12 @@ def bench_psp(args):
     print(json.dumps(line), flush=True)
 
 
-def batch_roofline(probes, pairs, lookups, ceiling, stages, alg_bytes):
+def batch_roofline(probes, pairs, lookups, ceiling, stages, alg_bytes, shape):
     """Roofline of the one rank launch of a batch (all sets), as for one set."""
     ms, n = stages["pairs"]
     t = ms / max(n, 1) / 1e3
-    return rank_roofline(probes, pairs, lookups, t, ceiling, None, alg_bytes,
-                         kernel="rank_pairs_kernel (all sets in one launch)")
+    return rank_roofline(probes, pairs, lookups, t, ceiling, measured_traffic("rank_pairs_kernel", "batched", shape),
+                         alg_bytes, kernel="rank_pairs_kernel (all sets in one launch)")
 
 
 def bench_batch_graph(ctx, res, off, first, Bs, args, out, t_eager):
@@ -615,7 +619,7 @@ def bench_batched(args):
         line = {"metric": "batched k-mer rank + split: pair-similarities/s", "value": pairs / t_batch,
                 "unit": "pair-similarities/s", "ms_per_step": t_batch * 1e3, "sets": len(sets),
                 "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
-                "roofline": batch_roofline(probes, pairs, lookups, ceiling, stages, alg_bytes), "graph": graph}
+                "roofline": batch_roofline(probes, pairs, lookups, ceiling, stages, alg_bytes, tune["tasks_per_cu"] if tune else 32), "graph": graph}
         ctx.close()
         print(json.dumps(line), flush=True)
         return
@@ -658,7 +662,7 @@ def bench_batched(args):
         "speedup_vs_per_set_loop": t_loop / t_batch,
         "identical_outputs": same,
         "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
-        "roofline": batch_roofline(probes, pairs, lookups, ceiling, stages, alg_bytes),
+        "roofline": batch_roofline(probes, pairs, lookups, ceiling, stages, alg_bytes, tune["tasks_per_cu"] if tune else 32),
         "graph": graph,
     }
     ctx.close()
@@ -952,7 +956,7 @@ def main():
     probes = probe_count(D)
     t_pair = pair_ms / max(pair_n, 1) / 1e3
     achieved = probes / t_pair / 1e12
-    tpc = tune["tasks_per_cu"] if tune else 4
+    tpc = tune["tasks_per_cu"] if tune else 32
     lookups = rank_lookups(D)
     ceiling = lds_ceiling(ctx)
     traffic = measured_traffic("rank_pairs_kernel", args.workload, tpc)

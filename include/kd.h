@@ -163,9 +163,11 @@ kd_status kmer_rank(kd_ctx *ctx, const kd_set *set, double delta, double *ranks)
  * counted object is cut into about T = t x (compute units) tasks of equal
  * estimated cost (runs of row blocks against strips of 2,048 sequences),
  * which one persistent workgroup per compute unit takes from per-XCD
- * queues; more tasks balance better, fewer flush fewer column sums to the
- * accumulators.  Times kmer_rank on `set` for each of the
- * KD_TUNE_CANDIDATES values t = {2, 4, 8, 16, 32} (one warm-up and three
+ * queues; more tasks balance better (and, in a batch, let more compute
+ * units of an XCD share one set's column lists in L2), fewer flush fewer
+ * column sums to the accumulators.  Without tuning t = 32.  Times
+ * kmer_rank on `set` for each of the
+ * KD_TUNE_CANDIDATES values t = {8, 16, 32, 64, 128} (one warm-up and three
  * timed runs each; the stream is synchronized), checks that all shapes give
  * bit-identical ranks (KD_EDEVICE otherwise), gives the set the smallest t
  * whose time is within 1% of the fastest (shapes that time alike are told

@@ -291,7 +291,7 @@ class Context:
                     "kmer_similarity")
         return (S, Dn) if denom else S
 
-    TUNE_SHAPES = (2, 4, 8, 16, 32)
+    TUNE_SHAPES = (8, 16, 32, 64, 128)
 
     def autotune(self, kset: KmerSet, delta: float = 0.1):
         """Pick the rank kernel's work-list shape for sets of this size class

@@ -1155,7 +1155,7 @@ extern "C" kd_status kd_autotune(kd_ctx *ctx, kd_set *s, double delta, uint32_t 
                                  double *ms_out) {
   if (!ctx || !s || s->ctx != ctx) return KD_EINVAL;
   if (!(delta > 0.0) || !std::isfinite(delta)) return KD_EINVAL;
-  static const uint32_t cand[KD_TUNE_CANDIDATES] = {2, 4, 8, 16, 32};
+  static const uint32_t cand[KD_TUNE_CANDIDATES] = {8, 16, 32, 64, 128};
   const uint32_t N = s->v.N;
   if (N == 0 || s->h_grp_len.size() != s->v.G) return KD_EINVAL;
   KD_TRY(hipSetDevice(ctx->device));

@@ -108,7 +108,7 @@ struct CrossTask {    // one workgroup's work in the globalized-rank pass
                       // 32 (batch-wide numbering, 0xFFFFFFFF = none)
   uint32_t rb0, rb1;  // row blocks [rb0, rb1) of the sample set
 };
-constexpr uint32_t kTasksPerCu = 4;  // default rank workgroups per compute unit (kd_autotune)
+constexpr uint32_t kTasksPerCu = 32;  // default rank tasks per compute unit (kd_autotune)
 constexpr size_t kGidsSlack = 16384;  // sentinel words after the last group (read-ahead)
 
 // ---------------------------------------------------------- host objects

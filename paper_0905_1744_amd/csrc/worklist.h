@@ -83,6 +83,11 @@ constexpr double kRowBlockCost = 6.0;
 //    fetched no fewer bytes.)  "Largest first" is a stable counting sort on
 //    the cost quantized to kCostLevels levels of the largest task: it runs
 //    in linear time while the device lays the lists out.
+//  - In a batch the key is the set's whole cost, so that a set's runs stay
+//    together in its queue and the compute units that take them at about
+//    the same time share its column lists in the XCD's L2 (ordered by the
+//    runs' own costs, every unit of an XCD worked on a set of its own and
+//    the 4,096-set launch fetched 36 GB).
 // grp_len: host copy of every column group's padded list length
 // (batch-wide numbering).
 constexpr uint32_t kCostLevels = 1024;
@@ -159,6 +164,21 @@ inline void build_costed_tasks(const std::vector<SetView> &views, const std::vec
   uint32_t levels = 16;
   while (levels < kCostLevels && levels < 4 * (uint32_t)(i / kXcdQueues + 1)) levels *= 2;
   levels = std::min(levels, kCostLevels);
+  if (views.size() > 1) {
+    // several sets: order by the set's whole cost instead, so that a set's
+    // runs stay together (stable sort: in row-block order) and the compute
+    // units of an XCD that take them at about the same time share the
+    // set's column lists in L2
+    std::vector<double> scost(views.size(), 0.0);
+    for (uint32_t x = 0; x < kXcdQueues; x++)
+      for (size_t k = 0; k < tk[x].size(); k++) scost[tk[x][k].set] += tc[x][k];
+    cmax = 0.0;
+    for (uint32_t x = 0; x < kXcdQueues; x++)
+      for (size_t k = 0; k < tk[x].size(); k++) {
+        tc[x][k] = scost[tk[x][k].set];
+        cmax = std::max(cmax, tc[x][k]);
+      }
+  }
   const double scale = cmax > 0.0 ? (levels - 1) / cmax : 0.0;
   std::vector<uint32_t> cnt(levels + 1);
   std::vector<uint16_t> key;
