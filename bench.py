@@ -51,7 +51,7 @@ TRAFFIC = {
     ("rank_pairs_kernel", "paper20k"): {"sources": RANK_SOURCES, "sha256_16": "0ebbc92f3c550ca3",
                                         "bytes_per_launch": {16: 209310720, 32: 204222805}},
     ("rank_pairs_kernel", "large100k"): {"sources": RANK_SOURCES, "sha256_16": "0ebbc92f3c550ca3",
-                                         "bytes_per_launch": {32: 6209227435}},
+                                         "bytes_per_launch": {32: 6209227435, 64: 4580742827}},
     ("rank_cross_kernel", "global100k"): {"sources": ["paper_0905_1744_amd/csrc/cross.hip",
                                                       "paper_0905_1744_amd/csrc/tile.h",
                                                       "paper_0905_1744_amd/csrc/bitcount.h",
