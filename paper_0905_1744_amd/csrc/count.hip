@@ -6,12 +6,16 @@
 // distinct words in increasing order with their counts, plus D (distinct
 // words), K and the number of words seen at least twice.
 //
-// Sequences of up to 4096 words: one 256-thread workgroup each; the
-// residues are mapped through an LDS Dayhoff-6 table and the words
-// collected in an LDS presence bitmap (see count_one).  Longer
-// sequences (rare) are queued and handled by a persistent kernel that
-// histograms into a dense 46656-bin LDS table (two 16-bit bins per word;
-// a sequence has at most 65535 words, so a bin never carries).
+// Four paths by the number of words K of a sequence:
+//  * K <= 256: one wave, the words in registers, sorted by a bitonic network
+//    (count_wave);
+//  * 256 < K <= 1024: one wave, a presence bitmap in the wave's LDS area
+//    (count_bitmap);
+//  * 1024 < K <= 4096: one 256-thread workgroup, a presence bitmap in LDS
+//    (count_one);
+//  * longer sequences (rare): a persistent kernel that histograms into a
+//    dense 46656-bin LDS table (two 16-bit bins per word; a sequence has at
+//    most 65535 words, so a bin never carries).
 #include <algorithm>
 
 #include "radix.h"
@@ -192,34 +196,15 @@ __device__ __forceinline__ void count_one(const uint8_t *__restrict__ res, uint6
 }
 
 // ------------------------------------------------------------------------
-// Register-resident counting of one sequence of K <= 64 E words by one
+// Register-resident counting of one sequence of n <= 64 E residues by one
 // wave: lane l forms words E l .. E l + E - 1 from its residues (and the
-// next lane's first five), the 64 E words are sorted across the wave with
-// a bitonic network (in-register stages for partners inside a lane, lane
-// shuffles otherwise), and runs of equal words give the distinct words and
-// their counts in order.  No LDS, no barriers.
-
-// 3-bit group code of the bytes 64 + x, x = 0..31 (7: not one of the 20
-// amino acids), eight per 32-bit word
-constexpr uint32_t letter_codes(int w) {
-  uint32_t t = 0;
-  for (int k = 0; k < 8; k++) {
-    const uint8_t c = dayhoff6((uint32_t)(64 + 8 * w + k));
-    t |= (uint32_t)(c == 255 ? 7 : c) << (3 * k);
-  }
-  return t;
-}
-constexpr uint32_t kCodes0 = letter_codes(0), kCodes1 = letter_codes(1);
-constexpr uint32_t kCodes2 = letter_codes(2), kCodes3 = letter_codes(3);
-
-__device__ __forceinline__ uint32_t code_of(uint32_t r) {
-  const uint32_t x = r & 31u, w = x >> 3;
-  const uint32_t t = w == 0 ? kCodes0 : w == 1 ? kCodes1 : w == 2 ? kCodes2 : kCodes3;
-  const uint32_t c = (t >> (3u * (x & 7u))) & 7u;
-  return (r >> 5) == 2u ? c : 7u;  // only bytes 64..95 can be letters
-}
+// following lanes' first five codes), the 64 E words are sorted across the
+// wave with a bitonic network (in-register stages for partners inside a
+// lane, lane shuffles otherwise), and runs of equal words give the distinct
+// words and their counts in order.  LDS holds only the residue table.
 
 constexpr uint32_t kPadWord = 0xFFFFu;  // above every word: sorts last
+constexpr uint32_t kWaveMaxLen = 1024;  // longest sequence (in residues) counted by one wave
 
 // Inclusive prefix sum over the wave by DPP moves (no LDS): shifts by 1, 2,
 // 4 and 8 inside each 16-lane row, then row 0's total into row 1 and row
@@ -319,8 +304,64 @@ __device__ __forceinline__ void bitonic_packed(uint32_t (&v)[E], uint32_t lane) 
   }
 }
 
+// Words E lane .. E lane + E - 1 of a sequence of n residues (kPadWord at
+// and past K = n - 5).  Each lane maps its own E residues through the
+// 256-entry group table lut (7: not one of the 20 amino acids) into 3-bit
+// codes, the first in the low bits; the five codes after them come from the
+// following lanes by DPP shifts.  The caller takes n <= 64 E, so the zeros
+// that lane 63 receives enter only padding words.  Word s + 1 follows
+// from word s by dropping its leading base-6 digit and appending the next
+// code.  A residue at or past n reads residue n - 1 instead, so its code is
+// valid whenever the sequence is; the words it enters are padding.  Returns
+// false, after recording the first position that is not an amino acid, when
+// there is one (uniform over the wave).
 template <int E>
-__device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint32_t i, uint64_t o0,
+__device__ __forceinline__ bool wave_words(const uint8_t *__restrict__ res, const uint8_t *lut,
+                                           uint32_t i, uint64_t o0, uint32_t n, uint32_t lane,
+                                           uint32_t (&v)[E], unsigned long long *err) {
+  static_assert(E >= 1 && 3 * (E + 5) <= 64, "codes of a lane and the five after them fit 64 bits");
+  const uint32_t K = n - (kK - 1);
+  const uint32_t t0 = lane * E;
+  const uint8_t *p = res + o0;
+  uint64_t win = 0;
+#pragma unroll
+  for (int u = 0; u < E; u++) win |= (uint64_t)lut[p[min(t0 + (uint32_t)u, n - 1)]] << (3 * u);
+  // a code is 7 exactly when its three bits are set
+  constexpr uint64_t kLow = 0x9249249249249249ull & ((1ull << (3 * E)) - 1);  // bit 0 of each code
+  const uint64_t sev = win & (win >> 1) & (win >> 2) & kLow;
+  if (__ballot(sev != 0)) {  // rare: the first bad position
+    uint32_t bad = 0xFFFFFFFFu;
+    if (sev) bad = t0 + (uint32_t)__builtin_ctzll(sev) / 3u;
+    bad = bad < n ? bad : 0xFFFFFFFFu;  // (a clamped read repeats residue n - 1)
+#pragma unroll
+    for (int o = 32; o; o >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, o, 64));
+    if (lane == 0) atomicMin(err, pack_err(i, kErrBadResidue, bad));
+    return false;
+  }
+  // the five codes after this lane's E: lane + 1's first min(E, 5), then
+  // lane + 2's, ...
+  uint32_t nxt = (uint32_t)win;
+#pragma unroll
+  for (int got = 0; got < 5; got += E) {
+    nxt = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)nxt, 0x130, 0xF, 0xF, false);  // wave_shl:1
+    const int take = 5 - got < E ? 5 - got : E;
+    win |= (uint64_t)(nxt & ((1u << (3 * take)) - 1u)) << (3 * (E + got));
+  }
+  uint32_t cd[E + 5];
+#pragma unroll
+  for (int j = 0; j < E + 5; j++) cd[j] = (uint32_t)(win >> (3 * j)) & 7u;
+  uint32_t w = cd[0] * 7776u + cd[1] * 1296u + cd[2] * 216u + cd[3] * 36u + cd[4] * 6u + cd[5];
+#pragma unroll
+  for (int s = 0; s < E; s++) {
+    if (s) w = (w - cd[s - 1] * 7776u) * 6u + cd[s + 5];
+    v[s] = t0 + s < K ? w : kPadWord;
+  }
+  return true;
+}
+
+template <int E>
+__device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, const uint8_t *lut,
+                                           uint32_t i, uint64_t o0,
                                            uint32_t n, uint64_t cap, uint16_t *__restrict__ cap_ids,
                                            uint16_t *__restrict__ cap_cnt,
                                            uint32_t *__restrict__ hi_cap,
@@ -328,33 +369,9 @@ __device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint
                                            uint32_t *__restrict__ nhiout, unsigned long long *err) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t K = n - (kK - 1);
-  const uint32_t t0 = lane * E;  // first word (and residue) of this lane
-  // residues t0 .. t0 + E + 4; positions past the end read the last
-  // residue (always in bounds) and are masked, so no load is conditional
-  const uint8_t *p = res + o0;
-  uint32_t c[E + 5];
-  uint32_t bad = 0xFFFFFFFFu;
-#pragma unroll
-  for (int u = 0; u < E + 5; u++) {
-    const uint32_t t = t0 + u;
-    const uint32_t code = code_of(p[min(t, n - 1)]);
-    const bool in = t < n;
-    c[u] = in ? code : 0u;
-    bad = (in && code == 7u) ? min(bad, t) : bad;
-  }
-  if (__ballot(bad != 0xFFFFFFFFu)) {  // rare: reduce to the first bad position
-#pragma unroll
-    for (int o = 32; o; o >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, o, 64));
-    if (lane == 0) atomicMin(err, pack_err(i, kErrBadResidue, bad));
-    return;
-  }
+  const uint32_t t0 = lane * E;
   uint32_t v[E];
-#pragma unroll
-  for (int s = 0; s < E; s++) {
-    const uint32_t w = c[s] * 7776u + c[s + 1] * 1296u + c[s + 2] * 216u + c[s + 3] * 36u +
-                       c[s + 4] * 6u + c[s + 5];
-    v[s] = t0 + s < K ? w : kPadWord;
-  }
+  if (!wave_words<E>(res, lut, i, o0, n, lane, v, err)) return;
   // Bitonic sort of the 64 E words, element index x = E lane + s, in the
   // form where every comparator puts the minimum at the lower index: each
   // merge of size k starts by comparing x with its mirror x ^ (k - 1), then
@@ -429,11 +446,184 @@ __device__ __forceinline__ void count_wave(const uint8_t *__restrict__ res, uint
   }
 }
 
-// First pass, one wave per sequence (four per workgroup): validates every
-// sequence, counts those of at most 1024 words in registers, and queues
-// longer ones for the 4096-word kernel or the dense-histogram one.
-constexpr uint32_t kWaveCountMax = 1024;
+// ------------------------------------------------------------------------
+// Counting of one sequence of kSortMaxLen < n <= kWaveMaxLen residues by one
+// wave through a presence bitmap in the wave's own LDS area, without a
+// sort.  Every word sets its bit (46656 bits, 1458 words).  Lane l then
+// owns bitmap words [24 l, 24 l + 24): their popcounts and a wave prefix
+// sum give, for each bitmap word, the number of distinct words below it.
+// A word's rank among the distinct words is that number plus the set bits
+// below it in its own bitmap word; each occurrence writes its word at its
+// rank (equal words write the same value) and adds one to the rank's
+// count.  Ranks in increasing order are the words in increasing order, so
+// the output (words, counts, the count >= 2 entries) is that of the sort.
+// The bitmap words an occurrence set and the counts are cleared after use,
+// so the area is clean for the wave's next sequence.
+constexpr uint32_t kSortMaxLen = 256;   // longest sequence (in residues) of the register sort
+constexpr uint32_t kBmLaneWords = 24;   // bitmap words per lane: 64 x 24 >= 1458
 
+struct alignas(16) BmWave {
+  uint32_t bm[64 * kBmLaneWords];   // presence bits; the words past 1458 stay zero
+  uint16_t pre[64 * kBmLaneWords];  // distinct words below each bitmap word
+  uint16_t dw[kWaveMaxLen];         // distinct words in increasing order
+  uint32_t cnt[kWaveMaxLen / 2];    // occurrences per rank, two 16-bit counts per entry
+};
+
+// Orders one wave's LDS accesses before and after it: a wave's LDS
+// operations reach the LDS in issue order, so a compiler barrier is all
+// that is needed for its lanes to see each other's writes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int E>
+__device__ __forceinline__ void count_bitmap(const uint8_t *__restrict__ res, const uint8_t *lut,
+                                             uint32_t i, uint64_t o0,
+                                             uint32_t n, uint64_t cap, BmWave &w,
+                                             uint16_t *__restrict__ cap_ids,
+                                             uint16_t *__restrict__ cap_cnt,
+                                             uint32_t *__restrict__ hi_cap,
+                                             uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout,
+                                             uint32_t *__restrict__ nhiout, unsigned long long *err) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t K = n - (kK - 1);
+  const uint32_t t0 = lane * E;
+  uint32_t v[E];
+  if (!wave_words<E>(res, lut, i, o0, n, lane, v, err)) return;
+#pragma unroll
+  for (int s = 0; s < E; s++)
+    if (t0 + s < K) atomicOr(&w.bm[v[s] >> 5], 1u << (v[s] & 31u));
+  wave_lds_sync();
+  uint32_t b[kBmLaneWords];
+  const uint4 *src = reinterpret_cast<const uint4 *>(w.bm + kBmLaneWords * lane);
+#pragma unroll
+  for (uint32_t q = 0; q < kBmLaneWords / 4; q++) {
+    const uint4 x = src[q];
+    b[4 * q] = x.x;
+    b[4 * q + 1] = x.y;
+    b[4 * q + 2] = x.z;
+    b[4 * q + 3] = x.w;
+  }
+  uint32_t below[kBmLaneWords], tot = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kBmLaneWords; q++) {
+    below[q] = tot;
+    tot += (uint32_t)__popc(b[q]);
+  }
+  const uint32_t incl = wave_incl_sum(tot);
+  const uint32_t D = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  const uint32_t base = incl - tot;
+  uint2 *dst = reinterpret_cast<uint2 *>(w.pre + kBmLaneWords * lane);
+#pragma unroll
+  for (uint32_t q = 0; q < kBmLaneWords / 4; q++)
+    dst[q] = make_uint2((base + below[4 * q]) | ((base + below[4 * q + 1]) << 16),
+                        (base + below[4 * q + 2]) | ((base + below[4 * q + 3]) << 16));
+  wave_lds_sync();
+  // every read before the first write, so the reads go out together
+  uint32_t pw[E], bw[E];
+#pragma unroll
+  for (int s = 0; s < E; s++) {
+    const uint32_t x = min(v[s] >> 5, 64u * kBmLaneWords - 1u);  // padding reads a zero word
+    pw[s] = w.pre[x];
+    bw[s] = w.bm[x];
+  }
+#pragma unroll
+  for (int s = 0; s < E; s++) {
+    if (t0 + s < K) {
+      const uint32_t r = pw[s] + (uint32_t)__popc(bw[s] & ((1u << (v[s] & 31u)) - 1u));
+      w.dw[r] = (uint16_t)v[s];
+      atomicAdd(&w.cnt[r >> 1], 1u << ((r & 1u) << 4));
+    }
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int s = 0; s < E; s++)
+    if (t0 + s < K) w.bm[v[s] >> 5] = 0u;
+  const uint64_t co = o0 - 5ull * i;
+  const bool ok = (o0 >= 5ull * i) && (co + K <= cap);
+  uint32_t nh = 0;
+  for (uint32_t r0 = 0; r0 < D; r0 += 64) {
+    const uint32_t r = r0 + lane;
+    uint32_t c = 0, wd = 0;
+    if (r < D) {
+      wd = w.dw[r];
+      c = (w.cnt[r >> 1] >> ((r & 1u) << 4)) & 0xFFFFu;
+      if (ok) {
+        cap_ids[co + r] = (uint16_t)wd;
+        cap_cnt[co + r] = (uint16_t)c;
+      }
+      if ((r & 1u) == 0) w.cnt[r >> 1] = 0u;  // after both ranks of the entry were read
+    }
+    const unsigned long long m = __ballot(c >= 2);
+    if (c >= 2 && ok) hi_cap[co + nh + (uint32_t)__popcll(m & lanemask_lt())] = wd | (c << 16);
+    nh += (uint32_t)__popcll(m);
+  }
+  wave_lds_sync();
+  if (lane == 0) {
+    Dout[i] = D;
+    Kout[i] = K;
+    nhiout[i] = nh;
+  }
+}
+
+// Second pass over the sequences of kSortMaxLen < n <= kWaveMaxLen residues:
+// persistent, one LDS area per wave.  A wave takes chunks of 64
+// consecutive sequences from a counter, finds with one ballot those on this
+// path (re-validating their offsets: an invalid sequence was reported by
+// the first pass and is skipped), and counts them one after the other.
+constexpr uint32_t kBmWavesPerGroup = 4;
+constexpr uint32_t kBmGroupsPerCu = 3;  // 3 x 4 x 13 KB of LDS per compute unit
+
+__global__ __launch_bounds__(64 * kBmWavesPerGroup) void count_bitmap_kernel(
+    const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint32_t N, uint64_t nres,
+    uint64_t cap, uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt,
+    uint32_t *__restrict__ hi_cap, uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout,
+    uint32_t *__restrict__ nhiout, uint32_t *__restrict__ next_chunk, unsigned long long *err) {
+  __shared__ BmWave area[kBmWavesPerGroup];
+  __shared__ uint8_t lut[256];
+  for (uint32_t c = threadIdx.x; c < 256; c += blockDim.x) lut[c] = dayhoff6(c) == 255 ? 7 : dayhoff6(c);
+  __syncthreads();  // the kernel's only workgroup barrier
+  const uint32_t lane = threadIdx.x & 63u;
+  BmWave &w = area[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
+  for (uint32_t x = lane; x < 64u * kBmLaneWords; x += 64) w.bm[x] = 0u;
+  for (uint32_t x = lane; x < kWaveMaxLen / 2; x += 64) w.cnt[x] = 0u;
+  wave_lds_sync();
+  for (;;) {
+    uint32_t ch = 0;
+    if (lane == 0) ch = atomicAdd(next_chunk, 1u);
+    ch = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)ch, 0, 64));
+    if ((uint64_t)ch * 64u >= N) break;  // every wave ends here once the chunks are taken
+    const uint32_t il = ch * 64u + lane;
+    uint64_t a0 = 0, a1 = 0;
+    bool take = false;
+    if (il < N && check_offsets(off, il, N, nres, a0, a1) == kErrNone) {
+      take = a1 - a0 > kSortMaxLen && a1 - a0 <= kWaveMaxLen;
+    }
+    unsigned long long m = __ballot(take);
+    while (m) {
+      const uint32_t j = (uint32_t)__builtin_ctzll(m);
+      m &= m - 1ull;
+      const uint32_t i = ch * 64u + j;
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)a0, j);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(a0 >> 32), j);
+      const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(a1 - a0), j);
+      const uint64_t o0 = ((uint64_t)hi << 32) | lo;
+      if (kSortMaxLen < 256u && n <= 256u)
+        count_bitmap<4>(res, lut, i, o0, n, cap, w, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+      else if (n <= 512u)
+        count_bitmap<8>(res, lut, i, o0, n, cap, w, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+      else
+        count_bitmap<16>(res, lut, i, o0, n, cap, w, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+    }
+  }
+}
+
+// First pass, one wave per sequence (four per workgroup): validates every
+// sequence, counts those of at most kSortMaxLen residues in registers,
+// leaves those of at most kWaveMaxLen residues to the bitmap pass, and queues
+// longer ones for the 4096-word kernel or the dense-histogram one.
 __global__ __launch_bounds__(256) void count_wave_kernel(
     const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint64_t *__restrict__ in_off,
     uint32_t N, uint64_t nres,
@@ -442,6 +632,9 @@ __global__ __launch_bounds__(256) void count_wave_kernel(
     uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout, uint32_t *__restrict__ nhiout,
     uint32_t *__restrict__ mid_list, uint32_t *__restrict__ nmid, uint32_t *__restrict__ long_list,
     uint32_t *__restrict__ nlong, unsigned long long *err) {
+  __shared__ uint8_t lut[256];
+  lut[threadIdx.x] = dayhoff6(threadIdx.x) == 255 ? 7 : dayhoff6(threadIdx.x);
+  __syncthreads();  // the kernel's only workgroup barrier
   const uint32_t i = blockIdx.x * 4u + (threadIdx.x >> 6), lane = threadIdx.x & 63u;
   if (i >= N) return;
   uint64_t o0, o1;
@@ -456,21 +649,21 @@ __global__ __launch_bounds__(256) void count_wave_kernel(
   }
   const uint32_t n = (uint32_t)(o1 - o0);
   const uint32_t K = n - (kK - 1);
-  if (K > kWaveCountMax) {
+  if (n > kSortMaxLen && n <= kWaveMaxLen) return;  // count_bitmap_kernel's
+  if (n > kWaveMaxLen) {
     if (lane == 0) {
       if (K <= (uint32_t)kShortMax) mid_list[atomicAdd(nmid, 1u)] = i;
       else long_list[atomicAdd(nlong, 1u)] = i;
     }
     return;
   }
-  if (K <= 64u) count_wave<1>(res, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
-  else if (K <= 128u) count_wave<2>(res, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
-  else if (K <= 256u) count_wave<4>(res, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
-  else if (K <= 512u) count_wave<8>(res, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
-  else count_wave<16>(res, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  if (n <= 64u) count_wave<1>(res, lut, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  else if (n <= 128u) count_wave<2>(res, lut, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  else count_wave<4>(res, lut, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
 }
 
-// Sequences of 1025..4096 words, queued by the first pass.
+// Sequences of more than 1024 residues and at most 4096 words, queued by
+// the first pass.
 __global__ __launch_bounds__(kCountThreads) void count_mid_kernel(
     const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint64_t nres, uint64_t cap,
     uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt, uint32_t *__restrict__ hi_cap,
@@ -567,13 +760,18 @@ hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off,
                         uint32_t N, uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
                         uint32_t *hi_cap, uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig,
                         uint32_t *mid_list, uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
-                        unsigned long long *err, int cus) {
+                        uint32_t *next_chunk, unsigned long long *err, int cus) {
   if (N == 0) return hipSuccess;
   hipLaunchKernelGGL(count_wave_kernel, dim3((N + 3) / 4), dim3(256), 0, st, res, off, in_off, N,
                      nres, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig, nhi_orig, mid_list, nmid,
                      long_list, nlong, err);
   KD_HIP(hipGetLastError());
   const uint32_t grid = (uint32_t)(cus > 0 ? cus : 256);
+  const uint32_t chunks = (N + 63) / 64;
+  const uint32_t bm_grid = std::min(kBmGroupsPerCu * grid, (chunks + kBmWavesPerGroup - 1) / kBmWavesPerGroup);
+  hipLaunchKernelGGL(count_bitmap_kernel, dim3(bm_grid), dim3(64 * kBmWavesPerGroup), 0, st, res, off, N,
+                     nres, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig, nhi_orig, next_chunk, err);
+  KD_HIP(hipGetLastError());
   hipLaunchKernelGGL(count_mid_kernel, dim3(2 * grid), dim3(kCountThreads), 0, st, res, off, nres,
                      cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig, nhi_orig, mid_list, nmid, err);
   KD_HIP(hipGetLastError());

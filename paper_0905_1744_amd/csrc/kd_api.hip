@@ -494,7 +494,8 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   uint32_t max_n = 0;
   for (uint32_t q = 0; q < nsets; q++) max_n = std::max(max_n, first[q + 1] - first[q]);
   void *sort_tmp = tmp.get<char>(sort_scratch_bytes(max_n));
-  // [0] err, [1] nlong | nmid, [8 ..] LayoutMeta: cleared by one launch
+  // [0] err, [1] nlong | nmid, [2] the bitmap pass's chunk counter, [8 ..]
+  // LayoutMeta: cleared by one launch
   unsigned long long *small = tmp.get<unsigned long long>(8 + (sizeof(LayoutMeta) + 7) / 8);
   LayoutMeta *meta = reinterpret_cast<LayoutMeta *>(small + 8);
   void *meta_tmp = tmp.get<char>(layout_meta_scratch_bytes(N, G, RB));
@@ -519,6 +520,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   unsigned long long *err = small;
   uint32_t *nlong = reinterpret_cast<uint32_t *>(small + 1);  // [0] long, [1] mid
   uint32_t *nmid = nlong + 1;
+  uint32_t *next_chunk = reinterpret_cast<uint32_t *>(small + 2);
   hipError_t e = upload(ctx, segb, hb.data(), sizeof(uint32_t) * hb.size());
   if (e == hipSuccess && nsets > 1)
     e = issue(ctx, [=](hipStream_t q) { return launch_seg_ids(q, sg, segid, segid + N, segid + N + G); });
@@ -538,7 +540,7 @@ kd_status build_sets(kd_ctx *ctx, const uint8_t *residues, const uint64_t *offse
   else if (e == hipSuccess)
     e = issue(ctx, [=](hipStream_t q) {
       return launch_count(q, residues, offsets, in_off, N, n_residues, cap, cap_ids, cap_cnt, hi_cap, Dorig,
-                          Korig, nhi_orig, mid_list, nmid, long_list, nlong, err, ctx->cus);
+                          Korig, nhi_orig, mid_list, nmid, long_list, nlong, next_chunk, err, ctx->cus);
     });
   t_count.done();
   StageTimer t_layout(ctx, KD_STAGE_LAYOUT);

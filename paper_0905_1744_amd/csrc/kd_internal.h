@@ -199,7 +199,7 @@ hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off,
                         uint32_t N, uint64_t nres, uint64_t cap, uint16_t *cap_ids, uint16_t *cap_cnt,
                         uint32_t *hi_cap, uint32_t *Dorig, uint32_t *Korig, uint32_t *nhi_orig,
                         uint32_t *mid_list, uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
-                        unsigned long long *err, int cus);
+                        uint32_t *next_chunk, unsigned long long *err, int cus);
 
 // per set s: stable sort of (key u32 < 2^16, value = local index) over the
 // set's range of keys; writes perm (local indices) over the same range.

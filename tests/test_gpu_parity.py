@@ -93,14 +93,15 @@ def test_count_long_sequences(kd, ctx, oracle_mod):
 
 @pytest.mark.parametrize("alphabet", [b"ACDEFGHIKLMNPQRSTVWY", b"AC"])
 def test_count_path_boundaries(kd, ctx, oracle_mod, alphabet):
-    """Word counts K at every boundary of the counting paths: one wave with
-    1, 2, 4, 8 or 16 words per lane (K <= 64, 128, 256, 512, 1024), the
-    4096-word pass and the dense-histogram pass; the two-letter alphabet
-    makes almost every word repeat."""
+    """Sequence sizes at every boundary of the counting paths: one wave with
+    1, 2 or 4 residues per lane and the register sort (n <= 64, 128, 256
+    residues), one wave with 8 or 16 per lane and the LDS bitmap (n <= 512,
+    1024), the 4096-word pass and the dense-histogram pass (K = n - 5 words);
+    the two-letter alphabet makes almost every word repeat."""
     rng = np.random.default_rng(24)
     al = np.frombuffer(alphabet, dtype=np.uint8)
-    Ks = [1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025,
-          2048, 4095, 4096, 4097]
+    Ks = [1, 2, 59, 60, 63, 64, 65, 123, 124, 127, 128, 129, 251, 252, 255, 256, 257, 507, 508,
+          511, 512, 513, 1019, 1020, 1023, 1024, 1025, 2048, 4095, 4096, 4097]
     seqs = [al[rng.integers(0, len(al), size=k + 5)].tobytes() for k in Ks]
     ss = synth.from_strings(seqs)
     say("count-boundaries", alphabet[:4], len(seqs))
@@ -114,7 +115,11 @@ def test_count_errors(kd, ctx):
         (["ACDEFGH", "ACDEFGH", "A" * 65541], -4, 2, None),
         (["ACDEFGH", "acdefgh"], -2, 1, 0),
         (["ACDEFGH", "B" * 5000], -2, 1, 0),   # bad residue on the long path
-        (["ACDEFGH" * 40, "ACDEFGH" * 40 + "Z"], -2, 1, 280),  # last residue, one-wave path
+        (["ACDEFGH" * 40, "ACDEFGH" * 40 + "Z"], -2, 1, 280),  # last residue, bitmap path
+        (["ACDEFGH" * 36 + "ACDZ"], -2, 0, 255),  # last residue, register path (256 residues)
+        (["ACDEFGH" * 146 + "AX"], -2, 0, 1023),  # last residue, 16 residues per lane
+        (["ACDEFGH" * 50 + "QQ*QQ*" + "ACDEFGH" * 20], -2, 0, 352),  # the first of two
+        (["ACDEFGH", "x" + "ACDEFGH" * 60], -2, 1, 0),  # first residue, bitmap path
         (["ACDEFGH" * 300 + "*" + "ACDEFGH"], -2, 0, 2100),  # the 4096-word path
         (["ACDEFGHIK", "ACDEFGHIK" * 30, "ACDEFGHIK", "ACDEFG1"], -2, 3, 6),
     ]
