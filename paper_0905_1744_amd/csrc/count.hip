@@ -6,13 +6,14 @@
 // distinct words in increasing order with their counts, plus D (distinct
 // words), K and the number of words seen at least twice.
 //
-// Four paths by the number of words K of a sequence:
-//  * K <= 256: one wave, the words in registers, sorted by a bitonic network
-//    (count_wave);
-//  * 256 < K <= 1024: one wave, a presence bitmap in the wave's LDS area
-//    (count_bitmap);
-//  * 1024 < K <= 4096: one 256-thread workgroup, a presence bitmap in LDS
-//    (count_one);
+// Four paths by the size of a sequence (n residues, K = n - 5 words):
+//  * n <= 1024: one wave, the words in registers, sorted by a bitonic
+//    network (count_wave); in a set of at least 64 x the bitmap pass's
+//    resident waves (196,608 sequences on 256 compute units) only n <= 256,
+//    and 256 < n <= 1024 one wave with a presence bitmap in the wave's LDS
+//    area (count_bitmap);
+//  * n > 1024 and K <= 4096: one 256-thread workgroup, a presence bitmap in
+//    LDS (count_one);
 //  * longer sequences (rare): a persistent kernel that histograms into a
 //    dense 46656-bin LDS table (two 16-bit bins per word; a sequence has at
 //    most 65535 words, so a bin never carries).
@@ -568,11 +569,14 @@ __device__ __forceinline__ void count_bitmap(const uint8_t *__restrict__ res, co
   }
 }
 
-// Second pass over the sequences of kSortMaxLen < n <= kWaveMaxLen residues:
-// persistent, one LDS area per wave.  A wave takes chunks of 64
-// consecutive sequences from a counter, finds with one ballot those on this
-// path (re-validating their offsets: an invalid sequence was reported by
-// the first pass and is skipped), and counts them one after the other.
+// Second pass over the sequences of kSortMaxLen < n <= kWaveMaxLen residues,
+// one LDS area per wave.  A wave takes chunks of cs <= 64 consecutive
+// sequences: its own, then, in a persistent launch, chunks from a counter.
+// One ballot finds a chunk's sequences on this path (re-validating their
+// offsets: an invalid sequence was reported by the first pass and is
+// skipped), and the wave counts them one after the other.  cs grows with N
+// (launch_count), so a small set still spreads its sequences over many
+// waves and a large one takes few counter increments.
 constexpr uint32_t kBmWavesPerGroup = 4;
 constexpr uint32_t kBmGroupsPerCu = 3;  // 3 x 4 x 13 KB of LDS per compute unit
 
@@ -580,7 +584,8 @@ __global__ __launch_bounds__(64 * kBmWavesPerGroup) void count_bitmap_kernel(
     const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint32_t N, uint64_t nres,
     uint64_t cap, uint16_t *__restrict__ cap_ids, uint16_t *__restrict__ cap_cnt,
     uint32_t *__restrict__ hi_cap, uint32_t *__restrict__ Dout, uint32_t *__restrict__ Kout,
-    uint32_t *__restrict__ nhiout, uint32_t *__restrict__ next_chunk, unsigned long long *err) {
+    uint32_t *__restrict__ nhiout, uint32_t cs, bool persistent, uint32_t *__restrict__ next_chunk,
+    unsigned long long *err) {
   __shared__ BmWave area[kBmWavesPerGroup];
   __shared__ uint8_t lut[256];
   for (uint32_t c = threadIdx.x; c < 256; c += blockDim.x) lut[c] = dayhoff6(c) == 255 ? 7 : dayhoff6(c);
@@ -590,22 +595,22 @@ __global__ __launch_bounds__(64 * kBmWavesPerGroup) void count_bitmap_kernel(
   for (uint32_t x = lane; x < 64u * kBmLaneWords; x += 64) w.bm[x] = 0u;
   for (uint32_t x = lane; x < kWaveMaxLen / 2; x += 64) w.cnt[x] = 0u;
   wave_lds_sync();
+  // the first chunk is the wave's own; a persistent launch continues with
+  // chunks from the counter, numbered after the launch's waves
+  uint32_t ch = blockIdx.x * kBmWavesPerGroup + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (;;) {
-    uint32_t ch = 0;
-    if (lane == 0) ch = atomicAdd(next_chunk, 1u);
-    ch = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)ch, 0, 64));
-    if ((uint64_t)ch * 64u >= N) break;  // every wave ends here once the chunks are taken
-    const uint32_t il = ch * 64u + lane;
+    if ((uint64_t)ch * cs >= N) break;  // every wave ends here once the chunks are taken
+    const uint32_t il = ch * cs + lane;
     uint64_t a0 = 0, a1 = 0;
     bool take = false;
-    if (il < N && check_offsets(off, il, N, nres, a0, a1) == kErrNone) {
+    if (lane < cs && il < N && check_offsets(off, il, N, nres, a0, a1) == kErrNone) {
       take = a1 - a0 > kSortMaxLen && a1 - a0 <= kWaveMaxLen;
     }
     unsigned long long m = __ballot(take);
     while (m) {
       const uint32_t j = (uint32_t)__builtin_ctzll(m);
       m &= m - 1ull;
-      const uint32_t i = ch * 64u + j;
+      const uint32_t i = ch * cs + j;
       const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)a0, j);
       const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(a0 >> 32), j);
       const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(a1 - a0), j);
@@ -617,13 +622,19 @@ __global__ __launch_bounds__(64 * kBmWavesPerGroup) void count_bitmap_kernel(
       else
         count_bitmap<16>(res, lut, i, o0, n, cap, w, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
     }
+    if (!persistent) break;
+    uint32_t nx = 0;
+    if (lane == 0) nx = atomicAdd(next_chunk, 1u);
+    ch = gridDim.x * kBmWavesPerGroup + (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)nx, 0, 64));
   }
 }
 
 // First pass, one wave per sequence (four per workgroup): validates every
-// sequence, counts those of at most kSortMaxLen residues in registers,
-// leaves those of at most kWaveMaxLen residues to the bitmap pass, and queues
-// longer ones for the 4096-word kernel or the dense-histogram one.
+// sequence, counts in registers those of at most kWaveMaxLen residues (ALL)
+// or of at most kSortMaxLen, leaving the others up to kWaveMaxLen to the
+// bitmap pass, and queues longer ones for the 4096-word kernel or the
+// dense-histogram one.
+template <bool ALL>
 __global__ __launch_bounds__(256) void count_wave_kernel(
     const uint8_t *__restrict__ res, const uint64_t *__restrict__ off, uint64_t *__restrict__ in_off,
     uint32_t N, uint64_t nres,
@@ -649,7 +660,7 @@ __global__ __launch_bounds__(256) void count_wave_kernel(
   }
   const uint32_t n = (uint32_t)(o1 - o0);
   const uint32_t K = n - (kK - 1);
-  if (n > kSortMaxLen && n <= kWaveMaxLen) return;  // count_bitmap_kernel's
+  if (!ALL && n > kSortMaxLen && n <= kWaveMaxLen) return;  // count_bitmap_kernel's
   if (n > kWaveMaxLen) {
     if (lane == 0) {
       if (K <= (uint32_t)kShortMax) mid_list[atomicAdd(nmid, 1u)] = i;
@@ -659,7 +670,9 @@ __global__ __launch_bounds__(256) void count_wave_kernel(
   }
   if (n <= 64u) count_wave<1>(res, lut, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
   else if (n <= 128u) count_wave<2>(res, lut, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
-  else count_wave<4>(res, lut, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  else if (!ALL || n <= 256u) count_wave<4>(res, lut, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  else if (n <= 512u) count_wave<8>(res, lut, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
+  else count_wave<16>(res, lut, i, o0, n, cap, cap_ids, cap_cnt, hi_cap, Dout, Kout, nhiout, err);
 }
 
 // Sequences of more than 1024 residues and at most 4096 words, queued by
@@ -762,16 +775,35 @@ hipError_t launch_count(hipStream_t st, const uint8_t *res, const uint64_t *off,
                         uint32_t *mid_list, uint32_t *nmid, uint32_t *long_list, uint32_t *nlong,
                         uint32_t *next_chunk, unsigned long long *err, int cus) {
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(count_wave_kernel, dim3((N + 3) / 4), dim3(256), 0, st, res, off, in_off, N,
-                     nres, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig, nhi_orig, mid_list, nmid,
-                     long_list, nlong, err);
-  KD_HIP(hipGetLastError());
   const uint32_t grid = (uint32_t)(cus > 0 ? cus : 256);
-  const uint32_t chunks = (N + 63) / 64;
-  const uint32_t bm_grid = std::min(kBmGroupsPerCu * grid, (chunks + kBmWavesPerGroup - 1) / kBmWavesPerGroup);
-  hipLaunchKernelGGL(count_bitmap_kernel, dim3(bm_grid), dim3(64 * kBmWavesPerGroup), 0, st, res, off, N,
-                     nres, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig, nhi_orig, next_chunk, err);
+  // The bitmap pass pays for its own launch only on large sets: from 64 x
+  // its resident waves on, sequences of 257..1024 residues go to it; below,
+  // the first pass sorts every sequence of up to 1024 residues.  Chunks of
+  // cs sequences, about four per wave of a full launch and at most 64.
+  // Below 64 every chunk gets a wave of its own (no counter); at 64 the
+  // launch is persistent and balances the chunks through the counter.
+  const uint32_t bm_waves = kBmGroupsPerCu * grid * kBmWavesPerGroup;
+  const bool bitmap = (uint64_t)N >= 64ull * bm_waves;
+  if (bitmap)
+    hipLaunchKernelGGL(count_wave_kernel<false>, dim3((N + 3) / 4), dim3(256), 0, st, res, off, in_off, N,
+                       nres, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig, nhi_orig, mid_list, nmid,
+                       long_list, nlong, err);
+  else
+    hipLaunchKernelGGL(count_wave_kernel<true>, dim3((N + 3) / 4), dim3(256), 0, st, res, off, in_off, N,
+                       nres, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig, nhi_orig, mid_list, nmid,
+                       long_list, nlong, err);
   KD_HIP(hipGetLastError());
+  if (bitmap) {
+    const uint32_t cs = std::max(1u, std::min(64u, N / (4u * bm_waves)));
+    const bool persistent = cs == 64u;
+    const uint32_t chunks = (N + cs - 1) / cs;
+    const uint32_t all_groups = (chunks + kBmWavesPerGroup - 1) / kBmWavesPerGroup;
+    const uint32_t bm_grid = persistent ? std::min(kBmGroupsPerCu * grid, all_groups) : all_groups;
+    hipLaunchKernelGGL(count_bitmap_kernel, dim3(bm_grid), dim3(64 * kBmWavesPerGroup), 0, st, res, off, N,
+                       nres, cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig, nhi_orig, cs, persistent,
+                       next_chunk, err);
+    KD_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(count_mid_kernel, dim3(2 * grid), dim3(kCountThreads), 0, st, res, off, nres,
                      cap, cap_ids, cap_cnt, hi_cap, Dorig, Korig, nhi_orig, mid_list, nmid, err);
   KD_HIP(hipGetLastError());

@@ -108,6 +108,43 @@ def test_count_path_boundaries(kd, ctx, oracle_mod, alphabet):
     check_lists(kd, ctx, ss, oracle_mod.count(ss))
 
 
+@pytest.mark.parametrize("N", [200_000, 800_000])
+def test_count_bitmap_pass_large_sets(kd, ctx, oracle_mod, N):
+    """Sets large enough for the LDS-bitmap pass (N >= 64 x its resident
+    waves, 196,608 on 256 compute units): at 200,000 one wave per chunk of
+    16 sequences, at 800,000 (>= 256 x the waves) a persistent launch that
+    takes chunks of 64 from its counter.  Most sequences have 257..1024
+    residues (that pass's range).  Word lists of 3,000 sampled sequences
+    bit-exact against the oracle."""
+    rng = np.random.default_rng(31)
+    lens = np.where(rng.random(N) < 0.9, rng.integers(257, 601, N), rng.integers(6, 1101, N))
+    off = np.zeros(N + 1, dtype=np.uint64)
+    np.cumsum(lens, out=off[1:])
+    al = np.frombuffer(b"ACDEFGHIKLMNPQRSTVWY", dtype=np.uint8)
+    res = al[rng.integers(0, 20, size=int(off[-1]), dtype=np.uint8)]
+    ss = synth.SeqSet(res, off, np.zeros(N, dtype=np.int32), f"bitmap-{N}")
+    say("count-bitmap-pass", N, int(off[-1]))
+    kset, ids, cnt, goff = gpu_lists(kd, ctx, ss)
+    assert kset.n == N
+    rows = np.sort(rng.choice(N, size=3000, replace=False))
+    L = oracle_mod.count(synth.from_strings([ss.seq(int(i)) for i in rows]))
+    for j, i in enumerate(rows):
+        a, b = int(goff[i]), int(goff[i + 1])
+        c, d = int(L.off[j]), int(L.off[j + 1])
+        assert np.array_equal(ids[a:b], L.ids[c:d]) and np.array_equal(cnt[a:b], L.cnt[c:d]), int(i)
+    # a residue that is not an amino acid in two sequences on the bitmap
+    # path: the first sequence's first bad position is reported
+    on = np.flatnonzero((lens > 256) & (lens <= 1024))
+    i0, i1 = int(on[N // 3 % len(on)]), int(on[-1])
+    res[int(off[i1]) + 7] = ord("Z")
+    res[int(off[i0]) + 200] = ord("*")
+    res[int(off[i0]) + 250] = ord("b")
+    say("count-bitmap-pass error", i0, i1)
+    with pytest.raises(kd.KdError) as e:
+        ctx.kmer_count(ss.residues, ss.offsets.view(np.int64))
+    assert e.value.status == -2 and e.value.seq == i0 and e.value.pos == 200
+
+
 def test_count_errors(kd, ctx):
     cases = [
         (["ACDEFGH", "ACDXFGH", "ACDEFGH"], -2, 1, 3),
