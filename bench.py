@@ -49,9 +49,10 @@ TRAFFIC = {
     # kernel a dict keyed by the work-list shape (tasks per compute unit) the
     # counters were taken at
     ("rank_pairs_kernel", "paper20k"): {"sources": RANK_SOURCES, "sha256_16": "0ebbc92f3c550ca3",
-                                        "bytes_per_launch": {16: 209310720, 32: 204222805}},
+                                        "bytes_per_launch": {16: 209310720, 32: 204222805, 64: 253211392,
+                                                             128: 251519403}},
     ("rank_pairs_kernel", "large100k"): {"sources": RANK_SOURCES, "sha256_16": "0ebbc92f3c550ca3",
-                                         "bytes_per_launch": {32: 6209227435, 64: 4580742827}},
+                                         "bytes_per_launch": {32: 6209227435, 64: 4580742827, 128: 4033544832}},
     ("rank_cross_kernel", "global100k"): {"sources": ["paper_0905_1744_amd/csrc/cross.hip",
                                                       "paper_0905_1744_amd/csrc/tile.h",
                                                       "paper_0905_1744_amd/csrc/bitcount.h",
