@@ -81,6 +81,10 @@ COUNTERS = {
                                         "valu_busy": 0.56, "lds_busy": 0.61,
                                         "lds_bank_conflict_share_of_lds_busy": 0.63,
                                         "source": "profiles/rank_pairs_paper20k.md"},
+    ("rank_pairs_kernel", "batched"): {"sources": BATCH_SOURCES, "sha256_16": "7ed972ae344349a1",
+                                       "tasks_per_cu": 64, "valu_busy": 0.40, "lds_busy": 0.37,
+                                       "lds_bank_conflict_share_of_lds_busy": 0.59,
+                                       "source": "profiles/batched_4096sets.md"},
 }
 
 
@@ -535,7 +539,8 @@ def batch_roofline(probes, pairs, lookups, ceiling, stages, alg_bytes, shape):
     ms, n = stages["pairs"]
     t = ms / max(n, 1) / 1e3
     return rank_roofline(probes, pairs, lookups, t, ceiling, measured_traffic("rank_pairs_kernel", "batched", shape),
-                         alg_bytes, kernel="rank_pairs_kernel (all sets in one launch)")
+                         alg_bytes, kernel="rank_pairs_kernel (all sets in one launch)",
+                         counters=profiled_counters("rank_pairs_kernel", "batched"))
 
 
 def bench_batch_graph(ctx, res, off, first, Bs, args, out, t_eager):
